@@ -1,0 +1,346 @@
+"""FP64 oracle for the Gaussian-splatting hot path (Python side).
+
+TEST INFRASTRUCTURE ONLY: only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this module.  It shares no code
+with the HIP path and never imports it.
+
+The per-view renderer, its reverse mode, the re-projection residual and the
+binning definition live in ``gs_oracle.c`` (plain C, FP64, OpenMP).  This
+module marshals numpy arrays into it and adds the parts that are a few lines
+of numpy:
+
+* the loss of the joint optimisation (Sec. 3.3, joint-loss equation) and the
+  L1 terms of the mapping loss (Sec. 3.4, mapping-loss equation), as means per
+  view averaged over views, with an optional constant pixel mask and the
+  filter gate of Sec. 3.3 (gate equation);
+* SE(3) exponential for the left-perturbation pose tangent xi = (v, w);
+* Adam (the paper says only "gradient-based optimization", Sec. 3.4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "gs_oracle.c")
+
+# decision bands for flagging pixels whose result an FP32 renderer may
+# legitimately decide the other way (relative for the 1/255 skip and the 1e-4
+# termination, absolute for the 0.99 clamp)
+BAND_SKIP = 2e-4
+BAND_CLAMP = 2e-4
+BAND_TERM = 2e-3
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (-O2, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
+                               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        L.or_project.argtypes = [i64, ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_int] + \
+            [ctypes.c_double] * 4 + [ctypes.c_void_p, ctypes.c_void_p]
+        L.or_render.argtypes = [i64, ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_int] + \
+            [ctypes.c_double] * 4 + [ctypes.c_void_p, i64, ctypes.c_void_p] + [ctypes.c_double] * 3 + \
+            [ctypes.c_void_p] * 7
+        L.or_backward.argtypes = [i64, ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_int] + \
+            [ctypes.c_double] * 4 + [ctypes.c_void_p, i64, ctypes.c_void_p] + [ctypes.c_void_p] * 3 + \
+            [ctypes.c_void_p] * 6
+        L.or_reproj.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4 + [i64] + [ctypes.c_void_p] * 3 + \
+            [ctypes.c_double] + [ctypes.c_void_p] * 4
+        L.or_binning_count.argtypes = [ctypes.c_int, i64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_void_p]
+        L.or_binning_count.restype = i64
+        L.or_binning.argtypes = [ctypes.c_int, i64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, i64]
+        L.or_sh_basis.argtypes = [ctypes.c_int, i64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_num_threads.restype = ctypes.c_int
+        del dp
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Gaussians:
+    """FP64 copies of the Gaussian parameters (promoted from the FP32 inputs)."""
+
+    def __init__(self, means, log_scales, quats, opacity_logits, colors, sh_degree: int = -1):
+        self.means = _d(means).reshape(-1, 3)
+        self.log_scales = _d(log_scales).reshape(-1, 3)
+        self.quats = _d(quats).reshape(-1, 4)
+        self.opacity_logits = _d(opacity_logits).reshape(-1)
+        self.sh_degree = int(sh_degree)
+        K = 1 if sh_degree < 0 else (sh_degree + 1) ** 2
+        self.colors = _d(colors).reshape(-1, 3) if sh_degree < 0 else _d(colors).reshape(-1, K, 3)
+        self.n = self.means.shape[0]
+
+    @classmethod
+    def from_scene(cls, s) -> "Gaussians":
+        return cls(s.means, s.log_scales, s.quats, s.opacity_logits, s.colors, s.sh_degree)
+
+    def args(self):
+        return (self.n, self.sh_degree, _p(self.means), _p(self.log_scales), _p(self.quats),
+                _p(self.opacity_logits), _p(self.colors))
+
+
+def _cam_args(cam, T):
+    T = _d(T).reshape(4, 4)
+    return (int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)), T
+
+
+def project(g: Gaussians, cam, T) -> np.ndarray:
+    """Per-Gaussian records [n,20]: valid, u, v, A, B, C, o, r, g, b, z,
+    radius, x0, x1, y0, y1, a, b, c, det."""
+    ca, T = _cam_args(cam, T)
+    out = np.zeros((g.n, 20), np.float64)
+    lib().or_project(*g.args(), *ca, _p(T), _p(out))
+    return out
+
+
+def render(g: Gaussians, cam, T, pixels: Optional[np.ndarray] = None, bands=(BAND_SKIP, BAND_CLAMP, BAND_TERM)
+           ) -> Dict[str, np.ndarray]:
+    """Render one view (whole image, or the pixels [k,2] (x, y) listed).
+
+    Returns color [3,H,W] (or [3,k]), depth, alpha, tfinal, nblend,
+    ambiguous (int8 flags) and nfrag (candidates visited)."""
+    ca, T = _cam_args(cam, T)
+    if pixels is None:
+        shape = (cam.height, cam.width)
+        npix, pix = -1, None
+        np_ = cam.width * cam.height
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        npix = np_ = pix.shape[0]
+        shape = (np_,)
+    color = np.zeros(3 * np_, np.float64)
+    depth = np.zeros(np_, np.float64)
+    alpha = np.zeros(np_, np.float64)
+    tfin = np.zeros(np_, np.float64)
+    nbl = np.zeros(np_, np.int32)
+    amb = np.zeros(np_, np.int8)
+    nfrag = np.zeros(1, np.int64)
+    rc = lib().or_render(*g.args(), *ca, _p(T), npix, _p(pix), float(bands[0]), float(bands[1]), float(bands[2]),
+                         _p(color), _p(depth), _p(alpha), _p(tfin), _p(nbl), _p(amb), _p(nfrag))
+    if rc != 0:
+        raise MemoryError("oracle render failed")
+    return {"color": color.reshape((3,) + shape), "depth": depth.reshape(shape), "alpha": alpha.reshape(shape),
+            "tfinal": tfin.reshape(shape), "nblend": nbl.reshape(shape), "ambiguous": amb.reshape(shape),
+            "nfrag": int(nfrag[0])}
+
+
+def backward(g: Gaussians, cam, T, dC=None, dD=None, dA=None, pixels: Optional[np.ndarray] = None,
+             grads: Optional[Dict[str, np.ndarray]] = None) -> Dict[str, np.ndarray]:
+    """Reverse mode of ``render`` for one view.  Accumulates into ``grads``
+    (created if None): means, log_scales, quats, opacity_logits, colors, pose
+    (the 6-vector d/dxi of T <- Exp(xi) T at xi = 0)."""
+    ca, T = _cam_args(cam, T)
+    if pixels is None:
+        npix, pix = -1, None
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        npix = pix.shape[0]
+    if grads is None:
+        grads = {"means": np.zeros_like(g.means), "log_scales": np.zeros_like(g.log_scales),
+                 "quats": np.zeros_like(g.quats), "opacity_logits": np.zeros_like(g.opacity_logits),
+                 "colors": np.zeros_like(g.colors), "pose": np.zeros(6)}
+    dC = None if dC is None else _d(dC).reshape(-1)
+    dD = None if dD is None else _d(dD).reshape(-1)
+    dA = None if dA is None else _d(dA).reshape(-1)
+    rc = lib().or_backward(*g.args(), *ca, _p(T), npix, _p(pix), _p(dC), _p(dD), _p(dA), _p(grads["means"]),
+                           _p(grads["log_scales"]), _p(grads["quats"]), _p(grads["opacity_logits"]),
+                           _p(grads["colors"]), _p(grads["pose"]))
+    if rc != 0:
+        raise MemoryError("oracle backward failed")
+    return grads
+
+
+def render_views(g: Gaussians, cams, poses) -> Dict[str, np.ndarray]:
+    """All views, flattened in the library's ragged layout: color is the
+    concatenation of each view's planar [3,H,W]; depth/alpha/tfinal of each
+    view's [H,W]."""
+    outs = [render(g, c, poses[v]) for v, c in enumerate(cams)]
+    return {"color": np.concatenate([o["color"].reshape(-1) for o in outs]),
+            "depth": np.concatenate([o["depth"].reshape(-1) for o in outs]),
+            "alpha": np.concatenate([o["alpha"].reshape(-1) for o in outs]),
+            "tfinal": np.concatenate([o["tfinal"].reshape(-1) for o in outs]),
+            "ambiguous": np.concatenate([o["ambiguous"].reshape(-1) for o in outs]),
+            "nfrag": sum(o["nfrag"] for o in outs)}
+
+
+def backward_views(g: Gaussians, cams, poses, dC, dD, dA) -> Dict[str, np.ndarray]:
+    """Reverse mode of ``render_views`` with flat ragged cotangents; returns
+    Gaussian gradients summed over views and pose [V,6]."""
+    grads = None
+    pose = np.zeros((len(cams), 6))
+    co = cd = 0
+    for v, c in enumerate(cams):
+        P = c.width * c.height
+        sl3 = None if dC is None else dC[co:co + 3 * P]
+        sl = None if dD is None else dD[cd:cd + P]
+        sa = None if dA is None else dA[cd:cd + P]
+        if grads is not None:
+            grads["pose"] = np.zeros(6)
+        grads = backward(g, c, poses[v], sl3, sl, sa, grads=grads)
+        pose[v] = grads["pose"]
+        co += 3 * P
+        cd += P
+    grads["pose"] = pose
+    return grads
+
+
+def reproj(cams, poses, points, uv, view_idx, delta: float) -> Dict[str, np.ndarray]:
+    """Sec. 3.2 Eq. lba residuals with a Huber kernel; per-view mean loss and
+    its pose gradient."""
+    V = len(cams)
+    W = np.array([c.width for c in cams], np.int32)
+    H = np.array([c.height for c in cams], np.int32)
+    intr = _d([[c.fx, c.fy, c.cx, c.cy] for c in cams]).reshape(V, 4)
+    T = _d(poses).reshape(V, 16)
+    P = _d(points).reshape(-1, 3)
+    U = _d(uv).reshape(-1, 2)
+    vid = np.ascontiguousarray(view_idx, dtype=np.int32)
+    M = P.shape[0]
+    res = np.zeros((M, 2))
+    loss = np.zeros(V)
+    dpose = np.zeros((V, 6))
+    nvalid = np.zeros(V, np.int64)
+    lib().or_reproj(V, _p(W), _p(H), _p(intr), _p(T), M, _p(P), _p(U), _p(vid), float(delta), _p(res), _p(loss),
+                    _p(dpose), _p(nvalid))
+    return {"residual": res, "loss": loss, "dpose": dpose, "nvalid": nvalid}
+
+
+def binning(sizes, n: int, tile_w: int, tile_h: int, rect: np.ndarray, depth: np.ndarray):
+    """Definition of the (tile, depth, record) binning: returns (values,
+    ranges) where values lists record ids sorted by (global tile, FP32 depth
+    bits, record) and ranges [T,2] holds each tile's [start, end), (0, 0)
+    when empty."""
+    V = len(sizes)
+    W = np.array([s[0] for s in sizes], np.int32)
+    H = np.array([s[1] for s in sizes], np.int32)
+    rect = np.ascontiguousarray(rect, dtype=np.uint32).reshape(-1, 2)
+    depth = np.ascontiguousarray(depth, dtype=np.float32).reshape(-1)
+    total = int(lib().or_binning_count(V, n, _p(W), _p(H), tile_w, tile_h, _p(rect)))
+    ntiles = int(sum(((w + tile_w - 1) // tile_w) * ((h + tile_h - 1) // tile_h) for w, h in sizes))
+    values = np.zeros(max(total, 1), np.uint32)
+    ranges = np.zeros((ntiles, 2), np.uint32)
+    lib().or_binning(V, n, _p(W), _p(H), tile_w, tile_h, _p(rect), _p(depth), _p(values), _p(ranges), ntiles)
+    return values[:total], ranges
+
+
+def sh_basis(deg: int, dirs: np.ndarray, grad: bool = False):
+    dirs = _d(dirs).reshape(-1, 3)
+    K = (deg + 1) ** 2
+    Y = np.zeros((dirs.shape[0], K))
+    dY = np.zeros((dirs.shape[0], K, 3)) if grad else None
+    lib().or_sh_basis(deg, dirs.shape[0], _p(dirs), _p(Y), _p(dY))
+    return (Y, dY) if grad else Y
+
+
+# ---------------------------------------------------------------------------
+# loss of the joint optimisation and of the mapping step (L1 parts)
+# ---------------------------------------------------------------------------
+
+def loss_and_upstream(cams, render_out, tgt_color, tgt_depth, w_color: float, w_depth: float,
+                      mask: Optional[np.ndarray] = None, gate_gamma: Optional[float] = None):
+    """Per view v: Lc_v = sum_{p,k} m_p |C - C^| / (3 H W), Ld_v = sum_p m_p
+    |D - D^| / (H W).  Total (render part) = (1/V) sum_v (w_c Lc_v + w_d Ld_v).
+    The mask m is the optional pixel weight times, if ``gate_gamma`` is given,
+    the filter gate of Sec. 3.3: target depth > 0, rendered depth > 0 and
+    rendered alpha > gamma (held constant: no gradient through it).
+    Returns (Lc [V], Ld [V], dL/dC flat, dL/dD flat); sign(0) = 0."""
+    V = len(cams)
+    C = render_out["color"]
+    D = render_out["depth"]
+    A = render_out["alpha"]
+    Lc = np.zeros(V)
+    Ld = np.zeros(V)
+    dC = np.zeros_like(C, dtype=np.float64)
+    dD = np.zeros_like(D, dtype=np.float64)
+    co = cd = 0
+    for v, c in enumerate(cams):
+        P = c.width * c.height
+        m = np.ones(P) if mask is None else _d(mask[cd:cd + P])
+        if gate_gamma is not None:
+            g = (_d(tgt_depth[cd:cd + P]) > 0) & (D[cd:cd + P] > 0) & (A[cd:cd + P] > gate_gamma)
+            m = m * g
+        ec = (C[co:co + 3 * P] - _d(tgt_color[co:co + 3 * P])).reshape(3, P)
+        ed = D[cd:cd + P] - _d(tgt_depth[cd:cd + P])
+        Lc[v] = float(np.sum(m[None] * np.abs(ec))) / (3 * P)
+        Ld[v] = float(np.sum(m * np.abs(ed))) / P
+        dC[co:co + 3 * P] = ((w_color / V) / (3 * P) * m[None] * np.sign(ec)).reshape(-1)
+        dD[cd:cd + P] = (w_depth / V) / P * m * np.sign(ed)
+        co += 3 * P
+        cd += P
+    return Lc, Ld, dC, dD
+
+
+# ---------------------------------------------------------------------------
+# SE(3) and Adam
+# ---------------------------------------------------------------------------
+
+def hat(w) -> np.ndarray:
+    w = np.asarray(w, np.float64)
+    return np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+
+
+def se3_exp(xi) -> np.ndarray:
+    """Closed-form exponential of the twist xi = (v, w): rotation by Rodrigues'
+    formula, translation V(w) v."""
+    xi = np.asarray(xi, np.float64)
+    v, w = xi[:3], xi[3:]
+    th = float(np.linalg.norm(w))
+    Wm = hat(w)
+    if th < 1e-8:
+        R = np.eye(3) + Wm + 0.5 * Wm @ Wm
+        Vm = np.eye(3) + 0.5 * Wm + Wm @ Wm / 6.0
+    else:
+        a = np.sin(th) / th
+        b = (1 - np.cos(th)) / th ** 2
+        c = (th - np.sin(th)) / th ** 3
+        R = np.eye(3) + a * Wm + b * Wm @ Wm
+        Vm = np.eye(3) + b * Wm + c * Wm @ Wm
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = Vm @ v
+    return T
+
+
+def adam_step(param, grad, m, v, t: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (bias-corrected), t = index of this update starting at 1.
+    Returns (delta, m, v) with delta the step to ADD to the parameter."""
+    grad = _d(grad)
+    m = b1 * m + (1 - b1) * grad
+    v = b2 * v + (1 - b2) * grad * grad
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return -lr * mh / (np.sqrt(vh) + eps), m, v
