@@ -1,0 +1,295 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) differentiable Gaussian-splatting hot
+ * path of TAMBRIDGE (arXiv 2405.19614): the 3DGS-centred encoder and the
+ * online mapping step, batched over the selected keyframes.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller, unless it is
+ *   marked "host".  The library owns only its context (a few pinned bytes for
+ *   read-backs, the reprojection accumulators and the captured-graph cache).
+ * - All work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *   the null stream).  Calls return once the work is enqueued, except where a
+ *   read-back is stated.
+ * - Every call returns an int status (gs_status).  Nothing aborts and no C++
+ *   exception crosses the boundary; on failure gs_last_error() describes it.
+ * - Gaussian parameters are FP32 structure-of-arrays (see gs_gaussians).
+ * - Images of several views are concatenated: view v occupies pixels
+ *   [P_v, P_v + H_v W_v) of the depth / alpha buffers and
+ *   [3 P_v, 3 P_v + 3 H_v W_v) of the colour buffer, with P_v = sum over u < v
+ *   of H_u W_u; each view's colour block is planar [3][H_v][W_v], row-major.
+ * - Poses are world-to-camera rigid transforms T_cw, FP32 4x4 row-major,
+ *   [V][16] on the device.  A pose gradient is the 6-vector d/dxi at xi = 0
+ *   of the left perturbation T_cw <- Exp(xi) T_cw, xi = (v, w) (translation
+ *   first, then rotation).
+ * - Camera model: pinhole (fx, fy, cx, cy); an integer pixel (x, y) samples
+ *   the image point (x, y) itself (OpenCV convention).
+ * - The forward model (Sec. 3.4 "Projection", "Differentiable Rasterization",
+ *   colour and depth compositing equations; Sec. 3.3 border mask): each
+ *   Gaussian is projected by its local affine (EWA) Jacobian, with 0.3 px^2
+ *   added to the 2D covariance diagonal; Gaussians with camera-space depth
+ *   <= 0.2 are culled; at each pixel the Gaussians whose opacity-aware
+ *   support rect contains it are blended front to back in ascending
+ *   (depth, index) order with alpha = min(0.99, o exp(-sigma)), fragments with
+ *   alpha < 1/255 skipped, and blending stops before the transmittance would
+ *   fall below 1e-4.  Outputs: colour C, depth D (not divided by alpha) and
+ *   alpha A = 1 - T_final (the border mask M_b).  Background is zero.
+ * - Results of the forward pass do not depend on the tile shape.
+ */
+#ifndef GS_H_
+#define GS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+#define GS_MAX_VIEWS 64
+
+typedef enum {
+    GS_OK = 0,
+    GS_EINVAL = -1,     /* bad argument: NULL pointer, size out of range, unsupported shape */
+    GS_ENOMEM = -2,     /* a buffer the caller passed is too small, or a library allocation failed */
+    GS_ECAPACITY = -3,  /* more (tile, Gaussian) pairs than the pair capacity; see gs_plan.n_pairs */
+    GS_EDEVICE = -4,    /* HIP runtime error; text in gs_last_error */
+    GS_ECAPTURE = -5    /* graph capture / instantiation failed */
+} gs_status;
+
+typedef struct gs_ctx gs_ctx;
+
+/* Gaussian parameters (Sec. 3.4 "Gaussian Representation", generalised to an
+ * anisotropic covariance).  n Gaussians, FP32, device.
+ *   means          [n][3]  world-space centres
+ *   log_scales     [n][3]  scale = exp(log_scale) per principal axis (equal
+ *                          values give the paper's isotropic Gaussian)
+ *   quats          [n][4]  rotation (w, x, y, z), normalised inside the forward
+ *   opacity_logits [n]     opacity = sigmoid(logit)
+ *   colors         sh_degree == -1: [n][3] RGB (view independent, as in the paper)
+ *                  sh_degree in 0..3: [n][(L+1)^2][3] real orthonormal SH
+ *                  coefficients; colour = max(0, sum Y_lm(dir) k_lm + 0.5)
+ *                  with dir the unit vector from the camera centre to the mean. */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* colors;
+} gs_gaussians;
+
+/* Gradients with the layout of gs_gaussians (device, FP32).  Overwritten by
+ * gs_render_backward; gs_mapping_step overwrites or accumulates (opts). */
+typedef struct {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* colors;
+} gs_gaussian_grads;
+
+/* Static camera geometry of one view (HOST memory). */
+typedef struct {
+    int32_t width, height;  /* 1 .. 16384 */
+    float fx, fy, cx, cy;
+} gs_camera;
+
+/* Tile plan of a forward pass.
+ *   tile_w, tile_h : in  tile shape; one of 16x16, 16x8, 8x8, 32x8, 32x16
+ *                    (0, 0 = the context's current choice, 16x16 unless
+ *                    gs_autotune chose another); out: the shape used
+ *   pair_capacity  : in  (tile, Gaussian) pairs the state buffer was sized for
+ *   n_pairs        : out pairs produced (on GS_ECAPACITY: pairs needed)
+ *   n_visible      : out visible (view, Gaussian) records */
+typedef struct {
+    int32_t tile_w, tile_h;
+    int64_t pair_capacity;
+    int64_t n_pairs;
+    int64_t n_visible;
+} gs_plan;
+
+int gs_abi_version(void);
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int gs_create(gs_ctx** out, int device);
+void gs_destroy(gs_ctx* ctx);
+
+/* Text of the last failure on this context (ctx may be NULL: last failure of
+ * gs_create on this thread).  Valid until the next call on the context. */
+const char* gs_last_error(const gs_ctx* ctx);
+
+/* Bytes of the opaque device state a forward pass writes and the matching
+ * backward reads: records of every (view, Gaussian), sort buffers for
+ * `pair_capacity` pairs, per-tile ranges and per-pixel final transmittance
+ * and stop index.  cams: HOST [V].  Returns 0 on invalid arguments. */
+size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t pair_capacity, int32_t tile_w,
+                      int32_t tile_h);
+
+/* Forward pass (Sec. 3.3 3DGS-centred encoder; Sec. 3.4 projection and
+ * rasterisation) over V views in one batched launch sequence.
+ *   g      Gaussians (device)          cams  HOST [V] camera geometry
+ *   poses  device [V][16] T_cw         V     1 .. GS_MAX_VIEWS
+ *   color  device [sum 3 H W]          depth, alpha  device [sum H W]
+ *   state  device buffer of state_bytes >= gs_state_bytes(...); written
+ *   plan   HOST in/out (see gs_plan)
+ * Reads the pair count back once (one stream synchronisation) and returns
+ * GS_ECAPACITY with plan->n_pairs = pairs needed when the capacity is too
+ * small; nothing after the count is then enqueued. */
+int gs_render_forward(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                      float* color, float* depth, float* alpha, void* state, size_t state_bytes, gs_plan* plan,
+                      void* stream);
+
+/* Reverse mode of gs_render_forward (differentiable rasterisation,
+ * Sec. 3.4; pose gradient for the joint optimisation, Sec. 3.3).  Takes the
+ * same g, cams, poses, V, state and the plan returned by the forward, and the
+ * upstream gradients dL/dcolor [sum 3HW], dL/ddepth [sum HW], dL/dalpha
+ * [sum HW] (device; any may be NULL = zero).  Overwrites every array of
+ * `grads` (device) and dL_dpose (device [V][6]).  The state is used as
+ * scratch and stays valid for further backward calls. */
+int gs_render_backward(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                       void* state, size_t state_bytes, const gs_plan* plan, const float* dL_dcolor,
+                       const float* dL_ddepth, const float* dL_dalpha, gs_gaussian_grads* grads, float* dL_dpose,
+                       void* stream);
+
+/* Re-projection residuals of Sec. 3.2 Eq. lba (the tracking-centred encoder
+ * of Sec. 3.3): for match m of view k = view_idx[m], r_m = uv_m - pi(K_k,
+ * T_k P_m).  Robust loss per view: mean over its matches with camera-space
+ * depth > 0.2 of h(|r_m|), h(e) = e^2/2 for e <= huber_delta, else
+ * huber_delta (e - huber_delta/2).
+ *   points device [M][3], uv device [M][2], view_idx device [M] (int32,
+ *   matches with an index outside [0, V) are ignored), M >= 0.
+ *   residual device [M][2] (0 for excluded matches), loss device [V]
+ *   (overwritten), dL_dpose device [V][6]: ACCUMULATES weight * d loss_k /
+ *   d xi_k, so it can be added to the rendering pose gradient. */
+int gs_reproj_residual(gs_ctx* ctx, const gs_camera* cams, const float* poses, int32_t V, const float* points,
+                       const float* uv, const int32_t* view_idx, int64_t M, float huber_delta, float weight,
+                       float* residual, float* loss, float* dL_dpose, void* stream);
+
+/* Options of one mapping / pose-refinement step.
+ * Loss (Sec. 3.3 joint-loss equation, L1 terms of the Sec. 3.4 mapping loss):
+ *   L = (1/V) sum_v ( w_color Lc_v + w_depth Ld_v + w_reproj Lr_v ),
+ *   Lc_v = sum_{p,k} m_p |C - C^| / (3 H_v W_v),  Ld_v = sum_p m_p |D - D^| / (H_v W_v),
+ *   Lr_v = the Huber re-projection loss of gs_reproj_residual.
+ *   m_p = target mask (1 if NULL) times, if use_gate, the filter gate of
+ *   Sec. 3.3: target depth > 0, rendered depth > 0, rendered alpha > gate_gamma
+ *   (a constant mask, no gradient through it).  sign(0) = 0.
+ * Update (the paper's "gradient-based optimization"; Adam with bias
+ * correction): update_gaussians applies Adam to every Gaussian parameter
+ * with its group's learning rate; update_poses applies Adam to each view's
+ * pose tangent and sets T <- Exp(step) T.
+ * accumulate_grads: add the Gaussian gradients to `grads` instead of
+ * overwriting them.  use_graph: capture the step as a hipGraph on first use
+ * of a given (shape, pointers, options) and replay it afterwards. */
+typedef struct {
+    float w_color, w_depth, w_reproj, huber_delta;
+    int32_t use_gate;
+    float gate_gamma;
+    int32_t update_gaussians, update_poses, accumulate_grads, use_graph;
+    float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_colors, lr_pose;
+    float adam_b1, adam_b2, adam_eps;
+    int32_t tile_w, tile_h;     /* 0, 0 = context choice */
+    int64_t pair_capacity;      /* capacity the workspace was sized for */
+} gs_step_opts;
+
+/* Targets of the rendering loss (device): color [sum 3HW], depth [sum HW],
+ * mask [sum HW] or NULL (per-pixel weight m_p). */
+typedef struct {
+    const float* color;
+    const float* depth;
+    const float* mask;
+} gs_targets;
+
+/* 2D-3D matches for the re-projection term (device; M may be 0). */
+typedef struct {
+    const float* points;
+    const float* uv;
+    const int32_t* view_idx;
+    int64_t M;
+} gs_matches;
+
+/* Adam state (device): m and v each hold n*(11 + 3K) + 6V floats laid out as
+ * means [3n], log_scales [3n], quats [4n], opacity [n], colors [3Kn] (K = 1 for
+ * RGB, (L+1)^2 for SH), poses [6V]; step is a device int32 counter of updates
+ * done (incremented on the device). */
+typedef struct {
+    float* m;
+    float* v;
+    int32_t* step;
+} gs_adam;
+
+/* Workspace bytes for gs_mapping_step (device; holds the forward state, the
+ * upstream gradients, loss partials and status flags). */
+size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int32_t sh_degree,
+                               int64_t pair_capacity, int32_t tile_w, int32_t tile_h);
+
+/* One mapping / joint-optimisation iteration, entirely on the device with no
+ * host synchronisation: forward over V views, fused loss and upstream
+ * gradients, re-projection term, backward, optional Adam updates.
+ *   params   in (out when update_gaussians)    grads  out (see accumulate_grads)
+ *   adam     Adam state (used when an update flag is set; may be NULL otherwise)
+ *   cams     HOST [V]                           poses  device [V][16] (out when update_poses)
+ *   color, depth, alpha  device render outputs (sum 3HW / sum HW)
+ *   loss_out device [1 + 3V]: total L, then (Lc_v, Ld_v, Lr_v) per view
+ *   dL_dpose device [V][6]: gradient of L w.r.t. each pose tangent
+ * A pair overflow is flagged on the device (results then invalid); read it
+ * with gs_step_status. */
+int gs_mapping_step(gs_ctx* ctx, gs_gaussians* params, gs_gaussian_grads* grads, const gs_adam* adam,
+                    const gs_camera* cams, float* poses, int32_t V, const gs_targets* targets,
+                    const gs_matches* matches, const gs_step_opts* opts, void* workspace, size_t workspace_bytes,
+                    float* color, float* depth, float* alpha, float* loss_out, float* dL_dpose, void* stream);
+
+/* Synchronous read of the workspace status after gs_mapping_step: *flags bit 0 =
+ * pair overflow; *n_pairs = pairs of the last step (needed ones on overflow),
+ * *n_visible = visible records.  Synchronises `stream`. */
+int gs_step_status(gs_ctx* ctx, const void* workspace, size_t workspace_bytes, int32_t* flags, int64_t* n_pairs,
+                   int64_t* n_visible, void* stream);
+
+/* Diagnostics: one eager mapping step (same arguments and results as
+ * gs_mapping_step, never graph-captured) with HIP events recorded on `stream`
+ * between its stages.  stage_ms (HOST [gs_num_stages()]) receives each
+ * stage's duration in milliseconds; frag_counts (HOST [2], may be NULL)
+ * receives the number of (pixel, Gaussian) candidates the forward
+ * compositing visited (support rect contains the pixel, up to and including
+ * the one that stops the pixel) and the number it blended.  Synchronises
+ * `stream`. */
+int gs_num_stages(void);
+const char* gs_stage_name(int i);
+int gs_step_profile(gs_ctx* ctx, gs_gaussians* params, gs_gaussian_grads* grads, const gs_adam* adam,
+                    const gs_camera* cams, float* poses, int32_t V, const gs_targets* targets,
+                    const gs_matches* matches, const gs_step_opts* opts, void* workspace, size_t workspace_bytes,
+                    float* color, float* depth, float* alpha, float* loss_out, float* dL_dpose, float* stage_ms,
+                    int64_t* frag_counts, void* stream);
+
+/* Binning stage on its own (integer; exact): records r = v*n + i carry an
+ * inclusive pixel rect rect[r] = (x0 | x1 << 16, y0 | y1 << 16) (empty when
+ * x0 > x1 or y0 > y1) and a positive FP32 depth.  Produces the record ids of
+ * every (tile, record) pair whose rect touches the tile, sorted by (global
+ * tile id, depth, record), and per-tile [start, end) ranges ((0, 0) when
+ * empty); the global id of tile (tx, ty) of view v counts the tiles of the
+ * views before v, then ty * tiles_x + tx.
+ *   rect device [V*n][2] u32, depth device [V*n] f32, values device
+ *   [values_capacity] u32, ranges device [total tiles][2] u32, n_pairs HOST out.
+ * Uses `state` (sized by gs_state_bytes with pair_capacity = values_capacity)
+ * as scratch; reads the pair count back (one synchronisation). */
+int gs_bin_records(gs_ctx* ctx, const gs_camera* cams, int32_t V, int64_t n, int32_t tile_w, int32_t tile_h,
+                   const uint32_t* rect, const float* depth, uint32_t* values, int64_t values_capacity,
+                   uint32_t* ranges, int64_t* n_pairs, void* state, size_t state_bytes, void* stream);
+
+/* Tile-shape autotuner: times forward + backward of the given scene for every
+ * supported tile shape (allocating temporary device buffers), keeps the
+ * fastest as the context's choice for this (V, sizes, n) class and returns
+ * it in *tile_w, *tile_h (HOST).  Synchronises the device. */
+int gs_autotune(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                int32_t iters, int32_t* tile_w, int32_t* tile_h, void* stream);
+
+/* Set the context's tile choice explicitly (0, 0 restores 16x16). */
+int gs_set_tile(gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H_ */

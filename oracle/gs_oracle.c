@@ -82,6 +82,7 @@ typedef struct {
     double dirn;       /* |mu - camera centre| */
     double Y[16];      /* SH basis at dir */
     double z;
+    double zsc;        /* sum of |terms| of the depth dot product (its rounding scale) */
     double radius;
     int x0, x1, y0, y1;
 } proj_t;
@@ -217,6 +218,7 @@ static void project(const gs_t* g, int64_t i, const cam_t* cam, proj_t* P) {
                   cam->tw[r];
     if (P->p[2] <= ZNEAR) return;
     const double px = P->p[0], py = P->p[1], pz = P->p[2];
+    P->zsc = fabs(cam->Rw[6] * mu[0]) + fabs(cam->Rw[7] * mu[1]) + fabs(cam->Rw[8] * mu[2]) + fabs(cam->tw[2]);
 
     /* pinhole projection of the mean (integer pixel coordinates sample the
        point itself: OpenCV convention) */
@@ -374,10 +376,11 @@ typedef struct {
  * if frags != NULL, the blended fragments.  Returns the number of blended
  * fragments. */
 static int composite_pixel(const view_t* V, int x, int y, double band_skip, double band_clamp,
-                           double band_term, double* col, double* dep, double* Tfin, int* amb,
-                           int64_t* nvisit, frag_t** frags, int* fcap) {
+                           double band_term, double band_order, double* col, double* dep, double* Tfin,
+                           int* amb, int64_t* nvisit, frag_t** frags, int* fcap) {
     const int64_t b = (int64_t)(y / BUCKET) * V->bx + x / BUCKET;
     double T = 1.0, C0 = 0, C1 = 0, C2 = 0, D = 0;
+    double zprev = -1.0, zscprev = 0.0;
     int nb = 0;
     int64_t visits = 0;
     *amb = 0;
@@ -391,13 +394,18 @@ static int composite_pixel(const view_t* V, int x, int y, double band_skip, doub
         if (sigma < 0) continue;
         const double G = exp(-sigma);
         const double raw = p->o * G;
-        if (fabs(raw - ALPHA_MIN) < band_skip * ALPHA_MIN) *amb = 1;
+        if (fabs(raw - ALPHA_MIN) < band_skip * ALPHA_MIN) *amb |= 1;
         if (fabs(raw - ALPHA_MAX) < band_clamp) *amb |= 2;
         const double alpha = raw < ALPHA_MAX ? raw : ALPHA_MAX;
         if (alpha < ALPHA_MIN) continue;
         const double Tn = T * (1.0 - alpha);
-        if (fabs(Tn - T_MIN) < band_term * T_MIN) *amb = 1;
+        if (fabs(Tn - T_MIN) < band_term * T_MIN) *amb |= 4;
         if (Tn < T_MIN) break;
+        /* two blended Gaussians whose depths a single-precision renderer
+           cannot order reliably: the blend order there is a rounding decision */
+        if (zprev >= 0 && fabs(p->z - zprev) <= band_order * (p->zsc > zscprev ? p->zsc : zscprev)) *amb |= 8;
+        zprev = p->z;
+        zscprev = p->zsc;
         const double w = alpha * T;
         C0 += p->col[0] * w;
         C1 += p->col[1] * w;
@@ -454,13 +462,17 @@ int or_project(int64_t n, int sh, const double* means, const double* ls, const d
 
 /* Render one view.  npix < 0: the whole image, outputs planar [3,H,W] / [H,W];
  * otherwise the listed pixels pix[npix,2] (x, y), outputs [3,npix] / [npix].
- * ambiguous[k] != 0 when a skip / clamp / termination decision lies within the
- * given relative bands of its threshold.  nfrag_alg returns the number of
+ * ambiguous[k] flags decisions near their thresholds: bit 0 the 1/255 skip
+ * (relative band), bit 1 the 0.99 clamp (absolute band; changes gradients
+ * only), bit 2 the 1e-4 termination (relative band), bit 3 two blended
+ * Gaussians whose depths differ by at most band_order times the magnitude of
+ * the terms their depths are summed from (the order a single-precision sort
+ * may swap).  nfrag_alg returns the number of
  * candidates visited up to and including the terminating one. */
 int or_render(int64_t n, int sh, const double* means, const double* ls, const double* q, const double* opl,
               const double* col, int W, int H, double fx, double fy, double cx, double cy, const double* T,
               int64_t npix, const int32_t* pix, double band_skip, double band_clamp, double band_term,
-              double* color, double* depth, double* alpha, double* tfinal, int32_t* nblend,
+              double band_order, double* color, double* depth, double* alpha, double* tfinal, int32_t* nblend,
               int8_t* ambiguous, int64_t* nfrag_alg) {
     gs_t g; cam_t cam; view_t V;
     unpack_gs(&g, n, sh, means, ls, q, opl, col);
@@ -475,8 +487,8 @@ int or_render(int64_t n, int sh, const double* means, const double* ls, const do
         double c3[3], d, t;
         int amb;
         int64_t visits;
-        int nb = composite_pixel(&V, x, y, band_skip, band_clamp, band_term, c3, &d, &t, &amb, &visits, NULL,
-                                 NULL);
+        int nb = composite_pixel(&V, x, y, band_skip, band_clamp, band_term, band_order, c3, &d, &t, &amb, &visits,
+                                 NULL, NULL);
         /* the terminating candidate counts as visited (it was evaluated) */
         total += visits;
         color[k] = c3[0]; color[np + k] = c3[1]; color[2 * np + k] = c3[2];
@@ -524,7 +536,7 @@ int or_backward(int64_t n, int sh, const double* means, const double* ls, const 
             double c3[3], d, Tf;
             int amb;
             int64_t visits;
-            int nb = composite_pixel(&V, x, y, 0, 0, 0, c3, &d, &Tf, &amb, &visits, &fr, &fcap);
+            int nb = composite_pixel(&V, x, y, 0, 0, 0, -1.0, c3, &d, &Tf, &amb, &visits, &fr, &fcap);
             const double gC0 = dC ? dC[k] : 0, gC1 = dC ? dC[np + k] : 0, gC2 = dC ? dC[2 * np + k] : 0;
             const double gD = dD ? dD[k] : 0, gA = dA ? dA[k] : 0;
             /* suffix sums S of later weighted colours / depths */

@@ -30,11 +30,21 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "gs_oracle.c")
 
 # decision bands for flagging pixels whose result an FP32 renderer may
-# legitimately decide the other way (relative for the 1/255 skip and the 1e-4
-# termination, absolute for the 0.99 clamp)
+# legitimately decide the other way: relative for the 1/255 skip and the 1e-4
+# termination, absolute for the 0.99 clamp, and for the blend order of two
+# Gaussians a multiple of the single-precision unit roundoff (2^-24) times
+# the magnitude of the terms of the depth dot product.  The defaults cover
+# images up to ~1200 px wide, where FP32 projected means carry ~1e-4 px of
+# rounding; SMALL_BANDS suit images of a few hundred pixels.
 BAND_SKIP = 2e-4
 BAND_CLAMP = 2e-4
-BAND_TERM = 2e-3
+BAND_TERM = 5e-4
+BAND_ORDER = 8 * 2.0 ** -24
+BANDS = (BAND_SKIP, BAND_CLAMP, BAND_TERM, BAND_ORDER)
+SMALL_BANDS = (5e-5, 5e-5, 2e-4, BAND_ORDER)
+# flag bits
+AMB_SKIP, AMB_CLAMP, AMB_TERM, AMB_ORDER = 1, 2, 4, 8
+AMB_VALUE = AMB_SKIP | AMB_TERM | AMB_ORDER    # decisions that change rendered values
 
 
 def build(force: bool = False) -> str:
@@ -60,7 +70,7 @@ def lib():
         L.or_project.argtypes = [i64, ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_int] + \
             [ctypes.c_double] * 4 + [ctypes.c_void_p, ctypes.c_void_p]
         L.or_render.argtypes = [i64, ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_int] + \
-            [ctypes.c_double] * 4 + [ctypes.c_void_p, i64, ctypes.c_void_p] + [ctypes.c_double] * 3 + \
+            [ctypes.c_double] * 4 + [ctypes.c_void_p, i64, ctypes.c_void_p] + [ctypes.c_double] * 4 + \
             [ctypes.c_void_p] * 7
         L.or_backward.argtypes = [i64, ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_int] + \
             [ctypes.c_double] * 4 + [ctypes.c_void_p, i64, ctypes.c_void_p] + [ctypes.c_void_p] * 3 + \
@@ -127,8 +137,7 @@ def project(g: Gaussians, cam, T) -> np.ndarray:
     return out
 
 
-def render(g: Gaussians, cam, T, pixels: Optional[np.ndarray] = None, bands=(BAND_SKIP, BAND_CLAMP, BAND_TERM)
-           ) -> Dict[str, np.ndarray]:
+def render(g: Gaussians, cam, T, pixels: Optional[np.ndarray] = None, bands=BANDS) -> Dict[str, np.ndarray]:
     """Render one view (whole image, or the pixels [k,2] (x, y) listed).
 
     Returns color [3,H,W] (or [3,k]), depth, alpha, tfinal, nblend,
@@ -149,8 +158,8 @@ def render(g: Gaussians, cam, T, pixels: Optional[np.ndarray] = None, bands=(BAN
     nbl = np.zeros(np_, np.int32)
     amb = np.zeros(np_, np.int8)
     nfrag = np.zeros(1, np.int64)
-    rc = lib().or_render(*g.args(), *ca, _p(T), npix, _p(pix), float(bands[0]), float(bands[1]), float(bands[2]),
-                         _p(color), _p(depth), _p(alpha), _p(tfin), _p(nbl), _p(amb), _p(nfrag))
+    b4 = tuple(bands) + ((BAND_ORDER,) if len(bands) == 3 else ())
+    rc = lib().or_render(*g.args(), *ca, _p(T), npix, _p(pix), *(float(b) for b in b4), _p(color), _p(depth), _p(alpha), _p(tfin), _p(nbl), _p(amb), _p(nfrag))
     if rc != 0:
         raise MemoryError("oracle render failed")
     return {"color": color.reshape((3,) + shape), "depth": depth.reshape(shape), "alpha": alpha.reshape(shape),
@@ -184,11 +193,11 @@ def backward(g: Gaussians, cam, T, dC=None, dD=None, dA=None, pixels: Optional[n
     return grads
 
 
-def render_views(g: Gaussians, cams, poses) -> Dict[str, np.ndarray]:
+def render_views(g: Gaussians, cams, poses, bands=BANDS) -> Dict[str, np.ndarray]:
     """All views, flattened in the library's ragged layout: color is the
     concatenation of each view's planar [3,H,W]; depth/alpha/tfinal of each
     view's [H,W]."""
-    outs = [render(g, c, poses[v]) for v, c in enumerate(cams)]
+    outs = [render(g, c, poses[v], bands=bands) for v, c in enumerate(cams)]
     return {"color": np.concatenate([o["color"].reshape(-1) for o in outs]),
             "depth": np.concatenate([o["depth"].reshape(-1) for o in outs]),
             "alpha": np.concatenate([o["alpha"].reshape(-1) for o in outs]),

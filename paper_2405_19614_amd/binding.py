@@ -1,0 +1,508 @@
+"""Python binding of the C ABI (include/gs.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of libgs.so.  PyTorch provides device memory and the current stream.
+There is no CPU fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _abi as A
+
+
+class GSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{A.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t: Optional[torch.Tensor], numel: int, name: str, dtype=torch.float32, device=None):
+    """Host-side check that a device buffer matches what the kernels index."""
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def _check_gaussians(g: "Gaussians", device):
+    n = g.n
+    _need(g.means, 3 * n, "means", device=device)
+    _need(g.log_scales, 3 * n, "log_scales", device=device)
+    _need(g.quats, 4 * n, "quats", device=device)
+    _need(g.opacity_logits, n, "opacity_logits", device=device)
+    _need(g.colors, 3 * n * sh_coeffs(g.sh_degree), "colors", device=device)
+
+
+def _dev_f32(t, device) -> torch.Tensor:
+    t = torch.as_tensor(t, dtype=torch.float32, device=device)
+    return t.contiguous()
+
+
+@dataclass
+class Camera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+    @property
+    def npix(self) -> int:
+        return self.width * self.height
+
+
+def as_cameras(cams) -> List[Camera]:
+    out = []
+    for c in cams:
+        if isinstance(c, Camera):
+            out.append(c)
+        elif hasattr(c, "as_tuple"):
+            out.append(Camera(*c.as_tuple()))
+        else:
+            out.append(Camera(*c))
+    return out
+
+
+def cam_array(cams: Sequence[Camera]):
+    arr = (A.gs_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = A.gs_camera(int(c.width), int(c.height), float(c.fx), float(c.fy), float(c.cx), float(c.cy))
+    return arr
+
+
+def sh_coeffs(sh_degree: int) -> int:
+    return 1 if sh_degree < 0 else (sh_degree + 1) ** 2
+
+
+@dataclass
+class Gaussians:
+    """Device FP32 parameters (structure of arrays)."""
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacity_logits: torch.Tensor
+    colors: torch.Tensor
+    sh_degree: int = -1
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @classmethod
+    def from_arrays(cls, means, log_scales, quats, opacity_logits, colors, sh_degree=-1, device="cuda"):
+        return cls(_dev_f32(means, device).reshape(-1, 3), _dev_f32(log_scales, device).reshape(-1, 3),
+                   _dev_f32(quats, device).reshape(-1, 4), _dev_f32(opacity_logits, device).reshape(-1),
+                   _dev_f32(colors, device), int(sh_degree))
+
+    @classmethod
+    def from_scene(cls, s, device="cuda"):
+        return cls.from_arrays(s.means, s.log_scales, s.quats, s.opacity_logits, s.colors, s.sh_degree, device)
+
+    def struct(self) -> A.gs_gaussians:
+        return A.gs_gaussians(self.n, self.sh_degree, _p(self.means), _p(self.log_scales), _p(self.quats),
+                              _p(self.opacity_logits), _p(self.colors))
+
+    def zeros_like(self) -> "Gaussians":
+        return Gaussians(torch.zeros_like(self.means), torch.zeros_like(self.log_scales),
+                         torch.zeros_like(self.quats), torch.zeros_like(self.opacity_logits),
+                         torch.zeros_like(self.colors), self.sh_degree)
+
+    def grad_struct(self) -> A.gs_gaussian_grads:
+        return A.gs_gaussian_grads(_p(self.means), _p(self.log_scales), _p(self.quats), _p(self.opacity_logits),
+                                   _p(self.colors))
+
+    def tensors(self) -> Tuple[torch.Tensor, ...]:
+        return (self.means, self.log_scales, self.quats, self.opacity_logits, self.colors)
+
+
+def split_images(cams: Sequence[Camera], color: torch.Tensor, depth: torch.Tensor, alpha: torch.Tensor):
+    """Per-view [3,H,W], [H,W], [H,W] views of the concatenated outputs."""
+    out = []
+    o = 0
+    for c in cams:
+        P = c.npix
+        out.append((color[3 * o:3 * (o + P)].view(3, c.height, c.width), depth[o:o + P].view(c.height, c.width),
+                    alpha[o:o + P].view(c.height, c.width)))
+        o += P
+    return out
+
+
+class Context:
+    """One library context (one device; use one per stream)."""
+
+    def __init__(self, device: Optional[int] = None):
+        self.lib = A.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP path has no CPU fallback")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        rc = self.lib.gs_create(ctypes.byref(h), self.device)
+        if rc != 0:
+            raise GSError(rc, self.lib.gs_last_error(None).decode())
+        self.h = h
+        self.pair_estimate = 1 << 16
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.gs_destroy(h)
+            self.h = None
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise GSError(rc, self.lib.gs_last_error(self.h).decode())
+
+    @property
+    def torch_device(self):
+        return torch.device("cuda", self.device)
+
+    # -------------------------------------------------------------- sizes
+    def state_bytes(self, cams, n: int, capacity: int, tile=(0, 0)) -> int:
+        cams = as_cameras(cams)
+        b = self.lib.gs_state_bytes(cam_array(cams), len(cams), n, capacity, tile[0], tile[1])
+        if b == 0:
+            raise GSError(A.GS_EINVAL, "invalid arguments for gs_state_bytes")
+        return int(b)
+
+    def workspace_bytes(self, cams, n: int, sh_degree: int, capacity: int, tile=(0, 0)) -> int:
+        cams = as_cameras(cams)
+        b = self.lib.gs_step_workspace_bytes(cam_array(cams), len(cams), n, sh_degree, capacity, tile[0], tile[1])
+        if b == 0:
+            raise GSError(A.GS_EINVAL, "invalid arguments for gs_step_workspace_bytes")
+        return int(b)
+
+    def set_tile(self, tw: int, th: int):
+        self._check(self.lib.gs_set_tile(self.h, tw, th))
+
+    # -------------------------------------------------------------- render
+    def forward(self, g: Gaussians, cams, poses: torch.Tensor, tile=(0, 0), capacity: Optional[int] = None):
+        """Returns (color, depth, alpha, state, plan)."""
+        cams = as_cameras(cams)
+        ca = cam_array(cams)
+        V = len(cams)
+        npix = sum(c.npix for c in cams)
+        dev = self.torch_device
+        color = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+        depth = torch.empty(npix, dtype=torch.float32, device=dev)
+        alpha = torch.empty(npix, dtype=torch.float32, device=dev)
+        poses = poses.contiguous()
+        _check_gaussians(g, dev)
+        _need(poses, 16 * V, "poses", device=dev)
+        cap = int(capacity if capacity is not None else self.pair_estimate)
+        gst = g.struct()
+        for _ in range(3):
+            nbytes = self.state_bytes(cams, g.n, cap, tile)
+            state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            plan = A.gs_plan(tile[0], tile[1], cap, 0, 0)
+            rc = self.lib.gs_render_forward(self.h, ctypes.byref(gst), ca, _p(poses), V, _p(color), _p(depth),
+                                            _p(alpha), _p(state), nbytes, ctypes.byref(plan), _stream())
+            if rc == A.GS_ECAPACITY:
+                cap = int(plan.n_pairs * 1.25) + 1024
+                self.pair_estimate = max(self.pair_estimate, cap)
+                continue
+            self._check(rc)
+            self.pair_estimate = max(self.pair_estimate, int(plan.n_pairs * 1.25) + 1024)
+            return color, depth, alpha, state, plan
+        raise GSError(A.GS_ECAPACITY, "pair capacity did not converge")
+
+    def backward(self, g: Gaussians, cams, poses: torch.Tensor, state: torch.Tensor, plan, dC=None, dD=None,
+                 dA=None) -> Tuple[Gaussians, torch.Tensor]:
+        cams = as_cameras(cams)
+        V = len(cams)
+        grads = g.zeros_like()
+        dpose = torch.zeros(V, 6, dtype=torch.float32, device=self.torch_device)
+        gst = g.struct()
+        gg = grads.grad_struct()
+        c = lambda t: None if t is None else t.contiguous()
+        dC, dD, dA = c(dC), c(dD), c(dA)
+        npix = sum(cm.npix for cm in cams)
+        _check_gaussians(g, self.torch_device)
+        _need(poses.contiguous(), 16 * V, "poses", device=self.torch_device)
+        _need(dC, 3 * npix, "dL_dcolor", device=self.torch_device)
+        _need(dD, npix, "dL_ddepth", device=self.torch_device)
+        _need(dA, npix, "dL_dalpha", device=self.torch_device)
+        if state.numel() < self.state_bytes(cams, g.n, plan.pair_capacity, (plan.tile_w, plan.tile_h)):
+            raise ValueError("state is smaller than the plan requires")
+        rc = self.lib.gs_render_backward(self.h, ctypes.byref(gst), cam_array(cams), _p(poses.contiguous()), V,
+                                         _p(state), state.numel(), ctypes.byref(plan), _p(dC), _p(dD), _p(dA),
+                                         ctypes.byref(gg), _p(dpose), _stream())
+        self._check(rc)
+        return grads, dpose
+
+    def reproj(self, cams, poses, points, uv, view_idx, delta: float, weight: float = 1.0,
+               dpose: Optional[torch.Tensor] = None):
+        """Returns (residual [M,2], loss [V], dpose [V,6]) (dpose accumulated)."""
+        cams = as_cameras(cams)
+        V = len(cams)
+        dev = self.torch_device
+        points = points.contiguous()
+        uv = uv.contiguous()
+        view_idx = view_idx.to(torch.int32).contiguous()
+        M = int(points.shape[0])
+        _need(poses.contiguous(), 16 * V, "poses", device=dev)
+        _need(points, 3 * M, "points", device=dev)
+        _need(uv, 2 * M, "uv", device=dev)
+        _need(view_idx, M, "view_idx", dtype=torch.int32, device=dev)
+        _need(dpose, 6 * V, "dpose", device=dev)
+        residual = torch.empty(max(M, 1), 2, dtype=torch.float32, device=dev)
+        loss = torch.empty(V, dtype=torch.float32, device=dev)
+        if dpose is None:
+            dpose = torch.zeros(V, 6, dtype=torch.float32, device=dev)
+        rc = self.lib.gs_reproj_residual(self.h, cam_array(cams), _p(poses.contiguous()), V, _p(points), _p(uv),
+                                         _p(view_idx), M, float(delta), float(weight), _p(residual), _p(loss),
+                                         _p(dpose), _stream())
+        self._check(rc)
+        return residual[:M], loss, dpose
+
+    def bin_records(self, cams, n: int, tile: Tuple[int, int], rect: torch.Tensor, depth: torch.Tensor,
+                    capacity: int):
+        """Binning stage alone: returns (values [P] int64, ranges [T,2] int64)."""
+        cams = as_cameras(cams)
+        V = len(cams)
+        dev = self.torch_device
+        nbytes = self.state_bytes(cams, n, capacity, tile)
+        state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        values = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        ntiles = sum(-(-c.width // tile[0]) * -(-c.height // tile[1]) for c in cams)
+        ranges = torch.empty(ntiles, 2, dtype=torch.int32, device=dev)
+        npairs = ctypes.c_int64()
+        rect = rect.contiguous()
+        depth = depth.contiguous()
+        _need(rect, 2 * V * n, "rect", dtype=rect.dtype, device=dev)
+        if rect.dtype not in (torch.int32,):
+            raise ValueError("rect must be int32 (bit pattern of the packed u32 rect)")
+        _need(depth, V * n, "depth", device=dev)
+        rc = self.lib.gs_bin_records(self.h, cam_array(cams), V, n, tile[0], tile[1], _p(rect), _p(depth),
+                                     _p(values), capacity, _p(ranges), ctypes.byref(npairs), _p(state), nbytes,
+                                     _stream())
+        self._check(rc)
+        P = int(npairs.value)
+        u = lambda t: t.to(torch.int64) & 0xFFFFFFFF
+        return u(values[:P]), u(ranges)
+
+    def autotune(self, g: Gaussians, cams, poses, iters: int = 3) -> Tuple[int, int]:
+        cams = as_cameras(cams)
+        tw, th = ctypes.c_int32(), ctypes.c_int32()
+        gst = g.struct()
+        _check_gaussians(g, self.torch_device)
+        _need(poses.contiguous(), 16 * len(cams), "poses", device=self.torch_device)
+        rc = self.lib.gs_autotune(self.h, ctypes.byref(gst), cam_array(cams), _p(poses.contiguous()), len(cams),
+                                  iters, ctypes.byref(tw), ctypes.byref(th), _stream())
+        self._check(rc)
+        return int(tw.value), int(th.value)
+
+
+_default: Dict[int, Context] = {}
+
+
+def default_context(device: Optional[int] = None) -> Context:
+    d = torch.cuda.current_device() if device is None else int(device)
+    if d not in _default:
+        _default[d] = Context(d)
+    return _default[d]
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+
+class GSRenderFn(torch.autograd.Function):
+    """Differentiable batched render: (means, log_scales, quats, opacity
+    logits, colours, poses [V,4,4]) -> (colour, depth, alpha), concatenated
+    over views.  The pose gradient is returned in the left-perturbation
+    tangent of T_cw through ``pose_tangent`` (see ``render``)."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_tangent, poses, gs_ctx, cams,
+                sh_degree, tile):
+        g = Gaussians(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacity_logits.contiguous(),
+                      colors.contiguous(), sh_degree)
+        color, depth, alpha, state, plan = gs_ctx.forward(g, cams, poses, tile=tile)
+        ctx.gs = (gs_ctx, cams, g, poses, state, plan)
+        return color, depth, alpha
+
+    @staticmethod
+    def backward(ctx, dC, dD, dA):
+        gs_ctx, cams, g, poses, state, plan = ctx.gs
+        grads, dpose = gs_ctx.backward(g, cams, poses, state, plan, dC, dD, dA)
+        return (grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.colors, dpose, None, None,
+                None, None, None)
+
+
+def render(g: Gaussians, cams, poses: torch.Tensor, pose_tangent: Optional[torch.Tensor] = None,
+           ctx: Optional[Context] = None, tile=(0, 0)):
+    """Differentiable render of V views.  Gradients flow to g's tensors (if
+    they require grad) and to ``pose_tangent`` ([V,6], the left-perturbation
+    tangent at zero; pass a zero tensor with requires_grad to get d/dxi)."""
+    cams = as_cameras(cams)
+    ctx = ctx or default_context()
+    if pose_tangent is None:
+        pose_tangent = torch.zeros(len(cams), 6, dtype=torch.float32, device=poses.device)
+    return GSRenderFn.apply(g.means, g.log_scales, g.quats, g.opacity_logits, g.colors, pose_tangent,
+                            poses.detach().reshape(len(cams), 16).contiguous(), ctx, cams, g.sh_degree, tuple(tile))
+
+
+# ---------------------------------------------------------------------------
+# mapping / pose-refinement step
+# ---------------------------------------------------------------------------
+
+@dataclass
+class StepOptions:
+    w_color: float = 1.0
+    w_depth: float = 0.1
+    w_reproj: float = 0.0
+    huber_delta: float = 2.0
+    use_gate: bool = False
+    gate_gamma: float = 0.99
+    update_gaussians: bool = False
+    update_poses: bool = False
+    accumulate_grads: bool = False
+    use_graph: bool = True
+    lr_means: float = 1e-4
+    lr_log_scales: float = 1e-3
+    lr_quats: float = 1e-3
+    lr_opacity: float = 5e-2
+    lr_colors: float = 2.5e-3
+    lr_pose: float = 1e-3
+    adam_b1: float = 0.9
+    adam_b2: float = 0.999
+    adam_eps: float = 1e-8
+    tile: Tuple[int, int] = (0, 0)
+
+    def struct(self, capacity: int) -> A.gs_step_opts:
+        return A.gs_step_opts(self.w_color, self.w_depth, self.w_reproj, self.huber_delta, int(self.use_gate),
+                              self.gate_gamma, int(self.update_gaussians), int(self.update_poses),
+                              int(self.accumulate_grads), int(self.use_graph), self.lr_means, self.lr_log_scales,
+                              self.lr_quats, self.lr_opacity, self.lr_colors, self.lr_pose, self.adam_b1,
+                              self.adam_b2, self.adam_eps, self.tile[0], self.tile[1], capacity)
+
+
+# the paper's Fusion Bridge weights (Supplementary, hyper-parameter table):
+# re-projection w1 = 1.5, colour w2 = 0.5, depth w3 = 1, border gate gamma = 0.99
+PAPER_FUSION_BRIDGE = dict(w_reproj=1.5, w_color=0.5, w_depth=1.0, use_gate=True, gate_gamma=0.99)
+
+
+class MappingStep:
+    """Owns the device buffers of ``gs_mapping_step`` for one scene shape and
+    enqueues one step per call (graph-captured by default)."""
+
+    def __init__(self, ctx: Context, g: Gaussians, cams, poses: torch.Tensor, target_color: torch.Tensor,
+                 target_depth: torch.Tensor, opts: StepOptions, mask: Optional[torch.Tensor] = None,
+                 matches: Optional[Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = None,
+                 capacity: Optional[int] = None):
+        self.ctx = ctx
+        self.g = g
+        self.cams = as_cameras(cams)
+        self.V = len(self.cams)
+        self.opts = opts
+        dev = ctx.torch_device
+        self.poses = poses.reshape(self.V, 16).contiguous()
+        self.tc = target_color.contiguous()
+        self.td = target_depth.contiguous()
+        self.mask = None if mask is None else mask.contiguous()
+        if matches is not None:
+            self.points, self.uv, self.vidx = (matches[0].contiguous(), matches[1].contiguous(),
+                                               matches[2].to(torch.int32).contiguous())
+            self.M = int(self.points.shape[0])
+        else:
+            self.points = self.uv = self.vidx = None
+            self.M = 0
+        npix_ = sum(c.npix for c in self.cams)
+        _check_gaussians(g, dev)
+        _need(self.poses, 16 * self.V, "poses", device=dev)
+        _need(self.tc, 3 * npix_, "target_color", device=dev)
+        _need(self.td, npix_, "target_depth", device=dev)
+        _need(self.mask, npix_, "mask", device=dev)
+        if self.M:
+            _need(self.points, 3 * self.M, "points", device=dev)
+            _need(self.uv, 2 * self.M, "uv", device=dev)
+            _need(self.vidx, self.M, "view_idx", dtype=torch.int32, device=dev)
+        if capacity is None:
+            # size from one counting forward pass
+            _, _, _, _, plan = ctx.forward(g, self.cams, self.poses, tile=opts.tile)
+            capacity = int(plan.n_pairs * 1.3) + 4096
+        self.capacity = int(capacity)
+        npix = sum(c.npix for c in self.cams)
+        self.ws_bytes = ctx.workspace_bytes(self.cams, g.n, g.sh_degree, self.capacity, opts.tile)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.grads = g.zeros_like()
+        K = sh_coeffs(g.sh_degree)
+        na = g.n * (11 + 3 * K) + 6 * self.V
+        self.adam_m = torch.zeros(na, dtype=torch.float32, device=dev)
+        self.adam_v = torch.zeros(na, dtype=torch.float32, device=dev)
+        self.adam_step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.color = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+        self.depth = torch.empty(npix, dtype=torch.float32, device=dev)
+        self.alpha = torch.empty(npix, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1 + 3 * self.V, dtype=torch.float32, device=dev)
+        self.dpose = torch.zeros(self.V, 6, dtype=torch.float32, device=dev)
+        self._build_structs()
+
+    def _build_structs(self):
+        self._gst = self.g.struct()
+        self._gg = self.grads.grad_struct()
+        self._adam = A.gs_adam(_p(self.adam_m), _p(self.adam_v), _p(self.adam_step))
+        self._ca = cam_array(self.cams)
+        self._tg = A.gs_targets(_p(self.tc), _p(self.td), _p(self.mask))
+        self._mt = A.gs_matches(_p(self.points), _p(self.uv), _p(self.vidx), self.M)
+        self._opts = self.opts.struct(self.capacity)
+
+    def set_options(self, opts: StepOptions):
+        self.opts = opts
+        self._opts = opts.struct(self.capacity)
+
+    def __call__(self):
+        rc = self.ctx.lib.gs_mapping_step(self.ctx.h, ctypes.byref(self._gst), ctypes.byref(self._gg),
+                                          ctypes.byref(self._adam), self._ca, _p(self.poses), self.V,
+                                          ctypes.byref(self._tg), ctypes.byref(self._mt), ctypes.byref(self._opts),
+                                          _p(self.ws), self.ws_bytes, _p(self.color), _p(self.depth),
+                                          _p(self.alpha), _p(self.loss), _p(self.dpose), _stream())
+        self.ctx._check(rc)
+
+    def profile(self, counts: bool = True):
+        """One eager step with per-stage HIP-event timing on the current
+        stream.  Returns ({stage: ms}, (visited, blended) or None)."""
+        L = self.ctx.lib
+        ns = L.gs_num_stages()
+        ms = (ctypes.c_float * ns)()
+        fc = (ctypes.c_int64 * 2)()
+        o = self.opts.struct(self.capacity)
+        o.use_graph = 0
+        rc = L.gs_step_profile(self.ctx.h, ctypes.byref(self._gst), ctypes.byref(self._gg), ctypes.byref(self._adam),
+                               self._ca, _p(self.poses), self.V, ctypes.byref(self._tg), ctypes.byref(self._mt),
+                               ctypes.byref(o), _p(self.ws), self.ws_bytes, _p(self.color), _p(self.depth),
+                               _p(self.alpha), _p(self.loss), _p(self.dpose), ms, fc if counts else None, _stream())
+        self.ctx._check(rc)
+        names = [L.gs_stage_name(i).decode() for i in range(ns)]
+        return dict(zip(names, list(ms))), ((int(fc[0]), int(fc[1])) if counts else None)
+
+    def status(self) -> Dict[str, int]:
+        fl = ctypes.c_int32()
+        npairs = ctypes.c_int64()
+        nvis = ctypes.c_int64()
+        rc = self.ctx.lib.gs_step_status(self.ctx.h, _p(self.ws), self.ws_bytes, ctypes.byref(fl),
+                                         ctypes.byref(npairs), ctypes.byref(nvis), _stream())
+        self.ctx._check(rc)
+        return {"flags": int(fl.value), "n_pairs": int(npairs.value), "n_visible": int(nvis.value)}

@@ -1,0 +1,795 @@
+// Host runtime behind the C ABI (include/gs.h): argument validation, device
+// buffer layout, launch sequencing, hipGraph capture and replay, and the
+// tile-shape autotuner.  No C++ exception crosses the boundary.
+#include "gs.h"
+#include "gs_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+struct gs_ctx {
+    int device = 0;
+    std::string err;
+    uint32_t* pinned = nullptr;      // 64 u32 of pinned host memory for read-backs
+    double* rp_acc = nullptr;        // per-view re-projection accumulators (standalone calls)
+    unsigned long long* counts = nullptr;  // fragment counters of gs_step_profile (device u64[2])
+    hipStream_t side = nullptr;      // capture / replay stream used when the caller passes the null stream
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int tile_w = 16, tile_h = 16;
+    std::unordered_map<uint64_t, hipGraphExec_t> graphs;
+    std::unordered_map<uint64_t, std::pair<int, int>> tuned;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(gs_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf; else g_create_err = buf;
+    return code;
+}
+
+int hip_fail(gs_ctx* c, hipError_t e, const char* where) {
+    return fail(c, GS_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GS_HIP(ctx, call)                                        \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+    } while (0)
+
+// Makes ctx->device current for the duration of a call and restores the
+// caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool tile_ok(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
+           (tw == 32 && th == 16);
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Validate the cameras and fill the per-view table.
+int build_vt(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int tw, int th, float wc, float wd,
+             gs::ViewTable& vt) {
+    if (!cams) return fail(c, GS_EINVAL, "cams is NULL");
+    if (V < 1 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V=%d outside [1, %d]", V, GS_MAX_VIEWS);
+    if (n < 0) return fail(c, GS_EINVAL, "n=%lld is negative", (long long)n);
+    if ((int64_t)V * n >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "V*n=%lld too large", (long long)V * n);
+    if (!tile_ok(tw, th)) return fail(c, GS_EINVAL, "unsupported tile shape %dx%d", tw, th);
+    std::memset(&vt, 0, sizeof vt);
+    vt.V = V;
+    vt.tw = tw;
+    vt.th = th;
+    vt.n = (int)n;
+    int64_t toff = 0, poff = 0;
+    for (int v = 0; v < V; v++) {
+        const gs_camera& cm = cams[v];
+        if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
+            return fail(c, GS_EINVAL, "view %d: size %dx%d outside [1, 16384]", v, cm.width, cm.height);
+        if (!(cm.fx > 0.f) || !(cm.fy > 0.f) || !std::isfinite(cm.fx) || !std::isfinite(cm.fy) ||
+            !std::isfinite(cm.cx) || !std::isfinite(cm.cy))
+            return fail(c, GS_EINVAL, "view %d: bad intrinsics", v);
+        gs::ViewInfo& vi = vt.v[v];
+        vi.W = cm.width;
+        vi.H = cm.height;
+        vi.tiles_x = (int)ceil_div(cm.width, tw);
+        vi.tiles_y = (int)ceil_div(cm.height, th);
+        vi.tile_off = (int)toff;
+        vi.pix_off = (int)poff;
+        vi.fx = cm.fx; vi.fy = cm.fy; vi.cx = cm.cx; vi.cy = cm.cy;
+        const double np = (double)cm.width * cm.height;
+        vi.lsc = (float)((double)wc / ((double)V * 3.0 * np));
+        vi.lsd = (float)((double)wd / ((double)V * np));
+        toff += (int64_t)vi.tiles_x * vi.tiles_y;
+        poff += (int64_t)cm.width * cm.height;
+        if (3 * poff >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "too many pixels in total");
+    }
+    vt.n_tiles = (int)toff;
+    vt.n_pix = (int)poff;
+    return GS_OK;
+}
+
+int check_gaussians(gs_ctx* c, const gs_gaussians* g) {
+    if (!g) return fail(c, GS_EINVAL, "gaussians is NULL");
+    if (g->n < 0) return fail(c, GS_EINVAL, "n is negative");
+    if (g->sh_degree < -1 || g->sh_degree > 3) return fail(c, GS_EINVAL, "sh_degree=%d outside [-1, 3]", g->sh_degree);
+    if (g->n > 0) {
+        if (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->colors)
+            return fail(c, GS_EINVAL, "a Gaussian parameter pointer is NULL");
+        if (((uintptr_t)g->quats) % 16) return fail(c, GS_EINVAL, "quats must be 16-byte aligned");
+    }
+    return GS_OK;
+}
+
+gs::Params params_of(const gs_gaussians* g) {
+    gs::Params P;
+    P.means = g->means;
+    P.ls = g->log_scales;
+    P.q = g->quats;
+    P.opl = g->opacity_logits;
+    P.col = g->colors;
+    P.n = (int)g->n;
+    P.sh = g->sh_degree;
+    return P;
+}
+
+int tile_passes(int64_t n_tiles) {
+    int b = 0;
+    while (((int64_t)1 << b) < n_tiles) b++;
+    return (b + 7) / 8;
+}
+
+struct Ptrs {
+    gs::Records rec;
+    uint2* ranges;
+    float* tfin;
+    uint32_t* last;
+    float* g2;
+    double* posepart;
+    uint32_t* scal;
+    uint32_t* vals;   // sorted pair values (valid after binning)
+    float* dC;
+    float* dD;
+    double2* tilepart;
+    double* rpacc;
+};
+
+Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
+    Ptrs p;
+    p.rec.xy = reinterpret_cast<float2*>(base + L.off_xy);
+    p.rec.conic = reinterpret_cast<float4*>(base + L.off_conic);
+    p.rec.col = reinterpret_cast<float4*>(base + L.off_col);
+    p.rec.rect = reinterpret_cast<uint2*>(base + L.off_rect);
+    p.rec.nt = reinterpret_cast<uint32_t*>(base + L.off_nt);
+    p.ranges = reinterpret_cast<uint2*>(base + L.off_ranges);
+    p.tfin = reinterpret_cast<float*>(base + L.off_tfin);
+    p.last = reinterpret_cast<uint32_t*>(base + L.off_last);
+    p.g2 = reinterpret_cast<float*>(base + L.off_g2);
+    p.posepart = reinterpret_cast<double*>(base + L.off_posepart);
+    p.scal = reinterpret_cast<uint32_t*>(base + L.off_scalars);
+    p.vals = reinterpret_cast<uint32_t*>(base + ((tile_passes(L.n_tiles) & 1) ? L.off_pv1 : L.off_pv0));
+    p.dC = workspace ? reinterpret_cast<float*>(base + L.off_dC) : nullptr;
+    p.dD = workspace ? reinterpret_cast<float*>(base + L.off_dD) : nullptr;
+    p.tilepart = workspace ? reinterpret_cast<double2*>(base + L.off_tilepart) : nullptr;
+    p.rpacc = workspace ? reinterpret_cast<double*>(base + L.off_rpacc) : nullptr;
+    return p;
+}
+
+void resolve_tile(const gs_ctx* c, int32_t tw, int32_t th, int& otw, int& oth) {
+    if (tw == 0 && th == 0) {
+        otw = c->tile_w;
+        oth = c->tile_h;
+    } else {
+        otw = tw;
+        oth = th;
+    }
+}
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; i++) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+namespace gs {
+
+Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace) {
+    Layout L;
+    std::memset(&L, 0, sizeof L);
+    L.R = (int64_t)vt.V * n;
+    L.cap = cap;
+    L.n_tiles = vt.n_tiles;
+    L.n_pix = vt.n_pix;
+    const int64_t R = L.R;
+    L.sort_blocks = ceil_div(std::max<int64_t>(std::max<int64_t>(R, cap), 1), 4096);
+    L.pose_blocks = ceil_div(n, 256);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.off_scalars = take((size_t)kNumScalars * 4);   // first: gs_step_status finds it at offset 0
+    L.off_xy = take((size_t)R * 8);
+    L.off_conic = take((size_t)R * 16);
+    L.off_col = take((size_t)R * 16);
+    L.off_rect = take((size_t)R * 8);
+    L.off_nt = take((size_t)R * 4);
+    L.off_k0 = take((size_t)R * 4);
+    L.off_v0 = take((size_t)R * 4);
+    L.off_k1 = take((size_t)R * 4);
+    L.off_v1 = take((size_t)R * 4);
+    L.off_cnt = take((size_t)R * 4);
+    L.off_pk0 = take((size_t)cap * 4);
+    L.off_pv0 = take((size_t)cap * 4);
+    L.off_pk1 = take((size_t)cap * 4);
+    L.off_pv1 = take((size_t)cap * 4);
+    L.off_hist = take((size_t)256 * L.sort_blocks * 4);
+    const int64_t nscan = std::max<int64_t>(std::max<int64_t>(ceil_div(R, 2048), ceil_div(256 * L.sort_blocks, 2048)), 1);
+    L.off_scan = take((size_t)nscan * 4);
+    L.off_ranges = take((size_t)vt.n_tiles * 8);
+    L.off_tfin = take((size_t)vt.n_pix * 4);
+    L.off_last = take((size_t)vt.n_pix * 4);
+    L.off_g2 = take((size_t)R * kG2Stride * 4);
+    L.off_posepart = take((size_t)vt.V * std::max<int64_t>(L.pose_blocks, 1) * 6 * 8);
+    if (workspace) {
+        L.off_dC = take((size_t)vt.n_pix * 3 * 4);
+        L.off_dD = take((size_t)vt.n_pix * 4);
+        L.off_tilepart = take((size_t)vt.n_tiles * 16);
+        L.off_rpacc = take((size_t)vt.V * 8 * 8);
+    }
+    L.bytes = o;
+    return L;
+}
+
+}  // namespace gs
+
+// ============================================================================ ABI
+
+extern "C" {
+
+int gs_abi_version(void) { return GS_ABI_VERSION; }
+
+int gs_create(gs_ctx** out, int device) {
+    if (!out) return fail(nullptr, GS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return fail(nullptr, GS_EDEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (device < 0 || device >= ndev) return fail(nullptr, GS_EINVAL, "device %d outside [0, %d)", device, ndev);
+    gs_ctx* c = new (std::nothrow) gs_ctx();
+    if (!c) return fail(nullptr, GS_ENOMEM, "out of host memory");
+    c->device = device;
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+        delete c;
+        return fail(nullptr, GS_EDEVICE, "hipSetDevice(%d) failed", device);
+    }
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 64 * sizeof(uint32_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(nullptr, GS_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    e = hipMalloc(reinterpret_cast<void**>(&c->rp_acc), (size_t)GS_MAX_VIEWS * 8 * sizeof(double) + 256);
+    if (e == hipSuccess)
+        c->counts = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(c->rp_acc) +
+                                                          (size_t)GS_MAX_VIEWS * 8 * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return fail(nullptr, GS_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return GS_OK;
+}
+
+void gs_destroy(gs_ctx* c) {
+    if (!c) return;
+    DeviceGuard dg(c->device);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->rp_acc) (void)hipFree(c->rp_acc);
+    delete c;
+}
+
+const char* gs_last_error(const gs_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int gs_set_tile(gs_ctx* c, int32_t tw, int32_t th) {
+    if (!c) return GS_EINVAL;
+    if (tw == 0 && th == 0) { tw = 16; th = 16; }
+    if (!tile_ok(tw, th)) return fail(c, GS_EINVAL, "unsupported tile shape %dx%d", tw, th);
+    c->tile_w = tw;
+    c->tile_h = th;
+    return GS_OK;
+}
+
+size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t cap, int32_t tw, int32_t th) {
+    gs::ViewTable vt;
+    if (tw == 0 && th == 0) { tw = 16; th = 16; }
+    if (cap < 0 || cap >= ((int64_t)1 << 31)) return 0;
+    if (build_vt(nullptr, cams, V, n, tw, th, 0.f, 0.f, vt) != GS_OK) return 0;
+    return gs::make_layout(vt, n, cap, false).bytes;
+}
+
+size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int32_t sh, int64_t cap, int32_t tw,
+                               int32_t th) {
+    (void)sh;
+    gs::ViewTable vt;
+    if (tw == 0 && th == 0) { tw = 16; th = 16; }
+    if (cap < 0 || cap >= ((int64_t)1 << 31)) return 0;
+    if (build_vt(nullptr, cams, V, n, tw, th, 0.f, 0.f, vt) != GS_OK) return 0;
+    return gs::make_layout(vt, n, cap, true).bytes;
+}
+
+int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                      float* color, float* depth, float* alpha, void* state, size_t state_bytes, gs_plan* plan,
+                      void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!plan) return fail(c, GS_EINVAL, "plan is NULL");
+    int r = check_gaussians(c, g);
+    if (r) return r;
+    if (!poses || !color || !depth || !alpha || !state) return fail(c, GS_EINVAL, "a device pointer is NULL");
+    if (plan->pair_capacity < 0 || plan->pair_capacity >= ((int64_t)1 << 31))
+        return fail(c, GS_EINVAL, "pair_capacity outside [0, 2^31)");
+    int tw, th;
+    resolve_tile(c, plan->tile_w, plan->tile_h, tw, th);
+    gs::ViewTable vt;
+    if ((r = build_vt(c, cams, V, g->n, tw, th, 0.f, 0.f, vt))) return r;
+    const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false);
+    if (state_bytes < L.bytes)
+        return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(state);
+    Ptrs p = ptrs_of(L, base, false);
+    const gs::Params P = params_of(g);
+    plan->tile_w = tw;
+    plan->tile_h = th;
+    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, nullptr, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, nullptr, s));
+    GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
+    GS_HIP(c, hipStreamSynchronize(s));
+    const int64_t total = (int64_t)((uint64_t)c->pinned[gs::kPairsLo] | ((uint64_t)c->pinned[gs::kPairsHi] << 32));
+    plan->n_pairs = total;
+    plan->n_visible = c->pinned[gs::kNVis];
+    if (total > plan->pair_capacity)
+        return fail(c, GS_ECAPACITY, "%lld pairs exceed the capacity %lld", (long long)total,
+                    (long long)plan->pair_capacity);
+    uint32_t* vals = nullptr;
+    GS_HIP(c, gs::launch_binning_emit(vt, L, base, p.rec.rect, total, s, &vals));
+    if (total > 0 && vals != p.vals) return fail(c, GS_EDEVICE, "internal: sorted values in unexpected buffer");
+    GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, p.vals, p.rec, color, depth, alpha, p.tfin, p.last, nullptr, s));
+    return GS_OK;
+}
+
+int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                       void* state, size_t state_bytes, const gs_plan* plan, const float* dC, const float* dD,
+                       const float* dA, gs_gaussian_grads* grads, float* dL_dpose, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!plan) return fail(c, GS_EINVAL, "plan is NULL");
+    int r = check_gaussians(c, g);
+    if (r) return r;
+    if (!poses || !state || !dL_dpose || !grads) return fail(c, GS_EINVAL, "a device pointer is NULL");
+    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->colors))
+        return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if (!tile_ok(plan->tile_w, plan->tile_h)) return fail(c, GS_EINVAL, "plan does not come from a forward pass");
+    if (plan->n_pairs > plan->pair_capacity) return fail(c, GS_ECAPACITY, "the forward pass overflowed");
+    gs::ViewTable vt;
+    if ((r = build_vt(c, cams, V, g->n, plan->tile_w, plan->tile_h, 0.f, 0.f, vt))) return r;
+    const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false);
+    if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ptrs p = ptrs_of(L, static_cast<char*>(state), false);
+    const gs::Params P = params_of(g);
+    gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
+    GS_HIP(c, gs::launch_zero_g2(p.rec.nt, p.g2, L.R, s));
+    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, s));
+    GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, 0, p.posepart, L.pose_blocks, s));
+    GS_HIP(c, gs::launch_pose_finalize(vt, p.posepart, L.pose_blocks, nullptr, 0.f, dL_dpose, s));
+    return GS_OK;
+}
+
+int gs_reproj_residual(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, const float* points,
+                       const float* uv, const int32_t* view_idx, int64_t M, float delta, float weight,
+                       float* residual, float* loss, float* dL_dpose, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (M < 0) return fail(c, GS_EINVAL, "M is negative");
+    if (M >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "M too large");
+    if (!(delta > 0.f)) return fail(c, GS_EINVAL, "huber_delta must be positive");
+    if (!poses || !loss || !dL_dpose) return fail(c, GS_EINVAL, "a device pointer is NULL");
+    if (M > 0 && (!points || !uv || !view_idx || !residual)) return fail(c, GS_EINVAL, "a match pointer is NULL");
+    gs::ViewTable vt;
+    int r = build_vt(c, cams, V, 0, 16, 16, 0.f, 0.f, vt);
+    if (r) return r;
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GS_HIP(c, gs::launch_zero_f64(c->rp_acc, 8 * V, s));
+    GS_HIP(c, gs::launch_reproj(vt, poses, points, uv, view_idx, M, delta, residual, c->rp_acc, s));
+    GS_HIP(c, gs::launch_reproj_finalize(vt, c->rp_acc, weight, loss, dL_dpose, s));
+    return GS_OK;
+}
+
+namespace {
+
+// Stages of one step, timed by gs_step_profile.
+const char* const kStageNames[] = {"preprocess_fwd", "binning", "composite_fwd", "loss_reproj", "composite_bwd",
+                                   "preprocess_bwd", "optimizer"};
+constexpr int kNumStages = 7;
+
+int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::Layout& L, char* base, gs_gaussians* g,
+                 gs_gaussian_grads* grads, const gs_adam* adam, float* poses, const gs_targets* tg,
+                 const gs_matches* mt, const gs_step_opts* o, float* color, float* depth, float* alpha,
+                 float* loss_out, float* dL_dpose, hipStream_t s, hipEvent_t* ev = nullptr,
+                 unsigned long long* counts = nullptr) {
+    Ptrs p = ptrs_of(L, base, true);
+    const gs::Params P = params_of(g);
+    gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
+    auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
+    GS_HIP(c, mark(0));
+    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, p.g2, s));
+    GS_HIP(c, mark(1));
+    uint32_t* vals = nullptr;
+    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.nt, p.rec.rect, nullptr, L.cap, s, &vals));
+    GS_HIP(c, mark(2));
+    gs::LossArgs la{tg->color, tg->depth, tg->mask, o->use_gate, o->gate_gamma, p.dC, p.dD, p.tilepart};
+    GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, s,
+                                       counts));
+    GS_HIP(c, mark(3));
+    const bool rp = mt && mt->M > 0;
+    GS_HIP(c, gs::launch_zero_f64(p.rpacc, 8 * vt.V, s));
+    if (rp)
+        GS_HIP(c, gs::launch_reproj(vt, poses, mt->points, mt->uv, mt->view_idx, mt->M, o->huber_delta, nullptr,
+                                    p.rpacc, s));
+    GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, o->w_color, o->w_depth, o->w_reproj,
+                                     loss_out, s));
+    GS_HIP(c, mark(4));
+    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, s));
+    GS_HIP(c, mark(5));
+    GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, o->accumulate_grads, p.posepart, L.pose_blocks,
+                                        s));
+    GS_HIP(c, gs::launch_pose_finalize(vt, p.posepart, L.pose_blocks, rp ? p.rpacc : nullptr,
+                                       o->w_reproj / (float)vt.V, dL_dpose, s));
+    GS_HIP(c, mark(6));
+    if (o->update_gaussians || o->update_poses) {
+        const int64_t n = g->n;
+        const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
+        const int64_t np = n * (11 + 3 * K);
+        if (o->update_gaussians) {
+            gs::AdamGroups ag;
+            float* pp[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->colors};
+            const float* gg[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
+            const int64_t cnt[5] = {3 * n, 3 * n, 4 * n, n, 3 * K * n};
+            const float lr[5] = {o->lr_means, o->lr_log_scales, o->lr_quats, o->lr_opacity, o->lr_colors};
+            for (int i = 0; i < 5; i++) {
+                ag.p[i] = pp[i];
+                ag.g[i] = gg[i];
+                ag.cnt[i] = cnt[i];
+                ag.lr[i] = lr[i];
+            }
+            GS_HIP(c, gs::launch_adam(ag, adam->m, adam->v, adam->step, o->adam_b1, o->adam_b2, o->adam_eps, 0, s));
+        }
+        if (o->update_poses)
+            GS_HIP(c, gs::launch_pose_update(vt.V, poses, dL_dpose, adam->m + np, adam->v + np, adam->step,
+                                             o->lr_pose, o->adam_b1, o->adam_b2, o->adam_eps, 0, s));
+        GS_HIP(c, gs::launch_step_bump(adam->step, s));
+    }
+    GS_HIP(c, mark(7));
+    return GS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+int check_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_adam* adam, const gs_camera* cams,
+               float* poses, int32_t V, const gs_targets* tg, const gs_matches* mt, const gs_step_opts* o, void* ws,
+               size_t ws_bytes, float* color, float* depth, float* alpha, float* loss_out, float* dL_dpose,
+               gs::ViewTable& vt, gs::Layout& L) {
+    if (!o) return fail(c, GS_EINVAL, "opts is NULL");
+    int r = check_gaussians(c, g);
+    if (r) return r;
+    if (!grads || !poses || !tg || !ws || !color || !depth || !alpha || !loss_out || !dL_dpose)
+        return fail(c, GS_EINVAL, "a required pointer is NULL");
+    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->colors))
+        return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if (!tg->color || !tg->depth) return fail(c, GS_EINVAL, "target colour / depth is NULL");
+    if (mt && mt->M > 0) {
+        if (!mt->points || !mt->uv || !mt->view_idx) return fail(c, GS_EINVAL, "a match pointer is NULL");
+        if (mt->M >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "M too large");
+        if (!(o->huber_delta > 0.f)) return fail(c, GS_EINVAL, "huber_delta must be positive");
+    }
+    if (mt && mt->M < 0) return fail(c, GS_EINVAL, "M is negative");
+    if ((o->update_gaussians || o->update_poses) && (!adam || !adam->m || !adam->v || !adam->step))
+        return fail(c, GS_EINVAL, "an update needs the Adam state");
+    if (o->pair_capacity < 0 || o->pair_capacity >= ((int64_t)1 << 31))
+        return fail(c, GS_EINVAL, "pair_capacity outside [0, 2^31)");
+    int tw, th;
+    resolve_tile(c, o->tile_w, o->tile_h, tw, th);
+    if ((r = build_vt(c, cams, V, g->n, tw, th, o->w_color, o->w_depth, vt))) return r;
+    L = gs::make_layout(vt, g->n, o->pair_capacity, true);
+    if (ws_bytes < L.bytes) return fail(c, GS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
+    return GS_OK;
+}
+
+}  // namespace
+
+int gs_mapping_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_adam* adam,
+                    const gs_camera* cams, float* poses, int32_t V, const gs_targets* tg, const gs_matches* mt,
+                    const gs_step_opts* o, void* ws, size_t ws_bytes, float* color, float* depth, float* alpha,
+                    float* loss_out, float* dL_dpose, void* stream) {
+    if (!c) return GS_EINVAL;
+    gs::ViewTable vt;
+    gs::Layout L;
+    int r = check_step(c, g, grads, adam, cams, poses, V, tg, mt, o, ws, ws_bytes, color, depth, alpha, loss_out,
+                       dL_dpose, vt, L);
+    if (r) return r;
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    if (!o->use_graph)
+        return enqueue_step(c, vt, L, base, g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
+                            dL_dpose, s);
+    // the null stream cannot be captured: capture and replay on the context's
+    // own stream, ordered after the caller's earlier work and before its later
+    // work by events
+    const bool on_side = (s == nullptr);
+    if (on_side) {
+        if (!c->side) {
+            GS_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+            GS_HIP(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+            GS_HIP(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+        }
+        GS_HIP(c, hipEventRecord(c->ev_in, s));
+        GS_HIP(c, hipStreamWaitEvent(c->side, c->ev_in, 0));
+        s = c->side;
+    }
+    // cache key: every argument the captured launches bake in
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &vt, sizeof vt);
+    h = fnv(h, g, sizeof *g);
+    h = fnv(h, grads, sizeof *grads);
+    gs_adam ad = adam ? *adam : gs_adam{nullptr, nullptr, nullptr};
+    h = fnv(h, &ad, sizeof ad);
+    h = fnv(h, &poses, sizeof poses);
+    h = fnv(h, tg, sizeof *tg);
+    gs_matches mm = mt ? *mt : gs_matches{nullptr, nullptr, nullptr, 0};
+    h = fnv(h, &mm, sizeof mm);
+    h = fnv(h, o, sizeof *o);
+    void* outs[7] = {ws, color, depth, alpha, loss_out, dL_dpose, (void*)s};
+    h = fnv(h, outs, sizeof outs);
+    auto it = c->graphs.find(h);
+    if (it == c->graphs.end()) {
+        GS_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_step(c, vt, L, base, g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
+                              dL_dpose, s);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (rc != GS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(c, GS_ECAPTURE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(c, GS_ECAPTURE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        it = c->graphs.emplace(h, exec).first;
+    }
+    GS_HIP(c, hipGraphLaunch(it->second, s));
+    if (on_side) {
+        GS_HIP(c, hipEventRecord(c->ev_out, s));
+        GS_HIP(c, hipStreamWaitEvent(nullptr, c->ev_out, 0));
+    }
+    return GS_OK;
+}
+
+int gs_num_stages(void) { return kNumStages; }
+
+const char* gs_stage_name(int i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : nullptr; }
+
+int gs_step_profile(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_adam* adam,
+                    const gs_camera* cams, float* poses, int32_t V, const gs_targets* tg, const gs_matches* mt,
+                    const gs_step_opts* o, void* ws, size_t ws_bytes, float* color, float* depth, float* alpha,
+                    float* loss_out, float* dL_dpose, float* stage_ms, int64_t* frag_counts, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!stage_ms) return fail(c, GS_EINVAL, "stage_ms is NULL");
+    gs::ViewTable vt;
+    gs::Layout L;
+    int r = check_step(c, g, grads, adam, cams, poses, V, tg, mt, o, ws, ws_bytes, color, depth, alpha, loss_out,
+                       dL_dpose, vt, L);
+    if (r) return r;
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[kNumStages + 1];
+    for (int i = 0; i <= kNumStages; i++) GS_HIP(c, hipEventCreate(&ev[i]));
+    auto destroy = [&]() {
+        for (int i = 0; i <= kNumStages; i++) (void)hipEventDestroy(ev[i]);
+    };
+    hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t*>(c->counts), 0u, 4, s);
+    if (e != hipSuccess) { destroy(); return hip_fail(c, e, "counter fill"); }
+    r = enqueue_step(c, vt, L, static_cast<char*>(ws), g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
+                     dL_dpose, s, ev, frag_counts ? c->counts : nullptr);
+    if (r) { destroy(); return r; }
+    unsigned long long hc[2] = {0, 0};
+    e = hipMemcpyAsync(hc, c->counts, sizeof hc, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { destroy(); return hip_fail(c, e, "profile read-back"); }
+    for (int i = 0; i < kNumStages; i++) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        if (e != hipSuccess) { destroy(); return hip_fail(c, e, "hipEventElapsedTime"); }
+        stage_ms[i] = ms;
+    }
+    if (frag_counts) {
+        frag_counts[0] = (int64_t)hc[0];
+        frag_counts[1] = (int64_t)hc[1];
+    }
+    destroy();
+    return GS_OK;
+}
+
+int gs_step_status(gs_ctx* c, const void* ws, size_t ws_bytes, int32_t* flags, int64_t* n_pairs, int64_t* n_visible,
+                   void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!ws || ws_bytes < gs::kNumScalars * 4) return fail(c, GS_EINVAL, "workspace is NULL or too small");
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GS_HIP(c, hipMemcpyAsync(c->pinned, ws, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
+    GS_HIP(c, hipStreamSynchronize(s));
+    if (flags) *flags = (int32_t)c->pinned[gs::kFlags];
+    if (n_pairs) *n_pairs = (int64_t)((uint64_t)c->pinned[gs::kPairsLo] | ((uint64_t)c->pinned[gs::kPairsHi] << 32));
+    if (n_visible) *n_visible = c->pinned[gs::kNVis];
+    return GS_OK;
+}
+
+int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32_t tw, int32_t th,
+                   const uint32_t* rect, const float* depth, uint32_t* values, int64_t cap, uint32_t* ranges,
+                   int64_t* n_pairs, void* state, size_t state_bytes, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!n_pairs) return fail(c, GS_EINVAL, "n_pairs is NULL");
+    if (!state || !ranges || (n > 0 && (!rect || !depth)) || (cap > 0 && !values))
+        return fail(c, GS_EINVAL, "a device pointer is NULL");
+    if (cap < 0 || cap >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "values_capacity outside [0, 2^31)");
+    gs::ViewTable vt;
+    int r = build_vt(c, cams, V, n, tw, th, 0.f, 0.f, vt);
+    if (r) return r;
+    const gs::Layout L = gs::make_layout(vt, n, cap, false);
+    if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(state);
+    Ptrs p = ptrs_of(L, base, false);
+    const uint2* rc = reinterpret_cast<const uint2*>(rect);
+    GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.rect, p.rec.nt, n, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, depth, s));
+    GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
+    GS_HIP(c, hipStreamSynchronize(s));
+    const int64_t total = (int64_t)((uint64_t)c->pinned[gs::kPairsLo] | ((uint64_t)c->pinned[gs::kPairsHi] << 32));
+    *n_pairs = total;
+    if (total > cap)
+        return fail(c, GS_ECAPACITY, "%lld pairs exceed the capacity %lld", (long long)total, (long long)cap);
+    uint32_t* vals = nullptr;
+    GS_HIP(c, gs::launch_binning_emit(vt, L, base, p.rec.rect, total, s, &vals));
+    if (total > 0) GS_HIP(c, hipMemcpyAsync(values, vals, (size_t)total * 4, hipMemcpyDeviceToDevice, s));
+    GS_HIP(c, hipMemcpyAsync(ranges, p.ranges, (size_t)L.n_tiles * 8, hipMemcpyDeviceToDevice, s));
+    return GS_OK;
+}
+
+int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                int32_t iters, int32_t* tile_w, int32_t* tile_h, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!tile_w || !tile_h) return fail(c, GS_EINVAL, "tile_w / tile_h is NULL");
+    int r = check_gaussians(c, g);
+    if (r) return r;
+    if (!poses) return fail(c, GS_EINVAL, "poses is NULL");
+    if (iters < 1) iters = 1;
+    gs::ViewTable vt0;
+    if ((r = build_vt(c, cams, V, g->n, 16, 16, 0.f, 0.f, vt0))) return r;
+    uint64_t key = 1469598103934665603ull;
+    key = fnv(key, &V, sizeof V);
+    key = fnv(key, cams, sizeof(gs_camera) * V);
+    key = fnv(key, &g->n, sizeof g->n);
+    key = fnv(key, &g->sh_degree, sizeof g->sh_degree);
+    auto hit = c->tuned.find(key);
+    if (hit != c->tuned.end()) {
+        c->tile_w = *tile_w = hit->second.first;
+        c->tile_h = *tile_h = hit->second.second;
+        return GS_OK;
+    }
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = g->n;
+    const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
+    const int64_t npix = vt0.n_pix;
+    // scratch: images, upstream gradients (ones), Gaussian and pose gradients
+    std::vector<void*> bufs;
+    auto dalloc = [&](size_t bytes) -> void* {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes ? bytes : 4) != hipSuccess) return nullptr;
+        bufs.push_back(p);
+        return p;
+    };
+    auto release = [&]() {
+        for (void* p : bufs) (void)hipFree(p);
+        bufs.clear();
+    };
+    float* img = static_cast<float*>(dalloc((size_t)npix * 5 * 4));
+    float* gr = static_cast<float*>(dalloc((size_t)n * (11 + 3 * K) * 4));
+    float* dpose = static_cast<float*>(dalloc((size_t)V * 6 * 4));
+    if (!img || !gr || !dpose) {
+        release();
+        return fail(c, GS_ENOMEM, "autotune scratch allocation failed");
+    }
+    if (gs::launch_fill_f32(img, 1e-3f, npix * 5, s) != hipSuccess) {
+        release();
+        return fail(c, GS_EDEVICE, "autotune fill failed");
+    }
+    gs_gaussian_grads G{gr, gr + 3 * n, gr + 6 * n, gr + 10 * n, gr + 11 * n};
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int cand[5][2] = {{16, 16}, {16, 8}, {8, 8}, {32, 8}, {32, 16}};
+    float best = 1e30f;
+    int bw = 16, bh = 16;
+    int rc = GS_OK;
+    for (int k = 0; k < 5 && rc == GS_OK; k++) {
+        gs_plan plan{cand[k][0], cand[k][1], 0, 0, 0};
+        // size the state from a count-only forward at zero capacity
+        void* st = nullptr;
+        size_t sb = gs_state_bytes(cams, V, n, 0, plan.tile_w, plan.tile_h);
+        if (hipMalloc(&st, sb) != hipSuccess) { rc = fail(c, GS_ENOMEM, "autotune state"); break; }
+        int f = gs_render_forward(c, g, cams, poses, V, img, img + 3 * npix, img + 4 * npix, st, sb, &plan, stream);
+        (void)hipFree(st);
+        if (f != GS_OK && f != GS_ECAPACITY) { rc = f; break; }
+        plan.pair_capacity = plan.n_pairs;
+        sb = gs_state_bytes(cams, V, n, plan.pair_capacity, plan.tile_w, plan.tile_h);
+        if (hipMalloc(&st, sb) != hipSuccess) { rc = fail(c, GS_ENOMEM, "autotune state"); break; }
+        float total = 0.f;
+        for (int it = 0; it <= iters && rc == GS_OK; it++) {
+            (void)hipEventRecord(e0, s);
+            int a = gs_render_forward(c, g, cams, poses, V, img, img + 3 * npix, img + 4 * npix, st, sb, &plan, stream);
+            int b = a == GS_OK ? gs_render_backward(c, g, cams, poses, V, st, sb, &plan, img, img + 3 * npix,
+                                                    img + 4 * npix, &G, dpose, stream)
+                               : a;
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            if (b != GS_OK) { rc = b; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (it > 0) total += ms;
+        }
+        (void)hipFree(st);
+        if (rc == GS_OK && total < best) {
+            best = total;
+            bw = cand[k][0];
+            bh = cand[k][1];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    release();
+    if (rc != GS_OK) return rc;
+    c->tuned[key] = {bw, bh};
+    c->tile_w = *tile_w = bw;
+    c->tile_h = *tile_h = bh;
+    return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,272 @@
+// Device-side math of the forward model and its derivatives (FP32).
+//
+// Projection (Sec. 3.4 "Projection"): camera transform, pinhole mean, local
+// affine (EWA) footprint J Sigma_c J^T + 0.3 I, conic, opacity-aware support.
+// Compositing weight of one fragment (Sec. 3.4 colour / depth equations).
+#pragma once
+
+#include "gs_internal.h"
+
+namespace gs {
+
+// rotation of a unit quaternion (w, x, y, z), row-major
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float* R) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+    R[0] = 1.f - 2.f * (yy + zz); R[1] = 2.f * (xy - wz);       R[2] = 2.f * (xz + wy);
+    R[3] = 2.f * (xy + wz);       R[4] = 1.f - 2.f * (xx + zz); R[5] = 2.f * (yz - wx);
+    R[6] = 2.f * (xz - wy);       R[7] = 2.f * (yz + wx);       R[8] = 1.f - 2.f * (xx + yy);
+}
+
+// Real orthonormal SH basis up to degree 3 at unit direction d, index
+// l*l + l + m; optionally the gradient of each polynomial w.r.t. (x, y, z).
+template <bool GRAD>
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y, float (*dY)[3]) {
+    constexpr float PI = 3.14159265358979323846f;
+    const float c0 = 0.28209479177387814f;            // 1/(2 sqrt(pi))
+    const float c1 = 0.48860251190291992f;            // sqrt(3/(4 pi))
+    const float c2a = 1.0925484305920792f;            // sqrt(15/pi)/2
+    const float c2b = 0.31539156525252005f;           // sqrt(5/pi)/4
+    const float c2c = 0.54627421529603959f;           // sqrt(15/pi)/4
+    const float c3a = 0.59004358992664352f;           // sqrt(35/(2 pi))/4
+    const float c3b = 2.8906114426405538f;            // sqrt(105/pi)/2
+    const float c3c = 0.45704579946446572f;           // sqrt(21/(2 pi))/4
+    const float c3d = 0.37317633259011546f;           // sqrt(7/pi)/4
+    const float c3e = 1.4453057213202769f;            // sqrt(105/pi)/4
+    (void)PI;
+    Y[0] = c0;
+    if (GRAD) { dY[0][0] = dY[0][1] = dY[0][2] = 0.f; }
+    if (deg < 1) return;
+    Y[1] = -c1 * y; Y[2] = c1 * z; Y[3] = -c1 * x;
+    if (GRAD) {
+        dY[1][0] = 0.f; dY[1][1] = -c1; dY[1][2] = 0.f;
+        dY[2][0] = 0.f; dY[2][1] = 0.f; dY[2][2] = c1;
+        dY[3][0] = -c1; dY[3][1] = 0.f; dY[3][2] = 0.f;
+    }
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = c2a * x * y;
+    Y[5] = -c2a * y * z;
+    Y[6] = c2b * (2.f * zz - xx - yy);
+    Y[7] = -c2a * x * z;
+    Y[8] = c2c * (xx - yy);
+    if (GRAD) {
+        dY[4][0] = c2a * y;         dY[4][1] = c2a * x;         dY[4][2] = 0.f;
+        dY[5][0] = 0.f;             dY[5][1] = -c2a * z;        dY[5][2] = -c2a * y;
+        dY[6][0] = -2.f * c2b * x;  dY[6][1] = -2.f * c2b * y;  dY[6][2] = 4.f * c2b * z;
+        dY[7][0] = -c2a * z;        dY[7][1] = 0.f;             dY[7][2] = -c2a * x;
+        dY[8][0] = 2.f * c2c * x;   dY[8][1] = -2.f * c2c * y;  dY[8][2] = 0.f;
+    }
+    if (deg < 3) return;
+    Y[9] = -c3a * y * (3.f * xx - yy);
+    Y[10] = c3b * x * y * z;
+    Y[11] = -c3c * y * (4.f * zz - xx - yy);
+    Y[12] = c3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+    Y[13] = -c3c * x * (4.f * zz - xx - yy);
+    Y[14] = c3e * z * (xx - yy);
+    Y[15] = -c3a * x * (xx - 3.f * yy);
+    if (GRAD) {
+        dY[9][0] = -6.f * c3a * x * y;  dY[9][1] = -3.f * c3a * (xx - yy);  dY[9][2] = 0.f;
+        dY[10][0] = c3b * y * z;        dY[10][1] = c3b * x * z;            dY[10][2] = c3b * x * y;
+        dY[11][0] = 2.f * c3c * x * y;  dY[11][1] = -c3c * (4.f * zz - xx - 3.f * yy);
+        dY[11][2] = -8.f * c3c * y * z;
+        dY[12][0] = -6.f * c3d * x * z; dY[12][1] = -6.f * c3d * y * z;
+        dY[12][2] = c3d * (6.f * zz - 3.f * xx - 3.f * yy);
+        dY[13][0] = -c3c * (4.f * zz - 3.f * xx - yy); dY[13][1] = 2.f * c3c * x * y;
+        dY[13][2] = -8.f * c3c * x * z;
+        dY[14][0] = 2.f * c3e * x * z;  dY[14][1] = -2.f * c3e * y * z;     dY[14][2] = c3e * (xx - yy);
+        dY[15][0] = -3.f * c3a * (xx - yy); dY[15][1] = 6.f * c3a * x * y;  dY[15][2] = 0.f;
+    }
+}
+
+// Everything the projection of one Gaussian into one view computes; the
+// backward recomputes it instead of storing it.
+struct Proj {
+    bool valid;
+    float qn;           // |q|
+    float qh[4];        // unit quaternion
+    float R[9];         // Gaussian rotation
+    float s[3];         // scales
+    float Sc[6];        // camera covariance (xx, xy, xz, yy, yz, zz)
+    float p[3];         // camera-space mean
+    bool clx, cly;      // Jacobian clamp active
+    float tx, ty;       // clamped x, y used in J
+    float j00, j02, j11, j12;
+    float a, b, c, det; // dilated 2D covariance
+    float u, v;
+    float A, B, C;      // conic
+    float o;
+    float col[3];
+    bool cclamp[3];     // SH colour clamped at 0
+    float dir[3], dirn; // unit view direction, |mu - camera centre|
+    float radius;
+    int x0, x1, y0, y1;
+};
+
+// Project Gaussian g into view vi with pose T (row-major 4x4, world->camera).
+// COL: also evaluate the colour (RGB or SH).
+template <bool COL>
+__device__ __forceinline__ void project_one(const Params& P, int g, const ViewInfo& vi, const float* T, Proj& o) {
+    o.valid = false;
+    const float4 q = reinterpret_cast<const float4*>(P.q)[g];
+    const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+    if (!(qn2 > 0.f)) return;
+    o.qn = sqrtf(qn2);
+    const float iq = 1.f / o.qn;
+    o.qh[0] = q.x * iq; o.qh[1] = q.y * iq; o.qh[2] = q.z * iq; o.qh[3] = q.w * iq;
+    quat_rot(o.qh[0], o.qh[1], o.qh[2], o.qh[3], o.R);
+    const float* lsp = P.ls + 3 * (int64_t)g;
+    o.s[0] = expf(lsp[0]); o.s[1] = expf(lsp[1]); o.s[2] = expf(lsp[2]);
+    o.o = 1.f / (1.f + expf(-P.opl[g]));
+
+    const float* mu = P.means + 3 * (int64_t)g;
+    const float mx = mu[0], my = mu[1], mz = mu[2];
+    o.p[0] = T[0] * mx + T[1] * my + T[2] * mz + T[3];
+    o.p[1] = T[4] * mx + T[5] * my + T[6] * mz + T[7];
+    o.p[2] = T[8] * mx + T[9] * my + T[10] * mz + T[11];
+    const float pz = o.p[2];
+    if (!(pz > kZNear)) return;
+    const float iz = 1.f / pz;
+    o.u = vi.fx * o.p[0] * iz + vi.cx;
+    o.v = vi.fy * o.p[1] * iz + vi.cy;
+
+    // EWA Jacobian with x/z, y/z clamped at 1.3x the half field of view
+    const float limx = kJClamp * (float)vi.W / (2.f * vi.fx);
+    const float limy = kJClamp * (float)vi.H / (2.f * vi.fy);
+    const float xz = o.p[0] * iz, yz = o.p[1] * iz;
+    o.clx = (xz < -limx) || (xz > limx);
+    o.cly = (yz < -limy) || (yz > limy);
+    o.tx = fminf(fmaxf(xz, -limx), limx) * pz;
+    o.ty = fminf(fmaxf(yz, -limy), limy) * pz;
+    o.j00 = vi.fx * iz;
+    o.j11 = vi.fy * iz;
+    o.j02 = -vi.fx * o.tx * iz * iz;
+    o.j12 = -vi.fy * o.ty * iz * iz;
+
+    // world covariance M = R diag(s^2) R^T, then Sigma_c = W M W^T
+    float M[6];
+    {
+        const float s0 = o.s[0] * o.s[0], s1 = o.s[1] * o.s[1], s2 = o.s[2] * o.s[2];
+        const float* R = o.R;
+        M[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
+        M[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
+        M[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
+        M[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
+        M[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
+        M[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
+    }
+    {
+        // WM = W * M (full 3x3), Sc = WM * W^T (symmetric)
+        float Mf[9] = {M[0], M[1], M[2], M[1], M[3], M[4], M[2], M[4], M[5]};
+        float WM[9];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+                WM[3 * r + c] = T[4 * r] * Mf[c] + T[4 * r + 1] * Mf[3 + c] + T[4 * r + 2] * Mf[6 + c];
+        o.Sc[0] = WM[0] * T[0] + WM[1] * T[1] + WM[2] * T[2];
+        o.Sc[1] = WM[0] * T[4] + WM[1] * T[5] + WM[2] * T[6];
+        o.Sc[2] = WM[0] * T[8] + WM[1] * T[9] + WM[2] * T[10];
+        o.Sc[3] = WM[3] * T[4] + WM[4] * T[5] + WM[5] * T[6];
+        o.Sc[4] = WM[3] * T[8] + WM[4] * T[9] + WM[5] * T[10];
+        o.Sc[5] = WM[6] * T[8] + WM[7] * T[9] + WM[8] * T[10];
+    }
+    // Sigma_2D = J Sc J^T with J = [[j00, 0, j02], [0, j11, j12]]
+    {
+        const float* S = o.Sc;
+        const float r00 = o.j00 * S[0] + o.j02 * S[2], r01 = o.j00 * S[1] + o.j02 * S[4],
+                    r02 = o.j00 * S[2] + o.j02 * S[5];
+        const float r11 = o.j11 * S[3] + o.j12 * S[4], r12 = o.j11 * S[4] + o.j12 * S[5];
+        o.a = r00 * o.j00 + r02 * o.j02 + kDilate;
+        o.b = r01 * o.j11 + r02 * o.j12;
+        o.c = r11 * o.j11 + r12 * o.j12 + kDilate;
+    }
+    o.det = o.a * o.c - o.b * o.b;
+    if (!(o.det > 0.f)) return;
+    const float idet = 1.f / o.det;
+    o.A = o.c * idet;
+    o.B = -o.b * idet;
+    o.C = o.a * idet;
+
+    if (COL) {
+        if (P.sh < 0) {
+            const float* cp = P.col + 3 * (int64_t)g;
+            o.col[0] = cp[0]; o.col[1] = cp[1]; o.col[2] = cp[2];
+            o.cclamp[0] = o.cclamp[1] = o.cclamp[2] = false;
+        } else {
+            // camera centre C = -R_cw^T t_cw
+            const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
+            const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
+            const float Cz = -(T[2] * T[3] + T[6] * T[7] + T[10] * T[11]);
+            const float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
+            o.dirn = sqrtf(dx * dx + dy * dy + dz * dz);
+            const float idn = 1.f / o.dirn;
+            o.dir[0] = dx * idn; o.dir[1] = dy * idn; o.dir[2] = dz * idn;
+            float Y[16];
+            sh_basis<false>(P.sh, o.dir[0], o.dir[1], o.dir[2], Y, nullptr);
+            const int K = (P.sh + 1) * (P.sh + 1);
+            const float* sh = P.col + (int64_t)g * K * 3;
+            float acc[3] = {0.5f, 0.5f, 0.5f};
+            for (int l = 0; l < K; l++) {
+                acc[0] += Y[l] * sh[3 * l];
+                acc[1] += Y[l] * sh[3 * l + 1];
+                acc[2] += Y[l] * sh[3 * l + 2];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                o.cclamp[k] = acc[k] < 0.f;
+                o.col[k] = fmaxf(acc[k], 0.f);
+            }
+        }
+    }
+
+    // opacity-aware support radius: alpha >= 1/255 only where
+    // |d|^2 <= 2 ln(255 o) lambda_max
+    if (o.o < kAlphaMin) return;
+    const float qmax = 2.f * logf(255.f * o.o);
+    const float m = 0.5f * (o.a + o.c);
+    const float lmax = m + sqrtf(fmaxf(m * m - o.det, 0.f));
+    o.radius = ceilf(sqrtf(qmax * lmax));
+    const float fx0 = fmaxf(ceilf(o.u - o.radius), 0.f);
+    const float fx1 = fminf(floorf(o.u + o.radius), (float)(vi.W - 1));
+    const float fy0 = fmaxf(ceilf(o.v - o.radius), 0.f);
+    const float fy1 = fminf(floorf(o.v + o.radius), (float)(vi.H - 1));
+    if (!(fx0 <= fx1) || !(fy0 <= fy1)) return;
+    o.x0 = (int)fx0; o.x1 = (int)fx1; o.y0 = (int)fy0; o.y1 = (int)fy1;
+    o.valid = true;
+}
+
+// Fragment weight (identical instruction sequence in forward and backward so
+// the skip / clamp / stop decisions agree bit for bit).
+struct Frag {
+    float dx, dy, G, raw, alpha;
+};
+
+__device__ __forceinline__ bool frag_eval(float px, float py, float2 xy, float4 co, Frag& f) {
+    f.dx = px - xy.x;
+    f.dy = py - xy.y;
+    const float sig = 0.5f * (co.x * f.dx * f.dx + co.z * f.dy * f.dy) + co.y * f.dx * f.dy;
+    if (sig < 0.f) return false;
+    f.G = __expf(-sig);
+    f.raw = co.w * f.G;
+    f.alpha = fminf(kAlphaMax, f.raw);
+    return f.alpha >= kAlphaMin;
+}
+
+__device__ __forceinline__ bool rect_has(uint2 r, int x, int y) {
+    const int x0 = (int)(r.x & 0xffffu), x1 = (int)(r.x >> 16);
+    const int y0 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
+    return x >= x0 && x <= x1 && y >= y0 && y <= y1;
+}
+
+// view of a global tile id (V is small; scalar binary search over tile_off)
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, int t) {
+    int lo = 0, hi = vt.V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (vt.v[mid].tile_off <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace gs

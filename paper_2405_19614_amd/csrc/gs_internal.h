@@ -1,0 +1,170 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+// Not part of the public ABI (include/gs.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gs {
+
+constexpr int kMaxViews = 64;
+
+// Forward-model constants (Sec. 3.4 rasterisation; the paper gives none, these
+// are the thresholds the ABI documents).
+constexpr float kZNear = 0.2f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kDilate = 0.3f;
+constexpr float kJClamp = 1.3f;
+
+// Per-view constants, passed by value in every launch (no upload, graph safe).
+struct ViewInfo {
+    int W, H;
+    int tiles_x, tiles_y;
+    int tile_off;   // global id of this view's first tile
+    int pix_off;    // first pixel of this view in the concatenated images
+    float fx, fy, cx, cy;
+    float lsc;      // dL/dC scale: w_color / (V * 3 * H * W)
+    float lsd;      // dL/dD scale: w_depth / (V * H * W)
+};
+
+struct ViewTable {
+    int V;
+    int tw, th;
+    int n_tiles;
+    int n_pix;
+    int n;          // Gaussians
+    ViewInfo v[kMaxViews];
+};
+
+// Gaussian parameters (device, FP32 SoA).
+struct Params {
+    const float* means;
+    const float* ls;
+    const float* q;
+    const float* opl;
+    const float* col;
+    int n;
+    int sh;         // -1 = RGB
+};
+
+struct Grads {
+    float* means;
+    float* ls;
+    float* q;
+    float* opl;
+    float* col;
+};
+
+// Per-(view, Gaussian) 2D records produced by the projection, r = v*n + g.
+struct Records {
+    float2* xy;       // projected mean
+    float4* conic;    // (A, B, C, opacity)
+    float4* col;      // (r, g, b, depth)
+    uint2* rect;      // inclusive pixel rect (x0 | x1 << 16, y0 | y1 << 16)
+    uint32_t* nt;     // tiles touched (0 = not visible)
+};
+
+constexpr int kG2Stride = 12;   // floats per record of the 2D-gradient buffer (10 used)
+
+// Device layout of the forward state / mapping workspace (byte offsets).
+struct Layout {
+    int64_t R;            // V * n records
+    int64_t cap;          // pair capacity
+    int64_t n_tiles, n_pix;
+    int64_t sort_blocks;  // radix-sort blocks for max(R, cap)
+    size_t off_xy, off_conic, off_col, off_rect, off_nt;
+    size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
+    size_t off_cnt;                               // R (scan buffer)
+    size_t off_pk0, off_pv0, off_pk1, off_pv1;    // pair sort (cap)
+    size_t off_hist;                              // 256 * sort_blocks
+    size_t off_scan;                              // scan block sums
+    size_t off_ranges;                            // n_tiles uint2
+    size_t off_tfin, off_last;                    // n_pix
+    size_t off_g2;                                // R * kG2Stride floats
+    size_t off_posepart;                          // V * pose_blocks * 6 doubles
+    size_t off_scalars;                           // counters and flags
+    // mapping workspace only
+    size_t off_dC, off_dD;                        // upstream gradients
+    size_t off_tilepart;                          // n_tiles double2
+    size_t off_rpacc;                             // V * 8 doubles
+    size_t bytes;
+    int64_t pose_blocks;
+};
+
+// scalars block (u32 unless noted), at off_scalars
+enum ScalarSlot { kNVis = 0, kNPairs = 1, kFlags = 2, kPairsLo = 4, kPairsHi = 5, kNumScalars = 16 };
+
+Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace);
+
+// ---------------------------------------------------------------------------
+// launchers (each enqueues kernels on `s` and returns hipGetLastError())
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+hipError_t launch_zero_g2(const uint32_t* nt, float* g2, int64_t R, hipStream_t s);
+hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
+hipError_t launch_step_bump(int32_t* step, hipStream_t s);
+hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, uint2* rect_out, uint32_t* nt, int64_t n,
+                             hipStream_t s);
+
+hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
+                                 float* g2_zero, hipStream_t s);
+hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const float* poses, const Records& rec,
+                                 const float* g2, Grads G, int accumulate, double* pose_part, int64_t pose_blocks,
+                                 hipStream_t s);
+hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, int64_t pose_blocks,
+                                const double* rp_acc, float rp_weight, float* dL_dpose, hipStream_t s);
+
+// Binning: records -> sorted pair values and tile ranges.  All sizes bounded by
+// the layout; counts live on the device in the scalars block.
+hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
+                          const uint2* rect_src, const float* depth_src, int64_t pair_bound, hipStream_t s,
+                          uint32_t** sorted_vals_out);
+// first half of binning (visibility, depth sort, pair offsets); leaves the pair total on the device
+hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
+                                const float* depth_src, hipStream_t s);
+hipError_t launch_binning_emit(const ViewTable& vt, const Layout& L, char* base, const uint2* rect_src,
+                               int64_t pair_bound, hipStream_t s, uint32_t** sorted_vals_out);
+
+struct LossArgs {
+    const float* tc;
+    const float* td;
+    const float* mask;
+    int use_gate;
+    float gamma;
+    float* dC;
+    float* dD;
+    double2* tile_part;
+};
+
+// counts (nullable, device u64[2]): += candidates visited (rect contains the
+// pixel, up to and including the terminating one) and fragments blended
+hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
+                                float* color, float* depth, float* alpha, float* tfin, uint32_t* last,
+                                const LossArgs* loss, hipStream_t s, unsigned long long* counts = nullptr);
+hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
+                                const float* tfin, const uint32_t* last, const float* dC, const float* dD,
+                                const float* dA, float* g2, hipStream_t s);
+
+hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc, float w_color,
+                              float w_depth, float w_reproj, float* loss_out, hipStream_t s);
+hipError_t launch_reproj(const ViewTable& vt, const float* poses, const float* pts, const float* uv,
+                         const int32_t* vid, int64_t M, float delta, float* residual, double* acc, hipStream_t s);
+hipError_t launch_reproj_finalize(const ViewTable& vt, const double* acc, float weight, float* loss,
+                                  float* dL_dpose, hipStream_t s);
+
+struct AdamGroups {
+    float* p[5];
+    const float* g[5];
+    int64_t cnt[5];
+    float lr[5];
+};
+hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, float b1, float b2, float eps,
+                       int bump_step, hipStream_t s);
+hipError_t launch_pose_update(int V, float* poses, const float* dpose, float* m, float* v, int32_t* step, float lr,
+                              float b1, float b2, float eps, int bump_step, hipStream_t s);
+
+}  // namespace gs

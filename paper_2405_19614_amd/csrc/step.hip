@@ -1,0 +1,291 @@
+// Loss reductions, the re-projection residual and the optimiser updates.
+//
+// Re-projection (Sec. 3.2 Eq. lba): one thread per match, Huber kernel on the
+// residual norm, per-view sums of loss, count and pose gradient in FP64.
+// Loss (Sec. 3.3 joint-loss equation, L1 terms of the Sec. 3.4 mapping loss):
+// FP64 reduction of the per-tile partials written by the compositing epilogue.
+// Updates: Adam on every parameter group; pose steps applied on SE(3) by
+// left multiplication with the exponential of the Adam step.
+#include "gs_device.h"
+
+namespace gs {
+
+namespace {
+
+__global__ void zero_g2_kernel(const uint32_t* nt, float* g2, int64_t R) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R || nt[r] == 0u) return;
+    float4* z = reinterpret_cast<float4*>(g2 + r * kG2Stride);
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    z[0] = zero; z[1] = zero; z[2] = zero;
+}
+
+__global__ void zero_f64_kernel(double* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// acc per view: [sum h, count, dxi(6)]
+__global__ __launch_bounds__(256) void reproj_kernel(ViewTable vt, const float* poses, const float* pts,
+                                                     const float* uv, const int32_t* vid, int64_t M, float delta,
+                                                     float* residual, double* acc) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = m < M;
+    int v = in ? vid[m] : -1;
+    if (v < 0 || v >= vt.V) v = -1;
+    double h = 0.0, g[6] = {0, 0, 0, 0, 0, 0}, c = 0.0;
+    float r0 = 0.f, r1 = 0.f;
+    if (v >= 0) {
+        const float* T = poses + 16 * v;
+        const float X = pts[3 * m], Y = pts[3 * m + 1], Z = pts[3 * m + 2];
+        const float px = T[0] * X + T[1] * Y + T[2] * Z + T[3];
+        const float py = T[4] * X + T[5] * Y + T[6] * Z + T[7];
+        const float pz = T[8] * X + T[9] * Y + T[10] * Z + T[11];
+        if (pz > kZNear) {
+            const ViewInfo& vi = vt.v[v];
+            const float iz = 1.f / pz;
+            r0 = uv[2 * m] - (vi.fx * px * iz + vi.cx);
+            r1 = uv[2 * m + 1] - (vi.fy * py * iz + vi.cy);
+            const float e = sqrtf(r0 * r0 + r1 * r1);
+            float s;
+            if (e <= delta) {
+                h = 0.5 * (double)e * (double)e;
+                s = 1.f;
+            } else {
+                h = (double)delta * ((double)e - 0.5 * (double)delta);
+                s = delta / e;
+            }
+            c = 1.0;
+            // dh/dr = s r and r = uv - pi, so dh/dpi = -s r
+            const float gu = -s * r0, gv = -s * r1;
+            const float dpx = gu * vi.fx * iz, dpy = gv * vi.fy * iz;
+            const float dpz = -(gu * vi.fx * px + gv * vi.fy * py) * iz * iz;
+            g[0] = dpx; g[1] = dpy; g[2] = dpz;
+            g[3] = (double)(py * dpz - pz * dpy);
+            g[4] = (double)(pz * dpx - px * dpz);
+            g[5] = (double)(px * dpy - py * dpx);
+        } else {
+            v = -1;
+        }
+    }
+    if (in && residual) {
+        residual[2 * m] = r0;
+        residual[2 * m + 1] = r1;
+    }
+    // matches are usually grouped by view: reduce over the wavefront when
+    // every valid lane has the same view, else one atomic set per lane
+    const uint64_t valid = __ballot(v >= 0);
+    if (valid == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const int first = __ffsll((unsigned long long)valid) - 1;
+    const int v0 = __shfl(v, first, 64);
+    if (__ballot(v >= 0 && v != v0) == 0ull) {
+        const double sh = wave_sum_d(h), sc = wave_sum_d(c);
+        double sg[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) sg[k] = wave_sum_d(g[k]);
+        if (lane == first) {
+            double* a = acc + 8 * v0;
+            atomicAdd(a, sh);
+            atomicAdd(a + 1, sc);
+#pragma unroll
+            for (int k = 0; k < 6; k++) atomicAdd(a + 2 + k, sg[k]);
+        }
+    } else if (v >= 0) {
+        double* a = acc + 8 * v;
+        atomicAdd(a, h);
+        atomicAdd(a + 1, c);
+#pragma unroll
+        for (int k = 0; k < 6; k++) atomicAdd(a + 2 + k, g[k]);
+    }
+}
+
+__global__ void reproj_finalize_kernel(int V, const double* acc, float weight, float* loss, float* dpose) {
+    const int v = threadIdx.x;
+    if (v >= V) return;
+    const double c = acc[8 * v + 1];
+    loss[v] = c > 0 ? (float)(acc[8 * v] / c) : 0.f;
+    if (dpose && c > 0) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) dpose[6 * v + k] += (float)((double)weight * acc[8 * v + 2 + k] / c);
+    }
+}
+
+__global__ __launch_bounds__(256) void loss_reduce_kernel(ViewTable vt, const double2* part, const double* rp,
+                                                          float wc, float wd, float wr, float* out) {
+    __shared__ double red[256][2];
+    double total = 0.0;
+    for (int v = 0; v < vt.V; v++) {
+        const ViewInfo& vi = vt.v[v];
+        const int nt = vi.tiles_x * vi.tiles_y;
+        double a = 0.0, b = 0.0;
+        for (int i = threadIdx.x; i < nt; i += 256) {
+            const double2 p = part[vi.tile_off + i];
+            a += p.x;
+            b += p.y;
+        }
+        red[threadIdx.x][0] = a;
+        red[threadIdx.x][1] = b;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                red[threadIdx.x][0] += red[threadIdx.x + s][0];
+                red[threadIdx.x][1] += red[threadIdx.x + s][1];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double npx = (double)vi.W * vi.H;
+            const double lc = red[0][0] / (3.0 * npx);
+            const double ld = red[0][1] / npx;
+            double lr = 0.0;
+            if (rp && rp[8 * v + 1] > 0) lr = rp[8 * v] / rp[8 * v + 1];
+            out[1 + 3 * v] = (float)lc;
+            out[2 + 3 * v] = (float)ld;
+            out[3 + 3 * v] = (float)lr;
+            total += (double)wc * lc + (double)wd * ld + (double)wr * lr;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (float)(total / (double)vt.V);
+}
+
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                            float eps, const int32_t* step) {
+    const float t = (float)(*step + 1);
+    const float c1 = 1.f / (1.f - powf(b1, t));
+    const float c2 = 1.f / (1.f - powf(b2, t));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+__global__ void pose_update_kernel(int V, float* poses, const float* dpose, float* m, float* v, float lr, float b1,
+                                   float b2, float eps, const int32_t* step) {
+    const int k = threadIdx.x;
+    if (k >= V) return;
+    const double t = (double)(*step + 1);
+    double xi[6];
+    for (int i = 0; i < 6; i++) {
+        const float gi = dpose[6 * k + i];
+        const float mi = b1 * m[6 * k + i] + (1.f - b1) * gi;
+        const float vi = b2 * v[6 * k + i] + (1.f - b2) * gi * gi;
+        m[6 * k + i] = mi;
+        v[6 * k + i] = vi;
+        const double mh = (double)mi / (1.0 - pow((double)b1, t));
+        const double vh = (double)vi / (1.0 - pow((double)b2, t));
+        xi[i] = -(double)lr * mh / (sqrt(vh) + (double)eps);
+    }
+    // Exp of the twist (v, w): R by Rodrigues, translation V(w) v
+    const double wx = xi[3], wy = xi[4], wz = xi[5];
+    const double th2 = wx * wx + wy * wy + wz * wz, th = sqrt(th2);
+    double A, B, Cc;
+    if (th < 1e-6) {
+        A = 1.0 - th2 / 6.0;
+        B = 0.5 - th2 / 24.0;
+        Cc = 1.0 / 6.0 - th2 / 120.0;
+    } else {
+        A = sin(th) / th;
+        B = (1.0 - cos(th)) / th2;
+        Cc = (th - sin(th)) / (th2 * th);
+    }
+    const double W[9] = {0, -wz, wy, wz, 0, -wx, -wy, wx, 0};
+    double W2[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) W2[3 * r + c] = W[3 * r] * W[c] + W[3 * r + 1] * W[3 + c] + W[3 * r + 2] * W[6 + c];
+    double R[9], Vm[9];
+    for (int i = 0; i < 9; i++) {
+        const double I = (i % 4 == 0) ? 1.0 : 0.0;
+        R[i] = I + A * W[i] + B * W2[i];
+        Vm[i] = I + B * W[i] + Cc * W2[i];
+    }
+    double tr[3];
+    for (int r = 0; r < 3; r++) tr[r] = Vm[3 * r] * xi[0] + Vm[3 * r + 1] * xi[1] + Vm[3 * r + 2] * xi[2];
+    float* P = poses + 16 * k;
+    double old[12];
+    for (int i = 0; i < 12; i++) old[i] = P[i];
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 4; c++) {
+            double s = R[3 * r] * old[c] + R[3 * r + 1] * old[4 + c] + R[3 * r + 2] * old[8 + c];
+            if (c == 3) s += tr[r];
+            P[4 * r + c] = (float)s;
+        }
+    }
+}
+
+__global__ void step_bump_kernel(int32_t* step) { *step += 1; }
+
+}  // namespace
+
+hipError_t launch_zero_g2(const uint32_t* nt, float* g2, int64_t R, hipStream_t s) {
+    if (R <= 0) return hipSuccess;
+    zero_g2_kernel<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(nt, g2, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    zero_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reproj(const ViewTable& vt, const float* poses, const float* pts, const float* uv,
+                         const int32_t* vid, int64_t M, float delta, float* residual, double* acc, hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    reproj_kernel<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(vt, poses, pts, uv, vid, M, delta, residual, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_reproj_finalize(const ViewTable& vt, const double* acc, float weight, float* loss,
+                                  float* dL_dpose, hipStream_t s) {
+    reproj_finalize_kernel<<<1, kMaxViews, 0, s>>>(vt.V, acc, weight, loss, dL_dpose);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc, float w_color,
+                              float w_depth, float w_reproj, float* loss_out, hipStream_t s) {
+    loss_reduce_kernel<<<1, 256, 0, s>>>(vt, tile_part, rp_acc, w_color, w_depth, w_reproj, loss_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, float b1, float b2, float eps,
+                       int bump_step, hipStream_t s) {
+    (void)bump_step;
+    int64_t off = 0;
+    for (int i = 0; i < 5; i++) {
+        const int64_t n = ag.cnt[i];
+        if (n > 0) {
+            int64_t b = (n + 255) / 256;
+            if (b > 16384) b = 16384;
+            adam_kernel<<<(unsigned)b, 256, 0, s>>>(ag.p[i], ag.g[i], m + off, v + off, n, ag.lr[i], b1, b2, eps,
+                                                    step);
+        }
+        off += n;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_update(int V, float* poses, const float* dpose, float* m, float* v, int32_t* step, float lr,
+                              float b1, float b2, float eps, int bump_step, hipStream_t s) {
+    (void)bump_step;
+    pose_update_kernel<<<1, kMaxViews, 0, s>>>(V, poses, dpose, m, v, lr, b1, b2, eps, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_bump(int32_t* step, hipStream_t s) {
+    step_bump_kernel<<<1, 1, 0, s>>>(step);
+    return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,95 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gs.h")
+LIB = os.path.join(ROOT, "paper_2405_19614_amd", "libgs.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2405_19614_amd import build
+        build.build()
+    from paper_2405_19614_amd import _abi
+    return _abi.load()
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ["gs_render_forward", "gs_render_backward", "gs_reproj_residual", "gs_mapping_step",
+                     "gs_create", "gs_destroy", "gs_last_error", "gs_abi_version"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_python_binding_names_every_export(lib):
+    from paper_2405_19614_amd import _abi
+    assert sorted(_abi.EXPORTS) == _declared()
+
+
+def test_abi_version(lib):
+    assert lib.gs_abi_version() == 1
+
+
+def test_null_context_rejected_without_device_work(lib):
+    from paper_2405_19614_amd import _abi as A
+    plan = A.gs_plan(16, 16, 0, 0, 0)
+    rc = lib.gs_render_forward(None, None, None, None, 1, None, None, None, None, 0, ctypes.byref(plan), None)
+    assert rc == A.GS_EINVAL
+    assert lib.gs_set_tile(None, 16, 16) == A.GS_EINVAL
+
+
+def test_state_bytes_validation(lib):
+    from paper_2405_19614_amd import _abi as A
+    cams = (A.gs_camera * 2)(A.gs_camera(64, 48, 60, 60, 32, 24), A.gs_camera(70, 45, 60, 60, 35, 22.5))
+    ok = lib.gs_state_bytes(cams, 2, 1000, 10000, 16, 16)
+    assert ok > 0
+    # monotone in every size
+    assert lib.gs_state_bytes(cams, 2, 2000, 10000, 16, 16) > ok
+    assert lib.gs_state_bytes(cams, 2, 1000, 20000, 16, 16) > ok
+    # invalid: unsupported tile, V = 0, V too large, negative n, bad camera, capacity too large
+    assert lib.gs_state_bytes(cams, 2, 1000, 10000, 12, 12) == 0
+    assert lib.gs_state_bytes(cams, 0, 1000, 10000, 16, 16) == 0
+    assert lib.gs_state_bytes(cams, 65, 1000, 10000, 16, 16) == 0
+    assert lib.gs_state_bytes(cams, 2, -1, 10000, 16, 16) == 0
+    assert lib.gs_state_bytes(cams, 2, 1000, 1 << 31, 16, 16) == 0
+    bad = (A.gs_camera * 1)(A.gs_camera(0, 48, 60, 60, 32, 24))
+    assert lib.gs_state_bytes(bad, 1, 10, 10, 16, 16) == 0
+    bad = (A.gs_camera * 1)(A.gs_camera(64, 48, -1.0, 60, 32, 24))
+    assert lib.gs_state_bytes(bad, 1, 10, 10, 16, 16) == 0
+    assert lib.gs_state_bytes(None, 1, 10, 10, 16, 16) == 0
+    # the workspace holds the state plus the loss buffers
+    assert lib.gs_step_workspace_bytes(cams, 2, 1000, -1, 10000, 16, 16) > ok
+
+
+def test_tile_shapes_accepted(lib):
+    from paper_2405_19614_amd import _abi as A
+    cams = (A.gs_camera * 1)(A.gs_camera(64, 48, 60, 60, 32, 24))
+    for tw, th in [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16), (0, 0)]:
+        assert lib.gs_state_bytes(cams, 1, 10, 10, tw, th) > 0
+
+
+def test_paper_preset_matches_table():
+    """The Fusion Bridge preset of the binding equals the paper's table."""
+    import json
+    from paper_2405_19614_amd.binding import PAPER_FUSION_BRIDGE
+    hp = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_hyperparams.json")))["values"]
+    assert PAPER_FUSION_BRIDGE["w_reproj"] == hp["w1"]
+    assert PAPER_FUSION_BRIDGE["w_color"] == hp["w2"]
+    assert PAPER_FUSION_BRIDGE["w_depth"] == hp["w3"]
+    assert PAPER_FUSION_BRIDGE["gate_gamma"] == hp["gamma"]

@@ -1,0 +1,175 @@
+"""HIP path vs FP64 oracle, through the C ABI (element by element)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from synth import scenes
+from tests.gpu_helpers import (GRAD_NAMES, TOL_A, TOL_C, TOL_D_REL, TOL_G, cotangents, dev_scene,
+                               forward_errors, oracle_views, rel)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2405_19614_amd as gs
+    torch.cuda.set_device(0)
+    return gs.Context(0)
+
+
+def _small_scenes():
+    return {
+        "c1": scenes.c1(),
+        "c1_ragged": scenes.c1(n=1500, width=70, height=45, seed=21),
+        "c2_small": scenes.c2(n=20000, width=160, height=120),
+        "c3_small": scenes.c3(n=40000, views=8, width=150, height=85),
+        "c5_small": scenes.c5(n=30000, views=3, width=120, height=68),
+    }
+
+
+SCENES = _small_scenes()
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_forward_matches_oracle(ctx, name):
+    s = SCENES[name]
+    print(f"[forward] {name} n={s.n} V={s.V}", flush=True)
+    g, poses = dev_scene(s)
+    color, depth, alpha, state, plan = ctx.forward(g, s.cams, poses)
+    torch.cuda.synchronize()
+    _, ref = oracle_views(s)
+    ec, ed, ea, namb = forward_errors(s, color, depth, alpha, ref)
+    zm = float(np.max(np.abs(ref["depth"]))) + 1.0
+    print(f"  pairs={plan.n_pairs} vis={plan.n_visible} err C={ec:.2e} D={ed:.2e} A={ea:.2e} ambiguous={namb}")
+    assert ec <= TOL_C and ea <= TOL_A and ed <= TOL_D_REL * zm
+    frac = namb / s.npix
+    assert frac <= 0.10, frac
+
+
+@pytest.mark.parametrize("name", ["c1", "c1_ragged", "c3_small", "c5_small"])
+def test_backward_matches_oracle(ctx, name):
+    s = SCENES[name]
+    print(f"[backward] {name}", flush=True)
+    g, poses = dev_scene(s)
+    color, depth, alpha, state, plan = ctx.forward(g, s.cams, poses)
+    og, ref = oracle_views(s)
+    dC, dD, dA = cotangents(s, ref, seed=7)
+    t = lambda a: torch.tensor(a, device="cuda")
+    grads, dpose = ctx.backward(g, s.cams, poses, state, plan, t(dC), t(dD), t(dA))
+    torch.cuda.synchronize()
+    rg = O.backward_views(og, s.cams, s.poses, dC, dD, dA)
+    for nm in GRAD_NAMES:
+        e = rel(getattr(grads, nm).cpu().numpy(), rg[nm])
+        print(f"  {nm}: rel {e:.2e}")
+        assert e < TOL_G, (nm, e)
+    for v in range(s.V):
+        e = rel(dpose[v].cpu().numpy(), rg["pose"][v])
+        print(f"  pose[{v}]: rel {e:.2e}")
+        assert e < TOL_G, ("pose", v, e)
+
+
+def test_forward_bit_identical_across_tile_shapes(ctx):
+    s = SCENES["c3_small"]
+    g, poses = dev_scene(s)
+    outs = []
+    for tile in [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16)]:
+        print(f"[tile] {tile}", flush=True)
+        c, d, a, _, _ = ctx.forward(g, s.cams, poses, tile=tile)
+        outs.append((c.cpu(), d.cpu(), a.cpu()))
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert torch.equal(x, y)
+
+
+def test_batched_equals_per_view(ctx):
+    s = SCENES["c3_small"]
+    g, poses = dev_scene(s)
+    c, d, a, st, plan = ctx.forward(g, s.cams, poses)
+    off = s.pix_offsets()
+    og, ref = oracle_views(s)
+    dC, dD, dA = cotangents(s, ref, seed=3)
+    t = lambda x: torch.tensor(x, device="cuda")
+    gb, pb = ctx.backward(g, s.cams, poses, st, plan, t(dC), t(dD), t(dA))
+    acc = {nm: torch.zeros_like(getattr(gb, nm)) for nm in GRAD_NAMES}
+    for v in range(s.V):
+        print(f"[per-view] {v}", flush=True)
+        cv, dv, av, stv, pv = ctx.forward(g, [s.cams[v]], poses[v:v + 1])
+        P = s.cams[v].npix
+        assert torch.equal(cv.cpu(), c[3 * off[v]:3 * off[v + 1]].cpu())
+        assert torch.equal(dv.cpu(), d[off[v]:off[v + 1]].cpu())
+        assert torch.equal(av.cpu(), a[off[v]:off[v + 1]].cpu())
+        gv, pvv = ctx.backward(g, [s.cams[v]], poses[v:v + 1], stv, pv, t(dC[3 * off[v]:3 * off[v + 1]]),
+                               t(dD[off[v]:off[v + 1]]), t(dA[off[v]:off[v + 1]]))
+        for nm in GRAD_NAMES:
+            acc[nm] += getattr(gv, nm)
+        assert rel(pvv[0].cpu().numpy(), pb[v].cpu().numpy()) < 1e-4
+    for nm in GRAD_NAMES:
+        assert rel(acc[nm].cpu().numpy(), getattr(gb, nm).cpu().numpy()) < 1e-4, nm
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_binning_stage_bit_exact(ctx, tile):
+    sizes = [(70, 45), (33, 17), (64, 48), (1, 1)]
+    n = 3000
+    rect, depth = scenes.synthetic_binning_records(sizes, n, seed=tile[0] * 31 + tile[1])
+    vals_ref, ranges_ref = O.binning(sizes, n, tile[0], tile[1], rect, depth)
+    cams = [scenes.Camera(w, h, 50.0, 50.0, w / 2, h / 2) for w, h in sizes]
+    print(f"[binning] tile={tile} pairs={vals_ref.size}", flush=True)
+    rt = torch.tensor(rect.view(np.int32), device="cuda")
+    dt = torch.tensor(depth, device="cuda")
+    vals, ranges = ctx.bin_records(cams, n, tile, rt, dt, capacity=int(vals_ref.size) + 7)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(vals.cpu().numpy(), vals_ref.astype(np.int64))
+    np.testing.assert_array_equal(ranges.cpu().numpy(), ranges_ref.astype(np.int64))
+
+
+def test_binning_capacity_error_then_retry(ctx):
+    import paper_2405_19614_amd as gs
+    sizes = [(70, 45)]
+    n = 500
+    rect, depth = scenes.synthetic_binning_records(sizes, n, seed=5)
+    vals_ref, ranges_ref = O.binning(sizes, n, 16, 16, rect, depth)
+    cams = [scenes.Camera(70, 45, 50.0, 50.0, 35, 22.5)]
+    rt = torch.tensor(rect.view(np.int32), device="cuda")
+    dt = torch.tensor(depth, device="cuda")
+    with pytest.raises(gs.GSError) as ei:
+        ctx.bin_records(cams, n, (16, 16), rt, dt, capacity=int(vals_ref.size) - 1)
+    assert ei.value.code == gs._abi.GS_ECAPACITY
+    vals, ranges = ctx.bin_records(cams, n, (16, 16), rt, dt, capacity=int(vals_ref.size))
+    np.testing.assert_array_equal(vals.cpu().numpy(), vals_ref.astype(np.int64))
+
+
+def test_reproj_matches_oracle(ctx):
+    s = scenes.c4(n=20000, views=5, res_scale=0.25, vis_range=(500, 20000), matches=(100, 300), seed=9)
+    print(f"[reproj] V={s.V} M={s.points.shape[0]}", flush=True)
+    _, poses = dev_scene(s)
+    t = lambda a: torch.tensor(a, device="cuda")
+    res, loss, dpose = ctx.reproj(s.cams, poses, t(s.points), t(s.uv), t(s.view_idx), 2.0, weight=0.5)
+    torch.cuda.synchronize()
+    r = O.reproj(s.cams, s.poses, s.points, s.uv, s.view_idx, 2.0)
+    np.testing.assert_allclose(res.cpu().numpy(), r["residual"], atol=2e-3)
+    np.testing.assert_allclose(loss.cpu().numpy(), r["loss"], rtol=1e-4)
+    for v in range(s.V):
+        assert rel(dpose[v].cpu().numpy(), 0.5 * r["dpose"][v]) < 1e-3
+
+
+def test_empty_and_culled_scenes(ctx):
+    import paper_2405_19614_amd as gs
+    s = scenes.c1(n=100, seed=3)
+    s.means[:, 2] = -1.0     # every Gaussian behind the camera
+    g, poses = dev_scene(s)
+    c, d, a, st, plan = ctx.forward(g, s.cams, poses)
+    assert plan.n_pairs == 0 and plan.n_visible == 0
+    assert float(c.abs().max()) == 0 and float(a.abs().max()) == 0
+    t = lambda x: torch.ones(x, device="cuda")
+    gr, dp = ctx.backward(g, s.cams, poses, st, plan, t(3 * s.npix), t(s.npix), t(s.npix))
+    for nm in GRAD_NAMES:
+        assert float(getattr(gr, nm).abs().max()) == 0
+    assert float(dp.abs().max()) == 0
+    # n = 0
+    s0 = scenes.c1(n=1, seed=3)
+    g0 = gs.Gaussians.from_arrays(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 4)), np.zeros(0),
+                                  np.zeros((0, 3)), -1)
+    c, d, a, st, plan = ctx.forward(g0, s0.cams, poses)
+    assert plan.n_pairs == 0 and float(c.abs().max()) == 0

@@ -1,0 +1,219 @@
+"""gs_mapping_step (fused loss, re-projection, backward, Adam, graph replay)
+against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from synth import scenes
+from tests.gpu_helpers import GRAD_NAMES, TOL_G, dev_scene, forward_errors, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2405_19614_amd as gs
+    torch.cuda.set_device(0)
+    return gs.Context(0)
+
+
+def _scene_c4():
+    return scenes.c4(n=30000, views=5, res_scale=0.3, vis_range=(2000, 30000), matches=(150, 300), seed=11)
+
+
+C4 = _scene_c4()
+C3 = scenes.c3(n=40000, views=4, width=150, height=85)
+
+
+def _targets(s):
+    """Oracle render at the true poses, cast to FP32 (both sides use it)."""
+    og = O.Gaussians.from_scene(s)
+    ref = O.render_views(og, s.cams, s.poses_true)
+    return ref["color"].astype(np.float32), ref["depth"].astype(np.float32)
+
+
+def _oracle_step(s, tc, td, wc, wd, wr, delta=2.0, gate=None, matches=True):
+    og = O.Gaussians.from_scene(s)
+    out = O.render_views(og, s.cams, s.poses, bands=O.SMALL_BANDS)
+    Lc, Ld, dC, dD = O.loss_and_upstream(s.cams, out, tc, td, wc, wd, gate_gamma=gate)
+    g = O.backward_views(og, s.cams, s.poses, dC, dD, None)
+    V = s.V
+    Lr = np.zeros(V)
+    if matches and s.points is not None:
+        r = O.reproj(s.cams, s.poses, s.points, s.uv, s.view_idx, delta)
+        Lr = r["loss"]
+        g["pose"] = g["pose"] + (wr / V) * r["dpose"]
+    total = float(np.mean(wc * Lc + wd * Ld + wr * Lr))
+    return out, total, Lc, Ld, Lr, g
+
+
+def _step(ctx, s, tc, td, opts, matches=True, g=None, poses=None):
+    import paper_2405_19614_amd as gs
+    if g is None:
+        g, poses = dev_scene(s)
+    t = lambda a: torch.tensor(a, device="cuda")
+    m = (t(s.points), t(s.uv), t(s.view_idx)) if (matches and s.points is not None) else None
+    st = gs.MappingStep(ctx, g, s.cams, poses, t(tc), t(td), opts, matches=m)
+    return st
+
+
+@pytest.mark.parametrize("use_gate", [False, True])
+def test_step_loss_and_gradients_match_oracle(ctx, use_gate):
+    import paper_2405_19614_amd as gs
+    s = C4
+    print(f"[step] c4-like V={s.V} M={s.points.shape[0]} gate={use_gate}", flush=True)
+    tc, td = _targets(s)
+    wc, wd, wr = 1.0, 0.1, 0.5
+    opts = gs.StepOptions(w_color=wc, w_depth=wd, w_reproj=wr, huber_delta=2.0, use_gate=use_gate,
+                          gate_gamma=0.99, use_graph=False)
+    st = _step(ctx, s, tc, td, opts)
+    st()
+    torch.cuda.synchronize()
+    assert st.status()["flags"] == 0
+    out, total, Lc, Ld, Lr, rg = _oracle_step(s, tc, td, wc, wd, wr, gate=0.99 if use_gate else None)
+    ec, ed, ea, namb = forward_errors(s, st.color, st.depth, st.alpha, out)
+    print(f"  forward err C={ec:.2e} D={ed:.2e} A={ea:.2e} ambiguous={namb}")
+    assert ec < 1e-5 and ea < 1e-5
+    loss = st.loss.cpu().numpy().astype(np.float64)
+    print(f"  loss gpu={loss[0]:.8f} oracle={total:.8f}")
+    assert abs(loss[0] - total) <= 1e-5 * abs(total)
+    np.testing.assert_allclose(loss[1::3], Lc, rtol=1e-4)
+    np.testing.assert_allclose(loss[2::3], Ld, rtol=1e-4, atol=1e-7)
+    np.testing.assert_allclose(loss[3::3], Lr, rtol=1e-4)
+    for nm in GRAD_NAMES:
+        e = rel(getattr(st.grads, nm).cpu().numpy(), rg[nm])
+        print(f"  {nm}: rel {e:.2e}")
+        assert e < TOL_G, (nm, e)
+    for v in range(s.V):
+        e = rel(st.dpose[v].cpu().numpy(), rg["pose"][v])
+        print(f"  pose[{v}]: rel {e:.2e}")
+        assert e < TOL_G, ("pose", v, e)
+
+
+def test_adam_and_pose_update_match_oracle(ctx):
+    """One step with both updates: new parameters equal the oracle's Adam
+    step from the oracle's gradients wherever the gradient's sign is well
+    determined (first Adam step ~ -lr sign(g)); elsewhere the step is within
+    the learning rate."""
+    import paper_2405_19614_amd as gs
+    s = C4
+    tc, td = _targets(s)
+    wc, wd, wr = 1.0, 0.1, 0.5
+    lrs = dict(lr_means=1e-3, lr_log_scales=2e-3, lr_quats=3e-3, lr_opacity=4e-3, lr_colors=5e-3, lr_pose=1e-3)
+    opts = gs.StepOptions(w_color=wc, w_depth=wd, w_reproj=wr, update_gaussians=True, update_poses=True,
+                          use_graph=False, **lrs)
+    g, poses = dev_scene(s)
+    before = {nm: getattr(g, nm).cpu().numpy().astype(np.float64).copy() for nm in GRAD_NAMES}
+    st = _step(ctx, s, tc, td, opts, g=g, poses=poses)
+    st()
+    torch.cuda.synchronize()
+    _, _, _, _, _, rg = _oracle_step(s, tc, td, wc, wd, wr)
+    lr_of = {"means": 1e-3, "log_scales": 2e-3, "quats": 3e-3, "opacity_logits": 4e-3, "colors": 5e-3}
+    for nm in GRAD_NAMES:
+        r = rg[nm].reshape(-1)
+        p0 = before[nm].reshape(-1)
+        d_ref, _, _ = O.adam_step(p0, r, np.zeros_like(r), np.zeros_like(r), 1, lr_of[nm])
+        got = getattr(g, nm).cpu().numpy().astype(np.float64).reshape(-1) - p0
+        # first Adam step is -lr g / (|g| + eps): well determined where |g| >> eps
+        sure = (np.abs(r) > 1e-3 * np.sqrt(np.mean(r * r))) & (np.abs(r) > 1e-5)
+        print(f"  {nm}: well-determined {sure.mean():.3f}")
+        np.testing.assert_allclose(got[sure], d_ref[sure], atol=2e-6 * lr_of[nm] * 1e3)
+        assert np.all(np.abs(got) <= lr_of[nm] * (1 + 1e-4) + 2e-7 * np.maximum(1.0, np.abs(p0)))
+    assert int(st.adam_step.item()) == 1
+    # pose: T <- Exp(-lr mhat / (sqrt(vhat) + eps)) T with the oracle's pose gradient
+    Pn = st.poses.cpu().numpy().reshape(s.V, 4, 4).astype(np.float64)
+    for v in range(s.V):
+        d, _, _ = O.adam_step(np.zeros(6), rg["pose"][v], np.zeros(6), np.zeros(6), 1, 1e-3)
+        ref = O.se3_exp(d) @ s.poses[v].astype(np.float64)
+        np.testing.assert_allclose(Pn[v], ref, atol=2e-6)
+
+
+def test_graph_replay_equals_eager(ctx):
+    """Replays of the captured step, with eager work between them, give the
+    eager step's results every time (forward and loss bit for bit, gradients
+    up to atomic ordering)."""
+    import paper_2405_19614_amd as gs
+    s = C3
+    tc, td = _targets(s)
+    base = dict(w_color=1.0, w_depth=0.1, w_reproj=0.0)
+    st_e = _step(ctx, s, tc, td, gs.StepOptions(use_graph=False, **base), matches=False)
+    st_g = _step(ctx, s, tc, td, gs.StepOptions(use_graph=True, **base), matches=False)
+    st_e()
+    torch.cuda.synchronize()
+    ref = (st_e.color.clone(), st_e.loss.clone(), {nm: getattr(st_e.grads, nm).clone() for nm in GRAD_NAMES},
+           st_e.dpose.clone())
+    for rep in range(4):
+        print(f"[graph] replay {rep}", flush=True)
+        st_g.color.zero_()
+        st_g.loss.zero_()
+        st_g()
+        torch.cuda.synchronize()
+        _ = torch.randn(1000, device="cuda").sum().item()   # eager work between replays
+        assert torch.equal(st_g.color, ref[0])
+        assert torch.equal(st_g.loss, ref[1])
+        for nm in GRAD_NAMES:
+            assert rel(getattr(st_g.grads, nm).cpu().numpy(), ref[2][nm].cpu().numpy()) < 1e-5
+        assert rel(st_g.dpose.cpu().numpy(), ref[3].cpu().numpy()) < 1e-5
+
+
+def test_graph_replay_with_updates_tracks_eager(ctx):
+    """Three updating steps replayed from a graph equal three eager steps."""
+    import paper_2405_19614_amd as gs
+    s = C3
+    tc, td = _targets(s)
+    kw = dict(w_color=1.0, w_depth=0.1, update_gaussians=True, update_poses=True, lr_pose=1e-4)
+    g1, p1 = dev_scene(s)
+    g2, p2 = dev_scene(s)
+    e = _step(ctx, s, tc, td, gs.StepOptions(use_graph=False, **kw), matches=False, g=g1, poses=p1)
+    r = _step(ctx, s, tc, td, gs.StepOptions(use_graph=True, **kw), matches=False, g=g2, poses=p2)
+    for k in range(3):
+        print(f"[graph-update] step {k}", flush=True)
+        e()
+        r()
+        torch.cuda.synchronize()
+        for nm in GRAD_NAMES:
+            a = getattr(g1, nm).cpu().numpy()
+            b = getattr(g2, nm).cpu().numpy()
+            # atomic ordering can flip the sign of a near-zero gradient, and
+            # Adam's early steps are ~lr sign(g): allow rare flips
+            diff = np.abs(a - b)
+            assert (diff > 1e-5).mean() < 1e-3, nm
+            assert diff.max() <= 6 * 2.5e-3, nm
+        assert torch.allclose(e.poses, r.poses, atol=1e-6)
+        assert int(r.adam_step.item()) == k + 1
+
+
+def test_pose_gradient_vs_gpu_finite_differences(ctx):
+    """Central differences of the GPU loss (h = 1e-3 rad / m) against the GPU
+    pose gradient: the looser, end-to-end check (tolerance 2e-2 relative)."""
+    import paper_2405_19614_amd as gs
+    s = C4
+    tc, td = _targets(s)
+    opts = gs.StepOptions(w_color=1.0, w_depth=0.1, w_reproj=0.5, use_graph=False)
+    st = _step(ctx, s, tc, td, opts)
+    st()
+    torch.cuda.synchronize()
+    grad = st.dpose.cpu().numpy().astype(np.float64)
+    P0 = st.poses.clone()
+    h = 1e-3
+    worst = 0.0
+    for v in range(min(s.V, 3)):
+        fd = np.zeros(6)
+        for k in range(6):
+            vals = []
+            for sgn in (1, -1):
+                xi = np.zeros(6)
+                xi[k] = sgn * h
+                T = O.se3_exp(xi) @ P0[v].cpu().numpy().reshape(4, 4).astype(np.float64)
+                st.poses.copy_(P0)
+                st.poses[v] = torch.tensor(T.reshape(-1), dtype=torch.float32, device="cuda")
+                st()
+                torch.cuda.synchronize()
+                vals.append(float(st.loss[0].item()))
+            fd[k] = (vals[0] - vals[1]) / (2 * h)
+        e = np.linalg.norm(fd - grad[v]) / np.linalg.norm(fd)
+        print(f"  view {v}: fd {fd} grad {grad[v]} rel {e:.2e}")
+        worst = max(worst, e)
+    st.poses.copy_(P0)
+    assert worst < 2e-2, worst
