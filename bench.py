@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--views", type=int, default=8)
     ap.add_argument("--width", type=int, default=1200)
     ap.add_argument("--height", type=int, default=680)
-    ap.add_argument("--tile", default="auto", help="auto | WxH")
+    ap.add_argument("--tile", default="auto", help="auto | TWxTH,PPT,BWxBH (tile, pixels per thread, bin)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2, help="views of the workload the CPU oracle runs")
     ap.add_argument("--no-per-view", action="store_true")
@@ -126,11 +126,14 @@ def main():
     s, ctx, g, poses, tc, td = make_inputs(args)
     npix = s.npix
     if args.tile == "auto":
-        tile = ctx.autotune(g, s.cams, poses, iters=2)
+        tile, binsz = ctx.autotune(g, s.cams, poses, iters=2)
     else:
-        tile = tuple(int(x) for x in args.tile.lower().split("x"))
-    log(f"[bench] tile {tile}")
-    base = dict(w_color=1.0, w_depth=0.1, w_reproj=0.0, tile=tile, use_graph=True)
+        tw, th, ppt, bw, bh = (int(x) for x in args.tile.lower().replace("x", ",").split(","))
+        ctx.set_tile(tw, th, ppt)
+        ctx.set_bin(bw, bh)
+        tile, binsz = (tw, th), (bw, bh)
+    log(f"[bench] tile {tile} bin {binsz}")
+    base = dict(w_color=1.0, w_depth=0.1, w_reproj=0.0, tile=tile, bin=binsz, use_graph=True)
 
     # batched fwd+bwd (no update): the value
     st = gs.MappingStep(ctx, g, s.cams, poses, tc, td, gs.StepOptions(**base))
@@ -182,7 +185,7 @@ def main():
     dom = max(stage_ms, key=stage_ms.get)
     roof = None
     if frag is not None and dom in ("composite_bwd", "composite_fwd"):
-        vis, blend = frag
+        vis, blend = frag[0], frag[1]
         if dom == "composite_fwd":
             flops = FWD_PER_VISIT * vis + FWD_PER_BLEND * blend + FWD_PER_PIXEL * npix
         else:
@@ -218,7 +221,7 @@ def main():
         "config": {"workload": f"batched keyframe window: {s.n} Gaussians, room shell, {s.V} views "
                                f"{args.width}x{args.height}, f=600, L1 colour + 0.1 L1 depth",
                    "gaussians": s.n, "views": s.V, "width": args.width, "height": args.height,
-                   "pixels_per_step": npix, "tile": f"{tile[0]}x{tile[1]}"},
+                   "pixels_per_step": npix, "tile": f"{tile[0]}x{tile[1]}", "bin": f"{binsz[0]}x{binsz[1]}"},
         "mapping_iters_per_s": round(iters, 3),
         "ms_per_mapping_iter": round(ms_map, 4),
         "per_view_mpx_s": None if per_view is None else round(per_view, 2),
@@ -226,7 +229,8 @@ def main():
         "ms_per_step_median_events": round(ms_med, 4),
         "pairs": status["n_pairs"],
         "visible": status["n_visible"],
-        "fragments": None if frag is None else {"visited": frag[0], "blended": frag[1]},
+        "fragments": None if frag is None else {"visited": frag[0], "blended": frag[1], "entries_staged": frag[2],
+                                                "list_entries": frag[3]},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
         "cpu_baseline": cpu,

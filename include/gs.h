@@ -98,14 +98,19 @@ typedef struct {
 } gs_camera;
 
 /* Tile plan of a forward pass.
- *   tile_w, tile_h : in  tile shape; one of 16x16, 16x8, 8x8, 32x8, 32x16
+ *   tile_w, tile_h : in  compositing tile; one of 16x16, 16x8, 8x8, 32x8, 32x16
  *                    (0, 0 = the context's current choice, 16x16 unless
  *                    gs_autotune chose another); out: the shape used
- *   pair_capacity  : in  (tile, Gaussian) pairs the state buffer was sized for
+ *   bin_w, bin_h   : in  binning rectangle, multiples of the tile in [8, 2048]
+ *                    (0, 0 = the context's choice, 64x64 by default); out: used.
+ *                    Gaussians are binned per bin; each tile composites the
+ *                    entries of its bin's list whose support rect meets it.
+ *   pair_capacity  : in  (bin, Gaussian) pairs the state buffer was sized for
  *   n_pairs        : out pairs produced (on GS_ECAPACITY: pairs needed)
  *   n_visible      : out visible (view, Gaussian) records */
 typedef struct {
     int32_t tile_w, tile_h;
+    int32_t bin_w, bin_h;
     int64_t pair_capacity;
     int64_t n_pairs;
     int64_t n_visible;
@@ -123,10 +128,11 @@ const char* gs_last_error(const gs_ctx* ctx);
 
 /* Bytes of the opaque device state a forward pass writes and the matching
  * backward reads: records of every (view, Gaussian), sort buffers for
- * `pair_capacity` pairs, per-tile ranges and per-pixel final transmittance
- * and stop index.  cams: HOST [V].  Returns 0 on invalid arguments. */
-size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t pair_capacity, int32_t tile_w,
-                      int32_t tile_h);
+ * `pair_capacity` pairs, per-bin ranges and per-pixel final transmittance
+ * and stop index, for bins of bin_w x bin_h (0, 0 = 64x64).  cams: HOST [V].
+ * Returns 0 on invalid arguments. */
+size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t pair_capacity, int32_t bin_w,
+                      int32_t bin_h);
 
 /* Forward pass (Sec. 3.3 3DGS-centred encoder; Sec. 3.4 projection and
  * rasterisation) over V views in one batched launch sequence.
@@ -191,6 +197,7 @@ typedef struct {
     float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_colors, lr_pose;
     float adam_b1, adam_b2, adam_eps;
     int32_t tile_w, tile_h;     /* 0, 0 = context choice */
+    int32_t bin_w, bin_h;       /* 0, 0 = context choice */
     int64_t pair_capacity;      /* capacity the workspace was sized for */
 } gs_step_opts;
 
@@ -221,9 +228,10 @@ typedef struct {
 } gs_adam;
 
 /* Workspace bytes for gs_mapping_step (device; holds the forward state, the
- * upstream gradients, loss partials and status flags). */
+ * upstream gradients, loss partials and status flags), for bins of
+ * bin_w x bin_h (0, 0 = 64x64) and any tile shape. */
 size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int32_t sh_degree,
-                               int64_t pair_capacity, int32_t tile_w, int32_t tile_h);
+                               int64_t pair_capacity, int32_t bin_w, int32_t bin_h);
 
 /* One mapping / joint-optimisation iteration, entirely on the device with no
  * host synchronisation: forward over V views, fused loss and upstream
@@ -250,11 +258,12 @@ int gs_step_status(gs_ctx* ctx, const void* workspace, size_t workspace_bytes, i
 /* Diagnostics: one eager mapping step (same arguments and results as
  * gs_mapping_step, never graph-captured) with HIP events recorded on `stream`
  * between its stages.  stage_ms (HOST [gs_num_stages()]) receives each
- * stage's duration in milliseconds; frag_counts (HOST [2], may be NULL)
+ * stage's duration in milliseconds; frag_counts (HOST [4], may be NULL)
  * receives the number of (pixel, Gaussian) candidates the forward
  * compositing visited (support rect contains the pixel, up to and including
- * the one that stops the pixel) and the number it blended.  Synchronises
- * `stream`. */
+ * the one that stops the pixel), the number it blended, the list entries
+ * the tiles staged before every pixel had stopped, and the total list
+ * length.  Synchronises `stream`. */
 int gs_num_stages(void);
 const char* gs_stage_name(int i);
 int gs_step_profile(gs_ctx* ctx, gs_gaussians* params, gs_gaussian_grads* grads, const gs_adam* adam,
@@ -265,28 +274,39 @@ int gs_step_profile(gs_ctx* ctx, gs_gaussians* params, gs_gaussian_grads* grads,
 
 /* Binning stage on its own (integer; exact): records r = v*n + i carry an
  * inclusive pixel rect rect[r] = (x0 | x1 << 16, y0 | y1 << 16) (empty when
- * x0 > x1 or y0 > y1) and a positive FP32 depth.  Produces the record ids of
- * every (tile, record) pair whose rect touches the tile, sorted by (global
- * tile id, depth, record), and per-tile [start, end) ranges ((0, 0) when
- * empty); the global id of tile (tx, ty) of view v counts the tiles of the
- * views before v, then ty * tiles_x + tx.
+ * x0 > x1 or y0 > y1) and a positive FP32 depth.  For bins of bin_w x bin_h
+ * pixels (multiples of 8), produces the record ids of every (bin, record)
+ * pair whose rect touches the bin, sorted by (global bin id, depth, record),
+ * and per-bin [start, end) ranges ((0, 0) when empty); the global id of bin
+ * (bx, by) of view v counts the bins of the views before v, then
+ * by * bins_x + bx.
  *   rect device [V*n][2] u32, depth device [V*n] f32, values device
  *   [values_capacity] u32, ranges device [total tiles][2] u32, n_pairs HOST out.
  * Uses `state` (sized by gs_state_bytes with pair_capacity = values_capacity)
  * as scratch; reads the pair count back (one synchronisation). */
-int gs_bin_records(gs_ctx* ctx, const gs_camera* cams, int32_t V, int64_t n, int32_t tile_w, int32_t tile_h,
+int gs_bin_records(gs_ctx* ctx, const gs_camera* cams, int32_t V, int64_t n, int32_t bin_w, int32_t bin_h,
                    const uint32_t* rect, const float* depth, uint32_t* values, int64_t values_capacity,
                    uint32_t* ranges, int64_t* n_pairs, void* state, size_t state_bytes, void* stream);
 
-/* Tile-shape autotuner: times forward + backward of the given scene for every
- * supported tile shape (allocating temporary device buffers), keeps the
- * fastest as the context's choice for this (V, sizes, n) class and returns
- * it in *tile_w, *tile_h (HOST).  Synchronises the device. */
+/* Launch-shape autotuner: times forward + backward of the given scene for
+ * every supported (tile shape, pixels per thread) pair with 64x64 bins, then
+ * for the best tile every bin size that is a multiple of it (allocating
+ * temporary device buffers); keeps the fastest as the context's choice for
+ * this (V, sizes, n) class and returns tile and bin (HOST outputs).
+ * Synchronises the device.  No result depends on the choice. */
 int gs_autotune(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
-                int32_t iters, int32_t* tile_w, int32_t* tile_h, void* stream);
+                int32_t iters, int32_t* tile_w, int32_t* tile_h, int32_t* bin_w, int32_t* bin_h, void* stream);
+
+/* Set the context's bin choice explicitly (0, 0 restores 64x64). */
+int gs_set_bin(gs_ctx* ctx, int32_t bin_w, int32_t bin_h);
 
 /* Set the context's tile choice explicitly (0, 0 restores 16x16). */
 int gs_set_tile(gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
+
+/* Pixels each thread of the compositing kernels owns for a tile shape (1, 2
+ * or 4; 4 needs a tile width of 32 or a 16x16 tile, 8x8 tiles take 1).  Does
+ * not change any result, only the launch shape; gs_autotune sets it too. */
+int gs_set_pixels_per_thread(gs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t ppt);
 
 #ifdef __cplusplus
 }

@@ -163,6 +163,7 @@ class Context:
             raise GSError(rc, self.lib.gs_last_error(None).decode())
         self.h = h
         self.pair_estimate = 1 << 16
+        self.bin_choice = (64, 64)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -179,25 +180,32 @@ class Context:
         return torch.device("cuda", self.device)
 
     # -------------------------------------------------------------- sizes
-    def state_bytes(self, cams, n: int, capacity: int, tile=(0, 0)) -> int:
+    def state_bytes(self, cams, n: int, capacity: int, bin=(0, 0)) -> int:
         cams = as_cameras(cams)
-        b = self.lib.gs_state_bytes(cam_array(cams), len(cams), n, capacity, tile[0], tile[1])
+        b = self.lib.gs_state_bytes(cam_array(cams), len(cams), n, capacity, bin[0], bin[1])
         if b == 0:
             raise GSError(A.GS_EINVAL, "invalid arguments for gs_state_bytes")
         return int(b)
 
-    def workspace_bytes(self, cams, n: int, sh_degree: int, capacity: int, tile=(0, 0)) -> int:
+    def workspace_bytes(self, cams, n: int, sh_degree: int, capacity: int, bin=(0, 0)) -> int:
         cams = as_cameras(cams)
-        b = self.lib.gs_step_workspace_bytes(cam_array(cams), len(cams), n, sh_degree, capacity, tile[0], tile[1])
+        b = self.lib.gs_step_workspace_bytes(cam_array(cams), len(cams), n, sh_degree, capacity, bin[0], bin[1])
         if b == 0:
             raise GSError(A.GS_EINVAL, "invalid arguments for gs_step_workspace_bytes")
         return int(b)
 
-    def set_tile(self, tw: int, th: int):
+    def set_tile(self, tw: int, th: int, ppt: Optional[int] = None):
         self._check(self.lib.gs_set_tile(self.h, tw, th))
+        if ppt is not None:
+            self._check(self.lib.gs_set_pixels_per_thread(self.h, tw, th, ppt))
+
+    def set_bin(self, bw: int, bh: int):
+        self._check(self.lib.gs_set_bin(self.h, bw, bh))
+        self.bin_choice = (int(bw), int(bh)) if (bw, bh) != (0, 0) else (64, 64)
 
     # -------------------------------------------------------------- render
-    def forward(self, g: Gaussians, cams, poses: torch.Tensor, tile=(0, 0), capacity: Optional[int] = None):
+    def forward(self, g: Gaussians, cams, poses: torch.Tensor, tile=(0, 0), capacity: Optional[int] = None,
+                bin=(0, 0)):
         """Returns (color, depth, alpha, state, plan)."""
         cams = as_cameras(cams)
         ca = cam_array(cams)
@@ -212,10 +220,11 @@ class Context:
         _need(poses, 16 * V, "poses", device=dev)
         cap = int(capacity if capacity is not None else self.pair_estimate)
         gst = g.struct()
+        bw, bh = self._bin(bin)
         for _ in range(3):
-            nbytes = self.state_bytes(cams, g.n, cap, tile)
+            nbytes = self.state_bytes(cams, g.n, cap, (bw, bh))
             state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-            plan = A.gs_plan(tile[0], tile[1], cap, 0, 0)
+            plan = A.gs_plan(tile[0], tile[1], bw, bh, cap, 0, 0)
             rc = self.lib.gs_render_forward(self.h, ctypes.byref(gst), ca, _p(poses), V, _p(color), _p(depth),
                                             _p(alpha), _p(state), nbytes, ctypes.byref(plan), _stream())
             if rc == A.GS_ECAPACITY:
@@ -243,7 +252,7 @@ class Context:
         _need(dC, 3 * npix, "dL_dcolor", device=self.torch_device)
         _need(dD, npix, "dL_ddepth", device=self.torch_device)
         _need(dA, npix, "dL_dalpha", device=self.torch_device)
-        if state.numel() < self.state_bytes(cams, g.n, plan.pair_capacity, (plan.tile_w, plan.tile_h)):
+        if state.numel() < self.state_bytes(cams, g.n, plan.pair_capacity, (plan.bin_w, plan.bin_h)):
             raise ValueError("state is smaller than the plan requires")
         rc = self.lib.gs_render_backward(self.h, ctypes.byref(gst), cam_array(cams), _p(poses.contiguous()), V,
                                          _p(state), state.numel(), ctypes.byref(plan), _p(dC), _p(dD), _p(dA),
@@ -276,9 +285,17 @@ class Context:
         self._check(rc)
         return residual[:M], loss, dpose
 
+    def _bin(self, bin):
+        """Resolve (0, 0) to the context's bin choice (kept in Python too, so
+        the state can be sized before the call)."""
+        if tuple(bin) != (0, 0):
+            return int(bin[0]), int(bin[1])
+        return self.bin_choice
+
     def bin_records(self, cams, n: int, tile: Tuple[int, int], rect: torch.Tensor, depth: torch.Tensor,
                     capacity: int):
-        """Binning stage alone: returns (values [P] int64, ranges [T,2] int64)."""
+        """Binning stage alone for bins of ``tile`` = (w, h) pixels: returns
+        (values [P] int64, ranges [bins,2] int64)."""
         cams = as_cameras(cams)
         V = len(cams)
         dev = self.torch_device
@@ -302,16 +319,19 @@ class Context:
         u = lambda t: t.to(torch.int64) & 0xFFFFFFFF
         return u(values[:P]), u(ranges)
 
-    def autotune(self, g: Gaussians, cams, poses, iters: int = 3) -> Tuple[int, int]:
+    def autotune(self, g: Gaussians, cams, poses, iters: int = 3):
+        """Returns ((tile_w, tile_h), (bin_w, bin_h)) and makes them the context's choice."""
         cams = as_cameras(cams)
-        tw, th = ctypes.c_int32(), ctypes.c_int32()
+        tw, th, bw, bh = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         gst = g.struct()
         _check_gaussians(g, self.torch_device)
         _need(poses.contiguous(), 16 * len(cams), "poses", device=self.torch_device)
         rc = self.lib.gs_autotune(self.h, ctypes.byref(gst), cam_array(cams), _p(poses.contiguous()), len(cams),
-                                  iters, ctypes.byref(tw), ctypes.byref(th), _stream())
+                                  iters, ctypes.byref(tw), ctypes.byref(th), ctypes.byref(bw), ctypes.byref(bh),
+                                  _stream())
         self._check(rc)
-        return int(tw.value), int(th.value)
+        self.bin_choice = (int(bw.value), int(bh.value))
+        return (int(tw.value), int(th.value)), self.bin_choice
 
 
 _default: Dict[int, Context] = {}
@@ -390,13 +410,15 @@ class StepOptions:
     adam_b2: float = 0.999
     adam_eps: float = 1e-8
     tile: Tuple[int, int] = (0, 0)
+    bin: Tuple[int, int] = (0, 0)
 
-    def struct(self, capacity: int) -> A.gs_step_opts:
+    def struct(self, capacity: int, bin=None) -> A.gs_step_opts:
+        b = self.bin if bin is None else bin
         return A.gs_step_opts(self.w_color, self.w_depth, self.w_reproj, self.huber_delta, int(self.use_gate),
                               self.gate_gamma, int(self.update_gaussians), int(self.update_poses),
                               int(self.accumulate_grads), int(self.use_graph), self.lr_means, self.lr_log_scales,
                               self.lr_quats, self.lr_opacity, self.lr_colors, self.lr_pose, self.adam_b1,
-                              self.adam_b2, self.adam_eps, self.tile[0], self.tile[1], capacity)
+                              self.adam_b2, self.adam_eps, self.tile[0], self.tile[1], b[0], b[1], capacity)
 
 
 # the paper's Fusion Bridge weights (Supplementary, hyper-parameter table):
@@ -439,13 +461,14 @@ class MappingStep:
             _need(self.points, 3 * self.M, "points", device=dev)
             _need(self.uv, 2 * self.M, "uv", device=dev)
             _need(self.vidx, self.M, "view_idx", dtype=torch.int32, device=dev)
+        self.bin = ctx._bin(opts.bin)
         if capacity is None:
             # size from one counting forward pass
-            _, _, _, _, plan = ctx.forward(g, self.cams, self.poses, tile=opts.tile)
+            _, _, _, _, plan = ctx.forward(g, self.cams, self.poses, tile=opts.tile, bin=self.bin)
             capacity = int(plan.n_pairs * 1.3) + 4096
         self.capacity = int(capacity)
         npix = sum(c.npix for c in self.cams)
-        self.ws_bytes = ctx.workspace_bytes(self.cams, g.n, g.sh_degree, self.capacity, opts.tile)
+        self.ws_bytes = ctx.workspace_bytes(self.cams, g.n, g.sh_degree, self.capacity, self.bin)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         self.grads = g.zeros_like()
         K = sh_coeffs(g.sh_degree)
@@ -467,11 +490,13 @@ class MappingStep:
         self._ca = cam_array(self.cams)
         self._tg = A.gs_targets(_p(self.tc), _p(self.td), _p(self.mask))
         self._mt = A.gs_matches(_p(self.points), _p(self.uv), _p(self.vidx), self.M)
-        self._opts = self.opts.struct(self.capacity)
+        self._opts = self.opts.struct(self.capacity, self.bin)
 
     def set_options(self, opts: StepOptions):
+        if self.ctx._bin(opts.bin) != self.bin:
+            raise ValueError("the bin size is fixed when the workspace is sized")
         self.opts = opts
-        self._opts = opts.struct(self.capacity)
+        self._opts = opts.struct(self.capacity, self.bin)
 
     def __call__(self):
         rc = self.ctx.lib.gs_mapping_step(self.ctx.h, ctypes.byref(self._gst), ctypes.byref(self._gg),
@@ -487,8 +512,8 @@ class MappingStep:
         L = self.ctx.lib
         ns = L.gs_num_stages()
         ms = (ctypes.c_float * ns)()
-        fc = (ctypes.c_int64 * 2)()
-        o = self.opts.struct(self.capacity)
+        fc = (ctypes.c_int64 * 4)()
+        o = self.opts.struct(self.capacity, self.bin)
         o.use_graph = 0
         rc = L.gs_step_profile(self.ctx.h, ctypes.byref(self._gst), ctypes.byref(self._gg), ctypes.byref(self._adam),
                                self._ca, _p(self.poses), self.V, ctypes.byref(self._tg), ctypes.byref(self._mt),
@@ -496,7 +521,7 @@ class MappingStep:
                                _p(self.alpha), _p(self.loss), _p(self.dpose), ms, fc if counts else None, _stream())
         self.ctx._check(rc)
         names = [L.gs_stage_name(i).decode() for i in range(ns)]
-        return dict(zip(names, list(ms))), ((int(fc[0]), int(fc[1])) if counts else None)
+        return dict(zip(names, list(ms))), (tuple(int(x) for x in fc) if counts else None)
 
     def status(self) -> Dict[str, int]:
         fl = ctypes.c_int32()

@@ -24,8 +24,11 @@ struct gs_ctx {
     hipStream_t side = nullptr;      // capture / replay stream used when the caller passes the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int tile_w = 16, tile_h = 16;
+    int bin_w = 64, bin_h = 64;
+    std::unordered_map<int, int> ppt;  // pixels per thread chosen per tile shape (key tw * 1000 + th)
     std::unordered_map<uint64_t, hipGraphExec_t> graphs;
-    std::unordered_map<uint64_t, std::pair<int, int>> tuned;
+    struct Tuned { int tw, th, bw, bh, ppt; };
+    std::unordered_map<uint64_t, Tuned> tuned;
 };
 
 namespace {
@@ -72,24 +75,49 @@ bool tile_ok(int tw, int th) {
            (tw == 32 && th == 16);
 }
 
+// pixels per thread the compositing kernels are built for (whole wavefronts)
+bool ppt_ok(int tw, int th, int ppt) {
+    if (!tile_ok(tw, th)) return false;
+    if (ppt == 1) return true;
+    if (ppt == 2) return !(tw == 8 && th == 8);
+    if (ppt == 4) return (tw == 16 && th == 16) || (tw == 32);
+    return false;
+}
+
+int ppt_of(const gs_ctx* c, int tw, int th) {
+    if (c) {
+        auto it = c->ppt.find(tw * 1000 + th);
+        if (it != c->ppt.end()) return it->second;
+    }
+    return ppt_ok(tw, th, 2) ? 2 : 1;
+}
+
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Validate the cameras and fill the per-view table.
-int build_vt(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int tw, int th, float wc, float wd,
-             gs::ViewTable& vt) {
+bool bin_ok(int bw, int bh) { return bw >= 8 && bh >= 8 && bw <= 2048 && bh <= 2048 && bw % 8 == 0 && bh % 8 == 0; }
+
+// Validate the cameras and fill the per-view table (compositing tiles tw x th
+// inside bins bw x bh).
+int build_vt(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int tw, int th, int bw, int bh, float wc,
+             float wd, gs::ViewTable& vt) {
     if (!cams) return fail(c, GS_EINVAL, "cams is NULL");
     if (V < 1 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V=%d outside [1, %d]", V, GS_MAX_VIEWS);
     if (n < 0) return fail(c, GS_EINVAL, "n=%lld is negative", (long long)n);
     if ((int64_t)V * n >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "V*n=%lld too large", (long long)V * n);
     if (!tile_ok(tw, th)) return fail(c, GS_EINVAL, "unsupported tile shape %dx%d", tw, th);
+    if (!bin_ok(bw, bh) || bw % tw || bh % th)
+        return fail(c, GS_EINVAL, "bin %dx%d is not a multiple of the tile %dx%d within [8, 2048]", bw, bh, tw, th);
     std::memset(&vt, 0, sizeof vt);
     vt.V = V;
     vt.tw = tw;
     vt.th = th;
+    vt.bw = bw;
+    vt.bh = bh;
+    vt.ppt = ppt_of(c, tw, th);
     vt.n = (int)n;
-    int64_t toff = 0, poff = 0;
+    int64_t toff = 0, poff = 0, boff = 0;
     for (int v = 0; v < V; v++) {
         const gs_camera& cm = cams[v];
         if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
@@ -103,18 +131,30 @@ int build_vt(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int tw, int
         vi.tiles_x = (int)ceil_div(cm.width, tw);
         vi.tiles_y = (int)ceil_div(cm.height, th);
         vi.tile_off = (int)toff;
+        vi.bins_x = (int)ceil_div(cm.width, bw);
+        vi.bins_y = (int)ceil_div(cm.height, bh);
+        vi.bin_off = (int)boff;
         vi.pix_off = (int)poff;
         vi.fx = cm.fx; vi.fy = cm.fy; vi.cx = cm.cx; vi.cy = cm.cy;
         const double np = (double)cm.width * cm.height;
         vi.lsc = (float)((double)wc / ((double)V * 3.0 * np));
         vi.lsd = (float)((double)wd / ((double)V * np));
         toff += (int64_t)vi.tiles_x * vi.tiles_y;
+        boff += (int64_t)vi.bins_x * vi.bins_y;
         poff += (int64_t)cm.width * cm.height;
         if (3 * poff >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "too many pixels in total");
     }
     vt.n_tiles = (int)toff;
+    vt.n_bins = (int)boff;
     vt.n_pix = (int)poff;
     return GS_OK;
+}
+
+// tiles of the smallest supported tile shape (upper bound for per-tile buffers)
+int64_t max_tiles(const gs_camera* cams, int32_t V) {
+    int64_t t = 0;
+    for (int v = 0; v < V; v++) t += ceil_div(cams[v].width, 8) * ceil_div(cams[v].height, 8);
+    return t;
 }
 
 int check_gaussians(gs_ctx* c, const gs_gaussians* g) {
@@ -175,7 +215,7 @@ Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     p.g2 = reinterpret_cast<float*>(base + L.off_g2);
     p.posepart = reinterpret_cast<double*>(base + L.off_posepart);
     p.scal = reinterpret_cast<uint32_t*>(base + L.off_scalars);
-    p.vals = reinterpret_cast<uint32_t*>(base + ((tile_passes(L.n_tiles) & 1) ? L.off_pv1 : L.off_pv0));
+    p.vals = reinterpret_cast<uint32_t*>(base + ((tile_passes(L.n_bins) & 1) ? L.off_pv1 : L.off_pv0));
     p.dC = workspace ? reinterpret_cast<float*>(base + L.off_dC) : nullptr;
     p.dD = workspace ? reinterpret_cast<float*>(base + L.off_dD) : nullptr;
     p.tilepart = workspace ? reinterpret_cast<double2*>(base + L.off_tilepart) : nullptr;
@@ -193,6 +233,16 @@ void resolve_tile(const gs_ctx* c, int32_t tw, int32_t th, int& otw, int& oth) {
     }
 }
 
+void resolve_bin(const gs_ctx* c, int32_t bw, int32_t bh, int& obw, int& obh) {
+    if (bw == 0 && bh == 0) {
+        obw = c ? c->bin_w : 64;
+        obh = c ? c->bin_h : 64;
+    } else {
+        obw = bw;
+        obh = bh;
+    }
+}
+
 uint64_t fnv(uint64_t h, const void* p, size_t n) {
     const unsigned char* b = static_cast<const unsigned char*>(p);
     for (size_t i = 0; i < n; i++) {
@@ -206,11 +256,12 @@ uint64_t fnv(uint64_t h, const void* p, size_t n) {
 
 namespace gs {
 
-Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace) {
+Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, int64_t tiles_bound) {
     Layout L;
     std::memset(&L, 0, sizeof L);
     L.R = (int64_t)vt.V * n;
     L.cap = cap;
+    L.n_bins = vt.n_bins;
     L.n_tiles = vt.n_tiles;
     L.n_pix = vt.n_pix;
     const int64_t R = L.R;
@@ -240,7 +291,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace) 
     L.off_hist = take((size_t)256 * L.sort_blocks * 4);
     const int64_t nscan = std::max<int64_t>(std::max<int64_t>(ceil_div(R, 2048), ceil_div(256 * L.sort_blocks, 2048)), 1);
     L.off_scan = take((size_t)nscan * 4);
-    L.off_ranges = take((size_t)vt.n_tiles * 8);
+    L.off_ranges = take((size_t)vt.n_bins * 8);
     L.off_tfin = take((size_t)vt.n_pix * 4);
     L.off_last = take((size_t)vt.n_pix * 4);
     L.off_g2 = take((size_t)R * kG2Stride * 4);
@@ -248,7 +299,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace) 
     if (workspace) {
         L.off_dC = take((size_t)vt.n_pix * 3 * 4);
         L.off_dD = take((size_t)vt.n_pix * 4);
-        L.off_tilepart = take((size_t)vt.n_tiles * 16);
+        L.off_tilepart = take((size_t)std::max<int64_t>(tiles_bound, vt.n_tiles) * 16);
         L.off_rpacc = take((size_t)vt.V * 8 * 8);
     }
     L.bytes = o;
@@ -319,22 +370,39 @@ int gs_set_tile(gs_ctx* c, int32_t tw, int32_t th) {
     return GS_OK;
 }
 
-size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t cap, int32_t tw, int32_t th) {
+int gs_set_bin(gs_ctx* c, int32_t bw, int32_t bh) {
+    if (!c) return GS_EINVAL;
+    if (bw == 0 && bh == 0) { bw = 64; bh = 64; }
+    if (!bin_ok(bw, bh)) return fail(c, GS_EINVAL, "unsupported bin %dx%d", bw, bh);
+    c->bin_w = bw;
+    c->bin_h = bh;
+    return GS_OK;
+}
+
+int gs_set_pixels_per_thread(gs_ctx* c, int32_t tw, int32_t th, int32_t ppt) {
+    if (!c) return GS_EINVAL;
+    if (!ppt_ok(tw, th, ppt))
+        return fail(c, GS_EINVAL, "no compositing kernel for tile %dx%d with %d pixels per thread", tw, th, ppt);
+    c->ppt[tw * 1000 + th] = ppt;
+    return GS_OK;
+}
+
+size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t cap, int32_t bw, int32_t bh) {
     gs::ViewTable vt;
-    if (tw == 0 && th == 0) { tw = 16; th = 16; }
+    resolve_bin(nullptr, bw, bh, bw, bh);
     if (cap < 0 || cap >= ((int64_t)1 << 31)) return 0;
-    if (build_vt(nullptr, cams, V, n, tw, th, 0.f, 0.f, vt) != GS_OK) return 0;
+    if (build_vt(nullptr, cams, V, n, 8, 8, bw, bh, 0.f, 0.f, vt) != GS_OK) return 0;
     return gs::make_layout(vt, n, cap, false).bytes;
 }
 
-size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int32_t sh, int64_t cap, int32_t tw,
-                               int32_t th) {
+size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int32_t sh, int64_t cap, int32_t bw,
+                               int32_t bh) {
     (void)sh;
     gs::ViewTable vt;
-    if (tw == 0 && th == 0) { tw = 16; th = 16; }
+    resolve_bin(nullptr, bw, bh, bw, bh);
     if (cap < 0 || cap >= ((int64_t)1 << 31)) return 0;
-    if (build_vt(nullptr, cams, V, n, tw, th, 0.f, 0.f, vt) != GS_OK) return 0;
-    return gs::make_layout(vt, n, cap, true).bytes;
+    if (build_vt(nullptr, cams, V, n, 8, 8, bw, bh, 0.f, 0.f, vt) != GS_OK) return 0;
+    return gs::make_layout(vt, n, cap, true, max_tiles(cams, V)).bytes;
 }
 
 int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
@@ -347,10 +415,11 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     if (!poses || !color || !depth || !alpha || !state) return fail(c, GS_EINVAL, "a device pointer is NULL");
     if (plan->pair_capacity < 0 || plan->pair_capacity >= ((int64_t)1 << 31))
         return fail(c, GS_EINVAL, "pair_capacity outside [0, 2^31)");
-    int tw, th;
+    int tw, th, bw, bh;
     resolve_tile(c, plan->tile_w, plan->tile_h, tw, th);
+    resolve_bin(c, plan->bin_w, plan->bin_h, bw, bh);
     gs::ViewTable vt;
-    if ((r = build_vt(c, cams, V, g->n, tw, th, 0.f, 0.f, vt))) return r;
+    if ((r = build_vt(c, cams, V, g->n, tw, th, bw, bh, 0.f, 0.f, vt))) return r;
     const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false);
     if (state_bytes < L.bytes)
         return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
@@ -361,6 +430,8 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     const gs::Params P = params_of(g);
     plan->tile_w = tw;
     plan->tile_h = th;
+    plan->bin_w = bw;
+    plan->bin_h = bh;
     GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, nullptr, s));
     GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
@@ -388,10 +459,12 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     if (!poses || !state || !dL_dpose || !grads) return fail(c, GS_EINVAL, "a device pointer is NULL");
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->colors))
         return fail(c, GS_EINVAL, "a gradient pointer is NULL");
-    if (!tile_ok(plan->tile_w, plan->tile_h)) return fail(c, GS_EINVAL, "plan does not come from a forward pass");
+    if (!tile_ok(plan->tile_w, plan->tile_h) || !bin_ok(plan->bin_w, plan->bin_h))
+        return fail(c, GS_EINVAL, "plan does not come from a forward pass");
     if (plan->n_pairs > plan->pair_capacity) return fail(c, GS_ECAPACITY, "the forward pass overflowed");
     gs::ViewTable vt;
-    if ((r = build_vt(c, cams, V, g->n, plan->tile_w, plan->tile_h, 0.f, 0.f, vt))) return r;
+    if ((r = build_vt(c, cams, V, g->n, plan->tile_w, plan->tile_h, plan->bin_w, plan->bin_h, 0.f, 0.f, vt)))
+        return r;
     const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false);
     if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
     DeviceGuard dg(c->device);
@@ -416,7 +489,7 @@ int gs_reproj_residual(gs_ctx* c, const gs_camera* cams, const float* poses, int
     if (!poses || !loss || !dL_dpose) return fail(c, GS_EINVAL, "a device pointer is NULL");
     if (M > 0 && (!points || !uv || !view_idx || !residual)) return fail(c, GS_EINVAL, "a match pointer is NULL");
     gs::ViewTable vt;
-    int r = build_vt(c, cams, V, 0, 16, 16, 0.f, 0.f, vt);
+    int r = build_vt(c, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt);
     if (r) return r;
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -520,10 +593,11 @@ int check_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_ad
         return fail(c, GS_EINVAL, "an update needs the Adam state");
     if (o->pair_capacity < 0 || o->pair_capacity >= ((int64_t)1 << 31))
         return fail(c, GS_EINVAL, "pair_capacity outside [0, 2^31)");
-    int tw, th;
+    int tw, th, bw, bh;
     resolve_tile(c, o->tile_w, o->tile_h, tw, th);
-    if ((r = build_vt(c, cams, V, g->n, tw, th, o->w_color, o->w_depth, vt))) return r;
-    L = gs::make_layout(vt, g->n, o->pair_capacity, true);
+    resolve_bin(c, o->bin_w, o->bin_h, bw, bh);
+    if ((r = build_vt(c, cams, V, g->n, tw, th, bw, bh, o->w_color, o->w_depth, vt))) return r;
+    L = gs::make_layout(vt, g->n, o->pair_capacity, true, max_tiles(cams, V));
     if (ws_bytes < L.bytes) return fail(c, GS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
     return GS_OK;
 }
@@ -622,12 +696,12 @@ int gs_step_profile(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const 
     auto destroy = [&]() {
         for (int i = 0; i <= kNumStages; i++) (void)hipEventDestroy(ev[i]);
     };
-    hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t*>(c->counts), 0u, 4, s);
+    hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t*>(c->counts), 0u, 8, s);
     if (e != hipSuccess) { destroy(); return hip_fail(c, e, "counter fill"); }
     r = enqueue_step(c, vt, L, static_cast<char*>(ws), g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
                      dL_dpose, s, ev, frag_counts ? c->counts : nullptr);
     if (r) { destroy(); return r; }
-    unsigned long long hc[2] = {0, 0};
+    unsigned long long hc[4] = {0, 0, 0, 0};
     e = hipMemcpyAsync(hc, c->counts, sizeof hc, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { destroy(); return hip_fail(c, e, "profile read-back"); }
@@ -638,8 +712,7 @@ int gs_step_profile(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const 
         stage_ms[i] = ms;
     }
     if (frag_counts) {
-        frag_counts[0] = (int64_t)hc[0];
-        frag_counts[1] = (int64_t)hc[1];
+        for (int i = 0; i < 4; i++) frag_counts[i] = (int64_t)hc[i];
     }
     destroy();
     return GS_OK;
@@ -659,7 +732,7 @@ int gs_step_status(gs_ctx* c, const void* ws, size_t ws_bytes, int32_t* flags, i
     return GS_OK;
 }
 
-int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32_t tw, int32_t th,
+int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32_t bw, int32_t bh,
                    const uint32_t* rect, const float* depth, uint32_t* values, int64_t cap, uint32_t* ranges,
                    int64_t* n_pairs, void* state, size_t state_bytes, void* stream) {
     if (!c) return GS_EINVAL;
@@ -668,7 +741,7 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
         return fail(c, GS_EINVAL, "a device pointer is NULL");
     if (cap < 0 || cap >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "values_capacity outside [0, 2^31)");
     gs::ViewTable vt;
-    int r = build_vt(c, cams, V, n, tw, th, 0.f, 0.f, vt);
+    int r = build_vt(c, cams, V, n, 8, 8, bw, bh, 0.f, 0.f, vt);
     if (r) return r;
     const gs::Layout L = gs::make_layout(vt, n, cap, false);
     if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
@@ -688,29 +761,35 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
     uint32_t* vals = nullptr;
     GS_HIP(c, gs::launch_binning_emit(vt, L, base, p.rec.rect, total, s, &vals));
     if (total > 0) GS_HIP(c, hipMemcpyAsync(values, vals, (size_t)total * 4, hipMemcpyDeviceToDevice, s));
-    GS_HIP(c, hipMemcpyAsync(ranges, p.ranges, (size_t)L.n_tiles * 8, hipMemcpyDeviceToDevice, s));
+    GS_HIP(c, hipMemcpyAsync(ranges, p.ranges, (size_t)L.n_bins * 8, hipMemcpyDeviceToDevice, s));
     return GS_OK;
 }
 
 int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
-                int32_t iters, int32_t* tile_w, int32_t* tile_h, void* stream) {
+                int32_t iters, int32_t* tile_w, int32_t* tile_h, int32_t* bin_w, int32_t* bin_h, void* stream) {
     if (!c) return GS_EINVAL;
-    if (!tile_w || !tile_h) return fail(c, GS_EINVAL, "tile_w / tile_h is NULL");
+    if (!tile_w || !tile_h || !bin_w || !bin_h) return fail(c, GS_EINVAL, "an output pointer is NULL");
     int r = check_gaussians(c, g);
     if (r) return r;
     if (!poses) return fail(c, GS_EINVAL, "poses is NULL");
     if (iters < 1) iters = 1;
     gs::ViewTable vt0;
-    if ((r = build_vt(c, cams, V, g->n, 16, 16, 0.f, 0.f, vt0))) return r;
+    if ((r = build_vt(c, cams, V, g->n, 16, 16, 64, 64, 0.f, 0.f, vt0))) return r;
     uint64_t key = 1469598103934665603ull;
     key = fnv(key, &V, sizeof V);
     key = fnv(key, cams, sizeof(gs_camera) * V);
     key = fnv(key, &g->n, sizeof g->n);
     key = fnv(key, &g->sh_degree, sizeof g->sh_degree);
+    auto apply = [&](const gs_ctx::Tuned& t) {
+        c->tile_w = *tile_w = t.tw;
+        c->tile_h = *tile_h = t.th;
+        c->bin_w = *bin_w = t.bw;
+        c->bin_h = *bin_h = t.bh;
+        c->ppt[t.tw * 1000 + t.th] = t.ppt;
+    };
     auto hit = c->tuned.find(key);
     if (hit != c->tuned.end()) {
-        c->tile_w = *tile_w = hit->second.first;
-        c->tile_h = *tile_h = hit->second.second;
+        apply(hit->second);
         return GS_OK;
     }
     DeviceGuard dg(c->device);
@@ -718,7 +797,7 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
     const int64_t n = g->n;
     const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
     const int64_t npix = vt0.n_pix;
-    // scratch: images, upstream gradients (ones), Gaussian and pose gradients
+    // scratch: images, upstream gradients, Gaussian and pose gradients
     std::vector<void*> bufs;
     auto dalloc = [&](size_t bytes) -> void* {
         void* p = nullptr;
@@ -745,24 +824,22 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    const int cand[5][2] = {{16, 16}, {16, 8}, {8, 8}, {32, 8}, {32, 16}};
-    float best = 1e30f;
-    int bw = 16, bh = 16;
-    int rc = GS_OK;
-    for (int k = 0; k < 5 && rc == GS_OK; k++) {
-        gs_plan plan{cand[k][0], cand[k][1], 0, 0, 0};
-        // size the state from a count-only forward at zero capacity
+    const auto saved_ppt = c->ppt;
+    // time forward + backward of one launch shape; < 0 on failure
+    auto time_shape = [&](int tw, int th, int ppt, int bw, int bh, int* rc) -> float {
+        c->ppt[tw * 1000 + th] = ppt;
+        gs_plan plan{tw, th, bw, bh, 0, 0, 0};
         void* st = nullptr;
-        size_t sb = gs_state_bytes(cams, V, n, 0, plan.tile_w, plan.tile_h);
-        if (hipMalloc(&st, sb) != hipSuccess) { rc = fail(c, GS_ENOMEM, "autotune state"); break; }
+        size_t sb = gs_state_bytes(cams, V, n, 0, bw, bh);
+        if (hipMalloc(&st, sb) != hipSuccess) { *rc = fail(c, GS_ENOMEM, "autotune state"); return -1.f; }
         int f = gs_render_forward(c, g, cams, poses, V, img, img + 3 * npix, img + 4 * npix, st, sb, &plan, stream);
         (void)hipFree(st);
-        if (f != GS_OK && f != GS_ECAPACITY) { rc = f; break; }
+        if (f != GS_OK && f != GS_ECAPACITY) { *rc = f; return -1.f; }
         plan.pair_capacity = plan.n_pairs;
-        sb = gs_state_bytes(cams, V, n, plan.pair_capacity, plan.tile_w, plan.tile_h);
-        if (hipMalloc(&st, sb) != hipSuccess) { rc = fail(c, GS_ENOMEM, "autotune state"); break; }
+        sb = gs_state_bytes(cams, V, n, plan.pair_capacity, bw, bh);
+        if (hipMalloc(&st, sb) != hipSuccess) { *rc = fail(c, GS_ENOMEM, "autotune state"); return -1.f; }
         float total = 0.f;
-        for (int it = 0; it <= iters && rc == GS_OK; it++) {
+        for (int it = 0; it <= iters; it++) {
             (void)hipEventRecord(e0, s);
             int a = gs_render_forward(c, g, cams, poses, V, img, img + 3 * npix, img + 4 * npix, st, sb, &plan, stream);
             int b = a == GS_OK ? gs_render_backward(c, g, cams, poses, V, st, sb, &plan, img, img + 3 * npix,
@@ -770,25 +847,47 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
                                : a;
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
-            if (b != GS_OK) { rc = b; break; }
+            if (b != GS_OK) { *rc = b; break; }
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
             if (it > 0) total += ms;
         }
         (void)hipFree(st);
-        if (rc == GS_OK && total < best) {
-            best = total;
-            bw = cand[k][0];
-            bh = cand[k][1];
+        return *rc == GS_OK ? total : -1.f;
+    };
+    // stage 1: tile shape and pixels per thread, bins 64x64 (or the tile's multiple)
+    const int cand[12][3] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {16, 8, 1}, {16, 8, 2}, {8, 8, 1},
+                             {32, 8, 1},  {32, 8, 2},  {32, 8, 4},  {32, 16, 1}, {32, 16, 2}, {32, 16, 4}};
+    gs_ctx::Tuned best{16, 16, 64, 64, 2};
+    float best_ms = 1e30f;
+    int rc = GS_OK;
+    for (int k = 0; k < 12 && rc == GS_OK; k++) {
+        const float ms = time_shape(cand[k][0], cand[k][1], cand[k][2], 64, 64, &rc);
+        if (rc == GS_OK && ms < best_ms) {
+            best_ms = ms;
+            best = gs_ctx::Tuned{cand[k][0], cand[k][1], 64, 64, cand[k][2]};
+        }
+    }
+    // stage 2: bin size for that tile
+    const int bins[9][2] = {{32, 16}, {32, 32}, {64, 32}, {64, 64}, {128, 64}, {128, 128}, {256, 128}, {256, 256},
+                            {512, 256}};
+    for (int k = 0; k < 9 && rc == GS_OK; k++) {
+        const int bw = bins[k][0], bh = bins[k][1];
+        if (bw % best.tw || bh % best.th || (bw == 64 && bh == 64)) continue;
+        const float ms = time_shape(best.tw, best.th, best.ppt, bw, bh, &rc);
+        if (rc == GS_OK && ms < best_ms) {
+            best_ms = ms;
+            best.bw = bw;
+            best.bh = bh;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release();
+    c->ppt = saved_ppt;
     if (rc != GS_OK) return rc;
-    c->tuned[key] = {bw, bh};
-    c->tile_w = *tile_w = bw;
-    c->tile_h = *tile_h = bh;
+    c->tuned[key] = best;
+    apply(best);
     return GS_OK;
 }
 

@@ -1,13 +1,15 @@
-// Binning: visible records -> (tile, depth, record)-ordered pair list and
-// per-tile ranges (the front-to-back order of the Sec. 3.4 rasteriser).
+// Binning: visible records -> (bin, depth, record)-ordered pair list and
+// per-bin ranges (the front-to-back order of the Sec. 3.4 rasteriser).  A bin
+// is a rectangle of pixels (a multiple of the compositing tile); each
+// compositing tile reads its bin's list.
 //
 // Two-stage design instead of one 64-bit-key sort of all pairs:
 //   1. compact the visible records (scan of a 0/1 flag) and sort them by the
 //      bit pattern of their positive FP32 depth (stable LSD radix sort, so
 //      equal depths keep ascending record order);
-//   2. emit one pair (global tile id, record) per touched tile in that depth
-//      order and sort the pairs stably by tile id only (ceil(log2 tiles)
-//      bits).  Stability makes the result the (tile, depth, record) order.
+//   2. emit one pair (global bin id, record) per touched bin in that depth
+//      order and sort the pairs stably by bin id only (ceil(log2 bins)
+//      bits).  Stability makes the result the (bin, depth, record) order.
 // Stage 1 sorts records (millions), stage 2 sorts only 8-18 key bits of the
 // pairs, instead of ~50 bits.
 //
@@ -329,11 +331,11 @@ __global__ void emit_kernel(ViewTable vt, const uint32_t* ids, const uint32_t* n
     const int v = (int)(r / (uint32_t)vt.n);
     const ViewInfo& vi = vt.v[v];
     const uint2 rc = rect[r];
-    const uint32_t tx0 = (rc.x & 0xffffu) / vt.tw, tx1 = (rc.x >> 16) / vt.tw;
-    const uint32_t ty0 = (rc.y & 0xffffu) / vt.th, ty1 = (rc.y >> 16) / vt.th;
+    const uint32_t tx0 = (rc.x & 0xffffu) / vt.bw, tx1 = (rc.x >> 16) / vt.bw;
+    const uint32_t ty0 = (rc.y & 0xffffu) / vt.bh, ty1 = (rc.y >> 16) / vt.bh;
     uint32_t o = off[i];
     for (uint32_t ty = ty0; ty <= ty1; ty++) {
-        const uint32_t row = (uint32_t)vi.tile_off + ty * (uint32_t)vi.tiles_x;
+        const uint32_t row = (uint32_t)vi.bin_off + ty * (uint32_t)vi.bins_x;
         for (uint32_t tx = tx0; tx <= tx1; tx++, o++) {
             pk[o] = row + tx;
             pv[o] = r;
@@ -362,7 +364,7 @@ __global__ void rect_tiles_kernel(ViewTable vt, const uint2* rect, uint2* rect_o
     const uint32_t x1 = min(rc.x >> 16, (uint32_t)vi.W - 1u), y1 = min(rc.y >> 16, (uint32_t)vi.H - 1u);
     const bool empty = x0 > x1 || y0 > y1;
     rect_out[i] = empty ? make_uint2(1u, 1u) : make_uint2(x0 | (x1 << 16), y0 | (y1 << 16));
-    nt[i] = empty ? 0u : (x1 / vt.tw - x0 / vt.tw + 1) * (y1 / vt.th - y0 / vt.th + 1);
+    nt[i] = empty ? 0u : (x1 / vt.bw - x0 / vt.bw + 1) * (y1 / vt.bh - y0 / vt.bh + 1);
 }
 
 inline int ceil_log2(int64_t x) {
@@ -446,12 +448,12 @@ hipError_t launch_binning_emit(const ViewTable& vt, const Layout& L, char* base,
                                                  pv0, scal);
     }
     bool second;
-    e = radix_sort(pk0, pv0, pk1, pv1, scal + kNPairs, pair_bound, ceil_log2(L.n_tiles),
+    e = radix_sort(pk0, pv0, pk1, pv1, scal + kNPairs, pair_bound, ceil_log2(L.n_bins),
                    GS_AT(uint32_t, L.off_hist), bsum, s, &second);
     if (e != hipSuccess) return e;
     const uint32_t* keys = second ? pk1 : pk0;
     uint2* ranges = GS_AT(uint2, L.off_ranges);
-    e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * L.n_tiles, s);
+    e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * L.n_bins, s);
     if (e != hipSuccess) return e;
     if (pair_bound > 0) {
         const int64_t g = (pair_bound + 255) / 256;

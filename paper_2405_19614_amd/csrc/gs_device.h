@@ -243,9 +243,12 @@ struct Frag {
 };
 
 __device__ __forceinline__ bool frag_eval(float px, float py, float2 xy, float4 co, Frag& f) {
+    // no contraction here: forward and backward must take the same skip and
+    // clamp decisions bit for bit, whatever code surrounds the inlined copy
+#pragma clang fp contract(off)
     f.dx = px - xy.x;
     f.dy = py - xy.y;
-    const float sig = 0.5f * (co.x * f.dx * f.dx + co.z * f.dy * f.dy) + co.y * f.dx * f.dy;
+    const float sig = 0.5f * (co.x * (f.dx * f.dx) + co.z * (f.dy * f.dy)) + co.y * (f.dx * f.dy);
     if (sig < 0.f) return false;
     f.G = __expf(-sig);
     f.raw = co.w * f.G;

@@ -23,16 +23,24 @@ constexpr float kJClamp = 1.3f;
 struct ViewInfo {
     int W, H;
     int tiles_x, tiles_y;
-    int tile_off;   // global id of this view's first tile
+    int tile_off;   // global id of this view's first compositing tile
+    int bins_x, bins_y;
+    int bin_off;    // global id of this view's first bin
     int pix_off;    // first pixel of this view in the concatenated images
     float fx, fy, cx, cy;
     float lsc;      // dL/dC scale: w_color / (V * 3 * H * W)
     float lsd;      // dL/dD scale: w_depth / (V * H * W)
 };
 
+// Binning works on bins of bw x bh pixels; compositing on tiles of tw x th
+// pixels (bw, bh multiples of tw, th), each tile reading its bin's list and
+// keeping the entries whose support rect meets the tile.
 struct ViewTable {
     int V;
     int tw, th;
+    int bw, bh;
+    int ppt;        // pixels per thread in the compositing kernels (1, 2 or 4)
+    int n_bins;
     int n_tiles;
     int n_pix;
     int n;          // Gaussians
@@ -64,7 +72,7 @@ struct Records {
     float4* conic;    // (A, B, C, opacity)
     float4* col;      // (r, g, b, depth)
     uint2* rect;      // inclusive pixel rect (x0 | x1 << 16, y0 | y1 << 16)
-    uint32_t* nt;     // tiles touched (0 = not visible)
+    uint32_t* nt;     // bins touched (0 = not visible)
 };
 
 constexpr int kG2Stride = 12;   // floats per record of the 2D-gradient buffer (10 used)
@@ -73,7 +81,7 @@ constexpr int kG2Stride = 12;   // floats per record of the 2D-gradient buffer (
 struct Layout {
     int64_t R;            // V * n records
     int64_t cap;          // pair capacity
-    int64_t n_tiles, n_pix;
+    int64_t n_bins, n_tiles, n_pix;
     int64_t sort_blocks;  // radix-sort blocks for max(R, cap)
     size_t off_xy, off_conic, off_col, off_rect, off_nt;
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
@@ -81,14 +89,14 @@ struct Layout {
     size_t off_pk0, off_pv0, off_pk1, off_pv1;    // pair sort (cap)
     size_t off_hist;                              // 256 * sort_blocks
     size_t off_scan;                              // scan block sums
-    size_t off_ranges;                            // n_tiles uint2
+    size_t off_ranges;                            // n_bins uint2
     size_t off_tfin, off_last;                    // n_pix
     size_t off_g2;                                // R * kG2Stride floats
     size_t off_posepart;                          // V * pose_blocks * 6 doubles
     size_t off_scalars;                           // counters and flags
     // mapping workspace only
     size_t off_dC, off_dD;                        // upstream gradients
-    size_t off_tilepart;                          // n_tiles double2
+    size_t off_tilepart;                          // tile partials (sized for the smallest tile)
     size_t off_rpacc;                             // V * 8 doubles
     size_t bytes;
     int64_t pose_blocks;
@@ -97,7 +105,8 @@ struct Layout {
 // scalars block (u32 unless noted), at off_scalars
 enum ScalarSlot { kNVis = 0, kNPairs = 1, kFlags = 2, kPairsLo = 4, kPairsHi = 5, kNumScalars = 16 };
 
-Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace);
+// tiles_bound: per-tile buffers (workspace) are sized for max(tiles_bound, n_tiles) tiles
+Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, int64_t tiles_bound = 0);
 
 // ---------------------------------------------------------------------------
 // launchers (each enqueues kernels on `s` and returns hipGetLastError())

@@ -1,7 +1,7 @@
 // Projection of every (view, Gaussian) pair and its reverse mode.
 //
 // Forward (Sec. 3.4 "Projection"): one thread per (view, Gaussian), writes the
-// 2D record (mean, conic + opacity, colour + depth, pixel rect, tile count).
+// 2D record (mean, conic + opacity, colour + depth, pixel rect, bin count).
 // Backward: one thread per Gaussian looping over the views, so each
 // Gaussian's parameter gradient is summed in registers (no atomics) and the
 // per-view pose 6-vector is reduced per block in FP64 (deterministic).
@@ -29,8 +29,8 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
         rec.nt[r] = 0u;
         return;
     }
-    const uint32_t tx0 = (uint32_t)pr.x0 / vt.tw, tx1 = (uint32_t)pr.x1 / vt.tw;
-    const uint32_t ty0 = (uint32_t)pr.y0 / vt.th, ty1 = (uint32_t)pr.y1 / vt.th;
+    const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
+    const uint32_t ty0 = (uint32_t)pr.y0 / vt.bh, ty1 = (uint32_t)pr.y1 / vt.bh;
     rec.xy[r] = make_float2(pr.u, pr.v);
     rec.conic[r] = make_float4(pr.A, pr.B, pr.C, pr.o);
     rec.col[r] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);

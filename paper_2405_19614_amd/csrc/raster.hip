@@ -1,15 +1,19 @@
 // Tile compositing, forward and backward (Sec. 3.4 "Differentiable
 // Rasterization": colour and depth compositing; Sec. 3.3 border mask).
 //
-// One workgroup per (view, tile) of every view in one launch; the tile's
+// One workgroup per (view, tile) of every view in one launch.  Each thread
+// owns PPT vertically adjacent pixels of the tile, so one LDS read of a list
+// entry and one wavefront reduction serve PPT pixels.  The tile's
 // depth-ordered list is staged through LDS in batches of one record per
-// thread.  Forward: front to back per pixel with a workgroup-wide early exit
-// once every pixel has stopped; an optional fused epilogue writes the L1
-// loss's upstream gradients and per-tile loss partials.  Backward: the same
-// lists walked back to front from each pixel's stop index, transmittance
-// recovered by division, per-Gaussian gradients reduced across the wavefront
-// (64 lanes) and then across the workgroup in LDS before one global atomic
-// per (tile, Gaussian, value).
+// thread.
+// Forward: front to back per pixel, workgroup-wide early exit once every
+// pixel has stopped; an optional fused epilogue writes the L1 loss's upstream
+// gradients and per-tile loss partials.
+// Backward: the list walked back to front from each pixel's stop index,
+// transmittance recovered by division, per-Gaussian gradients summed over the
+// thread's pixels, then across the 64-lane wavefront with DPP row shifts and
+// row broadcasts, then across the workgroup with LDS atomics, then one global
+// atomic per (tile, Gaussian, value).
 #include "gs_device.h"
 
 namespace gs {
@@ -38,13 +42,65 @@ __device__ __forceinline__ double2 block_sum2(float a, float b) {
     return r;
 }
 
-template <int TW, int TH, bool LOSS, bool COUNT>
-__global__ __launch_bounds__(TW* TH) void composite_fwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
-                                                               const uint32_t* __restrict__ vals, Records rec,
-                                                               float* color, float* depth, float* alpha,
-                                                               float* tfin, uint32_t* last, LossArgs la,
-                                                               unsigned long long* counts) {
-    constexpr int NT = TW * TH;
+// DPP move with zero fill for lanes whose source is outside the row / mask
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp0(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Sum of x over the 64-lane wavefront, valid in lane 63: inclusive row sums
+// by row_shr 1, 2, 4, 8, then row_bcast:15 and row_bcast:31 carry the row
+// totals up to the last row.
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+    x += dpp0<0x111, 0xf>(x);   // row_shr:1
+    x += dpp0<0x112, 0xf>(x);   // row_shr:2
+    x += dpp0<0x114, 0xf>(x);   // row_shr:4
+    x += dpp0<0x118, 0xf>(x);   // row_shr:8
+    x += dpp0<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp0<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// Block-wide stream compaction: the rank of this thread's flagged item among
+// the flagged items of the workgroup (in thread order); *total = their count.
+template <int NT>
+__device__ __forceinline__ int block_compact(bool flag, int* total) {
+    __shared__ int wcnt[NT / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t m = __ballot(flag);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[w] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; i++) {
+        const int c = wcnt[i];
+        off += (i < w) ? c : 0;
+        tot += c;
+    }
+    *total = tot;
+    __syncthreads();   // wcnt[] may be reused by the next call
+    return off + before;
+}
+
+// rect (x0 | x1 << 16, y0 | y1 << 16) meets the pixel box [bx0, bx1] x [by0, by1]
+__device__ __forceinline__ bool rect_meets(uint2 rc, int bx0, int bx1, int by0, int by1) {
+    return (int)(rc.x & 0xffffu) <= bx1 && (int)(rc.x >> 16) >= bx0 && (int)(rc.y & 0xffffu) <= by1 &&
+           (int)(rc.y >> 16) >= by0;
+}
+
+// bin of compositing tile (txi, tyi) of view vi
+__device__ __forceinline__ int bin_of_tile(const ViewTable& vt, const ViewInfo& vi, int txi, int tyi, int TW, int TH) {
+    return vi.bin_off + ((tyi * TH) / vt.bh) * vi.bins_x + (txi * TW) / vt.bw;
+}
+
+template <int TW, int TH, int PPT, bool LOSS, bool COUNT>
+__global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
+                                                                     const uint32_t* __restrict__ vals, Records rec,
+                                                                     float* color, float* depth, float* alpha,
+                                                                     float* tfin, uint32_t* last, LossArgs la,
+                                                                     unsigned long long* counts) {
+    constexpr int NT = TW * TH / PPT;
     __shared__ float2 s_xy[NT];
     __shared__ float4 s_co[NT];
     __shared__ float4 s_cz[NT];
@@ -55,71 +111,114 @@ __global__ __launch_bounds__(TW* TH) void composite_fwd_kernel(ViewTable vt, con
     const int lt = t - vi.tile_off;
     const int tyi = lt / vi.tiles_x, txi = lt - tyi * vi.tiles_x;
     const int px = txi * TW + (int)(threadIdx.x % TW);
-    const int py = tyi * TH + (int)(threadIdx.x / TW);
-    const bool inside = px < vi.W && py < vi.H;
-    const float fpx = (float)px, fpy = (float)py;
-    const uint2 rg = ranges[t];
+    const int py0 = tyi * TH + (int)(threadIdx.x / TW) * PPT;
+    const float fpx = (float)px;
+    const uint2 rg = ranges[bin_of_tile(vt, vi, txi, tyi, TW, TH)];
+    const int bx0 = txi * TW, bx1 = bx0 + TW - 1, by0 = tyi * TH, by1 = by0 + TH - 1;
+    __shared__ uint32_t s_j[NT];
 
-    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
-    uint32_t lastp = 0u;
-    uint32_t n_visit = 0u, n_blend = 0u;
-    bool done = !inside;
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
+    uint32_t lastp[PPT];
+    bool done[PPT];
+    uint32_t n_visit = 0u, n_blend = 0u, n_entries = 0u;
+    bool all_done = true;
+#pragma unroll
+    for (int q = 0; q < PPT; q++) {
+        T[q] = 1.f; C0[q] = C1[q] = C2[q] = D[q] = 0.f;
+        lastp[q] = 0u;
+        done[q] = !(px < vi.W && py0 + q < vi.H);
+        all_done = all_done && done[q];
+    }
     for (uint32_t b = rg.x; b < rg.y; b += NT) {
-        if (__syncthreads_count(done) == NT) break;
+        if (__syncthreads_count(all_done) == NT) break;
+        // stage the bin-list entries whose rect meets this tile, in list order
         const uint32_t j = b + threadIdx.x;
+        uint32_t r = 0u;
+        uint2 rc = make_uint2(1u, 1u);
+        bool pass = false;
         if (j < rg.y) {
-            const uint32_t r = vals[j];
-            s_xy[threadIdx.x] = rec.xy[r];
-            s_co[threadIdx.x] = rec.conic[r];
-            s_cz[threadIdx.x] = rec.col[r];
-            s_rc[threadIdx.x] = rec.rect[r];
+            r = vals[j];
+            rc = rec.rect[r];
+            pass = rect_meets(rc, bx0, bx1, by0, by1);
+        }
+        int cnt;
+        const int pos = block_compact<NT>(pass, &cnt);
+        if (pass) {
+            s_xy[pos] = rec.xy[r];
+            s_co[pos] = rec.conic[r];
+            s_cz[pos] = rec.col[r];
+            s_rc[pos] = rc;
+            s_j[pos] = j;
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)NT, rg.y - b);
-        if (!done) {
-            for (int k = 0; k < cnt; k++) {
-                if (!rect_has(s_rc[k], px, py)) continue;
+        if (COUNT) n_entries += (uint32_t)cnt;
+        for (int k = 0; k < cnt && !all_done; k++) {
+            const uint2 rc = s_rc[k];
+            if (px < (int)(rc.x & 0xffffu) || px > (int)(rc.x >> 16)) continue;
+            const int y0 = (int)(rc.y & 0xffffu), y1 = (int)(rc.y >> 16);
+            const float2 xy = s_xy[k];
+            const float4 co = s_co[k];
+            bool any_blend = false;
+            float w[PPT];
+#pragma unroll
+            for (int q = 0; q < PPT; q++) {
+                w[q] = 0.f;
+                const int py = py0 + q;
+                if (done[q] || py < y0 || py > y1) continue;
                 if (COUNT) n_visit++;
                 Frag f;
-                if (!frag_eval(fpx, fpy, s_xy[k], s_co[k], f)) continue;
-                const float Tn = T * (1.f - f.alpha);
-                if (Tn < kTMin) { done = true; break; }
+                if (!frag_eval(fpx, (float)py, xy, co, f)) continue;
+                const float Tn = T[q] * (1.f - f.alpha);
+                if (Tn < kTMin) { done[q] = true; continue; }
                 if (COUNT) n_blend++;
-                const float w = f.alpha * T;
-                const float4 cz = s_cz[k];
-                C0 += cz.x * w;
-                C1 += cz.y * w;
-                C2 += cz.z * w;
-                D += cz.w * w;
-                T = Tn;
-                lastp = b + (uint32_t)k + 1u;
+                w[q] = f.alpha * T[q];
+                T[q] = Tn;
+                lastp[q] = s_j[k] + 1u;
+                any_blend = true;
             }
+            if (any_blend) {
+                const float4 cz = s_cz[k];
+#pragma unroll
+                for (int q = 0; q < PPT; q++) {
+                    C0[q] += cz.x * w[q];
+                    C1[q] += cz.y * w[q];
+                    C2[q] += cz.z * w[q];
+                    D[q] += cz.w * w[q];
+                }
+            }
+            bool ad = true;
+#pragma unroll
+            for (int q = 0; q < PPT; q++) ad = ad && done[q];
+            all_done = ad;
         }
     }
     const int64_t hw = (int64_t)vi.W * vi.H;
-    const int64_t pl = (int64_t)py * vi.W + px;
-    const int64_t pi = (int64_t)vi.pix_off + pl;
-    const int64_t ci = 3 * (int64_t)vi.pix_off + pl;
     float lc = 0.f, ld = 0.f;
-    if (inside) {
-        color[ci] = C0;
-        color[ci + hw] = C1;
-        color[ci + 2 * hw] = C2;
-        depth[pi] = D;
-        alpha[pi] = 1.f - T;
-        tfin[pi] = T;
-        last[pi] = lastp;
+#pragma unroll
+    for (int q = 0; q < PPT; q++) {
+        const int py = py0 + q;
+        if (!(px < vi.W && py < vi.H)) continue;
+        const int64_t pl = (int64_t)py * vi.W + px;
+        const int64_t pi = (int64_t)vi.pix_off + pl;
+        const int64_t ci = 3 * (int64_t)vi.pix_off + pl;
+        color[ci] = C0[q];
+        color[ci + hw] = C1[q];
+        color[ci + 2 * hw] = C2[q];
+        depth[pi] = D[q];
+        alpha[pi] = 1.f - T[q];
+        tfin[pi] = T[q];
+        last[pi] = lastp[q];
         if (LOSS) {
             const float t0 = la.tc[ci], t1 = la.tc[ci + hw], t2 = la.tc[ci + 2 * hw], td = la.td[pi];
             float m = la.mask ? la.mask[pi] : 1.f;
-            if (la.use_gate && !(td > 0.f && D > 0.f && (1.f - T) > la.gamma)) m = 0.f;
-            const float e0 = C0 - t0, e1 = C1 - t1, e2 = C2 - t2, ed = D - td;
+            if (la.use_gate && !(td > 0.f && D[q] > 0.f && (1.f - T[q]) > la.gamma)) m = 0.f;
+            const float e0 = C0[q] - t0, e1 = C1[q] - t1, e2 = C2[q] - t2, ed = D[q] - td;
             la.dC[ci] = vi.lsc * m * sgnf(e0);
             la.dC[ci + hw] = vi.lsc * m * sgnf(e1);
             la.dC[ci + 2 * hw] = vi.lsc * m * sgnf(e2);
             la.dD[pi] = vi.lsd * m * sgnf(ed);
-            lc = m * (fabsf(e0) + fabsf(e1) + fabsf(e2));
-            ld = m * fabsf(ed);
+            lc += m * (fabsf(e0) + fabsf(e1) + fabsf(e2));
+            ld += m * fabsf(ed);
         }
     }
     if (LOSS) {
@@ -131,25 +230,21 @@ __global__ __launch_bounds__(TW* TH) void composite_fwd_kernel(ViewTable vt, con
         if (threadIdx.x == 0) {
             atomicAdd(counts, (unsigned long long)s.x);
             atomicAdd(counts + 1, (unsigned long long)s.y);
+            atomicAdd(counts + 2, (unsigned long long)n_entries);   // entries this tile composited
+            atomicAdd(counts + 3, (unsigned long long)(rg.y - rg.x));  // its bin's list length
         }
     }
 }
 
-__device__ __forceinline__ float wsum(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
-                                                               const uint32_t* __restrict__ vals, Records rec,
-                                                               const float* __restrict__ tfin,
-                                                               const uint32_t* __restrict__ last,
-                                                               const float* __restrict__ dC,
-                                                               const float* __restrict__ dD,
-                                                               const float* __restrict__ dA, float* g2) {
-    constexpr int NT = TW * TH;
+template <int TW, int TH, int PPT>
+__global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
+                                                                     const uint32_t* __restrict__ vals, Records rec,
+                                                                     const float* __restrict__ tfin,
+                                                                     const uint32_t* __restrict__ last,
+                                                                     const float* __restrict__ dC,
+                                                                     const float* __restrict__ dD,
+                                                                     const float* __restrict__ dA, float* g2) {
+    constexpr int NT = TW * TH / PPT;
     constexpr int NG = 10;
     __shared__ float2 s_xy[NT];
     __shared__ float4 s_co[NT];
@@ -164,87 +259,119 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(ViewTable vt, con
     const int lt = t - vi.tile_off;
     const int tyi = lt / vi.tiles_x, txi = lt - tyi * vi.tiles_x;
     const int px = txi * TW + (int)(threadIdx.x % TW);
-    const int py = tyi * TH + (int)(threadIdx.x / TW);
-    const bool inside = px < vi.W && py < vi.H;
-    const float fpx = (float)px, fpy = (float)py;
-    const uint2 rg = ranges[t];
+    const int py0 = tyi * TH + (int)(threadIdx.x / TW) * PPT;
+    const float fpx = (float)px;
+    const uint2 rg = ranges[bin_of_tile(vt, vi, txi, tyi, TW, TH)];
+    const int bx0 = txi * TW, bx1 = bx0 + TW - 1, by0 = tyi * TH, by1 = by0 + TH - 1;
+    __shared__ uint32_t s_j[NT];
     const int lane = threadIdx.x & 63;
-
     const int64_t hw = (int64_t)vi.W * vi.H;
-    const int64_t pl = (int64_t)py * vi.W + px;
-    const int64_t pi = (int64_t)vi.pix_off + pl;
-    const int64_t ci = 3 * (int64_t)vi.pix_off + pl;
-    float T = 1.f, Tf = 1.f, g0 = 0.f, g1 = 0.f, g2c = 0.f, gd = 0.f, ga = 0.f;
-    uint32_t lastp = 0u;
-    if (inside) {
-        Tf = tfin[pi];
-        T = Tf;
-        lastp = last[pi];
-        if (dC) { g0 = dC[ci]; g1 = dC[ci + hw]; g2c = dC[ci + 2 * hw]; }
-        if (dD) gd = dD[pi];
-        if (dA) ga = dA[pi];
+
+    float T[PPT], Tf[PPT], g0[PPT], g1[PPT], g2c[PPT], gd[PPT], ga[PPT];
+    float S0[PPT], S1[PPT], S2[PPT], SD[PPT];
+    uint32_t lastp[PPT];
+    uint32_t mylast = 0u;
+#pragma unroll
+    for (int q = 0; q < PPT; q++) {
+        T[q] = Tf[q] = 1.f;
+        g0[q] = g1[q] = g2c[q] = gd[q] = ga[q] = 0.f;
+        S0[q] = S1[q] = S2[q] = SD[q] = 0.f;
+        lastp[q] = 0u;
+        const int py = py0 + q;
+        if (px < vi.W && py < vi.H) {
+            const int64_t pl = (int64_t)py * vi.W + px;
+            const int64_t pi = (int64_t)vi.pix_off + pl;
+            const int64_t ci = 3 * (int64_t)vi.pix_off + pl;
+            Tf[q] = tfin[pi];
+            T[q] = Tf[q];
+            lastp[q] = last[pi];
+            if (dC) { g0[q] = dC[ci]; g1[q] = dC[ci + hw]; g2c[q] = dC[ci + 2 * hw]; }
+            if (dD) gd[q] = dD[pi];
+            if (dA) ga[q] = dA[pi];
+            mylast = max(mylast, lastp[q]);
+        }
     }
     if (threadIdx.x == 0) s_hi = rg.x;
     for (int i = threadIdx.x; i < NT * NG; i += NT) (&s_g[0][0])[i] = 0.f;
     __syncthreads();
-    if (lastp > rg.x) atomicMax(&s_hi, lastp);
+    if (mylast > rg.x) atomicMax(&s_hi, mylast);
     __syncthreads();
     const uint32_t hi0 = s_hi;
-    float S0 = 0.f, S1 = 0.f, S2 = 0.f, SD = 0.f;
 
     for (uint32_t hi = hi0; hi > rg.x;) {
         const uint32_t lo = (hi - rg.x > (uint32_t)NT) ? hi - NT : rg.x;
-        const int cnt = (int)(hi - lo);
-        // slot k holds list entry hi - 1 - k (back to front)
-        if ((int)threadIdx.x < cnt) {
-            const uint32_t r = vals[hi - 1u - threadIdx.x];
-            s_id[threadIdx.x] = r;
-            s_xy[threadIdx.x] = rec.xy[r];
-            s_co[threadIdx.x] = rec.conic[r];
-            s_cz[threadIdx.x] = rec.col[r];
-            s_rc[threadIdx.x] = rec.rect[r];
+        const int span = (int)(hi - lo);
+        // stage, back to front, the entries whose rect meets this tile
+        const uint32_t jj = hi - 1u - threadIdx.x;
+        uint32_t r = 0u;
+        uint2 rc0 = make_uint2(1u, 1u);
+        bool pass = false;
+        if ((int)threadIdx.x < span) {
+            r = vals[jj];
+            rc0 = rec.rect[r];
+            pass = rect_meets(rc0, bx0, bx1, by0, by1);
+        }
+        int cnt;
+        const int pos = block_compact<NT>(pass, &cnt);
+        if (pass) {
+            s_id[pos] = r;
+            s_j[pos] = jj;
+            s_xy[pos] = rec.xy[r];
+            s_co[pos] = rec.conic[r];
+            s_cz[pos] = rec.col[r];
+            s_rc[pos] = rc0;
         }
         __syncthreads();
         for (int k = 0; k < cnt; k++) {
-            const uint32_t j = hi - 1u - (uint32_t)k;
+            const uint32_t j = s_j[k];
             float gv[NG];
-            bool any = false;
 #pragma unroll
-            for (int q = 0; q < NG; q++) gv[q] = 0.f;
-            Frag f;
-            if (j < lastp && rect_has(s_rc[k], px, py) && frag_eval(fpx, fpy, s_xy[k], s_co[k], f)) {
+            for (int e = 0; e < NG; e++) gv[e] = 0.f;
+            bool any = false;
+            const uint2 rc = s_rc[k];
+            if (j < mylast && px >= (int)(rc.x & 0xffffu) && px <= (int)(rc.x >> 16)) {
+                const int y0 = (int)(rc.y & 0xffffu), y1 = (int)(rc.y >> 16);
+                const float2 xy = s_xy[k];
                 const float4 co = s_co[k];
                 const float4 cz = s_cz[k];
-                const float inv = 1.f / (1.f - f.alpha);
-                const float Ti = T * inv;
-                const float w = f.alpha * Ti;
-                gv[6] = w * g0;
-                gv[7] = w * g1;
-                gv[8] = w * g2c;
-                gv[9] = w * gd;
-                const float dal = inv * (g0 * (cz.x * T - S0) + g1 * (cz.y * T - S1) + g2c * (cz.z * T - S2) +
-                                         gd * (cz.w * T - SD) + ga * Tf);
-                S0 += cz.x * w;
-                S1 += cz.y * w;
-                S2 += cz.z * w;
-                SD += cz.w * w;
-                T = Ti;
-                if (f.raw <= kAlphaMax) {
-                    gv[5] = dal * f.G;
-                    const float ds = -dal * f.raw;
-                    gv[2] = 0.5f * ds * f.dx * f.dx;
-                    gv[3] = ds * f.dx * f.dy;
-                    gv[4] = 0.5f * ds * f.dy * f.dy;
-                    gv[0] = -ds * (co.x * f.dx + co.y * f.dy);
-                    gv[1] = -ds * (co.z * f.dy + co.y * f.dx);
+#pragma unroll
+                for (int q = 0; q < PPT; q++) {
+                    const int py = py0 + q;
+                    if (j >= lastp[q] || py < y0 || py > y1) continue;
+                    Frag f;
+                    if (!frag_eval(fpx, (float)py, xy, co, f)) continue;
+                    const float inv = __builtin_amdgcn_rcpf(1.f - f.alpha);
+                    const float Ti = T[q] * inv;
+                    const float w = f.alpha * Ti;
+                    gv[6] += w * g0[q];
+                    gv[7] += w * g1[q];
+                    gv[8] += w * g2c[q];
+                    gv[9] += w * gd[q];
+                    const float dal = inv * (g0[q] * (cz.x * T[q] - S0[q]) + g1[q] * (cz.y * T[q] - S1[q]) +
+                                             g2c[q] * (cz.z * T[q] - S2[q]) + gd[q] * (cz.w * T[q] - SD[q]) +
+                                             ga[q] * Tf[q]);
+                    S0[q] += cz.x * w;
+                    S1[q] += cz.y * w;
+                    S2[q] += cz.z * w;
+                    SD[q] += cz.w * w;
+                    T[q] = Ti;
+                    if (f.raw <= kAlphaMax) {
+                        gv[5] += dal * f.G;
+                        const float ds = -dal * f.raw;
+                        gv[2] += 0.5f * ds * f.dx * f.dx;
+                        gv[3] += ds * f.dx * f.dy;
+                        gv[4] += 0.5f * ds * f.dy * f.dy;
+                        gv[0] -= ds * (co.x * f.dx + co.y * f.dy);
+                        gv[1] -= ds * (co.z * f.dy + co.y * f.dx);
+                    }
+                    any = true;
                 }
-                any = true;
             }
             if (__ballot(any) != 0ull) {
 #pragma unroll
-                for (int q = 0; q < NG; q++) {
-                    const float s = wsum(gv[q]);
-                    if (lane == 0 && s != 0.f) atomicAdd(&s_g[k][q], s);
+                for (int e = 0; e < NG; e++) {
+                    const float s = wave_sum_lane63(gv[e]);
+                    if (lane == 63 && s != 0.f) atomicAdd(&s_g[k][e], s);
                 }
             }
         }
@@ -252,10 +379,10 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(ViewTable vt, con
         if ((int)threadIdx.x < cnt) {
             float* dst = g2 + (int64_t)s_id[threadIdx.x] * kG2Stride;
 #pragma unroll
-            for (int q = 0; q < NG; q++) {
-                const float s = s_g[threadIdx.x][q];
-                if (s != 0.f) atomicAdd(dst + q, s);
-                s_g[threadIdx.x][q] = 0.f;
+            for (int e = 0; e < NG; e++) {
+                const float s = s_g[threadIdx.x][e];
+                if (s != 0.f) atomicAdd(dst + e, s);
+                s_g[threadIdx.x][e] = 0.f;
             }
         }
         __syncthreads();
@@ -263,44 +390,55 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(ViewTable vt, con
     }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int PPT>
 hipError_t fwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec, float* color,
                  float* depth, float* alpha, float* tfin, uint32_t* last, const LossArgs* loss,
                  unsigned long long* counts, hipStream_t s) {
     if (vt.n_tiles == 0) return hipSuccess;
+    constexpr int NT = TW * TH / PPT;
     const LossArgs la = loss ? *loss : LossArgs{};
     if (loss && counts)
-        composite_fwd_kernel<TW, TH, true, true><<<vt.n_tiles, TW * TH, 0, s>>>(vt, ranges, vals, rec, color, depth,
+        composite_fwd_kernel<TW, TH, PPT, true, true><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, color, depth,
                                                                                  alpha, tfin, last, la, counts);
     else if (loss)
-        composite_fwd_kernel<TW, TH, true, false><<<vt.n_tiles, TW * TH, 0, s>>>(vt, ranges, vals, rec, color,
+        composite_fwd_kernel<TW, TH, PPT, true, false><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, color,
                                                                                   depth, alpha, tfin, last, la, counts);
     else if (counts)
-        composite_fwd_kernel<TW, TH, false, true><<<vt.n_tiles, TW * TH, 0, s>>>(vt, ranges, vals, rec, color,
+        composite_fwd_kernel<TW, TH, PPT, false, true><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, color,
                                                                                   depth, alpha, tfin, last, la, counts);
     else
-        composite_fwd_kernel<TW, TH, false, false><<<vt.n_tiles, TW * TH, 0, s>>>(vt, ranges, vals, rec, color,
+        composite_fwd_kernel<TW, TH, PPT, false, false><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, color,
                                                                                    depth, alpha, tfin, last, la, counts);
     return hipGetLastError();
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int PPT>
 hipError_t bwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                  const float* tfin, const uint32_t* last, const float* dC, const float* dD, const float* dA,
                  float* g2, hipStream_t s) {
     if (vt.n_tiles == 0) return hipSuccess;
-    composite_bwd_kernel<TW, TH><<<vt.n_tiles, TW * TH, 0, s>>>(vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2);
+    constexpr int NT = TW * TH / PPT;
+    composite_bwd_kernel<TW, TH, PPT><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2);
     return hipGetLastError();
 }
 
 }  // namespace
 
-#define GS_TILE_DISPATCH(FN, ...)                                        \
-    if (vt.tw == 16 && vt.th == 16) return FN<16, 16>(__VA_ARGS__);      \
-    if (vt.tw == 16 && vt.th == 8) return FN<16, 8>(__VA_ARGS__);        \
-    if (vt.tw == 8 && vt.th == 8) return FN<8, 8>(__VA_ARGS__);          \
-    if (vt.tw == 32 && vt.th == 8) return FN<32, 8>(__VA_ARGS__);        \
-    if (vt.tw == 32 && vt.th == 16) return FN<32, 16>(__VA_ARGS__);      \
+// (tile width, tile height, pixels per thread) combinations with whole
+// wavefronts per workgroup
+#define GS_TILE_DISPATCH(FN, ...)                                                   \
+    if (vt.tw == 16 && vt.th == 16 && vt.ppt == 1) return FN<16, 16, 1>(__VA_ARGS__); \
+    if (vt.tw == 16 && vt.th == 16 && vt.ppt == 2) return FN<16, 16, 2>(__VA_ARGS__); \
+    if (vt.tw == 16 && vt.th == 16 && vt.ppt == 4) return FN<16, 16, 4>(__VA_ARGS__); \
+    if (vt.tw == 16 && vt.th == 8 && vt.ppt == 1) return FN<16, 8, 1>(__VA_ARGS__);   \
+    if (vt.tw == 16 && vt.th == 8 && vt.ppt == 2) return FN<16, 8, 2>(__VA_ARGS__);   \
+    if (vt.tw == 8 && vt.th == 8 && vt.ppt == 1) return FN<8, 8, 1>(__VA_ARGS__);     \
+    if (vt.tw == 32 && vt.th == 8 && vt.ppt == 1) return FN<32, 8, 1>(__VA_ARGS__);   \
+    if (vt.tw == 32 && vt.th == 8 && vt.ppt == 2) return FN<32, 8, 2>(__VA_ARGS__);   \
+    if (vt.tw == 32 && vt.th == 8 && vt.ppt == 4) return FN<32, 8, 4>(__VA_ARGS__);   \
+    if (vt.tw == 32 && vt.th == 16 && vt.ppt == 1) return FN<32, 16, 1>(__VA_ARGS__); \
+    if (vt.tw == 32 && vt.th == 16 && vt.ppt == 2) return FN<32, 16, 2>(__VA_ARGS__); \
+    if (vt.tw == 32 && vt.th == 16 && vt.ppt == 4) return FN<32, 16, 4>(__VA_ARGS__); \
     return hipErrorInvalidValue;
 
 hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,

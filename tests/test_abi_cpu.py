@@ -48,7 +48,7 @@ def test_abi_version(lib):
 
 def test_null_context_rejected_without_device_work(lib):
     from paper_2405_19614_amd import _abi as A
-    plan = A.gs_plan(16, 16, 0, 0, 0)
+    plan = A.gs_plan(16, 16, 64, 64, 0, 0, 0)
     rc = lib.gs_render_forward(None, None, None, None, 1, None, None, None, None, 0, ctypes.byref(plan), None)
     assert rc == A.GS_EINVAL
     assert lib.gs_set_tile(None, 16, 16) == A.GS_EINVAL
@@ -62,7 +62,7 @@ def test_state_bytes_validation(lib):
     # monotone in every size
     assert lib.gs_state_bytes(cams, 2, 2000, 10000, 16, 16) > ok
     assert lib.gs_state_bytes(cams, 2, 1000, 20000, 16, 16) > ok
-    # invalid: unsupported tile, V = 0, V too large, negative n, bad camera, capacity too large
+    # invalid: bin not a multiple of 8, V = 0, V too large, negative n, bad camera, capacity too large
     assert lib.gs_state_bytes(cams, 2, 1000, 10000, 12, 12) == 0
     assert lib.gs_state_bytes(cams, 0, 1000, 10000, 16, 16) == 0
     assert lib.gs_state_bytes(cams, 65, 1000, 10000, 16, 16) == 0
@@ -77,11 +77,13 @@ def test_state_bytes_validation(lib):
     assert lib.gs_step_workspace_bytes(cams, 2, 1000, -1, 10000, 16, 16) > ok
 
 
-def test_tile_shapes_accepted(lib):
+def test_bin_shapes_accepted(lib):
     from paper_2405_19614_amd import _abi as A
     cams = (A.gs_camera * 1)(A.gs_camera(64, 48, 60, 60, 32, 24))
-    for tw, th in [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16), (0, 0)]:
-        assert lib.gs_state_bytes(cams, 1, 10, 10, tw, th) > 0
+    for bw, bh in [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16), (64, 64), (128, 64), (2048, 2048), (0, 0)]:
+        assert lib.gs_state_bytes(cams, 1, 10, 10, bw, bh) > 0
+    for bw, bh in [(4, 8), (8, 12), (4096, 8)]:
+        assert lib.gs_state_bytes(cams, 1, 10, 10, bw, bh) == 0
 
 
 def test_paper_preset_matches_table():

@@ -74,6 +74,7 @@ def test_c3_fragment_counts_match_oracle(setup):
     st = gs.MappingStep(ctx, g, sub.cams, poses, t(tgt["color"][:3 * npx]), t(tgt["depth"][:npx]),
                         gs.StepOptions(use_graph=False))
     _, frag = st.profile(counts=True)
+    assert frag[2] <= frag[3]
     out = O.render_views(og, sub.cams, sub.poses)
     amb = int(((out["ambiguous"] & O.AMB_VALUE) != 0).sum())
     print(f"  visited gpu {frag[0]} oracle {out['nfrag']} (ambiguous pixels {amb})", flush=True)

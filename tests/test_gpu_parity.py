@@ -69,17 +69,75 @@ def test_backward_matches_oracle(ctx, name):
         assert e < TOL_G, ("pose", v, e)
 
 
+LAUNCH_SHAPES = [(16, 16, 1), (16, 16, 2), (16, 16, 4), (16, 8, 1), (16, 8, 2), (8, 8, 1), (32, 8, 1),
+                 (32, 8, 2), (32, 8, 4), (32, 16, 1), (32, 16, 2), (32, 16, 4)]
+
+
 def test_forward_bit_identical_across_tile_shapes(ctx):
+    """Every (tile shape, pixels per thread) launch gives the same image bit for bit."""
     s = SCENES["c3_small"]
     g, poses = dev_scene(s)
     outs = []
-    for tile in [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16)]:
-        print(f"[tile] {tile}", flush=True)
-        c, d, a, _, _ = ctx.forward(g, s.cams, poses, tile=tile)
+    for tw, th, ppt in LAUNCH_SHAPES:
+        print(f"[tile] {tw}x{th} ppt={ppt}", flush=True)
+        ctx.set_tile(tw, th, ppt)
+        c, d, a, _, _ = ctx.forward(g, s.cams, poses, tile=(tw, th))
+        outs.append((c.cpu(), d.cpu(), a.cpu()))
+    ctx.set_tile(16, 16, 2)
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert torch.equal(x, y)
+
+
+def test_forward_bit_identical_across_bin_sizes(ctx):
+    """Binning granularity changes which list each tile reads, not the result."""
+    s = SCENES["c3_small"]
+    g, poses = dev_scene(s)
+    outs = []
+    for bw, bh in [(16, 16), (32, 32), (64, 64), (128, 64), (128, 128), (256, 256)]:
+        print(f"[bin] {bw}x{bh}", flush=True)
+        c, d, a, _, plan = ctx.forward(g, s.cams, poses, tile=(16, 16), bin=(bw, bh))
+        assert (plan.bin_w, plan.bin_h) == (bw, bh)
         outs.append((c.cpu(), d.cpu(), a.cpu()))
     for o in outs[1:]:
         for x, y in zip(o, outs[0]):
             assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("bin_size", [(16, 16), (128, 64)])
+def test_backward_bin_sizes(ctx, bin_size):
+    s = SCENES["c1_ragged"]
+    g, poses = dev_scene(s)
+    color, depth, alpha, state, plan = ctx.forward(g, s.cams, poses, tile=(16, 16), bin=bin_size)
+    og, ref = oracle_views(s)
+    dC, dD, dA = cotangents(s, ref, seed=13)
+    t = lambda a: torch.tensor(a, device="cuda")
+    grads, dpose = ctx.backward(g, s.cams, poses, state, plan, t(dC), t(dD), t(dA))
+    rg = O.backward_views(og, s.cams, s.poses, dC, dD, dA)
+    for nm in GRAD_NAMES:
+        assert rel(getattr(grads, nm).cpu().numpy(), rg[nm]) < TOL_G, nm
+
+
+@pytest.mark.parametrize("shape", LAUNCH_SHAPES)
+def test_backward_every_launch_shape(ctx, shape):
+    tw, th, ppt = shape
+    s = SCENES["c3_small"]
+    print(f"[backward-shape] {tw}x{th} ppt={ppt}", flush=True)
+    g, poses = dev_scene(s)
+    ctx.set_tile(tw, th, ppt)
+    color, depth, alpha, state, plan = ctx.forward(g, s.cams, poses, tile=(tw, th))
+    og, ref = oracle_views(s)
+    dC, dD, dA = cotangents(s, ref, seed=11)
+    t = lambda a: torch.tensor(a, device="cuda")
+    grads, dpose = ctx.backward(g, s.cams, poses, state, plan, t(dC), t(dD), t(dA))
+    torch.cuda.synchronize()
+    ctx.set_tile(16, 16, 2)
+    rg = O.backward_views(og, s.cams, s.poses, dC, dD, dA)
+    for nm in GRAD_NAMES:
+        e = rel(getattr(grads, nm).cpu().numpy(), rg[nm])
+        assert e < TOL_G, (nm, e)
+    for v in range(s.V):
+        assert rel(dpose[v].cpu().numpy(), rg["pose"][v]) < TOL_G
 
 
 def test_batched_equals_per_view(ctx):
