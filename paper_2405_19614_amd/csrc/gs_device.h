@@ -236,24 +236,33 @@ __device__ __forceinline__ void project_one(const Params& P, int g, const ViewIn
     o.valid = true;
 }
 
-// Fragment weight (identical instruction sequence in forward and backward so
-// the skip / clamp / stop decisions agree bit for bit).
-struct Frag {
-    float dx, dy, G, raw, alpha;
+// Records keep the conic in base-2 units with the opacity folded in:
+// co = (A', B', C', log2 o) with A' = c A, B' = 2 c B, C' = c C and
+// c = log2(e) / 2, so o exp(-sigma) = exp2(log2 o - (A' dx^2 + B' dx dy +
+// C' dy^2)).  For a thread's fixed pixel column the exponent is a quadratic
+// in dy, t(dy) = (C' dy + a1) dy + a0, evaluated with two FMAs per pixel.
+constexpr float kHalfLog2e = 0.72134752044448170368f;   // log2(e) / 2
+
+struct FragCol {
+    float dx, a0, a1;
 };
 
-__device__ __forceinline__ bool frag_eval(float px, float py, float2 xy, float4 co, Frag& f) {
-    // no contraction here: forward and backward must take the same skip and
-    // clamp decisions bit for bit, whatever code surrounds the inlined copy
+// Per-column part of the exponent.  No contraction, and the per-pixel part
+// uses explicit FMAs, so forward and backward take the same skip and clamp
+// decisions bit for bit whatever code surrounds the inlined copies.
+__device__ __forceinline__ FragCol frag_col(float px, float2 xy, float4 co) {
 #pragma clang fp contract(off)
+    FragCol f;
     f.dx = px - xy.x;
-    f.dy = py - xy.y;
-    const float sig = 0.5f * (co.x * (f.dx * f.dx) + co.z * (f.dy * f.dy)) + co.y * (f.dx * f.dy);
-    if (sig < 0.f) return false;
-    f.G = __expf(-sig);
-    f.raw = co.w * f.G;
-    f.alpha = fminf(kAlphaMax, f.raw);
-    return f.alpha >= kAlphaMin;
+    f.a0 = co.x * f.dx * f.dx - co.w;
+    f.a1 = co.y * f.dx;
+    return f;
+}
+
+// o exp(-sigma) at pixel row py (dy = py - v)
+__device__ __forceinline__ float frag_raw(const FragCol& f, float4 co, float dy) {
+    const float t = fmaf(fmaf(co.z, dy, f.a1), dy, f.a0);
+    return __builtin_amdgcn_exp2f(-t);
 }
 
 __device__ __forceinline__ bool rect_has(uint2 r, int x, int y) {

@@ -69,7 +69,7 @@ struct Grads {
 // Per-(view, Gaussian) 2D records produced by the projection, r = v*n + g.
 struct Records {
     float2* xy;       // projected mean
-    float4* conic;    // (A, B, C, opacity)
+    float4* conic;    // (A', B', C', log2 opacity): conic in base-2 units, see frag_col
     float4* col;      // (r, g, b, depth)
     uint2* rect;      // inclusive pixel rect (x0 | x1 << 16, y0 | y1 << 16)
     uint32_t* nt;     // bins touched (0 = not visible)

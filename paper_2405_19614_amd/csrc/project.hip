@@ -32,7 +32,8 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
     const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
     const uint32_t ty0 = (uint32_t)pr.y0 / vt.bh, ty1 = (uint32_t)pr.y1 / vt.bh;
     rec.xy[r] = make_float2(pr.u, pr.v);
-    rec.conic[r] = make_float4(pr.A, pr.B, pr.C, pr.o);
+    // base-2 conic with log2(opacity) (the compositing kernels' form)
+    rec.conic[r] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
     rec.col[r] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);
     rec.rect[r] = make_uint2((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16), (uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16));
     rec.nt[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);

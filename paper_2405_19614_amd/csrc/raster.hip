@@ -152,45 +152,42 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
         }
         __syncthreads();
         if (COUNT) n_entries += (uint32_t)cnt;
-        for (int k = 0; k < cnt && !all_done; k++) {
+        // every owned pixel is evaluated with predicated selects, no branch
+        for (int k = 0; k < cnt; k++) {
             const uint2 rc = s_rc[k];
-            if (px < (int)(rc.x & 0xffffu) || px > (int)(rc.x >> 16)) continue;
-            const int y0 = (int)(rc.y & 0xffffu), y1 = (int)(rc.y >> 16);
             const float2 xy = s_xy[k];
             const float4 co = s_co[k];
-            bool any_blend = false;
-            float w[PPT];
+            const float4 cz = s_cz[k];
+            const uint32_t jk = s_j[k] + 1u;
+            const bool colok = px >= (int)(rc.x & 0xffffu) && px <= (int)(rc.x >> 16);
+            const int rlo = (int)(rc.y & 0xffffu) - py0, rhi = (int)(rc.y >> 16) - py0;
+            const FragCol fc = frag_col(fpx, xy, co);
 #pragma unroll
             for (int q = 0; q < PPT; q++) {
-                w[q] = 0.f;
-                const int py = py0 + q;
-                if (done[q] || py < y0 || py > y1) continue;
-                if (COUNT) n_visit++;
-                Frag f;
-                if (!frag_eval(fpx, (float)py, xy, co, f)) continue;
-                const float Tn = T[q] * (1.f - f.alpha);
-                if (Tn < kTMin) { done[q] = true; continue; }
-                if (COUNT) n_blend++;
-                w[q] = f.alpha * T[q];
-                T[q] = Tn;
-                lastp[q] = s_j[k] + 1u;
-                any_blend = true;
-            }
-            if (any_blend) {
-                const float4 cz = s_cz[k];
-#pragma unroll
-                for (int q = 0; q < PPT; q++) {
-                    C0[q] += cz.x * w[q];
-                    C1[q] += cz.y * w[q];
-                    C2[q] += cz.z * w[q];
-                    D[q] += cz.w * w[q];
+                const float raw = frag_raw(fc, co, (float)(py0 + q) - xy.y);
+                const float a = fminf(kAlphaMax, raw);
+                const bool inr = colok && !done[q] && q >= rlo && q <= rhi;
+                const bool ok = inr && a >= kAlphaMin;
+                const float Tn = T[q] * (1.f - a);
+                const bool stop = ok && Tn < kTMin;
+                const bool bl = ok && !stop;
+                if (COUNT) {
+                    n_visit += inr ? 1u : 0u;
+                    n_blend += bl ? 1u : 0u;
                 }
+                done[q] = done[q] || stop;
+                const float w = bl ? a * T[q] : 0.f;
+                T[q] = bl ? Tn : T[q];
+                lastp[q] = bl ? jk : lastp[q];
+                C0[q] += cz.x * w;
+                C1[q] += cz.y * w;
+                C2[q] += cz.z * w;
+                D[q] += cz.w * w;
             }
-            bool ad = true;
-#pragma unroll
-            for (int q = 0; q < PPT; q++) ad = ad && done[q];
-            all_done = ad;
         }
+        all_done = true;
+#pragma unroll
+        for (int q = 0; q < PPT; q++) all_done = all_done && done[q];
     }
     const int64_t hw = (int64_t)vi.W * vi.H;
     float lc = 0.f, ld = 0.f;
@@ -267,27 +264,27 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
     const int lane = threadIdx.x & 63;
     const int64_t hw = (int64_t)vi.W * vi.H;
 
-    float T[PPT], Tf[PPT], g0[PPT], g1[PPT], g2c[PPT], gd[PPT], ga[PPT];
-    float S0[PPT], S1[PPT], S2[PPT], SD[PPT];
+    // per pixel: transmittance, upstream gradients, and Q = sum over the
+    // fragments behind the current one of (dL/dC . colour + dL/dD z) w
+    float T[PPT], gaTf[PPT], g0[PPT], g1[PPT], g2c[PPT], gd[PPT], Q[PPT];
     uint32_t lastp[PPT];
     uint32_t mylast = 0u;
 #pragma unroll
     for (int q = 0; q < PPT; q++) {
-        T[q] = Tf[q] = 1.f;
-        g0[q] = g1[q] = g2c[q] = gd[q] = ga[q] = 0.f;
-        S0[q] = S1[q] = S2[q] = SD[q] = 0.f;
+        T[q] = 1.f;
+        g0[q] = g1[q] = g2c[q] = gd[q] = gaTf[q] = 0.f;
+        Q[q] = 0.f;
         lastp[q] = 0u;
         const int py = py0 + q;
         if (px < vi.W && py < vi.H) {
             const int64_t pl = (int64_t)py * vi.W + px;
             const int64_t pi = (int64_t)vi.pix_off + pl;
             const int64_t ci = 3 * (int64_t)vi.pix_off + pl;
-            Tf[q] = tfin[pi];
-            T[q] = Tf[q];
+            T[q] = tfin[pi];
             lastp[q] = last[pi];
             if (dC) { g0[q] = dC[ci]; g1[q] = dC[ci + hw]; g2c[q] = dC[ci + 2 * hw]; }
             if (dD) gd[q] = dD[pi];
-            if (dA) ga[q] = dA[pi];
+            if (dA) gaTf[q] = dA[pi] * T[q];   // dA/dalpha_i = T_final / (1 - alpha_i)
             mylast = max(mylast, lastp[q]);
         }
     }
@@ -324,50 +321,61 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
         __syncthreads();
         for (int k = 0; k < cnt; k++) {
             const uint32_t j = s_j[k];
-            float gv[NG];
-#pragma unroll
-            for (int e = 0; e < NG; e++) gv[e] = 0.f;
-            bool any = false;
             const uint2 rc = s_rc[k];
-            if (j < mylast && px >= (int)(rc.x & 0xffffu) && px <= (int)(rc.x >> 16)) {
-                const int y0 = (int)(rc.y & 0xffffu), y1 = (int)(rc.y >> 16);
-                const float2 xy = s_xy[k];
-                const float4 co = s_co[k];
-                const float4 cz = s_cz[k];
+            const float2 xy = s_xy[k];
+            const float4 co = s_co[k];
+            const float4 cz = s_cz[k];
+            const bool colok = j < mylast && px >= (int)(rc.x & 0xffffu) && px <= (int)(rc.x >> 16);
+            const int rlo = (int)(rc.y & 0xffffu) - py0, rhi = (int)(rc.y >> 16) - py0;
+            const FragCol fc = frag_col(fpx, xy, co);
+            // sums over this thread's pixels; the column (dx) is shared
+            float s_ds = 0.f, s_dsdy = 0.f, s_dsdy2 = 0.f, s_dar = 0.f;
+            float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gcd = 0.f;
+            bool any = false;
 #pragma unroll
-                for (int q = 0; q < PPT; q++) {
-                    const int py = py0 + q;
-                    if (j >= lastp[q] || py < y0 || py > y1) continue;
-                    Frag f;
-                    if (!frag_eval(fpx, (float)py, xy, co, f)) continue;
-                    const float inv = __builtin_amdgcn_rcpf(1.f - f.alpha);
-                    const float Ti = T[q] * inv;
-                    const float w = f.alpha * Ti;
-                    gv[6] += w * g0[q];
-                    gv[7] += w * g1[q];
-                    gv[8] += w * g2c[q];
-                    gv[9] += w * gd[q];
-                    const float dal = inv * (g0[q] * (cz.x * T[q] - S0[q]) + g1[q] * (cz.y * T[q] - S1[q]) +
-                                             g2c[q] * (cz.z * T[q] - S2[q]) + gd[q] * (cz.w * T[q] - SD[q]) +
-                                             ga[q] * Tf[q]);
-                    S0[q] += cz.x * w;
-                    S1[q] += cz.y * w;
-                    S2[q] += cz.z * w;
-                    SD[q] += cz.w * w;
-                    T[q] = Ti;
-                    if (f.raw <= kAlphaMax) {
-                        gv[5] += dal * f.G;
-                        const float ds = -dal * f.raw;
-                        gv[2] += 0.5f * ds * f.dx * f.dx;
-                        gv[3] += ds * f.dx * f.dy;
-                        gv[4] += 0.5f * ds * f.dy * f.dy;
-                        gv[0] -= ds * (co.x * f.dx + co.y * f.dy);
-                        gv[1] -= ds * (co.z * f.dy + co.y * f.dx);
-                    }
-                    any = true;
-                }
+            for (int q = 0; q < PPT; q++) {
+                const float dy = (float)(py0 + q) - xy.y;
+                const float raw = frag_raw(fc, co, dy);
+                const float a = fminf(kAlphaMax, raw);
+                const bool ok = colok && j < lastp[q] && q >= rlo && q <= rhi && a >= kAlphaMin;
+                const float inv = __builtin_amdgcn_rcpf(1.f - a);
+                const float Ti = T[q] * inv;
+                const float gcol = g0[q] * cz.x + g1[q] * cz.y + g2c[q] * cz.z + gd[q] * cz.w;
+                // dL/dalpha_i = (T_{i+1} gcol - Q + dL/dA T_final) / (1 - alpha_i)
+                const float dal = inv * (T[q] * gcol - Q[q] + gaTf[q]);
+                const float wk = ok ? a * Ti : 0.f;
+                gc0 += wk * g0[q];
+                gc1 += wk * g1[q];
+                gc2 += wk * g2c[q];
+                gcd += wk * gd[q];
+                Q[q] += wk * gcol;
+                T[q] = ok ? Ti : T[q];
+                // alpha clamped at 0.99: no dependence on opacity or sigma
+                const float da = (ok && raw <= kAlphaMax) ? dal : 0.f;
+                const float dsig = -da * raw;   // dL/dsigma
+                const float dsdy = dsig * dy;
+                s_ds += dsig;
+                s_dsdy += dsdy;
+                s_dsdy2 += dsdy * dy;
+                s_dar += da * raw;
+                any = any || ok;
             }
             if (__ballot(any) != 0ull) {
+                // natural-unit conic: A = A'/c, B = B'/(2c), C = C'/c
+                const float ic = 1.f / kHalfLog2e;
+                const float A = co.x * ic, B = 0.5f * co.y * ic, C = co.z * ic;
+                const float dx = fc.dx;
+                float gv[NG];
+                gv[0] = -(A * dx * s_ds + B * s_dsdy);            // d/du (mean x)
+                gv[1] = -(C * s_dsdy + B * dx * s_ds);            // d/dv (mean y)
+                gv[2] = 0.5f * dx * dx * s_ds;                    // d/dA
+                gv[3] = dx * s_dsdy;                              // d/dB
+                gv[4] = 0.5f * s_dsdy2;                           // d/dC
+                gv[5] = s_dar * __builtin_amdgcn_exp2f(-co.w);    // d/do: sum of dL/dalpha exp(-sigma)
+                gv[6] = gc0;
+                gv[7] = gc1;
+                gv[8] = gc2;
+                gv[9] = gcd;
 #pragma unroll
                 for (int e = 0; e < NG; e++) {
                     const float s = wave_sum_lane63(gv[e]);

@@ -29,12 +29,12 @@ def test_c3_mapping_step_full_parity(setup):
     import paper_2405_19614_amd as gs
     ctx, s, og, tgt = setup
     g, poses = dev_scene(s)
-    tile = ctx.autotune(g, s.cams, poses, iters=1)
-    print(f"  tile {tile}", flush=True)
+    tile, binsz = ctx.autotune(g, s.cams, poses, iters=1)
+    print(f"  tile {tile} bin {binsz}", flush=True)
     t = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda")
     tc, td = tgt["color"].astype(np.float32), tgt["depth"].astype(np.float32)
     st = gs.MappingStep(ctx, g, s.cams, poses, t(tc), t(td),
-                        gs.StepOptions(w_color=1.0, w_depth=0.1, tile=tile, use_graph=True))
+                        gs.StepOptions(w_color=1.0, w_depth=0.1, tile=tile, bin=binsz, use_graph=True))
     st()
     st()   # second replay: graph path
     torch.cuda.synchronize()
