@@ -75,7 +75,14 @@ struct Records {
     uint32_t* nt;     // bins touched (0 = not visible)
 };
 
-constexpr int kG2Stride = 12;   // floats per record of the 2D-gradient buffer (10 used)
+// Per-record 2D gradients summed by the compositing backward, stride
+// kG2Stride floats: with c = log2(e)/2, sd = dL/dsigma per pixel and
+// (dx, dy) the pixel offset from the projected mean,
+//   [0] c dL/du = -sum sd (A' dx + B' dy / 2)   [1] c dL/dv = -sum sd (C' dy + B' dx / 2)
+//   [2] 2 dL/dA = sum sd dx^2   [3] dL/dB = sum sd dx dy   [4] 2 dL/dC = sum sd dy^2
+//   [5] o dL/do = -sum sd       [6..8] dL/dcolour          [9] dL/dz
+// The projection backward undoes the constant factors once per record.
+constexpr int kG2Stride = 12;
 
 // Device layout of the forward state / mapping workspace (byte offsets).
 struct Layout {

@@ -96,8 +96,10 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_bwd_kernel(ViewTable vt
             project_one<true>(P, g, vi, T, pr);
             const float4* a4 = reinterpret_cast<const float4*>(g2 + r * kG2Stride);
             const float4 a0 = a4[0], a1 = a4[1], a2 = a4[2];
-            const float du = a0.x, dv = a0.y, dA = a0.z, dB = a0.w;
-            const float dC = a1.x, dop = a1.y;
+            // undo the compositing kernel's constant factors (g2 layout)
+            const float du = a0.x * (1.f / kHalfLog2e), dv = a0.y * (1.f / kHalfLog2e);
+            const float dA = 0.5f * a0.z, dB = a0.w, dC = 0.5f * a1.x;
+            const float odo = a1.y;   // o dL/do
             const float dcol[3] = {a1.z, a1.w, a2.x};
             const float dz = a2.y;
             float dmu[3] = {0.f, 0.f, 0.f};
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_bwd_kernel(ViewTable vt
                 }
             }
             // opacity
-            go += dop * pr.o * (1.f - pr.o);
+            go += odo * (1.f - pr.o);   // dL/do o (1 - o)
 
             // camera-space mean from depth and projected mean
             const float px = pr.p[0], py = pr.p[1], pz = pr.p[2];

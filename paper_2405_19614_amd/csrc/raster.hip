@@ -11,9 +11,10 @@
 // gradients and per-tile loss partials.
 // Backward: the list walked back to front from each pixel's stop index,
 // transmittance recovered by division, per-Gaussian gradients summed over the
-// thread's pixels, then across the 64-lane wavefront with DPP row shifts and
-// row broadcasts, then across the workgroup with LDS atomics, then one global
-// atomic per (tile, Gaussian, value).
+// thread's pixels, then over each 16-lane row by a DPP reduce-scatter that
+// leaves the ten values in ten distinct lanes, then across rows and waves with
+// one LDS atomic instruction per entry, then one global atomic per (tile,
+// Gaussian, value).
 #include "gs_device.h"
 
 namespace gs {
@@ -42,23 +43,59 @@ __device__ __forceinline__ double2 block_sum2(float a, float b) {
     return r;
 }
 
-// DPP move with zero fill for lanes whose source is outside the row / mask
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp0(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+// Lane exchange inside a 16-lane DPP row: row_mirror pairs lane i with 15 - i,
+// row_half_mirror i with i ^ 7 (inside each half row), the two quad_perm
+// patterns i with i ^ 2 and i ^ 1.
+template <int CTRL>
+__device__ __forceinline__ float dpp_x(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
-// Sum of x over the 64-lane wavefront, valid in lane 63: inclusive row sums
-// by row_shr 1, 2, 4, 8, then row_bcast:15 and row_bcast:31 carry the row
-// totals up to the last row.
-__device__ __forceinline__ float wave_sum_lane63(float x) {
-    x += dpp0<0x111, 0xf>(x);   // row_shr:1
-    x += dpp0<0x112, 0xf>(x);   // row_shr:2
-    x += dpp0<0x114, 0xf>(x);   // row_shr:4
-    x += dpp0<0x118, 0xf>(x);   // row_shr:8
-    x += dpp0<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-    x += dpp0<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
-    return x;
+// Reduce-scatter of ten per-lane values over each 16-lane row: four
+// butterfly exchanges (lane pairs differing in bit 3, 2, 1, 0) in which each
+// lane keeps the half of its values that its bit selects and adds the
+// partner's copy of that half.  Afterwards lane i of a row holds the row total
+// of value kRsSlot[i] (-1: nothing).  33 VALU operations against 60 for ten
+// separate lane-63 reductions, and the results land in distinct lanes, so
+// one LDS atomic instruction stores all ten.
+__device__ __forceinline__ float row_reduce_scatter10(const float (&v)[10], int lane) {
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+    float u[5];
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        const float snd = b3 ? v[i] : v[i + 5];
+        const float kp = b3 ? v[i + 5] : v[i];
+        u[i] = kp + dpp_x<0x140>(snd);   // row_mirror
+    }
+    float w[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const float hi = (i < 2) ? u[i + 3] : 0.f;
+        const float snd = b2 ? u[i] : hi;
+        const float kp = b2 ? hi : u[i];
+        w[i] = kp + dpp_x<0x141>(snd);   // row_half_mirror
+    }
+    float x[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const float hi = (i < 1) ? w[i + 2] : 0.f;
+        const float snd = b1 ? w[i] : hi;
+        const float kp = b1 ? hi : w[i];
+        x[i] = kp + dpp_x<0x4E>(snd);    // quad_perm [2, 3, 0, 1]
+    }
+    const float snd = b0 ? x[0] : x[1];
+    const float kp = b0 ? x[1] : x[0];
+    return kp + dpp_x<0xB1>(snd);        // quad_perm [1, 0, 3, 2]
+}
+
+// value held by lane (i mod 16) after row_reduce_scatter10, -1 for none
+__device__ __forceinline__ int rs_slot(int lane) {
+    const int l = lane & 15;
+    const int w = (l & 3) == 3 ? -1 : (l & 3);         // bits 1, 0 -> index among three
+    if (w < 0) return -1;
+    const int u = (l & 4) ? (w + 3 < 5 ? w + 3 : -1) : w;   // bit 2 -> index among five
+    if (u < 0) return -1;
+    return ((l & 8) ? 5 : 0) + u;                      // bit 3 -> index among ten
 }
 
 // Block-wide stream compaction: the rank of this thread's flagged item among
@@ -89,6 +126,17 @@ __device__ __forceinline__ bool rect_meets(uint2 rc, int bx0, int bx1, int by0, 
            (int)(rc.y >> 16) >= by0;
 }
 
+// Rect of a staged entry.  Every lane reads the entry from the same LDS
+// address, so the packed words are moved to scalar registers and unpacked on
+// the scalar unit.
+struct RectS {
+    int x0, x1, y0, y1;
+};
+__device__ __forceinline__ RectS rect_scalar(uint2 rc) {
+    const uint32_t rx = __builtin_amdgcn_readfirstlane(rc.x), ry = __builtin_amdgcn_readfirstlane(rc.y);
+    return RectS{(int)(rx & 0xffffu), (int)(rx >> 16), (int)(ry & 0xffffu), (int)(ry >> 16)};
+}
+
 // bin of compositing tile (txi, tyi) of view vi
 __device__ __forceinline__ int bin_of_tile(const ViewTable& vt, const ViewInfo& vi, int txi, int tyi, int TW, int TH) {
     return vi.bin_off + ((tyi * TH) / vt.bh) * vi.bins_x + (txi * TW) / vt.bw;
@@ -117,17 +165,18 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
     const int bx0 = txi * TW, bx1 = bx0 + TW - 1, by0 = tyi * TH, by1 = by0 + TH - 1;
     __shared__ uint32_t s_j[NT];
 
+    // T[q] < 0 marks a pixel that has stopped (or lies outside the image);
+    // its transmittance is then -T[q]
     float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
     uint32_t lastp[PPT];
-    bool done[PPT];
     uint32_t n_visit = 0u, n_blend = 0u, n_entries = 0u;
     bool all_done = true;
 #pragma unroll
     for (int q = 0; q < PPT; q++) {
-        T[q] = 1.f; C0[q] = C1[q] = C2[q] = D[q] = 0.f;
+        T[q] = (px < vi.W && py0 + q < vi.H) ? 1.f : -1.f;
+        C0[q] = C1[q] = C2[q] = D[q] = 0.f;
         lastp[q] = 0u;
-        done[q] = !(px < vi.W && py0 + q < vi.H);
-        all_done = all_done && done[q];
+        all_done = all_done && T[q] < 0.f;
     }
     for (uint32_t b = rg.x; b < rg.y; b += NT) {
         if (__syncthreads_count(all_done) == NT) break;
@@ -159,25 +208,28 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
             const float4 co = s_co[k];
             const float4 cz = s_cz[k];
             const uint32_t jk = s_j[k] + 1u;
-            const bool colok = px >= (int)(rc.x & 0xffffu) && px <= (int)(rc.x >> 16);
-            const int rlo = (int)(rc.y & 0xffffu) - py0, rhi = (int)(rc.y >> 16) - py0;
+            // predicates combine with & (not &&): no per-pixel exec-mask branches
+            const RectS rs = rect_scalar(rc);
+            const bool colok = (px >= rs.x0) & (px <= rs.x1);
             const FragCol fc = frag_col(fpx, xy, co);
 #pragma unroll
             for (int q = 0; q < PPT; q++) {
                 const float raw = frag_raw(fc, co, (float)(py0 + q) - xy.y);
                 const float a = fminf(kAlphaMax, raw);
-                const bool inr = colok && !done[q] && q >= rlo && q <= rhi;
-                const bool ok = inr && a >= kAlphaMin;
-                const float Tn = T[q] * (1.f - a);
-                const bool stop = ok && Tn < kTMin;
-                const bool bl = ok && !stop;
+                const bool inr = colok & (py0 + q >= rs.y0) & (py0 + q <= rs.y1);
+                const bool ok = inr & (a >= kAlphaMin);
+                // T (1 - alpha), negative once stopped, so a stopped pixel
+                // never blends again
+                const float aT = a * T[q];
+                const float Tn = T[q] - aT;
+                const bool stop = ok & (Tn < kTMin);
+                const bool bl = ok & !stop;
                 if (COUNT) {
-                    n_visit += inr ? 1u : 0u;
+                    n_visit += (inr & (T[q] > 0.f)) ? 1u : 0u;
                     n_blend += bl ? 1u : 0u;
                 }
-                done[q] = done[q] || stop;
-                const float w = bl ? a * T[q] : 0.f;
-                T[q] = bl ? Tn : T[q];
+                const float w = bl ? aT : 0.f;
+                T[q] = bl ? Tn : (stop ? -fabsf(T[q]) : T[q]);
                 lastp[q] = bl ? jk : lastp[q];
                 C0[q] += cz.x * w;
                 C1[q] += cz.y * w;
@@ -187,7 +239,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
         }
         all_done = true;
 #pragma unroll
-        for (int q = 0; q < PPT; q++) all_done = all_done && done[q];
+        for (int q = 0; q < PPT; q++) all_done = all_done && T[q] < 0.f;
     }
     const int64_t hw = (int64_t)vi.W * vi.H;
     float lc = 0.f, ld = 0.f;
@@ -195,6 +247,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
     for (int q = 0; q < PPT; q++) {
         const int py = py0 + q;
         if (!(px < vi.W && py < vi.H)) continue;
+        T[q] = fabsf(T[q]);
         const int64_t pl = (int64_t)py * vi.W + px;
         const int64_t pi = (int64_t)vi.pix_off + pl;
         const int64_t ci = 3 * (int64_t)vi.pix_off + pl;
@@ -262,6 +315,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
     const int bx0 = txi * TW, bx1 = bx0 + TW - 1, by0 = tyi * TH, by1 = by0 + TH - 1;
     __shared__ uint32_t s_j[NT];
     const int lane = threadIdx.x & 63;
+    const int slot = rs_slot(lane);
     const int64_t hw = (int64_t)vi.W * vi.H;
 
     // per pixel: transmittance, upstream gradients, and Q = sum over the
@@ -325,11 +379,12 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
             const float2 xy = s_xy[k];
             const float4 co = s_co[k];
             const float4 cz = s_cz[k];
-            const bool colok = j < mylast && px >= (int)(rc.x & 0xffffu) && px <= (int)(rc.x >> 16);
-            const int rlo = (int)(rc.y & 0xffffu) - py0, rhi = (int)(rc.y >> 16) - py0;
+            const RectS rs = rect_scalar(rc);
+            const bool colok = (j < mylast) & (px >= rs.x0) & (px <= rs.x1);
             const FragCol fc = frag_col(fpx, xy, co);
-            // sums over this thread's pixels; the column (dx) is shared
-            float s_ds = 0.f, s_dsdy = 0.f, s_dsdy2 = 0.f, s_dar = 0.f;
+            // sums over this thread's pixels (the column, dx, is shared) of
+            // dL/dsigma, dL/dsigma dy and dL/dsigma dy^2
+            float s_ds = 0.f, s_dsdy = 0.f, s_dsdy2 = 0.f;
             float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gcd = 0.f;
             bool any = false;
 #pragma unroll
@@ -337,7 +392,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
                 const float dy = (float)(py0 + q) - xy.y;
                 const float raw = frag_raw(fc, co, dy);
                 const float a = fminf(kAlphaMax, raw);
-                const bool ok = colok && j < lastp[q] && q >= rlo && q <= rhi && a >= kAlphaMin;
+                const bool ok = colok & (j < lastp[q]) & (py0 + q >= rs.y0) & (py0 + q <= rs.y1) & (a >= kAlphaMin);
                 const float inv = __builtin_amdgcn_rcpf(1.f - a);
                 const float Ti = T[q] * inv;
                 const float gcol = g0[q] * cz.x + g1[q] * cz.y + g2c[q] * cz.z + gd[q] * cz.w;
@@ -351,36 +406,31 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
                 Q[q] += wk * gcol;
                 T[q] = ok ? Ti : T[q];
                 // alpha clamped at 0.99: no dependence on opacity or sigma
-                const float da = (ok && raw <= kAlphaMax) ? dal : 0.f;
+                const float da = (ok & (raw <= kAlphaMax)) ? dal : 0.f;
                 const float dsig = -da * raw;   // dL/dsigma
                 const float dsdy = dsig * dy;
                 s_ds += dsig;
                 s_dsdy += dsdy;
                 s_dsdy2 += dsdy * dy;
-                s_dar += da * raw;
-                any = any || ok;
+                any = any | ok;
             }
             if (__ballot(any) != 0ull) {
-                // natural-unit conic: A = A'/c, B = B'/(2c), C = C'/c
-                const float ic = 1.f / kHalfLog2e;
-                const float A = co.x * ic, B = 0.5f * co.y * ic, C = co.z * ic;
+                // constant factors are applied by the projection backward
+                const float hb = 0.5f * co.y;
                 const float dx = fc.dx;
                 float gv[NG];
-                gv[0] = -(A * dx * s_ds + B * s_dsdy);            // d/du (mean x)
-                gv[1] = -(C * s_dsdy + B * dx * s_ds);            // d/dv (mean y)
-                gv[2] = 0.5f * dx * dx * s_ds;                    // d/dA
-                gv[3] = dx * s_dsdy;                              // d/dB
-                gv[4] = 0.5f * s_dsdy2;                           // d/dC
-                gv[5] = s_dar * __builtin_amdgcn_exp2f(-co.w);    // d/do: sum of dL/dalpha exp(-sigma)
+                gv[0] = -(co.x * dx * s_ds + hb * s_dsdy);
+                gv[1] = -(co.z * s_dsdy + hb * dx * s_ds);
+                gv[2] = dx * dx * s_ds;
+                gv[3] = dx * s_dsdy;
+                gv[4] = s_dsdy2;
+                gv[5] = -s_ds;
                 gv[6] = gc0;
                 gv[7] = gc1;
                 gv[8] = gc2;
                 gv[9] = gcd;
-#pragma unroll
-                for (int e = 0; e < NG; e++) {
-                    const float s = wave_sum_lane63(gv[e]);
-                    if (lane == 63 && s != 0.f) atomicAdd(&s_g[k][e], s);
-                }
+                const float s = row_reduce_scatter10(gv, lane);
+                if (slot >= 0) atomicAdd(&s_g[k][slot], s);
             }
         }
         __syncthreads();
