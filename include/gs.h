@@ -308,6 +308,12 @@ int gs_set_tile(gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
  * not change any result, only the launch shape; gs_autotune sets it too. */
 int gs_set_pixels_per_thread(gs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t ppt);
 
+/* Pixels per thread the compositing kernels use for a tile shape (the value
+ * set by gs_set_pixels_per_thread or gs_autotune, else the default: 2 where a
+ * 2-pixel kernel exists, otherwise 1).  Returns GS_EINVAL for a null context
+ * or a tile shape without kernels. */
+int gs_get_pixels_per_thread(const gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
+
 #ifdef __cplusplus
 }
 #endif

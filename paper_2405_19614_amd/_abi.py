@@ -65,7 +65,7 @@ class gs_adam(ctypes.Structure):
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_state_bytes", "gs_render_forward",
            "gs_render_backward", "gs_reproj_residual", "gs_step_workspace_bytes", "gs_mapping_step",
            "gs_step_status", "gs_bin_records", "gs_autotune", "gs_set_tile", "gs_num_stages", "gs_stage_name",
-           "gs_step_profile", "gs_set_pixels_per_thread", "gs_set_bin"]
+           "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bin"]
 
 _lib = None
 
@@ -111,6 +111,8 @@ def load() -> ctypes.CDLL:
     L.gs_set_bin.argtypes = [c_void_p, c_int32, c_int32]
     L.gs_set_tile.argtypes = [c_void_p, c_int32, c_int32]
     L.gs_set_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32, c_int32]
+    L.gs_get_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32]
+    L.gs_get_pixels_per_thread.restype = c_int32
     L.gs_num_stages.restype = c_int32
     L.gs_stage_name.argtypes = [c_int32]
     L.gs_stage_name.restype = ctypes.c_char_p

@@ -199,6 +199,13 @@ class Context:
         if ppt is not None:
             self._check(self.lib.gs_set_pixels_per_thread(self.h, tw, th, ppt))
 
+    def ppt_choice(self, tile) -> int:
+        """Pixels per thread the compositing kernels use for ``tile`` (tw, th)."""
+        r = int(self.lib.gs_get_pixels_per_thread(self.h, int(tile[0]), int(tile[1])))
+        if r < 0:
+            self._check(r)
+        return r
+
     def set_bin(self, bw: int, bh: int):
         self._check(self.lib.gs_set_bin(self.h, bw, bh))
         self.bin_choice = (int(bw), int(bh)) if (bw, bh) != (0, 0) else (64, 64)

@@ -387,6 +387,11 @@ int gs_set_pixels_per_thread(gs_ctx* c, int32_t tw, int32_t th, int32_t ppt) {
     return GS_OK;
 }
 
+int gs_get_pixels_per_thread(const gs_ctx* c, int32_t tw, int32_t th) {
+    if (!c || !tile_ok(tw, th)) return GS_EINVAL;
+    return ppt_of(c, tw, th);
+}
+
 size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t cap, int32_t bw, int32_t bh) {
     gs::ViewTable vt;
     resolve_bin(nullptr, bw, bh, bw, bh);
