@@ -200,6 +200,7 @@ struct Ptrs {
     float* dD;
     double2* tilepart;
     double* rpacc;
+    gs::TileSched ts;
 };
 
 Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
@@ -213,6 +214,8 @@ Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     p.tfin = reinterpret_cast<float*>(base + L.off_tfin);
     p.last = reinterpret_cast<uint32_t*>(base + L.off_last);
     p.g2 = reinterpret_cast<float*>(base + L.off_g2);
+    p.ts.order = reinterpret_cast<uint32_t*>(base + L.off_torder);
+    p.ts.work = reinterpret_cast<uint32_t*>(base + L.off_twork);
     p.posepart = reinterpret_cast<double*>(base + L.off_posepart);
     p.scal = reinterpret_cast<uint32_t*>(base + L.off_scalars);
     p.vals = reinterpret_cast<uint32_t*>(base + ((tile_passes(L.n_bins) & 1) ? L.off_pv1 : L.off_pv0));
@@ -294,12 +297,15 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     L.off_ranges = take((size_t)vt.n_bins * 8);
     L.off_tfin = take((size_t)vt.n_pix * 4);
     L.off_last = take((size_t)vt.n_pix * 4);
+    const int64_t tb = std::max<int64_t>(tiles_bound, vt.n_tiles);
+    L.off_torder = take((size_t)tb * 4);
+    L.off_twork = take((size_t)tb * 4);
     L.off_g2 = take((size_t)R * kG2Stride * 4);
     L.off_posepart = take((size_t)vt.V * std::max<int64_t>(L.pose_blocks, 1) * 6 * 8);
     if (workspace) {
         L.off_dC = take((size_t)vt.n_pix * 3 * 4);
         L.off_dD = take((size_t)vt.n_pix * 4);
-        L.off_tilepart = take((size_t)std::max<int64_t>(tiles_bound, vt.n_tiles) * 16);
+        L.off_tilepart = take((size_t)tb * 16);
         L.off_rpacc = take((size_t)vt.V * 8 * 8);
     }
     L.bytes = o;
@@ -397,7 +403,7 @@ size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t cap, 
     resolve_bin(nullptr, bw, bh, bw, bh);
     if (cap < 0 || cap >= ((int64_t)1 << 31)) return 0;
     if (build_vt(nullptr, cams, V, n, 8, 8, bw, bh, 0.f, 0.f, vt) != GS_OK) return 0;
-    return gs::make_layout(vt, n, cap, false).bytes;
+    return gs::make_layout(vt, n, cap, false, max_tiles(cams, V)).bytes;
 }
 
 size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int32_t sh, int64_t cap, int32_t bw,
@@ -425,7 +431,7 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     resolve_bin(c, plan->bin_w, plan->bin_h, bw, bh);
     gs::ViewTable vt;
     if ((r = build_vt(c, cams, V, g->n, tw, th, bw, bh, 0.f, 0.f, vt))) return r;
-    const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false);
+    const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false, max_tiles(cams, V));
     if (state_bytes < L.bytes)
         return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
     DeviceGuard dg(c->device);
@@ -450,7 +456,8 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     uint32_t* vals = nullptr;
     GS_HIP(c, gs::launch_binning_emit(vt, L, base, p.rec.rect, total, s, &vals));
     if (total > 0 && vals != p.vals) return fail(c, GS_EDEVICE, "internal: sorted values in unexpected buffer");
-    GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, p.vals, p.rec, color, depth, alpha, p.tfin, p.last, nullptr, s));
+    GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, p.vals, p.rec, color, depth, alpha, p.tfin, p.last, nullptr, p.ts,
+                                       s));
     return GS_OK;
 }
 
@@ -470,7 +477,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     gs::ViewTable vt;
     if ((r = build_vt(c, cams, V, g->n, plan->tile_w, plan->tile_h, plan->bin_w, plan->bin_h, 0.f, 0.f, vt)))
         return r;
-    const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false);
+    const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false, max_tiles(cams, V));
     if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -478,7 +485,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     const gs::Params P = params_of(g);
     gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
     GS_HIP(c, gs::launch_zero_g2(p.rec.nt, p.g2, L.R, s));
-    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, s));
+    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, p.ts, s));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, 0, p.posepart, L.pose_blocks, s));
     GS_HIP(c, gs::launch_pose_finalize(vt, p.posepart, L.pose_blocks, nullptr, 0.f, dL_dpose, s));
     return GS_OK;
@@ -527,7 +534,7 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::Layout& L, char* 
     GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.nt, p.rec.rect, nullptr, L.cap, s, &vals));
     GS_HIP(c, mark(2));
     gs::LossArgs la{tg->color, tg->depth, tg->mask, o->use_gate, o->gate_gamma, p.dC, p.dD, p.tilepart};
-    GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, s,
+    GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, p.ts, s,
                                        counts));
     GS_HIP(c, mark(3));
     const bool rp = mt && mt->M > 0;
@@ -538,7 +545,7 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::Layout& L, char* 
     GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, o->w_color, o->w_depth, o->w_reproj,
                                      loss_out, s));
     GS_HIP(c, mark(4));
-    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, s));
+    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, s));
     GS_HIP(c, mark(5));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, o->accumulate_grads, p.posepart, L.pose_blocks,
                                         s));
@@ -748,7 +755,7 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
     gs::ViewTable vt;
     int r = build_vt(c, cams, V, n, 8, 8, bw, bh, 0.f, 0.f, vt);
     if (r) return r;
-    const gs::Layout L = gs::make_layout(vt, n, cap, false);
+    const gs::Layout L = gs::make_layout(vt, n, cap, false, max_tiles(cams, V));
     if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -98,6 +98,7 @@ struct Layout {
     size_t off_scan;                              // scan block sums
     size_t off_ranges;                            // n_bins uint2
     size_t off_tfin, off_last;                    // n_pix
+    size_t off_torder, off_twork;                 // tile order and work, sized for the smallest tile
     size_t off_g2;                                // R * kG2Stride floats
     size_t off_posepart;                          // V * pose_blocks * 6 doubles
     size_t off_scalars;                           // counters and flags
@@ -156,14 +157,25 @@ struct LossArgs {
     double2* tile_part;
 };
 
-// counts (nullable, device u64[2]): += candidates visited (rect contains the
-// pixel, up to and including the terminating one) and fragments blended
+// Order in which the compositing launches take their tiles (device, n_tiles
+// each): `order` is filled by the launchers themselves, heaviest first;
+// `work` receives, per tile, the list entries the forward staged, which
+// orders the backward.
+struct TileSched {
+    uint32_t* order;
+    uint32_t* work;
+};
+
+// counts (nullable, device u64[4]): += candidates visited (rect contains the
+// pixel, up to and including the terminating one), fragments blended, list
+// entries staged, bin-list entries scanned
 hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                                 float* color, float* depth, float* alpha, float* tfin, uint32_t* last,
-                                const LossArgs* loss, hipStream_t s, unsigned long long* counts = nullptr);
+                                const LossArgs* loss, const TileSched& ts, hipStream_t s,
+                                unsigned long long* counts = nullptr);
 hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                                 const float* tfin, const uint32_t* last, const float* dC, const float* dD,
-                                const float* dA, float* g2, hipStream_t s);
+                                const float* dA, float* g2, const TileSched& ts, hipStream_t s);
 
 hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc, float w_color,
                               float w_depth, float w_reproj, float* loss_out, hipStream_t s);

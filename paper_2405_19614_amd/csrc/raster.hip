@@ -1,7 +1,8 @@
 // Tile compositing, forward and backward (Sec. 3.4 "Differentiable
 // Rasterization": colour and depth compositing; Sec. 3.3 border mask).
 //
-// One workgroup per (view, tile) of every view in one launch.  Each thread
+// One workgroup per (view, tile) of every view in one launch, tiles taken
+// heaviest first (order_tiles_kernel).  Each thread
 // owns PPT vertically adjacent pixels of the tile, so one LDS read of a list
 // entry and one wavefront reduction serve PPT pixels.  The tile's
 // depth-ordered list is staged through LDS in batches of one record per
@@ -147,13 +148,15 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
                                                                      const uint32_t* __restrict__ vals, Records rec,
                                                                      float* color, float* depth, float* alpha,
                                                                      float* tfin, uint32_t* last, LossArgs la,
+                                                                     const uint32_t* __restrict__ order,
+                                                                     uint32_t* __restrict__ work,
                                                                      unsigned long long* counts) {
     constexpr int NT = TW * TH / PPT;
     __shared__ float2 s_xy[NT];
     __shared__ float4 s_co[NT];
     __shared__ float4 s_cz[NT];
     __shared__ uint2 s_rc[NT];
-    const int t = blockIdx.x;
+    const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;   // heaviest tiles first
     const int v = view_of_tile(vt, t);
     const ViewInfo& vi = vt.v[v];
     const int lt = t - vi.tile_off;
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
             s_j[pos] = j;
         }
         __syncthreads();
-        if (COUNT) n_entries += (uint32_t)cnt;
+        n_entries += (uint32_t)cnt;
         // every owned pixel is evaluated with predicated selects, no branch
         for (int k = 0; k < cnt; k++) {
             const uint2 rc = s_rc[k];
@@ -271,6 +274,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
             ld += m * fabsf(ed);
         }
     }
+    if (threadIdx.x == 0) work[t] = n_entries;   // orders the backward
     if (LOSS) {
         const double2 s = block_sum2<NT>(lc, ld);
         if (threadIdx.x == 0) la.tile_part[t] = s;
@@ -293,7 +297,8 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
                                                                      const uint32_t* __restrict__ last,
                                                                      const float* __restrict__ dC,
                                                                      const float* __restrict__ dD,
-                                                                     const float* __restrict__ dA, float* g2) {
+                                                                     const float* __restrict__ dA, float* g2,
+                                                                     const uint32_t* __restrict__ order) {
     constexpr int NT = TW * TH / PPT;
     constexpr int NG = 10;
     __shared__ float2 s_xy[NT];
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
     __shared__ uint32_t s_id[NT];
     __shared__ float s_g[NT][NG];
     __shared__ uint32_t s_hi;
-    const int t = blockIdx.x;
+    const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;   // heaviest tiles first
     const int v = view_of_tile(vt, t);
     const ViewInfo& vi = vt.v[v];
     const int lt = t - vi.tile_off;
@@ -448,35 +453,85 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
     }
 }
 
+// Heaviest tiles first (longest-processing-time order).  Workgroups start in
+// blockIdx order, so a tile with a long list that started late would finish
+// long after the rest of the grid.  One workgroup buckets the tiles by a work
+// estimate in quarter octaves, descending, with LDS counters: the bin's list
+// length before the forward, the entries the forward staged before the
+// backward.  Order inside a bucket is arbitrary; no result depends on it.
+constexpr int kOrderBuckets = 128;
+constexpr int kOrderThreads = 1024;
+
+__device__ __forceinline__ int order_bucket(const ViewTable& vt, const uint2* ranges, const uint32_t* work, int t) {
+    uint32_t w;
+    if (work) {
+        w = work[t];
+    } else {
+        const int v = view_of_tile(vt, t);
+        const ViewInfo& vi = vt.v[v];
+        const int lt = t - vi.tile_off;
+        const int tyi = lt / vi.tiles_x, txi = lt - tyi * vi.tiles_x;
+        const uint2 rg = ranges[bin_of_tile(vt, vi, txi, tyi, vt.tw, vt.th)];
+        w = rg.y - rg.x;
+    }
+    // 4 log2(w + 1) in whole steps: exponent and top two mantissa bits
+    const uint32_t b = (__float_as_uint((float)w + 1.f) >> 21) - (127u << 2);
+    return kOrderBuckets - 1 - (int)min(b, (uint32_t)(kOrderBuckets - 1));
+}
+
+__global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt, const uint2* __restrict__ ranges,
+                                                                    const uint32_t* __restrict__ work,
+                                                                    uint32_t* __restrict__ order) {
+    __shared__ uint32_t cnt[kOrderBuckets];
+    const int n = vt.n_tiles;
+    for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) cnt[i] = 0u;
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += kOrderThreads) atomicAdd(&cnt[order_bucket(vt, ranges, work, t)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0u;
+        for (int i = 0; i < kOrderBuckets; i++) {
+            const uint32_t c = cnt[i];
+            cnt[i] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += kOrderThreads)
+        order[atomicAdd(&cnt[order_bucket(vt, ranges, work, t)], 1u)] = (uint32_t)t;
+}
+
 template <int TW, int TH, int PPT>
 hipError_t fwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec, float* color,
-                 float* depth, float* alpha, float* tfin, uint32_t* last, const LossArgs* loss,
+                 float* depth, float* alpha, float* tfin, uint32_t* last, const LossArgs* loss, const TileSched& ts,
                  unsigned long long* counts, hipStream_t s) {
     if (vt.n_tiles == 0) return hipSuccess;
     constexpr int NT = TW * TH / PPT;
     const LossArgs la = loss ? *loss : LossArgs{};
     if (loss && counts)
-        composite_fwd_kernel<TW, TH, PPT, true, true><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, color, depth,
-                                                                                 alpha, tfin, last, la, counts);
+        composite_fwd_kernel<TW, TH, PPT, true, true><<<vt.n_tiles, NT, 0, s>>>(
+            vt, ranges, vals, rec, color, depth, alpha, tfin, last, la, nullptr, ts.work, counts);
     else if (loss)
-        composite_fwd_kernel<TW, TH, PPT, true, false><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, color,
-                                                                                  depth, alpha, tfin, last, la, counts);
+        composite_fwd_kernel<TW, TH, PPT, true, false><<<vt.n_tiles, NT, 0, s>>>(
+            vt, ranges, vals, rec, color, depth, alpha, tfin, last, la, nullptr, ts.work, counts);
     else if (counts)
-        composite_fwd_kernel<TW, TH, PPT, false, true><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, color,
-                                                                                  depth, alpha, tfin, last, la, counts);
+        composite_fwd_kernel<TW, TH, PPT, false, true><<<vt.n_tiles, NT, 0, s>>>(
+            vt, ranges, vals, rec, color, depth, alpha, tfin, last, la, nullptr, ts.work, counts);
     else
-        composite_fwd_kernel<TW, TH, PPT, false, false><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, color,
-                                                                                   depth, alpha, tfin, last, la, counts);
+        composite_fwd_kernel<TW, TH, PPT, false, false><<<vt.n_tiles, NT, 0, s>>>(
+            vt, ranges, vals, rec, color, depth, alpha, tfin, last, la, nullptr, ts.work, counts);
     return hipGetLastError();
 }
 
 template <int TW, int TH, int PPT>
 hipError_t bwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                  const float* tfin, const uint32_t* last, const float* dC, const float* dD, const float* dA,
-                 float* g2, hipStream_t s) {
+                 float* g2, const TileSched& ts, hipStream_t s) {
     if (vt.n_tiles == 0) return hipSuccess;
     constexpr int NT = TW * TH / PPT;
-    composite_bwd_kernel<TW, TH, PPT><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2);
+    order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt, ranges, ts.work, ts.order);
+    composite_bwd_kernel<TW, TH, PPT><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2,
+                                                                 ts.order);
     return hipGetLastError();
 }
 
@@ -501,14 +556,15 @@ hipError_t bwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals,
 
 hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                                 float* color, float* depth, float* alpha, float* tfin, uint32_t* last,
-                                const LossArgs* loss, hipStream_t s, unsigned long long* counts) {
-    GS_TILE_DISPATCH(fwd_t, vt, ranges, vals, rec, color, depth, alpha, tfin, last, loss, counts, s)
+                                const LossArgs* loss, const TileSched& ts, hipStream_t s,
+                                unsigned long long* counts) {
+    GS_TILE_DISPATCH(fwd_t, vt, ranges, vals, rec, color, depth, alpha, tfin, last, loss, ts, counts, s)
 }
 
 hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                                 const float* tfin, const uint32_t* last, const float* dC, const float* dD,
-                                const float* dA, float* g2, hipStream_t s) {
-    GS_TILE_DISPATCH(bwd_t, vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2, s)
+                                const float* dA, float* g2, const TileSched& ts, hipStream_t s) {
+    GS_TILE_DISPATCH(bwd_t, vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2, ts, s)
 }
 
 #undef GS_TILE_DISPATCH
