@@ -13,6 +13,8 @@ of numpy:
   L1 terms of the mapping loss (Sec. 3.4, mapping-loss equation), as means per
   view averaged over views, with an optional constant pixel mask and the
   filter gate of Sec. 3.3 (gate equation);
+* the SSIM term of the mapping loss (Sec. 3.4, mapping-loss equation) on the
+  RGB render, with its gradient;
 * SE(3) exponential for the left-perturbation pose tangent xi = (v, w);
 * Adam (the paper says only "gradient-based optimization", Sec. 3.4).
 """
@@ -311,6 +313,101 @@ def loss_and_upstream(cams, render_out, tgt_color, tgt_depth, w_color: float, w_
         co += 3 * P
         cd += P
     return Lc, Ld, dC, dD
+
+
+# ---------------------------------------------------------------------------
+# SSIM term of the mapping loss
+# ---------------------------------------------------------------------------
+# The paper adds an SSIM loss on the RGB render with weight zeta (Sec. 3.4,
+# mapping-loss equation) and does not define it further.  Reading: the usual
+# structural similarity with an 11 x 11 Gaussian window of standard deviation
+# 1.5 px, constants C1 = 0.01^2 and C2 = 0.03^2 (images in [0, 1]), windows
+# clipped at the image border by zero padding (a "same"-size correlation),
+# computed per colour channel; L_SSIM of a view = 1 - mean over its pixels and
+# channels.
+
+SSIM_RADIUS = 5
+SSIM_SIGMA = 1.5
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window() -> np.ndarray:
+    """The 1D window (11 taps, normalised); the 2D window is its outer product."""
+    x = np.arange(-SSIM_RADIUS, SSIM_RADIUS + 1, dtype=np.float64)
+    g = np.exp(-x * x / (2.0 * SSIM_SIGMA ** 2))
+    return g / g.sum()
+
+
+def _window_mean(img: np.ndarray) -> np.ndarray:
+    """Zero-padded same-size correlation of a [H, W] image with the 2D window
+    (separable: rows, then columns)."""
+    from scipy.ndimage import correlate1d
+    g = ssim_window()
+    t = correlate1d(img, g, axis=1, mode="constant", cval=0.0)
+    return correlate1d(t, g, axis=0, mode="constant", cval=0.0)
+
+
+def ssim_channel(x: np.ndarray, y: np.ndarray, grad: bool = False):
+    """SSIM map of one channel, x rendered and y reference ([H, W]).  With
+    ``grad``, also d(sum of the map)/dx.
+
+    Per pixel p: mu_x, mu_y, e_xx, e_yy, e_xy are window means of x, y, x^2,
+    y^2, xy; sigma_x^2 = e_xx - mu_x^2, sigma_y^2 = e_yy - mu_y^2,
+    sigma_xy = e_xy - mu_x mu_y; s = N / D with
+    N = (2 mu_x mu_y + C1)(2 sigma_xy + C2) and
+    D = (mu_x^2 + mu_y^2 + C1)(sigma_x^2 + sigma_y^2 + C2).
+    Reverse mode: s depends on x through mu_x, e_xx and e_xy; with
+    A1 = 2 mu_x mu_y + C1, A2 = 2 sigma_xy + C2, B1 = mu_x^2 + mu_y^2 + C1,
+    B2 = sigma_x^2 + sigma_y^2 + C2:
+    ds/dmu_x = (2 mu_y (A2 - A1) - s 2 mu_x (B2 - B1)) / D,
+    ds/de_xx = -s B1 / D, ds/de_xy = 2 A1 / D.  The window mean is a symmetric
+    zero-padded correlation, so its transpose is itself: the gradient at q is
+    M[ds/dmu_x](q) + 2 x_q M[ds/de_xx](q) + y_q M[ds/de_xy](q)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    mx, my = _window_mean(x), _window_mean(y)
+    exx, eyy, exy = _window_mean(x * x), _window_mean(y * y), _window_mean(x * y)
+    sxx, syy, sxy = exx - mx * mx, eyy - my * my, exy - mx * my
+    A1 = 2.0 * mx * my + SSIM_C1
+    A2 = 2.0 * sxy + SSIM_C2
+    B1 = mx * mx + my * my + SSIM_C1
+    B2 = sxx + syy + SSIM_C2
+    D = B1 * B2
+    smap = A1 * A2 / D
+    if not grad:
+        return smap
+    d_mx = (2.0 * my * (A2 - A1) - smap * 2.0 * mx * (B2 - B1)) / D
+    d_exx = -smap * B1 / D
+    d_exy = 2.0 * A1 / D
+    gx = _window_mean(d_mx) + 2.0 * x * _window_mean(d_exx) + y * _window_mean(d_exy)
+    return smap, gx
+
+
+def ssim_views(cams, img, ref, weights=None):
+    """Mean SSIM per view of planar colour images concatenated over views
+    ([3, H, W] per view, flat), and, with ``weights`` (one per view), the
+    gradient of L = sum_v weights[v] (1 - SSIM_v) with respect to ``img``.
+    Returns (ssim [V], dL/dimg flat or None)."""
+    V = len(cams)
+    S = np.zeros(V)
+    dimg = None if weights is None else np.zeros(np.asarray(img).shape, np.float64)
+    o = 0
+    for v, c in enumerate(cams):
+        P = c.width * c.height
+        X = _d(img[o:o + 3 * P]).reshape(3, c.height, c.width)
+        Y = _d(ref[o:o + 3 * P]).reshape(3, c.height, c.width)
+        tot = 0.0
+        for k in range(3):
+            if weights is None:
+                sm = ssim_channel(X[k], Y[k])
+            else:
+                sm, gk = ssim_channel(X[k], Y[k], grad=True)
+                dimg[o + k * P:o + (k + 1) * P] = -float(weights[v]) / (3.0 * P) * gk.reshape(-1)
+            tot += float(sm.sum())
+        S[v] = tot / (3.0 * P)
+        o += 3 * P
+    return S, dimg
 
 
 # ---------------------------------------------------------------------------
