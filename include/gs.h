@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 1
+#define GS_ABI_VERSION 2
 #define GS_MAX_VIEWS 64
 
 typedef enum {
@@ -175,10 +175,14 @@ int gs_reproj_residual(gs_ctx* ctx, const gs_camera* cams, const float* poses, i
                        float* residual, float* loss, float* dL_dpose, void* stream);
 
 /* Options of one mapping / pose-refinement step.
- * Loss (Sec. 3.3 joint-loss equation, L1 terms of the Sec. 3.4 mapping loss):
- *   L = (1/V) sum_v ( w_color Lc_v + w_depth Ld_v + w_reproj Lr_v ),
+ * Loss (Sec. 3.3 joint-loss equation; Sec. 3.4 mapping-loss equation):
+ *   L = (1/V) sum_v ( w_color Lc_v + w_depth Ld_v + w_reproj Lr_v + w_ssim Ls_v ),
  *   Lc_v = sum_{p,k} m_p |C - C^| / (3 H_v W_v),  Ld_v = sum_p m_p |D - D^| / (H_v W_v),
- *   Lr_v = the Huber re-projection loss of gs_reproj_residual.
+ *   Lr_v = the Huber re-projection loss of gs_reproj_residual,
+ *   Ls_v = 1 - the mean SSIM of the view's colour render against the target
+ *   colour (see gs_ssim; the mask does not apply to it; skipped when
+ *   w_ssim = 0).  The paper's mapping loss (1 - zeta)(w4 L1_D + w5 L1_C) +
+ *   zeta L_SSIM is w_color = (1 - zeta) w5, w_depth = (1 - zeta) w4, w_ssim = zeta.
  *   m_p = target mask (1 if NULL) times, if use_gate, the filter gate of
  *   Sec. 3.3: target depth > 0, rendered depth > 0, rendered alpha > gate_gamma
  *   (a constant mask, no gradient through it).  sign(0) = 0.
@@ -199,6 +203,7 @@ typedef struct {
     int32_t tile_w, tile_h;     /* 0, 0 = context choice */
     int32_t bin_w, bin_h;       /* 0, 0 = context choice */
     int64_t pair_capacity;      /* capacity the workspace was sized for */
+    float w_ssim;               /* weight of the SSIM term, >= 0 */
 } gs_step_opts;
 
 /* Targets of the rendering loss (device): color [sum 3HW], depth [sum HW],
@@ -240,7 +245,7 @@ size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int3
  *   adam     Adam state (used when an update flag is set; may be NULL otherwise)
  *   cams     HOST [V]                           poses  device [V][16] (out when update_poses)
  *   color, depth, alpha  device render outputs (sum 3HW / sum HW)
- *   loss_out device [1 + 3V]: total L, then (Lc_v, Ld_v, Lr_v) per view
+ *   loss_out device [1 + 4V]: total L, then (Lc_v, Ld_v, Lr_v, Ls_v) per view
  *   dL_dpose device [V][6]: gradient of L w.r.t. each pose tangent
  * A pair overflow is flagged on the device (results then invalid); read it
  * with gs_step_status. */
@@ -313,6 +318,25 @@ int gs_set_pixels_per_thread(gs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_
  * 2-pixel kernel exists, otherwise 1).  Returns GS_EINVAL for a null context
  * or a tile shape without kernels. */
 int gs_get_pixels_per_thread(const gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
+
+/* SSIM of Sec. 3.4's mapping loss, standalone.  The paper names the term
+ * without defining it; this is the usual structural similarity, per colour
+ * channel, with an 11 x 11 Gaussian window (standard deviation 1.5 px, taps
+ * normalised to sum 1), C1 = 0.01^2, C2 = 0.03^2, and windows clipped at the
+ * image border by zero padding (the window mean at a pixel is the weighted sum
+ * over the in-image pixels of its window):
+ *   s = (2 mu_x mu_y + C1)(2 sigma_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(sigma_x^2 + sigma_y^2 + C2)).
+ *   img, ref  device planar colour images concatenated over the V views
+ *             ([3][H_v][W_v] each, float, values nominally in [0, 1]); x = img.
+ *   ssim_out  device [V]: mean of s over each view's pixels and channels.
+ *   weights   device [V] or NULL; if not NULL, dL_dimg (device, same layout
+ *             as img) ACCUMULATES d/d img of L = sum_v weights[v] (1 - SSIM_v).
+ *   workspace device scratch of gs_ssim_workspace_bytes(cams, V) bytes.
+ * Returns GS_EINVAL for NULL pointers or bad cameras, GS_ENOMEM for a short
+ * workspace; asynchronous on `stream`. */
+size_t gs_ssim_workspace_bytes(const gs_camera* cams, int32_t V);
+int gs_ssim(gs_ctx* ctx, const gs_camera* cams, int32_t V, const float* img, const float* ref, const float* weights,
+            float* ssim_out, float* dL_dimg, void* workspace, size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

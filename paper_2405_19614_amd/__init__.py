@@ -2,11 +2,13 @@
 (arXiv 2405.19614): batched EWA projection, exact (tile, depth) binning,
 LDS-staged front-to-back compositing, its recomputing backward, the Huber
 re-projection residual and a graph-captured mapping / pose-refinement step,
-behind the C ABI in include/gs.h.
+the SSIM term of the mapping loss, behind the C ABI in include/gs.h.
 """
 from .binding import (Camera, Context, GSError, GSRenderFn, Gaussians, MappingStep, PAPER_FUSION_BRIDGE,
-                      StepOptions, as_cameras, default_context, render, sh_coeffs, split_images)
+                      PAPER_MAPPING, SSIMLossFn, StepOptions, as_cameras, default_context, render, sh_coeffs,
+                      split_images, ssim_loss)
 from . import _abi
 
 __all__ = ["Camera", "Context", "GSError", "GSRenderFn", "Gaussians", "MappingStep", "PAPER_FUSION_BRIDGE",
-           "StepOptions", "as_cameras", "default_context", "render", "sh_coeffs", "split_images", "_abi"]
+           "PAPER_MAPPING", "SSIMLossFn", "StepOptions", "as_cameras", "default_context", "render", "sh_coeffs",
+           "split_images", "ssim_loss", "_abi"]

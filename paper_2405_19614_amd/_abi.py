@@ -47,7 +47,7 @@ class gs_step_opts(ctypes.Structure):
                 ("lr_means", c_float), ("lr_log_scales", c_float), ("lr_quats", c_float), ("lr_opacity", c_float),
                 ("lr_colors", c_float), ("lr_pose", c_float), ("adam_b1", c_float), ("adam_b2", c_float),
                 ("adam_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32), ("bin_w", c_int32),
-                ("bin_h", c_int32), ("pair_capacity", c_int64)]
+                ("bin_h", c_int32), ("pair_capacity", c_int64), ("w_ssim", c_float)]
 
 
 class gs_targets(ctypes.Structure):
@@ -65,7 +65,8 @@ class gs_adam(ctypes.Structure):
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_state_bytes", "gs_render_forward",
            "gs_render_backward", "gs_reproj_residual", "gs_step_workspace_bytes", "gs_mapping_step",
            "gs_step_status", "gs_bin_records", "gs_autotune", "gs_set_tile", "gs_num_stages", "gs_stage_name",
-           "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bin"]
+           "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bin",
+           "gs_ssim_workspace_bytes", "gs_ssim"]
 
 _lib = None
 
@@ -112,6 +113,10 @@ def load() -> ctypes.CDLL:
     L.gs_set_tile.argtypes = [c_void_p, c_int32, c_int32]
     L.gs_set_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32, c_int32]
     L.gs_get_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32]
+    L.gs_ssim_workspace_bytes.argtypes = [PC, c_int32]
+    L.gs_ssim_workspace_bytes.restype = c_size_t
+    L.gs_ssim.argtypes = [c_void_p, PC, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                          c_size_t, c_void_p]
     L.gs_get_pixels_per_thread.restype = c_int32
     L.gs_num_stages.restype = c_int32
     L.gs_stage_name.argtypes = [c_int32]

@@ -292,6 +292,37 @@ class Context:
         self._check(rc)
         return residual[:M], loss, dpose
 
+    def ssim(self, cams, img: torch.Tensor, ref: torch.Tensor, weights: Optional[torch.Tensor] = None,
+             dimg: Optional[torch.Tensor] = None):
+        """Mean SSIM per view of planar colour images (concatenated [3,H,W]
+        per view) and, with ``weights`` ([V]), the gradient of
+        sum_v weights[v] (1 - SSIM_v) accumulated into ``dimg`` (allocated
+        zero if None).  Returns (ssim [V], dimg or None)."""
+        cams = as_cameras(cams)
+        V = len(cams)
+        dev = self.torch_device
+        npx = sum(c.npix for c in cams)
+        img = img.contiguous()
+        ref = ref.contiguous()
+        _need(img, 3 * npx, "img", device=dev)
+        _need(ref, 3 * npx, "ref", device=dev)
+        ca = cam_array(cams)
+        nbytes = int(self.lib.gs_ssim_workspace_bytes(ca, V))
+        if nbytes == 0:
+            raise GSError(A.GS_EINVAL, "bad cameras")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        out = torch.empty(V, dtype=torch.float32, device=dev)
+        if weights is not None:
+            weights = weights.to(torch.float32).contiguous()
+            _need(weights, V, "weights", device=dev)
+            if dimg is None:
+                dimg = torch.zeros(3 * npx, dtype=torch.float32, device=dev)
+            _need(dimg, 3 * npx, "dimg", device=dev)
+        rc = self.lib.gs_ssim(self.h, ca, V, _p(img), _p(ref), _p(weights), _p(out), _p(dimg), _p(ws), nbytes,
+                              _stream())
+        self._check(rc)
+        return out, dimg
+
     def _bin(self, bin):
         """Resolve (0, 0) to the context's bin choice (kept in Python too, so
         the state can be sized before the call)."""
@@ -391,6 +422,30 @@ def render(g: Gaussians, cams, poses: torch.Tensor, pose_tangent: Optional[torch
                             poses.detach().reshape(len(cams), 16).contiguous(), ctx, cams, g.sh_degree, tuple(tile))
 
 
+class SSIMLossFn(torch.autograd.Function):
+    """Per-view SSIM loss 1 - SSIM_v of a planar colour render against a
+    fixed reference (mapping loss, Sec. 3.4); differentiable in the render."""
+
+    @staticmethod
+    def forward(ctx, img, ref, gs_ctx, cams):
+        s, _ = gs_ctx.ssim(cams, img.detach(), ref)
+        ctx.save_for_backward(img, ref)
+        ctx.gs_ctx, ctx.cams = gs_ctx, cams
+        return 1.0 - s
+
+    @staticmethod
+    def backward(ctx, go):
+        img, ref = ctx.saved_tensors
+        _, d = ctx.gs_ctx.ssim(ctx.cams, img.detach(), ref, weights=go.contiguous())
+        return d, None, None, None
+
+
+def ssim_loss(img: torch.Tensor, ref: torch.Tensor, cams, ctx: Optional[Context] = None) -> torch.Tensor:
+    """[V] tensor of 1 - SSIM per view (see gs_ssim for the definition)."""
+    cams = as_cameras(cams)
+    return SSIMLossFn.apply(img, ref.detach(), ctx or default_context(), cams)
+
+
 # ---------------------------------------------------------------------------
 # mapping / pose-refinement step
 # ---------------------------------------------------------------------------
@@ -418,6 +473,7 @@ class StepOptions:
     adam_eps: float = 1e-8
     tile: Tuple[int, int] = (0, 0)
     bin: Tuple[int, int] = (0, 0)
+    w_ssim: float = 0.0
 
     def struct(self, capacity: int, bin=None) -> A.gs_step_opts:
         b = self.bin if bin is None else bin
@@ -425,12 +481,19 @@ class StepOptions:
                               self.gate_gamma, int(self.update_gaussians), int(self.update_poses),
                               int(self.accumulate_grads), int(self.use_graph), self.lr_means, self.lr_log_scales,
                               self.lr_quats, self.lr_opacity, self.lr_colors, self.lr_pose, self.adam_b1,
-                              self.adam_b2, self.adam_eps, self.tile[0], self.tile[1], b[0], b[1], capacity)
+                              self.adam_b2, self.adam_eps, self.tile[0], self.tile[1], b[0], b[1], capacity,
+                              self.w_ssim)
 
 
 # the paper's Fusion Bridge weights (Supplementary, hyper-parameter table):
 # re-projection w1 = 1.5, colour w2 = 0.5, depth w3 = 1, border gate gamma = 0.99
 PAPER_FUSION_BRIDGE = dict(w_reproj=1.5, w_color=0.5, w_depth=1.0, use_gate=True, gate_gamma=0.99)
+
+# the paper's mapping loss (Sec. 3.4; hyper-parameter table): zeta = 0.3, depth
+# w4 = 0.5, colour w5 = 1:  (1 - zeta)(w4 L1_D + w5 L1_C) + zeta L_SSIM, the pose
+# held fixed
+PAPER_MAPPING = dict(w_color=(1 - 0.3) * 1.0, w_depth=(1 - 0.3) * 0.5, w_reproj=0.0, w_ssim=0.3,
+                     update_gaussians=True, update_poses=False)
 
 
 class MappingStep:
@@ -486,7 +549,7 @@ class MappingStep:
         self.color = torch.empty(3 * npix, dtype=torch.float32, device=dev)
         self.depth = torch.empty(npix, dtype=torch.float32, device=dev)
         self.alpha = torch.empty(npix, dtype=torch.float32, device=dev)
-        self.loss = torch.zeros(1 + 3 * self.V, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1 + 4 * self.V, dtype=torch.float32, device=dev)
         self.dpose = torch.zeros(self.V, 6, dtype=torch.float32, device=dev)
         self._build_structs()
 

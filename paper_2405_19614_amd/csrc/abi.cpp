@@ -117,7 +117,7 @@ int build_vt(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int tw, int
     vt.bh = bh;
     vt.ppt = ppt_of(c, tw, th);
     vt.n = (int)n;
-    int64_t toff = 0, poff = 0, boff = 0;
+    int64_t toff = 0, poff = 0, boff = 0, soff = 0;
     for (int v = 0; v < V; v++) {
         const gs_camera& cm = cams[v];
         if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
@@ -135,18 +135,21 @@ int build_vt(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int tw, int
         vi.bins_y = (int)ceil_div(cm.height, bh);
         vi.bin_off = (int)boff;
         vi.pix_off = (int)poff;
+        vi.ssim_off = (int)soff;
         vi.fx = cm.fx; vi.fy = cm.fy; vi.cx = cm.cx; vi.cy = cm.cy;
         const double np = (double)cm.width * cm.height;
         vi.lsc = (float)((double)wc / ((double)V * 3.0 * np));
         vi.lsd = (float)((double)wd / ((double)V * np));
         toff += (int64_t)vi.tiles_x * vi.tiles_y;
         boff += (int64_t)vi.bins_x * vi.bins_y;
+        soff += ceil_div(cm.width, gs::kSsimTW) * ceil_div(cm.height, gs::kSsimTH);
         poff += (int64_t)cm.width * cm.height;
         if (3 * poff >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "too many pixels in total");
     }
     vt.n_tiles = (int)toff;
     vt.n_bins = (int)boff;
     vt.n_pix = (int)poff;
+    vt.n_ssim_tiles = (int)soff;
     return GS_OK;
 }
 
@@ -201,6 +204,8 @@ struct Ptrs {
     double2* tilepart;
     double* rpacc;
     gs::TileSched ts;
+    float* ssim_part;
+    double* ssim_tiles;
 };
 
 Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
@@ -223,6 +228,8 @@ Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     p.dD = workspace ? reinterpret_cast<float*>(base + L.off_dD) : nullptr;
     p.tilepart = workspace ? reinterpret_cast<double2*>(base + L.off_tilepart) : nullptr;
     p.rpacc = workspace ? reinterpret_cast<double*>(base + L.off_rpacc) : nullptr;
+    p.ssim_part = workspace ? reinterpret_cast<float*>(base + L.off_ssim_part) : nullptr;
+    p.ssim_tiles = workspace ? reinterpret_cast<double*>(base + L.off_ssim_tiles) : nullptr;
     return p;
 }
 
@@ -307,6 +314,8 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
         L.off_dD = take((size_t)vt.n_pix * 4);
         L.off_tilepart = take((size_t)tb * 16);
         L.off_rpacc = take((size_t)vt.V * 8 * 8);
+        L.off_ssim_part = take((size_t)vt.n_pix * 9 * 4);
+        L.off_ssim_tiles = take((size_t)vt.n_ssim_tiles * 8);
     }
     L.bytes = o;
     return L;
@@ -511,12 +520,39 @@ int gs_reproj_residual(gs_ctx* c, const gs_camera* cams, const float* poses, int
     return GS_OK;
 }
 
+size_t gs_ssim_workspace_bytes(const gs_camera* cams, int32_t V) {
+    gs::ViewTable vt;
+    if (build_vt(nullptr, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt) != GS_OK) return 0;
+    return align_up((size_t)vt.n_pix * 9 * 4) + (size_t)vt.n_ssim_tiles * 8;
+}
+
+int gs_ssim(gs_ctx* c, const gs_camera* cams, int32_t V, const float* img, const float* ref, const float* weights,
+            float* ssim_out, float* dL_dimg, void* ws, size_t ws_bytes, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!img || !ref || !ssim_out || !ws) return fail(c, GS_EINVAL, "a device pointer is NULL");
+    if (weights && !dL_dimg) return fail(c, GS_EINVAL, "weights given without dL_dimg");
+    gs::ViewTable vt;
+    int r = build_vt(c, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt);
+    if (r) return r;
+    const size_t part_bytes = align_up((size_t)vt.n_pix * 9 * 4);
+    const size_t need = part_bytes + (size_t)vt.n_ssim_tiles * 8;
+    if (ws_bytes < need) return fail(c, GS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* part = static_cast<float*>(ws);
+    double* tiles = reinterpret_cast<double*>(static_cast<char*>(ws) + part_bytes);
+    GS_HIP(c, gs::launch_ssim_fwd(vt, img, ref, part, tiles, s));
+    GS_HIP(c, gs::launch_ssim_reduce(vt, tiles, ssim_out, s));
+    if (weights) GS_HIP(c, gs::launch_ssim_bwd(vt, img, ref, part, weights, 0.f, dL_dimg, s));
+    return GS_OK;
+}
+
 namespace {
 
 // Stages of one step, timed by gs_step_profile.
-const char* const kStageNames[] = {"preprocess_fwd", "binning", "composite_fwd", "loss_reproj", "composite_bwd",
-                                   "preprocess_bwd", "optimizer"};
-constexpr int kNumStages = 7;
+const char* const kStageNames[] = {"preprocess_fwd", "binning",        "composite_fwd", "ssim",
+                                   "loss_reproj",    "composite_bwd",  "preprocess_bwd", "optimizer"};
+constexpr int kNumStages = 8;
 
 int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::Layout& L, char* base, gs_gaussians* g,
                  gs_gaussian_grads* grads, const gs_adam* adam, float* poses, const gs_targets* tg,
@@ -537,21 +573,28 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::Layout& L, char* 
     GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, p.ts, s,
                                        counts));
     GS_HIP(c, mark(3));
+    // SSIM term of the mapping loss: its gradient joins the L1 upstream gradient in dC
+    const bool ssim = o->w_ssim > 0.f;
+    if (ssim) {
+        GS_HIP(c, gs::launch_ssim_fwd(vt, color, tg->color, p.ssim_part, p.ssim_tiles, s));
+        GS_HIP(c, gs::launch_ssim_bwd(vt, color, tg->color, p.ssim_part, nullptr, o->w_ssim / (float)vt.V, p.dC, s));
+    }
+    GS_HIP(c, mark(4));
     const bool rp = mt && mt->M > 0;
     GS_HIP(c, gs::launch_zero_f64(p.rpacc, 8 * vt.V, s));
     if (rp)
         GS_HIP(c, gs::launch_reproj(vt, poses, mt->points, mt->uv, mt->view_idx, mt->M, o->huber_delta, nullptr,
                                     p.rpacc, s));
-    GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, o->w_color, o->w_depth, o->w_reproj,
-                                     loss_out, s));
-    GS_HIP(c, mark(4));
-    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, s));
+    GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, ssim ? p.ssim_tiles : nullptr,
+                                     o->w_color, o->w_depth, o->w_reproj, o->w_ssim, loss_out, s));
     GS_HIP(c, mark(5));
+    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, s));
+    GS_HIP(c, mark(6));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, o->accumulate_grads, p.posepart, L.pose_blocks,
                                         s));
     GS_HIP(c, gs::launch_pose_finalize(vt, p.posepart, L.pose_blocks, rp ? p.rpacc : nullptr,
                                        o->w_reproj / (float)vt.V, dL_dpose, s));
-    GS_HIP(c, mark(6));
+    GS_HIP(c, mark(7));
     if (o->update_gaussians || o->update_poses) {
         const int64_t n = g->n;
         const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
@@ -575,7 +618,7 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::Layout& L, char* 
                                              o->lr_pose, o->adam_b1, o->adam_b2, o->adam_eps, 0, s));
         GS_HIP(c, gs::launch_step_bump(adam->step, s));
     }
-    GS_HIP(c, mark(7));
+    GS_HIP(c, mark(8));
     return GS_OK;
 }
 
@@ -605,6 +648,7 @@ int check_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_ad
         return fail(c, GS_EINVAL, "an update needs the Adam state");
     if (o->pair_capacity < 0 || o->pair_capacity >= ((int64_t)1 << 31))
         return fail(c, GS_EINVAL, "pair_capacity outside [0, 2^31)");
+    if (!(o->w_ssim >= 0.f) || !std::isfinite(o->w_ssim)) return fail(c, GS_EINVAL, "w_ssim must be finite and >= 0");
     int tw, th, bw, bh;
     resolve_tile(c, o->tile_w, o->tile_h, tw, th);
     resolve_bin(c, o->bin_w, o->bin_h, bw, bh);

@@ -19,6 +19,10 @@ constexpr float kTMin = 1e-4f;
 constexpr float kDilate = 0.3f;
 constexpr float kJClamp = 1.3f;
 
+// SSIM term of the mapping loss: outputs per workgroup of the SSIM kernels
+constexpr int kSsimTW = 32;
+constexpr int kSsimTH = 16;
+
 // Per-view constants, passed by value in every launch (no upload, graph safe).
 struct ViewInfo {
     int W, H;
@@ -27,6 +31,7 @@ struct ViewInfo {
     int bins_x, bins_y;
     int bin_off;    // global id of this view's first bin
     int pix_off;    // first pixel of this view in the concatenated images
+    int ssim_off;   // global id of this view's first SSIM tile
     float fx, fy, cx, cy;
     float lsc;      // dL/dC scale: w_color / (V * 3 * H * W)
     float lsd;      // dL/dD scale: w_depth / (V * H * W)
@@ -43,6 +48,7 @@ struct ViewTable {
     int n_bins;
     int n_tiles;
     int n_pix;
+    int n_ssim_tiles;
     int n;          // Gaussians
     ViewInfo v[kMaxViews];
 };
@@ -106,6 +112,8 @@ struct Layout {
     size_t off_dC, off_dD;                        // upstream gradients
     size_t off_tilepart;                          // tile partials (sized for the smallest tile)
     size_t off_rpacc;                             // V * 8 doubles
+    size_t off_ssim_part;                         // 9 * n_pix floats (SSIM partials)
+    size_t off_ssim_tiles;                        // n_ssim_tiles doubles
     size_t bytes;
     int64_t pose_blocks;
 };
@@ -177,8 +185,24 @@ hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const 
                                 const float* tfin, const uint32_t* last, const float* dC, const float* dD,
                                 const float* dA, float* g2, const TileSched& ts, hipStream_t s);
 
-hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc, float w_color,
-                              float w_depth, float w_reproj, float* loss_out, hipStream_t s);
+// loss_out [1 + 4V]: total, then (Lc, Ld, Lr, Ls) per view; ssim_part (nullable)
+// holds per-SSIM-tile sums of the SSIM map over the tile's pixels and channels
+hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc,
+                              const double* ssim_part, float w_color, float w_depth, float w_reproj, float w_ssim,
+                              float* loss_out, hipStream_t s);
+
+// SSIM (mapping loss, Sec. 3.4) of planar colour images img against ref.
+// part: device float [9 * n_pix] scratch (per pixel and channel: the SSIM map's
+// partials with respect to the window means of x, x^2 and xy); tile_sum:
+// device double [n_ssim_tiles].  The forward fills both; the backward adds
+// -w_v / (3 H W) * d(sum of the view's SSIM map)/d img into dimg, with w_v =
+// wdev[v] if wdev is not null, else wconst.
+hipError_t launch_ssim_fwd(const ViewTable& vt, const float* img, const float* ref, float* part, double* tile_sum,
+                           hipStream_t s);
+hipError_t launch_ssim_bwd(const ViewTable& vt, const float* img, const float* ref, const float* part,
+                           const float* wdev, float wconst, float* dimg, hipStream_t s);
+// per-view mean SSIM from the tile sums
+hipError_t launch_ssim_reduce(const ViewTable& vt, const double* tile_sum, float* ssim_out, hipStream_t s);
 hipError_t launch_reproj(const ViewTable& vt, const float* poses, const float* pts, const float* uv,
                          const int32_t* vid, int64_t M, float delta, float* residual, double* acc, hipStream_t s);
 hipError_t launch_reproj_finalize(const ViewTable& vt, const double* acc, float weight, float* loss,

@@ -118,25 +118,32 @@ __global__ void reproj_finalize_kernel(int V, const double* acc, float weight, f
 }
 
 __global__ __launch_bounds__(256) void loss_reduce_kernel(ViewTable vt, const double2* part, const double* rp,
-                                                          float wc, float wd, float wr, float* out) {
-    __shared__ double red[256][2];
+                                                          const double* ssim_part, float wc, float wd, float wr,
+                                                          float wsm, float* out) {
+    __shared__ double red[256][3];
     double total = 0.0;
     for (int v = 0; v < vt.V; v++) {
         const ViewInfo& vi = vt.v[v];
         const int nt = vi.tiles_x * vi.tiles_y;
-        double a = 0.0, b = 0.0;
+        double a = 0.0, b = 0.0, c = 0.0;
         for (int i = threadIdx.x; i < nt; i += 256) {
             const double2 p = part[vi.tile_off + i];
             a += p.x;
             b += p.y;
         }
+        if (ssim_part) {
+            const int ns = ((vi.W + kSsimTW - 1) / kSsimTW) * ((vi.H + kSsimTH - 1) / kSsimTH);
+            for (int i = threadIdx.x; i < ns; i += 256) c += ssim_part[vi.ssim_off + i];
+        }
         red[threadIdx.x][0] = a;
         red[threadIdx.x][1] = b;
+        red[threadIdx.x][2] = c;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
             if ((int)threadIdx.x < s) {
                 red[threadIdx.x][0] += red[threadIdx.x + s][0];
                 red[threadIdx.x][1] += red[threadIdx.x + s][1];
+                red[threadIdx.x][2] += red[threadIdx.x + s][2];
             }
             __syncthreads();
         }
@@ -144,12 +151,14 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(ViewTable vt, const do
             const double npx = (double)vi.W * vi.H;
             const double lc = red[0][0] / (3.0 * npx);
             const double ld = red[0][1] / npx;
+            const double ls = ssim_part ? 1.0 - red[0][2] / (3.0 * npx) : 0.0;
             double lr = 0.0;
             if (rp && rp[8 * v + 1] > 0) lr = rp[8 * v] / rp[8 * v + 1];
-            out[1 + 3 * v] = (float)lc;
-            out[2 + 3 * v] = (float)ld;
-            out[3 + 3 * v] = (float)lr;
-            total += (double)wc * lc + (double)wd * ld + (double)wr * lr;
+            out[1 + 4 * v] = (float)lc;
+            out[2 + 4 * v] = (float)ld;
+            out[3 + 4 * v] = (float)lr;
+            out[4 + 4 * v] = (float)ls;
+            total += (double)wc * lc + (double)wd * ld + (double)wr * lr + (double)wsm * ls;
         }
         __syncthreads();
     }
@@ -253,9 +262,10 @@ hipError_t launch_reproj_finalize(const ViewTable& vt, const double* acc, float 
     return hipGetLastError();
 }
 
-hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc, float w_color,
-                              float w_depth, float w_reproj, float* loss_out, hipStream_t s) {
-    loss_reduce_kernel<<<1, 256, 0, s>>>(vt, tile_part, rp_acc, w_color, w_depth, w_reproj, loss_out);
+hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc,
+                              const double* ssim_part, float w_color, float w_depth, float w_reproj, float w_ssim,
+                              float* loss_out, hipStream_t s) {
+    loss_reduce_kernel<<<1, 256, 0, s>>>(vt, tile_part, rp_acc, ssim_part, w_color, w_depth, w_reproj, w_ssim, loss_out);
     return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ def test_python_binding_names_every_export(lib):
 
 
 def test_abi_version(lib):
-    assert lib.gs_abi_version() == 1
+    assert lib.gs_abi_version() == 2
 
 
 def test_null_context_rejected_without_device_work(lib):
@@ -85,6 +85,28 @@ def test_bin_shapes_accepted(lib):
         assert lib.gs_state_bytes(cams, 1, 10, 10, bw, bh) > 0
     for bw, bh in [(4, 8), (8, 12), (4096, 8)]:
         assert lib.gs_state_bytes(cams, 1, 10, 10, bw, bh) == 0
+
+
+def test_ssim_workspace_sizing(lib):
+    from paper_2405_19614_amd import _abi as A
+    cams = (A.gs_camera * 2)(A.gs_camera(64, 48, 60, 60, 32, 24), A.gs_camera(33, 17, 60, 60, 16, 8))
+    npx = 64 * 48 + 33 * 17
+    tiles = 2 * 3 + 2 * 2   # 32 x 16 SSIM tiles per view
+    b = lib.gs_ssim_workspace_bytes(cams, 2)
+    assert b >= 9 * 4 * npx + 8 * tiles
+    assert lib.gs_ssim_workspace_bytes(cams, 0) == 0
+    assert lib.gs_ssim(None, cams, 2, None, None, None, None, None, None, 0, None) == A.GS_EINVAL
+
+
+def test_paper_mapping_preset_matches_table():
+    """The mapping preset is the paper's (1 - zeta)(w4 L1_D + w5 L1_C) + zeta L_SSIM."""
+    import json
+    from paper_2405_19614_amd.binding import PAPER_MAPPING
+    hp = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_hyperparams.json")))["values"]
+    z = hp["zeta"]
+    assert abs(PAPER_MAPPING["w_ssim"] - z) < 1e-12
+    assert abs(PAPER_MAPPING["w_color"] - (1 - z) * hp["w5"]) < 1e-12
+    assert abs(PAPER_MAPPING["w_depth"] - (1 - z) * hp["w4"]) < 1e-12
 
 
 def test_paper_preset_matches_table():

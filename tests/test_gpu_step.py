@@ -78,9 +78,10 @@ def test_step_loss_and_gradients_match_oracle(ctx, use_gate):
     loss = st.loss.cpu().numpy().astype(np.float64)
     print(f"  loss gpu={loss[0]:.8f} oracle={total:.8f}")
     assert abs(loss[0] - total) <= 1e-5 * abs(total)
-    np.testing.assert_allclose(loss[1::3], Lc, rtol=1e-4)
-    np.testing.assert_allclose(loss[2::3], Ld, rtol=1e-4, atol=1e-7)
-    np.testing.assert_allclose(loss[3::3], Lr, rtol=1e-4)
+    np.testing.assert_allclose(loss[1::4], Lc, rtol=1e-4)
+    np.testing.assert_allclose(loss[2::4], Ld, rtol=1e-4, atol=1e-7)
+    np.testing.assert_allclose(loss[3::4], Lr, rtol=1e-4)
+    assert np.all(loss[4::4] == 0.0)   # no SSIM term requested
     for nm in GRAD_NAMES:
         e = rel(getattr(st.grads, nm).cpu().numpy(), rg[nm])
         print(f"  {nm}: rel {e:.2e}")
