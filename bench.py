@@ -221,6 +221,16 @@ def main():
     iters = 1000.0 / ms_map
     log(f"[bench] mapping step: {ms_map:.3f} ms -> {iters:.2f} it/s")
 
+    # the paper's mapping loss: (1 - zeta)(w4 L1_D + w5 L1_C) + zeta L_SSIM, Adam on the Gaussians
+    gp = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
+    popts = dict(base)
+    popts.update(gs.PAPER_MAPPING)
+    stp = gs.MappingStep(ctx, gp, s.cams, poses.clone(), tc, td, gs.StepOptions(**popts), capacity=st.capacity)
+    ms_paper, _ = timed_steps([stp], args.steps, args.warmup)
+    t_paper, _ = stp.profile(counts=False)
+    log(f"[bench] paper mapping loss (with SSIM): {ms_paper:.3f} ms -> {1000.0 / ms_paper:.2f} it/s; "
+        f"ssim stage {t_paper.get('ssim', 0.0):.4f} ms")
+
     # per-view: the same kernels, V = 1 per launch sequence, V sequences per step
     per_view = None
     if not args.no_per_view:
@@ -282,6 +292,8 @@ def main():
                    "pixels_per_step": npix, "tile": f"{tile[0]}x{tile[1]}", "bin": f"{binsz[0]}x{binsz[1]}"},
         "mapping_iters_per_s": round(iters, 3),
         "ms_per_mapping_iter": round(ms_map, 4),
+        "paper_mapping_loss_iters_per_s": round(1000.0 / ms_paper, 3),
+        "ssim_stage_ms": round(t_paper.get("ssim", 0.0), 4),
         "per_view_mpx_s": None if per_view is None else round(per_view, 2),
         "batched_over_per_view": None if per_view is None else round(mpx / per_view, 3),
         "ms_per_step_median_events": round(ms_med, 4),

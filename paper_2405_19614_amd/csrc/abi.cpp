@@ -315,7 +315,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
         L.off_tilepart = take((size_t)tb * 16);
         L.off_rpacc = take((size_t)vt.V * 8 * 8);
         L.off_ssim_part = take((size_t)vt.n_pix * 9 * 4);
-        L.off_ssim_tiles = take((size_t)vt.n_ssim_tiles * 8);
+        L.off_ssim_tiles = take((size_t)vt.n_ssim_tiles * 3 * 8);
     }
     L.bytes = o;
     return L;
@@ -523,7 +523,7 @@ int gs_reproj_residual(gs_ctx* c, const gs_camera* cams, const float* poses, int
 size_t gs_ssim_workspace_bytes(const gs_camera* cams, int32_t V) {
     gs::ViewTable vt;
     if (build_vt(nullptr, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt) != GS_OK) return 0;
-    return align_up((size_t)vt.n_pix * 9 * 4) + (size_t)vt.n_ssim_tiles * 8;
+    return align_up((size_t)vt.n_pix * 9 * 4) + (size_t)vt.n_ssim_tiles * 3 * 8;
 }
 
 int gs_ssim(gs_ctx* c, const gs_camera* cams, int32_t V, const float* img, const float* ref, const float* weights,
@@ -535,7 +535,7 @@ int gs_ssim(gs_ctx* c, const gs_camera* cams, int32_t V, const float* img, const
     int r = build_vt(c, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt);
     if (r) return r;
     const size_t part_bytes = align_up((size_t)vt.n_pix * 9 * 4);
-    const size_t need = part_bytes + (size_t)vt.n_ssim_tiles * 8;
+    const size_t need = part_bytes + (size_t)vt.n_ssim_tiles * 3 * 8;
     if (ws_bytes < need) return fail(c, GS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -113,7 +113,7 @@ struct Layout {
     size_t off_tilepart;                          // tile partials (sized for the smallest tile)
     size_t off_rpacc;                             // V * 8 doubles
     size_t off_ssim_part;                         // 9 * n_pix floats (SSIM partials)
-    size_t off_ssim_tiles;                        // n_ssim_tiles doubles
+    size_t off_ssim_tiles;                        // 3 * n_ssim_tiles doubles
     size_t bytes;
     int64_t pose_blocks;
 };
@@ -186,7 +186,7 @@ hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const 
                                 const float* dA, float* g2, const TileSched& ts, hipStream_t s);
 
 // loss_out [1 + 4V]: total, then (Lc, Ld, Lr, Ls) per view; ssim_part (nullable)
-// holds per-SSIM-tile sums of the SSIM map over the tile's pixels and channels
+// holds per-(channel, SSIM tile) sums of the SSIM map, channel-major
 hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc,
                               const double* ssim_part, float w_color, float w_depth, float w_reproj, float w_ssim,
                               float* loss_out, hipStream_t s);
@@ -194,7 +194,7 @@ hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, con
 // SSIM (mapping loss, Sec. 3.4) of planar colour images img against ref.
 // part: device float [9 * n_pix] scratch (per pixel and channel: the SSIM map's
 // partials with respect to the window means of x, x^2 and xy); tile_sum:
-// device double [n_ssim_tiles].  The forward fills both; the backward adds
+// device double [3 * n_ssim_tiles] (channel-major).  The forward fills both; the backward adds
 // -w_v / (3 H W) * d(sum of the view's SSIM map)/d img into dimg, with w_v =
 // wdev[v] if wdev is not null, else wconst.
 hipError_t launch_ssim_fwd(const ViewTable& vt, const float* img, const float* ref, float* part, double* tile_sum,

@@ -133,7 +133,10 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(ViewTable vt, const do
         }
         if (ssim_part) {
             const int ns = ((vi.W + kSsimTW - 1) / kSsimTW) * ((vi.H + kSsimTH - 1) / kSsimTH);
-            for (int i = threadIdx.x; i < ns; i += 256) c += ssim_part[vi.ssim_off + i];
+            for (int i = threadIdx.x; i < 3 * ns; i += 256) {
+                const int k = i / ns;
+                c += ssim_part[(int64_t)k * vt.n_ssim_tiles + vi.ssim_off + (i - k * ns)];
+            }
         }
         red[threadIdx.x][0] = a;
         red[threadIdx.x][1] = b;

@@ -93,7 +93,7 @@ def test_ssim_workspace_sizing(lib):
     npx = 64 * 48 + 33 * 17
     tiles = 2 * 3 + 2 * 2   # 32 x 16 SSIM tiles per view
     b = lib.gs_ssim_workspace_bytes(cams, 2)
-    assert b >= 9 * 4 * npx + 8 * tiles
+    assert b >= 9 * 4 * npx + 3 * 8 * tiles
     assert lib.gs_ssim_workspace_bytes(cams, 0) == 0
     assert lib.gs_ssim(None, cams, 2, None, None, None, None, None, None, 0, None) == A.GS_EINVAL
 
