@@ -4,11 +4,13 @@ LDS-staged front-to-back compositing, its recomputing backward, the Huber
 re-projection residual and a graph-captured mapping / pose-refinement step,
 the SSIM term of the mapping loss, behind the C ABI in include/gs.h.
 """
-from .binding import (Camera, Context, GSError, GSRenderFn, Gaussians, MappingStep, PAPER_FUSION_BRIDGE,
+from .binding import (Camera, Context, GSError, GSRenderFn, Gaussians, JointRefinement, MappingStep,
+                      PAPER_FUSION_BRIDGE,
                       PAPER_MAPPING, SSIMLossFn, StepOptions, as_cameras, default_context, render, sh_coeffs,
                       split_images, ssim_loss)
 from . import _abi
 
-__all__ = ["Camera", "Context", "GSError", "GSRenderFn", "Gaussians", "MappingStep", "PAPER_FUSION_BRIDGE",
+__all__ = ["Camera", "Context", "GSError", "GSRenderFn", "Gaussians", "JointRefinement", "MappingStep",
+           "PAPER_FUSION_BRIDGE",
            "PAPER_MAPPING", "SSIMLossFn", "StepOptions", "as_cameras", "default_context", "render", "sh_coeffs",
            "split_images", "ssim_loss", "_abi"]

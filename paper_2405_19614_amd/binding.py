@@ -601,3 +601,31 @@ class MappingStep:
                                          ctypes.byref(npairs), ctypes.byref(nvis), _stream())
         self.ctx._check(rc)
         return {"flags": int(fl.value), "n_pairs": int(npairs.value), "n_visible": int(nvis.value)}
+
+
+class JointRefinement:
+    """The alternating optimisation of the paper on one ``MappingStep``: k_pose
+    pose-refinement iterations with the Fusion Bridge loss (re-projection +
+    rendering terms, filter gate; Sec. 3.3, Gaussians held fixed), then k_map
+    mapping iterations with the mapping loss (Sec. 3.4, poses held fixed).
+    Both phases share the step's buffers and Adam state (pose and Gaussian
+    moments live in separate slots; the bias-correction counter is shared);
+    each phase's step is captured as its own hipGraph."""
+
+    def __init__(self, step: "MappingStep", pose_opts: Optional[StepOptions] = None,
+                 map_opts: Optional[StepOptions] = None):
+        from dataclasses import replace
+        base = step.opts
+        self.step = step
+        self.pose_opts = pose_opts or replace(base, **PAPER_FUSION_BRIDGE, w_ssim=0.0, update_poses=True,
+                                              update_gaussians=False)
+        self.map_opts = map_opts or replace(base, **PAPER_MAPPING)
+
+    def __call__(self, k_pose: int, k_map: int):
+        self.step.set_options(self.pose_opts)
+        for _ in range(k_pose):
+            self.step()
+        self.step.set_options(self.map_opts)
+        for _ in range(k_map):
+            self.step()
+

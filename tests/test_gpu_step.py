@@ -218,3 +218,40 @@ def test_pose_gradient_vs_gpu_finite_differences(ctx):
         worst = max(worst, e)
     st.poses.copy_(P0)
     assert worst < 2e-2, worst
+
+
+def _pose_error(T, T_true):
+    """(rotation angle in rad, translation distance) between two world-to-camera poses."""
+    D = np.asarray(T, np.float64).reshape(4, 4) @ np.linalg.inv(np.asarray(T_true, np.float64).reshape(4, 4))
+    ang = float(np.arccos(np.clip((np.trace(D[:3, :3]) - 1.0) / 2.0, -1.0, 1.0)))
+    return ang, float(np.linalg.norm(D[:3, 3]))
+
+
+def test_alternating_joint_refinement_converges(ctx):
+    """Alternating Fusion-Bridge pose refinement (the paper's w1..w3 and gate)
+    and mapping (the paper's mapping loss with SSIM) from perturbed poses:
+    the pose error to the true poses and the Fusion Bridge loss both fall."""
+    import paper_2405_19614_amd as gs
+    s = C4
+    tc, td = _targets(s)
+    st = _step(ctx, s, tc, td, gs.StepOptions(lr_pose=2e-3, use_graph=True))
+    jr = gs.JointRefinement(st)
+    err0 = [_pose_error(st.poses[v].cpu().numpy(), s.poses_true[v]) for v in range(s.V)]
+    st.set_options(jr.pose_opts)
+    st()
+    torch.cuda.synchronize()
+    loss0 = float(st.loss[0].item())
+    for _ in range(6):
+        jr(10, 3)
+    st.set_options(jr.pose_opts)
+    st()
+    torch.cuda.synchronize()
+    loss1 = float(st.loss[0].item())
+    err1 = [_pose_error(st.poses[v].cpu().numpy(), s.poses_true[v]) for v in range(s.V)]
+    r0, t0 = np.mean([e[0] for e in err0]), np.mean([e[1] for e in err0])
+    r1, t1 = np.mean([e[0] for e in err1]), np.mean([e[1] for e in err1])
+    print(f"  rotation {r0:.4f} -> {r1:.4f} rad, translation {t0:.4f} -> {t1:.4f}, loss {loss0:.5f} -> {loss1:.5f}",
+          flush=True)
+    assert st.status()["flags"] == 0
+    assert loss1 < loss0
+    assert t1 < 0.7 * t0 and r1 < r0
