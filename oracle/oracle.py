@@ -15,6 +15,8 @@ of numpy:
   filter gate of Sec. 3.3 (gate equation);
 * the SSIM term of the mapping loss (Sec. 3.4, mapping-loss equation) on the
   RGB render, with its gradient;
+* Gaussian pruning and densification (Sec. 3.4), with the re-layout of the
+  Adam moments they imply;
 * SE(3) exponential for the left-perturbation pose tangent xi = (v, w);
 * Adam (the paper says only "gradient-based optimization", Sec. 3.4).
 """
@@ -408,6 +410,99 @@ def ssim_views(cams, img, ref, weights=None):
         S[v] = tot / (3.0 * P)
         o += 3 * P
     return S, dimg
+
+
+# ---------------------------------------------------------------------------
+# Map maintenance: pruning and densification (Sec. 3.4)
+# ---------------------------------------------------------------------------
+# Readings.  Pruning (Sec. 3.4 pruning equation; the printed cases and the
+# text disagree on which side is removed): a Gaussian is removed when its
+# opacity o = sigmoid(logit) < tau, the order of the others is kept.
+# Densification: every pixel of a view whose rendered alpha (the border mask
+# M_b) is <= gamma -- every pixel on the first frame -- and whose target depth
+# d is > 0 gets one new Gaussian: its mean back-projects the pixel's sample
+# point (x, y) to depth d, it is isotropic with radius d / fx (a one-pixel
+# footprint, Eq. d read as r = d / f), identity rotation, opacity 1/2 (logit
+# 0; the paper gives no initial value), and the target colour (with SH, the
+# DC coefficient reproduces it and the others are 0).  New Gaussians follow
+# the existing ones, in view order, then row-major pixel order.
+
+SH_C0 = 0.28209479177387814   # Y_00 of the real orthonormal basis
+
+
+def prune(params: Dict[str, np.ndarray], tau: float):
+    """params: dict of arrays with the Gaussian index first.  Returns (kept
+    params, kept indices)."""
+    opl = _d(params["opacity_logits"]).reshape(-1)
+    o = 1.0 / (1.0 + np.exp(-opl))
+    keep = np.nonzero(~(o < tau))[0]
+    return {k: np.asarray(v)[keep] for k, v in params.items()}, keep
+
+
+def densify(cams, poses, alpha, tgt_color, tgt_depth, gamma: float, all_pixels: bool, sh_degree: int = -1):
+    """New Gaussians (dict of FP64 arrays: means [m,3], log_scales [m,3],
+    quats [m,4], opacity_logits [m], colors [m,3] or [m,K,3]) and, for each,
+    its (view, x, y)."""
+    K = 1 if sh_degree < 0 else (sh_degree + 1) ** 2
+    means, ls, cols, where = [], [], [], []
+    po = 0
+    for v, c in enumerate(cams):
+        P = c.width * c.height
+        A = _d(alpha[po:po + P]).reshape(c.height, c.width)
+        Dt = _d(tgt_depth[po:po + P]).reshape(c.height, c.width)
+        Ct = _d(tgt_color[3 * po:3 * po + 3 * P]).reshape(3, c.height, c.width)
+        T = _d(poses[v]).reshape(4, 4)
+        R, t = T[:3, :3], T[:3, 3]
+        for y in range(c.height):
+            for x in range(c.width):
+                d = Dt[y, x]
+                if not (d > 0.0) or not (all_pixels or A[y, x] <= gamma):
+                    continue
+                pc = np.array([(x - c.cx) / c.fx * d, (y - c.cy) / c.fy * d, d])
+                means.append(R.T @ (pc - t))
+                ls.append(np.full(3, np.log(d / c.fx)))
+                cols.append(Ct[:, y, x])
+                where.append((v, x, y))
+        po += P
+    m = len(means)
+    out = {"means": np.array(means).reshape(m, 3), "log_scales": np.array(ls).reshape(m, 3),
+           "quats": np.tile([1.0, 0.0, 0.0, 0.0], (m, 1)), "opacity_logits": np.zeros(m)}
+    rgb = np.array(cols).reshape(m, 3)
+    if sh_degree < 0:
+        out["colors"] = rgb
+    else:
+        sh = np.zeros((m, K, 3))
+        sh[:, 0, :] = (rgb - 0.5) / SH_C0
+        out["colors"] = sh
+    return out, np.array(where, np.int64).reshape(m, 3)
+
+
+def adam_groups(n: int, sh_degree: int, V: int):
+    """(offset, per-Gaussian width) of each parameter group in the Adam
+    moment layout, and the offset of the 6V pose moments."""
+    K = 1 if sh_degree < 0 else (sh_degree + 1) ** 2
+    widths = [3, 3, 4, 1, 3 * K]
+    offs, o = [], 0
+    for w in widths:
+        offs.append(o)
+        o += w * n
+    return list(zip(offs, widths)), o
+
+
+def adam_relayout(m: np.ndarray, n: int, sh_degree: int, V: int, src_index: np.ndarray, n_new: int):
+    """Moments of n_new Gaussians whose i-th comes from old Gaussian
+    src_index[i] (or is new with zero moments when src_index[i] < 0); the pose
+    moments are carried over."""
+    old, pose_old = adam_groups(n, sh_degree, V)
+    new, pose_new = adam_groups(n_new, sh_degree, V)
+    out = np.zeros(pose_new + 6 * V)
+    for (oo, w), (on, _) in zip(old, new):
+        src = np.asarray(m[oo:oo + w * n]).reshape(n, w)
+        dst = out[on:on + w * n_new].reshape(n_new, w)
+        ok = src_index >= 0
+        dst[ok] = src[src_index[ok]]
+    out[pose_new:] = m[pose_old:pose_old + 6 * V]
+    return out
 
 
 # ---------------------------------------------------------------------------
