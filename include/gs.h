@@ -338,6 +338,53 @@ size_t gs_ssim_workspace_bytes(const gs_camera* cams, int32_t V);
 int gs_ssim(gs_ctx* ctx, const gs_camera* cams, int32_t V, const float* img, const float* ref, const float* weights,
             float* ssim_out, float* dL_dimg, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Map maintenance of the online reconstruction (Sec. 3.4).
+ *
+ * Pruning (Sec. 3.4 pruning equation; its printed cases and the text
+ * disagree on which side is removed, the text is followed): a Gaussian is
+ * removed when its opacity sigmoid(opacity_logit) < tau, the others keep their
+ * order.  tau <= 0 keeps every Gaussian, tau >= 1 removes every one.
+ *   in        device arrays of in->n Gaussians (sh_degree as in gs_gaussians).
+ *   out       device arrays with room for in->n Gaussians, not overlapping in;
+ *             out->n and out->sh_degree are ignored.
+ *   adam_in / adam_out  optional (both NULL or both given, not overlapping):
+ *             Adam moments laid out for in->n Gaussians and V poses (see
+ *             gs_adam) are re-laid out for the kept ones; the step counter is
+ *             copied when adam_out->step differs.
+ *   n_out     device int64: the number kept.
+ *   workspace device scratch of gs_prune_workspace_bytes(in->n) bytes.
+ * Asynchronous on `stream`; GS_EINVAL for NULL pointers, GS_ENOMEM for a
+ * short workspace. */
+size_t gs_prune_workspace_bytes(int64_t n);
+int gs_prune(gs_ctx* ctx, const gs_gaussians* in, float tau, gs_gaussians* out, const gs_adam* adam_in,
+             gs_adam* adam_out, int32_t V, int64_t* n_out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Densification (Sec. 3.4 densification, Eq. d): for every pixel of the V
+ * views whose rendered alpha (the border mask M_b) is <= gamma -- every pixel
+ * when all_pixels is set, as on the first frame -- and whose target depth d
+ * is > 0, one Gaussian is appended after the g->n existing ones, in view then
+ * row-major pixel order: mean = the pixel's sample point (x, y) back-projected
+ * to depth d through the view's pose, isotropic log-scale log(d / fx) (a
+ * one-pixel footprint), quaternion (1, 0, 0, 0), opacity logit 0, colour =
+ * the target colour (with SH, the DC coefficient (rgb - 0.5) / Y_00 and the
+ * other coefficients 0).
+ *   cams HOST [V]; poses device [V][16] world-to-camera; alpha device [sum HW]
+ *   (rendered); tgt_color device planar [3][H][W] per view; tgt_depth device [sum HW].
+ *   g         device arrays holding g->n Gaussians with room for `capacity`;
+ *             the new ones are written in place after them (none past capacity).
+ *   adam_in / adam_out  optional (both NULL or both given, not overlapping):
+ *             moments for g->n Gaussians re-laid out for the grown set (new
+ *             Gaussians start at zero); adam_out must have room for capacity.
+ *   counts    device int64[2]: Gaussians now held (<= capacity), Gaussians
+ *             the selection asked for (g->n + selected pixels).
+ *   workspace device scratch of gs_densify_workspace_bytes(cams, V) bytes.
+ * Asynchronous on `stream`. */
+size_t gs_densify_workspace_bytes(const gs_camera* cams, int32_t V);
+int gs_densify(gs_ctx* ctx, const gs_camera* cams, const float* poses, int32_t V, const float* alpha,
+               const float* tgt_color, const float* tgt_depth, float gamma, int32_t all_pixels, gs_gaussians* g,
+               int64_t capacity, const gs_adam* adam_in, gs_adam* adam_out, int64_t* counts, void* workspace,
+               size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,7 +66,8 @@ EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_sta
            "gs_render_backward", "gs_reproj_residual", "gs_step_workspace_bytes", "gs_mapping_step",
            "gs_step_status", "gs_bin_records", "gs_autotune", "gs_set_tile", "gs_num_stages", "gs_stage_name",
            "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bin",
-           "gs_ssim_workspace_bytes", "gs_ssim"]
+           "gs_ssim_workspace_bytes", "gs_ssim", "gs_prune_workspace_bytes", "gs_prune",
+           "gs_densify_workspace_bytes", "gs_densify"]
 
 _lib = None
 
@@ -113,6 +114,15 @@ def load() -> ctypes.CDLL:
     L.gs_set_tile.argtypes = [c_void_p, c_int32, c_int32]
     L.gs_set_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32, c_int32]
     L.gs_get_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32]
+    PG = ctypes.POINTER(gs_gaussians)
+    PA = ctypes.POINTER(gs_adam)
+    L.gs_prune_workspace_bytes.argtypes = [c_int64]
+    L.gs_prune_workspace_bytes.restype = c_size_t
+    L.gs_prune.argtypes = [c_void_p, PG, ctypes.c_float, PG, PA, PA, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.gs_densify_workspace_bytes.argtypes = [PC, c_int32]
+    L.gs_densify_workspace_bytes.restype = c_size_t
+    L.gs_densify.argtypes = [c_void_p, PC, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_int32,
+                             PG, c_int64, PA, PA, c_void_p, c_void_p, c_size_t, c_void_p]
     L.gs_ssim_workspace_bytes.argtypes = [PC, c_int32]
     L.gs_ssim_workspace_bytes.restype = c_size_t
     L.gs_ssim.argtypes = [c_void_p, PC, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -323,6 +323,95 @@ class Context:
         self._check(rc)
         return out, dimg
 
+    def prune(self, g: Gaussians, tau: float, adam: Optional[Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = None,
+              V: int = 0):
+        """Removes Gaussians with opacity below tau (see gs_prune).  ``adam``:
+        optional (m, v, step) moments laid out for g.n Gaussians and V poses.
+        Returns (pruned Gaussians, re-laid-out (m, v, step) or None); reads the
+        kept count back (one synchronisation)."""
+        dev = self.torch_device
+        _check_gaussians(g, dev)
+        out = Gaussians(torch.empty_like(g.means), torch.empty_like(g.log_scales), torch.empty_like(g.quats),
+                        torch.empty_like(g.opacity_logits), torch.empty_like(g.colors), g.sh_degree)
+        nbytes = int(self.lib.gs_prune_workspace_bytes(g.n))
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        nout = torch.zeros(1, dtype=torch.int64, device=dev)
+        ain = aout = None
+        if adam is not None:
+            m, v, step = adam
+            m2, v2 = torch.empty_like(m), torch.empty_like(v)
+            ain = A.gs_adam(_p(m), _p(v), _p(step))
+            aout = A.gs_adam(_p(m2), _p(v2), _p(step))
+        gi, go = g.struct(), out.struct()
+        rc = self.lib.gs_prune(self.h, ctypes.byref(gi), float(tau), ctypes.byref(go),
+                               ctypes.byref(ain) if ain is not None else None,
+                               ctypes.byref(aout) if aout is not None else None, int(V), _p(nout), _p(ws), nbytes,
+                               _stream())
+        self._check(rc)
+        k = int(nout.item())
+        K = sh_coeffs(g.sh_degree)
+        pruned = Gaussians(out.means[:k], out.log_scales[:k], out.quats[:k], out.opacity_logits[:k], out.colors[:k],
+                           g.sh_degree)
+        if adam is None:
+            return pruned, None
+        keep = k * (11 + 3 * K) + 6 * V
+        return pruned, (m2[:keep], v2[:keep], adam[2])
+
+    def densify(self, g: Gaussians, capacity: int, cams, poses: torch.Tensor, alpha: torch.Tensor,
+                tgt_color: torch.Tensor, tgt_depth: torch.Tensor, gamma: float = 0.99, all_pixels: bool = False,
+                adam: Optional[Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = None):
+        """Appends new Gaussians at under-reconstructed pixels (see
+        gs_densify).  Allocates arrays for ``capacity`` Gaussians, copies g
+        into them and appends in place.  Returns (Gaussians, (held, asked),
+        grown (m, v, step) or None); one synchronisation for the counts."""
+        cams = as_cameras(cams)
+        V = len(cams)
+        dev = self.torch_device
+        _check_gaussians(g, dev)
+        if capacity < g.n:
+            raise ValueError("capacity below the current count")
+        K = sh_coeffs(g.sh_degree)
+        cap = Gaussians(torch.empty(capacity, 3, device=dev), torch.empty(capacity, 3, device=dev),
+                        torch.empty(capacity, 4, device=dev), torch.empty(capacity, device=dev),
+                        torch.empty((capacity, 3) if g.sh_degree < 0 else (capacity, K, 3), device=dev),
+                        g.sh_degree)
+        for dst, src in zip(cap.tensors(), g.tensors()):
+            dst[:g.n].copy_(src.reshape(dst[:g.n].shape))
+        held = Gaussians(*(t for t in cap.tensors()), g.sh_degree)
+        gst = A.gs_gaussians(g.n, g.sh_degree, _p(cap.means), _p(cap.log_scales), _p(cap.quats),
+                             _p(cap.opacity_logits), _p(cap.colors))
+        ca = cam_array(cams)
+        nbytes = int(self.lib.gs_densify_workspace_bytes(ca, V))
+        if nbytes == 0:
+            raise GSError(A.GS_EINVAL, "bad cameras")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        counts = torch.zeros(2, dtype=torch.int64, device=dev)
+        ain = aout = None
+        if adam is not None:
+            m, v, step = adam
+            m2 = torch.empty(capacity * (11 + 3 * K) + 6 * V, dtype=torch.float32, device=dev)
+            v2 = torch.empty_like(m2)
+            ain = A.gs_adam(_p(m), _p(v), _p(step))
+            aout = A.gs_adam(_p(m2), _p(v2), _p(step))
+        npx = sum(c.npix for c in cams)
+        _need(alpha.contiguous(), npx, "alpha", device=dev)
+        _need(tgt_color.contiguous(), 3 * npx, "tgt_color", device=dev)
+        _need(tgt_depth.contiguous(), npx, "tgt_depth", device=dev)
+        rc = self.lib.gs_densify(self.h, ca, _p(poses.contiguous()), V, _p(alpha.contiguous()),
+                                 _p(tgt_color.contiguous()), _p(tgt_depth.contiguous()), float(gamma),
+                                 int(all_pixels), ctypes.byref(gst), int(capacity),
+                                 ctypes.byref(ain) if ain is not None else None,
+                                 ctypes.byref(aout) if aout is not None else None, _p(counts), _p(ws), nbytes,
+                                 _stream())
+        self._check(rc)
+        c0, c1 = (int(x) for x in counts.cpu())
+        out = Gaussians(held.means[:c0], held.log_scales[:c0], held.quats[:c0], held.opacity_logits[:c0],
+                        held.colors[:c0], g.sh_degree)
+        if adam is None:
+            return out, (c0, c1), None
+        keep = c0 * (11 + 3 * K) + 6 * V
+        return out, (c0, c1), (m2[:keep], v2[:keep], adam[2])
+
     def _bin(self, bin):
         """Resolve (0, 0) to the context's bin choice (kept in Python too, so
         the state can be sized before the call)."""

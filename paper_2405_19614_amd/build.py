@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libgs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["project.hip", "binning.hip", "raster.hip", "step.hip", "ssim.hip", "abi.cpp"]
+SOURCES = ["project.hip", "binning.hip", "raster.hip", "step.hip", "ssim.hip", "maintain.hip", "abi.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

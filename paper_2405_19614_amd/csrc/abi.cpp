@@ -549,6 +549,104 @@ int gs_ssim(gs_ctx* c, const gs_camera* cams, int32_t V, const float* img, const
 
 namespace {
 
+// scratch of a flag / scan / scatter pass over m items
+size_t compaction_bytes(int64_t m) {
+    return 2 * align_up((size_t)std::max<int64_t>(m, 1) * 4) + align_up((size_t)gs::scan_bsum_entries(m) * 4) +
+           align_up(4);
+}
+
+void compaction_ptrs(void* ws, int64_t m, uint32_t*& flag, uint32_t*& off, uint32_t*& bsum, uint32_t*& total) {
+    char* b = static_cast<char*>(ws);
+    flag = reinterpret_cast<uint32_t*>(b);
+    b += align_up((size_t)std::max<int64_t>(m, 1) * 4);
+    off = reinterpret_cast<uint32_t*>(b);
+    b += align_up((size_t)std::max<int64_t>(m, 1) * 4);
+    bsum = reinterpret_cast<uint32_t*>(b);
+    b += align_up((size_t)gs::scan_bsum_entries(m) * 4);
+    total = reinterpret_cast<uint32_t*>(b);
+}
+
+int adam_io(gs_ctx* c, const gs_adam* ain, gs_adam* aout, gs::AdamIO& io) {
+    if (!ain && !aout) return 0;
+    if (!ain || !aout || !ain->m || !ain->v || !aout->m || !aout->v || !ain->step || !aout->step)
+        return fail(c, GS_EINVAL, "Adam state: give both adam_in and adam_out with m, v and step");
+    if (ain->m == aout->m || ain->v == aout->v) return fail(c, GS_EINVAL, "adam_out must not overlap adam_in");
+    io = gs::AdamIO{ain->m, ain->v, aout->m, aout->v, ain->step, aout->step};
+    return 1;
+}
+
+}  // namespace
+
+size_t gs_prune_workspace_bytes(int64_t n) { return n < 0 ? 0 : compaction_bytes(n); }
+
+int gs_prune(gs_ctx* c, const gs_gaussians* in, float tau, gs_gaussians* out, const gs_adam* adam_in,
+             gs_adam* adam_out, int32_t V, int64_t* n_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!c) return GS_EINVAL;
+    int r = check_gaussians(c, in);
+    if (r) return r;
+    if (!out || !n_out || !ws) return fail(c, GS_EINVAL, "a required pointer is NULL");
+    if (in->n > 0 && (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->colors))
+        return fail(c, GS_EINVAL, "an output array is NULL");
+    if (in->n >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "n too large");
+    if (V < 0 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V outside [0, %d]", GS_MAX_VIEWS);
+    if (std::isnan(tau)) return fail(c, GS_EINVAL, "tau is NaN");
+    if (ws_bytes < compaction_bytes(in->n)) return fail(c, GS_ENOMEM, "workspace too small");
+    gs::AdamIO io;
+    const int ha = adam_io(c, adam_in, adam_out, io);
+    if (ha < 0) return ha;
+    const double t = (double)tau;
+    const float logit = t <= 0.0 ? -INFINITY : (t >= 1.0 ? INFINITY : (float)std::log(t / (1.0 - t)));
+    const int K = in->sh_degree < 0 ? 1 : (in->sh_degree + 1) * (in->sh_degree + 1);
+    uint32_t *flag, *off, *bsum, *total;
+    compaction_ptrs(ws, in->n, flag, off, bsum, total);
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gs::GaussOut o{out->means, out->log_scales, out->quats, out->opacity_logits, out->colors};
+    GS_HIP(c, gs::launch_prune(params_of(in), 3 * K, logit, o, ha ? &io : nullptr, V, flag, off, bsum, total, n_out,
+                               s));
+    return GS_OK;
+}
+
+size_t gs_densify_workspace_bytes(const gs_camera* cams, int32_t V) {
+    gs::ViewTable vt;
+    if (build_vt(nullptr, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt) != GS_OK) return 0;
+    return compaction_bytes(vt.n_pix);
+}
+
+int gs_densify(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, const float* alpha,
+               const float* tgt_color, const float* tgt_depth, float gamma, int32_t all_pixels, gs_gaussians* g,
+               int64_t capacity, const gs_adam* adam_in, gs_adam* adam_out, int64_t* counts, void* ws,
+               size_t ws_bytes, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!g) return fail(c, GS_EINVAL, "g is NULL");
+    if (!poses || !alpha || !tgt_color || !tgt_depth || !counts || !ws)
+        return fail(c, GS_EINVAL, "a required pointer is NULL");
+    if (g->n < 0 || capacity < g->n || capacity >= ((int64_t)1 << 31))
+        return fail(c, GS_EINVAL, "need 0 <= n <= capacity < 2^31");
+    if (capacity > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->colors))
+        return fail(c, GS_EINVAL, "a Gaussian array is NULL");
+    if (g->sh_degree < -1 || g->sh_degree > 3) return fail(c, GS_EINVAL, "sh_degree outside [-1, 3]");
+    if (std::isnan(gamma)) return fail(c, GS_EINVAL, "gamma is NaN");
+    gs::ViewTable vt;
+    int r = build_vt(c, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt);
+    if (r) return r;
+    if (ws_bytes < compaction_bytes(vt.n_pix)) return fail(c, GS_ENOMEM, "workspace too small");
+    gs::AdamIO io;
+    const int ha = adam_io(c, adam_in, adam_out, io);
+    if (ha < 0) return ha;
+    const int K = g->sh_degree < 0 ? 1 : (g->sh_degree + 1) * (g->sh_degree + 1);
+    uint32_t *flag, *off, *bsum, *total;
+    compaction_ptrs(ws, vt.n_pix, flag, off, bsum, total);
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gs::GaussOut o{g->means, g->log_scales, g->quats, g->opacity_logits, g->colors};
+    GS_HIP(c, gs::launch_densify(vt, poses, alpha, tgt_color, tgt_depth, gamma, all_pixels, o, (int)g->n, K, capacity,
+                                 ha ? &io : nullptr, flag, off, bsum, total, counts, s));
+    return GS_OK;
+}
+
+namespace {
+
 // Stages of one step, timed by gs_step_profile.
 const char* const kStageNames[] = {"preprocess_fwd", "binning",        "composite_fwd", "ssim",
                                    "loss_reproj",    "composite_bwd",  "preprocess_bwd", "optimizer"};

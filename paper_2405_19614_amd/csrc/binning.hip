@@ -473,4 +473,9 @@ hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, cons
 
 #undef GS_AT
 
+hipError_t launch_scan_u32(const uint32_t* a, int64_t n, uint32_t* out, uint32_t* bsum, uint32_t* total32,
+                           hipStream_t s) {
+    return device_scan(LoadArr{a, n}, n, out, bsum, nullptr, total32, s);
+}
+
 }  // namespace gs

@@ -208,6 +208,46 @@ hipError_t launch_reproj(const ViewTable& vt, const float* poses, const float* p
 hipError_t launch_reproj_finalize(const ViewTable& vt, const double* acc, float weight, float* loss,
                                   float* dL_dpose, hipStream_t s);
 
+// exclusive scan of a[0..n) into out (u32), *total32 = sum; bsum needs
+// max(1, ceil(n / 2048)) entries
+hipError_t launch_scan_u32(const uint32_t* a, int64_t n, uint32_t* out, uint32_t* bsum, uint32_t* total32,
+                           hipStream_t s);
+inline int64_t scan_bsum_entries(int64_t n) { return n <= 0 ? 1 : (n + 2047) / 2048; }
+
+// Map maintenance (Sec. 3.4).  Gaussian arrays as in Params, `col` with 3K
+// floats per Gaussian.
+struct GaussOut {
+    float* means;
+    float* ls;
+    float* q;
+    float* opl;
+    float* col;
+};
+// Adam moments (m, v) of a layout for n Gaussians: groups of width 3, 3, 4,
+// 1, 3K floats per Gaussian, then 6V pose floats
+struct AdamIO {
+    const float* m_in;
+    const float* v_in;
+    float* m_out;
+    float* v_out;
+    const int32_t* step_in;
+    int32_t* step_out;
+};
+// pruning: keep Gaussians with opacity logit >= logit_tau, in order; scratch
+// u32 flag[n], off[n], bsum[scan_bsum_entries(n)], total[1]; n_out device
+// int64 = kept count; adam (nullable m_in) re-laid out for the kept ones
+hipError_t launch_prune(const Params& in, int K3, float logit_tau, GaussOut out, const AdamIO* adam, int V,
+                        uint32_t* flag, uint32_t* off, uint32_t* bsum, uint32_t* total, int64_t* n_out,
+                        hipStream_t s);
+// densification: append a Gaussian for every selected pixel after the n
+// existing ones (at most capacity in all); counts device int64[2] = (Gaussians
+// now held, Gaussians the selection asked for); scratch as for pruning over
+// the n_pix pixels
+hipError_t launch_densify(const ViewTable& vt, const float* poses, const float* alpha, const float* tc,
+                          const float* td, float gamma, int all_pixels, GaussOut g, int n, int K, int64_t capacity,
+                          const AdamIO* adam, uint32_t* flag, uint32_t* off, uint32_t* bsum, uint32_t* total,
+                          int64_t* counts, hipStream_t s);
+
 struct AdamGroups {
     float* p[5];
     const float* g[5];
