@@ -169,10 +169,13 @@ int gs_render_backward(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams
  *   matches with an index outside [0, V) are ignored), M >= 0.
  *   residual device [M][2] (0 for excluded matches), loss device [V]
  *   (overwritten), dL_dpose device [V][6]: ACCUMULATES weight * d loss_k /
- *   d xi_k, so it can be added to the rendering pose gradient. */
+ *   d xi_k, so it can be added to the rendering pose gradient.
+ *   dL_dpoints device [M][3] or NULL: OVERWRITTEN with d/dP_m of
+ *   weight * sum_k loss_k (the point side of the full bundle adjustment of
+ *   Sec. 3.2 Eq. for:ba; 0 for excluded matches). */
 int gs_reproj_residual(gs_ctx* ctx, const gs_camera* cams, const float* poses, int32_t V, const float* points,
                        const float* uv, const int32_t* view_idx, int64_t M, float huber_delta, float weight,
-                       float* residual, float* loss, float* dL_dpose, void* stream);
+                       float* residual, float* loss, float* dL_dpose, float* dL_dpoints, void* stream);
 
 /* Options of one mapping / pose-refinement step.
  * Loss (Sec. 3.3 joint-loss equation; Sec. 3.4 mapping-loss equation):
@@ -337,6 +340,20 @@ int gs_get_pixels_per_thread(const gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
 size_t gs_ssim_workspace_bytes(const gs_camera* cams, int32_t V);
 int gs_ssim(gs_ctx* ctx, const gs_camera* cams, int32_t V, const float* img, const float* ref, const float* weights,
             float* ssim_out, float* dL_dimg, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Viewpoint selection of the Fusion Bridge (Sec. 3.3 selection equation), a
+ * host-side rule over F keyframes in time order: keyframe 0 is selected;
+ * keyframe i > 0 is selected when beta <= M < alpha * T, where M =
+ * covis[p * F + i] is the number of feature matches between i and the last
+ * selected keyframe p, and T = n_obs[p] is the number of matched map points
+ * the keyframe p observes (the paper's "total number of matches in the
+ * previous keyframe"; "previous" is read as the previous selected one).
+ *   covis HOST int32 [F][F], n_obs HOST int32 [F], selected HOST int32 [F]
+ *   (out, 1 = selected).  The paper uses alpha = 0.75, beta = 20.
+ * Returns GS_EINVAL for F < 0, NULL pointers (F > 0) or a negative or
+ * non-finite alpha; needs no context and no device. */
+int gs_select_viewpoints(const int32_t* covis, const int32_t* n_obs, int32_t F, float alpha, int32_t beta,
+                         int32_t* selected);
 
 /* Map maintenance of the online reconstruction (Sec. 3.4).
  *

@@ -252,6 +252,58 @@ def reproj(cams, poses, points, uv, view_idx, delta: float) -> Dict[str, np.ndar
     return {"residual": res, "loss": loss, "dpose": dpose, "nvalid": nvalid}
 
 
+def reproj_point_grads(cams, poses, points, uv, view_idx, delta: float, weight: float = 1.0) -> np.ndarray:
+    """d/dP of weight * sum_v (mean over view v's valid matches of h(|r|)),
+    the point side of the full bundle adjustment (Sec. 3.2 Eq. for:ba):
+    p = R P + t, r = uv - pi(p), dh/dr = r (|r| <= delta) or delta r / |r|,
+    dr/dp = -[[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]], dp/dP = R."""
+    P = _d(points).reshape(-1, 3)
+    U = _d(uv).reshape(-1, 2)
+    vid = np.asarray(view_idx).reshape(-1)
+    V = len(cams)
+    out = np.zeros_like(P)
+    valid = np.zeros(len(P), bool)
+    for m in range(len(P)):
+        v = int(vid[m])
+        if v < 0 or v >= V:
+            continue
+        T = _d(poses[v]).reshape(4, 4)
+        p = T[:3, :3] @ P[m] + T[:3, 3]
+        if not p[2] > 0.2:
+            continue
+        c = cams[v]
+        r = U[m] - np.array([c.fx * p[0] / p[2] + c.cx, c.fy * p[1] / p[2] + c.cy])
+        e = np.linalg.norm(r)
+        dh_dr = r if e <= delta else delta * r / e
+        J = np.array([[c.fx / p[2], 0.0, -c.fx * p[0] / p[2] ** 2], [0.0, c.fy / p[2], -c.fy * p[1] / p[2] ** 2]])
+        out[m] = -(dh_dr @ J) @ T[:3, :3]
+        valid[m] = True
+    for v in range(V):
+        sel = valid & (vid == v)
+        if sel.any():
+            out[sel] *= weight / sel.sum()
+    return out
+
+
+def select_viewpoints(covis, n_obs, alpha: float, beta: int) -> np.ndarray:
+    """Sec. 3.3 selection equation over keyframes in time order: the first
+    is selected; keyframe i is selected when beta <= M < alpha T, M = feature
+    matches between i and the previous selected keyframe p, T = matched map
+    points observed by p."""
+    F = len(n_obs)
+    sel = np.zeros(F, bool)
+    if F == 0:
+        return sel
+    sel[0] = True
+    prev = 0
+    for i in range(1, F):
+        M = int(covis[prev][i])
+        if beta <= M and M < alpha * float(n_obs[prev]):
+            sel[i] = True
+            prev = i
+    return sel
+
+
 def binning(sizes, n: int, tile_w: int, tile_h: int, rect: np.ndarray, depth: np.ndarray):
     """Definition of the (tile, depth, record) binning: returns (values,
     ranges) where values lists record ids sorted by (global tile, FP32 depth

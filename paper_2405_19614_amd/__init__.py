@@ -7,10 +7,10 @@ the SSIM term of the mapping loss, behind the C ABI in include/gs.h.
 from .binding import (Camera, Context, GSError, GSRenderFn, Gaussians, JointRefinement, MappingStep,
                       PAPER_FUSION_BRIDGE,
                       PAPER_MAPPING, SSIMLossFn, StepOptions, as_cameras, default_context, render, sh_coeffs,
-                      split_images, ssim_loss)
+                      select_viewpoints, split_images, ssim_loss)
 from . import _abi
 
 __all__ = ["Camera", "Context", "GSError", "GSRenderFn", "Gaussians", "JointRefinement", "MappingStep",
            "PAPER_FUSION_BRIDGE",
            "PAPER_MAPPING", "SSIMLossFn", "StepOptions", "as_cameras", "default_context", "render", "sh_coeffs",
-           "split_images", "ssim_loss", "_abi"]
+           "select_viewpoints", "split_images", "ssim_loss", "_abi"]

@@ -67,7 +67,7 @@ EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_sta
            "gs_step_status", "gs_bin_records", "gs_autotune", "gs_set_tile", "gs_num_stages", "gs_stage_name",
            "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bin",
            "gs_ssim_workspace_bytes", "gs_ssim", "gs_prune_workspace_bytes", "gs_prune",
-           "gs_densify_workspace_bytes", "gs_densify"]
+           "gs_densify_workspace_bytes", "gs_densify", "gs_select_viewpoints"]
 
 _lib = None
 
@@ -98,7 +98,7 @@ def load() -> ctypes.CDLL:
                                      c_size_t, ctypes.POINTER(gs_plan), c_void_p, c_void_p, c_void_p,
                                      ctypes.POINTER(gs_gaussian_grads), c_void_p, c_void_p]
     L.gs_reproj_residual.argtypes = [c_void_p, PC, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int64,
-                                     c_float, c_float, c_void_p, c_void_p, c_void_p, c_void_p]
+                                     c_float, c_float, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.gs_mapping_step.argtypes = [c_void_p, ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_gaussian_grads),
                                   ctypes.POINTER(gs_adam), PC, c_void_p, c_int32, ctypes.POINTER(gs_targets),
                                   ctypes.POINTER(gs_matches), ctypes.POINTER(gs_step_opts), c_void_p, c_size_t,
@@ -116,6 +116,7 @@ def load() -> ctypes.CDLL:
     L.gs_get_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32]
     PG = ctypes.POINTER(gs_gaussians)
     PA = ctypes.POINTER(gs_adam)
+    L.gs_select_viewpoints.argtypes = [c_void_p, c_void_p, c_int32, ctypes.c_float, c_int32, c_void_p]
     L.gs_prune_workspace_bytes.argtypes = [c_int64]
     L.gs_prune_workspace_bytes.restype = c_size_t
     L.gs_prune.argtypes = [c_void_p, PG, ctypes.c_float, PG, PA, PA, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]

@@ -268,8 +268,9 @@ class Context:
         return grads, dpose
 
     def reproj(self, cams, poses, points, uv, view_idx, delta: float, weight: float = 1.0,
-               dpose: Optional[torch.Tensor] = None):
-        """Returns (residual [M,2], loss [V], dpose [V,6]) (dpose accumulated)."""
+               dpose: Optional[torch.Tensor] = None, point_grads: bool = False):
+        """Returns (residual [M,2], loss [V], dpose [V,6]) (dpose accumulated),
+        plus dL/dpoints [M,3] when ``point_grads``."""
         cams = as_cameras(cams)
         V = len(cams)
         dev = self.torch_device
@@ -286,10 +287,13 @@ class Context:
         loss = torch.empty(V, dtype=torch.float32, device=dev)
         if dpose is None:
             dpose = torch.zeros(V, 6, dtype=torch.float32, device=dev)
+        dpts = torch.empty(max(M, 1), 3, dtype=torch.float32, device=dev) if point_grads else None
         rc = self.lib.gs_reproj_residual(self.h, cam_array(cams), _p(poses.contiguous()), V, _p(points), _p(uv),
                                          _p(view_idx), M, float(delta), float(weight), _p(residual), _p(loss),
-                                         _p(dpose), _stream())
+                                         _p(dpose), _p(dpts), _stream())
         self._check(rc)
+        if point_grads:
+            return residual[:M], loss, dpose, dpts[:M]
         return residual[:M], loss, dpose
 
     def ssim(self, cams, img: torch.Tensor, ref: torch.Tensor, weights: Optional[torch.Tensor] = None,
@@ -717,4 +721,22 @@ class JointRefinement:
         self.step.set_options(self.map_opts)
         for _ in range(k_map):
             self.step()
+
+
+def select_viewpoints(covis, n_obs, alpha: float = 0.75, beta: int = 20):
+    """Viewpoint selection of the Fusion Bridge (see gs_select_viewpoints):
+    ``covis`` [F,F] feature matches between keyframes, ``n_obs`` [F] matched
+    map points per keyframe.  Returns a bool array [F]."""
+    import numpy as np
+    covis = np.ascontiguousarray(covis, dtype=np.int32)
+    n_obs = np.ascontiguousarray(n_obs, dtype=np.int32)
+    F = int(n_obs.shape[0])
+    if covis.shape != (F, F):
+        raise ValueError("covis must be [F, F]")
+    out = np.zeros(F, np.int32)
+    rc = A.load().gs_select_viewpoints(covis.ctypes.data, n_obs.ctypes.data, F, float(alpha), int(beta),
+                                       out.ctypes.data)
+    if rc != 0:
+        raise GSError(rc, "gs_select_viewpoints rejected its arguments")
+    return out.astype(bool)
 

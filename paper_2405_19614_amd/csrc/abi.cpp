@@ -502,7 +502,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
 
 int gs_reproj_residual(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, const float* points,
                        const float* uv, const int32_t* view_idx, int64_t M, float delta, float weight,
-                       float* residual, float* loss, float* dL_dpose, void* stream) {
+                       float* residual, float* loss, float* dL_dpose, float* dL_dpoints, void* stream) {
     if (!c) return GS_EINVAL;
     if (M < 0) return fail(c, GS_EINVAL, "M is negative");
     if (M >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "M too large");
@@ -515,8 +515,9 @@ int gs_reproj_residual(gs_ctx* c, const gs_camera* cams, const float* poses, int
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     GS_HIP(c, gs::launch_zero_f64(c->rp_acc, 8 * V, s));
-    GS_HIP(c, gs::launch_reproj(vt, poses, points, uv, view_idx, M, delta, residual, c->rp_acc, s));
+    GS_HIP(c, gs::launch_reproj(vt, poses, points, uv, view_idx, M, delta, residual, c->rp_acc, s, dL_dpoints));
     GS_HIP(c, gs::launch_reproj_finalize(vt, c->rp_acc, weight, loss, dL_dpose, s));
+    if (dL_dpoints) GS_HIP(c, gs::launch_reproj_points_scale(vt, view_idx, M, c->rp_acc, weight, dL_dpoints, s));
     return GS_OK;
 }
 
@@ -576,6 +577,24 @@ int adam_io(gs_ctx* c, const gs_adam* ain, gs_adam* aout, gs::AdamIO& io) {
 }
 
 }  // namespace
+
+int gs_select_viewpoints(const int32_t* covis, const int32_t* n_obs, int32_t F, float alpha, int32_t beta,
+                         int32_t* selected) {
+    if (F < 0) return GS_EINVAL;
+    if (F == 0) return GS_OK;
+    if (!covis || !n_obs || !selected) return GS_EINVAL;
+    if (!(alpha >= 0.f) || !std::isfinite(alpha)) return GS_EINVAL;
+    int32_t prev = 0;
+    selected[0] = 1;   // the first keyframe opens the map
+    for (int32_t i = 1; i < F; i++) {
+        const int64_t m = covis[(int64_t)prev * F + i];
+        const double cap = (double)alpha * (double)n_obs[prev];
+        const bool take = m >= beta && (double)m < cap;
+        selected[i] = take ? 1 : 0;
+        if (take) prev = i;
+    }
+    return GS_OK;
+}
 
 size_t gs_prune_workspace_bytes(int64_t n) { return n < 0 ? 0 : compaction_bytes(n); }
 

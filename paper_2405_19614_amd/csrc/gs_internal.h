@@ -203,8 +203,14 @@ hipError_t launch_ssim_bwd(const ViewTable& vt, const float* img, const float* r
                            const float* wdev, float wconst, float* dimg, hipStream_t s);
 // per-view mean SSIM from the tile sums
 hipError_t launch_ssim_reduce(const ViewTable& vt, const double* tile_sum, float* ssim_out, hipStream_t s);
+// dpts (nullable, device [M][3]): dh/dP per match, unscaled (0 for excluded
+// matches); launch_reproj_points_scale then multiplies by weight / matches of
+// the view, once acc holds the counts
 hipError_t launch_reproj(const ViewTable& vt, const float* poses, const float* pts, const float* uv,
-                         const int32_t* vid, int64_t M, float delta, float* residual, double* acc, hipStream_t s);
+                         const int32_t* vid, int64_t M, float delta, float* residual, double* acc, hipStream_t s,
+                         float* dpts = nullptr);
+hipError_t launch_reproj_points_scale(const ViewTable& vt, const int32_t* vid, int64_t M, const double* acc,
+                                      float weight, float* dpts, hipStream_t s);
 hipError_t launch_reproj_finalize(const ViewTable& vt, const double* acc, float weight, float* loss,
                                   float* dL_dpose, hipStream_t s);
 

@@ -34,7 +34,7 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 // acc per view: [sum h, count, dxi(6)]
 __global__ __launch_bounds__(256) void reproj_kernel(ViewTable vt, const float* poses, const float* pts,
                                                      const float* uv, const int32_t* vid, int64_t M, float delta,
-                                                     float* residual, double* acc) {
+                                                     float* residual, double* acc, float* dpts) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = m < M;
     int v = in ? vid[m] : -1;
@@ -70,6 +70,10 @@ __global__ __launch_bounds__(256) void reproj_kernel(ViewTable vt, const float* 
             g[3] = (double)(py * dpz - pz * dpy);
             g[4] = (double)(pz * dpx - px * dpz);
             g[5] = (double)(px * dpy - py * dpx);
+            if (dpts) {   // dh/dP = R^T dh/dp; scaled by weight / (matches of the view) afterwards
+#pragma unroll
+                for (int k = 0; k < 3; k++) dpts[3 * m + k] = T[k] * dpx + T[4 + k] * dpy + T[8 + k] * dpz;
+            }
         } else {
             v = -1;
         }
@@ -78,6 +82,7 @@ __global__ __launch_bounds__(256) void reproj_kernel(ViewTable vt, const float* 
         residual[2 * m] = r0;
         residual[2 * m + 1] = r1;
     }
+    if (in && dpts && v < 0) dpts[3 * m] = dpts[3 * m + 1] = dpts[3 * m + 2] = 0.f;
     // matches are usually grouped by view: reduce over the wavefront when
     // every valid lane has the same view, else one atomic set per lane
     const uint64_t valid = __ballot(v >= 0);
@@ -253,9 +258,31 @@ hipError_t launch_zero_f64(double* p, int n, hipStream_t s) {
 }
 
 hipError_t launch_reproj(const ViewTable& vt, const float* poses, const float* pts, const float* uv,
-                         const int32_t* vid, int64_t M, float delta, float* residual, double* acc, hipStream_t s) {
+                         const int32_t* vid, int64_t M, float delta, float* residual, double* acc, hipStream_t s,
+                         float* dpts) {
     if (M <= 0) return hipSuccess;
-    reproj_kernel<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(vt, poses, pts, uv, vid, M, delta, residual, acc);
+    reproj_kernel<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(vt, poses, pts, uv, vid, M, delta, residual, acc,
+                                                              dpts);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ __launch_bounds__(256) void reproj_points_scale_kernel(int V, const int32_t* vid, int64_t M,
+                                                                  const double* acc, float weight, float* dpts) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const int v = vid[m];
+    const double cnt = (v >= 0 && v < V) ? acc[8 * v + 1] : 0.0;
+    const float sc = cnt > 0.0 ? (float)((double)weight / cnt) : 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; k++) dpts[3 * m + k] *= sc;
+}
+}  // namespace
+
+hipError_t launch_reproj_points_scale(const ViewTable& vt, const int32_t* vid, int64_t M, const double* acc,
+                                      float weight, float* dpts, hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    reproj_points_scale_kernel<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(vt.V, vid, M, acc, weight, dpts);
     return hipGetLastError();
 }
 

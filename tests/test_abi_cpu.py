@@ -118,3 +118,26 @@ def test_paper_preset_matches_table():
     assert PAPER_FUSION_BRIDGE["w_color"] == hp["w2"]
     assert PAPER_FUSION_BRIDGE["w_depth"] == hp["w3"]
     assert PAPER_FUSION_BRIDGE["gate_gamma"] == hp["gamma"]
+
+
+def test_viewpoint_selection_matches_oracle(lib):
+    """The library's host rule equals the oracle's on random covisibility."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2405_19614_amd import select_viewpoints
+    rng = np.random.default_rng(21)
+    for trial in range(50):
+        F = int(rng.integers(1, 40))
+        covis = rng.integers(0, 150, (F, F)).astype(np.int32)
+        n_obs = rng.integers(0, 200, F).astype(np.int32)
+        alpha, beta = float(rng.choice([0.5, 0.75, 0.9])), int(rng.choice([5, 20, 40]))
+        got = select_viewpoints(covis, n_obs, alpha, beta)
+        want = O.select_viewpoints(covis, n_obs, alpha, beta)
+        assert list(got) == list(want), trial
+    # boundaries: M == beta selected, M == alpha * T not
+    covis = np.array([[0, 20, 0], [0, 0, 0], [0, 0, 0]], np.int32)
+    covis[1, 2] = 75
+    assert list(select_viewpoints(covis, np.array([100, 100, 0], np.int32), 0.75, 20)) == [True, True, False]
+    from paper_2405_19614_amd import _abi as A
+    assert lib.gs_select_viewpoints(None, None, -1, 0.75, 20, None) == A.GS_EINVAL
+    assert lib.gs_select_viewpoints(None, None, 0, 0.75, 20, None) == 0

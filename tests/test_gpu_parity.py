@@ -210,6 +210,15 @@ def test_reproj_matches_oracle(ctx):
     np.testing.assert_allclose(loss.cpu().numpy(), r["loss"], rtol=1e-4)
     for v in range(s.V):
         assert rel(dpose[v].cpu().numpy(), 0.5 * r["dpose"][v]) < 1e-3
+    # the point side of the bundle adjustment (Sec. 3.2 Eq. for:ba)
+    _, _, _, dpts = ctx.reproj(s.cams, poses, t(s.points), t(s.uv), t(s.view_idx), 2.0, weight=0.5,
+                               point_grads=True)
+    torch.cuda.synchronize()
+    g_ref = O.reproj_point_grads(s.cams, s.poses, s.points, s.uv, s.view_idx, 2.0, weight=0.5)
+    e = rel(dpts.cpu().numpy(), g_ref)
+    print(f"  point gradients rel {e:.2e}", flush=True)
+    assert e < 1e-3
+    assert np.all(dpts.cpu().numpy()[np.all(g_ref == 0, axis=1)] == 0)
 
 
 def test_empty_and_culled_scenes(ctx):

@@ -95,3 +95,44 @@ def test_adam_relayout():
                 want = 0.0 if j < 0 else m[oo + w * j + e]
                 assert out[on + w * i + e] == want
     np.testing.assert_array_equal(out[new_pose:], m[pose_off:])
+
+
+def test_point_gradients_match_central_differences():
+    """The oracle's point gradient against central differences of the C
+    oracle's re-projection loss (independent code)."""
+    rng = np.random.default_rng(12)
+    cams = [scenes.Camera(64, 48, 60.0, 60.0, 32.0, 24.0), scenes.Camera(40, 30, 35.0, 35.0, 20.0, 15.0)]
+    poses = [np.eye(4), O.se3_exp([0.1, 0.0, 0.05, 0.02, -0.03, 0.01])]
+    M = 12
+    P = np.column_stack([rng.uniform(-1, 1, M), rng.uniform(-1, 1, M), rng.uniform(2, 4, M)])
+    vid = (np.arange(M) % 2).astype(np.int32)
+    U = np.zeros((M, 2))
+    for m in range(M):
+        T = poses[vid[m]]
+        p = T[:3, :3] @ P[m] + T[:3, 3]
+        c = cams[vid[m]]
+        U[m] = [c.fx * p[0] / p[2] + c.cx, c.fy * p[1] / p[2] + c.cy]
+    U += rng.normal(0, 1.5, U.shape)      # some residuals beyond the Huber knee
+    g = O.reproj_point_grads(cams, poses, P, U, vid, 2.0, weight=0.7)
+
+    def loss(Pm):
+        return 0.7 * float(O.reproj(cams, poses, Pm, U, vid, 2.0)["loss"].sum())
+
+    h = 1e-6
+    for m in range(M):
+        for k in range(3):
+            e = np.zeros_like(P)
+            e[m, k] = h
+            fd = (loss(P + e) - loss(P - e)) / (2 * h)
+            assert abs(fd - g[m, k]) <= 1e-6 * max(1.0, abs(fd)), (m, k, fd, g[m, k])
+
+
+def test_viewpoint_selection_worked_example():
+    """A hand-worked sequence (alpha = 0.75, beta = 20): keyframe 1 shares 100
+    of the 120 points of keyframe 0 (>= 0.75 * 120 = 90: too similar), keyframe
+    2 shares 60 (selected), keyframe 3 shares 10 with keyframe 2 (< 20: too
+    few), keyframe 4 shares 30 with keyframe 2 (selected: 30 < 0.75 * 80)."""
+    covis = np.zeros((5, 5), np.int32)
+    covis[0, 1], covis[0, 2], covis[2, 3], covis[2, 4] = 100, 60, 10, 30
+    n_obs = np.array([120, 110, 80, 70, 90], np.int32)
+    assert list(O.select_viewpoints(covis, n_obs, 0.75, 20)) == [True, False, True, False, True]
