@@ -155,7 +155,8 @@ def main():
     ap.add_argument("--views", type=int, default=8)
     ap.add_argument("--width", type=int, default=1200)
     ap.add_argument("--height", type=int, default=680)
-    ap.add_argument("--tile", default="auto", help="auto | TWxTH,PPT,BWxBH (tile, pixels per thread, bin)")
+    ap.add_argument("--tile", default="auto",
+                    help="auto | TWxTH,PPT,BWxBH[,BTWxBTH,BPPT] (tile, pixels per thread, bin[, backward tile, ppt])")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the CPU oracle runs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum timed CPU oracle work")
@@ -182,11 +183,16 @@ def main():
     if args.tile == "auto":
         tile, binsz = ctx.autotune(g, s.cams, poses, iters=2)
     else:
-        tw, th, ppt, bw, bh = (int(x) for x in args.tile.lower().replace("x", ",").split(","))
+        # TWxTH,PPT,BWxBH[,BTWxBTH,BPPT]: forward tile, pixels per thread, bin[, backward tile and its ppt]
+        vals = [int(x) for x in args.tile.lower().replace("x", ",").split(",")]
+        tw, th, ppt, bw, bh = vals[:5]
         ctx.set_tile(tw, th, ppt)
         ctx.set_bin(bw, bh)
+        if len(vals) == 8:
+            ctx.set_bwd_shape(vals[5], vals[6], vals[7])
         tile, binsz = (tw, th), (bw, bh)
-    log(f"[bench] tile {tile} bin {binsz}")
+    btile = ctx.bwd_tile_choice if ctx.bwd_tile_choice != (0, 0) else tile
+    log(f"[bench] tile {tile} bin {binsz} backward tile {btile}")
     base = dict(w_color=1.0, w_depth=0.1, w_reproj=0.0, tile=tile, bin=binsz, use_graph=True)
 
     # batched fwd+bwd (no update): the value
@@ -255,7 +261,8 @@ def main():
         else:
             flops = BWD_PER_VISIT * vis + BWD_PER_BLEND * blend
         achieved = flops / (stage_ms[dom] / 1000.0) / 1e12
-        kname = f"composite_{dom.split('_')[1]}_kernel<{tile[0]}, {tile[1]}, {ctx.ppt_choice(tile)}>"
+        kt = btile if dom == "composite_bwd" else tile
+        kname = f"composite_{dom.split('_')[1]}_kernel<{kt[0]}, {kt[1]}, {ctx.ppt_choice(kt, dom == 'composite_bwd')}>"
         traffic = measured_traffic(kname)
         roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
@@ -289,7 +296,8 @@ def main():
         "config": {"workload": f"batched keyframe window: {s.n} Gaussians, room shell, {s.V} views "
                                f"{args.width}x{args.height}, f=600, L1 colour + 0.1 L1 depth",
                    "gaussians": s.n, "views": s.V, "width": args.width, "height": args.height,
-                   "pixels_per_step": npix, "tile": f"{tile[0]}x{tile[1]}", "bin": f"{binsz[0]}x{binsz[1]}"},
+                   "pixels_per_step": npix, "tile": f"{tile[0]}x{tile[1]}", "bin": f"{binsz[0]}x{binsz[1]}",
+                   "bwd_tile": f"{btile[0]}x{btile[1]}"},
         "mapping_iters_per_s": round(iters, 3),
         "ms_per_mapping_iter": round(ms_map, 4),
         "paper_mapping_loss_iters_per_s": round(1000.0 / ms_paper, 3),

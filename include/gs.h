@@ -98,22 +98,28 @@ typedef struct {
 } gs_camera;
 
 /* Tile plan of a forward pass.
- *   tile_w, tile_h : in  compositing tile; one of 16x16, 16x8, 8x8, 32x8, 32x16
- *                    (0, 0 = the context's current choice, 16x16 unless
- *                    gs_autotune chose another); out: the shape used
- *   bin_w, bin_h   : in  binning rectangle, multiples of the tile in [8, 2048]
- *                    (0, 0 = the context's choice, 64x64 by default); out: used.
- *                    Gaussians are binned per bin; each tile composites the
- *                    entries of its bin's list whose support rect meets it.
+ *   tile_w, tile_h : in  compositing tile of the forward; one of 16x16, 16x8,
+ *                    8x8, 32x8, 32x16, 32x32 (0, 0 = the context's current
+ *                    choice, 16x16 unless gs_autotune chose another); out: used
+ *   bin_w, bin_h   : in  binning rectangle, multiples of both tiles in
+ *                    [8, 2048] (0, 0 = the context's choice, 64x64 by
+ *                    default); out: used.  Gaussians are binned per bin; each
+ *                    tile composites the entries of its bin's list whose
+ *                    support rect meets it.
  *   pair_capacity  : in  (bin, Gaussian) pairs the state buffer was sized for
  *   n_pairs        : out pairs produced (on GS_ECAPACITY: pairs needed)
- *   n_visible      : out visible (view, Gaussian) records */
+ *   n_visible      : out visible (view, Gaussian) records
+ *   bwd_tile_w, bwd_tile_h : in  compositing tile of the backward (same shapes;
+ *                    0, 0 = the context's backward choice, else the forward
+ *                    tile); out: the shape gs_render_backward will use.  The
+ *                    shapes change only the launch, never a result. */
 typedef struct {
     int32_t tile_w, tile_h;
     int32_t bin_w, bin_h;
     int64_t pair_capacity;
     int64_t n_pairs;
     int64_t n_visible;
+    int32_t bwd_tile_w, bwd_tile_h;
 } gs_plan;
 
 int gs_abi_version(void);
@@ -207,6 +213,7 @@ typedef struct {
     int32_t bin_w, bin_h;       /* 0, 0 = context choice */
     int64_t pair_capacity;      /* capacity the workspace was sized for */
     float w_ssim;               /* weight of the SSIM term, >= 0 */
+    int32_t bwd_tile_w, bwd_tile_h;  /* backward tile; 0, 0 = context choice, else the forward tile */
 } gs_step_opts;
 
 /* Targets of the rendering loss (device): color [sum 3HW], depth [sum HW],
@@ -296,14 +303,18 @@ int gs_bin_records(gs_ctx* ctx, const gs_camera* cams, int32_t V, int64_t n, int
                    const uint32_t* rect, const float* depth, uint32_t* values, int64_t values_capacity,
                    uint32_t* ranges, int64_t* n_pairs, void* state, size_t state_bytes, void* stream);
 
-/* Launch-shape autotuner: times forward + backward of the given scene for
- * every supported (tile shape, pixels per thread) pair with 64x64 bins, then
- * for the best tile every bin size that is a multiple of it (allocating
- * temporary device buffers); keeps the fastest as the context's choice for
- * this (V, sizes, n) class and returns tile and bin (HOST outputs).
- * Synchronises the device.  No result depends on the choice. */
+/* Launch-shape autotuner: times the forward and the backward of the given
+ * scene for every supported (tile shape, pixels per thread) pair with 64x64
+ * bins and keeps the fastest forward and the fastest backward shape
+ * separately, then times every bin size that is a multiple of both, then
+ * every shape again at the chosen bins (allocating temporary device
+ * buffers); keeps the result as the context's
+ * choice for this (V, sizes, n) class and returns the forward tile, the bin
+ * and the backward tile (HOST outputs).  Synchronises the device.  No result
+ * depends on the choice. */
 int gs_autotune(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
-                int32_t iters, int32_t* tile_w, int32_t* tile_h, int32_t* bin_w, int32_t* bin_h, void* stream);
+                int32_t iters, int32_t* tile_w, int32_t* tile_h, int32_t* bin_w, int32_t* bin_h, int32_t* bwd_tile_w,
+                int32_t* bwd_tile_h, void* stream);
 
 /* Set the context's bin choice explicitly (0, 0 restores 64x64). */
 int gs_set_bin(gs_ctx* ctx, int32_t bin_w, int32_t bin_h);
@@ -311,16 +322,24 @@ int gs_set_bin(gs_ctx* ctx, int32_t bin_w, int32_t bin_h);
 /* Set the context's tile choice explicitly (0, 0 restores 16x16). */
 int gs_set_tile(gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
 
-/* Pixels each thread of the compositing kernels owns for a tile shape (1, 2
- * or 4; 4 needs a tile width of 32 or a 16x16 tile, 8x8 tiles take 1).  Does
- * not change any result, only the launch shape; gs_autotune sets it too. */
+/* Pixels each thread of the compositing kernels owns for a tile shape (1, 2,
+ * 4 or 8: 1 and 2 for every shape but 32x32 (2 not for 8x8), 4 for 16x16 and
+ * the 32-wide shapes, 8 for 32x16 and 32x32), for the forward and the
+ * backward.  Does not change any result, only the launch shape; gs_autotune
+ * sets it too. */
 int gs_set_pixels_per_thread(gs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t ppt);
 
-/* Pixels per thread the compositing kernels use for a tile shape (the value
- * set by gs_set_pixels_per_thread or gs_autotune, else the default: 2 where a
- * 2-pixel kernel exists, otherwise 1).  Returns GS_EINVAL for a null context
+/* The backward's own tile shape and pixels per thread (0, 0, 0: use the
+ * forward's).  Bins must be a multiple of both tiles; where a call's bins are
+ * not, the forward tile is used.  Changes no result. */
+int gs_set_bwd_shape(gs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t ppt);
+
+/* Pixels per thread the compositing kernels use for a tile shape, pass 0 =
+ * forward, 1 = backward (the value set by gs_set_pixels_per_thread,
+ * gs_set_bwd_shape or gs_autotune, else the default: 2 where a 2-pixel kernel
+ * exists, else 1, else 4).  Returns GS_EINVAL for a null context, a bad pass
  * or a tile shape without kernels. */
-int gs_get_pixels_per_thread(const gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
+int gs_get_pixels_per_thread(const gs_ctx* ctx, int32_t pass, int32_t tile_w, int32_t tile_h);
 
 /* SSIM of Sec. 3.4's mapping loss, standalone.  The paper names the term
  * without defining it; this is the usual structural similarity, per colour

@@ -37,7 +37,8 @@ class gs_camera(ctypes.Structure):
 
 class gs_plan(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("bin_w", c_int32), ("bin_h", c_int32),
-                ("pair_capacity", c_int64), ("n_pairs", c_int64), ("n_visible", c_int64)]
+                ("pair_capacity", c_int64), ("n_pairs", c_int64), ("n_visible", c_int64),
+                ("bwd_tile_w", c_int32), ("bwd_tile_h", c_int32)]
 
 
 class gs_step_opts(ctypes.Structure):
@@ -47,7 +48,8 @@ class gs_step_opts(ctypes.Structure):
                 ("lr_means", c_float), ("lr_log_scales", c_float), ("lr_quats", c_float), ("lr_opacity", c_float),
                 ("lr_colors", c_float), ("lr_pose", c_float), ("adam_b1", c_float), ("adam_b2", c_float),
                 ("adam_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32), ("bin_w", c_int32),
-                ("bin_h", c_int32), ("pair_capacity", c_int64), ("w_ssim", c_float)]
+                ("bin_h", c_int32), ("pair_capacity", c_int64), ("w_ssim", c_float),
+                ("bwd_tile_w", c_int32), ("bwd_tile_h", c_int32)]
 
 
 class gs_targets(ctypes.Structure):
@@ -65,7 +67,7 @@ class gs_adam(ctypes.Structure):
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_state_bytes", "gs_render_forward",
            "gs_render_backward", "gs_reproj_residual", "gs_step_workspace_bytes", "gs_mapping_step",
            "gs_step_status", "gs_bin_records", "gs_autotune", "gs_set_tile", "gs_num_stages", "gs_stage_name",
-           "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bin",
+           "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bwd_shape", "gs_set_bin",
            "gs_ssim_workspace_bytes", "gs_ssim", "gs_prune_workspace_bytes", "gs_prune",
            "gs_densify_workspace_bytes", "gs_densify", "gs_select_viewpoints"]
 
@@ -109,11 +111,12 @@ def load() -> ctypes.CDLL:
                                  c_int64, c_void_p, ctypes.POINTER(c_int64), c_void_p, c_size_t, c_void_p]
     L.gs_autotune.argtypes = [c_void_p, ctypes.POINTER(gs_gaussians), PC, c_void_p, c_int32, c_int32,
                               ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
-                              ctypes.POINTER(c_int32), c_void_p]
+                              ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), c_void_p]
     L.gs_set_bin.argtypes = [c_void_p, c_int32, c_int32]
     L.gs_set_tile.argtypes = [c_void_p, c_int32, c_int32]
     L.gs_set_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32, c_int32]
-    L.gs_get_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32]
+    L.gs_get_pixels_per_thread.argtypes = [c_void_p, c_int32, c_int32, c_int32]
+    L.gs_set_bwd_shape.argtypes = [c_void_p, c_int32, c_int32, c_int32]
     PG = ctypes.POINTER(gs_gaussians)
     PA = ctypes.POINTER(gs_adam)
     L.gs_select_viewpoints.argtypes = [c_void_p, c_void_p, c_int32, ctypes.c_float, c_int32, c_void_p]

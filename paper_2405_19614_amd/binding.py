@@ -164,6 +164,7 @@ class Context:
         self.h = h
         self.pair_estimate = 1 << 16
         self.bin_choice = (64, 64)
+        self.bwd_tile_choice = (0, 0)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -199,12 +200,17 @@ class Context:
         if ppt is not None:
             self._check(self.lib.gs_set_pixels_per_thread(self.h, tw, th, ppt))
 
-    def ppt_choice(self, tile) -> int:
+    def ppt_choice(self, tile, backward: bool = False) -> int:
         """Pixels per thread the compositing kernels use for ``tile`` (tw, th)."""
-        r = int(self.lib.gs_get_pixels_per_thread(self.h, int(tile[0]), int(tile[1])))
+        r = int(self.lib.gs_get_pixels_per_thread(self.h, int(backward), int(tile[0]), int(tile[1])))
         if r < 0:
             self._check(r)
         return r
+
+    def set_bwd_shape(self, tw: int, th: int, ppt: int):
+        """The backward's own tile and pixels per thread (0, 0, 0: the forward's)."""
+        self._check(self.lib.gs_set_bwd_shape(self.h, tw, th, ppt))
+        self.bwd_tile_choice = (int(tw), int(th))
 
     def set_bin(self, bw: int, bh: int):
         self._check(self.lib.gs_set_bin(self.h, bw, bh))
@@ -451,17 +457,20 @@ class Context:
         return u(values[:P]), u(ranges)
 
     def autotune(self, g: Gaussians, cams, poses, iters: int = 3):
-        """Returns ((tile_w, tile_h), (bin_w, bin_h)) and makes them the context's choice."""
+        """Returns ((tile_w, tile_h), (bin_w, bin_h)) and makes them, and the
+        backward tile (``bwd_tile_choice``), the context's choice."""
         cams = as_cameras(cams)
         tw, th, bw, bh = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        btw, bth = ctypes.c_int32(), ctypes.c_int32()
         gst = g.struct()
         _check_gaussians(g, self.torch_device)
         _need(poses.contiguous(), 16 * len(cams), "poses", device=self.torch_device)
         rc = self.lib.gs_autotune(self.h, ctypes.byref(gst), cam_array(cams), _p(poses.contiguous()), len(cams),
                                   iters, ctypes.byref(tw), ctypes.byref(th), ctypes.byref(bw), ctypes.byref(bh),
-                                  _stream())
+                                  ctypes.byref(btw), ctypes.byref(bth), _stream())
         self._check(rc)
         self.bin_choice = (int(bw.value), int(bh.value))
+        self.bwd_tile_choice = (int(btw.value), int(bth.value))
         return (int(tw.value), int(th.value)), self.bin_choice
 
 
@@ -567,6 +576,7 @@ class StepOptions:
     tile: Tuple[int, int] = (0, 0)
     bin: Tuple[int, int] = (0, 0)
     w_ssim: float = 0.0
+    bwd_tile: Tuple[int, int] = (0, 0)
 
     def struct(self, capacity: int, bin=None) -> A.gs_step_opts:
         b = self.bin if bin is None else bin
@@ -575,7 +585,7 @@ class StepOptions:
                               int(self.accumulate_grads), int(self.use_graph), self.lr_means, self.lr_log_scales,
                               self.lr_quats, self.lr_opacity, self.lr_colors, self.lr_pose, self.adam_b1,
                               self.adam_b2, self.adam_eps, self.tile[0], self.tile[1], b[0], b[1], capacity,
-                              self.w_ssim)
+                              self.w_ssim, self.bwd_tile[0], self.bwd_tile[1])
 
 
 # the paper's Fusion Bridge weights (Supplementary, hyper-parameter table):

@@ -24,10 +24,12 @@ struct gs_ctx {
     hipStream_t side = nullptr;      // capture / replay stream used when the caller passes the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int tile_w = 16, tile_h = 16;
+    int btile_w = 0, btile_h = 0;      // backward tile (0, 0: the forward's)
     int bin_w = 64, bin_h = 64;
-    std::unordered_map<int, int> ppt;  // pixels per thread chosen per tile shape (key tw * 1000 + th)
+    std::unordered_map<int, int> ppt;      // pixels per thread per tile shape (key tw * 1000 + th)
+    std::unordered_map<int, int> ppt_bwd;  // the backward's, where it differs
     std::unordered_map<uint64_t, hipGraphExec_t> graphs;
-    struct Tuned { int tw, th, bw, bh, ppt; };
+    struct Tuned { int tw, th, bw, bh, ppt, btw, bth, bppt; };
     std::unordered_map<uint64_t, Tuned> tuned;
 };
 
@@ -72,15 +74,17 @@ struct DeviceGuard {
 
 bool tile_ok(int tw, int th) {
     return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
-           (tw == 32 && th == 16);
+           (tw == 32 && th == 16) || (tw == 32 && th == 32);
 }
 
 // pixels per thread the compositing kernels are built for (whole wavefronts)
 bool ppt_ok(int tw, int th, int ppt) {
     if (!tile_ok(tw, th)) return false;
+    if (tw == 32 && th == 32) return ppt == 4 || ppt == 8;
     if (ppt == 1) return true;
     if (ppt == 2) return !(tw == 8 && th == 8);
     if (ppt == 4) return (tw == 16 && th == 16) || (tw == 32);
+    if (ppt == 8) return tw == 32 && th == 16;
     return false;
 }
 
@@ -89,7 +93,15 @@ int ppt_of(const gs_ctx* c, int tw, int th) {
         auto it = c->ppt.find(tw * 1000 + th);
         if (it != c->ppt.end()) return it->second;
     }
-    return ppt_ok(tw, th, 2) ? 2 : 1;
+    return ppt_ok(tw, th, 2) ? 2 : (ppt_ok(tw, th, 1) ? 1 : 4);
+}
+
+int bwd_ppt_of(const gs_ctx* c, int tw, int th) {
+    if (c) {
+        auto it = c->ppt_bwd.find(tw * 1000 + th);
+        if (it != c->ppt_bwd.end()) return it->second;
+    }
+    return ppt_of(c, tw, th);
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -241,6 +253,31 @@ void resolve_tile(const gs_ctx* c, int32_t tw, int32_t th, int& otw, int& oth) {
         otw = tw;
         oth = th;
     }
+}
+
+// backward tile: the request, else the context's backward choice when the
+// bins are a multiple of it, else the forward tile
+void resolve_btile(const gs_ctx* c, int32_t btw, int32_t bth, int tw, int th, int bw, int bh, int& obtw,
+                   int& obth) {
+    if (btw != 0 || bth != 0) {
+        obtw = btw;
+        obth = bth;
+    } else if (c && c->btile_w != 0 && bw % c->btile_w == 0 && bh % c->btile_h == 0) {
+        obtw = c->btile_w;
+        obth = c->btile_h;
+    } else {
+        obtw = tw;
+        obth = th;
+    }
+}
+
+// view table of the backward's tiling (same bins as vt)
+int build_bwd_vt(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int btw, int bth, const gs::ViewTable& vt,
+                 float wc, float wd, gs::ViewTable& vtb) {
+    const int r = build_vt(c, cams, V, n, btw, bth, vt.bw, vt.bh, wc, wd, vtb);
+    if (r) return r;
+    vtb.ppt = bwd_ppt_of(c, btw, bth);
+    return GS_OK;
 }
 
 void resolve_bin(const gs_ctx* c, int32_t bw, int32_t bh, int& obw, int& obh) {
@@ -402,9 +439,24 @@ int gs_set_pixels_per_thread(gs_ctx* c, int32_t tw, int32_t th, int32_t ppt) {
     return GS_OK;
 }
 
-int gs_get_pixels_per_thread(const gs_ctx* c, int32_t tw, int32_t th) {
-    if (!c || !tile_ok(tw, th)) return GS_EINVAL;
-    return ppt_of(c, tw, th);
+int gs_get_pixels_per_thread(const gs_ctx* c, int32_t pass, int32_t tw, int32_t th) {
+    if (!c || !tile_ok(tw, th) || (pass != 0 && pass != 1)) return GS_EINVAL;
+    return pass == 0 ? ppt_of(c, tw, th) : bwd_ppt_of(c, tw, th);
+}
+
+int gs_set_bwd_shape(gs_ctx* c, int32_t tw, int32_t th, int32_t ppt) {
+    if (!c) return GS_EINVAL;
+    if (tw == 0 && th == 0) {
+        c->btile_w = c->btile_h = 0;
+        c->ppt_bwd.clear();
+        return GS_OK;
+    }
+    if (!ppt_ok(tw, th, ppt))
+        return fail(c, GS_EINVAL, "no compositing kernel for tile %dx%d with %d pixels per thread", tw, th, ppt);
+    c->btile_w = tw;
+    c->btile_h = th;
+    c->ppt_bwd[tw * 1000 + th] = ppt;
+    return GS_OK;
 }
 
 size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t cap, int32_t bw, int32_t bh) {
@@ -438,8 +490,11 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     int tw, th, bw, bh;
     resolve_tile(c, plan->tile_w, plan->tile_h, tw, th);
     resolve_bin(c, plan->bin_w, plan->bin_h, bw, bh);
-    gs::ViewTable vt;
+    gs::ViewTable vt, vtb;
     if ((r = build_vt(c, cams, V, g->n, tw, th, bw, bh, 0.f, 0.f, vt))) return r;
+    int btw, bth;
+    resolve_btile(c, plan->bwd_tile_w, plan->bwd_tile_h, tw, th, bw, bh, btw, bth);
+    if ((r = build_bwd_vt(c, cams, V, g->n, btw, bth, vt, 0.f, 0.f, vtb))) return r;
     const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false, max_tiles(cams, V));
     if (state_bytes < L.bytes)
         return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
@@ -452,6 +507,8 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     plan->tile_h = th;
     plan->bin_w = bw;
     plan->bin_h = bh;
+    plan->bwd_tile_w = btw;
+    plan->bwd_tile_h = bth;
     GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, nullptr, s));
     GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
@@ -480,12 +537,14 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     if (!poses || !state || !dL_dpose || !grads) return fail(c, GS_EINVAL, "a device pointer is NULL");
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->colors))
         return fail(c, GS_EINVAL, "a gradient pointer is NULL");
-    if (!tile_ok(plan->tile_w, plan->tile_h) || !bin_ok(plan->bin_w, plan->bin_h))
+    if (!tile_ok(plan->tile_w, plan->tile_h) || !bin_ok(plan->bin_w, plan->bin_h) ||
+        !tile_ok(plan->bwd_tile_w, plan->bwd_tile_h))
         return fail(c, GS_EINVAL, "plan does not come from a forward pass");
     if (plan->n_pairs > plan->pair_capacity) return fail(c, GS_ECAPACITY, "the forward pass overflowed");
-    gs::ViewTable vt;
+    gs::ViewTable vt, vtb;
     if ((r = build_vt(c, cams, V, g->n, plan->tile_w, plan->tile_h, plan->bin_w, plan->bin_h, 0.f, 0.f, vt)))
         return r;
+    if ((r = build_bwd_vt(c, cams, V, g->n, plan->bwd_tile_w, plan->bwd_tile_h, vt, 0.f, 0.f, vtb))) return r;
     const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false, max_tiles(cams, V));
     if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
     DeviceGuard dg(c->device);
@@ -494,7 +553,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     const gs::Params P = params_of(g);
     gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
     GS_HIP(c, gs::launch_zero_g2(p.rec.nt, p.g2, L.R, s));
-    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, p.ts, s));
+    GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, p.ts, vt, s));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, 0, p.posepart, L.pose_blocks, s));
     GS_HIP(c, gs::launch_pose_finalize(vt, p.posepart, L.pose_blocks, nullptr, 0.f, dL_dpose, s));
     return GS_OK;
@@ -671,7 +730,8 @@ const char* const kStageNames[] = {"preprocess_fwd", "binning",        "composit
                                    "loss_reproj",    "composite_bwd",  "preprocess_bwd", "optimizer"};
 constexpr int kNumStages = 8;
 
-int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::Layout& L, char* base, gs_gaussians* g,
+int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, const gs::Layout& L, char* base,
+                 gs_gaussians* g,
                  gs_gaussian_grads* grads, const gs_adam* adam, float* poses, const gs_targets* tg,
                  const gs_matches* mt, const gs_step_opts* o, float* color, float* depth, float* alpha,
                  float* loss_out, float* dL_dpose, hipStream_t s, hipEvent_t* ev = nullptr,
@@ -705,7 +765,8 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::Layout& L, char* 
     GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, ssim ? p.ssim_tiles : nullptr,
                                      o->w_color, o->w_depth, o->w_reproj, o->w_ssim, loss_out, s));
     GS_HIP(c, mark(5));
-    GS_HIP(c, gs::launch_composite_bwd(vt, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, s));
+    GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, vt,
+                                       s));
     GS_HIP(c, mark(6));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, o->accumulate_grads, p.posepart, L.pose_blocks,
                                         s));
@@ -746,7 +807,7 @@ namespace {
 int check_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_adam* adam, const gs_camera* cams,
                float* poses, int32_t V, const gs_targets* tg, const gs_matches* mt, const gs_step_opts* o, void* ws,
                size_t ws_bytes, float* color, float* depth, float* alpha, float* loss_out, float* dL_dpose,
-               gs::ViewTable& vt, gs::Layout& L) {
+               gs::ViewTable& vt, gs::ViewTable& vtb, gs::Layout& L) {
     if (!o) return fail(c, GS_EINVAL, "opts is NULL");
     int r = check_gaussians(c, g);
     if (r) return r;
@@ -770,6 +831,9 @@ int check_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_ad
     resolve_tile(c, o->tile_w, o->tile_h, tw, th);
     resolve_bin(c, o->bin_w, o->bin_h, bw, bh);
     if ((r = build_vt(c, cams, V, g->n, tw, th, bw, bh, o->w_color, o->w_depth, vt))) return r;
+    int btw, bth;
+    resolve_btile(c, o->bwd_tile_w, o->bwd_tile_h, tw, th, bw, bh, btw, bth);
+    if ((r = build_bwd_vt(c, cams, V, g->n, btw, bth, vt, o->w_color, o->w_depth, vtb))) return r;
     L = gs::make_layout(vt, g->n, o->pair_capacity, true, max_tiles(cams, V));
     if (ws_bytes < L.bytes) return fail(c, GS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
     return GS_OK;
@@ -782,16 +846,16 @@ int gs_mapping_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const 
                     const gs_step_opts* o, void* ws, size_t ws_bytes, float* color, float* depth, float* alpha,
                     float* loss_out, float* dL_dpose, void* stream) {
     if (!c) return GS_EINVAL;
-    gs::ViewTable vt;
+    gs::ViewTable vt, vtb;
     gs::Layout L;
     int r = check_step(c, g, grads, adam, cams, poses, V, tg, mt, o, ws, ws_bytes, color, depth, alpha, loss_out,
-                       dL_dpose, vt, L);
+                       dL_dpose, vt, vtb, L);
     if (r) return r;
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
     if (!o->use_graph)
-        return enqueue_step(c, vt, L, base, g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
+        return enqueue_step(c, vt, vtb, L, base, g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
                             dL_dpose, s);
     // the null stream cannot be captured: capture and replay on the context's
     // own stream, ordered after the caller's earlier work and before its later
@@ -810,6 +874,7 @@ int gs_mapping_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const 
     // cache key: every argument the captured launches bake in
     uint64_t h = 1469598103934665603ull;
     h = fnv(h, &vt, sizeof vt);
+    h = fnv(h, &vtb, sizeof vtb);
     h = fnv(h, g, sizeof *g);
     h = fnv(h, grads, sizeof *grads);
     gs_adam ad = adam ? *adam : gs_adam{nullptr, nullptr, nullptr};
@@ -824,7 +889,7 @@ int gs_mapping_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const 
     auto it = c->graphs.find(h);
     if (it == c->graphs.end()) {
         GS_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_step(c, vt, L, base, g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
+        int rc = enqueue_step(c, vt, vtb, L, base, g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
                               dL_dpose, s);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(s, &graph);
@@ -857,10 +922,10 @@ int gs_step_profile(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const 
                     float* loss_out, float* dL_dpose, float* stage_ms, int64_t* frag_counts, void* stream) {
     if (!c) return GS_EINVAL;
     if (!stage_ms) return fail(c, GS_EINVAL, "stage_ms is NULL");
-    gs::ViewTable vt;
+    gs::ViewTable vt, vtb;
     gs::Layout L;
     int r = check_step(c, g, grads, adam, cams, poses, V, tg, mt, o, ws, ws_bytes, color, depth, alpha, loss_out,
-                       dL_dpose, vt, L);
+                       dL_dpose, vt, vtb, L);
     if (r) return r;
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -871,7 +936,7 @@ int gs_step_profile(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const 
     };
     hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t*>(c->counts), 0u, 8, s);
     if (e != hipSuccess) { destroy(); return hip_fail(c, e, "counter fill"); }
-    r = enqueue_step(c, vt, L, static_cast<char*>(ws), g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
+    r = enqueue_step(c, vt, vtb, L, static_cast<char*>(ws), g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
                      dL_dpose, s, ev, frag_counts ? c->counts : nullptr);
     if (r) { destroy(); return r; }
     unsigned long long hc[4] = {0, 0, 0, 0};
@@ -939,9 +1004,11 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
 }
 
 int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
-                int32_t iters, int32_t* tile_w, int32_t* tile_h, int32_t* bin_w, int32_t* bin_h, void* stream) {
+                int32_t iters, int32_t* tile_w, int32_t* tile_h, int32_t* bin_w, int32_t* bin_h, int32_t* bwd_tile_w,
+                int32_t* bwd_tile_h, void* stream) {
     if (!c) return GS_EINVAL;
-    if (!tile_w || !tile_h || !bin_w || !bin_h) return fail(c, GS_EINVAL, "an output pointer is NULL");
+    if (!tile_w || !tile_h || !bin_w || !bin_h || !bwd_tile_w || !bwd_tile_h)
+        return fail(c, GS_EINVAL, "an output pointer is NULL");
     int r = check_gaussians(c, g);
     if (r) return r;
     if (!poses) return fail(c, GS_EINVAL, "poses is NULL");
@@ -959,6 +1026,9 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
         c->bin_w = *bin_w = t.bw;
         c->bin_h = *bin_h = t.bh;
         c->ppt[t.tw * 1000 + t.th] = t.ppt;
+        c->btile_w = *bwd_tile_w = t.btw;
+        c->btile_h = *bwd_tile_h = t.bth;
+        c->ppt_bwd[t.btw * 1000 + t.bth] = t.bppt;
     };
     auto hit = c->tuned.find(key);
     if (hit != c->tuned.end()) {
@@ -998,66 +1068,112 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     const auto saved_ppt = c->ppt;
-    // time forward + backward of one launch shape; < 0 on failure
-    auto time_shape = [&](int tw, int th, int ppt, int bw, int bh, int* rc) -> float {
+    const auto saved_ppt_bwd = c->ppt_bwd;
+    hipEvent_t e2;
+    (void)hipEventCreate(&e2);
+    // time the forward and the backward of one launch configuration (summed
+    // over iters replays after one warm-up); false on failure
+    auto time_cfg = [&](int tw, int th, int ppt, int btw, int bth, int bppt, int bw, int bh, float* fwd_ms,
+                        float* bwd_ms, int* rc) -> bool {
         c->ppt[tw * 1000 + th] = ppt;
-        gs_plan plan{tw, th, bw, bh, 0, 0, 0};
+        c->ppt_bwd[btw * 1000 + bth] = bppt;
+        gs_plan plan{tw, th, bw, bh, 0, 0, 0, btw, bth};
         void* st = nullptr;
         size_t sb = gs_state_bytes(cams, V, n, 0, bw, bh);
-        if (hipMalloc(&st, sb) != hipSuccess) { *rc = fail(c, GS_ENOMEM, "autotune state"); return -1.f; }
+        if (hipMalloc(&st, sb) != hipSuccess) { *rc = fail(c, GS_ENOMEM, "autotune state"); return false; }
         int f = gs_render_forward(c, g, cams, poses, V, img, img + 3 * npix, img + 4 * npix, st, sb, &plan, stream);
         (void)hipFree(st);
-        if (f != GS_OK && f != GS_ECAPACITY) { *rc = f; return -1.f; }
+        if (f != GS_OK && f != GS_ECAPACITY) { *rc = f; return false; }
         plan.pair_capacity = plan.n_pairs;
         sb = gs_state_bytes(cams, V, n, plan.pair_capacity, bw, bh);
-        if (hipMalloc(&st, sb) != hipSuccess) { *rc = fail(c, GS_ENOMEM, "autotune state"); return -1.f; }
-        float total = 0.f;
+        if (hipMalloc(&st, sb) != hipSuccess) { *rc = fail(c, GS_ENOMEM, "autotune state"); return false; }
+        *fwd_ms = *bwd_ms = 0.f;
         for (int it = 0; it <= iters; it++) {
             (void)hipEventRecord(e0, s);
             int a = gs_render_forward(c, g, cams, poses, V, img, img + 3 * npix, img + 4 * npix, st, sb, &plan, stream);
+            (void)hipEventRecord(e1, s);
             int b = a == GS_OK ? gs_render_backward(c, g, cams, poses, V, st, sb, &plan, img, img + 3 * npix,
                                                     img + 4 * npix, &G, dpose, stream)
                                : a;
-            (void)hipEventRecord(e1, s);
-            (void)hipEventSynchronize(e1);
+            (void)hipEventRecord(e2, s);
+            (void)hipEventSynchronize(e2);
             if (b != GS_OK) { *rc = b; break; }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (it > 0) total += ms;
+            float m1 = 0.f, m2 = 0.f;
+            (void)hipEventElapsedTime(&m1, e0, e1);
+            (void)hipEventElapsedTime(&m2, e1, e2);
+            if (it > 0) { *fwd_ms += m1; *bwd_ms += m2; }
         }
         (void)hipFree(st);
-        return *rc == GS_OK ? total : -1.f;
+        return *rc == GS_OK;
     };
-    // stage 1: tile shape and pixels per thread, bins 64x64 (or the tile's multiple)
-    const int cand[12][3] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {16, 8, 1}, {16, 8, 2}, {8, 8, 1},
-                             {32, 8, 1},  {32, 8, 2},  {32, 8, 4},  {32, 16, 1}, {32, 16, 2}, {32, 16, 4}};
-    gs_ctx::Tuned best{16, 16, 64, 64, 2};
-    float best_ms = 1e30f;
+    // stage 1: the forward's and the backward's tile shape and pixels per
+    // thread, chosen separately, bins 64x64
+    const int cand[15][3] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {16, 8, 1},  {16, 8, 2},
+                             {8, 8, 1},   {32, 8, 1},  {32, 8, 2},  {32, 8, 4},  {32, 16, 1},
+                             {32, 16, 2}, {32, 16, 4}, {32, 16, 8}, {32, 32, 4}, {32, 32, 8}};
+    gs_ctx::Tuned best{16, 16, 64, 64, 2, 16, 16, 2};
+    float best_f = 1e30f, best_b = 1e30f;
     int rc = GS_OK;
-    for (int k = 0; k < 12 && rc == GS_OK; k++) {
-        const float ms = time_shape(cand[k][0], cand[k][1], cand[k][2], 64, 64, &rc);
-        if (rc == GS_OK && ms < best_ms) {
-            best_ms = ms;
-            best = gs_ctx::Tuned{cand[k][0], cand[k][1], 64, 64, cand[k][2]};
+    for (int k = 0; k < 15 && rc == GS_OK; k++) {
+        float fm, bm;
+        if (!time_cfg(cand[k][0], cand[k][1], cand[k][2], cand[k][0], cand[k][1], cand[k][2], 64, 64, &fm, &bm, &rc))
+            break;
+        if (fm < best_f) {
+            best_f = fm;
+            best.tw = cand[k][0]; best.th = cand[k][1]; best.ppt = cand[k][2];
+        }
+        if (bm < best_b) {
+            best_b = bm;
+            best.btw = cand[k][0]; best.bth = cand[k][1]; best.bppt = cand[k][2];
         }
     }
-    // stage 2: bin size for that tile
+    // stage 2: bin size for those two shapes
+    float best_ms = 1e30f;
+    if (rc == GS_OK) {
+        float fm, bm;
+        if (time_cfg(best.tw, best.th, best.ppt, best.btw, best.bth, best.bppt, 64, 64, &fm, &bm, &rc))
+            best_ms = fm + bm;
+    }
     const int bins[9][2] = {{32, 16}, {32, 32}, {64, 32}, {64, 64}, {128, 64}, {128, 128}, {256, 128}, {256, 256},
                             {512, 256}};
     for (int k = 0; k < 9 && rc == GS_OK; k++) {
         const int bw = bins[k][0], bh = bins[k][1];
-        if (bw % best.tw || bh % best.th || (bw == 64 && bh == 64)) continue;
-        const float ms = time_shape(best.tw, best.th, best.ppt, bw, bh, &rc);
-        if (rc == GS_OK && ms < best_ms) {
-            best_ms = ms;
+        if (bw % best.tw || bh % best.th || bw % best.btw || bh % best.bth || (bw == 64 && bh == 64)) continue;
+        float fm, bm;
+        if (!time_cfg(best.tw, best.th, best.ppt, best.btw, best.bth, best.bppt, bw, bh, &fm, &bm, &rc)) break;
+        if (fm + bm < best_ms) {
+            best_ms = fm + bm;
             best.bw = bw;
             best.bh = bh;
         }
     }
+    // stage 3: the two shapes again at the chosen bins
+    if (rc == GS_OK && (best.bw != 64 || best.bh != 64)) {
+        float bf = 1e30f, bb = 1e30f;
+        gs_ctx::Tuned t3 = best;
+        for (int k = 0; k < 15 && rc == GS_OK; k++) {
+            if (best.bw % cand[k][0] || best.bh % cand[k][1]) continue;
+            float fm, bm;
+            if (!time_cfg(cand[k][0], cand[k][1], cand[k][2], cand[k][0], cand[k][1], cand[k][2], best.bw, best.bh,
+                          &fm, &bm, &rc))
+                break;
+            if (fm < bf) {
+                bf = fm;
+                t3.tw = cand[k][0]; t3.th = cand[k][1]; t3.ppt = cand[k][2];
+            }
+            if (bm < bb) {
+                bb = bm;
+                t3.btw = cand[k][0]; t3.bth = cand[k][1]; t3.bppt = cand[k][2];
+            }
+        }
+        if (rc == GS_OK) best = t3;
+    }
+    (void)hipEventDestroy(e2);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release();
     c->ppt = saved_ppt;
+    c->ppt_bwd = saved_ppt_bwd;
     if (rc != GS_OK) return rc;
     c->tuned[key] = best;
     apply(best);

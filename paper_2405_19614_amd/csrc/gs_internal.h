@@ -53,6 +53,26 @@ struct ViewTable {
     ViewInfo v[kMaxViews];
 };
 
+// The compositing tiles of a ViewTable, compact enough to pass beside one.
+struct TileGrid {
+    int tw, th;
+    int tile_off[kMaxViews];
+    int tiles_x[kMaxViews];
+    int tiles_y[kMaxViews];
+};
+
+inline TileGrid tile_grid(const ViewTable& vt) {
+    TileGrid g{};
+    g.tw = vt.tw;
+    g.th = vt.th;
+    for (int v = 0; v < vt.V; v++) {
+        g.tile_off[v] = vt.v[v].tile_off;
+        g.tiles_x[v] = vt.v[v].tiles_x;
+        g.tiles_y[v] = vt.v[v].tiles_y;
+    }
+    return g;
+}
+
 // Gaussian parameters (device, FP32 SoA).
 struct Params {
     const float* means;
@@ -181,9 +201,12 @@ hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const 
                                 float* color, float* depth, float* alpha, float* tfin, uint32_t* last,
                                 const LossArgs* loss, const TileSched& ts, hipStream_t s,
                                 unsigned long long* counts = nullptr);
+// vt: the backward's own tiling (same bins); vtf: the forward's tiling, whose
+// per-tile work orders the backward's tiles
 hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                                 const float* tfin, const uint32_t* last, const float* dC, const float* dD,
-                                const float* dA, float* g2, const TileSched& ts, hipStream_t s);
+                                const float* dA, float* g2, const TileSched& ts, const ViewTable& vtf,
+                                hipStream_t s);
 
 // loss_out [1 + 4V]: total, then (Lc, Ld, Lr, Ls) per view; ssim_part (nullable)
 // holds per-(channel, SSIM tile) sums of the SSIM map, channel-major

@@ -462,15 +462,24 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
 constexpr int kOrderBuckets = 128;
 constexpr int kOrderThreads = 1024;
 
-__device__ __forceinline__ int order_bucket(const ViewTable& vt, const uint2* ranges, const uint32_t* work, int t) {
-    uint32_t w;
+// work estimate of tile t of vt: with `work` (per tile of vtf, the forward's
+// tiling), the sum over the forward tiles that overlap it; else its bin's
+// list length
+__device__ __forceinline__ int order_bucket(const ViewTable& vt, const TileGrid& vtf, const uint2* ranges,
+                                            const uint32_t* work, int t) {
+    const int v = view_of_tile(vt, t);
+    const ViewInfo& vi = vt.v[v];
+    const int lt = t - vi.tile_off;
+    const int tyi = lt / vi.tiles_x, txi = lt - tyi * vi.tiles_x;
+    uint32_t w = 0u;
     if (work) {
-        w = work[t];
+        const int x0 = txi * vt.tw, y0 = tyi * vt.th;
+        const int fx0 = x0 / vtf.tw, fy0 = y0 / vtf.th;
+        const int fx1 = min((x0 + vt.tw - 1) / vtf.tw, vtf.tiles_x[v] - 1);
+        const int fy1 = min((y0 + vt.th - 1) / vtf.th, vtf.tiles_y[v] - 1);
+        for (int fy = fy0; fy <= fy1; fy++)
+            for (int fx = fx0; fx <= fx1; fx++) w += work[vtf.tile_off[v] + fy * vtf.tiles_x[v] + fx];
     } else {
-        const int v = view_of_tile(vt, t);
-        const ViewInfo& vi = vt.v[v];
-        const int lt = t - vi.tile_off;
-        const int tyi = lt / vi.tiles_x, txi = lt - tyi * vi.tiles_x;
         const uint2 rg = ranges[bin_of_tile(vt, vi, txi, tyi, vt.tw, vt.th)];
         w = rg.y - rg.x;
     }
@@ -479,14 +488,15 @@ __device__ __forceinline__ int order_bucket(const ViewTable& vt, const uint2* ra
     return kOrderBuckets - 1 - (int)min(b, (uint32_t)(kOrderBuckets - 1));
 }
 
-__global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt, const uint2* __restrict__ ranges,
+__global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt, TileGrid vtf,
+                                                                    const uint2* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ work,
                                                                     uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[kOrderBuckets];
     const int n = vt.n_tiles;
     for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) cnt[i] = 0u;
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += kOrderThreads) atomicAdd(&cnt[order_bucket(vt, ranges, work, t)], 1u);
+    for (int t = threadIdx.x; t < n; t += kOrderThreads) atomicAdd(&cnt[order_bucket(vt, vtf, ranges, work, t)], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t acc = 0u;
@@ -498,7 +508,7 @@ __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt
     }
     __syncthreads();
     for (int t = threadIdx.x; t < n; t += kOrderThreads)
-        order[atomicAdd(&cnt[order_bucket(vt, ranges, work, t)], 1u)] = (uint32_t)t;
+        order[atomicAdd(&cnt[order_bucket(vt, vtf, ranges, work, t)], 1u)] = (uint32_t)t;
 }
 
 template <int TW, int TH, int PPT>
@@ -526,10 +536,10 @@ hipError_t fwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals,
 template <int TW, int TH, int PPT>
 hipError_t bwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                  const float* tfin, const uint32_t* last, const float* dC, const float* dD, const float* dA,
-                 float* g2, const TileSched& ts, hipStream_t s) {
+                 float* g2, const TileSched& ts, const ViewTable& vtf, hipStream_t s) {
     if (vt.n_tiles == 0) return hipSuccess;
     constexpr int NT = TW * TH / PPT;
-    order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt, ranges, ts.work, ts.order);
+    order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt, tile_grid(vtf), ranges, ts.work, ts.order);
     composite_bwd_kernel<TW, TH, PPT><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2,
                                                                  ts.order);
     return hipGetLastError();
@@ -552,6 +562,9 @@ hipError_t bwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals,
     if (vt.tw == 32 && vt.th == 16 && vt.ppt == 1) return FN<32, 16, 1>(__VA_ARGS__); \
     if (vt.tw == 32 && vt.th == 16 && vt.ppt == 2) return FN<32, 16, 2>(__VA_ARGS__); \
     if (vt.tw == 32 && vt.th == 16 && vt.ppt == 4) return FN<32, 16, 4>(__VA_ARGS__); \
+    if (vt.tw == 32 && vt.th == 16 && vt.ppt == 8) return FN<32, 16, 8>(__VA_ARGS__); \
+    if (vt.tw == 32 && vt.th == 32 && vt.ppt == 4) return FN<32, 32, 4>(__VA_ARGS__); \
+    if (vt.tw == 32 && vt.th == 32 && vt.ppt == 8) return FN<32, 32, 8>(__VA_ARGS__); \
     return hipErrorInvalidValue;
 
 hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
@@ -563,8 +576,9 @@ hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const 
 
 hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                                 const float* tfin, const uint32_t* last, const float* dC, const float* dD,
-                                const float* dA, float* g2, const TileSched& ts, hipStream_t s) {
-    GS_TILE_DISPATCH(bwd_t, vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2, ts, s)
+                                const float* dA, float* g2, const TileSched& ts, const ViewTable& vtf,
+                                hipStream_t s) {
+    GS_TILE_DISPATCH(bwd_t, vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2, ts, vtf, s)
 }
 
 #undef GS_TILE_DISPATCH

@@ -52,7 +52,8 @@ def test_null_context_rejected_without_device_work(lib):
     rc = lib.gs_render_forward(None, None, None, None, 1, None, None, None, None, 0, ctypes.byref(plan), None)
     assert rc == A.GS_EINVAL
     assert lib.gs_set_tile(None, 16, 16) == A.GS_EINVAL
-    assert lib.gs_get_pixels_per_thread(None, 16, 16) == A.GS_EINVAL
+    assert lib.gs_get_pixels_per_thread(None, 0, 16, 16) == A.GS_EINVAL
+    assert lib.gs_set_bwd_shape(None, 32, 32, 4) == A.GS_EINVAL
 
 
 def test_state_bytes_validation(lib):

@@ -70,7 +70,8 @@ def test_backward_matches_oracle(ctx, name):
 
 
 LAUNCH_SHAPES = [(16, 16, 1), (16, 16, 2), (16, 16, 4), (16, 8, 1), (16, 8, 2), (8, 8, 1), (32, 8, 1),
-                 (32, 8, 2), (32, 8, 4), (32, 16, 1), (32, 16, 2), (32, 16, 4)]
+                 (32, 8, 2), (32, 8, 4), (32, 16, 1), (32, 16, 2), (32, 16, 4), (32, 16, 8), (32, 32, 4),
+                 (32, 32, 8)]
 
 
 def test_forward_bit_identical_across_tile_shapes(ctx):
@@ -240,3 +241,30 @@ def test_empty_and_culled_scenes(ctx):
                                   np.zeros((0, 3)), -1)
     c, d, a, st, plan = ctx.forward(g0, s0.cams, poses)
     assert plan.n_pairs == 0 and float(c.abs().max()) == 0
+
+
+@pytest.mark.parametrize("fwd,bwd", [((16, 16, 4), (32, 32, 8)), ((32, 32, 4), (8, 8, 1)), ((32, 8, 2), (32, 16, 4))])
+def test_backward_with_its_own_tile_shape(ctx, fwd, bwd):
+    """The backward on a different tiling than the forward (ordered by the
+    forward's per-tile work) gives the oracle's gradients."""
+    s = SCENES["c3_small"]
+    print(f"[split-shape] forward {fwd} backward {bwd}", flush=True)
+    g, poses = dev_scene(s)
+    ctx.set_tile(fwd[0], fwd[1], fwd[2])
+    ctx.set_bwd_shape(*bwd)
+    color, depth, alpha, state, plan = ctx.forward(g, s.cams, poses, tile=fwd[:2])
+    assert (plan.bwd_tile_w, plan.bwd_tile_h) == bwd[:2]
+    og, ref = oracle_views(s)
+    dC, dD, dA = cotangents(s, ref, seed=17)
+    t = lambda a: torch.tensor(a, device="cuda")
+    grads, dpose = ctx.backward(g, s.cams, poses, state, plan, t(dC), t(dD), t(dA))
+    torch.cuda.synchronize()
+    ctx.set_bwd_shape(0, 0, 0)
+    ctx.set_tile(16, 16, 2)
+    rg = O.backward_views(og, s.cams, s.poses, dC, dD, dA)
+    for nm in GRAD_NAMES:
+        e = rel(getattr(grads, nm).cpu().numpy(), rg[nm])
+        assert e < TOL_G, (nm, e)
+    for v in range(s.V):
+        assert rel(dpose[v].cpu().numpy(), rg["pose"][v]) < TOL_G
+
