@@ -192,7 +192,8 @@ def main():
             ctx.set_bwd_shape(vals[5], vals[6], vals[7])
         tile, binsz = (tw, th), (bw, bh)
     btile = ctx.bwd_tile_choice if ctx.bwd_tile_choice != (0, 0) else tile
-    log(f"[bench] tile {tile} bin {binsz} backward tile {btile}")
+    ppt_f, ppt_b = ctx.ppt_choice(tile), ctx.ppt_choice(btile, True)
+    log(f"[bench] tile {tile} x{ppt_f} bin {binsz} backward tile {btile} x{ppt_b}")
     base = dict(w_color=1.0, w_depth=0.1, w_reproj=0.0, tile=tile, bin=binsz, use_graph=True)
 
     # batched fwd+bwd (no update): the value
@@ -297,7 +298,7 @@ def main():
                                f"{args.width}x{args.height}, f=600, L1 colour + 0.1 L1 depth",
                    "gaussians": s.n, "views": s.V, "width": args.width, "height": args.height,
                    "pixels_per_step": npix, "tile": f"{tile[0]}x{tile[1]}", "bin": f"{binsz[0]}x{binsz[1]}",
-                   "bwd_tile": f"{btile[0]}x{btile[1]}"},
+                   "bwd_tile": f"{btile[0]}x{btile[1]}", "pixels_per_thread": [ppt_f, ppt_b]},
         "mapping_iters_per_s": round(iters, 3),
         "ms_per_mapping_iter": round(ms_map, 4),
         "paper_mapping_loss_iters_per_s": round(1000.0 / ms_paper, 3),

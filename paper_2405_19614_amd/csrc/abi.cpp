@@ -350,7 +350,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
         L.off_dC = take((size_t)vt.n_pix * 3 * 4);
         L.off_dD = take((size_t)vt.n_pix * 4);
         L.off_tilepart = take((size_t)tb * 16);
-        L.off_rpacc = take((size_t)vt.V * 8 * 8);
+        L.off_rpacc = take((size_t)vt.V * 9 * 8);   // 8 accumulators per view, then the per-view loss totals
         L.off_ssim_part = take((size_t)vt.n_pix * 9 * 4);
         L.off_ssim_tiles = take((size_t)vt.n_ssim_tiles * 3 * 8);
     }
@@ -763,7 +763,8 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
         GS_HIP(c, gs::launch_reproj(vt, poses, mt->points, mt->uv, mt->view_idx, mt->M, o->huber_delta, nullptr,
                                     p.rpacc, s));
     GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, ssim ? p.ssim_tiles : nullptr,
-                                     o->w_color, o->w_depth, o->w_reproj, o->w_ssim, loss_out, s));
+                                     o->w_color, o->w_depth, o->w_reproj, o->w_ssim, loss_out, p.rpacc + 8 * vt.V,
+                                     s));
     GS_HIP(c, mark(5));
     GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, vt,
                                        s));

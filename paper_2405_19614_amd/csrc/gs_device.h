@@ -103,24 +103,56 @@ struct Proj {
     int x0, x1, y0, y1;
 };
 
-// Project Gaussian g into view vi with pose T (row-major 4x4, world->camera).
-// COL: also evaluate the colour (RGB or SH).
-template <bool COL>
-__device__ __forceinline__ void project_one(const Params& P, int g, const ViewInfo& vi, const float* T, Proj& o) {
-    o.valid = false;
+// View-independent part of a Gaussian's projection: activations and the
+// world covariance M = R diag(s^2) R^T.
+struct GPrep {
+    bool ok;
+    float qn, qh[4], R[9], s[3], o;
+    float mu[3];
+    float M[6];
+};
+
+__device__ __forceinline__ void gauss_prep(const Params& P, int g, GPrep& gp) {
+    gp.ok = false;
     const float4 q = reinterpret_cast<const float4*>(P.q)[g];
     const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
     if (!(qn2 > 0.f)) return;
-    o.qn = sqrtf(qn2);
-    const float iq = 1.f / o.qn;
-    o.qh[0] = q.x * iq; o.qh[1] = q.y * iq; o.qh[2] = q.z * iq; o.qh[3] = q.w * iq;
-    quat_rot(o.qh[0], o.qh[1], o.qh[2], o.qh[3], o.R);
+    gp.ok = true;
+    gp.qn = sqrtf(qn2);
+    const float iq = 1.f / gp.qn;
+    gp.qh[0] = q.x * iq; gp.qh[1] = q.y * iq; gp.qh[2] = q.z * iq; gp.qh[3] = q.w * iq;
+    quat_rot(gp.qh[0], gp.qh[1], gp.qh[2], gp.qh[3], gp.R);
     const float* lsp = P.ls + 3 * (int64_t)g;
-    o.s[0] = expf(lsp[0]); o.s[1] = expf(lsp[1]); o.s[2] = expf(lsp[2]);
-    o.o = 1.f / (1.f + expf(-P.opl[g]));
-
+    gp.s[0] = expf(lsp[0]); gp.s[1] = expf(lsp[1]); gp.s[2] = expf(lsp[2]);
+    gp.o = 1.f / (1.f + expf(-P.opl[g]));
     const float* mu = P.means + 3 * (int64_t)g;
-    const float mx = mu[0], my = mu[1], mz = mu[2];
+    gp.mu[0] = mu[0]; gp.mu[1] = mu[1]; gp.mu[2] = mu[2];
+    const float s0 = gp.s[0] * gp.s[0], s1 = gp.s[1] * gp.s[1], s2 = gp.s[2] * gp.s[2];
+    const float* R = gp.R;
+    gp.M[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
+    gp.M[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
+    gp.M[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
+    gp.M[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
+    gp.M[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
+    gp.M[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
+}
+
+// Project a prepared Gaussian g into view vi with pose T (row-major 4x4,
+// world->camera).  COL: also evaluate the colour (RGB or SH).
+template <bool COL>
+__device__ __forceinline__ void project_view(const Params& P, int g, const GPrep& gp, const ViewInfo& vi,
+                                             const float* T, Proj& o) {
+    o.valid = false;
+    if (!gp.ok) return;
+    o.qn = gp.qn;
+#pragma unroll
+    for (int k = 0; k < 4; k++) o.qh[k] = gp.qh[k];
+#pragma unroll
+    for (int k = 0; k < 9; k++) o.R[k] = gp.R[k];
+    o.s[0] = gp.s[0]; o.s[1] = gp.s[1]; o.s[2] = gp.s[2];
+    o.o = gp.o;
+
+    const float mx = gp.mu[0], my = gp.mu[1], mz = gp.mu[2];
     o.p[0] = T[0] * mx + T[1] * my + T[2] * mz + T[3];
     o.p[1] = T[4] * mx + T[5] * my + T[6] * mz + T[7];
     o.p[2] = T[8] * mx + T[9] * my + T[10] * mz + T[11];
@@ -143,18 +175,8 @@ __device__ __forceinline__ void project_one(const Params& P, int g, const ViewIn
     o.j02 = -vi.fx * o.tx * iz * iz;
     o.j12 = -vi.fy * o.ty * iz * iz;
 
-    // world covariance M = R diag(s^2) R^T, then Sigma_c = W M W^T
-    float M[6];
-    {
-        const float s0 = o.s[0] * o.s[0], s1 = o.s[1] * o.s[1], s2 = o.s[2] * o.s[2];
-        const float* R = o.R;
-        M[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
-        M[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
-        M[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
-        M[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
-        M[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
-        M[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
-    }
+    // Sigma_c = W M W^T with the world covariance M of gauss_prep
+    const float* M = gp.M;
     {
         // WM = W * M (full 3x3), Sc = WM * W^T (symmetric)
         float Mf[9] = {M[0], M[1], M[2], M[1], M[3], M[4], M[2], M[4], M[5]};
@@ -234,6 +256,13 @@ __device__ __forceinline__ void project_one(const Params& P, int g, const ViewIn
     if (!(fx0 <= fx1) || !(fy0 <= fy1)) return;
     o.x0 = (int)fx0; o.x1 = (int)fx1; o.y0 = (int)fy0; o.y1 = (int)fy1;
     o.valid = true;
+}
+
+template <bool COL>
+__device__ __forceinline__ void project_one(const Params& P, int g, const ViewInfo& vi, const float* T, Proj& o) {
+    GPrep gp;
+    gauss_prep(P, g, gp);
+    project_view<COL>(P, g, gp, vi, T, o);
 }
 
 // Records keep the conic in base-2 units with the opacity folded in:

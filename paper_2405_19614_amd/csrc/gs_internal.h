@@ -131,7 +131,7 @@ struct Layout {
     // mapping workspace only
     size_t off_dC, off_dD;                        // upstream gradients
     size_t off_tilepart;                          // tile partials (sized for the smallest tile)
-    size_t off_rpacc;                             // V * 8 doubles
+    size_t off_rpacc;                             // V * 9 doubles (accumulators, per-view loss)
     size_t off_ssim_part;                         // 9 * n_pix floats (SSIM partials)
     size_t off_ssim_tiles;                        // 3 * n_ssim_tiles doubles
     size_t bytes;
@@ -210,9 +210,10 @@ hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const 
 
 // loss_out [1 + 4V]: total, then (Lc, Ld, Lr, Ls) per view; ssim_part (nullable)
 // holds per-(channel, SSIM tile) sums of the SSIM map, channel-major
+// view_tot: device double [V] scratch
 hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc,
                               const double* ssim_part, float w_color, float w_depth, float w_reproj, float w_ssim,
-                              float* loss_out, hipStream_t s);
+                              float* loss_out, double* view_tot, hipStream_t s);
 
 // SSIM (mapping loss, Sec. 3.4) of planar colour images img against ref.
 // part: device float [9 * n_pix] scratch (per pixel and channel: the SSIM map's

@@ -1,7 +1,8 @@
 // Projection of every (view, Gaussian) pair and its reverse mode.
 //
-// Forward (Sec. 3.4 "Projection"): one thread per (view, Gaussian), writes the
-// 2D record (mean, conic + opacity, colour + depth, pixel rect, bin count).
+// Forward (Sec. 3.4 "Projection"): one thread per Gaussian looping over the
+// views, writes each (view, Gaussian) 2D record (mean, conic + opacity,
+// colour + depth, pixel rect, bin count).
 // Backward: one thread per Gaussian looping over the views, so each
 // Gaussian's parameter gradient is summed in registers (no atomics) and the
 // per-view pose 6-vector is reduced per block in FP64 (deterministic).
@@ -13,34 +14,40 @@ namespace {
 
 constexpr int kProjBlock = 256;
 
+// One thread per Gaussian, looping over the views: the parameters come from
+// HBM once and stay in the thread's cache lines for the other views.
 __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt, Params P, const float* poses,
                                                                     Records rec, float* g2_zero) {
     const int g = blockIdx.x * kProjBlock + threadIdx.x;
-    const int v = blockIdx.y;
     if (g >= P.n) return;
-    const ViewInfo& vi = vt.v[v];
-    float T[12];
+    GPrep gp;
+    gauss_prep(P, g, gp);
+    for (int v = 0; v < vt.V; v++) {
+        const ViewInfo& vi = vt.v[v];
+        float T[12];
 #pragma unroll
-    for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
-    Proj pr;
-    project_one<true>(P, g, vi, T, pr);
-    const int64_t r = (int64_t)v * P.n + g;
-    if (!pr.valid) {
-        rec.nt[r] = 0u;
-        return;
-    }
-    const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
-    const uint32_t ty0 = (uint32_t)pr.y0 / vt.bh, ty1 = (uint32_t)pr.y1 / vt.bh;
-    rec.xy[r] = make_float2(pr.u, pr.v);
-    // base-2 conic with log2(opacity) (the compositing kernels' form)
-    rec.conic[r] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
-    rec.col[r] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);
-    rec.rect[r] = make_uint2((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16), (uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16));
-    rec.nt[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-    if (g2_zero) {
-        float4* z = reinterpret_cast<float4*>(g2_zero + r * kG2Stride);
-        const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-        z[0] = zero; z[1] = zero; z[2] = zero;
+        for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
+        Proj pr;
+        project_view<true>(P, g, gp, vi, T, pr);
+        const int64_t r = (int64_t)v * P.n + g;
+        if (!pr.valid) {
+            rec.nt[r] = 0u;
+            continue;
+        }
+        const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
+        const uint32_t ty0 = (uint32_t)pr.y0 / vt.bh, ty1 = (uint32_t)pr.y1 / vt.bh;
+        rec.xy[r] = make_float2(pr.u, pr.v);
+        // base-2 conic with log2(opacity) (the compositing kernels' form)
+        rec.conic[r] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
+        rec.col[r] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);
+        rec.rect[r] =
+            make_uint2((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16), (uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16));
+        rec.nt[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        if (g2_zero) {
+            float4* z = reinterpret_cast<float4*>(g2_zero + r * kG2Stride);
+            const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+            z[0] = zero; z[1] = zero; z[2] = zero;
+        }
     }
 }
 
@@ -83,6 +90,9 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_bwd_kernel(ViewTable vt
     float gc[3 * K];
 #pragma unroll
     for (int k = 0; k < 3 * K; k++) gc[k] = 0.f;
+    GPrep gp;
+    gp.ok = false;
+    if (live) gauss_prep(P, g, gp);
 
     for (int v = 0; v < vt.V; v++) {
         float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -93,7 +103,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_bwd_kernel(ViewTable vt
 #pragma unroll
             for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
             Proj pr;
-            project_one<true>(P, g, vi, T, pr);
+            project_view<true>(P, g, gp, vi, T, pr);
             const float4* a4 = reinterpret_cast<const float4*>(g2 + r * kG2Stride);
             const float4 a0 = a4[0], a1 = a4[1], a2 = a4[2];
             // undo the compositing kernel's constant factors (g2 layout)
@@ -311,8 +321,7 @@ __global__ __launch_bounds__(256) void pose_finalize_kernel(const double* part, 
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
                                  float* g2_zero, hipStream_t s) {
     if (P.n == 0) return hipSuccess;
-    dim3 grid((P.n + kProjBlock - 1) / kProjBlock, vt.V);
-    preprocess_fwd_kernel<<<grid, kProjBlock, 0, s>>>(vt, P, poses, rec, g2_zero);
+    preprocess_fwd_kernel<<<(P.n + kProjBlock - 1) / kProjBlock, kProjBlock, 0, s>>>(vt, P, poses, rec, g2_zero);
     return hipGetLastError();
 }
 

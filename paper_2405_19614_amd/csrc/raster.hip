@@ -493,10 +493,21 @@ __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt
                                                                     const uint32_t* __restrict__ work,
                                                                     uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[kOrderBuckets];
+    constexpr int kKeep = 8;   // buckets a thread keeps for the second pass
     const int n = vt.n_tiles;
     for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) cnt[i] = 0u;
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += kOrderThreads) atomicAdd(&cnt[order_bucket(vt, vtf, ranges, work, t)], 1u);
+    int keep[kKeep];
+#pragma unroll
+    for (int k = 0; k < kKeep; k++) {
+        const int t = threadIdx.x + k * kOrderThreads;
+        keep[k] = t < n ? order_bucket(vt, vtf, ranges, work, t) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kKeep; k++)
+        if (threadIdx.x + k * kOrderThreads < n) atomicAdd(&cnt[keep[k]], 1u);
+    for (int t = threadIdx.x + kKeep * kOrderThreads; t < n; t += kOrderThreads)
+        atomicAdd(&cnt[order_bucket(vt, vtf, ranges, work, t)], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t acc = 0u;
@@ -507,7 +518,12 @@ __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += kOrderThreads)
+#pragma unroll
+    for (int k = 0; k < kKeep; k++) {
+        const int t = threadIdx.x + k * kOrderThreads;
+        if (t < n) order[atomicAdd(&cnt[keep[k]], 1u)] = (uint32_t)t;
+    }
+    for (int t = threadIdx.x + kKeep * kOrderThreads; t < n; t += kOrderThreads)
         order[atomicAdd(&cnt[order_bucket(vt, vtf, ranges, work, t)], 1u)] = (uint32_t)t;
 }
 

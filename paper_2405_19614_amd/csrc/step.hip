@@ -122,55 +122,60 @@ __global__ void reproj_finalize_kernel(int V, const double* acc, float weight, f
     }
 }
 
-__global__ __launch_bounds__(256) void loss_reduce_kernel(ViewTable vt, const double2* part, const double* rp,
-                                                          const double* ssim_part, float wc, float wd, float wr,
-                                                          float wsm, float* out) {
+// one workgroup per view: its loss terms, and its weighted sum in tot[v]
+__global__ __launch_bounds__(256) void loss_view_kernel(ViewTable vt, const double2* part, const double* rp,
+                                                        const double* ssim_part, float wc, float wd, float wr,
+                                                        float wsm, float* out, double* tot) {
     __shared__ double red[256][3];
-    double total = 0.0;
-    for (int v = 0; v < vt.V; v++) {
-        const ViewInfo& vi = vt.v[v];
-        const int nt = vi.tiles_x * vi.tiles_y;
-        double a = 0.0, b = 0.0, c = 0.0;
-        for (int i = threadIdx.x; i < nt; i += 256) {
-            const double2 p = part[vi.tile_off + i];
-            a += p.x;
-            b += p.y;
+    const int v = blockIdx.x;
+    const ViewInfo& vi = vt.v[v];
+    const int nt = vi.tiles_x * vi.tiles_y;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nt; i += 256) {
+        const double2 p = part[vi.tile_off + i];
+        a += p.x;
+        b += p.y;
+    }
+    if (ssim_part) {
+        const int ns = ((vi.W + kSsimTW - 1) / kSsimTW) * ((vi.H + kSsimTH - 1) / kSsimTH);
+        for (int i = threadIdx.x; i < 3 * ns; i += 256) {
+            const int k = i / ns;
+            c += ssim_part[(int64_t)k * vt.n_ssim_tiles + vi.ssim_off + (i - k * ns)];
         }
-        if (ssim_part) {
-            const int ns = ((vi.W + kSsimTW - 1) / kSsimTW) * ((vi.H + kSsimTH - 1) / kSsimTH);
-            for (int i = threadIdx.x; i < 3 * ns; i += 256) {
-                const int k = i / ns;
-                c += ssim_part[(int64_t)k * vt.n_ssim_tiles + vi.ssim_off + (i - k * ns)];
-            }
-        }
-        red[threadIdx.x][0] = a;
-        red[threadIdx.x][1] = b;
-        red[threadIdx.x][2] = c;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) {
-                red[threadIdx.x][0] += red[threadIdx.x + s][0];
-                red[threadIdx.x][1] += red[threadIdx.x + s][1];
-                red[threadIdx.x][2] += red[threadIdx.x + s][2];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const double npx = (double)vi.W * vi.H;
-            const double lc = red[0][0] / (3.0 * npx);
-            const double ld = red[0][1] / npx;
-            const double ls = ssim_part ? 1.0 - red[0][2] / (3.0 * npx) : 0.0;
-            double lr = 0.0;
-            if (rp && rp[8 * v + 1] > 0) lr = rp[8 * v] / rp[8 * v + 1];
-            out[1 + 4 * v] = (float)lc;
-            out[2 + 4 * v] = (float)ld;
-            out[3 + 4 * v] = (float)lr;
-            out[4 + 4 * v] = (float)ls;
-            total += (double)wc * lc + (double)wd * ld + (double)wr * lr + (double)wsm * ls;
+    }
+    red[threadIdx.x][0] = a;
+    red[threadIdx.x][1] = b;
+    red[threadIdx.x][2] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[threadIdx.x][0] += red[threadIdx.x + s][0];
+            red[threadIdx.x][1] += red[threadIdx.x + s][1];
+            red[threadIdx.x][2] += red[threadIdx.x + s][2];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = (float)(total / (double)vt.V);
+    if (threadIdx.x == 0) {
+        const double npx = (double)vi.W * vi.H;
+        const double lc = red[0][0] / (3.0 * npx);
+        const double ld = red[0][1] / npx;
+        const double ls = ssim_part ? 1.0 - red[0][2] / (3.0 * npx) : 0.0;
+        double lr = 0.0;
+        if (rp && rp[8 * v + 1] > 0) lr = rp[8 * v] / rp[8 * v + 1];
+        out[1 + 4 * v] = (float)lc;
+        out[2 + 4 * v] = (float)ld;
+        out[3 + 4 * v] = (float)lr;
+        out[4 + 4 * v] = (float)ls;
+        tot[v] = (double)wc * lc + (double)wd * ld + (double)wr * lr + (double)wsm * ls;
+    }
+}
+
+__global__ void loss_total_kernel(int V, const double* tot, float* out) {
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int v = 0; v < V; v++) t += tot[v];
+        out[0] = (float)(t / (double)V);
+    }
 }
 
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
@@ -294,8 +299,10 @@ hipError_t launch_reproj_finalize(const ViewTable& vt, const double* acc, float 
 
 hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc,
                               const double* ssim_part, float w_color, float w_depth, float w_reproj, float w_ssim,
-                              float* loss_out, hipStream_t s) {
-    loss_reduce_kernel<<<1, 256, 0, s>>>(vt, tile_part, rp_acc, ssim_part, w_color, w_depth, w_reproj, w_ssim, loss_out);
+                              float* loss_out, double* view_tot, hipStream_t s) {
+    loss_view_kernel<<<vt.V, 256, 0, s>>>(vt, tile_part, rp_acc, ssim_part, w_color, w_depth, w_reproj, w_ssim,
+                                          loss_out, view_tot);
+    loss_total_kernel<<<1, 64, 0, s>>>(vt.V, view_tot, loss_out);
     return hipGetLastError();
 }
 
