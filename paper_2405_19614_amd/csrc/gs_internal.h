@@ -53,6 +53,17 @@ struct ViewTable {
     ViewInfo v[kMaxViews];
 };
 
+// Workgroups of a launch are dealt round-robin to the 8 XCDs (each with its
+// own L2).  xcd_slot maps the linear workgroup id to an item index so that
+// every XCD processes one contiguous range of items: neighbouring tiles then
+// share their halos and lists in one L2.
+constexpr int kNumXcd = 8;
+__host__ __device__ inline int64_t xcd_slot(int64_t wg, int64_t n) {
+    const int64_t q = n / kNumXcd, r = n % kNumXcd;
+    const int64_t k = wg % kNumXcd, slot = wg / kNumXcd;
+    return k * q + (k < r ? k : r) + slot;
+}
+
 // The compositing tiles of a ViewTable, compact enough to pass beside one.
 struct TileGrid {
     int tw, th;

@@ -156,7 +156,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
     __shared__ float4 s_co[NT];
     __shared__ float4 s_cz[NT];
     __shared__ uint2 s_rc[NT];
-    const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;   // heaviest tiles first
+    const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;   // heaviest tiles first when ordered
     const int v = view_of_tile(vt, t);
     const ViewInfo& vi = vt.v[v];
     const int lt = t - vi.tile_off;
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
     __shared__ uint32_t s_id[NT];
     __shared__ float s_g[NT][NG];
     __shared__ uint32_t s_hi;
-    const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;   // heaviest tiles first
+    const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;   // heaviest tiles first when ordered
     const int v = view_of_tile(vt, t);
     const ViewInfo& vi = vt.v[v];
     const int lt = t - vi.tile_off;

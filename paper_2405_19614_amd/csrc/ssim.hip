@@ -111,10 +111,12 @@ __global__ __launch_bounds__(kNT) void ssim_fwd_kernel(ViewTable vt, Window w, c
     __shared__ float sx[kRH][kRW], sy[kRH][kRW];
     __shared__ float hm[5][kRH][kTW];
     __shared__ double red[kNT / 64];
-    const TileGeom g = tile_geom(vt, blockIdx.x);
+    // (channel, tile) of this workgroup, contiguous per XCD
+    const int item = (int)xcd_slot((int64_t)blockIdx.y * gridDim.x + blockIdx.x, 3 * (int64_t)vt.n_ssim_tiles);
+    const int k = item / vt.n_ssim_tiles, tile = item - k * vt.n_ssim_tiles;
+    const TileGeom g = tile_geom(vt, tile);
     const ViewInfo& vi = vt.v[g.v];
     const int64_t np = vt.n_pix;
-    const int k = blockIdx.y;   // colour channel
     const int64_t plane = 3 * (int64_t)vi.pix_off + k * g.hw;
     {
         float (*const dst[2])[kRW] = {sx, sy};
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(kNT) void ssim_fwd_kernel(ViewTable vt, Window w, c
         double t = 0.0;
 #pragma unroll
         for (int i = 0; i < kNT / 64; i++) t += red[i];
-        tile_sum[(int64_t)k * vt.n_ssim_tiles + blockIdx.x] = t;
+        tile_sum[(int64_t)k * vt.n_ssim_tiles + tile] = t;
     }
 }
 
@@ -184,12 +186,14 @@ __global__ __launch_bounds__(kNT) void ssim_bwd_kernel(ViewTable vt, Window w, c
                                                        float* __restrict__ dimg) {
     __shared__ float sp[3][kRH][kRW];
     __shared__ float hm[3][kRH][kTW];
-    const TileGeom g = tile_geom(vt, blockIdx.x);
+    // (channel, tile) of this workgroup, contiguous per XCD
+    const int item = (int)xcd_slot((int64_t)blockIdx.y * gridDim.x + blockIdx.x, 3 * (int64_t)vt.n_ssim_tiles);
+    const int k = item / vt.n_ssim_tiles, tile = item - k * vt.n_ssim_tiles;
+    const TileGeom g = tile_geom(vt, tile);
     const ViewInfo& vi = vt.v[g.v];
     const int64_t np = vt.n_pix;
     const float wv = wdev ? wdev[g.v] : wconst;
     const float scale = -wv / (3.f * (float)g.hw);
-    const int k = blockIdx.y;
     const int64_t plane = 3 * (int64_t)vi.pix_off + k * g.hw;
     {
         float (*const dst[3])[kRW] = {sp[0], sp[1], sp[2]};
