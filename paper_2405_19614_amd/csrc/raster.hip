@@ -16,6 +16,8 @@
 // leaves the ten values in ten distinct lanes, then across rows and waves with
 // one LDS atomic instruction per entry, then one global atomic per (tile,
 // Gaussian, value).
+#include <type_traits>
+
 #include "gs_device.h"
 
 namespace gs {
@@ -152,6 +154,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
                                                                      uint32_t* __restrict__ work,
                                                                      unsigned long long* counts) {
     constexpr int NT = TW * TH / PPT;
+    static_assert(64 % TW == 0 && NT % 64 == 0, "a wavefront spans whole rows of the tile");
     __shared__ float2 s_xy[NT];
     __shared__ float4 s_co[NT];
     __shared__ float4 s_cz[NT];
@@ -173,6 +176,8 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
     float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
     uint32_t lastp[PPT];
     uint32_t n_visit = 0u, n_blend = 0u, n_entries = 0u;
+    // rows of this wavefront: (64 / TW) row groups of PPT rows
+    const int wy0 = __builtin_amdgcn_readfirstlane(py0), wy1 = wy0 + (64 / TW) * PPT - 1;
     bool all_done = true;
 #pragma unroll
     for (int q = 0; q < PPT; q++) {
@@ -210,35 +215,41 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
             const float2 xy = s_xy[k];
             const float4 co = s_co[k];
             const float4 cz = s_cz[k];
-            const uint32_t jk = s_j[k] + 1u;
+            const uint32_t jk = __builtin_amdgcn_readfirstlane(s_j[k]) + 1u;
             // predicates combine with & (not &&): no per-pixel exec-mask branches
             const RectS rs = rect_scalar(rc);
             const bool colok = (px >= rs.x0) & (px <= rs.x1);
             const FragCol fc = frag_col(fpx, xy, co);
+            // rows known to lie inside the rect skip the per-row compares
+            const auto blend = [&](auto rows_in) {
 #pragma unroll
-            for (int q = 0; q < PPT; q++) {
-                const float raw = frag_raw(fc, co, (float)(py0 + q) - xy.y);
-                const float a = fminf(kAlphaMax, raw);
-                const bool inr = colok & (py0 + q >= rs.y0) & (py0 + q <= rs.y1);
-                const bool ok = inr & (a >= kAlphaMin);
-                // T (1 - alpha), negative once stopped, so a stopped pixel
-                // never blends again
-                const float aT = a * T[q];
-                const float Tn = T[q] - aT;
-                const bool stop = ok & (Tn < kTMin);
-                const bool bl = ok & !stop;
-                if (COUNT) {
-                    n_visit += (inr & (T[q] > 0.f)) ? 1u : 0u;
-                    n_blend += bl ? 1u : 0u;
+                for (int q = 0; q < PPT; q++) {
+                    const float raw = frag_raw(fc, co, (float)(py0 + q) - xy.y);
+                    const float a = fminf(kAlphaMax, raw);
+                    bool inr = colok;
+                    if constexpr (!decltype(rows_in)::value) inr = inr & (py0 + q >= rs.y0) & (py0 + q <= rs.y1);
+                    const bool ok = inr & (a >= kAlphaMin);
+                    // T (1 - alpha), negative once stopped, so a stopped pixel
+                    // never blends again
+                    const float aT = a * T[q];
+                    const float Tn = T[q] - aT;
+                    const bool stop = ok & (Tn < kTMin);
+                    const bool bl = ok & !stop;
+                    if (COUNT) {
+                        n_visit += (inr & (T[q] > 0.f)) ? 1u : 0u;
+                        n_blend += bl ? 1u : 0u;
+                    }
+                    const float w = bl ? aT : 0.f;
+                    T[q] = bl ? Tn : (stop ? -fabsf(T[q]) : T[q]);
+                    lastp[q] = bl ? jk : lastp[q];
+                    C0[q] += cz.x * w;
+                    C1[q] += cz.y * w;
+                    C2[q] += cz.z * w;
+                    D[q] += cz.w * w;
                 }
-                const float w = bl ? aT : 0.f;
-                T[q] = bl ? Tn : (stop ? -fabsf(T[q]) : T[q]);
-                lastp[q] = bl ? jk : lastp[q];
-                C0[q] += cz.x * w;
-                C1[q] += cz.y * w;
-                C2[q] += cz.z * w;
-                D[q] += cz.w * w;
-            }
+            };
+            if (rs.y0 <= wy0 && rs.y1 >= wy1) blend(std::true_type{});
+            else blend(std::false_type{});
         }
         all_done = true;
 #pragma unroll
@@ -300,6 +311,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
                                                                      const float* __restrict__ dA, float* g2,
                                                                      const uint32_t* __restrict__ order) {
     constexpr int NT = TW * TH / PPT;
+    static_assert(64 % TW == 0 && NT % 64 == 0, "a wavefront spans whole rows of the tile");
     constexpr int NG = 10;
     __shared__ float2 s_xy[NT];
     __shared__ float4 s_co[NT];
@@ -346,7 +358,20 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
             if (dA) gaTf[q] = dA[pi] * T[q];   // dA/dalpha_i = T_final / (1 - alpha_i)
             mylast = max(mylast, lastp[q]);
         }
+        // a pixel that blended nothing (or lies outside the image) carries
+        // zero transmittance and zero upstream gradients, so evaluating it
+        // adds exact zeros
+        if (lastp[q] == 0u) T[q] = g0[q] = g1[q] = g2c[q] = gd[q] = gaTf[q] = 0.f;
     }
+    // rows of this wavefront, and the smallest stop index among its pixels
+    // that blended something: entries before it need no per-pixel stop test
+    const int wy0 = __builtin_amdgcn_readfirstlane(py0), wy1 = wy0 + (64 / TW) * PPT - 1;
+    uint32_t wmin = 0xffffffffu;
+#pragma unroll
+    for (int q = 0; q < PPT; q++) wmin = min(wmin, lastp[q] ? lastp[q] : 0xffffffffu);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wmin = min(wmin, (uint32_t)__shfl_xor((int)wmin, o, 64));
+    wmin = __builtin_amdgcn_readfirstlane(wmin);
     if (threadIdx.x == 0) s_hi = rg.x;
     for (int i = threadIdx.x; i < NT * NG; i += NT) (&s_g[0][0])[i] = 0.f;
     __syncthreads();
@@ -379,30 +404,50 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
         }
         __syncthreads();
         for (int k = 0; k < cnt; k++) {
-            const uint32_t j = s_j[k];
+            const uint32_t j = __builtin_amdgcn_readfirstlane(s_j[k]);
             const uint2 rc = s_rc[k];
             const float2 xy = s_xy[k];
             const float4 co = s_co[k];
             const float4 cz = s_cz[k];
             const RectS rs = rect_scalar(rc);
-            const bool colok = (j < mylast) & (px >= rs.x0) & (px <= rs.x1);
-            const FragCol fc = frag_col(fpx, xy, co);
-            // sums over this thread's pixels (the column, dx, is shared) of
-            // dL/dsigma, dL/dsigma dy and dL/dsigma dy^2
+            // a column outside the rect (or past every stop index of this
+            // thread) gets an infinite exponent, so its alpha is exactly zero
+            FragCol fc = frag_col(fpx, xy, co);
+            if (!((j < mylast) & (px >= rs.x0) & (px <= rs.x1))) fc.a0 = __builtin_inff();
+            // pass 1: the alpha of every owned pixel, zeroed where the forward
+            // did not blend it (past the pixel's stop index or outside the
+            // rect's rows); min(0.99, raw) >= 1/255 exactly when raw >= 1/255.
+            // Entries before every pixel's stop index whose rect covers the
+            // wavefront's rows need neither test.
+            float raw[PPT];
+            if (j < wmin && rs.y0 <= wy0 && rs.y1 >= wy1) {
+#pragma unroll
+                for (int q = 0; q < PPT; q++) raw[q] = frag_raw(fc, co, (float)(py0 + q) - xy.y);
+            } else {
+#pragma unroll
+                for (int q = 0; q < PPT; q++) {
+                    const float r = frag_raw(fc, co, (float)(py0 + q) - xy.y);
+                    raw[q] = ((j < lastp[q]) & (py0 + q >= rs.y0) & (py0 + q <= rs.y1)) ? r : 0.f;
+                }
+            }
+            float rmax = raw[0];
+#pragma unroll
+            for (int q = 1; q < PPT; q++) rmax = fmaxf(rmax, raw[q]);
+            if (__ballot(rmax >= kAlphaMin) == 0ull) continue;   // no pixel of the wavefront blended it
+            // pass 2: gradients.  Sums over this thread's pixels (the column,
+            // dx, is shared) of dL/dsigma, dL/dsigma dy and dL/dsigma dy^2
             float s_ds = 0.f, s_dsdy = 0.f, s_dsdy2 = 0.f;
             float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gcd = 0.f;
-            bool any = false;
 #pragma unroll
             for (int q = 0; q < PPT; q++) {
                 const float dy = (float)(py0 + q) - xy.y;
-                const float raw = frag_raw(fc, co, dy);
-                const float a = fminf(kAlphaMax, raw);
-                const bool ok = colok & (j < lastp[q]) & (py0 + q >= rs.y0) & (py0 + q <= rs.y1) & (a >= kAlphaMin);
+                const float a = fminf(kAlphaMax, raw[q]);
                 const float inv = __builtin_amdgcn_rcpf(1.f - a);
                 const float Ti = T[q] * inv;
                 const float gcol = g0[q] * cz.x + g1[q] * cz.y + g2c[q] * cz.z + gd[q] * cz.w;
                 // dL/dalpha_i = (T_{i+1} gcol - Q + dL/dA T_final) / (1 - alpha_i)
                 const float dal = inv * (T[q] * gcol - Q[q] + gaTf[q]);
+                const bool ok = raw[q] >= kAlphaMin;
                 const float wk = ok ? a * Ti : 0.f;
                 gc0 += wk * g0[q];
                 gc1 += wk * g1[q];
@@ -411,32 +456,29 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
                 Q[q] += wk * gcol;
                 T[q] = ok ? Ti : T[q];
                 // alpha clamped at 0.99: no dependence on opacity or sigma
-                const float da = (ok & (raw <= kAlphaMax)) ? dal : 0.f;
-                const float dsig = -da * raw;   // dL/dsigma
+                const float da = (ok & (raw[q] <= kAlphaMax)) ? dal : 0.f;
+                const float dsig = -da * raw[q];   // dL/dsigma
                 const float dsdy = dsig * dy;
                 s_ds += dsig;
                 s_dsdy += dsdy;
                 s_dsdy2 += dsdy * dy;
-                any = any | ok;
             }
-            if (__ballot(any) != 0ull) {
-                // constant factors are applied by the projection backward
-                const float hb = 0.5f * co.y;
-                const float dx = fc.dx;
-                float gv[NG];
-                gv[0] = -(co.x * dx * s_ds + hb * s_dsdy);
-                gv[1] = -(co.z * s_dsdy + hb * dx * s_ds);
-                gv[2] = dx * dx * s_ds;
-                gv[3] = dx * s_dsdy;
-                gv[4] = s_dsdy2;
-                gv[5] = -s_ds;
-                gv[6] = gc0;
-                gv[7] = gc1;
-                gv[8] = gc2;
-                gv[9] = gcd;
-                const float s = row_reduce_scatter10(gv, lane);
-                if (slot >= 0) atomicAdd(&s_g[k][slot], s);
-            }
+            // constant factors are applied by the projection backward
+            const float hb = 0.5f * co.y;
+            const float dx = fc.dx;
+            float gv[NG];
+            gv[0] = -(co.x * dx * s_ds + hb * s_dsdy);
+            gv[1] = -(co.z * s_dsdy + hb * dx * s_ds);
+            gv[2] = dx * dx * s_ds;
+            gv[3] = dx * s_dsdy;
+            gv[4] = s_dsdy2;
+            gv[5] = -s_ds;
+            gv[6] = gc0;
+            gv[7] = gc1;
+            gv[8] = gc2;
+            gv[9] = gcd;
+            const float s = row_reduce_scatter10(gv, lane);
+            if (slot >= 0) atomicAdd(&s_g[k][slot], s);
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
