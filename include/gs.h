@@ -99,8 +99,9 @@ typedef struct {
 
 /* Tile plan of a forward pass.
  *   tile_w, tile_h : in  compositing tile of the forward; one of 16x16, 16x8,
- *                    8x8, 32x8, 32x16, 32x32 (0, 0 = the context's current
- *                    choice, 16x16 unless gs_autotune chose another); out: used
+ *                    8x8, 32x8, 32x16, 32x32, 32x64, 64x32, 64x64 (0, 0 = the
+ *                    context's current choice, 16x16 unless gs_autotune
+ *                    chose another); out: used
  *   bin_w, bin_h   : in  binning rectangle, multiples of both tiles in
  *                    [8, 2048] (0, 0 = the context's choice, 64x64 by
  *                    default); out: used.  Gaussians are binned per bin; each
@@ -323,10 +324,10 @@ int gs_set_bin(gs_ctx* ctx, int32_t bin_w, int32_t bin_h);
 int gs_set_tile(gs_ctx* ctx, int32_t tile_w, int32_t tile_h);
 
 /* Pixels each thread of the compositing kernels owns for a tile shape (1, 2,
- * 4 or 8: 1 and 2 for every shape but 32x32 (2 not for 8x8), 4 for 16x16 and
- * the 32-wide shapes, 8 for 32x16 and 32x32), for the forward and the
- * backward.  Does not change any result, only the launch shape; gs_autotune
- * sets it too. */
+ * 4 or 8: 1 and 2 for the shapes up to 32x16 (2 not for 8x8), 4 for 16x16 and
+ * the 32-wide shapes, 8 for 32x16, 32x32 and the shapes 64 wide or tall, which
+ * take only 8), for the forward and the backward.  Does not change any
+ * result, only the launch shape; gs_autotune sets it too. */
 int gs_set_pixels_per_thread(gs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t ppt);
 
 /* The backward's own tile shape and pixels per thread (0, 0, 0: use the

@@ -207,6 +207,7 @@ def render_views(g: Gaussians, cams, poses, bands=BANDS) -> Dict[str, np.ndarray
             "alpha": np.concatenate([o["alpha"].reshape(-1) for o in outs]),
             "tfinal": np.concatenate([o["tfinal"].reshape(-1) for o in outs]),
             "ambiguous": np.concatenate([o["ambiguous"].reshape(-1) for o in outs]),
+            "nblend": np.concatenate([o["nblend"].reshape(-1) for o in outs]),
             "nfrag": sum(o["nfrag"] for o in outs)}
 
 

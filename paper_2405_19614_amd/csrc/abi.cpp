@@ -74,13 +74,15 @@ struct DeviceGuard {
 
 bool tile_ok(int tw, int th) {
     return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
-           (tw == 32 && th == 16) || (tw == 32 && th == 32);
+           (tw == 32 && th == 16) || (tw == 32 && th == 32) || (tw == 32 && th == 64) || (tw == 64 && th == 32) ||
+           (tw == 64 && th == 64);
 }
 
 // pixels per thread the compositing kernels are built for (whole wavefronts)
 bool ppt_ok(int tw, int th, int ppt) {
     if (!tile_ok(tw, th)) return false;
     if (tw == 32 && th == 32) return ppt == 4 || ppt == 8;
+    if (th == 64 || tw == 64) return ppt == 8;
     if (ppt == 1) return true;
     if (ppt == 2) return !(tw == 8 && th == 8);
     if (ppt == 4) return (tw == 16 && th == 16) || (tw == 32);
@@ -93,7 +95,9 @@ int ppt_of(const gs_ctx* c, int tw, int th) {
         auto it = c->ppt.find(tw * 1000 + th);
         if (it != c->ppt.end()) return it->second;
     }
-    return ppt_ok(tw, th, 2) ? 2 : (ppt_ok(tw, th, 1) ? 1 : 4);
+    for (int p : {2, 1, 4, 8})
+        if (ppt_ok(tw, th, p)) return p;
+    return 8;
 }
 
 int bwd_ppt_of(const gs_ctx* c, int tw, int th) {
@@ -1109,13 +1113,14 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
     };
     // stage 1: the forward's and the backward's tile shape and pixels per
     // thread, chosen separately, bins 64x64
-    const int cand[15][3] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {16, 8, 1},  {16, 8, 2},
-                             {8, 8, 1},   {32, 8, 1},  {32, 8, 2},  {32, 8, 4},  {32, 16, 1},
-                             {32, 16, 2}, {32, 16, 4}, {32, 16, 8}, {32, 32, 4}, {32, 32, 8}};
+    constexpr int kCand = 18;
+    const int cand[kCand][3] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {16, 8, 1},  {16, 8, 2},  {8, 8, 1},
+                                {32, 8, 1},  {32, 8, 2},  {32, 8, 4},  {32, 16, 1}, {32, 16, 2}, {32, 16, 4},
+                                {32, 16, 8}, {32, 32, 4}, {32, 32, 8}, {32, 64, 8}, {64, 32, 8}, {64, 64, 8}};
     gs_ctx::Tuned best{16, 16, 64, 64, 2, 16, 16, 2};
     float best_f = 1e30f, best_b = 1e30f;
     int rc = GS_OK;
-    for (int k = 0; k < 15 && rc == GS_OK; k++) {
+    for (int k = 0; k < kCand && rc == GS_OK; k++) {
         float fm, bm;
         if (!time_cfg(cand[k][0], cand[k][1], cand[k][2], cand[k][0], cand[k][1], cand[k][2], 64, 64, &fm, &bm, &rc))
             break;
@@ -1152,7 +1157,7 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
     if (rc == GS_OK && (best.bw != 64 || best.bh != 64)) {
         float bf = 1e30f, bb = 1e30f;
         gs_ctx::Tuned t3 = best;
-        for (int k = 0; k < 15 && rc == GS_OK; k++) {
+        for (int k = 0; k < kCand && rc == GS_OK; k++) {
             if (best.bw % cand[k][0] || best.bh % cand[k][1]) continue;
             float fm, bm;
             if (!time_cfg(cand[k][0], cand[k][1], cand[k][2], cand[k][0], cand[k][1], cand[k][2], best.bw, best.bh,

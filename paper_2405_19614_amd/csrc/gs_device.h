@@ -249,10 +249,20 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
     const float m = 0.5f * (o.a + o.c);
     const float lmax = m + sqrtf(fmaxf(m * m - o.det, 0.f));
     o.radius = ceilf(sqrtf(qmax * lmax));
-    const float fx0 = fmaxf(ceilf(o.u - o.radius), 0.f);
-    const float fx1 = fminf(floorf(o.u + o.radius), (float)(vi.W - 1));
-    const float fy0 = fmaxf(ceilf(o.v - o.radius), 0.f);
-    const float fy1 = fminf(floorf(o.v + o.radius), (float)(vi.H - 1));
+    // The pixel rect is the bounding box of that ellipse, which is tighter
+    // than the square of the radius unless the ellipse is round or
+    // axis-aligned: for a fixed dx the smallest sigma over dy is
+    // dx^2 / (2 Sigma_xx), so alpha >= 1/255 needs |dx| <= sqrt(qmax Sigma_xx)
+    // (and |dy| <= sqrt(qmax Sigma_yy)).  The widened qmax and the extra
+    // hundredth of a pixel keep the box conservative under FP32 rounding: a
+    // pixel outside it has an exact alpha at least 2.5 % below 1/255.
+    const float qbox = qmax + 0.05f;
+    const float hx = fminf(o.radius, sqrtf(qbox * o.a) + 0.01f);
+    const float hy = fminf(o.radius, sqrtf(qbox * o.c) + 0.01f);
+    const float fx0 = fmaxf(ceilf(o.u - hx), 0.f);
+    const float fx1 = fminf(floorf(o.u + hx), (float)(vi.W - 1));
+    const float fy0 = fmaxf(ceilf(o.v - hy), 0.f);
+    const float fy1 = fminf(floorf(o.v + hy), (float)(vi.H - 1));
     if (!(fx0 <= fx1) || !(fy0 <= fy1)) return;
     o.x0 = (int)fx0; o.x1 = (int)fx1; o.y0 = (int)fy0; o.y1 = (int)fy1;
     o.valid = true;

@@ -623,6 +623,9 @@ hipError_t bwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals,
     if (vt.tw == 32 && vt.th == 16 && vt.ppt == 8) return FN<32, 16, 8>(__VA_ARGS__); \
     if (vt.tw == 32 && vt.th == 32 && vt.ppt == 4) return FN<32, 32, 4>(__VA_ARGS__); \
     if (vt.tw == 32 && vt.th == 32 && vt.ppt == 8) return FN<32, 32, 8>(__VA_ARGS__); \
+    if (vt.tw == 32 && vt.th == 64 && vt.ppt == 8) return FN<32, 64, 8>(__VA_ARGS__); \
+    if (vt.tw == 64 && vt.th == 32 && vt.ppt == 8) return FN<64, 32, 8>(__VA_ARGS__); \
+    if (vt.tw == 64 && vt.th == 64 && vt.ppt == 8) return FN<64, 64, 8>(__VA_ARGS__); \
     return hipErrorInvalidValue;
 
 hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,

@@ -71,7 +71,7 @@ def test_backward_matches_oracle(ctx, name):
 
 LAUNCH_SHAPES = [(16, 16, 1), (16, 16, 2), (16, 16, 4), (16, 8, 1), (16, 8, 2), (8, 8, 1), (32, 8, 1),
                  (32, 8, 2), (32, 8, 4), (32, 16, 1), (32, 16, 2), (32, 16, 4), (32, 16, 8), (32, 32, 4),
-                 (32, 32, 8)]
+                 (32, 32, 8), (32, 64, 8), (64, 32, 8), (64, 64, 8)]
 
 
 def test_forward_bit_identical_across_tile_shapes(ctx):
@@ -243,7 +243,8 @@ def test_empty_and_culled_scenes(ctx):
     assert plan.n_pairs == 0 and float(c.abs().max()) == 0
 
 
-@pytest.mark.parametrize("fwd,bwd", [((16, 16, 4), (32, 32, 8)), ((32, 32, 4), (8, 8, 1)), ((32, 8, 2), (32, 16, 4))])
+@pytest.mark.parametrize("fwd,bwd", [((16, 16, 4), (32, 32, 8)), ((32, 32, 4), (8, 8, 1)), ((32, 8, 2), (32, 16, 4)),
+                                     ((16, 16, 4), (64, 32, 8))])
 def test_backward_with_its_own_tile_shape(ctx, fwd, bwd):
     """The backward on a different tiling than the forward (ordered by the
     forward's per-tile work) gives the oracle's gradients."""
