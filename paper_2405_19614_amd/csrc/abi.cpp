@@ -557,7 +557,8 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     const gs::Params P = params_of(g);
     gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
     GS_HIP(c, gs::launch_zero_g2(p.rec.nt, p.g2, L.R, s));
-    GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, p.ts, vt, s));
+    GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, p.ts, vt,
+                                       false, s));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, 0, p.posepart, L.pose_blocks, s));
     GS_HIP(c, gs::launch_pose_finalize(vt, p.posepart, L.pose_blocks, nullptr, 0.f, dL_dpose, s));
     return GS_OK;
@@ -729,7 +730,8 @@ int gs_densify(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, 
 
 namespace {
 
-// Stages of one step, timed by gs_step_profile.
+// Stages of one step, timed by gs_step_profile ("loss_reproj" also orders the
+// backward's tiles, so "composite_bwd" is the backward compositing kernel alone).
 const char* const kStageNames[] = {"preprocess_fwd", "binning",        "composite_fwd", "ssim",
                                    "loss_reproj",    "composite_bwd",  "preprocess_bwd", "optimizer"};
 constexpr int kNumStages = 8;
@@ -769,9 +771,10 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, ssim ? p.ssim_tiles : nullptr,
                                      o->w_color, o->w_depth, o->w_reproj, o->w_ssim, loss_out, p.rpacc + 8 * vt.V,
                                      s));
+    GS_HIP(c, gs::launch_order_tiles(vtb, vt, p.ranges, p.ts, s));
     GS_HIP(c, mark(5));
     GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, vt,
-                                       s));
+                                       true, s));
     GS_HIP(c, mark(6));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, o->accumulate_grads, p.posepart, L.pose_blocks,
                                         s));

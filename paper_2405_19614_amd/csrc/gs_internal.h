@@ -213,11 +213,16 @@ hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const 
                                 const LossArgs* loss, const TileSched& ts, hipStream_t s,
                                 unsigned long long* counts = nullptr);
 // vt: the backward's own tiling (same bins); vtf: the forward's tiling, whose
-// per-tile work orders the backward's tiles
+// per-tile work orders the backward's tiles.  ordered: ts.order already holds
+// that order (launch_order_tiles ran after the forward); else it is computed
+// first.
 hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                                 const float* tfin, const uint32_t* last, const float* dC, const float* dD,
                                 const float* dA, float* g2, const TileSched& ts, const ViewTable& vtf,
-                                hipStream_t s);
+                                bool ordered, hipStream_t s);
+// the backward's tile order (heaviest first) from the forward's per-tile work
+hipError_t launch_order_tiles(const ViewTable& vt, const ViewTable& vtf, const uint2* ranges, const TileSched& ts,
+                              hipStream_t s);
 
 // loss_out [1 + 4V]: total, then (Lc, Ld, Lr, Ls) per view; ssim_part (nullable)
 // holds per-(channel, SSIM tile) sums of the SSIM map, channel-major

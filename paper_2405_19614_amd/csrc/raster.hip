@@ -336,14 +336,16 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
     const int64_t hw = (int64_t)vi.W * vi.H;
 
     // per pixel: transmittance, upstream gradients, and Q = sum over the
-    // fragments behind the current one of (dL/dC . colour + dL/dD z) w
-    float T[PPT], gaTf[PPT], g0[PPT], g1[PPT], g2c[PPT], gd[PPT], Q[PPT];
+    // fragments behind the current one of (dL/dC . colour + dL/dD z) w,
+    // started at -dL/dA T_final (dA/dalpha_i = T_final / (1 - alpha_i)), so
+    // that T_{i+1} gcol_i - Q is the numerator of dL/dalpha_i
+    float T[PPT], g0[PPT], g1[PPT], g2c[PPT], gd[PPT], Q[PPT];
     uint32_t lastp[PPT];
     uint32_t mylast = 0u;
 #pragma unroll
     for (int q = 0; q < PPT; q++) {
         T[q] = 1.f;
-        g0[q] = g1[q] = g2c[q] = gd[q] = gaTf[q] = 0.f;
+        g0[q] = g1[q] = g2c[q] = gd[q] = 0.f;
         Q[q] = 0.f;
         lastp[q] = 0u;
         const int py = py0 + q;
@@ -355,13 +357,13 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
             lastp[q] = last[pi];
             if (dC) { g0[q] = dC[ci]; g1[q] = dC[ci + hw]; g2c[q] = dC[ci + 2 * hw]; }
             if (dD) gd[q] = dD[pi];
-            if (dA) gaTf[q] = dA[pi] * T[q];   // dA/dalpha_i = T_final / (1 - alpha_i)
+            if (dA) Q[q] = -(dA[pi] * T[q]);
             mylast = max(mylast, lastp[q]);
         }
         // a pixel that blended nothing (or lies outside the image) carries
         // zero transmittance and zero upstream gradients, so evaluating it
         // adds exact zeros
-        if (lastp[q] == 0u) T[q] = g0[q] = g1[q] = g2c[q] = gd[q] = gaTf[q] = 0.f;
+        if (lastp[q] == 0u) T[q] = g0[q] = g1[q] = g2c[q] = gd[q] = Q[q] = 0.f;
     }
     // rows of this wavefront, and the smallest stop index among its pixels
     // that blended something: entries before it need no per-pixel stop test
@@ -434,35 +436,42 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
 #pragma unroll
             for (int q = 1; q < PPT; q++) rmax = fmaxf(rmax, raw[q]);
             if (__ballot(rmax >= kAlphaMin) == 0ull) continue;   // no pixel of the wavefront blended it
-            // pass 2: gradients.  Sums over this thread's pixels (the column,
-            // dx, is shared) of dL/dsigma, dL/dsigma dy and dL/dsigma dy^2
-            float s_ds = 0.f, s_dsdy = 0.f, s_dsdy2 = 0.f;
+            // pass 2: gradients.  A pixel that did not blend the entry gets
+            // alpha 0, so its transmittance is divided by exactly 1 and its
+            // weight is 0; a clamped alpha (0.99) does not depend on opacity
+            // or sigma, so its raw value is zeroed for the sigma gradient.
+            // Sums over this thread's pixels (the column, dx, is shared) of
+            // dL/dsigma times 1, q and q^2, with dy = dy0 + q.
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f;
             float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gcd = 0.f;
 #pragma unroll
             for (int q = 0; q < PPT; q++) {
-                const float dy = (float)(py0 + q) - xy.y;
-                const float a = fminf(kAlphaMax, raw[q]);
+                const bool ok = raw[q] >= kAlphaMin;
+                const float a = ok ? __builtin_amdgcn_fmed3f(raw[q], 0.f, kAlphaMax) : 0.f;
+                const float rsig = (ok & (raw[q] <= kAlphaMax)) ? raw[q] : 0.f;
                 const float inv = __builtin_amdgcn_rcpf(1.f - a);
                 const float Ti = T[q] * inv;
                 const float gcol = g0[q] * cz.x + g1[q] * cz.y + g2c[q] * cz.z + gd[q] * cz.w;
-                // dL/dalpha_i = (T_{i+1} gcol - Q + dL/dA T_final) / (1 - alpha_i)
-                const float dal = inv * (T[q] * gcol - Q[q] + gaTf[q]);
-                const bool ok = raw[q] >= kAlphaMin;
-                const float wk = ok ? a * Ti : 0.f;
+                // dL/dalpha_i = (T_{i+1} gcol - Q) / (1 - alpha_i)
+                const float dal = inv * (T[q] * gcol - Q[q]);
+                const float wk = a * Ti;
                 gc0 += wk * g0[q];
                 gc1 += wk * g1[q];
                 gc2 += wk * g2c[q];
                 gcd += wk * gd[q];
                 Q[q] += wk * gcol;
-                T[q] = ok ? Ti : T[q];
-                // alpha clamped at 0.99: no dependence on opacity or sigma
-                const float da = (ok & (raw[q] <= kAlphaMax)) ? dal : 0.f;
-                const float dsig = -da * raw[q];   // dL/dsigma
-                const float dsdy = dsig * dy;
-                s_ds += dsig;
-                s_dsdy += dsdy;
-                s_dsdy2 += dsdy * dy;
+                T[q] = Ti;
+                const float dsig = -dal * rsig;   // dL/dsigma
+                s0 += dsig;
+                if (q > 0) {
+                    s1 += (float)q * dsig;
+                    s2 += (float)(q * q) * dsig;
+                }
             }
+            const float dy0 = (float)py0 - xy.y;
+            const float s_ds = s0;
+            const float s_dsdy = dy0 * s0 + s1;
+            const float s_dsdy2 = dy0 * (dy0 * s0 + 2.f * s1) + s2;
             // constant factors are applied by the projection backward
             const float hb = 0.5f * co.y;
             const float dx = fc.dx;
@@ -594,10 +603,10 @@ hipError_t fwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals,
 template <int TW, int TH, int PPT>
 hipError_t bwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                  const float* tfin, const uint32_t* last, const float* dC, const float* dD, const float* dA,
-                 float* g2, const TileSched& ts, const ViewTable& vtf, hipStream_t s) {
+                 float* g2, const TileSched& ts, const ViewTable& vtf, bool ordered, hipStream_t s) {
     if (vt.n_tiles == 0) return hipSuccess;
     constexpr int NT = TW * TH / PPT;
-    order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt, tile_grid(vtf), ranges, ts.work, ts.order);
+    if (!ordered) order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt, tile_grid(vtf), ranges, ts.work, ts.order);
     composite_bwd_kernel<TW, TH, PPT><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2,
                                                                  ts.order);
     return hipGetLastError();
@@ -638,8 +647,15 @@ hipError_t launch_composite_fwd(const ViewTable& vt, const uint2* ranges, const 
 hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const uint32_t* vals, const Records& rec,
                                 const float* tfin, const uint32_t* last, const float* dC, const float* dD,
                                 const float* dA, float* g2, const TileSched& ts, const ViewTable& vtf,
-                                hipStream_t s) {
-    GS_TILE_DISPATCH(bwd_t, vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2, ts, vtf, s)
+                                bool ordered, hipStream_t s) {
+    GS_TILE_DISPATCH(bwd_t, vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2, ts, vtf, ordered, s)
+}
+
+hipError_t launch_order_tiles(const ViewTable& vt, const ViewTable& vtf, const uint2* ranges, const TileSched& ts,
+                              hipStream_t s) {
+    if (vt.n_tiles == 0) return hipSuccess;
+    order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt, tile_grid(vtf), ranges, ts.work, ts.order);
+    return hipGetLastError();
 }
 
 #undef GS_TILE_DISPATCH
