@@ -16,6 +16,7 @@ constexpr float kZNear = 0.2f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
+constexpr float kLog2AlphaMinInv = 7.99435343685885793f;   // log2(255)
 constexpr float kDilate = 0.3f;
 constexpr float kJClamp = 1.3f;
 

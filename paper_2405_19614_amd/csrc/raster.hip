@@ -129,6 +129,30 @@ __device__ __forceinline__ bool rect_meets(uint2 rc, int bx0, int bx1, int by0, 
            (int)(rc.y >> 16) >= by0;
 }
 
+// Whether any pixel of the box [x0, x1] x [y0, y1] (a compositing tile clipped
+// to the entry's rect) can reach alpha >= 1/255: the smallest exponent
+// t = A'dx^2 + B'dx dy + C'dy^2 - log2 o over the box (a convex quadratic, so
+// at the mean if the box holds it, else on an edge, where it is a parabola
+// minimised in closed form and clamped to the edge) against log2(255).  The
+// rect is the box of the alpha ellipse, but a tile inside it can still miss
+// the ellipse (thin, tilted Gaussians); such entries are not staged.  The
+// 0.1 margin (7 % in alpha) keeps the test conservative under FP32 rounding,
+// so no entry that blends a pixel of the tile is dropped.
+__device__ __forceinline__ bool ellipse_meets(float2 xy, float4 co, int x0, int x1, int y0, int y1) {
+    const float X0 = (float)x0 - xy.x, X1 = (float)x1 - xy.x;
+    const float Y0 = (float)y0 - xy.y, Y1 = (float)y1 - xy.y;
+    if (X0 <= 0.f && X1 >= 0.f && Y0 <= 0.f && Y1 >= 0.f) return true;
+    const auto q = [&](float dx, float dy) { return (co.x * dx + co.y * dy) * dx + co.z * dy * dy; };
+    // vertical edges dx = X: minimum at dy = -B' X / (2 C'); horizontal edges likewise
+    const float iA = 0.5f / co.x, iC = 0.5f / co.z;
+    const float m0 = q(X0, fminf(fmaxf(-co.y * X0 * iC, Y0), Y1));
+    const float m1 = q(X1, fminf(fmaxf(-co.y * X1 * iC, Y0), Y1));
+    const float m2 = q(fminf(fmaxf(-co.y * Y0 * iA, X0), X1), Y0);
+    const float m3 = q(fminf(fmaxf(-co.y * Y1 * iA, X0), X1), Y1);
+    const float tmin = fminf(fminf(m0, m1), fminf(m2, m3)) - co.w;
+    return tmin <= kLog2AlphaMinInv + 0.1f;
+}
+
 // Rect of a staged entry.  Every lane reads the entry from the same LDS
 // address, so the packed words are moved to scalar registers and unpacked on
 // the scalar unit.
@@ -193,16 +217,24 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
         uint32_t r = 0u;
         uint2 rc = make_uint2(1u, 1u);
         bool pass = false;
+        float2 exy;
+        float4 eco;
         if (j < rg.y) {
             r = vals[j];
             rc = rec.rect[r];
             pass = rect_meets(rc, bx0, bx1, by0, by1);
+            if (pass) {
+                exy = rec.xy[r];
+                eco = rec.conic[r];
+                pass = ellipse_meets(exy, eco, max(bx0, (int)(rc.x & 0xffffu)), min(bx1, (int)(rc.x >> 16)),
+                                     max(by0, (int)(rc.y & 0xffffu)), min(by1, (int)(rc.y >> 16)));
+            }
         }
         int cnt;
         const int pos = block_compact<NT>(pass, &cnt);
         if (pass) {
-            s_xy[pos] = rec.xy[r];
-            s_co[pos] = rec.conic[r];
+            s_xy[pos] = exy;
+            s_co[pos] = eco;
             s_cz[pos] = rec.col[r];
             s_rc[pos] = rc;
             s_j[pos] = j;
@@ -389,18 +421,26 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
         uint32_t r = 0u;
         uint2 rc0 = make_uint2(1u, 1u);
         bool pass = false;
+        float2 exy;
+        float4 eco;
         if ((int)threadIdx.x < span) {
             r = vals[jj];
             rc0 = rec.rect[r];
             pass = rect_meets(rc0, bx0, bx1, by0, by1);
+            if (pass) {
+                exy = rec.xy[r];
+                eco = rec.conic[r];
+                pass = ellipse_meets(exy, eco, max(bx0, (int)(rc0.x & 0xffffu)), min(bx1, (int)(rc0.x >> 16)),
+                                     max(by0, (int)(rc0.y & 0xffffu)), min(by1, (int)(rc0.y >> 16)));
+            }
         }
         int cnt;
         const int pos = block_compact<NT>(pass, &cnt);
         if (pass) {
             s_id[pos] = r;
             s_j[pos] = jj;
-            s_xy[pos] = rec.xy[r];
-            s_co[pos] = rec.conic[r];
+            s_xy[pos] = exy;
+            s_co[pos] = eco;
             s_cz[pos] = rec.col[r];
             s_rc[pos] = rc0;
         }
