@@ -266,7 +266,9 @@ int gs_mapping_step(gs_ctx* ctx, gs_gaussians* params, gs_gaussian_grads* grads,
                     float* color, float* depth, float* alpha, float* loss_out, float* dL_dpose, void* stream);
 
 /* Synchronous read of the workspace status after gs_mapping_step: *flags bit 0 =
- * pair overflow; *n_pairs = pairs of the last step (needed ones on overflow),
+ * pair overflow, bit 1 = a binning scan gave up waiting for another workgroup
+ * (the step's results are then invalid); *n_pairs = pairs of the last step
+ * (needed ones on overflow),
  * *n_visible = visible records.  Synchronises `stream`. */
 int gs_step_status(gs_ctx* ctx, const void* workspace, size_t workspace_bytes, int32_t* flags, int64_t* n_pairs,
                    int64_t* n_visible, void* stream);

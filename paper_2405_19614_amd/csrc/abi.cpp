@@ -325,6 +325,11 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
         return at;
     };
     L.off_scalars = take((size_t)kNumScalars * 4);   // first: gs_step_status finds it at offset 0
+    L.n_chunks = std::max<int64_t>(ceil_div(R, 2048), 1);
+    L.lb_tiles_chunk = ceil_div(L.n_chunks, 2048);
+    L.lb_tiles_hist = std::max<int64_t>(ceil_div(256 * L.sort_blocks, 2048), 1);
+    L.off_lb = take((size_t)lb_words(L) * 8);       // cleared with the scalars at the start of binning
+    L.off_chunk = take((size_t)L.n_chunks * 8);
     L.off_xy = take((size_t)R * 8);
     L.off_conic = take((size_t)R * 16);
     L.off_col = take((size_t)R * 16);
@@ -334,14 +339,11 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     L.off_v0 = take((size_t)R * 4);
     L.off_k1 = take((size_t)R * 4);
     L.off_v1 = take((size_t)R * 4);
-    L.off_cnt = take((size_t)R * 4);
     L.off_pk0 = take((size_t)cap * 4);
     L.off_pv0 = take((size_t)cap * 4);
     L.off_pk1 = take((size_t)cap * 4);
     L.off_pv1 = take((size_t)cap * 4);
     L.off_hist = take((size_t)256 * L.sort_blocks * 4);
-    const int64_t nscan = std::max<int64_t>(std::max<int64_t>(ceil_div(R, 2048), ceil_div(256 * L.sort_blocks, 2048)), 1);
-    L.off_scan = take((size_t)nscan * 4);
     L.off_ranges = take((size_t)vt.n_bins * 8);
     L.off_tfin = take((size_t)vt.n_pix * 4);
     L.off_last = take((size_t)vt.n_pix * 4);
@@ -514,9 +516,10 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     plan->bwd_tile_w = btw;
     plan->bwd_tile_h = bth;
     GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, nullptr, s));
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, nullptr, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.rect, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
+    if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");
     const int64_t total = (int64_t)((uint64_t)c->pinned[gs::kPairsLo] | ((uint64_t)c->pinned[gs::kPairsHi] << 32));
     plan->n_pairs = total;
     plan->n_visible = c->pinned[gs::kNVis];
@@ -524,7 +527,7 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
         return fail(c, GS_ECAPACITY, "%lld pairs exceed the capacity %lld", (long long)total,
                     (long long)plan->pair_capacity);
     uint32_t* vals = nullptr;
-    GS_HIP(c, gs::launch_binning_emit(vt, L, base, p.rec.rect, total, s, &vals));
+    GS_HIP(c, gs::launch_binning_sort(vt, L, base, total, s, &vals));
     if (total > 0 && vals != p.vals) return fail(c, GS_EDEVICE, "internal: sorted values in unexpected buffer");
     GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, p.vals, p.rec, color, depth, alpha, p.tfin, p.last, nullptr, p.ts,
                                        s));
@@ -997,15 +1000,16 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
     Ptrs p = ptrs_of(L, base, false);
     const uint2* rc = reinterpret_cast<const uint2*>(rect);
     GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.rect, p.rec.nt, n, s));
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, depth, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.rect, depth, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
+    if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");
     const int64_t total = (int64_t)((uint64_t)c->pinned[gs::kPairsLo] | ((uint64_t)c->pinned[gs::kPairsHi] << 32));
     *n_pairs = total;
     if (total > cap)
         return fail(c, GS_ECAPACITY, "%lld pairs exceed the capacity %lld", (long long)total, (long long)cap);
     uint32_t* vals = nullptr;
-    GS_HIP(c, gs::launch_binning_emit(vt, L, base, p.rec.rect, total, s, &vals));
+    GS_HIP(c, gs::launch_binning_sort(vt, L, base, total, s, &vals));
     if (total > 0) GS_HIP(c, hipMemcpyAsync(values, vals, (size_t)total * 4, hipMemcpyDeviceToDevice, s));
     GS_HIP(c, hipMemcpyAsync(ranges, p.ranges, (size_t)L.n_bins * 8, hipMemcpyDeviceToDevice, s));
     return GS_OK;

@@ -4,14 +4,26 @@
 // compositing tile reads its bin's list.
 //
 // Two-stage design instead of one 64-bit-key sort of all pairs:
-//   1. compact the visible records (scan of a 0/1 flag) and sort them by the
-//      bit pattern of their positive FP32 depth (stable LSD radix sort, so
-//      equal depths keep ascending record order);
+//   1. compact the visible records and sort them by the bit pattern of their
+//      positive FP32 depth (stable LSD radix sort, so equal depths keep
+//      ascending record order);
 //   2. emit one pair (global bin id, record) per touched bin in that depth
 //      order and sort the pairs stably by bin id only (ceil(log2 bins)
 //      bits).  Stability makes the result the (bin, depth, record) order.
 // Stage 1 sorts records (millions), stage 2 sorts only 8-18 key bits of the
 // pairs, instead of ~50 bits.
+//
+// Kernel launches, not bandwidth, dominate binning at these sizes (about
+// 4.5 us per small kernel), so the short scans (per-chunk sums of visible
+// records and of pairs, radix histograms) are chained across workgroups
+// (decoupled look-back): each workgroup publishes its tile's total, then
+// reads its predecessors' totals or running prefixes, so one launch does what
+// a reduce / scan / down-sweep triple does.  A workgroup takes its tile index
+// in arrival order, so every tile it waits for belongs to a workgroup that is
+// already running, and every wait is bounded.  The long passes (compaction,
+// pair emission) rank within 2048-record chunks and take the chunk offsets
+// from such a scan; chaining them directly measured slower (every status
+// poll crosses the XCDs).
 //
 // All kernels read element counts from the device (scalars block), so the
 // whole sequence needs no host synchronisation; grids are sized from host
@@ -46,12 +58,6 @@ struct LoadVis {   // 1 if the record is visible
     const uint32_t* nt;
     int64_t n;
     __device__ uint32_t operator()(int64_t i) const { return (i < n && nt[i] != 0u) ? 1u : 0u; }
-};
-struct LoadCnt {   // tile count of the i-th depth-sorted visible record
-    const uint32_t* nt;
-    const uint32_t* ids;
-    const uint32_t* nvis;
-    __device__ uint32_t operator()(int64_t i) const { return i < (int64_t)*nvis ? nt[ids[i]] : 0u; }
 };
 struct LoadArr {
     const uint32_t* a;
@@ -172,22 +178,241 @@ hipError_t device_scan(Ld ld, int64_t n, uint32_t* out, uint32_t* bsum, uint32_t
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ compaction
-__global__ void compact_kernel(const uint32_t* nt, const float4* col, const uint32_t* off, int64_t R, uint32_t* keys,
-                               uint32_t* vals) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R || nt[r] == 0u) return;
-    const uint32_t o = off[r];
-    keys[o] = __float_as_uint(col[r].w);
-    vals[o] = (uint32_t)r;
+// ------------------------------------------------------------------ chained scans
+// Tile status word: bits 62-63 the state (0 not yet published, 1 the tile's
+// own total, 2 the running total through this tile), bits 0-61 the value.
+constexpr uint64_t kLbAgg = 1ull << 62, kLbPrefix = 2ull << 62, kLbValue = (1ull << 62) - 1ull;
+// about 4 s of polling before a workgroup gives up (flagging kFlagLookback)
+constexpr uint32_t kLbMaxPolls = 1u << 22;
+
+// The value travels inside the status word, so relaxed device-scope atomics
+// suffice: no other memory is published through it (acquire / release here
+// would write back and invalidate the XCD's L2 on every poll).
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__global__ void compact_depth_kernel(const uint32_t* nt, const float* depth, const uint32_t* off, int64_t R,
-                                     uint32_t* keys, uint32_t* vals) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R || nt[r] == 0u) return;
-    const uint32_t o = off[r];
-    keys[o] = __float_as_uint(depth[r]);
-    vals[o] = (uint32_t)r;
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// this workgroup's tile, in arrival order
+__device__ __forceinline__ uint32_t lb_tile(uint32_t* counter) {
+    __shared__ uint32_t s_t;
+    if (threadIdx.x == 0) s_t = atomicAdd(counter, 1u);
+    __syncthreads();
+    return s_t;
+}
+
+// Exclusive prefix of `agg` (this tile's total) over the tiles before it.
+// Called by every thread; wavefront 0 publishes and looks back 64 tiles at a
+// time, summing back to the nearest running total.
+__device__ uint64_t lb_exclusive(uint64_t* status, uint32_t tile, uint64_t agg, uint32_t* flags) {
+    __shared__ uint64_t s_excl;
+    if (threadIdx.x < 64) {
+        const int lane = (int)threadIdx.x;
+        if (lane == 0) lb_store(&status[tile], (tile == 0 ? kLbPrefix : kLbAgg) | agg);
+        uint64_t excl = 0;
+        if (tile > 0) {
+            int64_t p = (int64_t)tile - 1;
+            uint32_t polls = 0;
+            while (true) {
+                const int64_t q = p - lane;
+                const uint64_t w = q >= 0 ? lb_load(&status[q]) : kLbPrefix;   // before tile 0: prefix 0
+                const uint32_t st = (uint32_t)(w >> 62);
+                const uint64_t pre = __ballot(st == 2u);
+                const int fp = pre ? __ffsll((long long)pre) - 1 : 64;
+                const uint64_t need = fp >= 63 ? ~0ull : ((2ull << fp) - 1ull);
+                if (__ballot(st == 0u) & need) {
+                    if (++polls > kLbMaxPolls) {
+                        if (lane == 0) atomicOr(flags, kFlagLookback);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                    continue;
+                }
+                uint64_t v = lane <= fp ? (w & kLbValue) : 0ull;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                excl += v;
+                if (fp < 64) break;
+                p -= 64;
+            }
+            if (lane == 0) lb_store(&status[tile], kLbPrefix | (excl + agg));
+        }
+        if (lane == 0) s_excl = excl;
+    }
+    __syncthreads();
+    return s_excl;
+}
+
+// exclusive scan of one 64-bit value per thread over the block; returns the total
+__device__ __forceinline__ uint64_t block_excl_scan64(uint64_t x, uint64_t& excl) {
+    __shared__ uint64_t wsum[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kScanThreads / 64; i++) {
+        const uint64_t s = wsum[i];
+        if (i < w) off += s;
+        tot += s;
+    }
+    excl = off + incl - x;
+    __syncthreads();
+    return tot;
+}
+
+// In-place exclusive scan of a[0..n), one chained launch (radix histograms,
+// visible records per chunk).
+__global__ __launch_bounds__(kScanThreads) void scan_chained_kernel(uint32_t* a, int64_t n, uint64_t* status,
+                                                                    uint32_t* counter, uint32_t* flags) {
+    const uint32_t t = lb_tile(counter);
+    const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = base + k < n ? a[base + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t ex;
+    const uint32_t agg = block_excl_scan(sum, ex);
+    uint32_t run = (uint32_t)lb_exclusive(status, t, agg, flags) + ex;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < n) a[base + k] = run;
+        run += v[k];
+    }
+}
+
+// Visible records (nt != 0) of chunk blockIdx.x (kScanTile records) to
+// (depth bits, record) at the chunk's offset, in record order; the last
+// chunk stores the visible count.  Depth from `depth` when given, else from
+// the records' colour w.
+__global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* nt, const float4* col,
+                                                               const float* depth, const uint32_t* chunk_off,
+                                                               int64_t R, uint32_t* keys, uint32_t* vals,
+                                                               uint32_t* n_visible) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t vis = 0u, cnt = 0u;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        const bool f = base + k < R && nt[base + k] != 0u;
+        vis |= (f ? 1u : 0u) << k;
+        cnt += f ? 1u : 0u;
+    }
+    uint32_t ex;
+    const uint32_t tot = block_excl_scan(cnt, ex);
+    uint32_t o = chunk_off[blockIdx.x] + ex;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if ((vis >> k) & 1u) {
+            const int64_t r = base + k;
+            keys[o] = __float_as_uint(depth ? depth[r] : col[r].w);
+            vals[o] = (uint32_t)r;
+            o++;
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *n_visible = chunk_off[blockIdx.x] + tot;
+}
+
+// pairs (touched bins) of the depth-sorted visible records of one chunk
+__global__ __launch_bounds__(kScanThreads) void pair_count_kernel(const uint32_t* ids, const uint32_t* nt,
+                                                                  const uint32_t* nvis_p, uint64_t* chunk) {
+    const int64_t nvis = (int64_t)*nvis_p;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++)
+        if (base + k < nvis) sum += nt[ids[base + k]];
+    uint64_t ex;
+    const uint64_t tot = block_excl_scan64(sum, ex);
+    if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
+}
+
+// In-place exclusive scan of the chunks' pair counts (64-bit), chained; the
+// last tile stores the total (kPairsLo/Hi) and the pair count for the sort
+// (kNPairs, 0 with kFlagCapacity when the total exceeds the capacity).
+__global__ __launch_bounds__(kScanThreads) void pair_offsets_kernel(uint64_t* a, int64_t n, int64_t cap,
+                                                                    uint64_t* status, uint32_t* scal) {
+    const uint32_t t = lb_tile(scal + kLbPairs);
+    const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = base + k < n ? a[base + k] : 0ull;
+        sum += v[k];
+    }
+    uint64_t ex;
+    const uint64_t agg = block_excl_scan64(sum, ex);
+    const uint64_t excl = lb_exclusive(status, t, agg, scal + kFlags);
+    uint64_t run = excl + ex;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < n) a[base + k] = run;
+        run += v[k];
+    }
+    if (t == gridDim.x - 1 && threadIdx.x == 0) {
+        const uint64_t total = excl + agg;
+        scal[kPairsLo] = (uint32_t)(total & 0xffffffffu);
+        scal[kPairsHi] = (uint32_t)(total >> 32);
+        if (total > (uint64_t)cap) {
+            atomicOr(&scal[kFlags], kFlagCapacity);
+            scal[kNPairs] = 0u;
+        } else {
+            scal[kNPairs] = (uint32_t)total;
+        }
+    }
+}
+
+// One (global bin id, record) pair per bin each depth-sorted visible record
+// of the chunk touches, at the chunk's offset plus the rank within it; pairs
+// past the capacity are not written.  Also clears the per-bin ranges.
+__global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const uint32_t* ids, const uint32_t* nt,
+                                                            const uint2* rect, const uint32_t* nvis_p,
+                                                            const uint64_t* chunk_off, int64_t cap, uint32_t* pk,
+                                                            uint32_t* pv, uint2* ranges, int64_t n_bins) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_bins; b += (int64_t)gridDim.x * blockDim.x)
+        ranges[b] = make_uint2(0u, 0u);
+    const int64_t nvis = (int64_t)*nvis_p;
+    if ((int64_t)blockIdx.x * kScanTile >= nvis) return;   // uniform: the whole chunk is past the records
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t c[kScanItems];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        c[k] = base + k < nvis ? nt[ids[base + k]] : 0u;
+        sum += c[k];
+    }
+    uint64_t ex;
+    block_excl_scan64(sum, ex);
+    uint64_t o = chunk_off[blockIdx.x] + ex;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (c[k] == 0u) continue;
+        const uint32_t r = ids[base + k];
+        const ViewInfo& vi = vt.v[(int)(r / (uint32_t)vt.n)];
+        const uint2 rc = rect[r];
+        const uint32_t tx0 = (rc.x & 0xffffu) / vt.bw, tx1 = (rc.x >> 16) / vt.bw;
+        const uint32_t ty0 = (rc.y & 0xffffu) / vt.bh, ty1 = (rc.y >> 16) / vt.bh;
+        for (uint32_t ty = ty0; ty <= ty1; ty++) {
+            const uint32_t row = (uint32_t)vi.bin_off + ty * (uint32_t)vi.bins_x;
+            for (uint32_t tx = tx0; tx <= tx1; tx++, o++) {
+                if (o < (uint64_t)cap) {
+                    pk[o] = row + tx;
+                    pv[o] = r;
+                }
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -288,23 +513,27 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep_kernel(const uint32_t
 
 // Stable LSD sort of (key, value) pairs on key bits [0, bits).  Element count
 // from n_dev (or n_host when n_dev is null), at most n_bound.  Ping-pongs
-// between (k0, v0) and (k1, v1); *in_second tells where the result is.
+// between (k0, v0) and (k1, v1); *in_second tells where the result is.  The
+// histogram of pass i is scanned by one chained launch using status[i] and
+// counters[i] (cleared beforehand).
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
-                      int64_t n_bound, int bits, uint32_t* hist, uint32_t* scan_bsum, hipStream_t s,
-                      bool* in_second) {
+                      int64_t n_bound, int bits, uint32_t* hist, uint64_t* const* status, uint32_t* counters,
+                      uint32_t* flags, int max_passes, hipStream_t s, bool* in_second) {
     *in_second = false;
     const int64_t nb = (n_bound + kRsTile - 1) / kRsTile;
     if (nb == 0 || bits <= 0) return hipSuccess;
+    if ((bits + 7) / 8 > max_passes) return hipErrorInvalidValue;
     const uint32_t n_host = (uint32_t)n_bound;
+    const int64_t nh = 256 * nb;
+    const unsigned scan_grid = (unsigned)((nh + kScanTile - 1) / kScanTile);
     bool second = false;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = 0, pass = 0; shift < bits; shift += 8, pass++) {
         const uint32_t* ki = second ? k1 : k0;
         const uint32_t* vi = second ? v1 : v0;
         uint32_t* ko = second ? k0 : k1;
         uint32_t* vo = second ? v0 : v1;
         rs_upsweep_kernel<<<(unsigned)nb, kRsThreads, 0, s>>>(ki, n_dev, n_host, shift, hist);
-        hipError_t e = device_scan(LoadArr{hist, 256 * nb}, 256 * nb, hist, scan_bsum, nullptr, nullptr, s);
-        if (e != hipSuccess) return e;
+        scan_chained_kernel<<<scan_grid, kScanThreads, 0, s>>>(hist, nh, status[pass], counters + pass, flags);
         rs_downsweep_kernel<<<(unsigned)nb, kRsThreads, 0, s>>>(ki, vi, ko, vo, n_dev, n_host, shift, hist);
         second = !second;
     }
@@ -312,37 +541,7 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, co
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ pairs
-__global__ void emit_kernel(ViewTable vt, const uint32_t* ids, const uint32_t* nvis, const uint2* rect,
-                            const uint32_t* off, const uint32_t* total64, int64_t cap, uint32_t* pk, uint32_t* pv,
-                            uint32_t* scal) {
-    const uint64_t total = (uint64_t)total64[0] | ((uint64_t)total64[1] << 32);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (total > (uint64_t)cap) {
-        if (i == 0) {
-            atomicOr(&scal[kFlags], 1u);
-            scal[kNPairs] = 0u;
-        }
-        return;
-    }
-    if (i == 0) scal[kNPairs] = (uint32_t)total;
-    if (i >= (int64_t)*nvis) return;
-    const uint32_t r = ids[i];
-    const int v = (int)(r / (uint32_t)vt.n);
-    const ViewInfo& vi = vt.v[v];
-    const uint2 rc = rect[r];
-    const uint32_t tx0 = (rc.x & 0xffffu) / vt.bw, tx1 = (rc.x >> 16) / vt.bw;
-    const uint32_t ty0 = (rc.y & 0xffffu) / vt.bh, ty1 = (rc.y >> 16) / vt.bh;
-    uint32_t o = off[i];
-    for (uint32_t ty = ty0; ty <= ty1; ty++) {
-        const uint32_t row = (uint32_t)vi.bin_off + ty * (uint32_t)vi.bins_x;
-        for (uint32_t tx = tx0; tx <= tx1; tx++, o++) {
-            pk[o] = row + tx;
-            pv[o] = r;
-        }
-    }
-}
-
+// ------------------------------------------------------------------ ranges
 __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* np, uint2* ranges) {
     const uint32_t P = *np;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -397,64 +596,62 @@ hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, uint2* rect
 #define GS_AT(T, off) reinterpret_cast<T*>(base + (off))
 
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
-                                const float* depth_src, hipStream_t s) {
+                                const uint2* rect_src, const float* depth_src, hipStream_t s) {
     uint32_t* scal = GS_AT(uint32_t, L.off_scalars);
-    uint32_t* cnt = GS_AT(uint32_t, L.off_cnt);
-    uint32_t* bsum = GS_AT(uint32_t, L.off_scan);
+    uint64_t* lb = GS_AT(uint64_t, L.off_lb);
     uint32_t* k0 = GS_AT(uint32_t, L.off_k0);
     uint32_t* v0 = GS_AT(uint32_t, L.off_v0);
     uint32_t* k1 = GS_AT(uint32_t, L.off_k1);
     uint32_t* v1 = GS_AT(uint32_t, L.off_v1);
+    uint32_t* csum = GS_AT(uint32_t, L.off_chunk);
+    uint64_t* psum = GS_AT(uint64_t, L.off_chunk);
     const int64_t R = L.R;
-    hipError_t e = launch_fill_u32(scal, 0u, kNumScalars, s);
+    const int64_t nc = L.n_chunks;
+    const unsigned g = (unsigned)nc, gs = (unsigned)L.lb_tiles_chunk;
+    // scalars and every chained-scan status word start at zero
+    hipError_t e = launch_fill_u32(scal, 0u, (int64_t)((L.off_lb - L.off_scalars) / 4) + 2 * lb_words(L), s);
     if (e != hipSuccess) return e;
     // 1. visible records -> compacted (depth bits, record) in record order
-    e = device_scan(LoadVis{nt_src, R}, R, cnt, bsum, nullptr, scal + kNVis, s);
-    if (e != hipSuccess) return e;
-    if (R > 0) {
-        const unsigned g = (unsigned)((R + 255) / 256);
-        if (depth_src)
-            compact_depth_kernel<<<g, 256, 0, s>>>(nt_src, depth_src, cnt, R, k0, v0);
-        else
-            compact_kernel<<<g, 256, 0, s>>>(nt_src, GS_AT(float4, L.off_col), cnt, R, k0, v0);
-    }
-    // 2. stable sort by depth bits
+    scan_reduce_kernel<LoadVis><<<g, kScanThreads, 0, s>>>(LoadVis{nt_src, R}, R, csum);
+    scan_chained_kernel<<<gs, kScanThreads, 0, s>>>(csum, nc, lb, scal + kLbVis, scal + kFlags);
+    compact_kernel<<<g, kScanThreads, 0, s>>>(nt_src, GS_AT(float4, L.off_col), depth_src, csum, R, k0, v0,
+                                              scal + kNVis);
+    // 2. stable sort by depth bits (4 passes: the result is back in (k0, v0))
+    uint64_t* hs[kLbHistUses];
+    for (int i = 0; i < kLbHistUses; i++) hs[i] = lb + 2 * L.lb_tiles_chunk + (int64_t)i * L.lb_tiles_hist;
     bool second;
-    e = radix_sort(k0, v0, k1, v1, scal + kNVis, R, 32, GS_AT(uint32_t, L.off_hist), bsum, s, &second);
+    e = radix_sort(k0, v0, k1, v1, scal + kNVis, R, 32, GS_AT(uint32_t, L.off_hist), hs, scal + kLbHist0,
+                   scal + kFlags, 4, s, &second);
     if (e != hipSuccess) return e;
     const uint32_t* ids = second ? v1 : v0;
-    // 3. pair offsets of the sorted records, 64-bit total in the scalars
-    e = device_scan(LoadCnt{nt_src, ids, scal + kNVis}, R, cnt, bsum, scal + kPairsLo, nullptr, s);
-    if (e != hipSuccess) return e;
+    // 3. pairs in depth order: per-chunk counts, chained offsets (the total
+    //    stays on the device), emission
+    pair_count_kernel<<<g, kScanThreads, 0, s>>>(ids, nt_src, scal + kNVis, psum);
+    pair_offsets_kernel<<<gs, kScanThreads, 0, s>>>(psum, nc, L.cap, lb + L.lb_tiles_chunk, scal);
+    emit_kernel<<<g, kScanThreads, 0, s>>>(vt, ids, nt_src, rect_src, scal + kNVis, psum, L.cap,
+                                           GS_AT(uint32_t, L.off_pk0), GS_AT(uint32_t, L.off_pv0),
+                                           GS_AT(uint2, L.off_ranges), L.n_bins);
     return hipGetLastError();
 }
 
-hipError_t launch_binning_emit(const ViewTable& vt, const Layout& L, char* base, const uint2* rect_src,
-                               int64_t pair_bound, hipStream_t s, uint32_t** sorted_vals_out) {
+hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base, int64_t pair_bound, hipStream_t s,
+                               uint32_t** sorted_vals_out) {
     uint32_t* scal = GS_AT(uint32_t, L.off_scalars);
-    uint32_t* cnt = GS_AT(uint32_t, L.off_cnt);
-    uint32_t* bsum = GS_AT(uint32_t, L.off_scan);
-    // the record sort always runs 4 passes (32 bits): result back in (k0, v0)
-    const uint32_t* ids = GS_AT(uint32_t, L.off_v0);
+    uint64_t* lb = GS_AT(uint64_t, L.off_lb);
     uint32_t* pk0 = GS_AT(uint32_t, L.off_pk0);
     uint32_t* pv0 = GS_AT(uint32_t, L.off_pv0);
     uint32_t* pk1 = GS_AT(uint32_t, L.off_pk1);
     uint32_t* pv1 = GS_AT(uint32_t, L.off_pv1);
-    const int64_t R = L.R;
-    hipError_t e;
-    {
-        const int64_t g = R > 0 ? (R + 255) / 256 : 1;
-        emit_kernel<<<(unsigned)g, 256, 0, s>>>(vt, ids, scal + kNVis, rect_src, cnt, scal + kPairsLo, L.cap, pk0,
-                                                 pv0, scal);
-    }
+    // the pair sort's histogram scans follow the record sort's four
+    uint64_t* hs[kLbHistUses - 4];
+    for (int i = 0; i < kLbHistUses - 4; i++) hs[i] = lb + 2 * L.lb_tiles_chunk + (int64_t)(4 + i) * L.lb_tiles_hist;
     bool second;
-    e = radix_sort(pk0, pv0, pk1, pv1, scal + kNPairs, pair_bound, ceil_log2(L.n_bins),
-                   GS_AT(uint32_t, L.off_hist), bsum, s, &second);
+    hipError_t e = radix_sort(pk0, pv0, pk1, pv1, scal + kNPairs, pair_bound, ceil_log2(L.n_bins),
+                              GS_AT(uint32_t, L.off_hist), hs, scal + kLbHist0 + 4, scal + kFlags, kLbHistUses - 4,
+                              s, &second);
     if (e != hipSuccess) return e;
     const uint32_t* keys = second ? pk1 : pk0;
     uint2* ranges = GS_AT(uint2, L.off_ranges);
-    e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * L.n_bins, s);
-    if (e != hipSuccess) return e;
     if (pair_bound > 0) {
         const int64_t g = (pair_bound + 255) / 256;
         ranges_kernel<<<(unsigned)g, 256, 0, s>>>(keys, scal + kNPairs, ranges);
@@ -466,9 +663,9 @@ hipError_t launch_binning_emit(const ViewTable& vt, const Layout& L, char* base,
 hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
                           const uint2* rect_src, const float* depth_src, int64_t pair_bound, hipStream_t s,
                           uint32_t** sorted_vals_out) {
-    hipError_t e = launch_binning_count(vt, L, base, nt_src, depth_src, s);
+    hipError_t e = launch_binning_count(vt, L, base, nt_src, rect_src, depth_src, s);
     if (e != hipSuccess) return e;
-    return launch_binning_emit(vt, L, base, rect_src, pair_bound, s, sorted_vals_out);
+    return launch_binning_sort(vt, L, base, pair_bound, s, sorted_vals_out);
 }
 
 #undef GS_AT

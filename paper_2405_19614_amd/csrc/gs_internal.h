@@ -130,16 +130,18 @@ struct Layout {
     int64_t sort_blocks;  // radix-sort blocks for max(R, cap)
     size_t off_xy, off_conic, off_col, off_rect, off_nt;
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
-    size_t off_cnt;                               // R (scan buffer)
     size_t off_pk0, off_pv0, off_pk1, off_pv1;    // pair sort (cap)
     size_t off_hist;                              // 256 * sort_blocks
-    size_t off_scan;                              // scan block sums
     size_t off_ranges;                            // n_bins uint2
     size_t off_tfin, off_last;                    // n_pix
     size_t off_torder, off_twork;                 // tile order and work, sized for the smallest tile
     size_t off_g2;                                // R * kG2Stride floats
     size_t off_posepart;                          // V * pose_blocks * 6 doubles
     size_t off_scalars;                           // counters and flags
+    size_t off_lb;                                // chained-scan tile status words (u64), right after the scalars
+    int64_t n_chunks;                             // 2048-record chunks of the records (binning)
+    int64_t lb_tiles_chunk, lb_tiles_hist;        // tiles of a chunk-sum scan and of a radix histogram scan
+    size_t off_chunk;                             // n_chunks u64 chunk sums / offsets
     // mapping workspace only
     size_t off_dC, off_dD;                        // upstream gradients
     size_t off_tilepart;                          // tile partials (sized for the smallest tile)
@@ -150,8 +152,19 @@ struct Layout {
     int64_t pose_blocks;
 };
 
-// scalars block (u32 unless noted), at off_scalars
-enum ScalarSlot { kNVis = 0, kNPairs = 1, kFlags = 2, kPairsLo = 4, kPairsHi = 5, kNumScalars = 16 };
+// scalars block (u32 unless noted), at off_scalars.  kLb*: arrival counters
+// of the chained scans (visible counts and pair counts per chunk, radix
+// histograms: up to kLbHistUses passes per step).
+enum ScalarSlot {
+    kNVis = 0, kNPairs = 1, kFlags = 2, kPairsLo = 4, kPairsHi = 5,
+    kLbVis = 6, kLbPairs = 7, kLbHist0 = 8, kNumScalars = 16
+};
+constexpr int kLbHistUses = kNumScalars - kLbHist0;
+// kFlags bits: pair capacity exceeded; a chained scan gave up waiting
+constexpr uint32_t kFlagCapacity = 1u, kFlagLookback = 2u;
+// status words of the chained scans: two chunk-sum scans (visible records,
+// pairs), then kLbHistUses histogram scans
+inline int64_t lb_words(const Layout& L) { return 2 * L.lb_tiles_chunk + (int64_t)kLbHistUses * L.lb_tiles_hist; }
 
 // tiles_bound: per-tile buffers (workspace) are sized for max(tiles_bound, n_tiles) tiles
 Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, int64_t tiles_bound = 0);
@@ -180,11 +193,14 @@ hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, in
 hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
                           const uint2* rect_src, const float* depth_src, int64_t pair_bound, hipStream_t s,
                           uint32_t** sorted_vals_out);
-// first half of binning (visibility, depth sort, pair offsets); leaves the pair total on the device
+// first half of binning (visibility, depth sort, pair emission); leaves the
+// pair total on the device (kPairsLo/Hi) and flags an exceeded capacity
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
-                                const float* depth_src, hipStream_t s);
-hipError_t launch_binning_emit(const ViewTable& vt, const Layout& L, char* base, const uint2* rect_src,
-                               int64_t pair_bound, hipStream_t s, uint32_t** sorted_vals_out);
+                                const uint2* rect_src, const float* depth_src, hipStream_t s);
+// second half: the pairs' sort by bin (pair_bound: an upper bound of the
+// pair count, which is read on the device) and the per-bin ranges
+hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base, int64_t pair_bound, hipStream_t s,
+                               uint32_t** sorted_vals_out);
 
 struct LossArgs {
     const float* tc;

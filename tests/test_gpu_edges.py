@@ -1,0 +1,88 @@
+"""Edge cases of the batched path against the FP64 oracle: the largest view
+batch the library accepts (64 views in one launch), one more than that
+(rejected), and degenerate image shapes (a single pixel, one row, one
+column)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from synth import scenes
+from tests.gpu_helpers import (GRAD_NAMES, TOL_A, TOL_C, TOL_D_REL, TOL_G, cotangents, dev_scene, forward_errors,
+                               oracle_views, rel)
+
+pytestmark = pytest.mark.gpu
+
+MAX_VIEWS = 64   # views one call accepts (GS_MAX_VIEWS)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2405_19614_amd as gs
+    torch.cuda.set_device(0)
+    return gs.Context(0)
+
+
+def _check_forward_backward(ctx, s, seed):
+    g, poses = dev_scene(s)
+    color, depth, alpha, state, plan = ctx.forward(g, s.cams, poses)
+    og, ref = oracle_views(s)
+    ec, ed, ea, namb = forward_errors(s, color, depth, alpha, ref)
+    zm = float(np.max(np.abs(ref["depth"]), initial=0.0)) + 1.0
+    print(f"  V={s.V} pairs={plan.n_pairs} err C={ec:.2e} D={ed:.2e} A={ea:.2e} ambiguous={namb}", flush=True)
+    assert ec <= TOL_C and ea <= TOL_A and ed <= TOL_D_REL * zm
+    dC, dD, dA = cotangents(s, ref, seed=seed)
+    t = lambda a: torch.tensor(a, device="cuda")
+    grads, dpose = ctx.backward(g, s.cams, poses, state, plan, t(dC), t(dD), t(dA))
+    torch.cuda.synchronize()
+    rg = O.backward_views(og, s.cams, s.poses, dC, dD, dA)
+    for nm in GRAD_NAMES:
+        e = rel(getattr(grads, nm).cpu().numpy(), rg[nm])
+        assert e < TOL_G, (nm, e)
+    for v in range(s.V):
+        assert rel(dpose[v].cpu().numpy(), rg["pose"][v]) < TOL_G, v
+
+
+def test_max_views_in_one_launch(ctx):
+    s = scenes.c3(n=8000, views=MAX_VIEWS, width=48, height=32)
+    print(f"[max-views] V={s.V}", flush=True)
+    _check_forward_backward(ctx, s, seed=31)
+
+
+def test_one_view_too_many_is_rejected(ctx):
+    import paper_2405_19614_amd as gs
+    s = scenes.c3(n=500, views=MAX_VIEWS + 1, width=16, height=16)
+    g, poses = dev_scene(s)
+    with pytest.raises(gs.GSError):
+        ctx.forward(g, s.cams, poses)
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (1, 19), (23, 1), (17, 3)])
+def test_degenerate_image_shapes(ctx, wh):
+    w, h = wh
+    s = scenes.c1(n=400, width=w, height=h, seed=40 + w + h)
+    print(f"[degenerate] {w}x{h}", flush=True)
+    _check_forward_backward(ctx, s, seed=33)
+
+
+def test_mapping_step_loss_per_view_at_max_views(ctx):
+    """The fused loss reduction writes one (Lc, Ld, Lr, Ls) row per view for
+    the largest batch; the colour and depth terms equal the oracle's."""
+    import paper_2405_19614_amd as gs
+    s = scenes.c3(n=8000, views=MAX_VIEWS, width=48, height=32, seed=13)
+    og = O.Gaussians.from_scene(s)
+    tgt = O.render_views(og, s.cams, s.poses_true)
+    tc, td = tgt["color"].astype(np.float32), tgt["depth"].astype(np.float32)
+    g, poses = dev_scene(s)
+    t = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda")
+    st = gs.MappingStep(ctx, g, s.cams, poses, t(tc), t(td), gs.StepOptions(w_color=1.0, w_depth=0.1, use_graph=True))
+    st()
+    torch.cuda.synchronize()
+    assert st.status()["flags"] == 0
+    out = O.render_views(og, s.cams, s.poses)
+    Lc, Ld, _, _ = O.loss_and_upstream(s.cams, out, tc, td, 1.0, 0.1)
+    loss = st.loss.cpu().numpy().astype(np.float64)
+    assert loss.shape == (1 + 4 * s.V,)
+    np.testing.assert_allclose(loss[1::4], Lc, rtol=1e-4, atol=1e-7)
+    np.testing.assert_allclose(loss[2::4], Ld, rtol=1e-4, atol=1e-7)
+    assert abs(loss[0] - float(np.mean(Lc + 0.1 * Ld))) <= 1e-5 * float(np.mean(Lc + 0.1 * Ld)) + 1e-9
