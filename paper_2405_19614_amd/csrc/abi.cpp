@@ -231,6 +231,7 @@ Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     p.rec.col = reinterpret_cast<float4*>(base + L.off_col);
     p.rec.rect = reinterpret_cast<uint2*>(base + L.off_rect);
     p.rec.nt = reinterpret_cast<uint32_t*>(base + L.off_nt);
+    p.rec.vmask = reinterpret_cast<uint64_t*>(base + L.off_vmask);
     p.ranges = reinterpret_cast<uint2*>(base + L.off_ranges);
     p.tfin = reinterpret_cast<float*>(base + L.off_tfin);
     p.last = reinterpret_cast<uint32_t*>(base + L.off_last);
@@ -317,7 +318,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     L.n_pix = vt.n_pix;
     const int64_t R = L.R;
     L.sort_blocks = ceil_div(std::max<int64_t>(std::max<int64_t>(R, cap), 1), 4096);
-    L.pose_blocks = ceil_div(n, 256);
+    L.pose_blocks = ceil_div(n, gs::kProjBwdSpan);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -360,6 +361,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
         L.off_ssim_part = take((size_t)vt.n_pix * 9 * 4);
         L.off_ssim_tiles = take((size_t)vt.n_ssim_tiles * 3 * 8);
     }
+    L.off_vmask = take((size_t)std::max<int64_t>(n, 1) * 8);
     L.bytes = o;
     return L;
 }

@@ -111,6 +111,7 @@ struct Records {
     float4* col;      // (r, g, b, depth)
     uint2* rect;      // inclusive pixel rect (x0 | x1 << 16, y0 | y1 << 16)
     uint32_t* nt;     // bins touched (0 = not visible)
+    uint64_t* vmask;  // per Gaussian (n entries): bit v set when its record in view v is visible
 };
 
 // Per-record 2D gradients summed by the compositing backward, stride
@@ -122,6 +123,10 @@ struct Records {
 // The projection backward undoes the constant factors once per record.
 constexpr int kG2Stride = 12;
 
+// Gaussians per block of the projection backward; the per-view pose partial
+// sums are kept per such block (Layout::pose_blocks = ceil(n / kProjBwdSpan)).
+constexpr int kProjBwdSpan = 1024;
+
 // Device layout of the forward state / mapping workspace (byte offsets).
 struct Layout {
     int64_t R;            // V * n records
@@ -129,6 +134,7 @@ struct Layout {
     int64_t n_bins, n_tiles, n_pix;
     int64_t sort_blocks;  // radix-sort blocks for max(R, cap)
     size_t off_xy, off_conic, off_col, off_rect, off_nt;
+    size_t off_vmask;                             // n uint64 (last, so it moves no other array)
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
     size_t off_pk0, off_pv0, off_pk1, off_pv1;    // pair sort (cap)
     size_t off_hist;                              // 256 * sort_blocks
