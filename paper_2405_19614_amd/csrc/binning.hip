@@ -28,6 +28,8 @@
 // All kernels read element counts from the device (scalars block), so the
 // whole sequence needs no host synchronisation; grids are sized from host
 // upper bounds.
+#include <algorithm>
+
 #include "gs_device.h"
 
 namespace gs {
@@ -422,8 +424,21 @@ constexpr int kRsTile = kRsThreads * kRsItems;   // 4096
 constexpr int kRsWaves = kRsThreads / 64;
 constexpr int kRsPerWave = 64 * kRsItems;        // 1024
 
+// element count: the device count, never more than the bound the launch was sized for
 __device__ __forceinline__ uint32_t load_count(const uint32_t* n_dev, uint32_t n_host) {
-    return n_dev ? *n_dev : n_host;
+    return n_dev ? min(*n_dev, n_host) : n_host;
+}
+
+// Items [lo, hi) of this block: the n items are split into gridDim.x
+// contiguous ranges whose length is a multiple of one wavefront's share of a
+// tile, so block b's items all precede block b + 1's (what makes the
+// digit-major histogram scan give stable positions).  A block walks its range
+// one 4096-item tile at a time.
+__device__ __forceinline__ void rs_range(uint32_t n, uint64_t& lo, uint64_t& hi) {
+    const uint64_t per = ((uint64_t)n + gridDim.x - 1) / gridDim.x;
+    const uint64_t S = (per + kRsPerWave - 1) / kRsPerWave * kRsPerWave;
+    lo = (uint64_t)blockIdx.x * S < n ? (uint64_t)blockIdx.x * S : (uint64_t)n;
+    hi = lo + S < n ? lo + S : (uint64_t)n;
 }
 
 __global__ __launch_bounds__(kRsThreads) void rs_upsweep_kernel(const uint32_t* keys, const uint32_t* n_dev,
@@ -432,12 +447,15 @@ __global__ __launch_bounds__(kRsThreads) void rs_upsweep_kernel(const uint32_t* 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&h[0][0])[i] = 0u;
     __syncthreads();
-    const uint32_t n = load_count(n_dev, n_host);
-    const uint64_t base = (uint64_t)blockIdx.x * kRsTile + (uint64_t)w * kRsPerWave;
+    uint64_t lo, hi;
+    rs_range(load_count(n_dev, n_host), lo, hi);
+    for (uint64_t t0 = lo; t0 < hi; t0 += kRsTile) {
+        const uint64_t base = t0 + (uint64_t)w * kRsPerWave;
 #pragma unroll 4
-    for (int k = 0; k < kRsItems; k++) {
-        const uint64_t e = base + (uint64_t)k * 64 + lane;
-        if (e < n) atomicAdd(&h[w][(keys[e] >> shift) & 255u], 1u);
+        for (int k = 0; k < kRsItems; k++) {
+            const uint64_t e = base + (uint64_t)k * 64 + lane;
+            if (e < hi) atomicAdd(&h[w][(keys[e] >> shift) & 255u], 1u);
+        }
     }
     __syncthreads();
     const int d = threadIdx.x;
@@ -454,60 +472,67 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep_kernel(const uint32_t
     __shared__ uint32_t cnt[kRsWaves][256];
     __shared__ uint32_t goff[256];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&cnt[0][0])[i] = 0u;
     goff[threadIdx.x] = hist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x];
-    __syncthreads();
-    const uint32_t n = load_count(n_dev, n_host);
-    const uint64_t base = (uint64_t)blockIdx.x * kRsTile + (uint64_t)w * kRsPerWave;
+    uint64_t lo, hi;
+    rs_range(load_count(n_dev, n_host), lo, hi);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t key[kRsItems], val[kRsItems], rank[kRsItems];
+    for (uint64_t t0 = lo; t0 < hi; t0 += kRsTile) {
+        for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&cnt[0][0])[i] = 0u;
+        __syncthreads();
+        const uint64_t base = t0 + (uint64_t)w * kRsPerWave;
+        uint32_t key[kRsItems], val[kRsItems], rank[kRsItems];
 #pragma unroll
-    for (int k = 0; k < kRsItems; k++) {
-        const uint64_t e = base + (uint64_t)k * 64 + lane;
-        const bool act = e < n;
-        key[k] = act ? kin[e] : 0u;
-        val[k] = act ? vin[e] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < kRsItems; k++) {
-        const uint64_t e = base + (uint64_t)k * 64 + lane;
-        const bool act = e < n;
-        const uint32_t d = (key[k] >> shift) & 255u;
-        uint64_t peers = __ballot(act);
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
+        for (int k = 0; k < kRsItems; k++) {
+            const uint64_t e = base + (uint64_t)k * 64 + lane;
+            const bool act = e < hi;
+            key[k] = act ? kin[e] : 0u;
+            val[k] = act ? vin[e] : 0u;
         }
-        rank[k] = 0;
-        if (act) {
-            const uint32_t before = cnt[w][d];
-            rank[k] = before + (uint32_t)__popcll(peers & lt);
-            if ((peers >> lane) == 1ull) cnt[w][d] = before + (uint32_t)__popcll(peers);
-        }
-    }
-    __syncthreads();
-    {
-        const int d = threadIdx.x;
-        uint32_t run = 0;
 #pragma unroll
-        for (int i = 0; i < kRsWaves; i++) {
-            const uint32_t c = cnt[i][d];
-            cnt[i][d] = run;
-            run += c;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kRsItems; k++) {
-        const uint64_t e = base + (uint64_t)k * 64 + lane;
-        if (e < n) {
+        for (int k = 0; k < kRsItems; k++) {
+            const uint64_t e = base + (uint64_t)k * 64 + lane;
+            const bool act = e < hi;
             const uint32_t d = (key[k] >> shift) & 255u;
-            const uint32_t pos = goff[d] + cnt[w][d] + rank[k];
-            kout[pos] = key[k];
-            vout[pos] = val[k];
+            uint64_t peers = __ballot(act);
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            rank[k] = 0;
+            if (act) {
+                const uint32_t before = cnt[w][d];
+                rank[k] = before + (uint32_t)__popcll(peers & lt);
+                if ((peers >> lane) == 1ull) cnt[w][d] = before + (uint32_t)__popcll(peers);
+            }
         }
+        __syncthreads();
+        uint32_t tile_total;
+        {
+            const int d = threadIdx.x;
+            uint32_t run = 0;
+#pragma unroll
+            for (int i = 0; i < kRsWaves; i++) {
+                const uint32_t c = cnt[i][d];
+                cnt[i][d] = run;
+                run += c;
+            }
+            tile_total = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kRsItems; k++) {
+            const uint64_t e = base + (uint64_t)k * 64 + lane;
+            if (e < hi) {
+                const uint32_t d = (key[k] >> shift) & 255u;
+                const uint32_t pos = goff[d] + cnt[w][d] + rank[k];
+                kout[pos] = key[k];
+                vout[pos] = val[k];
+            }
+        }
+        __syncthreads();   // goff and cnt are updated for the next tile
+        goff[threadIdx.x] += tile_total;
     }
 }
 
@@ -520,7 +545,7 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, co
                       int64_t n_bound, int bits, uint32_t* hist, uint64_t* const* status, uint32_t* counters,
                       uint32_t* flags, int max_passes, hipStream_t s, bool* in_second) {
     *in_second = false;
-    const int64_t nb = (n_bound + kRsTile - 1) / kRsTile;
+    const int64_t nb = std::min<int64_t>((n_bound + kRsTile - 1) / kRsTile, kRsMaxGrid);
     if (nb == 0 || bits <= 0) return hipSuccess;
     if ((bits + 7) / 8 > max_passes) return hipErrorInvalidValue;
     const uint32_t n_host = (uint32_t)n_bound;

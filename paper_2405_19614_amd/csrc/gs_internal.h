@@ -127,12 +127,17 @@ constexpr int kG2Stride = 12;
 // sums are kept per such block (Layout::pose_blocks = ceil(n / kProjBwdSpan)).
 constexpr int kProjBwdSpan = 1024;
 
+// Largest radix-sort grid: each block sorts a contiguous range of the keys,
+// so the digit histograms (256 x grid words) and their scans stay small
+// however large the key-count bound is.
+constexpr int kRsMaxGrid = 512;
+
 // Device layout of the forward state / mapping workspace (byte offsets).
 struct Layout {
     int64_t R;            // V * n records
     int64_t cap;          // pair capacity
     int64_t n_bins, n_tiles, n_pix;
-    int64_t sort_blocks;  // radix-sort blocks for max(R, cap)
+    int64_t sort_blocks;  // radix-sort grid for max(R, cap), at most kRsMaxGrid
     size_t off_xy, off_conic, off_col, off_rect, off_nt;
     size_t off_vmask;                             // n uint64 (last, so it moves no other array)
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
