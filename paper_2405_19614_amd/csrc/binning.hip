@@ -29,6 +29,7 @@
 // whole sequence needs no host synchronisation; grids are sized from host
 // upper bounds.
 #include <algorithm>
+#include <type_traits>
 
 #include "gs_device.h"
 
@@ -67,6 +68,22 @@ struct LoadArr {
     __device__ uint32_t operator()(int64_t i) const { return i < n ? a[i] : 0u; }
 };
 
+// a[base .. base + 8) into v, zeros past n.  Every array read this way is a
+// workspace array (256-byte aligned) and base is a multiple of 8, so a full
+// group is two 16-byte loads.
+__device__ __forceinline__ void load8(const uint32_t* a, int64_t base, int64_t n, uint32_t (&v)[kScanItems]) {
+    static_assert(kScanItems == 8, "load8 reads eight items");
+    if (base + 8 <= n) {
+        const uint4 x = *reinterpret_cast<const uint4*>(a + base);
+        const uint4 y = *reinterpret_cast<const uint4*>(a + base + 4);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) v[k] = base + k < n ? a[base + k] : 0u;
+    }
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -99,9 +116,16 @@ template <class Ld>
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(Ld ld, int64_t n, uint32_t* bsum) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t s = 0;
+    if constexpr (std::is_same<Ld, LoadVis>::value) {
+        uint32_t v[kScanItems];
+        load8(ld.nt, base, ld.n < n ? ld.n : n, v);
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++)
-        if (base + k < n) s += ld(base + k);
+        for (int k = 0; k < kScanItems; k++) s += v[k] != 0u ? 1u : 0u;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++)
+            if (base + k < n) s += ld(base + k);
+    }
     uint32_t ex;
     const uint32_t tot = block_excl_scan(s, ex);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -278,12 +302,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_chained_kernel(uint32_t* a,
     const uint32_t t = lb_tile(counter);
     const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
+    load8(a, base, n, v);
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        v[k] = base + k < n ? a[base + k] : 0u;
-        sum += v[k];
-    }
+    for (int k = 0; k < kScanItems; k++) sum += v[k];
     uint32_t ex;
     const uint32_t agg = block_excl_scan(sum, ex);
     uint32_t run = (uint32_t)lb_exclusive(status, t, agg, flags) + ex;
@@ -303,10 +325,12 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* n
                                                                int64_t R, uint32_t* keys, uint32_t* vals,
                                                                uint32_t* n_visible) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t c8[kScanItems];
+    load8(nt, base, R, c8);
     uint32_t vis = 0u, cnt = 0u;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-        const bool f = base + k < R && nt[base + k] != 0u;
+        const bool f = c8[k] != 0u;
         vis |= (f ? 1u : 0u) << k;
         cnt += f ? 1u : 0u;
     }
@@ -330,10 +354,12 @@ __global__ __launch_bounds__(kScanThreads) void pair_count_kernel(const uint32_t
                                                                   const uint32_t* nvis_p, uint64_t* chunk) {
     const int64_t nvis = (int64_t)*nvis_p;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t id[kScanItems];
+    load8(ids, base, nvis, id);
     uint64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++)
-        if (base + k < nvis) sum += nt[ids[base + k]];
+        if (base + k < nvis) sum += nt[id[k]];
     uint64_t ex;
     const uint64_t tot = block_excl_scan64(sum, ex);
     if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
@@ -387,11 +413,12 @@ __global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const 
     const int64_t nvis = (int64_t)*nvis_p;
     if ((int64_t)blockIdx.x * kScanTile >= nvis) return;   // uniform: the whole chunk is past the records
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t c[kScanItems];
+    uint32_t id[kScanItems], c[kScanItems];
+    load8(ids, base, nvis, id);
     uint64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-        c[k] = base + k < nvis ? nt[ids[base + k]] : 0u;
+        c[k] = base + k < nvis ? nt[id[k]] : 0u;
         sum += c[k];
     }
     uint64_t ex;
@@ -400,7 +427,7 @@ __global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const 
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
         if (c[k] == 0u) continue;
-        const uint32_t r = ids[base + k];
+        const uint32_t r = id[k];
         const ViewInfo& vi = vt.v[(int)(r / (uint32_t)vt.n)];
         const uint2 rc = rect[r];
         const uint32_t tx0 = (rc.x & 0xffffu) / vt.bw, tx1 = (rc.x >> 16) / vt.bw;
@@ -465,12 +492,19 @@ __global__ __launch_bounds__(kRsThreads) void rs_upsweep_kernel(const uint32_t* 
     hist[(uint64_t)d * gridDim.x + blockIdx.x] = c;
 }
 
+// Per tile: rank every key among the tile's keys of its digit (ballots over
+// the 8 digit bits within a wavefront, per-wavefront digit counters across
+// them), place the tile in LDS in digit order, then write it out with
+// consecutive threads on consecutive positions of each digit's run.
 __global__ __launch_bounds__(kRsThreads) void rs_downsweep_kernel(const uint32_t* kin, const uint32_t* vin,
                                                                   uint32_t* kout, uint32_t* vout,
                                                                   const uint32_t* n_dev, uint32_t n_host, int shift,
                                                                   const uint32_t* hist) {
+    static_assert(kRsThreads == kScanThreads && kRsThreads == 256, "one thread per digit");
     __shared__ uint32_t cnt[kRsWaves][256];
-    __shared__ uint32_t goff[256];
+    __shared__ uint32_t goff[256];   // global position of the block's next key of each digit
+    __shared__ uint32_t toff[256];   // first LDS slot of each digit in the current tile
+    __shared__ uint32_t sk[kRsTile], sv[kRsTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     goff[threadIdx.x] = hist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x];
     uint64_t lo, hi;
@@ -520,18 +554,29 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep_kernel(const uint32_t
             }
             tile_total = run;
         }
+        uint32_t tex;
+        const uint32_t tile_n = block_excl_scan(tile_total, tex);   // (its barriers order cnt as well)
+        toff[threadIdx.x] = tex;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kRsItems; k++) {
             const uint64_t e = base + (uint64_t)k * 64 + lane;
             if (e < hi) {
                 const uint32_t d = (key[k] >> shift) & 255u;
-                const uint32_t pos = goff[d] + cnt[w][d] + rank[k];
-                kout[pos] = key[k];
-                vout[pos] = val[k];
+                const uint32_t loc = toff[d] + cnt[w][d] + rank[k];
+                sk[loc] = key[k];
+                sv[loc] = val[k];
             }
         }
-        __syncthreads();   // goff and cnt are updated for the next tile
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < tile_n; i += kRsThreads) {
+            const uint32_t kk = sk[i];
+            const uint32_t d = (kk >> shift) & 255u;
+            const uint32_t pos = goff[d] + (i - toff[d]);
+            kout[pos] = kk;
+            vout[pos] = sv[i];
+        }
+        __syncthreads();   // goff, cnt and the staging arrays are reused by the next tile
         goff[threadIdx.x] += tile_total;
     }
 }
