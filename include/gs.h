@@ -146,7 +146,8 @@ size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t pair_
  *   g      Gaussians (device)          cams  HOST [V] camera geometry
  *   poses  device [V][16] T_cw         V     1 .. GS_MAX_VIEWS
  *   color  device [sum 3 H W]          depth, alpha  device [sum H W]
- *   state  device buffer of state_bytes >= gs_state_bytes(...); written
+ *   state  device buffer of state_bytes >= gs_state_bytes(...), 256-byte
+ *          aligned (as hipMalloc returns; GS_EINVAL otherwise); written
  *   plan   HOST in/out (see gs_plan)
  * Reads the pair count back once (one stream synchronisation) and returns
  * GS_ECAPACITY with plan->n_pairs = pairs needed when the capacity is too
@@ -245,7 +246,8 @@ typedef struct {
 
 /* Workspace bytes for gs_mapping_step (device; holds the forward state, the
  * upstream gradients, loss partials and status flags), for bins of
- * bin_w x bin_h (0, 0 = 64x64) and any tile shape. */
+ * bin_w x bin_h (0, 0 = 64x64) and any tile shape.  The workspace must be
+ * 256-byte aligned (as hipMalloc returns; GS_EINVAL otherwise). */
 size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int32_t sh_degree,
                                int64_t pair_capacity, int32_t bin_w, int32_t bin_h);
 
@@ -300,8 +302,9 @@ int gs_step_profile(gs_ctx* ctx, gs_gaussians* params, gs_gaussian_grads* grads,
  * by * bins_x + bx.
  *   rect device [V*n][2] u32, depth device [V*n] f32, values device
  *   [values_capacity] u32, ranges device [total tiles][2] u32, n_pairs HOST out.
- * Uses `state` (sized by gs_state_bytes with pair_capacity = values_capacity)
- * as scratch; reads the pair count back (one synchronisation). */
+ * Uses `state` (sized by gs_state_bytes with pair_capacity = values_capacity,
+ * 256-byte aligned) as scratch; reads the pair count back (one
+ * synchronisation). */
 int gs_bin_records(gs_ctx* ctx, const gs_camera* cams, int32_t V, int64_t n, int32_t bin_w, int32_t bin_h,
                    const uint32_t* rect, const float* depth, uint32_t* values, int64_t values_capacity,
                    uint32_t* ranges, int64_t* n_pairs, void* state, size_t state_bytes, void* stream);

@@ -226,16 +226,13 @@ struct Ptrs {
 
 Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     Ptrs p;
-    p.rec.xy = reinterpret_cast<float2*>(base + L.off_xy);
-    p.rec.conic = reinterpret_cast<float4*>(base + L.off_conic);
-    p.rec.col = reinterpret_cast<float4*>(base + L.off_col);
-    p.rec.rect = reinterpret_cast<uint2*>(base + L.off_rect);
+    p.rec.line = reinterpret_cast<gs::RecLine*>(base + L.off_line);
     p.rec.nt = reinterpret_cast<uint32_t*>(base + L.off_nt);
     p.rec.vmask = reinterpret_cast<uint64_t*>(base + L.off_vmask);
     p.ranges = reinterpret_cast<uint2*>(base + L.off_ranges);
     p.tfin = reinterpret_cast<float*>(base + L.off_tfin);
     p.last = reinterpret_cast<uint32_t*>(base + L.off_last);
-    p.g2 = reinterpret_cast<float*>(base + L.off_g2);
+    p.g2 = reinterpret_cast<float*>(base + L.off_line) + gs::kG2Offset;
     p.ts.order = reinterpret_cast<uint32_t*>(base + L.off_torder);
     p.ts.work = reinterpret_cast<uint32_t*>(base + L.off_twork);
     p.posepart = reinterpret_cast<double*>(base + L.off_posepart);
@@ -332,10 +329,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     L.lb_tiles_hist = std::max<int64_t>(ceil_div(256 * L.sort_blocks, 2048), 1);
     L.off_lb = take((size_t)lb_words(L) * 8);       // cleared with the scalars at the start of binning
     L.off_chunk = take((size_t)L.n_chunks * 8);
-    L.off_xy = take((size_t)R * 8);
-    L.off_conic = take((size_t)R * 16);
-    L.off_col = take((size_t)R * 16);
-    L.off_rect = take((size_t)R * 8);
+    L.off_line = take((size_t)R * sizeof(RecLine));
     L.off_nt = take((size_t)R * 4);
     L.off_k0 = take((size_t)R * 4);
     L.off_v0 = take((size_t)R * 4);
@@ -352,7 +346,6 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     const int64_t tb = std::max<int64_t>(tiles_bound, vt.n_tiles);
     L.off_torder = take((size_t)tb * 4);
     L.off_twork = take((size_t)tb * 4);
-    L.off_g2 = take((size_t)R * kG2Stride * 4);
     L.off_posepart = take((size_t)vt.V * std::max<int64_t>(L.pose_blocks, 1) * 6 * 8);
     if (workspace) {
         L.off_dC = take((size_t)vt.n_pix * 3 * 4);
@@ -507,6 +500,7 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false, max_tiles(cams, V));
     if (state_bytes < L.bytes)
         return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
+    if ((uintptr_t)state % 256) return fail(c, GS_EINVAL, "state must be 256-byte aligned");
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(state);
@@ -518,8 +512,8 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     plan->bin_h = bh;
     plan->bwd_tile_w = btw;
     plan->bwd_tile_h = bth;
-    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, nullptr, s));
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.rect, nullptr, s));
+    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, false, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.line, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");
@@ -557,6 +551,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     if ((r = build_bwd_vt(c, cams, V, g->n, plan->bwd_tile_w, plan->bwd_tile_h, vt, 0.f, 0.f, vtb))) return r;
     const gs::Layout L = gs::make_layout(vt, g->n, plan->pair_capacity, false, max_tiles(cams, V));
     if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
+    if ((uintptr_t)state % 256) return fail(c, GS_EINVAL, "state must be 256-byte aligned");
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     Ptrs p = ptrs_of(L, static_cast<char*>(state), false);
@@ -753,10 +748,10 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
     auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     GS_HIP(c, mark(0));
-    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, p.g2, s));
+    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, true, s));
     GS_HIP(c, mark(1));
     uint32_t* vals = nullptr;
-    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.nt, p.rec.rect, nullptr, L.cap, s, &vals));
+    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.nt, p.rec.line, nullptr, L.cap, s, &vals));
     GS_HIP(c, mark(2));
     gs::LossArgs la{tg->color, tg->depth, tg->mask, o->use_gate, o->gate_gamma, p.dC, p.dD, p.tilepart};
     GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, p.ts, s,
@@ -850,6 +845,7 @@ int check_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_ad
     if ((r = build_bwd_vt(c, cams, V, g->n, btw, bth, vt, o->w_color, o->w_depth, vtb))) return r;
     L = gs::make_layout(vt, g->n, o->pair_capacity, true, max_tiles(cams, V));
     if (ws_bytes < L.bytes) return fail(c, GS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
+    if ((uintptr_t)ws % 256) return fail(c, GS_EINVAL, "workspace must be 256-byte aligned");
     return GS_OK;
 }
 
@@ -997,13 +993,14 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
     if (r) return r;
     const gs::Layout L = gs::make_layout(vt, n, cap, false, max_tiles(cams, V));
     if (state_bytes < L.bytes) return fail(c, GS_ENOMEM, "state has %zu bytes, needs %zu", state_bytes, L.bytes);
+    if ((uintptr_t)state % 256) return fail(c, GS_EINVAL, "state must be 256-byte aligned");
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(state);
     Ptrs p = ptrs_of(L, base, false);
     const uint2* rc = reinterpret_cast<const uint2*>(rect);
-    GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.rect, p.rec.nt, n, s));
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.rect, depth, s));
+    GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.line, p.rec.nt, n, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.line, depth, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");

@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_chained_kernel(uint32_t* a,
 // (depth bits, record) at the chunk's offset, in record order; the last
 // chunk stores the visible count.  Depth from `depth` when given, else from
 // the records' colour w.
-__global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* nt, const float4* col,
+__global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* nt, const RecLine* lines,
                                                                const float* depth, const uint32_t* chunk_off,
                                                                int64_t R, uint32_t* keys, uint32_t* vals,
                                                                uint32_t* n_visible) {
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* n
     for (int k = 0; k < kScanItems; k++) {
         if ((vis >> k) & 1u) {
             const int64_t r = base + k;
-            keys[o] = __float_as_uint(depth ? depth[r] : col[r].w);
+            keys[o] = __float_as_uint(depth ? depth[r] : lines[r].col.w);
             vals[o] = (uint32_t)r;
             o++;
         }
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kScanThreads) void pair_offsets_kernel(uint64_t* a,
 // of the chunk touches, at the chunk's offset plus the rank within it; pairs
 // past the capacity are not written.  Also clears the per-bin ranges.
 __global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const uint32_t* ids, const uint32_t* nt,
-                                                            const uint2* rect, const uint32_t* nvis_p,
+                                                            const RecLine* lines, const uint32_t* nvis_p,
                                                             const uint64_t* chunk_off, int64_t cap, uint32_t* pk,
                                                             uint32_t* pv, uint2* ranges, int64_t n_bins) {
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_bins; b += (int64_t)gridDim.x * blockDim.x)
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const 
         if (c[k] == 0u) continue;
         const uint32_t r = id[k];
         const ViewInfo& vi = vt.v[(int)(r / (uint32_t)vt.n)];
-        const uint2 rc = rect[r];
+        const uint2 rc = lines[r].rect;
         const uint32_t tx0 = (rc.x & 0xffffu) / vt.bw, tx1 = (rc.x >> 16) / vt.bw;
         const uint32_t ty0 = (rc.y & 0xffffu) / vt.bh, ty1 = (rc.y >> 16) / vt.bh;
         for (uint32_t ty = ty0; ty <= ty1; ty++) {
@@ -624,7 +624,7 @@ __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* np, uint2* r
 // tile count of each record from its pixel rect (binning entry point); the
 // rect is clipped to its image and the clipped copy is what pairs are emitted
 // from, so a caller's out-of-image rect cannot address a tile of another view
-__global__ void rect_tiles_kernel(ViewTable vt, const uint2* rect, uint2* rect_out, uint32_t* nt, int64_t n) {
+__global__ void rect_tiles_kernel(ViewTable vt, const uint2* rect, RecLine* lines, uint32_t* nt, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * vt.V) return;
     const ViewInfo& vi = vt.v[i / n];
@@ -632,7 +632,7 @@ __global__ void rect_tiles_kernel(ViewTable vt, const uint2* rect, uint2* rect_o
     const uint32_t x0 = rc.x & 0xffffu, y0 = rc.y & 0xffffu;
     const uint32_t x1 = min(rc.x >> 16, (uint32_t)vi.W - 1u), y1 = min(rc.y >> 16, (uint32_t)vi.H - 1u);
     const bool empty = x0 > x1 || y0 > y1;
-    rect_out[i] = empty ? make_uint2(1u, 1u) : make_uint2(x0 | (x1 << 16), y0 | (y1 << 16));
+    lines[i].rect = empty ? make_uint2(1u, 1u) : make_uint2(x0 | (x1 << 16), y0 | (y1 << 16));
     nt[i] = empty ? 0u : (x1 / vt.bw - x0 / vt.bw + 1) * (y1 / vt.bh - y0 / vt.bh + 1);
 }
 
@@ -655,18 +655,18 @@ hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, uint2* rect_out, uint32_t* nt, int64_t n,
+hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* lines, uint32_t* nt, int64_t n,
                              hipStream_t s) {
     const int64_t R = n * vt.V;
     if (R <= 0) return hipSuccess;
-    rect_tiles_kernel<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(vt, rect, rect_out, nt, n);
+    rect_tiles_kernel<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(vt, rect, lines, nt, n);
     return hipGetLastError();
 }
 
 #define GS_AT(T, off) reinterpret_cast<T*>(base + (off))
 
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
-                                const uint2* rect_src, const float* depth_src, hipStream_t s) {
+                                const RecLine* lines, const float* depth_src, hipStream_t s) {
     uint32_t* scal = GS_AT(uint32_t, L.off_scalars);
     uint64_t* lb = GS_AT(uint64_t, L.off_lb);
     uint32_t* k0 = GS_AT(uint32_t, L.off_k0);
@@ -684,7 +684,7 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     // 1. visible records -> compacted (depth bits, record) in record order
     scan_reduce_kernel<LoadVis><<<g, kScanThreads, 0, s>>>(LoadVis{nt_src, R}, R, csum);
     scan_chained_kernel<<<gs, kScanThreads, 0, s>>>(csum, nc, lb, scal + kLbVis, scal + kFlags);
-    compact_kernel<<<g, kScanThreads, 0, s>>>(nt_src, GS_AT(float4, L.off_col), depth_src, csum, R, k0, v0,
+    compact_kernel<<<g, kScanThreads, 0, s>>>(nt_src, lines, depth_src, csum, R, k0, v0,
                                               scal + kNVis);
     // 2. stable sort by depth bits (4 passes: the result is back in (k0, v0))
     uint64_t* hs[kLbHistUses];
@@ -698,7 +698,7 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     //    stays on the device), emission
     pair_count_kernel<<<g, kScanThreads, 0, s>>>(ids, nt_src, scal + kNVis, psum);
     pair_offsets_kernel<<<gs, kScanThreads, 0, s>>>(psum, nc, L.cap, lb + L.lb_tiles_chunk, scal);
-    emit_kernel<<<g, kScanThreads, 0, s>>>(vt, ids, nt_src, rect_src, scal + kNVis, psum, L.cap,
+    emit_kernel<<<g, kScanThreads, 0, s>>>(vt, ids, nt_src, lines, scal + kNVis, psum, L.cap,
                                            GS_AT(uint32_t, L.off_pk0), GS_AT(uint32_t, L.off_pv0),
                                            GS_AT(uint2, L.off_ranges), L.n_bins);
     return hipGetLastError();
@@ -731,9 +731,9 @@ hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base,
 }
 
 hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
-                          const uint2* rect_src, const float* depth_src, int64_t pair_bound, hipStream_t s,
+                          const RecLine* lines, const float* depth_src, int64_t pair_bound, hipStream_t s,
                           uint32_t** sorted_vals_out) {
-    hipError_t e = launch_binning_count(vt, L, base, nt_src, rect_src, depth_src, s);
+    hipError_t e = launch_binning_count(vt, L, base, nt_src, lines, depth_src, s);
     if (e != hipSuccess) return e;
     return launch_binning_sort(vt, L, base, pair_bound, s, sorted_vals_out);
 }

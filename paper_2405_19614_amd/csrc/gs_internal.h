@@ -104,24 +104,40 @@ struct Grads {
     float* col;
 };
 
-// Per-(view, Gaussian) 2D records produced by the projection, r = v*n + g.
-struct Records {
-    float2* xy;       // projected mean
-    float4* conic;    // (A', B', C', log2 opacity): conic in base-2 units, see frag_col
-    float4* col;      // (r, g, b, depth)
-    uint2* rect;      // inclusive pixel rect (x0 | x1 << 16, y0 | y1 << 16)
-    uint32_t* nt;     // bins touched (0 = not visible)
-    uint64_t* vmask;  // per Gaussian (n entries): bit v set when its record in view v is visible
-};
-
-// Per-record 2D gradients summed by the compositing backward, stride
-// kG2Stride floats: with c = log2(e)/2, sd = dL/dsigma per pixel and
-// (dx, dy) the pixel offset from the projected mean,
+// Per-record 2D gradients summed by the compositing backward (twelve floats,
+// ten used): with c = log2(e)/2, sd = dL/dsigma per pixel and (dx, dy) the
+// pixel offset from the projected mean,
 //   [0] c dL/du = -sum sd (A' dx + B' dy / 2)   [1] c dL/dv = -sum sd (C' dy + B' dx / 2)
 //   [2] 2 dL/dA = sum sd dx^2   [3] dL/dB = sum sd dx dy   [4] 2 dL/dC = sum sd dy^2
 //   [5] o dL/do = -sum sd       [6..8] dL/dcolour          [9] dL/dz
 // The projection backward undoes the constant factors once per record.
-constexpr int kG2Stride = 12;
+constexpr int kG2Floats = 12;
+
+// One (view, Gaussian) record, r = v*n + g, in one 128-byte line: what the
+// projection leaves for binning and compositing in the first half, the
+// compositing backward's gradient sums in the second.  The projection of a
+// visible record writes the whole line, and compositing reads one half-line
+// per staged entry, instead of partial lines of five separate arrays.
+struct alignas(128) RecLine {
+    float4 conic;   // (A', B', C', log2 opacity): conic in base-2 units, see frag_col
+    float4 col;     // (r, g, b, depth)
+    float2 xy;      // projected mean
+    uint2 rect;     // inclusive pixel rect (x0 | x1 << 16, y0 | y1 << 16)
+    float4 pad0;
+    float g2[kG2Floats];
+    float4 pad1;
+};
+static_assert(sizeof(RecLine) == 128, "one record per 128-byte line");
+
+// The gradient sums seen as a strided float array: g2 + r * kG2Stride.
+constexpr int kG2Stride = (int)(sizeof(RecLine) / sizeof(float));
+constexpr int kG2Offset = (int)(offsetof(RecLine, g2) / sizeof(float));
+
+struct Records {
+    RecLine* line;    // R record lines
+    uint32_t* nt;     // bins touched (0 = not visible), dense
+    uint64_t* vmask;  // per Gaussian (n entries): bit v set when its record in view v is visible
+};
 
 // Gaussians per block of the projection backward; the per-view pose partial
 // sums are kept per such block (Layout::pose_blocks = ceil(n / kProjBwdSpan)).
@@ -138,7 +154,7 @@ struct Layout {
     int64_t cap;          // pair capacity
     int64_t n_bins, n_tiles, n_pix;
     int64_t sort_blocks;  // radix-sort grid for max(R, cap), at most kRsMaxGrid
-    size_t off_xy, off_conic, off_col, off_rect, off_nt;
+    size_t off_line, off_nt;                      // R record lines (gradient sums inside), R bin counts
     size_t off_vmask;                             // n uint64 (last, so it moves no other array)
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
     size_t off_pk0, off_pv0, off_pk1, off_pv1;    // pair sort (cap)
@@ -146,7 +162,6 @@ struct Layout {
     size_t off_ranges;                            // n_bins uint2
     size_t off_tfin, off_last;                    // n_pix
     size_t off_torder, off_twork;                 // tile order and work, sized for the smallest tile
-    size_t off_g2;                                // R * kG2Stride floats
     size_t off_posepart;                          // V * pose_blocks * 6 doubles
     size_t off_scalars;                           // counters and flags
     size_t off_lb;                                // chained-scan tile status words (u64), right after the scalars
@@ -188,11 +203,12 @@ hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 hipError_t launch_zero_g2(const uint32_t* nt, float* g2, int64_t R, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
 hipError_t launch_step_bump(int32_t* step, hipStream_t s);
-hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, uint2* rect_out, uint32_t* nt, int64_t n,
+hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* lines, uint32_t* nt, int64_t n,
                              hipStream_t s);
 
+// zero_g2: also clear each visible record's gradient sums (mapping step)
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
-                                 float* g2_zero, hipStream_t s);
+                                 bool zero_g2, hipStream_t s);
 hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const float* poses, const Records& rec,
                                  const float* g2, Grads G, int accumulate, double* pose_part, int64_t pose_blocks,
                                  hipStream_t s);
@@ -202,12 +218,12 @@ hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, in
 // Binning: records -> sorted pair values and tile ranges.  All sizes bounded by
 // the layout; counts live on the device in the scalars block.
 hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
-                          const uint2* rect_src, const float* depth_src, int64_t pair_bound, hipStream_t s,
+                          const RecLine* lines, const float* depth_src, int64_t pair_bound, hipStream_t s,
                           uint32_t** sorted_vals_out);
 // first half of binning (visibility, depth sort, pair emission); leaves the
 // pair total on the device (kPairsLo/Hi) and flags an exceeded capacity
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
-                                const uint2* rect_src, const float* depth_src, hipStream_t s);
+                                const RecLine* lines, const float* depth_src, hipStream_t s);
 // second half: the pairs' sort by bin (pair_bound: an upper bound of the
 // pair count, which is read on the device) and the per-bin ranges
 hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base, int64_t pair_bound, hipStream_t s,

@@ -17,7 +17,7 @@ constexpr int kProjBlock = 256;
 // One thread per Gaussian, looping over the views: the parameters come from
 // HBM once and stay in the thread's cache lines for the other views.
 __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt, Params P, const float* poses,
-                                                                    Records rec, float* g2_zero) {
+                                                                    Records rec, bool zero_g2) {
     const int g = blockIdx.x * kProjBlock + threadIdx.x;
     if (g >= P.n) return;
     GPrep gp;
@@ -37,19 +37,21 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
         }
         const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
         const uint32_t ty0 = (uint32_t)pr.y0 / vt.bh, ty1 = (uint32_t)pr.y1 / vt.bh;
-        rec.xy[r] = make_float2(pr.u, pr.v);
-        // base-2 conic with log2(opacity) (the compositing kernels' form)
-        rec.conic[r] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
-        rec.col[r] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);
-        rec.rect[r] =
-            make_uint2((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16), (uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16));
+        // the record line in 16-byte stores: base-2 conic with log2(opacity)
+        // (the compositing kernels' form), colour and depth, mean and rect,
+        // then (mapping step) the zeroed gradient sums
+        float4* q = reinterpret_cast<float4*>(rec.line + r);
+        const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+        q[0] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
+        q[1] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);
+        q[2] = make_float4(pr.u, pr.v, __uint_as_float((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16)),
+                           __uint_as_float((uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16)));
+        q[3] = zero;
+        if (zero_g2) {
+            q[4] = zero; q[5] = zero; q[6] = zero; q[7] = zero;
+        }
         rec.nt[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
         vm |= 1ull << v;
-        if (g2_zero) {
-            float4* z = reinterpret_cast<float4*>(g2_zero + r * kG2Stride);
-            const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-            z[0] = zero; z[1] = zero; z[2] = zero;
-        }
     }
     rec.vmask[g] = vm;
 }
@@ -421,9 +423,9 @@ __global__ __launch_bounds__(256) void pose_finalize_kernel(const double* part, 
 }  // namespace
 
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
-                                 float* g2_zero, hipStream_t s) {
+                                 bool zero_g2, hipStream_t s) {
     if (P.n == 0) return hipSuccess;
-    preprocess_fwd_kernel<<<(P.n + kProjBlock - 1) / kProjBlock, kProjBlock, 0, s>>>(vt, P, poses, rec, g2_zero);
+    preprocess_fwd_kernel<<<(P.n + kProjBlock - 1) / kProjBlock, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2);
     return hipGetLastError();
 }
 

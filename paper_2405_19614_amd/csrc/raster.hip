@@ -221,11 +221,12 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
         float4 eco;
         if (j < rg.y) {
             r = vals[j];
-            rc = rec.rect[r];
+            const float4 xr = reinterpret_cast<const float4*>(rec.line + r)[2];   // (x, y, rect)
+            rc = make_uint2(__float_as_uint(xr.z), __float_as_uint(xr.w));
             pass = rect_meets(rc, bx0, bx1, by0, by1);
             if (pass) {
-                exy = rec.xy[r];
-                eco = rec.conic[r];
+                exy = make_float2(xr.x, xr.y);
+                eco = rec.line[r].conic;
                 pass = ellipse_meets(exy, eco, max(bx0, (int)(rc.x & 0xffffu)), min(bx1, (int)(rc.x >> 16)),
                                      max(by0, (int)(rc.y & 0xffffu)), min(by1, (int)(rc.y >> 16)));
             }
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
         if (pass) {
             s_xy[pos] = exy;
             s_co[pos] = eco;
-            s_cz[pos] = rec.col[r];
+            s_cz[pos] = rec.line[r].col;
             s_rc[pos] = rc;
             s_j[pos] = j;
         }
@@ -425,11 +426,12 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
         float4 eco;
         if ((int)threadIdx.x < span) {
             r = vals[jj];
-            rc0 = rec.rect[r];
+            const float4 xr = reinterpret_cast<const float4*>(rec.line + r)[2];   // (x, y, rect)
+            rc0 = make_uint2(__float_as_uint(xr.z), __float_as_uint(xr.w));
             pass = rect_meets(rc0, bx0, bx1, by0, by1);
             if (pass) {
-                exy = rec.xy[r];
-                eco = rec.conic[r];
+                exy = make_float2(xr.x, xr.y);
+                eco = rec.line[r].conic;
                 pass = ellipse_meets(exy, eco, max(bx0, (int)(rc0.x & 0xffffu)), min(bx1, (int)(rc0.x >> 16)),
                                      max(by0, (int)(rc0.y & 0xffffu)), min(by1, (int)(rc0.y >> 16)));
             }
@@ -441,7 +443,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
             s_j[pos] = jj;
             s_xy[pos] = exy;
             s_co[pos] = eco;
-            s_cz[pos] = rec.col[r];
+            s_cz[pos] = rec.line[r].col;
             s_rc[pos] = rc0;
         }
         __syncthreads();
