@@ -316,14 +316,16 @@ __global__ __launch_bounds__(kScanThreads) void scan_chained_kernel(uint32_t* a,
     }
 }
 
-// Visible records (nt != 0) of chunk blockIdx.x (kScanTile records) to
-// (depth bits, record) at the chunk's offset, in record order; the last
-// chunk stores the visible count.  Depth from `depth` when given, else from
-// the records' colour w.
+// Visible records (nt != 0) of chunk blockIdx.x (kScanTile records), in
+// record order from the chunk's offset o: sort key = depth bits, sort value =
+// o, and info[o] = (record, bin count, pixel rect), so that the passes after
+// the depth sort read one 16-byte entry of a dense array per record instead
+// of gathering from the record lines.  The last chunk stores the visible
+// count.  Depth from `depth` when given, else from the records' colour w.
 __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* nt, const RecLine* lines,
                                                                const float* depth, const uint32_t* chunk_off,
                                                                int64_t R, uint32_t* keys, uint32_t* vals,
-                                                               uint32_t* n_visible) {
+                                                               uint4* info, uint32_t* n_visible) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t c8[kScanItems];
     load8(nt, base, R, c8);
@@ -334,15 +336,25 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* n
         vis |= (f ? 1u : 0u) << k;
         cnt += f ? 1u : 0u;
     }
+    // depths and rects are gathered before any store, so they are in flight at once
+    float dz[kScanItems];
+    uint2 rc[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        const int64_t r = base + k;
+        const bool f = (vis >> k) & 1u;
+        dz[k] = f ? (depth ? depth[r] : lines[r].col.w) : 0.f;
+        rc[k] = f ? lines[r].rect : make_uint2(0u, 0u);
+    }
     uint32_t ex;
     const uint32_t tot = block_excl_scan(cnt, ex);
     uint32_t o = chunk_off[blockIdx.x] + ex;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
         if ((vis >> k) & 1u) {
-            const int64_t r = base + k;
-            keys[o] = __float_as_uint(depth ? depth[r] : lines[r].col.w);
-            vals[o] = (uint32_t)r;
+            keys[o] = __float_as_uint(dz[k]);
+            vals[o] = o;
+            info[o] = make_uint4((uint32_t)(base + k), c8[k], rc[k].x, rc[k].y);
             o++;
         }
     }
@@ -350,7 +362,7 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* n
 }
 
 // pairs (touched bins) of the depth-sorted visible records of one chunk
-__global__ __launch_bounds__(kScanThreads) void pair_count_kernel(const uint32_t* ids, const uint32_t* nt,
+__global__ __launch_bounds__(kScanThreads) void pair_count_kernel(const uint32_t* ids, const uint4* info,
                                                                   const uint32_t* nvis_p, uint64_t* chunk) {
     const int64_t nvis = (int64_t)*nvis_p;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -359,7 +371,7 @@ __global__ __launch_bounds__(kScanThreads) void pair_count_kernel(const uint32_t
     uint64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++)
-        if (base + k < nvis) sum += nt[id[k]];
+        if (base + k < nvis) sum += info[id[k]].y;
     uint64_t ex;
     const uint64_t tot = block_excl_scan64(sum, ex);
     if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
@@ -404,8 +416,8 @@ __global__ __launch_bounds__(kScanThreads) void pair_offsets_kernel(uint64_t* a,
 // One (global bin id, record) pair per bin each depth-sorted visible record
 // of the chunk touches, at the chunk's offset plus the rank within it; pairs
 // past the capacity are not written.  Also clears the per-bin ranges.
-__global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const uint32_t* ids, const uint32_t* nt,
-                                                            const RecLine* lines, const uint32_t* nvis_p,
+__global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const uint32_t* ids, const uint4* info,
+                                                            const uint32_t* nvis_p,
                                                             const uint64_t* chunk_off, int64_t cap, uint32_t* pk,
                                                             uint32_t* pv, uint2* ranges, int64_t n_bins) {
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_bins; b += (int64_t)gridDim.x * blockDim.x)
@@ -413,23 +425,24 @@ __global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const 
     const int64_t nvis = (int64_t)*nvis_p;
     if ((int64_t)blockIdx.x * kScanTile >= nvis) return;   // uniform: the whole chunk is past the records
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t id[kScanItems], c[kScanItems];
+    uint32_t id[kScanItems];
+    uint4 inf[kScanItems];   // (record, bin count, rect) of each depth-ordered record
     load8(ids, base, nvis, id);
     uint64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-        c[k] = base + k < nvis ? nt[id[k]] : 0u;
-        sum += c[k];
+        inf[k] = base + k < nvis ? info[id[k]] : make_uint4(0u, 0u, 0u, 0u);
+        sum += inf[k].y;
     }
     uint64_t ex;
     block_excl_scan64(sum, ex);
     uint64_t o = chunk_off[blockIdx.x] + ex;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-        if (c[k] == 0u) continue;
-        const uint32_t r = id[k];
+        if (inf[k].y == 0u) continue;
+        const uint32_t r = inf[k].x;
         const ViewInfo& vi = vt.v[(int)(r / (uint32_t)vt.n)];
-        const uint2 rc = lines[r].rect;
+        const uint2 rc = make_uint2(inf[k].z, inf[k].w);
         const uint32_t tx0 = (rc.x & 0xffffu) / vt.bw, tx1 = (rc.x >> 16) / vt.bw;
         const uint32_t ty0 = (rc.y & 0xffffu) / vt.bh, ty1 = (rc.y >> 16) / vt.bh;
         for (uint32_t ty = ty0; ty <= ty1; ty++) {
@@ -684,7 +697,8 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     // 1. visible records -> compacted (depth bits, record) in record order
     scan_reduce_kernel<LoadVis><<<g, kScanThreads, 0, s>>>(LoadVis{nt_src, R}, R, csum);
     scan_chained_kernel<<<gs, kScanThreads, 0, s>>>(csum, nc, lb, scal + kLbVis, scal + kFlags);
-    compact_kernel<<<g, kScanThreads, 0, s>>>(nt_src, lines, depth_src, csum, R, k0, v0,
+    uint4* info = GS_AT(uint4, L.off_info);
+    compact_kernel<<<g, kScanThreads, 0, s>>>(nt_src, lines, depth_src, csum, R, k0, v0, info,
                                               scal + kNVis);
     // 2. stable sort by depth bits (4 passes: the result is back in (k0, v0))
     uint64_t* hs[kLbHistUses];
@@ -696,9 +710,9 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     const uint32_t* ids = second ? v1 : v0;
     // 3. pairs in depth order: per-chunk counts, chained offsets (the total
     //    stays on the device), emission
-    pair_count_kernel<<<g, kScanThreads, 0, s>>>(ids, nt_src, scal + kNVis, psum);
+    pair_count_kernel<<<g, kScanThreads, 0, s>>>(ids, info, scal + kNVis, psum);
     pair_offsets_kernel<<<gs, kScanThreads, 0, s>>>(psum, nc, L.cap, lb + L.lb_tiles_chunk, scal);
-    emit_kernel<<<g, kScanThreads, 0, s>>>(vt, ids, nt_src, lines, scal + kNVis, psum, L.cap,
+    emit_kernel<<<g, kScanThreads, 0, s>>>(vt, ids, info, scal + kNVis, psum, L.cap,
                                            GS_AT(uint32_t, L.off_pk0), GS_AT(uint32_t, L.off_pv0),
                                            GS_AT(uint2, L.off_ranges), L.n_bins);
     return hipGetLastError();

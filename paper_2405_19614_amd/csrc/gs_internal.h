@@ -156,6 +156,7 @@ struct Layout {
     int64_t sort_blocks;  // radix-sort grid for max(R, cap), at most kRsMaxGrid
     size_t off_line, off_nt;                      // R record lines (gradient sums inside), R bin counts
     size_t off_vmask;                             // n uint64 (last, so it moves no other array)
+    size_t off_info;                              // R uint4: (record, bin count, rect) per visible record (binning)
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
     size_t off_pk0, off_pv0, off_pk1, off_pv1;    // pair sort (cap)
     size_t off_hist;                              // 256 * sort_blocks

@@ -602,13 +602,20 @@ __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt
     for (int t = threadIdx.x + kKeep * kOrderThreads; t < n; t += kOrderThreads)
         atomicAdd(&cnt[order_bucket(vt, vtf, ranges, work, t)], 1u);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0u;
-        for (int i = 0; i < kOrderBuckets; i++) {
-            const uint32_t c = cnt[i];
-            cnt[i] = acc;
-            acc += c;
+    static_assert(kOrderBuckets == 128, "two buckets per lane of one wavefront");
+    if (threadIdx.x < 64) {
+        // exclusive scan of the bucket counts by the first wavefront
+        const int l = threadIdx.x;
+        const uint32_t a = cnt[2 * l], b = cnt[2 * l + 1];
+        uint32_t x = a + b;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (l >= o) x += y;
         }
+        const uint32_t ex = x - (a + b);
+        cnt[2 * l] = ex;
+        cnt[2 * l + 1] = ex + a;
     }
     __syncthreads();
 #pragma unroll
