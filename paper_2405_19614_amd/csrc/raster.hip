@@ -555,25 +555,38 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable v
 constexpr int kOrderBuckets = 128;
 constexpr int kOrderThreads = 1024;
 
+// Per-view tile geometry of the ordering kernel, staged in LDS once so that
+// the per-tile lookups (a binary search over the views, the tile grids) do
+// not each wait on loads of the kernel arguments.
+struct OrderViews {
+    int toff[kMaxViews], tx[kMaxViews];                 // tiles being ordered
+    int ftoff[kMaxViews], ftx[kMaxViews], fty[kMaxViews];   // forward tiles (work counts)
+    int boff[kMaxViews], bx[kMaxViews];                 // bins
+};
+
 // work estimate of tile t of vt: with `work` (per tile of vtf, the forward's
 // tiling), the sum over the forward tiles that overlap it; else its bin's
 // list length
-__device__ __forceinline__ int order_bucket(const ViewTable& vt, const TileGrid& vtf, const uint2* ranges,
-                                            const uint32_t* work, int t) {
-    const int v = view_of_tile(vt, t);
-    const ViewInfo& vi = vt.v[v];
-    const int lt = t - vi.tile_off;
-    const int tyi = lt / vi.tiles_x, txi = lt - tyi * vi.tiles_x;
+__device__ __forceinline__ int order_bucket(const ViewTable& vt, const TileGrid& vtf, const OrderViews& ov,
+                                            const uint2* ranges, const uint32_t* work, int t) {
+    int lo = 0, hi = vt.V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ov.toff[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int v = lo;
+    const int lt = t - ov.toff[v];
+    const int tyi = lt / ov.tx[v], txi = lt - tyi * ov.tx[v];
     uint32_t w = 0u;
     if (work) {
         const int x0 = txi * vt.tw, y0 = tyi * vt.th;
         const int fx0 = x0 / vtf.tw, fy0 = y0 / vtf.th;
-        const int fx1 = min((x0 + vt.tw - 1) / vtf.tw, vtf.tiles_x[v] - 1);
-        const int fy1 = min((y0 + vt.th - 1) / vtf.th, vtf.tiles_y[v] - 1);
+        const int fx1 = min((x0 + vt.tw - 1) / vtf.tw, ov.ftx[v] - 1);
+        const int fy1 = min((y0 + vt.th - 1) / vtf.th, ov.fty[v] - 1);
         for (int fy = fy0; fy <= fy1; fy++)
-            for (int fx = fx0; fx <= fx1; fx++) w += work[vtf.tile_off[v] + fy * vtf.tiles_x[v] + fx];
+            for (int fx = fx0; fx <= fx1; fx++) w += work[ov.ftoff[v] + fy * ov.ftx[v] + fx];
     } else {
-        const uint2 rg = ranges[bin_of_tile(vt, vi, txi, tyi, vt.tw, vt.th)];
+        const uint2 rg = ranges[ov.boff[v] + ((tyi * vt.th) / vt.bh) * ov.bx[v] + (txi * vt.tw) / vt.bw];
         w = rg.y - rg.x;
     }
     // 4 log2(w + 1) in whole steps: exponent and top two mantissa bits
@@ -586,21 +599,27 @@ __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt
                                                                     const uint32_t* __restrict__ work,
                                                                     uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[kOrderBuckets];
+    __shared__ OrderViews ov;
     constexpr int kKeep = 8;   // buckets a thread keeps for the second pass
     const int n = vt.n_tiles;
     for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) cnt[i] = 0u;
+    for (int v = threadIdx.x; v < vt.V; v += kOrderThreads) {
+        ov.toff[v] = vt.v[v].tile_off; ov.tx[v] = vt.v[v].tiles_x;
+        ov.ftoff[v] = vtf.tile_off[v]; ov.ftx[v] = vtf.tiles_x[v]; ov.fty[v] = vtf.tiles_y[v];
+        ov.boff[v] = vt.v[v].bin_off; ov.bx[v] = vt.v[v].bins_x;
+    }
     __syncthreads();
     int keep[kKeep];
 #pragma unroll
     for (int k = 0; k < kKeep; k++) {
         const int t = threadIdx.x + k * kOrderThreads;
-        keep[k] = t < n ? order_bucket(vt, vtf, ranges, work, t) : 0;
+        keep[k] = t < n ? order_bucket(vt, vtf, ov, ranges, work, t) : 0;
     }
 #pragma unroll
     for (int k = 0; k < kKeep; k++)
         if (threadIdx.x + k * kOrderThreads < n) atomicAdd(&cnt[keep[k]], 1u);
     for (int t = threadIdx.x + kKeep * kOrderThreads; t < n; t += kOrderThreads)
-        atomicAdd(&cnt[order_bucket(vt, vtf, ranges, work, t)], 1u);
+        atomicAdd(&cnt[order_bucket(vt, vtf, ov, ranges, work, t)], 1u);
     __syncthreads();
     static_assert(kOrderBuckets == 128, "two buckets per lane of one wavefront");
     if (threadIdx.x < 64) {
@@ -624,7 +643,7 @@ __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt
         if (t < n) order[atomicAdd(&cnt[keep[k]], 1u)] = (uint32_t)t;
     }
     for (int t = threadIdx.x + kKeep * kOrderThreads; t < n; t += kOrderThreads)
-        order[atomicAdd(&cnt[order_bucket(vt, vtf, ranges, work, t)], 1u)] = (uint32_t)t;
+        order[atomicAdd(&cnt[order_bucket(vt, vtf, ov, ranges, work, t)], 1u)] = (uint32_t)t;
 }
 
 template <int TW, int TH, int PPT>
