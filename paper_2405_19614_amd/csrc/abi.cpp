@@ -23,6 +23,8 @@ struct gs_ctx {
     unsigned long long* counts = nullptr;  // fragment counters of gs_step_profile (device u64[2])
     hipStream_t side = nullptr;      // capture / replay stream used when the caller passes the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t fork = nullptr;      // second stream of a step: the backward's tile order beside the loss
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int tile_w = 16, tile_h = 16;
     int btile_w = 0, btile_h = 0;      // backward tile (0, 0: the forward's)
     int bin_w = 64, bin_h = 64;
@@ -398,6 +400,14 @@ int gs_create(gs_ctx** out, int device) {
         delete c;
         return fail(nullptr, GS_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
     }
+    // default priority (no stream priorities anywhere)
+    e = hipStreamCreateWithFlags(&c->fork, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        gs_destroy(c);
+        return fail(nullptr, GS_EDEVICE, "stream or event creation: %s", hipGetErrorString(e));
+    }
     *out = c;
     return GS_OK;
 }
@@ -409,6 +419,9 @@ void gs_destroy(gs_ctx* c) {
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->fork) (void)hipStreamDestroy(c->fork);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->rp_acc) (void)hipFree(c->rp_acc);
     delete c;
@@ -732,8 +745,9 @@ int gs_densify(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, 
 
 namespace {
 
-// Stages of one step, timed by gs_step_profile ("loss_reproj" also orders the
-// backward's tiles, so "composite_bwd" is the backward compositing kernel alone).
+// Stages of one step, timed by gs_step_profile ("loss_reproj" ends when the
+// backward's tile order, computed beside it on the second stream, is ready, so
+// "composite_bwd" is the backward compositing kernel alone).
 const char* const kStageNames[] = {"preprocess_fwd", "binning",        "composite_fwd", "ssim",
                                    "loss_reproj",    "composite_bwd",  "preprocess_bwd", "optimizer"};
 constexpr int kNumStages = 8;
@@ -758,6 +772,13 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, p.ts, s,
                                        counts));
     GS_HIP(c, mark(3));
+    // The backward's tile order needs only the forward's per-tile work: it runs
+    // on the context's second stream while the loss terms are reduced here
+    // (captured into the step's graph as a parallel branch).
+    GS_HIP(c, hipEventRecord(c->ev_fork, s));
+    GS_HIP(c, hipStreamWaitEvent(c->fork, c->ev_fork, 0));
+    GS_HIP(c, gs::launch_order_tiles(vtb, vt, p.ranges, p.ts, c->fork));
+    GS_HIP(c, hipEventRecord(c->ev_join, c->fork));
     // SSIM term of the mapping loss: its gradient joins the L1 upstream gradient in dC
     const bool ssim = o->w_ssim > 0.f;
     if (ssim) {
@@ -773,7 +794,7 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, ssim ? p.ssim_tiles : nullptr,
                                      o->w_color, o->w_depth, o->w_reproj, o->w_ssim, loss_out, p.rpacc + 8 * vt.V,
                                      s));
-    GS_HIP(c, gs::launch_order_tiles(vtb, vt, p.ranges, p.ts, s));
+    GS_HIP(c, hipStreamWaitEvent(s, c->ev_join, 0));
     GS_HIP(c, mark(5));
     GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, vt,
                                        true, s));
