@@ -86,3 +86,24 @@ def test_mapping_step_loss_per_view_at_max_views(ctx):
     np.testing.assert_allclose(loss[1::4], Lc, rtol=1e-4, atol=1e-7)
     np.testing.assert_allclose(loss[2::4], Ld, rtol=1e-4, atol=1e-7)
     assert abs(loss[0] - float(np.mean(Lc + 0.1 * Ld))) <= 1e-5 * float(np.mean(Lc + 0.1 * Ld)) + 1e-9
+
+
+def test_binning_multi_tile_sort_ranges(ctx):
+    """More keys than 512 sort blocks x 4096 keys: each radix block then walks
+    several tiles of its contiguous range, in both the depth sort (2.4M
+    visible records) and the bin sort (about 5M pairs); the result must still
+    equal the oracle's (tile, depth, record) order bit for bit, ties included."""
+    sizes = [(1200, 680), (1200, 680)]
+    n = 1_500_000
+    rect, depth = scenes.synthetic_binning_records(sizes, n, seed=77, max_ext=8)
+    vals_ref, ranges_ref = O.binning(sizes, n, 16, 16, rect, depth)
+    visible = int(np.count_nonzero((rect[:, 0] & 0xFFFF) <= (rect[:, 0] >> 16)))
+    print(f"[binning-large] visible={visible} pairs={vals_ref.size}", flush=True)
+    assert visible > 512 * 4096 and vals_ref.size > 512 * 4096
+    cams = [scenes.Camera(w, h, 600.0, 600.0, w / 2, h / 2) for w, h in sizes]
+    rt = torch.tensor(rect.view(np.int32), device="cuda")
+    dt = torch.tensor(depth, device="cuda")
+    vals, ranges = ctx.bin_records(cams, n, (16, 16), rt, dt, capacity=int(vals_ref.size) + 7)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(vals.cpu().numpy(), vals_ref.astype(np.int64))
+    np.testing.assert_array_equal(ranges.cpu().numpy(), ranges_ref.astype(np.int64))
