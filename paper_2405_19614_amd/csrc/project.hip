@@ -105,8 +105,10 @@ static_assert(kProjBwdSpan % kProjBlock == 0 && kProjBwdSpan <= 65536, "span of 
 // per-view pose 6-vector is summed over each wavefront (FP32), added to that
 // wavefront's FP64 slot, and the four slots are added at the end: a fixed
 // order, with no barrier inside the walk.
+// RGB colours: at most 128 VGPRs (four waves per SIMD; it fits without
+// spilling).  The SH variants keep the compiler's choice: capped, they spill.
 template <int SH>
-__global__ __launch_bounds__(kProjBlock) __attribute__((amdgpu_waves_per_eu(4))) void preprocess_bwd_kernel(ViewTable vt, Params P, const float* poses,
+__global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_kernel(ViewTable vt, Params P, const float* poses,
                                                                     const uint64_t* vmask, const float* g2, Grads G,
                                                                     int accumulate, double* pose_part,
                                                                     int pose_blocks) {

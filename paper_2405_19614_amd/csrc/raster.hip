@@ -334,8 +334,11 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
     }
 }
 
+// At most 128 VGPRs (four waves per SIMD): left to itself the compiler takes
+// 140 for the 8-pixel shapes, which leaves room for three, and the kernel
+// fits in 128 without spilling.
 template <int TW, int TH, int PPT>
-__global__ __launch_bounds__(TW* TH / PPT) void composite_bwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
+__global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4))) void composite_bwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
                                                                      const uint32_t* __restrict__ vals, Records rec,
                                                                      const float* __restrict__ tfin,
                                                                      const uint32_t* __restrict__ last,
