@@ -25,6 +25,12 @@
 // from such a scan; chaining them directly measured slower (every status
 // poll crosses the XCDs).
 //
+// The compaction also writes each visible record's (record, bin count, rect)
+// into a dense array at its compaction slot, and the depth sort carries the
+// slot, so the pair kernels read that small array instead of gathering from
+// the record lines.  Radix blocks take contiguous ranges of the keys, at most
+// 512 of them, so the histogram table does not grow with the key bound.
+//
 // All kernels read element counts from the device (scalars block), so the
 // whole sequence needs no host synchronisation; grids are sized from host
 // upper bounds.

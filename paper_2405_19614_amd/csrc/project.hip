@@ -1,11 +1,13 @@
 // Projection of every (view, Gaussian) pair and its reverse mode.
 //
 // Forward (Sec. 3.4 "Projection"): one thread per Gaussian looping over the
-// views, writes each (view, Gaussian) 2D record (mean, conic + opacity,
-// colour + depth, pixel rect, bin count).
-// Backward: one thread per Gaussian looping over the views, so each
+// views, writes each visible (view, Gaussian) record line (conic + opacity,
+// colour + depth, mean, pixel rect), every record's bin count, and each
+// Gaussian's view mask.
+// Backward: per block of Gaussians, the ones some view sees are packed into a
+// list and one thread per listed Gaussian loops over its views, so each
 // Gaussian's parameter gradient is summed in registers (no atomics) and the
-// per-view pose 6-vector is reduced per block in FP64 (deterministic).
+// per-view pose 6-vector is reduced in a fixed order in FP64 (deterministic).
 #include "gs_device.h"
 
 namespace gs {
