@@ -316,7 +316,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     L.n_tiles = vt.n_tiles;
     L.n_pix = vt.n_pix;
     const int64_t R = L.R;
-    L.sort_blocks = std::min<int64_t>(ceil_div(std::max<int64_t>(std::max<int64_t>(R, cap), 1), 4096),
+    L.sort_blocks = std::min<int64_t>(ceil_div(std::max<int64_t>(std::max<int64_t>(R, cap), 1), gs::kRsTileKeys),
                                       gs::kRsMaxGrid);
     L.pose_blocks = ceil_div(n, gs::kProjBwdSpan);
     size_t o = 0;

@@ -465,10 +465,11 @@ __global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const 
 
 // ------------------------------------------------------------------ radix sort
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kRsThreads * kRsItems;   // 4096
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;   // 2048
+static_assert(kRsTile == kRsTileKeys, "the layout sizes the histogram table with kRsTileKeys");
 constexpr int kRsWaves = kRsThreads / 64;
-constexpr int kRsPerWave = 64 * kRsItems;        // 1024
+constexpr int kRsPerWave = 64 * kRsItems;        // 512
 
 // element count: the device count, never more than the bound the launch was sized for
 __device__ __forceinline__ uint32_t load_count(const uint32_t* n_dev, uint32_t n_host) {
@@ -479,7 +480,7 @@ __device__ __forceinline__ uint32_t load_count(const uint32_t* n_dev, uint32_t n
 // contiguous ranges whose length is a multiple of one wavefront's share of a
 // tile, so block b's items all precede block b + 1's (what makes the
 // digit-major histogram scan give stable positions).  A block walks its range
-// one 4096-item tile at a time.
+// one 2048-item tile at a time.
 __device__ __forceinline__ void rs_range(uint32_t n, uint64_t& lo, uint64_t& hi) {
     const uint64_t per = ((uint64_t)n + gridDim.x - 1) / gridDim.x;
     const uint64_t S = (per + kRsPerWave - 1) / kRsPerWave * kRsPerWave;

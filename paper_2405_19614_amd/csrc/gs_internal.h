@@ -147,6 +147,9 @@ constexpr int kProjBwdSpan = 1024;
 // so the digit histograms (256 x grid words) and their scans stay small
 // however large the key-count bound is.
 constexpr int kRsMaxGrid = 512;
+// Keys one radix-sort block ranks per tile (the layout sizes the histogram
+// table as 256 x min(ceil(bound / kRsTileKeys), kRsMaxGrid)).
+constexpr int kRsTileKeys = 2048;
 
 // Device layout of the forward state / mapping workspace (byte offsets).
 struct Layout {
