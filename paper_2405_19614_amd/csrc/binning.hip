@@ -74,19 +74,21 @@ struct LoadArr {
     __device__ uint32_t operator()(int64_t i) const { return i < n ? a[i] : 0u; }
 };
 
-// a[base .. base + 8) into v, zeros past n.  Every array read this way is a
-// workspace array (256-byte aligned) and base is a multiple of 8, so a full
-// group is two 16-byte loads.
-__device__ __forceinline__ void load8(const uint32_t* a, int64_t base, int64_t n, uint32_t (&v)[kScanItems]) {
-    static_assert(kScanItems == 8, "load8 reads eight items");
-    if (base + 8 <= n) {
-        const uint4 x = *reinterpret_cast<const uint4*>(a + base);
-        const uint4 y = *reinterpret_cast<const uint4*>(a + base + 4);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+// a[base .. base + N) into v, zeros past n.  Every array read this way is a
+// workspace array (256-byte aligned) and base is a multiple of N (N a
+// multiple of 4), so a full group is N / 4 16-byte loads.
+template <int N>
+__device__ __forceinline__ void loadN(const uint32_t* a, int64_t base, int64_t n, uint32_t (&v)[N]) {
+    static_assert(N % 4 == 0, "whole 16-byte loads");
+    if (base + N <= n) {
+#pragma unroll
+        for (int i = 0; i < N / 4; i++) {
+            const uint4 x = *reinterpret_cast<const uint4*>(a + base + 4 * i);
+            v[4 * i] = x.x; v[4 * i + 1] = x.y; v[4 * i + 2] = x.z; v[4 * i + 3] = x.w;
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < kScanItems; k++) v[k] = base + k < n ? a[base + k] : 0u;
+        for (int k = 0; k < N; k++) v[k] = base + k < n ? a[base + k] : 0u;
     }
 }
 
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(Ld ld, int64_
     uint32_t s = 0;
     if constexpr (std::is_same<Ld, LoadVis>::value) {
         uint32_t v[kScanItems];
-        load8(ld.nt, base, ld.n < n ? ld.n : n, v);
+        loadN(ld.nt, base, ld.n < n ? ld.n : n, v);
 #pragma unroll
         for (int k = 0; k < kScanItems; k++) s += v[k] != 0u ? 1u : 0u;
     } else {
@@ -277,9 +279,11 @@ __device__ uint64_t lb_exclusive(uint64_t* status, uint32_t tile, uint64_t agg, 
     return s_excl;
 }
 
-// exclusive scan of one 64-bit value per thread over the block; returns the total
+// exclusive scan of one 64-bit value per thread over the block of NT
+// threads; returns the total
+template <int NT = kScanThreads>
 __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t x, uint64_t& excl) {
-    __shared__ uint64_t wsum[kScanThreads / 64];
+    __shared__ uint64_t wsum[NT / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint64_t incl = x;
 #pragma unroll
@@ -291,7 +295,7 @@ __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t x, uint64_t& excl
     __syncthreads();
     uint64_t off = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kScanThreads / 64; i++) {
+    for (int i = 0; i < NT / 64; i++) {
         const uint64_t s = wsum[i];
         if (i < w) off += s;
         tot += s;
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_chained_kernel(uint32_t* a,
     const uint32_t t = lb_tile(counter);
     const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
-    load8(a, base, n, v);
+    loadN(a, base, n, v);
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) sum += v[k];
@@ -334,7 +338,7 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* n
                                                                uint4* info, uint32_t* n_visible) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t c8[kScanItems];
-    load8(nt, base, R, c8);
+    loadN(nt, base, R, c8);
     uint32_t vis = 0u, cnt = 0u;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
@@ -367,19 +371,25 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* n
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *n_visible = chunk_off[blockIdx.x] + tot;
 }
 
+// The pair kernels walk the depth-sorted visible records: 512 threads per
+// 2048-record chunk (four records each), so that the few chunks there are
+// run as many wavefronts.
+constexpr int kPairThreads = 512;
+constexpr int kPairItems = kScanTile / kPairThreads;
+
 // pairs (touched bins) of the depth-sorted visible records of one chunk
-__global__ __launch_bounds__(kScanThreads) void pair_count_kernel(const uint32_t* ids, const uint4* info,
+__global__ __launch_bounds__(kPairThreads) void pair_count_kernel(const uint32_t* ids, const uint4* info,
                                                                   const uint32_t* nvis_p, uint64_t* chunk) {
     const int64_t nvis = (int64_t)*nvis_p;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t id[kScanItems];
-    load8(ids, base, nvis, id);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kPairItems;
+    uint32_t id[kPairItems];
+    loadN(ids, base, nvis, id);
     uint64_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++)
+    for (int k = 0; k < kPairItems; k++)
         if (base + k < nvis) sum += info[id[k]].y;
     uint64_t ex;
-    const uint64_t tot = block_excl_scan64(sum, ex);
+    const uint64_t tot = block_excl_scan64<kPairThreads>(sum, ex);
     if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
 }
 
@@ -422,7 +432,7 @@ __global__ __launch_bounds__(kScanThreads) void pair_offsets_kernel(uint64_t* a,
 // One (global bin id, record) pair per bin each depth-sorted visible record
 // of the chunk touches, at the chunk's offset plus the rank within it; pairs
 // past the capacity are not written.  Also clears the per-bin ranges.
-__global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const uint32_t* ids, const uint4* info,
+__global__ __launch_bounds__(kPairThreads) void emit_kernel(ViewTable vt, const uint32_t* ids, const uint4* info,
                                                             const uint32_t* nvis_p,
                                                             const uint64_t* chunk_off, int64_t cap, uint32_t* pk,
                                                             uint32_t* pv, uint2* ranges, int64_t n_bins) {
@@ -430,21 +440,21 @@ __global__ __launch_bounds__(kScanThreads) void emit_kernel(ViewTable vt, const 
         ranges[b] = make_uint2(0u, 0u);
     const int64_t nvis = (int64_t)*nvis_p;
     if ((int64_t)blockIdx.x * kScanTile >= nvis) return;   // uniform: the whole chunk is past the records
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t id[kScanItems];
-    uint4 inf[kScanItems];   // (record, bin count, rect) of each depth-ordered record
-    load8(ids, base, nvis, id);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kPairItems;
+    uint32_t id[kPairItems];
+    uint4 inf[kPairItems];   // (record, bin count, rect) of each depth-ordered record
+    loadN(ids, base, nvis, id);
     uint64_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
+    for (int k = 0; k < kPairItems; k++) {
         inf[k] = base + k < nvis ? info[id[k]] : make_uint4(0u, 0u, 0u, 0u);
         sum += inf[k].y;
     }
     uint64_t ex;
-    block_excl_scan64(sum, ex);
+    block_excl_scan64<kPairThreads>(sum, ex);
     uint64_t o = chunk_off[blockIdx.x] + ex;
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
+    for (int k = 0; k < kPairItems; k++) {
         if (inf[k].y == 0u) continue;
         const uint32_t r = inf[k].x;
         const ViewInfo& vi = vt.v[(int)(r / (uint32_t)vt.n)];
@@ -717,9 +727,9 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     const uint32_t* ids = second ? v1 : v0;
     // 3. pairs in depth order: per-chunk counts, chained offsets (the total
     //    stays on the device), emission
-    pair_count_kernel<<<g, kScanThreads, 0, s>>>(ids, info, scal + kNVis, psum);
+    pair_count_kernel<<<g, kPairThreads, 0, s>>>(ids, info, scal + kNVis, psum);
     pair_offsets_kernel<<<gs, kScanThreads, 0, s>>>(psum, nc, L.cap, lb + L.lb_tiles_chunk, scal);
-    emit_kernel<<<g, kScanThreads, 0, s>>>(vt, ids, info, scal + kNVis, psum, L.cap,
+    emit_kernel<<<g, kPairThreads, 0, s>>>(vt, ids, info, scal + kNVis, psum, L.cap,
                                            GS_AT(uint32_t, L.off_pk0), GS_AT(uint32_t, L.off_pv0),
                                            GS_AT(uint2, L.off_ranges), L.n_bins);
     return hipGetLastError();
