@@ -26,9 +26,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # launch shape timed by default: forward tiles 16x16 with 4 pixels per thread,
-# bins 256x256, backward tiles 32x64 with 8 pixels per thread (the fastest in
+# bins 512x256, backward tiles 32x64 with 8 pixels per thread (the fastest in
 # a sweep of shapes and bins on this workload; --tile auto tunes instead)
-DEFAULT_LAUNCH = "16x16,4,256x256,32x64,8"
+DEFAULT_LAUNCH = "16x16,4,512x256,32x64,8"
 
 # published MI355X peaks
 PEAK_HBM_GBS = 8000.0
