@@ -146,3 +146,31 @@ def test_mapping_step_accumulates_gradients(ctx, use_graph):
         visible |= (base[nm].reshape(s.n, -1) != 0).any(dim=1).cpu()
     print(f"[accumulate] graph={use_graph} Gaussians with a gradient: {int(visible.sum())} of {s.n}", flush=True)
     assert 0 < int(visible.sum()) < s.n
+
+
+def test_misaligned_state_is_rejected(ctx):
+    """The record lines need a 256-byte aligned state buffer: a state pointer
+    16 bytes past an aligned one is refused on the host (GS_EINVAL) before any
+    launch; the aligned one works."""
+    import ctypes
+    from paper_2405_19614_amd import _abi as A
+    from paper_2405_19614_amd.binding import _p, _stream, cam_array
+    s = scenes.c1(n=300, width=32, height=24, seed=3)
+    g, poses = dev_scene(s)
+    cap = 1 << 14
+    nbytes = ctx.state_bytes(s.cams, s.n, cap)
+    buf = torch.empty(nbytes + 512, dtype=torch.uint8, device="cuda")
+    assert buf.data_ptr() % 256 == 0
+    npix = s.npix
+    color = torch.empty(3 * npix, device="cuda")
+    depth = torch.empty(npix, device="cuda")
+    alpha = torch.empty(npix, device="cuda")
+    gst = g.struct()
+    for off, want in [(16, A.GS_EINVAL), (256, A.GS_OK)]:
+        plan = A.gs_plan(0, 0, 0, 0, cap, 0, 0)
+        rc = ctx.lib.gs_render_forward(ctx.h, ctypes.byref(gst), cam_array(s.cams), _p(poses), s.V, _p(color),
+                                       _p(depth), _p(alpha), ctypes.c_void_p(buf.data_ptr() + off), nbytes,
+                                       ctypes.byref(plan), _stream())
+        torch.cuda.synchronize()
+        print(f"[alignment] offset {off}: rc {rc}", flush=True)
+        assert rc == want, (off, rc, ctx.lib.gs_last_error(ctx.h))
