@@ -259,9 +259,14 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
                 for (int q = 0; q < PPT; q++) {
                     const float raw = frag_raw(fc, co, (float)(py0 + q) - xy.y);
                     const float a = fminf(kAlphaMax, raw);
+                    // the rect's rows need no test: outside the rect the exact alpha
+                    // is at least 2.5 % below 1/255 (the projection's margins), so
+                    // the alpha test rejects those pixels by itself; the counters
+                    // still count candidates inside the rect
                     bool inr = colok;
-                    if constexpr (!decltype(rows_in)::value) inr = inr & (py0 + q >= rs.y0) & (py0 + q <= rs.y1);
-                    const bool ok = inr & (a >= kAlphaMin);
+                    if constexpr (COUNT && !decltype(rows_in)::value)
+                        inr = inr & (py0 + q >= rs.y0) & (py0 + q <= rs.y1);
+                    const bool ok = colok & (a >= kAlphaMin);
                     // T (1 - alpha), negative once stopped, so a stopped pixel
                     // never blends again
                     const float aT = a * T[q];
@@ -281,7 +286,7 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
                     D[q] += cz.w * w;
                 }
             };
-            if (rs.y0 <= wy0 && rs.y1 >= wy1) blend(std::true_type{});
+            if (!COUNT || (rs.y0 <= wy0 && rs.y1 >= wy1)) blend(std::true_type{});
             else blend(std::false_type{});
         }
         all_done = true;
@@ -401,9 +406,8 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
         // adds exact zeros
         if (lastp[q] == 0u) T[q] = g0[q] = g1[q] = g2c[q] = gd[q] = Q[q] = 0.f;
     }
-    // rows of this wavefront, and the smallest stop index among its pixels
-    // that blended something: entries before it need no per-pixel stop test
-    const int wy0 = __builtin_amdgcn_readfirstlane(py0), wy1 = wy0 + (64 / TW) * PPT - 1;
+    // the smallest stop index among this wavefront's pixels that blended
+    // something: entries before it need no per-pixel stop test
     uint32_t wmin = 0xffffffffu;
 #pragma unroll
     for (int q = 0; q < PPT; q++) wmin = min(wmin, lastp[q] ? lastp[q] : 0xffffffffu);
@@ -461,20 +465,21 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
             // thread) gets an infinite exponent, so its alpha is exactly zero
             FragCol fc = frag_col(fpx, xy, co);
             if (!((j < mylast) & (px >= rs.x0) & (px <= rs.x1))) fc.a0 = __builtin_inff();
-            // pass 1: the alpha of every owned pixel, zeroed where the forward
-            // did not blend it (past the pixel's stop index or outside the
-            // rect's rows); min(0.99, raw) >= 1/255 exactly when raw >= 1/255.
-            // Entries before every pixel's stop index whose rect covers the
-            // wavefront's rows need neither test.
+            // pass 1: the alpha of every owned pixel, zeroed past the pixel's
+            // stop index (where the forward did not blend it); min(0.99, raw)
+            // >= 1/255 exactly when raw >= 1/255.  Rows outside the rect need
+            // no test, as in the forward: there raw < 1/255 by the
+            // projection's margins.  Entries before every pixel's stop index
+            // need no per-pixel test at all.
             float raw[PPT];
-            if (j < wmin && rs.y0 <= wy0 && rs.y1 >= wy1) {
+            if (j < wmin) {
 #pragma unroll
                 for (int q = 0; q < PPT; q++) raw[q] = frag_raw(fc, co, (float)(py0 + q) - xy.y);
             } else {
 #pragma unroll
                 for (int q = 0; q < PPT; q++) {
                     const float r = frag_raw(fc, co, (float)(py0 + q) - xy.y);
-                    raw[q] = ((j < lastp[q]) & (py0 + q >= rs.y0) & (py0 + q <= rs.y1)) ? r : 0.f;
+                    raw[q] = (j < lastp[q]) ? r : 0.f;
                 }
             }
             float rmax = raw[0];
