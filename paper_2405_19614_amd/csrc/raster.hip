@@ -251,22 +251,22 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
             const uint32_t jk = __builtin_amdgcn_readfirstlane(s_j[k]) + 1u;
             // predicates combine with & (not &&): no per-pixel exec-mask branches
             const RectS rs = rect_scalar(rc);
-            const bool colok = (px >= rs.x0) & (px <= rs.x1);
+            const bool colok = (px >= rs.x0) & (px <= rs.x1);   // counters only
             const FragCol fc = frag_col(fpx, xy, co);
-            // rows known to lie inside the rect skip the per-row compares
+            // rows known to lie inside the rect skip the counters' per-row compares
             const auto blend = [&](auto rows_in) {
 #pragma unroll
                 for (int q = 0; q < PPT; q++) {
                     const float raw = frag_raw(fc, co, (float)(py0 + q) - xy.y);
                     const float a = fminf(kAlphaMax, raw);
-                    // the rect's rows need no test: outside the rect the exact alpha
-                    // is at least 2.5 % below 1/255 (the projection's margins), so
-                    // the alpha test rejects those pixels by itself; the counters
+                    // the rect needs no test: outside it the exact alpha is at
+                    // least 2.5 % below 1/255 (the projection's margins), so the
+                    // alpha test rejects those pixels by itself; the counters
                     // still count candidates inside the rect
                     bool inr = colok;
                     if constexpr (COUNT && !decltype(rows_in)::value)
                         inr = inr & (py0 + q >= rs.y0) & (py0 + q <= rs.y1);
-                    const bool ok = colok & (a >= kAlphaMin);
+                    const bool ok = a >= kAlphaMin;
                     // T (1 - alpha), negative once stopped, so a stopped pixel
                     // never blends again
                     const float aT = a * T[q];
@@ -357,7 +357,6 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
     __shared__ float2 s_xy[NT];
     __shared__ float4 s_co[NT];
     __shared__ float4 s_cz[NT];
-    __shared__ uint2 s_rc[NT];
     __shared__ uint32_t s_id[NT];
     __shared__ float s_g[NT][NG];
     __shared__ uint32_t s_hi;
@@ -451,26 +450,23 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
             s_xy[pos] = exy;
             s_co[pos] = eco;
             s_cz[pos] = rec.line[r].col;
-            s_rc[pos] = rc0;
         }
         __syncthreads();
         for (int k = 0; k < cnt; k++) {
             const uint32_t j = __builtin_amdgcn_readfirstlane(s_j[k]);
-            const uint2 rc = s_rc[k];
             const float2 xy = s_xy[k];
             const float4 co = s_co[k];
             const float4 cz = s_cz[k];
-            const RectS rs = rect_scalar(rc);
-            // a column outside the rect (or past every stop index of this
-            // thread) gets an infinite exponent, so its alpha is exactly zero
+            // past every stop index of this thread the column gets an infinite
+            // exponent, so its alpha is exactly zero
             FragCol fc = frag_col(fpx, xy, co);
-            if (!((j < mylast) & (px >= rs.x0) & (px <= rs.x1))) fc.a0 = __builtin_inff();
+            if (!(j < mylast)) fc.a0 = __builtin_inff();
             // pass 1: the alpha of every owned pixel, zeroed past the pixel's
             // stop index (where the forward did not blend it); min(0.99, raw)
-            // >= 1/255 exactly when raw >= 1/255.  Rows outside the rect need
-            // no test, as in the forward: there raw < 1/255 by the
-            // projection's margins.  Entries before every pixel's stop index
-            // need no per-pixel test at all.
+            // >= 1/255 exactly when raw >= 1/255.  The rect needs no test, as
+            // in the forward: outside it raw < 1/255 by the projection's
+            // margins.  Entries before every pixel's stop index need no
+            // per-pixel test at all.
             float raw[PPT];
             if (j < wmin) {
 #pragma unroll
