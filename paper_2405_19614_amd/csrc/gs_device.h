@@ -255,10 +255,14 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
     // dx^2 / (2 Sigma_xx), so alpha >= 1/255 needs |dx| <= sqrt(qmax Sigma_xx)
     // (and |dy| <= sqrt(qmax Sigma_yy)).  The widened qmax and the extra
     // hundredth of a pixel keep the box conservative under FP32 rounding: a
-    // pixel outside it has an exact alpha at least 2.5 % below 1/255.
+    // pixel outside it has an exact alpha at least 2.5 % below 1/255.  The
+    // cap by the radius is taken at the widened qmax too, so the bound holds
+    // where the cap binds; the compositing kernels rely on it (they test no
+    // rect per pixel and let the alpha test reject pixels outside it).
     const float qbox = qmax + 0.05f;
-    const float hx = fminf(o.radius, sqrtf(qbox * o.a) + 0.01f);
-    const float hy = fminf(o.radius, sqrtf(qbox * o.c) + 0.01f);
+    const float rbox = ceilf(sqrtf(qbox * lmax));
+    const float hx = fminf(rbox, sqrtf(qbox * o.a) + 0.01f);
+    const float hy = fminf(rbox, sqrtf(qbox * o.c) + 0.01f);
     const float fx0 = fmaxf(ceilf(o.u - hx), 0.f);
     const float fx1 = fminf(floorf(o.u + hx), (float)(vi.W - 1));
     const float fy0 = fmaxf(ceilf(o.v - hy), 0.f);
