@@ -452,6 +452,14 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
             s_cz[pos] = rec.line[r].col;
         }
         __syncthreads();
+        // the wavefront reduction of an entry's gradients runs one blended
+        // entry late, beside the next one's arithmetic (they are independent,
+        // so the cross-lane steps no longer wait on each other alone); the
+        // first reduction of a chunk adds zeros to entry 0
+        float gp[NG];
+#pragma unroll
+        for (int e = 0; e < NG; e++) gp[e] = 0.f;
+        int kp = 0;
         for (int k = 0; k < cnt; k++) {
             const uint32_t j = __builtin_amdgcn_readfirstlane(s_j[k]);
             const float2 xy = s_xy[k];
@@ -532,8 +540,15 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
             gv[7] = gc1;
             gv[8] = gc2;
             gv[9] = gcd;
-            const float s = row_reduce_scatter10(gv, lane);
-            if (slot >= 0) atomicAdd(&s_g[k][slot], s);
+            const float s = row_reduce_scatter10(gp, lane);
+            if (slot >= 0) atomicAdd(&s_g[kp][slot], s);
+#pragma unroll
+            for (int e = 0; e < NG; e++) gp[e] = gv[e];
+            kp = k;
+        }
+        {
+            const float s = row_reduce_scatter10(gp, lane);
+            if (slot >= 0) atomicAdd(&s_g[kp][slot], s);
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
