@@ -526,16 +526,16 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
             const float s_ds = s0;
             const float s_dsdy = dy0 * s0 + s1;
             const float s_dsdy2 = dy0 * (dy0 * s0 + 2.f * s1) + s2;
-            // constant factors are applied by the projection backward
-            const float hb = 0.5f * co.y;
+            // moments of dL/dsigma over the pixels; the conic factors, the
+            // same for every pixel, are applied once per entry at write-back
             const float dx = fc.dx;
             float gv[NG];
-            gv[0] = -(co.x * dx * s_ds + hb * s_dsdy);
-            gv[1] = -(co.z * s_dsdy + hb * dx * s_ds);
-            gv[2] = dx * dx * s_ds;
+            gv[0] = dx * s_ds;
+            gv[1] = s_dsdy;
+            gv[2] = dx * gv[0];
             gv[3] = dx * s_dsdy;
             gv[4] = s_dsdy2;
-            gv[5] = -s_ds;
+            gv[5] = s_ds;
             gv[6] = gc0;
             gv[7] = gc1;
             gv[8] = gc2;
@@ -553,6 +553,15 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             float* dst = g2 + (int64_t)s_id[threadIdx.x] * kG2Stride;
+            // the gradient with respect to (x, y) of the mean takes the conic
+            // factors of the pixel-independent part of d sigma / d mean;
+            // constant factors are applied by the projection backward
+            const float4 co = s_co[threadIdx.x];
+            const float hb = 0.5f * co.y;
+            const float m_dx = s_g[threadIdx.x][0], m_dy = s_g[threadIdx.x][1];
+            s_g[threadIdx.x][0] = -(co.x * m_dx + hb * m_dy);
+            s_g[threadIdx.x][1] = -(co.z * m_dy + hb * m_dx);
+            s_g[threadIdx.x][5] = -s_g[threadIdx.x][5];
 #pragma unroll
             for (int e = 0; e < NG; e++) {
                 const float s = s_g[threadIdx.x][e];
