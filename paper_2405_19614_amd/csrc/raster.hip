@@ -553,9 +553,11 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             float* dst = g2 + (int64_t)s_id[threadIdx.x] * kG2Stride;
-            // the gradient with respect to (x, y) of the mean takes the conic
-            // factors of the pixel-independent part of d sigma / d mean;
-            // constant factors are applied by the projection backward
+            // d sigma / d mean is linear in (dx, dy) with the entry's conic
+            // coefficients, which every pixel shares, so the mean gradient is
+            // those coefficients applied to the two summed moments; slot 5
+            // holds the plain sum of dL/dsigma, whose negative is the opacity
+            // term.  Constant factors are applied by the projection backward.
             const float4 co = s_co[threadIdx.x];
             const float hb = 0.5f * co.y;
             const float m_dx = s_g[threadIdx.x][0], m_dy = s_g[threadIdx.x][1];
