@@ -172,8 +172,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5, help="eager steps timed per stage with HIP events")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is a design "
-              "note, not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU sharding", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
