@@ -8,6 +8,9 @@ the pose perturbation from ``matrix_exp`` of the twist, and every gradient
 from autograd.  Front-to-back blending follows the colour / depth / border
 mask compositing equations of Sec. 3.3-3.4 with the clamp 0.99, the 1/255
 skip and the 1e-4 termination; the discrete decisions are held constant.
+The EWA Jacobian is taken at the camera-space point whose x/z and y/z are
+clamped at 1.3 times the half field of view (the projected mean itself is
+not clamped), so autograd sees no derivative through a clamped coordinate.
 """
 import math
 
@@ -15,6 +18,7 @@ import numpy as np
 import torch
 
 ZNEAR = 0.2
+JCLAMP = 1.3
 
 
 def _hat(w):
@@ -77,10 +81,15 @@ def real_sh(deg, d, signs=None):
     return Y
 
 
-def render_dense(means, log_scales, quats, opl, colors, sh_degree, cam, T_cw, xi=None, sh_signs=None):
+def render_dense(means, log_scales, quats, opl, colors, sh_degree, cam, T_cw, xi=None, sh_signs=None,
+                 stats=None):
     """Returns (C [3,H,W], D [H,W], A [H,W]) as differentiable torch tensors.
     All inputs are torch float64 tensors; ``xi`` (6,) perturbs the pose as
-    Exp(xi) T_cw."""
+    Exp(xi) T_cw.  ``stats`` (a dict, optional) receives how often the
+    discrete branches were taken: 'alpha_clamped' fragments blended with
+    o exp(-sigma) > 0.99, 'terminated' pixels that stopped before a candidate
+    with alpha >= 1/255, 'jclamped' Gaussians whose Jacobian point was
+    clamped, 'jclamped_blended' fragments of those."""
     W, H = cam.width, cam.height
     fx, fy, cx, cy = cam.fx, cam.fy, cam.cx, cam.cy
     T = T_cw if xi is None else twist_exp(xi) @ T_cw
@@ -93,7 +102,15 @@ def render_dense(means, log_scales, quats, opl, colors, sh_degree, cam, T_cw, xi
         return torch.stack([fx * pt[0] / pt[2] + cx, fy * pt[1] / pt[2] + cy])
 
     mu2 = torch.stack([proj(p[i]) for i in range(n)])
-    J = torch.func.vmap(torch.func.jacrev(proj))(p)   # [n,2,3]
+    # the Jacobian of the pinhole projection, taken where x/z and y/z are
+    # clamped to the widened field of view
+    limx = JCLAMP * W / (2.0 * fx)
+    limy = JCLAMP * H / (2.0 * fy)
+    xz = torch.clamp(p[:, 0] / p[:, 2], -limx, limx)
+    yz = torch.clamp(p[:, 1] / p[:, 2], -limy, limy)
+    pj = torch.stack([xz * p[:, 2], yz * p[:, 2], p[:, 2]], dim=1)
+    J = torch.func.vmap(torch.func.jacrev(proj))(pj)   # [n,2,3]
+    jcl = ((p[:, 0] / p[:, 2]).abs() > limx) | ((p[:, 1] / p[:, 2]).abs() > limy)
     Rs = torch.stack([quat_to_R(quats[i]) for i in range(n)])
     s2 = torch.exp(2 * log_scales)
     Sig = Rs @ torch.diag_embed(s2) @ Rs.transpose(1, 2)
@@ -132,6 +149,12 @@ def render_dense(means, log_scales, quats, opl, colors, sh_degree, cam, T_cw, xi
     C = w @ col[order]                       # [P,3]
     D = w @ z[order]
     A = 1 - Tincl[:, -1]
+    if stats is not None:
+        blended = (a > 0).detach()
+        stats["alpha_clamped"] = int((blended & (rawa.detach() > 0.99)).sum())
+        stats["terminated"] = int((keep & ~live).any(dim=1).sum())
+        stats["jclamped"] = int(jcl.sum())
+        stats["jclamped_blended"] = int((blended & jcl[order][None, :]).sum())
     return C.T.reshape(3, H, W), D.reshape(H, W), A.reshape(H, W)
 
 

@@ -559,3 +559,269 @@ def test_loss_and_upstream_closed_form(oracle):
     assert Ld[1] == pytest.approx(np.sum(np.abs(out["depth"][8:12] - td[8:12]) * m) / 4)
     np.testing.assert_allclose(dD[8:12], 0.1 / 2 / 4 * np.sign(out["depth"][8:12] - td[8:12]) * m)
     assert P == [c.width * c.height for c in cams]
+
+
+# --------------------------------------------------------------------------
+# the discrete branches of the forward model: the 0.99 alpha clamp, the
+# termination before T falls below 1e-4, and the Jacobian clamp at 1.3x the
+# half field of view (readings of the colour / depth compositing equations,
+# Sec. 3.4, and of its local-affine projection, Sec. 3.3-3.4)
+# --------------------------------------------------------------------------
+
+def _iso_alpha(cam, u, v, var, o):
+    """The paper's isotropic 2D kernel o exp(-|p - mu|^2 / (2 var)) on the
+    pixel grid, clamped at 0.99 and cut below 1/255."""
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    f = o * np.exp(-((xs - u) ** 2 + (ys - v) ** 2) / (2 * var))
+    f = np.minimum(f, 0.99)
+    f[f < 1 / 255] = 0
+    return f
+
+
+def test_alpha_clamp_closed_form(oracle):
+    """A wide, nearly opaque Gaussian on the axis: alpha = min(0.99, o e^-sigma)
+    exactly, with several pixels at the clamp (the centre pixel reads 0.99,
+    not o)."""
+    cam = _cam()
+    z, s, opl = 2.0, 0.3, 8.0
+    col = np.array([0.2, 0.5, 0.9])
+    g = _one(oracle, (0.0, 0.0, z), (math.log(s),) * 3, opl=opl, col=col)
+    out = oracle.render(g, cam, np.eye(4))
+    o = 1 / (1 + math.exp(-opl))
+    f = _iso_alpha(cam, cam.cx, cam.cy, (cam.fx * s / z) ** 2 + 0.3, o)
+    assert int((f == 0.99).sum()) >= 5
+    assert out["alpha"][int(cam.cy), int(cam.cx)] == 0.99
+    np.testing.assert_allclose(out["alpha"], f, atol=1e-14)
+    np.testing.assert_allclose(out["depth"], z * f, atol=1e-13)
+    for k in range(3):
+        np.testing.assert_allclose(out["color"][k], col[k] * f, atol=1e-14)
+
+
+def test_alpha_clamp_reverse_mode_is_flat(oracle):
+    """Where the clamp holds, alpha = 0.99 does not move with the opacity, the
+    mean or the covariance: d/dparams of (C, A) there is zero except
+    dC/dcolour = 0.99, and central differences of the oracle's own forward
+    agree (the clamp has a margin of ~1 % at the centre)."""
+    cam = _cam()
+    z, s, opl = 2.0, 0.3, 8.0
+    g = _one(oracle, (0.0, 0.0, z), (math.log(s),) * 3, opl=opl)
+    pix = np.array([[int(cam.cx), int(cam.cy)]], np.int32)
+    dC = np.array([[1.0], [0.0], [0.0]])
+    dA = np.array([1.0])
+    gr = oracle.backward(g, cam, np.eye(4), dC=dC, dA=dA, pixels=pix)
+    assert gr["colors"][0, 0] == pytest.approx(0.99, rel=1e-15)
+    for name in ["means", "log_scales", "quats", "opacity_logits"]:
+        assert np.all(gr[name] == 0), name
+    assert np.all(gr["pose"] == 0)
+
+    def loss(gg):
+        o = oracle.render(gg, cam, np.eye(4), pixels=pix)
+        return float(o["color"][0, 0] + o["alpha"][0])
+
+    for name in ["opacity_logits", "means", "log_scales"]:
+        arr = getattr(g, name).reshape(-1)
+        for i in range(arr.size):
+            old = arr[i]
+            arr[i] = old + 1e-6
+            lp = loss(g)
+            arr[i] = old - 1e-6
+            lm = loss(g)
+            arr[i] = old
+            assert abs(lp - lm) / 2e-6 < 1e-9, (name, i)
+
+
+def _stack(oracle, k, o, zs, cols, s=0.02):
+    """k isotropic Gaussians on the optical axis, one behind the other."""
+    opl = math.log(o / (1 - o))
+    return oracle.Gaussians(np.array([[0.0, 0.0, z] for z in zs]), np.full((k, 3), math.log(s)),
+                            np.tile([1.0, 0, 0, 0], (k, 1)), np.full(k, opl), np.asarray(cols, np.float64))
+
+
+@pytest.mark.parametrize("o,k,m", [(0.85, 8, 4), (0.55, 14, 11), (0.97, 6, 2)])
+def test_termination_closed_form(oracle, o, k, m):
+    """k Gaussians of opacity o stacked on the axis: at the centre pixel every
+    alpha is o, T after n blends is (1 - o)^n, and blending stops before the
+    first n with (1 - o)^n < 1e-4, so exactly m are blended.  C, D, A are the
+    m-term sums (colour and depth equations; border mask A = 1 - (1 - o)^m)."""
+    assert (1 - o) ** m >= 1e-4 * 1.2 and (1 - o) ** (m + 1) < 1e-4 / 1.2   # decisions with margin
+    cam = _cam()
+    rng = np.random.default_rng(k)
+    zs = 2.0 + 0.1 * np.arange(k)
+    cols = rng.uniform(0, 1, (k, 3))
+    g = _stack(oracle, k, o, zs, cols)
+    pix = np.array([[int(cam.cx), int(cam.cy)]], np.int32)
+    out = oracle.render(g, cam, np.eye(4), pixels=pix)
+    w = o * (1 - o) ** np.arange(m)
+    np.testing.assert_allclose(out["color"][:, 0], w @ cols[:m], rtol=1e-13)
+    assert out["depth"][0] == pytest.approx(float(w @ zs[:m]), rel=1e-13)
+    assert out["alpha"][0] == pytest.approx(1 - (1 - o) ** m, rel=1e-14)
+    assert out["tfinal"][0] == pytest.approx((1 - o) ** m, rel=1e-12)
+    assert int(out["nblend"][0]) == m
+    # the whole image: A never exceeds 1 - 1e-4
+    full = oracle.render(g, cam, np.eye(4))
+    assert full["alpha"].max() <= 1 - 1e-4
+
+
+def test_termination_reverse_mode(oracle):
+    """Gaussians behind the stop get no gradient at that pixel, the blended
+    ones the closed form dA/dlogit_i = o (1 - o) T_final / (1 - o) with
+    T_final = (1 - o)^m (product rule on 1 - prod(1 - alpha_j))."""
+    cam = _cam()
+    o, k, m = 0.85, 8, 4
+    zs = 2.0 + 0.1 * np.arange(k)
+    g = _stack(oracle, k, o, zs, np.full((k, 3), 0.5))
+    pix = np.array([[int(cam.cx), int(cam.cy)]], np.int32)
+    gr = oracle.backward(g, cam, np.eye(4), dA=np.array([1.0]), pixels=pix)
+    tf = (1 - o) ** m
+    np.testing.assert_allclose(gr["opacity_logits"][:m], o * (1 - o) * tf / (1 - o), rtol=1e-12)
+    assert np.all(gr["opacity_logits"][m:] == 0)
+    assert np.all(gr["means"][m:] == 0) and np.all(gr["log_scales"][m:] == 0)
+
+
+def _jclamp_scene(oracle, cam, x_over_z, y_over_z, z, s, opl=2.2):
+    return _one(oracle, (x_over_z * z, y_over_z * z, z), (math.log(s),) * 3, opl=opl)
+
+
+@pytest.mark.parametrize("xz,yz", [(0.9, 0.0), (-0.95, 0.1), (0.2, 0.7), (0.78, -0.6)])
+def test_jacobian_clamp_closed_form(oracle, xz, yz):
+    """An isotropic Gaussian outside the widened field of view (|x/z| > 1.3 W /
+    (2 fx) or |y/z| > 1.3 H / (2 fy)) whose footprint still reaches the image:
+    its 2D covariance is s^2 J_c J_c^T + 0.3 I with J_c the pinhole Jacobian at
+    the clamped point (t_x, t_y, z), t = clamp(x/z) z, while the mean projects
+    unclamped.  The render equals the kernel of that covariance."""
+    cam = _cam()
+    z, s, opl = 2.0, 0.25, 2.2
+    limx, limy = 1.3 * cam.width / (2 * cam.fx), 1.3 * cam.height / (2 * cam.fy)
+    assert abs(xz) > limx or abs(yz) > limy
+    g = _jclamp_scene(oracle, cam, xz, yz, z, s, opl)
+    out = oracle.render(g, cam, np.eye(4))
+    tx, ty = np.clip(xz, -limx, limx) * z, np.clip(yz, -limy, limy) * z
+    f = cam.fx
+    Jc = np.array([[f / z, 0, -f * tx / z ** 2], [0, cam.fy / z, -cam.fy * ty / z ** 2]])
+    S = s * s * Jc @ Jc.T + 0.3 * np.eye(2)
+    Qm = np.linalg.inv(S)
+    u, v = f * xz + cam.cx, cam.fy * yz + cam.cy
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    dx, dy = xs - u, ys - v
+    sig = 0.5 * (Qm[0, 0] * dx * dx + 2 * Qm[0, 1] * dx * dy + Qm[1, 1] * dy * dy)
+    a = np.minimum(1 / (1 + math.exp(-opl)) * np.exp(-sig), 0.99)
+    a[a < 1 / 255] = 0
+    assert (a > 0).sum() > 20          # the footprint reaches into the image
+    np.testing.assert_allclose(out["alpha"], a, atol=1e-13)
+
+
+def _deep_scene(seed, n=42, W=32, H=24, sh_degree=-1):
+    """A tiny scene that takes every discrete branch: a third of the Gaussians
+    crowd the image centre at high opacity (alpha clamp, termination), a third
+    sit outside the widened field of view with footprints reaching the image
+    (Jacobian clamp), the rest as _tiny_scene."""
+    rng = np.random.default_rng(seed)
+    fx = 30.0
+    limx, limy = 1.3 * W / (2 * fx), 1.3 * H / (2 * 31.0)
+    k = n // 3
+    z1 = rng.uniform(1.5, 3.0, k)
+    crowd = np.stack([rng.normal(0, 0.05, k) * z1, rng.normal(0, 0.05, k) * z1, z1], 1)
+    z2 = rng.uniform(1.5, 3.0, k)
+    sx = rng.choice([-1, 1], k)
+    sy = rng.choice([-1, 1], k)
+    tx = np.where(rng.uniform(0, 1, k) < 0.6, sx * limx * rng.uniform(1.08, 1.4, k), rng.uniform(-0.3, 0.3, k))
+    ty = np.where(np.abs(tx) > limx, rng.uniform(-0.3, 0.3, k), sy * limy * rng.uniform(1.08, 1.4, k))
+    outer = np.stack([tx * z2, ty * z2, z2], 1)
+    m = n - 2 * k
+    z3 = rng.uniform(1.5, 4.0, m)
+    rest = np.stack([rng.uniform(-0.6, 0.6, m), rng.uniform(-0.45, 0.45, m), z3], 1)
+    # the first three of the crowd are wide and in front: their alpha stays
+    # at the 0.99 clamp over a few pixels each
+    zf = rng.uniform(1.3, 1.45, 3)
+    crowd[:3] = np.stack([np.array([-0.25, 0.0, 0.25]) * zf, rng.uniform(-0.15, 0.15, 3) * zf, zf], 1)
+    means = np.concatenate([crowd, outer, rest])
+    ls = np.concatenate([rng.normal(-1.3, 0.2, (k, 3)), rng.normal(-1.6, 0.2, (k, 3)), rng.normal(-2.6, 0.4, (m, 3))])
+    ls[:3] = rng.normal(-0.6, 0.05, (3, 3))
+    q = rng.standard_normal((n, 4))
+    opl = np.concatenate([rng.normal(7.0, 1.5, k), rng.normal(1.5, 0.5, k), rng.normal(0.5, 1.0, m)])
+    if sh_degree < 0:
+        col = rng.uniform(0, 1, (n, 3))
+    else:
+        K = (sh_degree + 1) ** 2
+        col = rng.normal(0, 0.2, (n, K, 3))
+        col[:, 0] = rng.uniform(0, 1, (n, 3))
+    cam = scenes.Camera(W, H, fx, 31.0, W / 2 - 0.3, H / 2 + 0.2)
+    return means, ls, q, opl, col, cam, np.eye(4)
+
+
+@pytest.mark.parametrize("seed,sh", [(20, -1), (21, 2)])
+def test_dense_brute_force_with_every_branch(oracle, seed, sh):
+    """The dense torch renderer (clamped Jacobian, alpha clamp and termination
+    as masks, gradients by autograd) equals the oracle's forward and reverse
+    mode on a scene where each branch is taken many times."""
+    means, ls, q, opl, col, cam, T = _deep_scene(seed, sh_degree=sh)
+    g = oracle.Gaussians(means, ls, q, opl, col, sh)
+    out = oracle.render(g, cam, T, bands=(0, 0, 0, -1.0))
+    signs = _sh_signs(oracle, sh) if sh >= 0 else None
+    tp = DT.torch_params(g)
+    xi = torch.zeros(6, dtype=torch.float64, requires_grad=True)
+    st = {}
+    C, D, A = DT.render_dense(*tp, sh, cam, torch.tensor(T), xi=xi, sh_signs=signs, stats=st)
+    print(st)
+    assert st["alpha_clamped"] >= 5 and st["terminated"] >= 10 and st["jclamped_blended"] >= 20, st
+    np.testing.assert_allclose(C.detach().numpy(), out["color"], atol=1e-11)
+    np.testing.assert_allclose(D.detach().numpy(), out["depth"], atol=1e-11)
+    np.testing.assert_allclose(A.detach().numpy(), out["alpha"], atol=1e-11)
+    rng = np.random.default_rng(300 + seed)
+    dC = rng.standard_normal(C.shape)
+    dD = rng.standard_normal(D.shape)
+    dA = rng.standard_normal(A.shape)
+    L = (C * torch.tensor(dC)).sum() + (D * torch.tensor(dD)).sum() + (A * torch.tensor(dA)).sum()
+    L.backward()
+    gr = oracle.backward(g, cam, T, dC, dD, dA)
+    for name, t in zip(["means", "log_scales", "quats", "opacity_logits", "colors"], tp):
+        ref = t.grad.numpy()
+        err = np.linalg.norm(gr[name] - ref) / max(np.linalg.norm(ref), 1e-30)
+        assert err < 1e-9, (name, err)
+    err = np.linalg.norm(gr["pose"] - xi.grad.numpy()) / np.linalg.norm(xi.grad.numpy())
+    assert err < 1e-9, ("pose", err)
+
+
+@pytest.mark.parametrize("seed,sh", [(22, -1), (23, 1)])
+def test_reverse_mode_vs_central_fd_every_branch(oracle, seed, sh):
+    """Central differences of the oracle's own loss on the branch-heavy scene,
+    cotangents zeroed where a decision sits within the FD step of a threshold
+    (the clamped Jacobian has a margin of >= 8 % by construction)."""
+    means, ls, q, opl, col, cam, T = _deep_scene(seed, n=30, W=24, H=20, sh_degree=sh)
+    g = oracle.Gaussians(means, ls, q, opl, col, sh)
+    wide = oracle.render(g, cam, T, bands=(5e-3, 5e-3, 5e-3))
+    rng = np.random.default_rng(seed + 50)
+    keep = (wide["ambiguous"] == 0).astype(np.float64)
+    dC = rng.standard_normal((3, cam.height, cam.width)) * keep
+    dD = rng.standard_normal((cam.height, cam.width)) * keep
+    dA = rng.standard_normal((cam.height, cam.width)) * keep
+    gr = oracle.backward(g, cam, T, dC, dD, dA)
+    n = means.shape[0]
+    k = n // 3
+    # every parameter of the clamped-Jacobian Gaussians, a sample of the rest
+    checks = []
+    for name, width in [("means", 3), ("log_scales", 3), ("quats", 4), ("opacity_logits", 1)]:
+        for i in range(k, 2 * k):
+            for j in range(width):
+                checks.append((name, i * width + j))
+        for i in rng.choice(n, 4, replace=False):
+            checks.append((name, int(i) * width))
+    for name, idx in checks:
+        flat = getattr(g, name).reshape(-1)
+        h = 1e-6 * max(1.0, abs(flat[idx]))
+        old = flat[idx]
+        flat[idx] = old + h
+        lp = _loss(oracle, g, cam, T, dC, dD, dA)
+        flat[idx] = old - h
+        lm = _loss(oracle, g, cam, T, dC, dD, dA)
+        flat[idx] = old
+        fd = (lp - lm) / (2 * h)
+        an = gr[name].reshape(-1)[idx]
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)) + 1e-7, (name, idx, fd, an)
+    for j in range(6):
+        xi = np.zeros(6)
+        xi[j] = 1e-6
+        lp = _loss(oracle, g, cam, oracle.se3_exp(xi) @ T, dC, dD, dA)
+        lm = _loss(oracle, g, cam, oracle.se3_exp(-xi) @ T, dC, dD, dA)
+        fd = (lp - lm) / 2e-6
+        assert abs(fd - gr["pose"][j]) <= 1e-6 * max(1.0, abs(fd)) + 1e-7, (j, fd, gr["pose"][j])
