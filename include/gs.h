@@ -185,6 +185,22 @@ int gs_reproj_residual(gs_ctx* ctx, const gs_camera* cams, const float* poses, i
                        const float* uv, const int32_t* view_idx, int64_t M, float huber_delta, float weight,
                        float* residual, float* loss, float* dL_dpose, float* dL_dpoints, void* stream);
 
+/* Allocation-free variant of gs_reproj_residual, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and error
+ * behaviour as gs_reproj_residual; the per-view accumulators live in a static
+ * device array of the library (GS_MAX_VIEWS x 8 doubles = 4 KiB per GPU,
+ * located once per device by gs_create and held until the process ends)
+ * instead of the context's buffer, and the call makes no allocation.
+ * V above GS_MAX_VIEWS is rejected (GS_EINVAL).  Every call on one GPU shares
+ * that GPU's array, which keeps the last call's sums (each call clears what it
+ * uses first): calls that overlap on one GPU (several streams or contexts)
+ * race and must be serialised by the caller. */
+int gs_reproj_residual_noalloc(gs_ctx* ctx, const gs_camera* cams, const float* poses, int32_t V,
+                               const float* points, const float* uv, const int32_t* view_idx, int64_t M,
+                               float huber_delta, float weight, float* residual, float* loss, float* dL_dpose,
+                               float* dL_dpoints, void* stream);
+
 /* Options of one mapping / pose-refinement step.
  * Loss (Sec. 3.3 joint-loss equation; Sec. 3.4 mapping-loss equation):
  *   L = (1/V) sum_v ( w_color Lc_v + w_depth Ld_v + w_reproj Lr_v + w_ssim Ls_v ),

@@ -65,7 +65,7 @@ class gs_adam(ctypes.Structure):
 
 
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_state_bytes", "gs_render_forward",
-           "gs_render_backward", "gs_reproj_residual", "gs_step_workspace_bytes", "gs_mapping_step",
+           "gs_render_backward", "gs_reproj_residual", "gs_reproj_residual_noalloc", "gs_step_workspace_bytes", "gs_mapping_step",
            "gs_step_status", "gs_bin_records", "gs_autotune", "gs_set_tile", "gs_num_stages", "gs_stage_name",
            "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bwd_shape", "gs_set_bin",
            "gs_ssim_workspace_bytes", "gs_ssim", "gs_prune_workspace_bytes", "gs_prune",
@@ -101,6 +101,7 @@ def load() -> ctypes.CDLL:
                                      ctypes.POINTER(gs_gaussian_grads), c_void_p, c_void_p]
     L.gs_reproj_residual.argtypes = [c_void_p, PC, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int64,
                                      c_float, c_float, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.gs_reproj_residual_noalloc.argtypes = L.gs_reproj_residual.argtypes
     L.gs_mapping_step.argtypes = [c_void_p, ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_gaussian_grads),
                                   ctypes.POINTER(gs_adam), PC, c_void_p, c_int32, ctypes.POINTER(gs_targets),
                                   ctypes.POINTER(gs_matches), ctypes.POINTER(gs_step_opts), c_void_p, c_size_t,

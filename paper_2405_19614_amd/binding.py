@@ -274,9 +274,11 @@ class Context:
         return grads, dpose
 
     def reproj(self, cams, poses, points, uv, view_idx, delta: float, weight: float = 1.0,
-               dpose: Optional[torch.Tensor] = None, point_grads: bool = False):
+               dpose: Optional[torch.Tensor] = None, point_grads: bool = False, noalloc: bool = False):
         """Returns (residual [M,2], loss [V], dpose [V,6]) (dpose accumulated),
-        plus dL/dpoints [M,3] when ``point_grads``."""
+        plus dL/dpoints [M,3] when ``point_grads``.  ``noalloc`` calls
+        gs_reproj_residual_noalloc (the library's static scratch instead of
+        the context's buffer; same results)."""
         cams = as_cameras(cams)
         V = len(cams)
         dev = self.torch_device
@@ -294,9 +296,9 @@ class Context:
         if dpose is None:
             dpose = torch.zeros(V, 6, dtype=torch.float32, device=dev)
         dpts = torch.empty(max(M, 1), 3, dtype=torch.float32, device=dev) if point_grads else None
-        rc = self.lib.gs_reproj_residual(self.h, cam_array(cams), _p(poses.contiguous()), V, _p(points), _p(uv),
-                                         _p(view_idx), M, float(delta), float(weight), _p(residual), _p(loss),
-                                         _p(dpose), _p(dpts), _stream())
+        fn = self.lib.gs_reproj_residual_noalloc if noalloc else self.lib.gs_reproj_residual
+        rc = fn(self.h, cam_array(cams), _p(poses.contiguous()), V, _p(points), _p(uv), _p(view_idx), M,
+                float(delta), float(weight), _p(residual), _p(loss), _p(dpose), _p(dpts), _stream())
         self._check(rc)
         if point_grads:
             return residual[:M], loss, dpose, dpts[:M]

@@ -11,9 +11,17 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
+
+// Device scratch of gs_reproj_residual_noalloc: the per-view accumulators of
+// the re-projection kernels (Huber sum, match count, pose gradient: 8 doubles
+// per view) for up to GS_MAX_VIEWS views, 4 KiB per GPU, held until the
+// process ends.  Host code never passes this name to a kernel: its address
+// on each device comes from hipGetSymbolAddress (scratch_on below).
+static __device__ __align__(256) double scratch[GS_MAX_VIEWS * 8];
 
 struct gs_ctx {
     int device = 0;
@@ -38,6 +46,30 @@ struct gs_ctx {
 namespace {
 
 thread_local std::string g_create_err;
+
+// Per-device address of `scratch`, looked up once per device (with that
+// device current) by gs_create; read by gs_reproj_residual_noalloc.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+double* scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return static_cast<double*>(g_scratch_ptr[device]);
+}
 
 int fail(gs_ctx* c, int code, const char* fmt, ...) {
     char buf[512];
@@ -400,6 +432,13 @@ int gs_create(gs_ctx** out, int device) {
         delete c;
         return fail(nullptr, GS_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
     }
+    // the device address of the static scratch (gs_reproj_residual_noalloc),
+    // looked up here, with the context's device current, once per device
+    e = scratch_setup(device);
+    if (e != hipSuccess) {
+        gs_destroy(c);
+        return fail(nullptr, GS_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
     // default priority (no stream priorities anywhere)
     e = hipStreamCreateWithFlags(&c->fork, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
@@ -597,6 +636,32 @@ int gs_reproj_residual(gs_ctx* c, const gs_camera* cams, const float* poses, int
     GS_HIP(c, gs::launch_reproj(vt, poses, points, uv, view_idx, M, delta, residual, c->rp_acc, s, dL_dpoints));
     GS_HIP(c, gs::launch_reproj_finalize(vt, c->rp_acc, weight, loss, dL_dpose, s));
     if (dL_dpoints) GS_HIP(c, gs::launch_reproj_points_scale(vt, view_idx, M, c->rp_acc, weight, dL_dpoints, s));
+    return GS_OK;
+}
+
+int gs_reproj_residual_noalloc(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, const float* points,
+                               const float* uv, const int32_t* view_idx, int64_t M, float delta, float weight,
+                               float* residual, float* loss, float* dL_dpose, float* dL_dpoints, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (V > GS_MAX_VIEWS)
+        return fail(c, GS_EINVAL, "V=%d views exceed the static scratch, which holds %d", V, GS_MAX_VIEWS);
+    if (M < 0) return fail(c, GS_EINVAL, "M is negative");
+    if (M >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "M too large");
+    if (!(delta > 0.f)) return fail(c, GS_EINVAL, "huber_delta must be positive");
+    if (!poses || !loss || !dL_dpose) return fail(c, GS_EINVAL, "a device pointer is NULL");
+    if (M > 0 && (!points || !uv || !view_idx || !residual)) return fail(c, GS_EINVAL, "a match pointer is NULL");
+    gs::ViewTable vt;
+    int r = build_vt(c, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt);
+    if (r) return r;
+    double* acc = scratch_on(c->device);
+    if (!acc) return fail(c, GS_EDEVICE, "static scratch of device %d was not set up", c->device);
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the array keeps the previous call's sums: cleared by a kernel first
+    GS_HIP(c, gs::launch_zero_f64(acc, 8 * V, s));
+    GS_HIP(c, gs::launch_reproj(vt, poses, points, uv, view_idx, M, delta, residual, acc, s, dL_dpoints));
+    GS_HIP(c, gs::launch_reproj_finalize(vt, acc, weight, loss, dL_dpose, s));
+    if (dL_dpoints) GS_HIP(c, gs::launch_reproj_points_scale(vt, view_idx, M, acc, weight, dL_dpoints, s));
     return GS_OK;
 }
 
