@@ -1,16 +1,21 @@
-"""Benchmark of the batched Gaussian-splatting mapping step on one MI355X.
+"""Benchmark of the batched Gaussian-splatting hot path on one MI355X.
 
-Workload: the batched keyframe window -- 1,000,000 Gaussians in an 8x8x3 m
-room shell, 8 views at 1200x680 (f = 600) on a smooth trajectory, L1 colour
-+ 0.1 L1 depth against renders from the unperturbed poses.  One step = the
-whole hot path over all 8 views: projection, binning, compositing with the
-fused loss, backward, pose reduction (and, for the mapping-iteration rate, the
-Adam updates).  Every step is one hipGraph replay.
+Workload (default): the long-session window -- 3,000,000 Gaussians with
+degree-3 SH colour in an 8x8x3 m room shell, 16 views at 1200x680 (f = 600)
+from a 515-pose trajectory, estimated poses perturbed by 0.02 rad / 0.05 m,
+L1 colour + 0.1 L1 depth against renders from the true poses.  One step =
+the whole hot path over all 16 views: projection, binning, compositing with
+the fused loss, backward, pose reduction (and, for the mapping-iteration
+rate, the Adam updates).  Every step is one hipGraph replay; the launch shape
+(tiles, pixels per thread, bins) is chosen by the library's autotuner in the
+run.
 
-Prints one JSON line: fwd+bwd megapixels/s (the value), mapping iterations/s,
-the per-view rate (the same kernels launched with V = 1 per view), the
-roofline of the dominant kernel and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line: fwd+bwd megapixels/s of the batched step (the value),
+mapping iterations/s, the per-view rate (the same kernels launched with V = 1
+per view) and its gradient agreement with the batched step, a 500-step
+sliding-window session (memory stability), peak device memory, the roofline
+of the dominant kernel, the FP64 CPU oracle timed on a bounded sample of the
+same workload, and the 1M-Gaussian 8-view RGB window as an extra key.
 """
 from __future__ import annotations
 
@@ -24,11 +29,6 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
-
-# launch shape timed by default: forward tiles 16x16 with 4 pixels per thread,
-# bins 512x256, backward tiles 32x64 with 8 pixels per thread (the fastest in
-# a sweep of shapes and bins on this workload; --tile auto tunes instead)
-DEFAULT_LAUNCH = "16x16,4,512x256,32x64,8"
 
 # published MI355X peaks
 PEAK_HBM_GBS = 8000.0
@@ -45,33 +45,44 @@ FWD_PER_VISIT, FWD_PER_BLEND, FWD_PER_PIXEL = 13, 11, 16
 # opacity / sigma gradients 3, conic gradients 5, mean gradients 8 = +48
 BWD_PER_VISIT, BWD_PER_BLEND = 13, 48
 
+WORKLOADS = {
+    "c5": "long-session window: 3000000 Gaussians with SH degree 3 colour, room shell, 16 views 1200x680, f=600, "
+          "L1 colour + 0.1 L1 depth",
+    "c3": "batched keyframe window: 1000000 Gaussians with RGB colour, room shell, 8 views 1200x680, f=600, "
+          "L1 colour + 0.1 L1 depth",
+}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_inputs(args):
+def make_scene(name):
+    from synth import scenes
+    return scenes.c5() if name == "c5" else scenes.c3()
+
+
+def dev_inputs(ctx, s):
     import numpy as np
     import torch
     import paper_2405_19614_amd as gs
-    from synth import scenes
-    s = scenes.c3(n=args.n, views=args.views, width=args.width, height=args.height)
-    ctx = gs.Context(0)
     g = gs.Gaussians.from_scene(s, "cuda:0")
     poses = torch.tensor(np.asarray(s.poses, np.float32), device="cuda:0").reshape(s.V, 16).contiguous()
     poses_true = torch.tensor(np.asarray(s.poses_true, np.float32), device="cuda:0").reshape(s.V, 16).contiguous()
-    # targets: renders from the unperturbed poses (input preparation, untimed)
+    # targets: renders from the true poses (input preparation, untimed)
     tc, td, _, _, _ = ctx.forward(g, s.cams, poses_true)
-    return s, ctx, g, poses, tc, td
+    return g, poses, tc, td
 
 
 def timed_steps(step_fns, K, W):
+    """W untimed rounds, then K timed rounds of every function in step_fns,
+    bracketed by synchronisations.  Returns (ms per round from the wall
+    clock, median ms per round from events on the current stream)."""
     import torch
     for _ in range(W):
         for f in step_fns:
             f()
     torch.cuda.synchronize()
-    # per-step event times (median) alongside the bracketed wall time
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -86,19 +97,50 @@ def timed_steps(step_fns, K, W):
     return wall * 1000.0 / K, statistics.median(per)
 
 
-def cpu_baseline(s, views, min_seconds=10.0, max_reps=4):
-    """FP64 oracle forward + L1 loss + backward on ``views`` of the workload,
-    repeated until at least ``min_seconds`` of timed work (at most
-    ``max_reps`` passes)."""
+def check(step, what):
+    """Raise if any step of ``step`` since the last check was flagged (such
+    steps made no update and their timing would not count)."""
+    try:
+        return step.check()
+    except Exception as e:
+        raise RuntimeError(f"{what}: {e}") from e
+
+
+def rel(a, r):
+    import torch
+    a = a.double().reshape(-1)
+    r = r.double().reshape(-1)
+    n = torch.linalg.norm(r)
+    return float(torch.linalg.norm(a - r) / n) if n > 0 else float(torch.linalg.norm(a))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(s, views, min_seconds, one_thread_pixels):
+    """FP64 oracle forward + L1 loss + backward on ``views`` of the workload
+    (all host threads), repeated until ``min_seconds`` (at most 3 passes);
+    then the same on ``one_thread_pixels`` sampled pixels of view 0 with one
+    thread."""
     import numpy as np
     from oracle import oracle as O
+    from synth import scenes
     og = O.Gaussians.from_scene(s)
     cams = [s.cams[v] for v in views]
     ptrue = [s.poses_true[v] for v in views]
     pest = [s.poses[v] for v in views]
     tgt = O.render_views(og, cams, ptrue)       # targets (untimed)
+    threads = O.num_threads()
     reps, dt = 0, 0.0
-    while reps < max_reps and (reps == 0 or dt < min_seconds):
+    while reps < 3 and (reps == 0 or dt < min_seconds):
         t0 = time.perf_counter()
         out = O.render_views(og, cams, pest)
         _, _, dC, dD = O.loss_and_upstream(cams, out, tgt["color"], tgt["depth"], 1.0, 0.1)
@@ -106,7 +148,23 @@ def cpu_baseline(s, views, min_seconds=10.0, max_reps=4):
         dt += time.perf_counter() - t0
         reps += 1
     px = sum(c.npix for c in cams)
-    return px, reps, dt, O.num_threads()
+    # one thread, sampled pixels of view 0
+    cam = s.cams[0]
+    pix = scenes.sample_pixels(cam, one_thread_pixels, 5)
+    t1 = O.render(og, cam, s.poses_true[0], pixels=pix)
+    O.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o1 = O.render(og, cam, s.poses[0], pixels=pix)
+        k = pix.shape[0]
+        dC1 = np.sign(o1["color"] - t1["color"]) / (3.0 * k)
+        dD1 = 0.1 * np.sign(o1["depth"] - t1["depth"]) / k
+        O.backward(og, cam, s.poses[0], dC=dC1, dD=dD1, pixels=pix)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(threads)
+    return {"px": px, "reps": reps, "seconds": dt, "threads": threads, "one_thread_px": int(pix.shape[0]),
+            "one_thread_seconds": dt1}
 
 
 def source_digest(paths):
@@ -121,14 +179,15 @@ def source_digest(paths):
 # sources that determine the compositing kernels' code
 KERNEL_SOURCES = ["paper_2405_19614_amd/csrc/raster.hip", "paper_2405_19614_amd/csrc/gs_device.h",
                   "paper_2405_19614_amd/csrc/gs_internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "composite_hbm_traffic_c3.md")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed PMC summary, or
-    None when the summary is missing or the kernel sources changed since."""
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of ``kernel`` at ``workload`` from the committed
+    PMC summary, or None when it is missing or the kernel sources changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"composite_hbm_traffic_{workload}.md")
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     import re
@@ -151,24 +210,246 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
+def set_shape(ctx, spec, g, cams, poses):
+    """'auto' runs the autotuner on the workload; else
+    TWxTH,PPT,BWxBH[,BTWxBTH,BPPT].  Returns (tile, bin, bwd tile, seconds)."""
+    t0 = time.perf_counter()
+    if spec == "auto":
+        tile, binsz = ctx.autotune(g, cams, poses, iters=2)
+    else:
+        vals = [int(x) for x in spec.lower().replace("x", ",").split(",")]
+        tw, th, ppt, bw, bh = vals[:5]
+        ctx.set_tile(tw, th, ppt)
+        ctx.set_bin(bw, bh)
+        if len(vals) == 8:
+            ctx.set_bwd_shape(vals[5], vals[6], vals[7])
+        tile, binsz = (tw, th), (bw, bh)
+    btile = ctx.bwd_tile_choice if ctx.bwd_tile_choice != (0, 0) else tile
+    return tile, binsz, btile, time.perf_counter() - t0
+
+
+def per_view_steps(gs, ctx, s, g, poses, tc, td, base):
+    off = s.pix_offsets()
+    out = []
+    for v in range(s.V):
+        out.append(gs.MappingStep(ctx, g, [s.cams[v]], poses[v:v + 1].clone(),
+                                  tc[3 * off[v]:3 * off[v + 1]].contiguous(), td[off[v]:off[v + 1]].contiguous(),
+                                  gs.StepOptions(**base)))
+    return out
+
+
+def batched_vs_per_view_grads(st, pv, V):
+    """Relative L2 error of the summed per-view gradients (each view's own
+    loss, so V times its share of the batched mean) against the batched ones,
+    per tensor, and of each view's pose gradient."""
+    import torch
+    errs = {}
+    for nm in ["means", "log_scales", "quats", "opacity_logits", "colors"]:
+        acc = torch.zeros_like(getattr(st.grads, nm), dtype=torch.float64)
+        for p in pv:
+            acc += getattr(p.grads, nm).double()
+        errs[nm] = rel(acc / V, getattr(st.grads, nm))
+    errs["pose"] = max(rel(pv[v].dpose[0] / V, st.dpose[v]) for v in range(V))
+    return errs
+
+
+def session(gs, ctx, s, g, base, nsteps, tile, binsz, btile):
+    """``nsteps`` mapping steps (Adam on the Gaussians) over a window of V
+    views sliding one pose per step along the trajectory; each step's poses
+    and targets are copied into the step's buffers on the device first."""
+    import numpy as np
+    import torch
+    from synth import scenes
+    traj = np.asarray(s.extra["trajectory"], np.float64)
+    V = s.V
+    L = min(len(traj), nsteps + V - 1)
+    rng = np.random.Generator(np.random.PCG64(55))
+    est = np.stack([scenes.perturb_pose(T, rng) for T in traj[:L]]).astype(np.float32)
+    cams = [s.cams[0]] * V
+    P = s.cams[0].npix
+    gm = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
+    tcol = torch.empty(L * 3 * P, dtype=torch.float32, device="cuda:0")
+    tdep = torch.empty(L * P, dtype=torch.float32, device="cuda:0")
+    tru = torch.tensor(traj[:L].astype(np.float32), device="cuda:0").reshape(L, 16)
+    cap = 0
+    for a in range(0, L, V):
+        b = min(L, a + V)
+        c, d, _, _, plan = ctx.forward(gm, cams[:b - a], tru[a:b].contiguous())
+        tcol[3 * P * a:3 * P * b] = c
+        tdep[P * a:P * b] = d
+    est_d = torch.tensor(est, device="cuda:0").reshape(L, 16)
+    for w in sorted(set([0, (L - V) // 2, L - V])):
+        _, _, _, _, plan = ctx.forward(gm, cams, est_d[w:w + V].contiguous())
+        cap = max(cap, plan.n_pairs)
+    cap = int(cap * 1.3) + 4096
+    st = gs.MappingStep(ctx, gm, cams, est_d[0:V].clone(), tcol[:3 * P * V].clone(), tdep[:P * V].clone(),
+                        gs.StepOptions(update_gaussians=True, **base), capacity=cap)
+    st()
+    torch.cuda.synchronize()
+    check(st, "session")
+    mem0 = torch.cuda.max_memory_allocated()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for k in range(nsteps):
+        w = min(k, L - V)
+        st.poses.copy_(est_d[w:w + V])
+        st.tc.copy_(tcol[3 * P * w:3 * P * (w + V)])
+        st.td.copy_(tdep[P * w:P * (w + V)])
+        st()
+        if k % 100 == 0 or k == nsteps - 1:
+            losses.append(st.loss[0].clone())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stat = st.status()
+    mem1 = torch.cuda.max_memory_allocated()
+    lv = [float(x.item()) for x in losses]
+    return {"steps": nsteps, "views": V, "trajectory_poses": L, "ms_per_step": round(dt * 1000.0 / nsteps, 4),
+            "flags": stat["flags"], "pairs_last": stat["n_pairs"], "capacity": cap,
+            "peak_allocated_before_GB": round(mem0 / 1e9, 3), "peak_allocated_after_GB": round(mem1 / 1e9, 3),
+            "memory_growth_bytes": int(mem1 - mem0), "loss_every_100": [round(x, 6) for x in lv],
+            "adam_updates": [int(x) for x in st.adam_step.tolist()]}
+
+
+def run_workload(gs, ctx, name, args, per_view=True, profile=True):
+    import torch
+    log(f"[bench] {name}: building inputs")
+    s = make_scene(name)
+    g, poses, tc, td = dev_inputs(ctx, s)
+    npix = s.npix
+    tile, binsz, btile, t_tune = set_shape(ctx, args.tile, g, s.cams, poses)
+    ppt_f, ppt_b = ctx.ppt_choice(tile), ctx.ppt_choice(btile, True)
+    log(f"[bench] {name}: tile {tile} x{ppt_f} bin {binsz} backward tile {btile} x{ppt_b} "
+        f"(shape chosen in {t_tune:.1f} s)")
+    base = dict(w_color=1.0, w_depth=0.1, w_reproj=0.0, tile=tile, bin=binsz, use_graph=True)
+    res = {"workload": WORKLOADS[name], "gaussians": s.n, "sh_degree": s.sh_degree, "views": s.V,
+           "width": s.cams[0].width, "height": s.cams[0].height, "pixels_per_step": npix,
+           "tile": f"{tile[0]}x{tile[1]}", "bin": f"{binsz[0]}x{binsz[1]}", "bwd_tile": f"{btile[0]}x{btile[1]}",
+           "pixels_per_thread": [ppt_f, ppt_b], "shape_from": "gs_autotune" if args.tile == "auto" else "fixed",
+           "autotune_s": round(t_tune, 2)}
+
+    # batched fwd+bwd (no update): the value
+    st = gs.MappingStep(ctx, g, s.cams, poses, tc, td, gs.StepOptions(**base))
+    st()
+    torch.cuda.synchronize()
+    status = check(st, "batched")
+    log(f"[bench] {name}: pairs {status['n_pairs']} visible {status['n_visible']} capacity {st.capacity}")
+    ms, ms_med = timed_steps([st], args.steps, args.warmup)
+    check(st, "batched")
+    mpx = npix / (ms / 1000.0) / 1e6
+    log(f"[bench] {name}: batched fwd+bwd {ms:.3f} ms/step ({ms_med:.3f} median) -> {mpx:.1f} Mpx/s")
+    res.update(ms_per_step=round(ms, 4), ms_per_step_median_events=round(ms_med, 4), mpx_s=round(mpx, 2),
+               pairs=status["n_pairs"], visible=status["n_visible"])
+
+    if profile:
+        _, frag = st.profile(counts=True)
+        acc = {}
+        for _ in range(args.profile_steps):
+            t, _ = st.profile(counts=False)
+            for k, v in t.items():
+                acc.setdefault(k, []).append(v)
+        check(st, "profile")
+        stage_ms = {k: sum(v) / len(v) for k, v in acc.items()}
+        log(f"[bench] {name}: stages {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})} frags {frag}")
+        res["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
+        res["fragments"] = {"visited": frag[0], "blended": frag[1], "entries_staged": frag[2],
+                            "list_entries": frag[3]}
+        res["_stage_ms"], res["_frag"] = stage_ms, frag
+
+    # mapping iterations (Adam on every Gaussian parameter)
+    gm = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
+    stm = gs.MappingStep(ctx, gm, s.cams, poses.clone(), tc, td, gs.StepOptions(update_gaussians=True, **base),
+                         capacity=st.capacity)
+    ms_map, _ = timed_steps([stm], args.steps, args.warmup)
+    check(stm, "mapping")
+    res["mapping_iters_per_s"] = round(1000.0 / ms_map, 3)
+    res["ms_per_mapping_iter"] = round(ms_map, 4)
+    log(f"[bench] {name}: mapping step {ms_map:.3f} ms -> {1000.0 / ms_map:.2f} it/s")
+    del stm, gm
+
+    # the paper's mapping loss: (1 - zeta)(w4 L1_D + w5 L1_C) + zeta L_SSIM, Adam on the Gaussians
+    gp = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
+    popts = dict(base)
+    popts.update(gs.PAPER_MAPPING)
+    stp = gs.MappingStep(ctx, gp, s.cams, poses.clone(), tc, td, gs.StepOptions(**popts), capacity=st.capacity)
+    ms_paper, _ = timed_steps([stp], args.steps, args.warmup)
+    check(stp, "paper mapping loss")
+    res["paper_mapping_loss_iters_per_s"] = round(1000.0 / ms_paper, 3)
+    log(f"[bench] {name}: paper mapping loss (with SSIM) {ms_paper:.3f} ms -> {1000.0 / ms_paper:.2f} it/s")
+    del stp, gp
+
+    if per_view:
+        pv = per_view_steps(gs, ctx, s, g, poses, tc, td, base)
+        ms_pv, _ = timed_steps(pv, args.steps, args.warmup)
+        for p in pv:
+            check(p, "per-view")
+        mpv = npix / (ms_pv / 1000.0) / 1e6
+        # equal accuracy: the batched and the per-view gradients of this input
+        st()
+        for p in pv:
+            p()
+        torch.cuda.synchronize()
+        errs = batched_vs_per_view_grads(st, pv, s.V)
+        worst = max(errs.values())
+        log(f"[bench] {name}: per-view fwd+bwd {ms_pv:.3f} ms/step -> {mpv:.1f} Mpx/s; gradient agreement "
+            f"{json.dumps({k: float(f'{v:.2e}') for k, v in errs.items()})}")
+        if worst > 1e-3:
+            raise RuntimeError(f"per-view and batched gradients differ by {worst:.2e} > 1e-3")
+        res.update(per_view_mpx_s=round(mpv, 2), batched_over_per_view=round(mpx / mpv, 3),
+                   per_view_vs_batched_grad_rel_err={k: float(f"{v:.3e}") for k, v in errs.items()})
+        del pv
+    res["_scene"], res["_inputs"], res["_step"], res["_base"] = s, (g, poses, tc, td), st, base
+    res["_shape"] = (tile, binsz, btile)
+    return res
+
+
+def roofline(res, workload, ctx):
+    stage_ms, frag = res.get("_stage_ms"), res.get("_frag")
+    if not stage_ms or frag is None:
+        return None
+    dom = max(stage_ms, key=stage_ms.get)
+    if dom not in ("composite_bwd", "composite_fwd"):
+        return {"kernel": dom, "note": "dominant stage is not a compositing kernel"}
+    vis, blend = frag[0], frag[1]
+    npix = res["pixels_per_step"]
+    if dom == "composite_fwd":
+        flops = FWD_PER_VISIT * vis + FWD_PER_BLEND * blend + FWD_PER_PIXEL * npix
+    else:
+        flops = BWD_PER_VISIT * vis + BWD_PER_BLEND * blend
+    achieved = flops / (stage_ms[dom] / 1000.0) / 1e12
+    tile, _, btile = res["_shape"]
+    kt = btile if dom == "composite_bwd" else tile
+    kname = f"composite_{dom.split('_')[1]}_kernel<{kt[0]}, {kt[1]}, {ctx.ppt_choice(kt, dom == 'composite_bwd')}>"
+    traffic = measured_traffic(workload, kname)
+    return {"bound": "alu", "kernel": dom, "kernel_name": kname, "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+            "traffic": None if traffic is None else int(traffic), "flops_per_launch": int(flops),
+            "ms_per_launch": round(stage_ms[dom], 4),
+            "traffic_GBs": None if traffic is None else round(traffic / (stage_ms[dom] / 1000.0) / 1e9, 1)}
+
+
+def public(res):
+    return {k: v for k, v in res.items() if not k.startswith("_")}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--views", type=int, default=8)
-    ap.add_argument("--width", type=int, default=1200)
-    ap.add_argument("--height", type=int, default=680)
-    ap.add_argument("--tile", default=DEFAULT_LAUNCH,
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c5")
+    ap.add_argument("--tile", default="auto",
                     help="auto | TWxTH,PPT,BWxBH[,BTWxBTH,BPPT] (tile, pixels per thread, bin[, backward tile, ppt]); "
-                         "auto runs gs_autotune")
+                         "auto runs gs_autotune on the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the CPU oracle runs")
+    ap.add_argument("--cpu-views", type=int, default=2, help="views of the workload the CPU oracle runs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum timed CPU oracle work")
+    ap.add_argument("--cpu-one-thread-pixels", type=int, default=20000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (PMC byte-counter calibration) and exit")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the second workload")
+    ap.add_argument("--session-steps", type=int, default=500, help="sliding-window session steps (0: skip)")
     ap.add_argument("--profile-steps", type=int, default=5, help="eager steps timed per stage with HIP events")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -183,142 +464,72 @@ def main():
     import torch
     import paper_2405_19614_amd as gs
     torch.cuda.set_device(0)
-    log("[bench] building inputs")
-    s, ctx, g, poses, tc, td = make_inputs(args)
-    npix = s.npix
-    if args.tile == "auto":
-        tile, binsz = ctx.autotune(g, s.cams, poses, iters=2)
-    else:
-        # TWxTH,PPT,BWxBH[,BTWxBTH,BPPT]: forward tile, pixels per thread, bin[, backward tile and its ppt]
-        vals = [int(x) for x in args.tile.lower().replace("x", ",").split(",")]
-        tw, th, ppt, bw, bh = vals[:5]
-        ctx.set_tile(tw, th, ppt)
-        ctx.set_bin(bw, bh)
-        if len(vals) == 8:
-            ctx.set_bwd_shape(vals[5], vals[6], vals[7])
-        tile, binsz = (tw, th), (bw, bh)
-    btile = ctx.bwd_tile_choice if ctx.bwd_tile_choice != (0, 0) else tile
-    ppt_f, ppt_b = ctx.ppt_choice(tile), ctx.ppt_choice(btile, True)
-    log(f"[bench] tile {tile} x{ppt_f} bin {binsz} backward tile {btile} x{ppt_b}")
-    base = dict(w_color=1.0, w_depth=0.1, w_reproj=0.0, tile=tile, bin=binsz, use_graph=True)
+    torch.cuda.reset_peak_memory_stats()
+    ctx = gs.Context(0)
+    main_res = run_workload(gs, ctx, args.workload, args, per_view=not args.no_per_view)
+    roof = roofline(main_res, args.workload, ctx)
+    peak_alloc = torch.cuda.max_memory_allocated()
+    free, total = torch.cuda.mem_get_info()
 
-    # batched fwd+bwd (no update): the value
-    st = gs.MappingStep(ctx, g, s.cams, poses, tc, td, gs.StepOptions(**base))
-    st()
-    torch.cuda.synchronize()
-    status = st.status()
-    if status["flags"]:
-        raise RuntimeError(f"pair overflow: {status}")
-    log(f"[bench] pairs {status['n_pairs']} visible {status['n_visible']} capacity {st.capacity}")
-    ms, ms_med = timed_steps([st], args.steps, args.warmup)
-    mpx = npix / (ms / 1000.0) / 1e6
-    log(f"[bench] batched fwd+bwd: {ms:.3f} ms/step ({ms_med:.3f} median) -> {mpx:.1f} Mpx/s")
+    sess = None
+    if args.session_steps > 0 and "trajectory" in main_res["_scene"].extra:
+        log(f"[bench] session: {args.session_steps} sliding-window mapping steps")
+        tile, binsz, btile = main_res["_shape"]
+        sess = session(gs, ctx, main_res["_scene"], main_res["_inputs"][0], main_res["_base"], args.session_steps,
+                       tile, binsz, btile)
+        log(f"[bench] session: {json.dumps(sess)}")
 
-    # per-stage times and fragment counts (eager steps with HIP events)
-    # (the counting pass runs the counting forward, so it is not timed)
-    _, frag = st.profile(counts=True)
-    stage_acc = {}
-    for i in range(args.profile_steps):
-        t, _ = st.profile(counts=False)
-        for k, v in t.items():
-            stage_acc.setdefault(k, []).append(v)
-    stage_ms = {k: sum(v) / len(v) for k, v in stage_acc.items()}
-    log(f"[bench] stages {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})} frags {frag}")
-
-    # mapping iterations (Adam on every Gaussian parameter)
-    gm = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
-    stm = gs.MappingStep(ctx, gm, s.cams, poses.clone(), tc, td,
-                         gs.StepOptions(update_gaussians=True, **base), capacity=st.capacity)
-    ms_map, _ = timed_steps([stm], args.steps, args.warmup)
-    iters = 1000.0 / ms_map
-    log(f"[bench] mapping step: {ms_map:.3f} ms -> {iters:.2f} it/s")
-
-    # the paper's mapping loss: (1 - zeta)(w4 L1_D + w5 L1_C) + zeta L_SSIM, Adam on the Gaussians
-    gp = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
-    popts = dict(base)
-    popts.update(gs.PAPER_MAPPING)
-    stp = gs.MappingStep(ctx, gp, s.cams, poses.clone(), tc, td, gs.StepOptions(**popts), capacity=st.capacity)
-    ms_paper, _ = timed_steps([stp], args.steps, args.warmup)
-    t_paper, _ = stp.profile(counts=False)
-    log(f"[bench] paper mapping loss (with SSIM): {ms_paper:.3f} ms -> {1000.0 / ms_paper:.2f} it/s; "
-        f"ssim stage {t_paper.get('ssim', 0.0):.4f} ms")
-
-    # per-view: the same kernels, V = 1 per launch sequence, V sequences per step
-    per_view = None
-    if not args.no_per_view:
-        off = s.pix_offsets()
-        pv_steps = []
-        for v in range(s.V):
-            pv_steps.append(gs.MappingStep(ctx, g, [s.cams[v]], poses[v:v + 1].clone(),
-                                           tc[3 * off[v]:3 * off[v + 1]].contiguous(),
-                                           td[off[v]:off[v + 1]].contiguous(),
-                                           gs.StepOptions(**base)))
-        ms_pv, _ = timed_steps(pv_steps, args.steps, args.warmup)
-        per_view = npix / (ms_pv / 1000.0) / 1e6
-        log(f"[bench] per-view fwd+bwd: {ms_pv:.3f} ms/step -> {per_view:.1f} Mpx/s")
-
-    # roofline of the dominant kernel (compositing stages are one kernel each)
-    dom = max(stage_ms, key=stage_ms.get)
-    roof = None
-    if frag is not None and dom in ("composite_bwd", "composite_fwd"):
-        vis, blend = frag[0], frag[1]
-        if dom == "composite_fwd":
-            flops = FWD_PER_VISIT * vis + FWD_PER_BLEND * blend + FWD_PER_PIXEL * npix
-        else:
-            flops = BWD_PER_VISIT * vis + BWD_PER_BLEND * blend
-        achieved = flops / (stage_ms[dom] / 1000.0) / 1e12
-        kt = btile if dom == "composite_bwd" else tile
-        kname = f"composite_{dom.split('_')[1]}_kernel<{kt[0]}, {kt[1]}, {ctx.ppt_choice(kt, dom == 'composite_bwd')}>"
-        traffic = measured_traffic(kname)
-        roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                "traffic": None if traffic is None else int(traffic),
-                "flops_per_launch": int(flops), "ms_per_launch": round(stage_ms[dom], 4),
-                "traffic_GBs": None if traffic is None else round(traffic / (stage_ms[dom] / 1000.0) / 1e9, 1)}
+    extra = None
+    if not args.no_extra:
+        other = "c3" if args.workload == "c5" else "c5"
+        ctx2 = gs.Context(0)
+        r2 = run_workload(gs, ctx2, other, args, per_view=not args.no_per_view, profile=True)
+        extra = public(r2)
+        extra["roofline"] = roofline(r2, other, ctx2)
+        del r2
 
     cpu = None
     if not args.no_cpu_baseline:
-        views = list(range(min(args.cpu_views, s.V)))
+        views = list(range(min(args.cpu_views, main_res["views"])))
         log(f"[bench] CPU oracle on views {views}")
-        px, reps, dt, cores = cpu_baseline(s, views, args.cpu_seconds)
-        cpu = {"value": round(px * reps / dt / 1e6, 5), "unit": "Mpx/s", "cores": cores, "kind": "oracle",
+        cb = cpu_baseline(main_res["_scene"], views, args.cpu_seconds, args.cpu_one_thread_pixels)
+        cpu = {"value": round(cb["px"] * cb["reps"] / cb["seconds"] / 1e6, 5), "unit": "Mpx/s",
+               "cores": cb["threads"], "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"FP64 oracle forward + L1 loss + backward of views {views} of the same workload "
-                         f"({px} px), {reps} pass(es) in {dt:.1f} s"}
+                         f"({cb['px']} px) on {cb['threads']} threads, {cb['reps']} pass(es) in {cb['seconds']:.1f} s",
+               "one_thread": {"value": round(cb["one_thread_px"] / cb["one_thread_seconds"] / 1e6, 6),
+                              "unit": "Mpx/s", "seconds": round(cb["one_thread_seconds"], 2),
+                              "sample": f"{cb['one_thread_px']} sampled pixels of view 0 (projection of every "
+                                        "Gaussian included), one thread"}}
 
+    m = public(main_res)
+    cfg_keys = ["workload", "gaussians", "sh_degree", "views", "width", "height", "pixels_per_step", "tile", "bin",
+                "bwd_tile", "pixels_per_thread", "shape_from", "autotune_s"]
     out = {
         "metric": "fwd+bwd megapixels/s (batched, one graph replay per step); mapping iters/s and per-view rate "
                   "alongside",
-        "value": round(mpx, 2),
+        "value": m["mpx_s"],
         "unit": "Mpx/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"batched keyframe window: {s.n} Gaussians, room shell, {s.V} views "
-                               f"{args.width}x{args.height}, f=600, L1 colour + 0.1 L1 depth",
-                   "gaussians": s.n, "views": s.V, "width": args.width, "height": args.height,
-                   "pixels_per_step": npix, "tile": f"{tile[0]}x{tile[1]}", "bin": f"{binsz[0]}x{binsz[1]}",
-                   "bwd_tile": f"{btile[0]}x{btile[1]}", "pixels_per_thread": [ppt_f, ppt_b]},
-        "mapping_iters_per_s": round(iters, 3),
-        "ms_per_mapping_iter": round(ms_map, 4),
-        "paper_mapping_loss_iters_per_s": round(1000.0 / ms_paper, 3),
-        "ssim_stage_ms": round(t_paper.get("ssim", 0.0), 4),
-        "per_view_mpx_s": None if per_view is None else round(per_view, 2),
-        "batched_over_per_view": None if per_view is None else round(mpx / per_view, 3),
-        "ms_per_step_median_events": round(ms_med, 4),
-        "pairs": status["n_pairs"],
-        "visible": status["n_visible"],
-        "fragments": None if frag is None else {"visited": frag[0], "blended": frag[1], "entries_staged": frag[2],
-                                                "list_entries": frag[3]},
-        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "roofline": roof,
-        "cpu_baseline": cpu,
+        "config": {k: m[k] for k in cfg_keys},
     }
+    for k, v in m.items():
+        if k not in cfg_keys and k not in ("mpx_s", "ms_per_step"):
+            out[k] = v
+    out["peak_memory"] = {"torch_max_allocated_GB": round(peak_alloc / 1e9, 3),
+                          "device_used_GB": round((total - free) / 1e9, 3), "device_total_GB": round(total / 1e9, 3)}
+    out["session"] = sess
+    out["roofline"] = roof
+    out["cpu_baseline"] = cpu
+    out["extra_workload"] = extra
     print(json.dumps(out), flush=True)
 
 

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 2
+#define GS_ABI_VERSION 3
 #define GS_MAX_VIEWS 64
 
 typedef enum {
@@ -151,7 +151,9 @@ size_t gs_state_bytes(const gs_camera* cams, int32_t V, int64_t n, int64_t pair_
  *   plan   HOST in/out (see gs_plan)
  * Reads the pair count back once (one stream synchronisation) and returns
  * GS_ECAPACITY with plan->n_pairs = pairs needed when the capacity is too
- * small; nothing after the count is then enqueued. */
+ * small, or GS_EINVAL when a mean, log-scale, quaternion or opacity logit (or
+ * the colour of a visible Gaussian) is not finite; nothing after the count is
+ * then enqueued. */
 int gs_render_forward(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
                       float* color, float* depth, float* alpha, void* state, size_t state_bytes, gs_plan* plan,
                       void* stream);
@@ -252,8 +254,9 @@ typedef struct {
 
 /* Adam state (device): m and v each hold n*(11 + 3K) + 6V floats laid out as
  * means [3n], log_scales [3n], quats [4n], opacity [n], colors [3Kn] (K = 1 for
- * RGB, (L+1)^2 for SH), poses [6V]; step is a device int32 counter of updates
- * done (incremented on the device). */
+ * RGB, (L+1)^2 for SH), poses [6V]; step is a device int32[2]: the Gaussian
+ * updates done and the pose updates done (incremented on the device).  Each
+ * group's bias correction uses its own count, as two optimisers would. */
 typedef struct {
     float* m;
     float* v;
@@ -276,18 +279,53 @@ size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int3
  *   color, depth, alpha  device render outputs (sum 3HW / sum HW)
  *   loss_out device [1 + 4V]: total L, then (Lc_v, Ld_v, Lr_v, Ls_v) per view
  *   dL_dpose device [V][6]: gradient of L w.r.t. each pose tangent
- * A pair overflow is flagged on the device (results then invalid); read it
- * with gs_step_status. */
+ * A pair overflow or a non-finite parameter is flagged on the device: the
+ * step's results are then invalid and it skips every update (see
+ * gs_step_status, which reads the flags). */
 int gs_mapping_step(gs_ctx* ctx, gs_gaussians* params, gs_gaussian_grads* grads, const gs_adam* adam,
                     const gs_camera* cams, float* poses, int32_t V, const gs_targets* targets,
                     const gs_matches* matches, const gs_step_opts* opts, void* workspace, size_t workspace_bytes,
                     float* color, float* depth, float* alpha, float* loss_out, float* dL_dpose, void* stream);
 
-/* Synchronous read of the workspace status after gs_mapping_step: *flags bit 0 =
- * pair overflow, bit 1 = a binning scan gave up waiting for another workgroup
- * (the step's results are then invalid); *n_pairs = pairs of the last step
- * (needed ones on overflow),
- * *n_visible = visible records.  Synchronises `stream`. */
+/* The optimiser update of gs_mapping_step on its own (Adam with bias
+ * correction; the paper's "gradient-based optimization", Sec. 3.4), for
+ * gradients the caller computed (e.g. through gs_render_backward):
+ * opts->update_gaussians applies Adam to every Gaussian parameter with its
+ * group's learning rate (grads device, layout of g); opts->update_poses
+ * applies Adam to each view's pose tangent gradient dL_dpose (device [V][6])
+ * and sets poses[v] <- Exp(step) poses[v] (device [V][16]).  Uses lr_*,
+ * adam_b1, adam_b2, adam_eps of opts and nothing else; the matching
+ * counters of adam->step advance by one.  Asynchronous on `stream`. */
+int gs_adam_update(gs_ctx* ctx, gs_gaussians* g, const gs_gaussian_grads* grads, const gs_adam* adam, float* poses,
+                   const float* dL_dpose, int32_t V, const gs_step_opts* opts, void* stream);
+
+/* Pose retraction for the pose refinement of the joint optimisation
+ * (Sec. 3.3): poses_out[v] = Exp(xi[v]) poses[v], with xi = (v, w) the
+ * left-perturbation twist (translation first) and Exp the SE(3)
+ * exponential.  poses, poses_out device [V][16] (may alias), xi device
+ * [V][6].  Asynchronous on `stream`. */
+int gs_pose_retract(gs_ctx* ctx, int32_t V, const float* poses, const float* xi, float* poses_out, void* stream);
+
+/* Chain rule through the retraction: given dL_dpose, the left-perturbation
+ * gradient at the retracted pose Exp(xi) T (as gs_render_backward returns
+ * it), dL_dxi = J_l(xi)^T dL_dpose is the gradient with respect to xi itself
+ * (J_l the left Jacobian of SE(3); the identity at xi = 0).  Device [V][6]
+ * each.  Asynchronous on `stream`. */
+int gs_pose_tangent_grad(gs_ctx* ctx, int32_t V, const float* xi, const float* dL_dpose, float* dL_dxi,
+                         void* stream);
+
+/* Synchronous read of the workspace status after gs_mapping_step.  *flags is
+ * the OR over every step since the previous gs_step_status call on this
+ * workspace (the sticky word, which this call then clears) and the last
+ * step: bit 0 = pair overflow, bit 1 = a binning scan gave up waiting for
+ * another workgroup, bit 2 = a Gaussian parameter the step read was not
+ * finite (a mean, log-scale, quaternion or opacity logit of any Gaussian, or
+ * the colour of one some view sees).  A step with any bit set has invalid
+ * results and makes no update: parameters, poses, Adam moments and the step
+ * counter keep their values.  *n_pairs = pairs of the last step (needed ones
+ * on overflow), *n_visible = its visible records.  The sticky word of a new
+ * workspace must start at zero: zero the first 64 bytes, or call
+ * gs_step_status once, before the first step.  Synchronises `stream`. */
 int gs_step_status(gs_ctx* ctx, const void* workspace, size_t workspace_bytes, int32_t* flags, int64_t* n_pairs,
                    int64_t* n_visible, void* stream);
 
@@ -401,7 +439,9 @@ int gs_select_viewpoints(const int32_t* covis, const int32_t* n_obs, int32_t F, 
  * Pruning (Sec. 3.4 pruning equation; its printed cases and the text
  * disagree on which side is removed, the text is followed): a Gaussian is
  * removed when its opacity sigmoid(opacity_logit) < tau, the others keep their
- * order.  tau <= 0 keeps every Gaussian, tau >= 1 removes every one.
+ * order.  tau <= 0 keeps every Gaussian, tau >= 1 removes every one.  tau is a
+ * double and the decision is exact: the FP32 logit is compared with
+ * logit(tau) in FP64.
  *   in        device arrays of in->n Gaussians (sh_degree as in gs_gaussians).
  *   out       device arrays with room for in->n Gaussians, not overlapping in;
  *             out->n and out->sh_degree are ignored.
@@ -414,11 +454,12 @@ int gs_select_viewpoints(const int32_t* covis, const int32_t* n_obs, int32_t F, 
  * Asynchronous on `stream`; GS_EINVAL for NULL pointers, GS_ENOMEM for a
  * short workspace. */
 size_t gs_prune_workspace_bytes(int64_t n);
-int gs_prune(gs_ctx* ctx, const gs_gaussians* in, float tau, gs_gaussians* out, const gs_adam* adam_in,
+int gs_prune(gs_ctx* ctx, const gs_gaussians* in, double tau, gs_gaussians* out, const gs_adam* adam_in,
              gs_adam* adam_out, int32_t V, int64_t* n_out, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Densification (Sec. 3.4 densification, Eq. d): for every pixel of the V
- * views whose rendered alpha (the border mask M_b) is <= gamma -- every pixel
+ * views whose rendered alpha (the border mask M_b) is <= gamma (the FP32
+ * alpha compared with the double gamma in FP64) -- every pixel
  * when all_pixels is set, as on the first frame -- and whose target depth d
  * is > 0, one Gaussian is appended after the g->n existing ones, in view then
  * row-major pixel order: mean = the pixel's sample point (x, y) back-projected
@@ -439,7 +480,7 @@ int gs_prune(gs_ctx* ctx, const gs_gaussians* in, float tau, gs_gaussians* out, 
  * Asynchronous on `stream`. */
 size_t gs_densify_workspace_bytes(const gs_camera* cams, int32_t V);
 int gs_densify(gs_ctx* ctx, const gs_camera* cams, const float* poses, int32_t V, const float* alpha,
-               const float* tgt_color, const float* tgt_depth, float gamma, int32_t all_pixels, gs_gaussians* g,
+               const float* tgt_color, const float* tgt_depth, double gamma, int32_t all_pixels, gs_gaussians* g,
                int64_t capacity, const gs_adam* adam_in, gs_adam* adam_out, int64_t* counts, void* workspace,
                size_t workspace_bytes, void* stream);
 

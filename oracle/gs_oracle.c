@@ -849,3 +849,6 @@ int or_sh_basis(int deg, int64_t m, const double* dirs, double* Y, double* dY) {
 }
 
 int or_num_threads(void) { return omp_get_max_threads(); }
+
+/* thread count of the OpenMP loops (the benchmark's 1-thread baseline) */
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

@@ -97,6 +97,11 @@ def num_threads() -> int:
     return int(lib().or_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().or_set_num_threads(int(n))
+
+
 def _d(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
@@ -587,6 +592,26 @@ def se3_exp(xi) -> np.ndarray:
     T[:3, :3] = R
     T[:3, 3] = Vm @ v
     return T
+
+
+def se3_left_jacobian(xi, terms: int = 60) -> np.ndarray:
+    """Left Jacobian J_l of SE(3) at the twist xi = (v, w): the 6x6 matrix with
+    Exp(xi + e) = Exp(J_l e) Exp(xi) to first order in e, from its defining
+    series sum_n ad(xi)^n / (n + 1)!, ad(xi) = [[w^, v^], [0, w^]] (the
+    bracket of se(3) in (v, w) coordinates).  The gradient of L(Exp(xi) T)
+    with respect to xi is J_l(xi)^T times the left-perturbation gradient at
+    Exp(xi) T (the pose tangent of the joint optimisation, Sec. 3.3)."""
+    xi = np.asarray(xi, np.float64)
+    ad = np.zeros((6, 6))
+    ad[:3, :3] = hat(xi[3:])
+    ad[:3, 3:] = hat(xi[:3])
+    ad[3:, 3:] = hat(xi[3:])
+    J = np.eye(6)
+    term = np.eye(6)
+    for n in range(1, terms):
+        term = term @ ad / (n + 1)
+        J = J + term
+    return J
 
 
 def adam_step(param, grad, m, v, t: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):

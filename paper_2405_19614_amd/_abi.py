@@ -69,7 +69,8 @@ EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_sta
            "gs_step_status", "gs_bin_records", "gs_autotune", "gs_set_tile", "gs_num_stages", "gs_stage_name",
            "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bwd_shape", "gs_set_bin",
            "gs_ssim_workspace_bytes", "gs_ssim", "gs_prune_workspace_bytes", "gs_prune",
-           "gs_densify_workspace_bytes", "gs_densify", "gs_select_viewpoints"]
+           "gs_densify_workspace_bytes", "gs_densify", "gs_select_viewpoints", "gs_adam_update", "gs_pose_retract",
+           "gs_pose_tangent_grad"]
 
 _lib = None
 
@@ -123,10 +124,10 @@ def load() -> ctypes.CDLL:
     L.gs_select_viewpoints.argtypes = [c_void_p, c_void_p, c_int32, ctypes.c_float, c_int32, c_void_p]
     L.gs_prune_workspace_bytes.argtypes = [c_int64]
     L.gs_prune_workspace_bytes.restype = c_size_t
-    L.gs_prune.argtypes = [c_void_p, PG, ctypes.c_float, PG, PA, PA, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.gs_prune.argtypes = [c_void_p, PG, ctypes.c_double, PG, PA, PA, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]
     L.gs_densify_workspace_bytes.argtypes = [PC, c_int32]
     L.gs_densify_workspace_bytes.restype = c_size_t
-    L.gs_densify.argtypes = [c_void_p, PC, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_int32,
+    L.gs_densify.argtypes = [c_void_p, PC, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_double, c_int32,
                              PG, c_int64, PA, PA, c_void_p, c_void_p, c_size_t, c_void_p]
     L.gs_ssim_workspace_bytes.argtypes = [PC, c_int32]
     L.gs_ssim_workspace_bytes.restype = c_size_t
@@ -137,5 +138,9 @@ def load() -> ctypes.CDLL:
     L.gs_stage_name.argtypes = [c_int32]
     L.gs_stage_name.restype = ctypes.c_char_p
     L.gs_step_profile.argtypes = L.gs_mapping_step.argtypes[:-1] + [c_void_p, c_void_p, c_void_p]
+    L.gs_adam_update.argtypes = [c_void_p, PG, ctypes.POINTER(gs_gaussian_grads), PA, c_void_p, c_void_p, c_int32,
+                                 ctypes.POINTER(gs_step_opts), c_void_p]
+    L.gs_pose_retract.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.gs_pose_tangent_grad.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     _lib = L
     return L

@@ -304,6 +304,63 @@ class Context:
             return residual[:M], loss, dpose, dpts[:M]
         return residual[:M], loss, dpose
 
+    def pose_retract(self, poses: torch.Tensor, xi: torch.Tensor) -> torch.Tensor:
+        """Exp(xi[v]) poses[v] per view (see gs_pose_retract): poses [V,16] or
+        [V,4,4], xi [V,6]; returns a new [V,16] tensor."""
+        dev = self.torch_device
+        poses = poses.reshape(-1, 16).contiguous()
+        V = int(poses.shape[0])
+        xi = xi.detach().to(torch.float32).contiguous()
+        _need(poses, 16 * V, "poses", device=dev)
+        _need(xi, 6 * V, "xi", device=dev)
+        out = torch.empty_like(poses)
+        self._check(self.lib.gs_pose_retract(self.h, V, _p(poses), _p(xi), _p(out), _stream()))
+        return out
+
+    def pose_tangent_grad(self, xi: torch.Tensor, dpose: torch.Tensor) -> torch.Tensor:
+        """J_l(xi)^T dpose per view (see gs_pose_tangent_grad)."""
+        dev = self.torch_device
+        xi = xi.detach().to(torch.float32).contiguous()
+        dpose = dpose.to(torch.float32).contiguous()
+        V = int(xi.numel() // 6)
+        _need(xi, 6 * V, "xi", device=dev)
+        _need(dpose, 6 * V, "dpose", device=dev)
+        out = torch.empty(V, 6, dtype=torch.float32, device=dev)
+        self._check(self.lib.gs_pose_tangent_grad(self.h, V, _p(xi), _p(dpose), _p(out), _stream()))
+        return out
+
+    def adam_update(self, g: "Gaussians", grads: Optional["Gaussians"], adam, opts: "StepOptions",
+                    poses: Optional[torch.Tensor] = None, dpose: Optional[torch.Tensor] = None):
+        """The optimiser of gs_mapping_step on caller-given gradients (see
+        gs_adam_update): ``adam`` = (m, v, step) laid out for g.n Gaussians
+        and V poses, step an int32[2] (Gaussian, pose updates); updates g's
+        tensors and ``poses`` ([V,16]) in place."""
+        dev = self.torch_device
+        _check_gaussians(g, dev)
+        m, v, step = adam
+        V = 0 if poses is None else int(poses.numel() // 16)
+        K = sh_coeffs(g.sh_degree)
+        na = g.n * (11 + 3 * K) + 6 * V
+        _need(m, na, "adam m", device=dev)
+        _need(v, na, "adam v", device=dev)
+        _need(step, 2, "adam step", dtype=torch.int32, device=dev)
+        if opts.update_gaussians:
+            if grads is None:
+                raise ValueError("update_gaussians needs the gradients")
+            _check_gaussians(grads, dev)
+        if opts.update_poses and V:
+            if dpose is None or not poses.is_contiguous():
+                raise ValueError("update_poses needs contiguous poses and dpose")
+            _need(dpose.contiguous(), 6 * V, "dpose", device=dev)
+        gst = g.struct()
+        gg = grads.grad_struct() if grads is not None else None
+        ad = A.gs_adam(_p(m), _p(v), _p(step))
+        o = opts.struct(0, (0, 0))
+        rc = self.lib.gs_adam_update(self.h, ctypes.byref(gst), ctypes.byref(gg) if gg is not None else None,
+                                     ctypes.byref(ad), _p(poses), _p(None if dpose is None else dpose.contiguous()),
+                                     V, ctypes.byref(o), _stream())
+        self._check(rc)
+
     def ssim(self, cams, img: torch.Tensor, ref: torch.Tensor, weights: Optional[torch.Tensor] = None,
              dimg: Optional[torch.Tensor] = None):
         """Mean SSIM per view of planar colour images (concatenated [3,H,W]
@@ -492,32 +549,45 @@ def default_context(device: Optional[int] = None) -> Context:
 
 class GSRenderFn(torch.autograd.Function):
     """Differentiable batched render: (means, log_scales, quats, opacity
-    logits, colours, poses [V,4,4]) -> (colour, depth, alpha), concatenated
-    over views.  The pose gradient is returned in the left-perturbation
-    tangent of T_cw through ``pose_tangent`` (see ``render``)."""
+    logits, colours, pose tangent xi [V,6], poses [V,16]) -> (colour, depth,
+    alpha), concatenated over views.  The views are rendered at
+    Exp(xi[v]) poses[v] (gs_pose_retract); the gradient with respect to xi is
+    J_l(xi)^T times the left-perturbation gradient at the rendered pose
+    (gs_pose_tangent_grad), so it is exact at any xi, and the plain
+    left-perturbation gradient at xi = 0.  Inputs are saved with
+    save_for_backward, so an in-place change between forward and backward
+    raises."""
 
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_tangent, poses, gs_ctx, cams,
                 sh_degree, tile):
         g = Gaussians(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacity_logits.contiguous(),
                       colors.contiguous(), sh_degree)
-        color, depth, alpha, state, plan = gs_ctx.forward(g, cams, poses, tile=tile)
-        ctx.gs = (gs_ctx, cams, g, poses, state, plan)
+        rposes = gs_ctx.pose_retract(poses, pose_tangent)
+        color, depth, alpha, state, plan = gs_ctx.forward(g, cams, rposes, tile=tile)
+        ctx.save_for_backward(means, log_scales, quats, opacity_logits, colors, pose_tangent, rposes, state)
+        ctx.gs = (gs_ctx, cams, sh_degree, plan)
         return color, depth, alpha
 
     @staticmethod
     def backward(ctx, dC, dD, dA):
-        gs_ctx, cams, g, poses, state, plan = ctx.gs
-        grads, dpose = gs_ctx.backward(g, cams, poses, state, plan, dC, dD, dA)
-        return (grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.colors, dpose, None, None,
-                None, None, None)
+        means, log_scales, quats, opacity_logits, colors, pose_tangent, rposes, state = ctx.saved_tensors
+        gs_ctx, cams, sh_degree, plan = ctx.gs
+        g = Gaussians(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacity_logits.contiguous(),
+                      colors.contiguous(), sh_degree)
+        grads, dpose = gs_ctx.backward(g, cams, rposes, state, plan, dC, dD, dA)
+        dxi = gs_ctx.pose_tangent_grad(pose_tangent, dpose)
+        return (grads.means.view_as(means), grads.log_scales.view_as(log_scales), grads.quats.view_as(quats),
+                grads.opacity_logits.view_as(opacity_logits), grads.colors.view_as(colors),
+                dxi.view_as(pose_tangent), None, None, None, None, None)
 
 
 def render(g: Gaussians, cams, poses: torch.Tensor, pose_tangent: Optional[torch.Tensor] = None,
            ctx: Optional[Context] = None, tile=(0, 0)):
-    """Differentiable render of V views.  Gradients flow to g's tensors (if
-    they require grad) and to ``pose_tangent`` ([V,6], the left-perturbation
-    tangent at zero; pass a zero tensor with requires_grad to get d/dxi)."""
+    """Differentiable render of V views at Exp(pose_tangent[v]) poses[v].
+    Gradients flow to g's tensors (if they require grad) and to
+    ``pose_tangent`` ([V,6], xi = (v, w), translation first; a zero tensor
+    with requires_grad gives the left-perturbation gradient d/dxi at 0)."""
     cams = as_cameras(cams)
     ctx = ctx or default_context()
     if pose_tangent is None:
@@ -645,12 +715,13 @@ class MappingStep:
         npix = sum(c.npix for c in self.cams)
         self.ws_bytes = ctx.workspace_bytes(self.cams, g.n, g.sh_degree, self.capacity, self.bin)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.ws[:64].zero_()     # the status words (the sticky flags start at zero)
         self.grads = g.zeros_like()
         K = sh_coeffs(g.sh_degree)
         na = g.n * (11 + 3 * K) + 6 * self.V
         self.adam_m = torch.zeros(na, dtype=torch.float32, device=dev)
         self.adam_v = torch.zeros(na, dtype=torch.float32, device=dev)
-        self.adam_step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.adam_step = torch.zeros(2, dtype=torch.int32, device=dev)   # Gaussian updates, pose updates
         self.color = torch.empty(3 * npix, dtype=torch.float32, device=dev)
         self.depth = torch.empty(npix, dtype=torch.float32, device=dev)
         self.alpha = torch.empty(npix, dtype=torch.float32, device=dev)
@@ -699,6 +770,10 @@ class MappingStep:
         return dict(zip(names, list(ms))), (tuple(int(x) for x in fc) if counts else None)
 
     def status(self) -> Dict[str, int]:
+        """Flags of every step since the previous call (bit 0 pair overflow,
+        bit 1 binning scan timed out, bit 2 non-finite parameter; a flagged
+        step made no update), and the last step's pair and visible counts.
+        Synchronises the stream and clears the sticky flags."""
         fl = ctypes.c_int32()
         npairs = ctypes.c_int64()
         nvis = ctypes.c_int64()
@@ -706,6 +781,20 @@ class MappingStep:
                                          ctypes.byref(npairs), ctypes.byref(nvis), _stream())
         self.ctx._check(rc)
         return {"flags": int(fl.value), "n_pairs": int(npairs.value), "n_visible": int(nvis.value)}
+
+    def check(self) -> Dict[str, int]:
+        """status(), raising GSError when a step since the previous check was
+        flagged."""
+        st = self.status()
+        f = st["flags"]
+        if f & 1:
+            raise GSError(A.GS_ECAPACITY, f"{st['n_pairs']} pairs exceed the capacity {self.capacity}; "
+                                          "re-plan the step with a larger capacity")
+        if f & 4:
+            raise GSError(A.GS_EINVAL, "a Gaussian parameter is not finite; the flagged steps made no update")
+        if f:
+            raise GSError(A.GS_EDEVICE, f"step status flags {f:#x}")
+        return st
 
 
 class JointRefinement:
@@ -727,12 +816,16 @@ class JointRefinement:
         self.map_opts = map_opts or replace(base, **PAPER_MAPPING)
 
     def __call__(self, k_pose: int, k_map: int):
+        """Runs the two phases, then reads the step status once (one
+        synchronisation) and raises GSError if any step was flagged (such
+        steps made no update)."""
         self.step.set_options(self.pose_opts)
         for _ in range(k_pose):
             self.step()
         self.step.set_options(self.map_opts)
         for _ in range(k_map):
             self.step()
+        self.step.check()
 
 
 def select_viewpoints(covis, n_obs, alpha: float = 0.75, beta: int = 20):

@@ -565,11 +565,14 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     plan->bin_h = bh;
     plan->bwd_tile_w = btw;
     plan->bwd_tile_h = bth;
-    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, false, s));
+    GS_HIP(c, gs::launch_status_clear(L, base, s));
+    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, false, s, p.scal + gs::kFlags));
     GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.line, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");
+    if (c->pinned[gs::kFlags] & gs::kFlagNonFinite)
+        return fail(c, GS_EINVAL, "a Gaussian parameter is not finite (NaN or infinite)");
     const int64_t total = (int64_t)((uint64_t)c->pinned[gs::kPairsLo] | ((uint64_t)c->pinned[gs::kPairsHi] << 32));
     plan->n_pairs = total;
     plan->n_visible = c->pinned[gs::kNVis];
@@ -665,6 +668,65 @@ int gs_reproj_residual_noalloc(gs_ctx* c, const gs_camera* cams, const float* po
     return GS_OK;
 }
 
+int gs_pose_retract(gs_ctx* c, int32_t V, const float* poses, const float* xi, float* poses_out, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (V < 0 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V=%d outside [0, %d]", V, GS_MAX_VIEWS);
+    if (V > 0 && (!poses || !xi || !poses_out)) return fail(c, GS_EINVAL, "a device pointer is NULL");
+    DeviceGuard dg(c->device);
+    GS_HIP(c, gs::launch_pose_retract(V, poses, xi, poses_out, static_cast<hipStream_t>(stream)));
+    return GS_OK;
+}
+
+int gs_pose_tangent_grad(gs_ctx* c, int32_t V, const float* xi, const float* dL_dpose, float* dL_dxi,
+                         void* stream) {
+    if (!c) return GS_EINVAL;
+    if (V < 0 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V=%d outside [0, %d]", V, GS_MAX_VIEWS);
+    if (V > 0 && (!xi || !dL_dpose || !dL_dxi)) return fail(c, GS_EINVAL, "a device pointer is NULL");
+    DeviceGuard dg(c->device);
+    GS_HIP(c, gs::launch_pose_tangent_grad(V, xi, dL_dpose, dL_dxi, static_cast<hipStream_t>(stream)));
+    return GS_OK;
+}
+
+int gs_adam_update(gs_ctx* c, gs_gaussians* g, const gs_gaussian_grads* grads, const gs_adam* adam, float* poses,
+                   const float* dL_dpose, int32_t V, const gs_step_opts* o, void* stream) {
+    if (!c) return GS_EINVAL;
+    if (!o) return fail(c, GS_EINVAL, "opts is NULL");
+    int r = check_gaussians(c, g);
+    if (r) return r;
+    if (!adam || !adam->m || !adam->v || !adam->step) return fail(c, GS_EINVAL, "the Adam state is incomplete");
+    if (V < 0 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V=%d outside [0, %d]", V, GS_MAX_VIEWS);
+    if (o->update_gaussians && g->n > 0 &&
+        (!grads || !grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->colors))
+        return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if (o->update_poses && V > 0 && (!poses || !dL_dpose)) return fail(c, GS_EINVAL, "poses or dL_dpose is NULL");
+    DeviceGuard dg(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = g->n;
+    const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
+    const int64_t np = n * (11 + 3 * K);
+    if (o->update_gaussians) {
+        gs::AdamGroups ag;
+        float* pp[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->colors};
+        const float* gg[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
+        const int64_t cnt[5] = {3 * n, 3 * n, 4 * n, n, 3 * K * n};
+        const float lr[5] = {o->lr_means, o->lr_log_scales, o->lr_quats, o->lr_opacity, o->lr_colors};
+        for (int i = 0; i < 5; i++) {
+            ag.p[i] = pp[i];
+            ag.g[i] = gg[i];
+            ag.cnt[i] = cnt[i];
+            ag.lr[i] = lr[i];
+        }
+        GS_HIP(c, gs::launch_adam(ag, adam->m, adam->v, adam->step, o->adam_b1, o->adam_b2, o->adam_eps, nullptr, s));
+    }
+    if (o->update_poses && V > 0)
+        GS_HIP(c, gs::launch_pose_update(V, poses, dL_dpose, adam->m + np, adam->v + np, adam->step, o->lr_pose,
+                                         o->adam_b1, o->adam_b2, o->adam_eps, nullptr, s));
+    if (o->update_gaussians || o->update_poses)
+        GS_HIP(c, gs::launch_step_bump(adam->step, o->update_gaussians ? 1 : 0, (o->update_poses && V > 0) ? 1 : 0,
+                                       s));
+    return GS_OK;
+}
+
 size_t gs_ssim_workspace_bytes(const gs_camera* cams, int32_t V) {
     gs::ViewTable vt;
     if (build_vt(nullptr, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt) != GS_OK) return 0;
@@ -742,7 +804,7 @@ int gs_select_viewpoints(const int32_t* covis, const int32_t* n_obs, int32_t F, 
 
 size_t gs_prune_workspace_bytes(int64_t n) { return n < 0 ? 0 : compaction_bytes(n); }
 
-int gs_prune(gs_ctx* c, const gs_gaussians* in, float tau, gs_gaussians* out, const gs_adam* adam_in,
+int gs_prune(gs_ctx* c, const gs_gaussians* in, double tau, gs_gaussians* out, const gs_adam* adam_in,
              gs_adam* adam_out, int32_t V, int64_t* n_out, void* ws, size_t ws_bytes, void* stream) {
     if (!c) return GS_EINVAL;
     int r = check_gaussians(c, in);
@@ -757,8 +819,8 @@ int gs_prune(gs_ctx* c, const gs_gaussians* in, float tau, gs_gaussians* out, co
     gs::AdamIO io;
     const int ha = adam_io(c, adam_in, adam_out, io);
     if (ha < 0) return ha;
-    const double t = (double)tau;
-    const float logit = t <= 0.0 ? -INFINITY : (t >= 1.0 ? INFINITY : (float)std::log(t / (1.0 - t)));
+    const double t = tau;
+    const double logit = t <= 0.0 ? -INFINITY : (t >= 1.0 ? INFINITY : std::log(t) - std::log1p(-t));
     const int K = in->sh_degree < 0 ? 1 : (in->sh_degree + 1) * (in->sh_degree + 1);
     uint32_t *flag, *off, *bsum, *total;
     compaction_ptrs(ws, in->n, flag, off, bsum, total);
@@ -777,7 +839,7 @@ size_t gs_densify_workspace_bytes(const gs_camera* cams, int32_t V) {
 }
 
 int gs_densify(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, const float* alpha,
-               const float* tgt_color, const float* tgt_depth, float gamma, int32_t all_pixels, gs_gaussians* g,
+               const float* tgt_color, const float* tgt_depth, double gamma, int32_t all_pixels, gs_gaussians* g,
                int64_t capacity, const gs_adam* adam_in, gs_adam* adam_out, int64_t* counts, void* ws,
                size_t ws_bytes, void* stream) {
     if (!c) return GS_EINVAL;
@@ -828,7 +890,8 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
     auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     GS_HIP(c, mark(0));
-    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, true, s));
+    GS_HIP(c, gs::launch_status_clear(L, base, s));
+    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, true, s, p.scal + gs::kFlags));
     GS_HIP(c, mark(1));
     uint32_t* vals = nullptr;
     GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.nt, p.rec.line, nullptr, L.cap, s, &vals));
@@ -858,7 +921,7 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
                                     p.rpacc, s));
     GS_HIP(c, gs::launch_loss_reduce(vt, p.tilepart, rp ? p.rpacc : nullptr, ssim ? p.ssim_tiles : nullptr,
                                      o->w_color, o->w_depth, o->w_reproj, o->w_ssim, loss_out, p.rpacc + 8 * vt.V,
-                                     s));
+                                     s, p.scal));
     GS_HIP(c, hipStreamWaitEvent(s, c->ev_join, 0));
     GS_HIP(c, mark(5));
     GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, vt,
@@ -885,12 +948,15 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
                 ag.cnt[i] = cnt[i];
                 ag.lr[i] = lr[i];
             }
-            GS_HIP(c, gs::launch_adam(ag, adam->m, adam->v, adam->step, o->adam_b1, o->adam_b2, o->adam_eps, 0, s));
+            GS_HIP(c, gs::launch_adam(ag, adam->m, adam->v, adam->step, o->adam_b1, o->adam_b2, o->adam_eps,
+                                      p.scal + gs::kFlags, s));
         }
         if (o->update_poses)
             GS_HIP(c, gs::launch_pose_update(vt.V, poses, dL_dpose, adam->m + np, adam->v + np, adam->step,
-                                             o->lr_pose, o->adam_b1, o->adam_b2, o->adam_eps, 0, s));
-        GS_HIP(c, gs::launch_step_bump(adam->step, s));
+                                             o->lr_pose, o->adam_b1, o->adam_b2, o->adam_eps, p.scal + gs::kFlags,
+                                             s));
+        GS_HIP(c, gs::launch_step_bump(adam->step, o->update_gaussians ? 1 : 0, o->update_poses ? 1 : 0, s,
+                                       p.scal + gs::kFlags));
     }
     GS_HIP(c, mark(8));
     return GS_OK;
@@ -1061,7 +1127,10 @@ int gs_step_status(gs_ctx* c, const void* ws, size_t ws_bytes, int32_t* flags, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     GS_HIP(c, hipMemcpyAsync(c->pinned, ws, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
-    if (flags) *flags = (int32_t)c->pinned[gs::kFlags];
+    // read and clear: the sticky word starts over (a kernel, ordered before
+    // the stream's later steps)
+    GS_HIP(c, gs::launch_fill_u32(static_cast<uint32_t*>(const_cast<void*>(ws)) + gs::kSticky, 0u, 1, s));
+    if (flags) *flags = (int32_t)(c->pinned[gs::kFlags] | c->pinned[gs::kSticky]);
     if (n_pairs) *n_pairs = (int64_t)((uint64_t)c->pinned[gs::kPairsLo] | ((uint64_t)c->pinned[gs::kPairsHi] << 32));
     if (n_visible) *n_visible = c->pinned[gs::kNVis];
     return GS_OK;
@@ -1086,6 +1155,7 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
     char* base = static_cast<char*>(state);
     Ptrs p = ptrs_of(L, base, false);
     const uint2* rc = reinterpret_cast<const uint2*>(rect);
+    GS_HIP(c, gs::launch_status_clear(L, base, s));
     GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.line, p.rec.nt, n, s));
     GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.line, depth, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));

@@ -695,6 +695,23 @@ hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* li
 
 #define GS_AT(T, off) reinterpret_cast<T*>(base + (off))
 
+namespace {
+// zero p[0, n) except the sticky status word
+__global__ void status_clear_kernel(uint32_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (i != kSticky) p[i] = 0u;
+}
+}  // namespace
+
+hipError_t launch_status_clear(const Layout& L, char* base, hipStream_t s) {
+    uint32_t* scal = GS_AT(uint32_t, L.off_scalars);
+    const int64_t n = (int64_t)((L.off_lb - L.off_scalars) / 4) + 2 * lb_words(L);
+    int64_t b = (n + 255) / 256;
+    if (b > 1024) b = 1024;
+    status_clear_kernel<<<(unsigned)b, 256, 0, s>>>(scal, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
                                 const RecLine* lines, const float* depth_src, hipStream_t s) {
     uint32_t* scal = GS_AT(uint32_t, L.off_scalars);
@@ -708,9 +725,9 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     const int64_t R = L.R;
     const int64_t nc = L.n_chunks;
     const unsigned g = (unsigned)nc, gs = (unsigned)L.lb_tiles_chunk;
-    // scalars and every chained-scan status word start at zero
-    hipError_t e = launch_fill_u32(scal, 0u, (int64_t)((L.off_lb - L.off_scalars) / 4) + 2 * lb_words(L), s);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    // (the scalars and every chained-scan status word were cleared by
+    // launch_status_clear before the projection)
     // 1. visible records -> compacted (depth bits, record) in record order
     scan_reduce_kernel<LoadVis><<<g, kScanThreads, 0, s>>>(LoadVis{nt_src, R}, R, csum);
     scan_chained_kernel<<<gs, kScanThreads, 0, s>>>(csum, nc, lb, scal + kLbVis, scal + kFlags);

@@ -98,6 +98,7 @@ struct Proj {
     float o;
     float col[3];
     bool cclamp[3];     // SH colour clamped at 0
+    bool colbad;        // the colour (RGB, or the SH sum before its clamp) is not finite
     float dir[3], dirn; // unit view direction, |mu - camera centre|
     float radius;
     int x0, x1, y0, y1;
@@ -107,6 +108,7 @@ struct Proj {
 // world covariance M = R diag(s^2) R^T.
 struct GPrep {
     bool ok;
+    bool finite;        // mean, log-scales, quaternion and opacity logit all finite
     float qn, qh[4], R[9], s[3], o;
     float mu[3];
     float M[6];
@@ -115,6 +117,14 @@ struct GPrep {
 __device__ __forceinline__ void gauss_prep(const Params& P, int g, GPrep& gp) {
     gp.ok = false;
     const float4 q = reinterpret_cast<const float4*>(P.q)[g];
+    {
+        const float* lp = P.ls + 3 * (int64_t)g;
+        const float* mp = P.means + 3 * (int64_t)g;
+        // one non-finite value makes the sum non-finite (finite values of this
+        // size do not overflow the sum)
+        const float sum = (q.x + q.y + q.z + q.w) + (lp[0] + lp[1] + lp[2]) + (mp[0] + mp[1] + mp[2]) + P.opl[g];
+        gp.finite = __builtin_isfinite(sum);
+    }
     const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
     if (!(qn2 > 0.f)) return;
     gp.ok = true;
@@ -215,6 +225,7 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
             const float* cp = P.col + 3 * (int64_t)g;
             o.col[0] = cp[0]; o.col[1] = cp[1]; o.col[2] = cp[2];
             o.cclamp[0] = o.cclamp[1] = o.cclamp[2] = false;
+            o.colbad = !__builtin_isfinite(cp[0] + cp[1] + cp[2]);
         } else {
             // camera centre C = -R_cw^T t_cw
             const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
@@ -239,6 +250,7 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
                 o.cclamp[k] = acc[k] < 0.f;
                 o.col[k] = fmaxf(acc[k], 0.f);
             }
+            o.colbad = !__builtin_isfinite(acc[0] + acc[1] + acc[2]);
         }
     }
 

@@ -182,16 +182,19 @@ struct Layout {
     int64_t pose_blocks;
 };
 
-// scalars block (u32 unless noted), at off_scalars.  kLb*: arrival counters
-// of the chained scans (visible counts and pair counts per chunk, radix
-// histograms: up to kLbHistUses passes per step).
+// scalars block (u32 unless noted), at off_scalars.  kFlags: this step's
+// status bits (cleared when a step starts); kSticky: the OR of kFlags over the
+// steps since gs_step_status last read it (never cleared by a step).  kLb*:
+// arrival counters of the chained scans (visible counts and pair counts per
+// chunk, radix histograms: up to kLbHistUses passes per step).
 enum ScalarSlot {
-    kNVis = 0, kNPairs = 1, kFlags = 2, kPairsLo = 4, kPairsHi = 5,
+    kNVis = 0, kNPairs = 1, kFlags = 2, kSticky = 3, kPairsLo = 4, kPairsHi = 5,
     kLbVis = 6, kLbPairs = 7, kLbHist0 = 8, kNumScalars = 16
 };
 constexpr int kLbHistUses = kNumScalars - kLbHist0;
-// kFlags bits: pair capacity exceeded; a chained scan gave up waiting
-constexpr uint32_t kFlagCapacity = 1u, kFlagLookback = 2u;
+// kFlags bits: pair capacity exceeded; a chained scan gave up waiting; a
+// Gaussian parameter the step read is not finite
+constexpr uint32_t kFlagCapacity = 1u, kFlagLookback = 2u, kFlagNonFinite = 4u;
 // status words of the chained scans: two chunk-sum scans (visible records,
 // pairs), then kLbHistUses histogram scans
 inline int64_t lb_words(const Layout& L) { return 2 * L.lb_tiles_chunk + (int64_t)kLbHistUses * L.lb_tiles_hist; }
@@ -206,18 +209,31 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 hipError_t launch_zero_g2(const uint32_t* nt, float* g2, int64_t R, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
-hipError_t launch_step_bump(int32_t* step, hipStream_t s);
+// step[0] += gaussians, step[1] += poses (the two update counters)
+hipError_t launch_step_bump(int32_t* step, int gaussians, int poses, hipStream_t s, const uint32_t* flags = nullptr);
+// pout = Exp(xi) pin per view (device [V][16], [V][6]; may alias)
+hipError_t launch_pose_retract(int V, const float* pin, const float* xi, float* pout, hipStream_t s);
+// out = J_l(xi)^T g per view (device [V][6] each)
+hipError_t launch_pose_tangent_grad(int V, const float* xi, const float* g, float* out, hipStream_t s);
 hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* lines, uint32_t* nt, int64_t n,
                              hipStream_t s);
 
-// zero_g2: also clear each visible record's gradient sums (mapping step)
+// zero_g2: also clear each visible record's gradient sums (mapping step);
+// flags (nullable, device u32): OR-ed with kFlagNonFinite when a mean,
+// log-scale, quaternion or opacity logit, or the colour of a visible record,
+// is not finite
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
-                                 bool zero_g2, hipStream_t s);
+                                 bool zero_g2, hipStream_t s, uint32_t* flags = nullptr);
 hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const float* poses, const Records& rec,
                                  const float* g2, Grads G, int accumulate, double* pose_part, int64_t pose_blocks,
                                  hipStream_t s);
 hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, int64_t pose_blocks,
                                 const double* rp_acc, float rp_weight, float* dL_dpose, hipStream_t s);
+
+// Clears the scalars block (all but kSticky) and the chained-scan status
+// words; enqueued first in every pass that bins, before the projection, whose
+// non-finite check already writes kFlags.
+hipError_t launch_status_clear(const Layout& L, char* base, hipStream_t s);
 
 // Binning: records -> sorted pair values and tile ranges.  All sizes bounded by
 // the layout; counts live on the device in the scalars block.
@@ -275,9 +291,10 @@ hipError_t launch_order_tiles(const ViewTable& vt, const ViewTable& vtf, const u
 // loss_out [1 + 4V]: total, then (Lc, Ld, Lr, Ls) per view; ssim_part (nullable)
 // holds per-(channel, SSIM tile) sums of the SSIM map, channel-major
 // view_tot: device double [V] scratch
+// scal (nullable): the scalars block; kFlags is then OR-ed into kSticky
 hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc,
                               const double* ssim_part, float w_color, float w_depth, float w_reproj, float w_ssim,
-                              float* loss_out, double* view_tot, hipStream_t s);
+                              float* loss_out, double* view_tot, hipStream_t s, uint32_t* scal = nullptr);
 
 // SSIM (mapping loss, Sec. 3.4) of planar colour images img against ref.
 // part: device float [9 * n_pix] scratch (per pixel and channel: the SSIM map's
@@ -327,10 +344,10 @@ struct AdamIO {
     const int32_t* step_in;
     int32_t* step_out;
 };
-// pruning: keep Gaussians with opacity logit >= logit_tau, in order; scratch
+// pruning: keep Gaussians with opacity logit >= logit_tau (compared in FP64), in order; scratch
 // u32 flag[n], off[n], bsum[scan_bsum_entries(n)], total[1]; n_out device
 // int64 = kept count; adam (nullable m_in) re-laid out for the kept ones
-hipError_t launch_prune(const Params& in, int K3, float logit_tau, GaussOut out, const AdamIO* adam, int V,
+hipError_t launch_prune(const Params& in, int K3, double logit_tau, GaussOut out, const AdamIO* adam, int V,
                         uint32_t* flag, uint32_t* off, uint32_t* bsum, uint32_t* total, int64_t* n_out,
                         hipStream_t s);
 // densification: append a Gaussian for every selected pixel after the n
@@ -338,7 +355,7 @@ hipError_t launch_prune(const Params& in, int K3, float logit_tau, GaussOut out,
 // now held, Gaussians the selection asked for); scratch as for pruning over
 // the n_pix pixels
 hipError_t launch_densify(const ViewTable& vt, const float* poses, const float* alpha, const float* tc,
-                          const float* td, float gamma, int all_pixels, GaussOut g, int n, int K, int64_t capacity,
+                          const float* td, double gamma, int all_pixels, GaussOut g, int n, int K, int64_t capacity,
                           const AdamIO* adam, uint32_t* flag, uint32_t* off, uint32_t* bsum, uint32_t* total,
                           int64_t* counts, hipStream_t s);
 
@@ -348,9 +365,13 @@ struct AdamGroups {
     int64_t cnt[5];
     float lr[5];
 };
+// The updates (and launch_step_bump) do nothing when *flags (the step's
+// kFlags word; nullable = always update) is non-zero: a step whose binning
+// overflowed or read a non-finite parameter leaves parameters, poses, moments
+// and the step counter as they were.
 hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, float b1, float b2, float eps,
-                       int bump_step, hipStream_t s);
+                       const uint32_t* flags, hipStream_t s);
 hipError_t launch_pose_update(int V, float* poses, const float* dpose, float* m, float* v, int32_t* step, float lr,
-                              float b1, float b2, float eps, int bump_step, hipStream_t s);
+                              float b1, float b2, float eps, const uint32_t* flags, hipStream_t s);
 
 }  // namespace gs

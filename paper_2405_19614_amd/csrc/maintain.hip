@@ -18,10 +18,14 @@ namespace {
 
 constexpr float kShC0 = 0.28209479177387814f;   // Y_00 of the real orthonormal SH basis
 
-__global__ void prune_flags_kernel(const float* __restrict__ opl, int64_t n, float logit_tau,
+// sigmoid(logit) < tau  <=>  logit < logit(tau) (sigmoid is increasing); the
+// FP32 logit is compared with logit(tau) in FP64, so the decision is that of
+// the real numbers for every FP32 logit (none lies within FP64 rounding of
+// logit(tau) unless it equals it)
+__global__ void prune_flags_kernel(const float* __restrict__ opl, int64_t n, double logit_tau,
                                    uint32_t* __restrict__ flag) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        flag[i] = (opl[i] >= logit_tau) ? 1u : 0u;
+        flag[i] = ((double)opl[i] >= logit_tau) ? 1u : 0u;
 }
 
 __global__ void prune_scatter_kernel(Params in, int K3, GaussOut out, const uint32_t* __restrict__ flag,
@@ -54,7 +58,10 @@ __global__ void prune_adam_kernel(AdamIO a, int64_t n, int K3, int V, const uint
             a.m_out[pn + e] = a.m_in[po + e];
             a.v_out[pn + e] = a.v_in[po + e];
         }
-        if (a.step_out != a.step_in) *a.step_out = *a.step_in;
+        if (a.step_out != a.step_in) {
+            a.step_out[0] = a.step_in[0];   // both update counters (Gaussians, poses)
+            a.step_out[1] = a.step_in[1];
+        }
     }
     for (int64_t i = gid; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         if (!flag[i]) continue;
@@ -87,11 +94,13 @@ __device__ __forceinline__ int view_of_pixel(const ViewTable& vt, int64_t p) {
     return lo;
 }
 
+// alpha <= gamma with the FP32 alpha compared against gamma in FP64 (gamma is
+// the caller's double, e.g. 0.99 itself rather than its FP32 rounding)
 __global__ void densify_flags_kernel(ViewTable vt, const float* __restrict__ alpha, const float* __restrict__ td,
-                                     float gamma, int all_pixels, uint32_t* __restrict__ flag) {
+                                     double gamma, int all_pixels, uint32_t* __restrict__ flag) {
     const int64_t np = vt.n_pix;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x)
-        flag[p] = (td[p] > 0.f && (all_pixels || alpha[p] <= gamma)) ? 1u : 0u;
+        flag[p] = (td[p] > 0.f && (all_pixels || (double)alpha[p] <= gamma)) ? 1u : 0u;
 }
 
 __global__ void densify_write_kernel(ViewTable vt, const float* __restrict__ poses, const float* __restrict__ tc,
@@ -149,7 +158,10 @@ __global__ void densify_adam_kernel(AdamIO a, int64_t n, int K3, int V, const in
             a.m_out[pn + e] = a.m_in[po + e];
             a.v_out[pn + e] = a.v_in[po + e];
         }
-        if (a.step_out != a.step_in) *a.step_out = *a.step_in;
+        if (a.step_out != a.step_in) {
+            a.step_out[0] = a.step_in[0];   // both update counters (Gaussians, poses)
+            a.step_out[1] = a.step_in[1];
+        }
     }
     for (int64_t j = gid; j < capacity; j += (int64_t)gridDim.x * blockDim.x) {
         if (j >= nn) break;
@@ -173,7 +185,7 @@ unsigned grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_prune(const Params& in, int K3, float logit_tau, GaussOut out, const AdamIO* adam, int V,
+hipError_t launch_prune(const Params& in, int K3, double logit_tau, GaussOut out, const AdamIO* adam, int V,
                         uint32_t* flag, uint32_t* off, uint32_t* bsum, uint32_t* total, int64_t* n_out,
                         hipStream_t s) {
     const int64_t n = in.n;
@@ -187,7 +199,7 @@ hipError_t launch_prune(const Params& in, int K3, float logit_tau, GaussOut out,
 }
 
 hipError_t launch_densify(const ViewTable& vt, const float* poses, const float* alpha, const float* tc,
-                          const float* td, float gamma, int all_pixels, GaussOut g, int n, int K, int64_t capacity,
+                          const float* td, double gamma, int all_pixels, GaussOut g, int n, int K, int64_t capacity,
                           const AdamIO* adam, uint32_t* flag, uint32_t* off, uint32_t* bsum, uint32_t* total,
                           int64_t* counts, hipStream_t s) {
     const int64_t np = vt.n_pix;

@@ -19,11 +19,12 @@ constexpr int kProjBlock = 256;
 // One thread per Gaussian, looping over the views: the parameters come from
 // HBM once and stay in the thread's cache lines for the other views.
 __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt, Params P, const float* poses,
-                                                                    Records rec, bool zero_g2) {
+                                                                    Records rec, bool zero_g2, uint32_t* flags) {
     const int g = blockIdx.x * kProjBlock + threadIdx.x;
     if (g >= P.n) return;
     GPrep gp;
     gauss_prep(P, g, gp);
+    bool bad = !gp.finite;
     uint64_t vm = 0;
     for (int v = 0; v < vt.V; v++) {
         const ViewInfo& vi = vt.v[v];
@@ -54,8 +55,14 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
         }
         rec.nt[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
         vm |= 1ull << v;
+        bad |= pr.colbad;
     }
     rec.vmask[g] = vm;
+    // one atomic per wavefront that read a non-finite parameter, from its
+    // first active lane
+    const uint64_t bad_lanes = __ballot(bad);
+    const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
+    if (flags && bad_lanes != 0ull && (int)(threadIdx.x & 63) == first) atomicOr(flags, kFlagNonFinite);
 }
 
 template <int CTRL, int ROWM, int BANKM>
@@ -427,9 +434,10 @@ __global__ __launch_bounds__(256) void pose_finalize_kernel(const double* part, 
 }  // namespace
 
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
-                                 bool zero_g2, hipStream_t s) {
+                                 bool zero_g2, hipStream_t s, uint32_t* flags) {
     if (P.n == 0) return hipSuccess;
-    preprocess_fwd_kernel<<<(P.n + kProjBlock - 1) / kProjBlock, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2);
+    preprocess_fwd_kernel<<<(P.n + kProjBlock - 1) / kProjBlock, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2,
+                                                                                       flags);
     return hipGetLastError();
 }
 

@@ -170,16 +170,19 @@ __global__ __launch_bounds__(256) void loss_view_kernel(ViewTable vt, const doub
     }
 }
 
-__global__ void loss_total_kernel(int V, const double* tot, float* out) {
+// the step's total loss; also folds the step's status bits into the sticky word
+__global__ void loss_total_kernel(int V, const double* tot, float* out, uint32_t* scal) {
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int v = 0; v < V; v++) t += tot[v];
         out[0] = (float)(t / (double)V);
+        if (scal) scal[kSticky] |= scal[kFlags];
     }
 }
 
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                            float eps, const int32_t* step) {
+                            float eps, const int32_t* step, const uint32_t* flags) {
+    if (flags && *flags != 0u) return;   // the step is invalid: leave everything as it was
     const float t = (float)(*step + 1);
     const float c1 = 1.f / (1.f - powf(b1, t));
     const float c2 = 1.f / (1.f - powf(b2, t));
@@ -193,23 +196,10 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_
     }
 }
 
-__global__ void pose_update_kernel(int V, float* poses, const float* dpose, float* m, float* v, float lr, float b1,
-                                   float b2, float eps, const int32_t* step) {
-    const int k = threadIdx.x;
-    if (k >= V) return;
-    const double t = (double)(*step + 1);
-    double xi[6];
-    for (int i = 0; i < 6; i++) {
-        const float gi = dpose[6 * k + i];
-        const float mi = b1 * m[6 * k + i] + (1.f - b1) * gi;
-        const float vi = b2 * v[6 * k + i] + (1.f - b2) * gi * gi;
-        m[6 * k + i] = mi;
-        v[6 * k + i] = vi;
-        const double mh = (double)mi / (1.0 - pow((double)b1, t));
-        const double vh = (double)vi / (1.0 - pow((double)b2, t));
-        xi[i] = -(double)lr * mh / (sqrt(vh) + (double)eps);
-    }
-    // Exp of the twist (v, w): R by Rodrigues, translation V(w) v
+// T_out = Exp(xi) T_in for the twist xi = (v, w) (translation first): R by
+// Rodrigues, translation V(w) v; FP64 arithmetic, the bottom row (0 0 0 1)
+// written as such.  T_in and T_out may alias.
+__device__ void se3_exp_left(const double xi[6], const float* Tin, float* Tout) {
     const double wx = xi[3], wy = xi[4], wz = xi[5];
     const double th2 = wx * wx + wy * wy + wz * wz, th = sqrt(th2);
     double A, B, Cc;
@@ -234,19 +224,95 @@ __global__ void pose_update_kernel(int V, float* poses, const float* dpose, floa
     }
     double tr[3];
     for (int r = 0; r < 3; r++) tr[r] = Vm[3 * r] * xi[0] + Vm[3 * r + 1] * xi[1] + Vm[3 * r + 2] * xi[2];
-    float* P = poses + 16 * k;
     double old[12];
-    for (int i = 0; i < 12; i++) old[i] = P[i];
+    for (int i = 0; i < 12; i++) old[i] = Tin[i];
     for (int r = 0; r < 3; r++) {
         for (int c = 0; c < 4; c++) {
-            double s = R[3 * r] * old[c] + R[3 * r + 1] * old[4 + c] + R[3 * r + 2] * old[8 + c];
-            if (c == 3) s += tr[r];
-            P[4 * r + c] = (float)s;
+            double sum = R[3 * r] * old[c] + R[3 * r + 1] * old[4 + c] + R[3 * r + 2] * old[8 + c];
+            if (c == 3) sum += tr[r];
+            Tout[4 * r + c] = (float)sum;
         }
     }
+    Tout[12] = 0.f; Tout[13] = 0.f; Tout[14] = 0.f; Tout[15] = 1.f;
 }
 
-__global__ void step_bump_kernel(int32_t* step) { *step += 1; }
+// step[1] counts the pose updates (step[0] the Gaussian ones): separate
+// bias corrections, as two optimisers would keep
+__global__ void pose_update_kernel(int V, float* poses, const float* dpose, float* m, float* v, float lr, float b1,
+                                   float b2, float eps, const int32_t* step, const uint32_t* flags) {
+    const int k = threadIdx.x;
+    if (k >= V) return;
+    if (flags && *flags != 0u) return;
+    const double t = (double)(step[1] + 1);
+    double xi[6];
+    for (int i = 0; i < 6; i++) {
+        const float gi = dpose[6 * k + i];
+        const float mi = b1 * m[6 * k + i] + (1.f - b1) * gi;
+        const float vi = b2 * v[6 * k + i] + (1.f - b2) * gi * gi;
+        m[6 * k + i] = mi;
+        v[6 * k + i] = vi;
+        const double mh = (double)mi / (1.0 - pow((double)b1, t));
+        const double vh = (double)vi / (1.0 - pow((double)b2, t));
+        xi[i] = -(double)lr * mh / (sqrt(vh) + (double)eps);
+    }
+    float* P = poses + 16 * k;
+    se3_exp_left(xi, P, P);
+}
+
+// poses_out[k] = Exp(xi[k]) poses_in[k]
+__global__ void pose_retract_kernel(int V, const float* pin, const float* xi, float* pout) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= V) return;
+    double x[6];
+    for (int i = 0; i < 6; i++) x[i] = xi[6 * k + i];
+    float T[16];
+    for (int i = 0; i < 16; i++) T[i] = pin[16 * k + i];
+    se3_exp_left(x, T, pout + 16 * k);
+}
+
+// out[k] = J_l(xi[k])^T g[k]: the gradient with respect to xi of L(Exp(xi) T)
+// from the left-perturbation gradient g at Exp(xi) T, since
+// Exp(xi + e) = Exp(J_l(xi) e) Exp(xi) to first order.  J_l is summed from its
+// series sum_n ad(xi)^n / (n + 1)!, ad(xi) = [[w^, v^], [0, w^]]; 40 terms in
+// FP64 (the remainder is below 1e-16 relative for |xi| <= 4).
+__global__ void pose_tangent_grad_kernel(int V, const float* xi, const float* g, float* out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= V) return;
+    const double vx = xi[6 * k], vy = xi[6 * k + 1], vz = xi[6 * k + 2];
+    const double wx = xi[6 * k + 3], wy = xi[6 * k + 4], wz = xi[6 * k + 5];
+    double ad[36];
+    for (int i = 0; i < 36; i++) ad[i] = 0.0;
+    const double wh[9] = {0, -wz, wy, wz, 0, -wx, -wy, wx, 0};
+    const double vh[9] = {0, -vz, vy, vz, 0, -vx, -vy, vx, 0};
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            ad[6 * r + c] = wh[3 * r + c];
+            ad[6 * r + 3 + c] = vh[3 * r + c];
+            ad[6 * (r + 3) + 3 + c] = wh[3 * r + c];
+        }
+    // J^T g = sum_n (ad^T)^n g / (n + 1)!: iterate the vector u_n = ad^T u_{n-1} / (n + 1)
+    double u[6], acc[6];
+    for (int i = 0; i < 6; i++) u[i] = acc[i] = g[6 * k + i];
+    for (int n = 1; n <= 40; n++) {
+        double w[6];
+        for (int i = 0; i < 6; i++) {
+            double sum = 0.0;
+            for (int j = 0; j < 6; j++) sum += ad[6 * j + i] * u[j];
+            w[i] = sum / (double)(n + 1);
+        }
+        for (int i = 0; i < 6; i++) {
+            u[i] = w[i];
+            acc[i] += w[i];
+        }
+    }
+    for (int i = 0; i < 6; i++) out[6 * k + i] = (float)acc[i];
+}
+
+__global__ void step_bump_kernel(int32_t* step, int gaussians, int poses, const uint32_t* flags) {
+    if (flags && *flags != 0u) return;
+    if (gaussians) step[0] += 1;
+    if (poses) step[1] += 1;
+}
 
 }  // namespace
 
@@ -299,16 +365,15 @@ hipError_t launch_reproj_finalize(const ViewTable& vt, const double* acc, float 
 
 hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, const double* rp_acc,
                               const double* ssim_part, float w_color, float w_depth, float w_reproj, float w_ssim,
-                              float* loss_out, double* view_tot, hipStream_t s) {
+                              float* loss_out, double* view_tot, hipStream_t s, uint32_t* scal) {
     loss_view_kernel<<<vt.V, 256, 0, s>>>(vt, tile_part, rp_acc, ssim_part, w_color, w_depth, w_reproj, w_ssim,
                                           loss_out, view_tot);
-    loss_total_kernel<<<1, 64, 0, s>>>(vt.V, view_tot, loss_out);
+    loss_total_kernel<<<1, 64, 0, s>>>(vt.V, view_tot, loss_out, scal);
     return hipGetLastError();
 }
 
 hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, float b1, float b2, float eps,
-                       int bump_step, hipStream_t s) {
-    (void)bump_step;
+                       const uint32_t* flags, hipStream_t s) {
     int64_t off = 0;
     for (int i = 0; i < 5; i++) {
         const int64_t n = ag.cnt[i];
@@ -316,7 +381,7 @@ hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, 
             int64_t b = (n + 255) / 256;
             if (b > 16384) b = 16384;
             adam_kernel<<<(unsigned)b, 256, 0, s>>>(ag.p[i], ag.g[i], m + off, v + off, n, ag.lr[i], b1, b2, eps,
-                                                    step);
+                                                    step, flags);
         }
         off += n;
     }
@@ -324,14 +389,25 @@ hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, 
 }
 
 hipError_t launch_pose_update(int V, float* poses, const float* dpose, float* m, float* v, int32_t* step, float lr,
-                              float b1, float b2, float eps, int bump_step, hipStream_t s) {
-    (void)bump_step;
-    pose_update_kernel<<<1, kMaxViews, 0, s>>>(V, poses, dpose, m, v, lr, b1, b2, eps, step);
+                              float b1, float b2, float eps, const uint32_t* flags, hipStream_t s) {
+    pose_update_kernel<<<1, kMaxViews, 0, s>>>(V, poses, dpose, m, v, lr, b1, b2, eps, step, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_step_bump(int32_t* step, hipStream_t s) {
-    step_bump_kernel<<<1, 1, 0, s>>>(step);
+hipError_t launch_step_bump(int32_t* step, int gaussians, int poses, hipStream_t s, const uint32_t* flags) {
+    step_bump_kernel<<<1, 1, 0, s>>>(step, gaussians, poses, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_retract(int V, const float* pin, const float* xi, float* pout, hipStream_t s) {
+    if (V <= 0) return hipSuccess;
+    pose_retract_kernel<<<1, kMaxViews, 0, s>>>(V, pin, xi, pout);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_tangent_grad(int V, const float* xi, const float* g, float* out, hipStream_t s) {
+    if (V <= 0) return hipSuccess;
+    pose_tangent_grad_kernel<<<1, kMaxViews, 0, s>>>(V, xi, g, out);
     return hipGetLastError();
 }
 

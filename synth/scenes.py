@@ -354,7 +354,10 @@ def c5(n: int = 3_000_000, views: int = 16, width: int = 1200, height: int = 680
     cam = _scaled_cam(1200, 680, 600.0, width, height)
     traj = _circle_trajectory(rng, traj_len, step=0.05)
     T_true = traj[window:window + views]
-    return Scene("c5", *p, 3, [cam] * views, T_true.astype(F32), T_true.astype(F32),
+    # the estimated poses the mapping holds fixed: perturbed as in c2, so the
+    # rendering loss against the true-pose targets is not zero
+    T_est = np.stack([perturb_pose(T, rng) for T in T_true])
+    return Scene("c5", *p, 3, [cam] * views, T_est.astype(F32), T_true.astype(F32),
                  1.0, 0.1, 0.0, 2.0, extra={"window": window, "trajectory": traj.astype(F32)})
 
 

@@ -41,7 +41,7 @@ def test_prune_matches_oracle_bit_exact(ctx, sh):
     m = rng.standard_normal(n * (11 + 3 * K) + 6 * V).astype(np.float32)
     v = rng.random(m.shape).astype(np.float32)
     t = lambda a: torch.tensor(a, device="cuda")
-    step = torch.tensor([7], dtype=torch.int32, device="cuda")
+    step = torch.tensor([7, 2], dtype=torch.int32, device="cuda")
     out, (m2, v2, _) = ctx.prune(_dev(p, sh), 0.3, adam=(t(m), t(v), step), V=V)
     kept, idx = O.prune(p, 0.3)
     assert out.n == len(idx)
@@ -86,7 +86,7 @@ def test_densify_matches_oracle(ctx, sh, all_px):
     K = 1 if sh < 0 else (sh + 1) ** 2
     rng = np.random.default_rng(7)
     m = rng.standard_normal(500 * (11 + 3 * K) + 6 * 3).astype(np.float32)
-    step = torch.tensor([3], dtype=torch.int32, device="cuda")
+    step = torch.tensor([3, 1], dtype=torch.int32, device="cuda")
     cap = 500 + len(where) + 10
     out, (held, asked), (m2, _, _) = ctx.densify(_dev(p, sh), cap, cams, P, t(alpha), t(col), t(dep), gamma=0.5,
                                                  all_pixels=all_px, adam=(t(m), t(m), step))
@@ -155,3 +155,56 @@ def test_first_frame_densify_then_mapping(ctx):
     pruned, _ = ctx.prune(st.g, 0.005)
     o = torch.sigmoid(st.g.opacity_logits).cpu().numpy()
     assert pruned.n == int((~(o < 0.005)).sum())
+
+
+@pytest.mark.parametrize("tau", [0.005, 0.3, 0.7, 0.99, 1e-7])
+def test_prune_threshold_exact_at_the_boundary(ctx, tau):
+    """FP32 logits on both sides of logit(tau) (the floats next to it, and a
+    few ulps further): the GPU keeps exactly the Gaussians whose FP64 opacity
+    is >= tau (the paper's tau = 0.005 among the thresholds)."""
+    lt = np.log(tau) - np.log1p(-tau)
+    f = np.float32(lt)
+    cand = [f]
+    up, dn = f, f
+    for _ in range(3):
+        up = np.nextafter(up, np.float32(np.inf))
+        dn = np.nextafter(dn, np.float32(-np.inf))
+        cand += [up, dn]
+    logits = np.array(cand, np.float32)
+    n = len(logits)
+    p = _params(n, 9)
+    p["opacity_logits"] = logits
+    out, _ = ctx.prune(_dev(p, -1), tau)
+    kept, idx = O.prune(p, tau)
+    print(f"[prune boundary tau={tau}] logit(tau)={lt:.9g} kept {len(idx)}/{n}", flush=True)
+    assert 0 < len(idx) < n
+    np.testing.assert_array_equal(out.opacity_logits.cpu().numpy(), logits[idx])
+
+
+@pytest.mark.parametrize("gamma", [0.99, 0.5, 0.3])
+def test_densify_threshold_exact_at_the_boundary(ctx, gamma):
+    """Rendered alphas at float(gamma) and the floats next to it: a pixel is
+    densified exactly when its FP32 alpha is <= gamma in FP64."""
+    import paper_2405_19614_amd as gs
+    f = np.float32(gamma)
+    vals = [f]
+    up, dn = f, f
+    for _ in range(3):
+        up = np.nextafter(up, np.float32(np.inf))
+        dn = np.nextafter(dn, np.float32(-np.inf))
+        vals += [up, dn]
+    W = len(vals)
+    cams = [gs.Camera(W, 1, 50.0, 50.0, W / 2, 0.5)]
+    alpha = np.array(vals, np.float32)
+    col = np.full(3 * W, 0.5, np.float32)
+    dep = np.full(W, 2.0, np.float32)
+    T = np.eye(4)
+    t = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda")
+    p = _params(4, 10)
+    new, where = O.densify(cams, [T], alpha, col, dep, gamma, False)
+    out, (held, asked), _ = ctx.densify(_dev(p, -1), 4 + W, cams, t(T.reshape(1, 16)), t(alpha), t(col), t(dep),
+                                        gamma=gamma)
+    print(f"[densify boundary gamma={gamma}] oracle new {len(where)} gpu new {held - 4}", flush=True)
+    assert 0 < len(where) < W
+    assert held == asked == 4 + len(where)
+    np.testing.assert_allclose(out.means[4:].cpu().numpy(), new["means"], rtol=1e-6, atol=1e-6)

@@ -121,7 +121,7 @@ def test_adam_and_pose_update_match_oracle(ctx):
         print(f"  {nm}: well-determined {sure.mean():.3f}")
         np.testing.assert_allclose(got[sure], d_ref[sure], atol=2e-6 * lr_of[nm] * 1e3)
         assert np.all(np.abs(got) <= lr_of[nm] * (1 + 1e-4) + 2e-7 * np.maximum(1.0, np.abs(p0)))
-    assert int(st.adam_step.item()) == 1
+    assert int(st.adam_step[0].item()) == 1
     # pose: T <- Exp(-lr mhat / (sqrt(vhat) + eps)) T with the oracle's pose gradient
     Pn = st.poses.cpu().numpy().reshape(s.V, 4, 4).astype(np.float64)
     for v in range(s.V):
@@ -182,7 +182,7 @@ def test_graph_replay_with_updates_tracks_eager(ctx):
             assert (diff > 1e-5).mean() < 1e-3, nm
             assert diff.max() <= 6 * 2.5e-3, nm
         assert torch.allclose(e.poses, r.poses, atol=1e-6)
-        assert int(r.adam_step.item()) == k + 1
+        assert int(r.adam_step[0].item()) == k + 1
 
 
 def test_pose_gradient_vs_gpu_finite_differences(ctx):
@@ -255,3 +255,74 @@ def test_alternating_joint_refinement_converges(ctx):
     assert st.status()["flags"] == 0
     assert loss1 < loss0
     assert t1 < 0.7 * t0 and r1 < r0
+
+
+@pytest.mark.parametrize("sh_degree", [-1, 2])
+def test_adam_multistep_matches_oracle_every_element(ctx, sh_degree):
+    """gs_adam_update on fixed seeded gradients for six updates: two pose-only
+    (the Fusion Bridge phase), three Gaussian-only (the mapping phase), one of
+    both, with non-default betas and epsilon.  Every parameter, moment and
+    pose equals the oracle's iterated Adam (each group with its own update
+    count) and SE(3) exponential."""
+    import paper_2405_19614_amd as gs
+    rng = np.random.default_rng(60 + sh_degree)
+    n, V = 3000, 3
+    K = 1 if sh_degree < 0 else (sh_degree + 1) ** 2
+    shapes = {"means": (n, 3), "log_scales": (n, 3), "quats": (n, 4), "opacity_logits": (n,),
+              "colors": (n, 3) if sh_degree < 0 else (n, K, 3)}
+    p = {k: rng.standard_normal(v) for k, v in shapes.items()}
+    lr = {"means": 1e-3, "log_scales": 2e-3, "quats": 3e-3, "opacity_logits": 4e-2, "colors": 5e-3}
+    b1, b2, eps, lr_pose = 0.8, 0.95, 1e-6, 2e-3
+    opts_kw = dict(lr_means=lr["means"], lr_log_scales=lr["log_scales"], lr_quats=lr["quats"],
+                   lr_opacity=lr["opacity_logits"], lr_colors=lr["colors"], lr_pose=lr_pose, adam_b1=b1,
+                   adam_b2=b2, adam_eps=eps)
+    t32 = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda").contiguous()
+    g = gs.Gaussians(*(t32(p[k]) for k in GRAD_NAMES), sh_degree)
+    s = scenes.c3(n=10, views=V, width=16, height=16, seed=61)
+    poses = t32(np.asarray(s.poses, np.float32).reshape(V, 16))
+    na = n * (11 + 3 * K) + 6 * V
+    m = torch.zeros(na, device="cuda")
+    v = torch.zeros(na, device="cuda")
+    step = torch.zeros(2, dtype=torch.int32, device="cuda")
+    # oracle state (FP64 from the same FP32 start)
+    P = {k: np.asarray(p[k], np.float32).astype(np.float64).reshape(-1) for k in GRAD_NAMES}
+    M = {k: np.zeros_like(P[k]) for k in GRAD_NAMES}
+    Vv = {k: np.zeros_like(P[k]) for k in GRAD_NAMES}
+    Tp = [np.asarray(s.poses[i], np.float32).astype(np.float64) for i in range(V)]
+    Mp, Vp = np.zeros((V, 6)), np.zeros((V, 6))
+    tg = tp = 0
+    phases = [(False, True), (False, True), (True, False), (True, False), (True, False), (True, True)]
+    for k, (upd_g, upd_p) in enumerate(phases):
+        grads = {nm: rng.standard_normal(shapes[nm]).astype(np.float32) for nm in GRAD_NAMES}
+        dpose = rng.standard_normal((V, 6)).astype(np.float32) * 0.1
+        gg = gs.Gaussians(*(t32(grads[nm]) for nm in GRAD_NAMES), sh_degree)
+        opts = gs.StepOptions(update_gaussians=upd_g, update_poses=upd_p, **opts_kw)
+        ctx.adam_update(g, gg, (m, v, step), opts, poses=poses, dpose=t32(dpose))
+        if upd_g:
+            tg += 1
+            for nm in GRAD_NAMES:
+                d, M[nm], Vv[nm] = O.adam_step(P[nm], grads[nm].astype(np.float64).reshape(-1), M[nm], Vv[nm], tg,
+                                               lr[nm], b1, b2, eps)
+                P[nm] = P[nm] + d
+        if upd_p:
+            tp += 1
+            for i in range(V):
+                d, Mp[i], Vp[i] = O.adam_step(np.zeros(6), dpose[i].astype(np.float64), Mp[i], Vp[i], tp, lr_pose,
+                                              b1, b2, eps)
+                Tp[i] = O.se3_exp(d) @ Tp[i]
+        torch.cuda.synchronize()
+        print(f"[adam multistep sh={sh_degree}] update {k + 1}: gaussians={upd_g} poses={upd_p}", flush=True)
+        assert step.tolist() == [tg, tp]
+        off = 0
+        mm, vv = m.cpu().numpy(), v.cpu().numpy()
+        for nm in GRAD_NAMES:
+            got = getattr(g, nm).cpu().numpy().astype(np.float64).reshape(-1)
+            np.testing.assert_allclose(got, P[nm], rtol=0, atol=2e-5 * lr[nm] + 1e-6 * np.abs(P[nm]).max(),
+                                       err_msg=nm)
+            cnt = P[nm].size
+            np.testing.assert_allclose(mm[off:off + cnt], M[nm], rtol=1e-5, atol=1e-7, err_msg=nm)
+            np.testing.assert_allclose(vv[off:off + cnt], Vv[nm], rtol=1e-5, atol=1e-7, err_msg=nm)
+            off += cnt
+        np.testing.assert_allclose(mm[off:].reshape(V, 6), Mp, rtol=1e-5, atol=1e-8)
+        np.testing.assert_allclose(vv[off:].reshape(V, 6), Vp, rtol=1e-5, atol=1e-9)
+        np.testing.assert_allclose(poses.cpu().numpy().reshape(V, 4, 4), np.stack(Tp), atol=2e-6)

@@ -825,3 +825,36 @@ def test_reverse_mode_vs_central_fd_every_branch(oracle, seed, sh):
         lm = _loss(oracle, g, cam, oracle.se3_exp(-xi) @ T, dC, dD, dA)
         fd = (lp - lm) / 2e-6
         assert abs(fd - gr["pose"][j]) <= 1e-6 * max(1.0, abs(fd)) + 1e-7, (j, fd, gr["pose"][j])
+
+
+def test_se3_left_jacobian_vs_expm_logm(oracle):
+    """J_l(xi) e = Log(Exp(xi + e) Exp(xi)^-1) to first order: central
+    differences of scipy's matrix exponential and logarithm.  Also J_l(0) = I
+    and J_l(xi) xi = xi (ad(xi) xi = 0)."""
+    from scipy.linalg import expm, logm
+    rng = np.random.default_rng(8)
+
+    def hat6(x):
+        M = np.zeros((4, 4))
+        M[:3, :3] = oracle.hat(x[3:])
+        M[:3, 3] = x[:3]
+        return M
+
+    def vee(M):
+        return np.array([M[0, 3], M[1, 3], M[2, 3], M[2, 1], M[0, 2], M[1, 0]])
+
+    np.testing.assert_allclose(oracle.se3_left_jacobian(np.zeros(6)), np.eye(6), atol=0)
+    for scale in (1e-3, 0.3, 1.2):
+        xi = rng.standard_normal(6) * scale
+        J = oracle.se3_left_jacobian(xi)
+        np.testing.assert_allclose(J @ xi, xi, atol=1e-13)
+        Einv = expm(-hat6(xi))
+        h = 1e-6
+        Jn = np.zeros((6, 6))
+        for k in range(6):
+            e = np.zeros(6)
+            e[k] = h
+            lp = vee(np.real(logm(expm(hat6(xi + e)) @ Einv)))
+            lm = vee(np.real(logm(expm(hat6(xi - e)) @ Einv)))
+            Jn[:, k] = (lp - lm) / (2 * h)
+        np.testing.assert_allclose(J, Jn, atol=1e-7)
