@@ -79,6 +79,83 @@ __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, flo
     }
 }
 
+// sum_l s[l] grad Y_l(x, y, z) for the basis of sh_basis (the gradient of each
+// polynomial with respect to (x, y, z) as free variables), without storing
+// the per-function gradients.
+template <int DEG>
+__device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const float* s, float* g) {
+    const float c1 = 0.48860251190291992f;
+    const float c2a = 1.0925484305920792f;
+    const float c2b = 0.31539156525252005f;
+    const float c2c = 0.54627421529603959f;
+    const float c3a = 0.59004358992664352f;
+    const float c3b = 2.8906114426405538f;
+    const float c3c = 0.45704579946446572f;
+    const float c3d = 0.37317633259011546f;
+    const float c3e = 1.4453057213202769f;
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if (DEG >= 1) {
+        gy -= c1 * s[1];
+        gz += c1 * s[2];
+        gx -= c1 * s[3];
+    }
+    if (DEG >= 2) {
+        gx += c2a * y * s[4];                gy += c2a * x * s[4];
+        gy -= c2a * z * s[5];                gz -= c2a * y * s[5];
+        gx -= 2.f * c2b * x * s[6];          gy -= 2.f * c2b * y * s[6];   gz += 4.f * c2b * z * s[6];
+        gx -= c2a * z * s[7];                gz -= c2a * x * s[7];
+        gx += 2.f * c2c * x * s[8];          gy -= 2.f * c2c * y * s[8];
+    }
+    if (DEG >= 3) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        gx += -6.f * c3a * x * y * s[9];     gy += -3.f * c3a * (xx - yy) * s[9];
+        gx += c3b * y * z * s[10];           gy += c3b * x * z * s[10];    gz += c3b * x * y * s[10];
+        gx += 2.f * c3c * x * y * s[11];     gy += -c3c * (4.f * zz - xx - 3.f * yy) * s[11];
+        gz += -8.f * c3c * y * z * s[11];
+        gx += -6.f * c3d * x * z * s[12];    gy += -6.f * c3d * y * z * s[12];
+        gz += c3d * (6.f * zz - 3.f * xx - 3.f * yy) * s[12];
+        gx += -c3c * (4.f * zz - 3.f * xx - yy) * s[13];                   gy += 2.f * c3c * x * y * s[13];
+        gz += -8.f * c3c * x * z * s[13];
+        gx += 2.f * c3e * x * z * s[14];     gy += -2.f * c3e * y * z * s[14];   gz += c3e * (xx - yy) * s[14];
+        gx += -3.f * c3a * (xx - yy) * s[15];                              gy += 6.f * c3a * x * y * s[15];
+    }
+    g[0] = gx; g[1] = gy; g[2] = gz;
+}
+
+// View-dependent colour of Gaussian g (SH, degree P.sh >= 0) seen from the
+// camera of world-to-camera pose T: dir = unit vector from the camera centre
+// C = -R^T t to the mean (mx, my, mz), colour = max(0, sum Y_lm(dir) k_lm +
+// 0.5) per channel.  The projection, its deferred colour pass and the
+// backward all evaluate the colour through this one function, so they agree
+// bit for bit (the clamp decisions included).
+__device__ __forceinline__ void sh_colour(const Params& P, int g, float mx, float my, float mz, const float* T,
+                                          float* dir, float& dirn, float* col, bool* cclamp, bool& colbad) {
+    // camera centre C = -R_cw^T t_cw
+    const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
+    const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
+    const float Cz = -(T[2] * T[3] + T[6] * T[7] + T[10] * T[11]);
+    const float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
+    dirn = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float idn = 1.f / dirn;
+    dir[0] = dx * idn; dir[1] = dy * idn; dir[2] = dz * idn;
+    float Y[16];
+    sh_basis<false>(P.sh, dir[0], dir[1], dir[2], Y, nullptr);
+    const int K = (P.sh + 1) * (P.sh + 1);
+    const float* sh = P.col + (int64_t)g * K * 3;
+    float acc[3] = {0.5f, 0.5f, 0.5f};
+    for (int l = 0; l < K; l++) {
+        acc[0] += Y[l] * sh[3 * l];
+        acc[1] += Y[l] * sh[3 * l + 1];
+        acc[2] += Y[l] * sh[3 * l + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        cclamp[k] = acc[k] < 0.f;
+        col[k] = fmaxf(acc[k], 0.f);
+    }
+    colbad = !__builtin_isfinite(acc[0] + acc[1] + acc[2]);
+}
+
 // Everything the projection of one Gaussian into one view computes; the
 // backward recomputes it instead of storing it.
 struct Proj {
@@ -227,30 +304,7 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
             o.cclamp[0] = o.cclamp[1] = o.cclamp[2] = false;
             o.colbad = !__builtin_isfinite(cp[0] + cp[1] + cp[2]);
         } else {
-            // camera centre C = -R_cw^T t_cw
-            const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
-            const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
-            const float Cz = -(T[2] * T[3] + T[6] * T[7] + T[10] * T[11]);
-            const float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
-            o.dirn = sqrtf(dx * dx + dy * dy + dz * dz);
-            const float idn = 1.f / o.dirn;
-            o.dir[0] = dx * idn; o.dir[1] = dy * idn; o.dir[2] = dz * idn;
-            float Y[16];
-            sh_basis<false>(P.sh, o.dir[0], o.dir[1], o.dir[2], Y, nullptr);
-            const int K = (P.sh + 1) * (P.sh + 1);
-            const float* sh = P.col + (int64_t)g * K * 3;
-            float acc[3] = {0.5f, 0.5f, 0.5f};
-            for (int l = 0; l < K; l++) {
-                acc[0] += Y[l] * sh[3 * l];
-                acc[1] += Y[l] * sh[3 * l + 1];
-                acc[2] += Y[l] * sh[3 * l + 2];
-            }
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                o.cclamp[k] = acc[k] < 0.f;
-                o.col[k] = fmaxf(acc[k], 0.f);
-            }
-            o.colbad = !__builtin_isfinite(acc[0] + acc[1] + acc[2]);
+            sh_colour(P, g, mx, my, mz, T, o.dir, o.dirn, o.col, o.cclamp, o.colbad);
         }
     }
 

@@ -16,53 +16,122 @@ namespace {
 
 constexpr int kProjBlock = 256;
 
+// Views per round of the deferred colour pass (and the LDS queue it uses:
+// kProjBlock x kProjChunk entries of 8 bytes).
+constexpr int kProjChunk = 16;
+
 // One thread per Gaussian, looping over the views: the parameters come from
 // HBM once and stay in the thread's cache lines for the other views.
+// RGB (SH < 0): the colour is written with the rest of the record.  SH: the
+// colour needs the Gaussian's (L+1)^2 x 3 coefficients, and only about a
+// tenth of the (view, Gaussian) pairs is visible, so evaluating it in the
+// view loop would run the SH code on nearly every wavefront for every view
+// (a lane is visible somewhere in it) and fetch the coefficients once per
+// visible view.  Instead each round of kProjChunk views queues its visible
+// pairs in LDS (geometry already written), and the block then evaluates the
+// colours of the queued pairs with every lane busy.
+template <int SH>
 __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt, Params P, const float* poses,
                                                                     Records rec, bool zero_g2, uint32_t* flags) {
+    constexpr bool DEFER = SH >= 0;
+    constexpr int kQ = DEFER ? kProjBlock * kProjChunk : 1;
+    __shared__ uint32_t s_ent[kQ];   // (thread << 8) | view
+    __shared__ float s_z[kQ];        // its depth
+    __shared__ int s_n;
+    const int lane = threadIdx.x & 63;
     const int g = blockIdx.x * kProjBlock + threadIdx.x;
-    if (g >= P.n) return;
+    const bool live = g < P.n;
     GPrep gp;
-    gauss_prep(P, g, gp);
+    gp.ok = false;
+    gp.finite = true;
+    if (live) gauss_prep(P, g, gp);
     bool bad = !gp.finite;
     uint64_t vm = 0;
-    for (int v = 0; v < vt.V; v++) {
-        const ViewInfo& vi = vt.v[v];
-        float T[12];
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int step = DEFER ? kProjChunk : vt.V;
+    for (int v0 = 0; v0 < vt.V; v0 += step) {
+        const int v1 = v0 + step < vt.V ? v0 + step : vt.V;
+        if (DEFER) {
+            if (threadIdx.x == 0) s_n = 0;
+            __syncthreads();
+        }
+        if (live) {
+            for (int v = v0; v < v1; v++) {
+                const ViewInfo& vi = vt.v[v];
+                float T[12];
 #pragma unroll
-        for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
-        Proj pr;
-        project_view<true>(P, g, gp, vi, T, pr);
-        const int64_t r = (int64_t)v * P.n + g;
-        if (!pr.valid) {
-            rec.nt[r] = 0u;
-            continue;
+                for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
+                Proj pr;
+                project_view<!DEFER>(P, g, gp, vi, T, pr);
+                const int64_t r = (int64_t)v * P.n + g;
+                if (pr.valid) {
+                    const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
+                    const uint32_t ty0 = (uint32_t)pr.y0 / vt.bh, ty1 = (uint32_t)pr.y1 / vt.bh;
+                    // the record line in 16-byte stores: base-2 conic with
+                    // log2(opacity) (the compositing kernels' form), colour and
+                    // depth, mean and rect, then (mapping step) the zeroed
+                    // gradient sums
+                    float4* q = reinterpret_cast<float4*>(rec.line + r);
+                    q[0] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
+                    if (!DEFER) {
+                        q[1] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);
+                        bad |= pr.colbad;
+                    }
+                    q[2] = make_float4(pr.u, pr.v, __uint_as_float((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16)),
+                                       __uint_as_float((uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16)));
+                    q[3] = zero;
+                    if (zero_g2) {
+                        q[4] = zero; q[5] = zero; q[6] = zero; q[7] = zero;
+                    }
+                    rec.nt[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                    vm |= 1ull << v;
+                } else {
+                    rec.nt[r] = 0u;
+                }
+                if (DEFER) {
+                    // queue the wavefront's visible pairs: one LDS atomic per wavefront
+                    const uint64_t bm = __ballot(pr.valid);
+                    if (bm != 0ull) {
+                        const int leader = __ffsll((unsigned long long)bm) - 1;
+                        int base = 0;
+                        if (lane == leader) base = atomicAdd(&s_n, __popcll(bm));
+                        base = __shfl(base, leader, 64);
+                        if (pr.valid) {
+                            const int k = base + __popcll(bm & ((1ull << lane) - 1ull));
+                            s_ent[k] = ((uint32_t)threadIdx.x << 8) | (uint32_t)v;
+                            s_z[k] = pr.p[2];
+                        }
+                    }
+                }
+            }
         }
-        const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
-        const uint32_t ty0 = (uint32_t)pr.y0 / vt.bh, ty1 = (uint32_t)pr.y1 / vt.bh;
-        // the record line in 16-byte stores: base-2 conic with log2(opacity)
-        // (the compositing kernels' form), colour and depth, mean and rect,
-        // then (mapping step) the zeroed gradient sums
-        float4* q = reinterpret_cast<float4*>(rec.line + r);
-        const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-        q[0] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
-        q[1] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);
-        q[2] = make_float4(pr.u, pr.v, __uint_as_float((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16)),
-                           __uint_as_float((uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16)));
-        q[3] = zero;
-        if (zero_g2) {
-            q[4] = zero; q[5] = zero; q[6] = zero; q[7] = zero;
+        if (DEFER) {
+            __syncthreads();
+            const int nq = s_n;
+            for (int i = threadIdx.x; i < nq; i += kProjBlock) {
+                const uint32_t e = s_ent[i];
+                const int v = (int)(e & 255u);
+                const int gg = blockIdx.x * kProjBlock + (int)(e >> 8);
+                float T[12];
+#pragma unroll
+                for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
+                const float* mu = P.means + 3 * (int64_t)gg;
+                float dir[3], dirn, col[3];
+                bool cclamp[3], cb;
+                sh_colour(P, gg, mu[0], mu[1], mu[2], T, dir, dirn, col, cclamp, cb);
+                bad |= cb;
+                reinterpret_cast<float4*>(rec.line + ((int64_t)v * P.n + gg))[1] =
+                    make_float4(col[0], col[1], col[2], s_z[i]);
+            }
+            __syncthreads();
         }
-        rec.nt[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-        vm |= 1ull << v;
-        bad |= pr.colbad;
     }
-    rec.vmask[g] = vm;
+    if (live) rec.vmask[g] = vm;
     // one atomic per wavefront that read a non-finite parameter, from its
     // first active lane
     const uint64_t bad_lanes = __ballot(bad);
     const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
-    if (flags && bad_lanes != 0ull && (int)(threadIdx.x & 63) == first) atomicOr(flags, kFlagNonFinite);
+    if (flags && bad_lanes != 0ull && lane == first) atomicOr(flags, kFlagNonFinite);
 }
 
 template <int CTRL, int ROWM, int BANKM>
@@ -103,34 +172,14 @@ __device__ __forceinline__ void block_zero(float* p, int64_t e0, int64_t e1) {
 constexpr int kBwdPer = kProjBwdSpan / kProjBlock;   // Gaussians each thread scans
 static_assert(kProjBwdSpan % kProjBlock == 0 && kProjBwdSpan <= 65536, "span of a backward block");
 
-// One block per span of kProjBwdSpan Gaussians.  The block first reads the
-// view masks the forward projection left (bit v: visible in view v); the
-// Gaussians visible in none get a zero gradient (or nothing, when
-// accumulating) and the others are packed, in increasing index order,
-// into a list that the block then walks 256 at a time.  Every lane of that
-// walk holds a Gaussian some view sees, so the per-view recomputation runs on
-// full wavefronts instead of on the few lanes a random 64 Gaussians leave
-// visible.  The per-Gaussian gradient is summed over views in registers; the
-// per-view pose 6-vector is summed over each wavefront (FP32), added to that
-// wavefront's FP64 slot, and the four slots are added at the end: a fixed
-// order, with no barrier inside the walk.
-// RGB colours: at most 128 VGPRs (four waves per SIMD; it fits without
-// spilling).  The SH variants keep the compiler's choice: capped, they spill.
-template <int SH>
-__global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_kernel(ViewTable vt, Params P, const float* poses,
-                                                                    const uint64_t* vmask, const float* g2, Grads G,
-                                                                    int accumulate, double* pose_part,
-                                                                    int pose_blocks) {
-    constexpr int K = SH < 0 ? 1 : (SH + 1) * (SH + 1);
-    __shared__ uint16_t s_loc[kProjBwdSpan];
-    __shared__ uint64_t s_mask[kProjBwdSpan];
-    __shared__ int s_cnt[kBwdPer][kProjBlock / 64];
-    __shared__ double s_pose[kProjBlock / 64][kMaxViews][6];
+// Pack the Gaussians of the span [g0, g0 + kProjBwdSpan) that some view sees
+// (view mask non-zero) into s_loc (offset in the span) and s_mask (their
+// masks), in increasing index order: the position of Gaussian g0 + threadIdx.x
+// + kProjBlock j is (j, wavefront, lane) order.  Returns their number (the
+// same in every thread).  Ends with a barrier.
+__device__ __forceinline__ int pack_visible(const Params& P, const uint64_t* vmask, int64_t g0, uint16_t* s_loc,
+                                            uint64_t* s_mask, int (*s_cnt)[kProjBlock / 64]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t g0 = (int64_t)blockIdx.x * kProjBwdSpan;
-    const int V = vt.V;
-
-    // view mask of Gaussian g0 + threadIdx.x + kProjBlock * j
     uint64_t m[kBwdPer];
 #pragma unroll
     for (int j = 0; j < kBwdPer; j++) {
@@ -144,10 +193,7 @@ __global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_ker
 #pragma unroll
         for (int j = 0; j < kBwdPer; j++) s_cnt[j][w] = __popcll(ball[j]);
     }
-    for (int k = threadIdx.x; k < (kProjBlock / 64) * V * 6; k += kProjBlock)
-        s_pose[k / (V * 6)][(k / 6) % V][k % 6] = 0.0;
     __syncthreads();
-    // list position: (j, wave, lane) order, which is increasing Gaussian order
     int total = 0, off[kBwdPer];
 #pragma unroll
     for (int j = 0; j < kBwdPer; j++)
@@ -166,17 +212,174 @@ __global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_ker
             s_mask[e] = m[j];
         }
     }
+    __syncthreads();
+    return total;
+}
+
+// Colour part of the projection backward for SH colours, one block per span
+// of kProjBwdSpan Gaussians, one thread per Gaussian some view sees looping
+// over its views (as preprocess_bwd_kernel): the SH coefficient gradient
+// sum_v Y(dir_v) dL/dcolour_v over the unclamped channels, the direction's
+// gradient mapped to the mean and to the camera centre (the pose tangent's
+// translation; the centre does not move under a rotation about itself).
+// Runs before preprocess_bwd_kernel<SH>, which adds the geometric gradients
+// to the means and to the pose partials written here.  Kept apart because the
+// coefficient gradients (3K floats per Gaussian) and the geometric chain rule
+// together need twice the registers (two wavefronts per SIMD instead of four).
+template <int SH>
+__global__ __launch_bounds__(kProjBlock, 4) void sh_bwd_kernel(ViewTable vt, Params P, const float* poses,
+                                                            const uint64_t* vmask, const float* g2, Grads G,
+                                                            int accumulate, double* pose_part, int pose_blocks) {
+    constexpr int K = (SH + 1) * (SH + 1);
+    __shared__ uint16_t s_loc[kProjBwdSpan];
+    __shared__ uint64_t s_mask[kProjBwdSpan];
+    __shared__ int s_cnt[kBwdPer][kProjBlock / 64];
+    __shared__ double s_pose[kProjBlock / 64][kMaxViews][3];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t g0 = (int64_t)blockIdx.x * kProjBwdSpan;
+    const int V = vt.V;
+    for (int k = threadIdx.x; k < (kProjBlock / 64) * V * 3; k += kProjBlock)
+        s_pose[k / (V * 3)][(k / 3) % V][k % 3] = 0.0;
     if (!accumulate) {
-        // the whole span's gradient starts at zero; the walk below overwrites
-        // the visible Gaussians' entries after the barrier
         const int64_t g1 = g0 + kProjBwdSpan < (int64_t)P.n ? g0 + kProjBwdSpan : (int64_t)P.n;
         block_zero(G.means, 3 * g0, 3 * g1);
+        block_zero(G.col, 3 * K * g0, 3 * K * g1);
+    }
+    const int total = pack_visible(P, vmask, g0, s_loc, s_mask, s_cnt);
+
+    for (int base = 0; base < total; base += kProjBlock) {
+        if (base + 64 * w >= total) break;   // nothing left for this wavefront
+        const int e = base + (int)threadIdx.x;
+        const bool live = e < total;
+        const int g = live ? (int)(g0 + s_loc[e]) : 0;
+        const uint64_t vm = live ? s_mask[e] : 0ull;
+        float mx = 0.f, my = 0.f, mz = 0.f;
+        if (live) {
+            const float* mu = P.means + 3 * (int64_t)g;
+            mx = mu[0]; my = mu[1]; mz = mu[2];
+        }
+        const float* sh = P.col + (int64_t)g * K * 3;
+        float gc[3 * K];
+#pragma unroll
+        for (int k = 0; k < 3 * K; k++) gc[k] = 0.f;
+        float dmu[3] = {0.f, 0.f, 0.f};
+        for (int v = 0; v < V; v++) {
+            const bool on = (vm >> v) & 1ull;
+            if (__ballot(on) == 0) continue;
+            float pose[3] = {0.f, 0.f, 0.f};
+            if (on) {
+                float T[12];
+#pragma unroll
+                for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
+                float dir[3], dirn, col[3];
+                bool cclamp[3], cb;
+                sh_colour(P, g, mx, my, mz, T, dir, dirn, col, cclamp, cb);
+                const float* a = g2 + ((int64_t)v * P.n + g) * kG2Stride;
+                const float dcol[3] = {cclamp[0] ? 0.f : a[6], cclamp[1] ? 0.f : a[7], cclamp[2] ? 0.f : a[8]};
+                float Y[16];
+                sh_basis<false>(SH, dir[0], dir[1], dir[2], Y, nullptr);
+                float sl[K];
+#pragma unroll
+                for (int l = 0; l < K; l++) {
+                    gc[3 * l] += Y[l] * dcol[0];
+                    gc[3 * l + 1] += Y[l] * dcol[1];
+                    gc[3 * l + 2] += Y[l] * dcol[2];
+                    sl[l] = dcol[0] * sh[3 * l] + dcol[1] * sh[3 * l + 1] + dcol[2] * sh[3 * l + 2];
+                }
+                float dd[3];
+                sh_grad_dot<SH>(dir[0], dir[1], dir[2], sl, dd);
+                // dir = (mu - C) / |mu - C|
+                const float pj = dd[0] * dir[0] + dd[1] * dir[1] + dd[2] * dir[2];
+                const float idn = 1.f / dirn;
+                float t[3];
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    t[j] = (dd[j] - dir[j] * pj) * idn;
+                    dmu[j] += t[j];
+                }
+                // the centre C = -W^T t moves by -W^T v: dL/dv = -W dL/dC = W t
+#pragma unroll
+                for (int i = 0; i < 3; i++) pose[i] = T[4 * i] * t[0] + T[4 * i + 1] * t[1] + T[4 * i + 2] * t[2];
+            }
+            float ps[3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) ps[k] = wave_sum_to_last(pose[k]);
+            if (lane == 63) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) s_pose[w][v][k] += (double)ps[k];
+            }
+        }
+        if (live) {
+            float* om = G.means + 3 * (int64_t)g;
+            float* oc = G.col + (int64_t)g * 3 * K;
+            if (accumulate) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) om[k] += dmu[k];
+#pragma unroll
+                for (int k = 0; k < 3 * K; k++) oc[k] += gc[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3; k++) om[k] = dmu[k];
+#pragma unroll
+                for (int k = 0; k < 3 * K; k++) oc[k] = gc[k];
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < V * 6; k += kProjBlock) {
+        double t = 0.0;
+        if (k % 6 < 3) {
+#pragma unroll
+            for (int i = 0; i < kProjBlock / 64; i++) t += s_pose[i][k / 6][k % 6];
+        }
+        pose_part[((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6] = t;
+    }
+}
+
+// One block per span of kProjBwdSpan Gaussians.  The block first reads the
+// view masks the forward projection left (bit v: visible in view v); the
+// Gaussians visible in none get a zero gradient (or nothing, when
+// accumulating) and the others are packed, in increasing index order,
+// into a list that the block then walks 256 at a time.  Every lane of that
+// walk holds a Gaussian some view sees, so the per-view recomputation runs on
+// full wavefronts instead of on the few lanes a random 64 Gaussians leave
+// visible.  The per-Gaussian gradient is summed over views in registers; the
+// per-view pose 6-vector is summed over each wavefront (FP32), added to that
+// wavefront's FP64 slot, and the four slots are added at the end: a fixed
+// order, with no barrier inside the walk.
+// With SH colours the colour part runs in sh_bwd_kernel first: this kernel
+// then adds its mean and pose gradients to what that one wrote.  At most 128
+// VGPRs (four waves per SIMD; it fits without spilling).
+template <int SH>
+__global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable vt, Params P, const float* poses,
+                                                                    const uint64_t* vmask, const float* g2, Grads G,
+                                                                    int accumulate, double* pose_part,
+                                                                    int pose_blocks) {
+    constexpr int K = SH < 0 ? 1 : (SH + 1) * (SH + 1);
+    __shared__ uint16_t s_loc[kProjBwdSpan];
+    __shared__ uint64_t s_mask[kProjBwdSpan];
+    __shared__ int s_cnt[kBwdPer][kProjBlock / 64];
+    __shared__ double s_pose[kProjBlock / 64][kMaxViews][6];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t g0 = (int64_t)blockIdx.x * kProjBwdSpan;
+    const int V = vt.V;
+
+    for (int k = threadIdx.x; k < (kProjBlock / 64) * V * 6; k += kProjBlock)
+        s_pose[k / (V * 6)][(k / 6) % V][k % 6] = 0.0;
+    if (!accumulate) {
+        // the whole span's gradient starts at zero; the walk below overwrites
+        // the visible Gaussians' entries after the barrier (with SH colours
+        // sh_bwd_kernel has already written the colour and mean gradients)
+        const int64_t g1 = g0 + kProjBwdSpan < (int64_t)P.n ? g0 + kProjBwdSpan : (int64_t)P.n;
+        if (SH < 0) {
+            block_zero(G.means, 3 * g0, 3 * g1);
+            block_zero(G.col, 3 * g0, 3 * g1);
+        }
         block_zero(G.ls, 3 * g0, 3 * g1);
         block_zero(G.q, 4 * g0, 4 * g1);
         block_zero(G.opl, g0, g1);
-        block_zero(G.col, 3 * K * g0, 3 * K * g1);
     }
-    __syncthreads();
+    const int total = pack_visible(P, vmask, g0, s_loc, s_mask, s_cnt);
 
     for (int base = 0; base < total; base += kProjBlock) {
         if (base + 64 * w >= total) break;   // nothing left for this wavefront
@@ -185,9 +388,7 @@ __global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_ker
         const int g = live ? (int)(g0 + s_loc[e]) : 0;
         const uint64_t vmask = live ? s_mask[e] : 0ull;
         float gm[3] = {0.f, 0.f, 0.f}, gl[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f;
-        float gc[3 * K];
-#pragma unroll
-        for (int k = 0; k < 3 * K; k++) gc[k] = 0.f;
+        float gc[3] = {0.f, 0.f, 0.f};   // RGB only
         GPrep gp;
         gp.ok = false;
         if (live) gauss_prep(P, g, gp);
@@ -203,7 +404,7 @@ __global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_ker
 #pragma unroll
                 for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
                 Proj pr;
-                project_view<true>(P, g, gp, vi, T, pr);
+                project_view<false>(P, g, gp, vi, T, pr);
                 const float4* a4 = reinterpret_cast<const float4*>(g2 + r * kG2Stride);
                 const float4 a0 = a4[0], a1 = a4[1], a2 = a4[2];
                 // undo the compositing kernel's constant factors (g2 layout)
@@ -213,34 +414,10 @@ __global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_ker
                 const float dcol[3] = {a1.z, a1.w, a2.x};
                 const float dz = a2.y;
                 float dmu[3] = {0.f, 0.f, 0.f};
-                float dcam[3] = {0.f, 0.f, 0.f};   // gradient w.r.t. the camera centre (SH path)
 
-                // colour
+                // colour (RGB: the gradient is dL/dcolour itself; SH: sh_bwd_kernel)
                 if (SH < 0) {
                     gc[0] += dcol[0]; gc[1] += dcol[1]; gc[2] += dcol[2];
-                } else {
-                    float Y[16], dY[16][3];
-                    sh_basis<true>(SH, pr.dir[0], pr.dir[1], pr.dir[2], Y, dY);
-                    const float* sh = P.col + (int64_t)g * K * 3;
-                    float dd[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int k = 0; k < 3; k++) {
-                        if (pr.cclamp[k]) continue;
-#pragma unroll
-                        for (int l = 0; l < K; l++) {
-                            gc[3 * l + k] += Y[l] * dcol[k];
-                            const float w = dcol[k] * sh[3 * l + k];
-                            dd[0] += w * dY[l][0]; dd[1] += w * dY[l][1]; dd[2] += w * dY[l][2];
-                        }
-                    }
-                    const float proj = dd[0] * pr.dir[0] + dd[1] * pr.dir[1] + dd[2] * pr.dir[2];
-                    const float idn = 1.f / pr.dirn;
-#pragma unroll
-                    for (int j = 0; j < 3; j++) {
-                        const float t = (dd[j] - pr.dir[j] * proj) * idn;
-                        dmu[j] += t;
-                        dcam[j] -= t;
-                    }
                 }
                 // opacity
                 go += odo * (1.f - pr.o);   // dL/do o (1 - o)
@@ -346,11 +523,11 @@ __global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_ker
                 dmu[2] += T[2] * dpx + T[6] * dpy + T[10] * dpz;
                 gm[0] += dmu[0]; gm[1] += dmu[1]; gm[2] += dmu[2];
 
-                // pose (left perturbation): dp/dv = I, dp/dw = -[p]x, the camera
-                // centre moves by -W^T v, and Sc picks up [w]x Sc - Sc [w]x
-                pose[0] = dpx - (T[0] * dcam[0] + T[1] * dcam[1] + T[2] * dcam[2]);
-                pose[1] = dpy - (T[4] * dcam[0] + T[5] * dcam[1] + T[6] * dcam[2]);
-                pose[2] = dpz - (T[8] * dcam[0] + T[9] * dcam[1] + T[10] * dcam[2]);
+                // pose (left perturbation): dp/dv = I, dp/dw = -[p]x, and Sc picks
+                // up [w]x Sc - Sc [w]x (the camera centre's share: sh_bwd_kernel)
+                pose[0] = dpx;
+                pose[1] = dpy;
+                pose[2] = dpz;
                 const float Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
                 // N = Sc Gs - Gs Sc (antisymmetric); d/dw = 2 (N12, N20, N01)
                 auto Nij = [&](int i, int j) {
@@ -373,23 +550,26 @@ __global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_ker
             float* om = G.means + 3 * (int64_t)g;
             float* ol = G.ls + 3 * (int64_t)g;
             float* oq = G.q + 4 * (int64_t)g;
-            float* oc = G.col + (int64_t)g * 3 * K;
             if (accumulate) {
 #pragma unroll
                 for (int k = 0; k < 3; k++) { om[k] += gm[k]; ol[k] += gl[k]; }
 #pragma unroll
                 for (int k = 0; k < 4; k++) oq[k] += gq[k];
                 G.opl[g] += go;
-#pragma unroll
-                for (int k = 0; k < 3 * K; k++) oc[k] += gc[k];
             } else {
 #pragma unroll
-                for (int k = 0; k < 3; k++) { om[k] = gm[k]; ol[k] = gl[k]; }
+                for (int k = 0; k < 3; k++) {
+                    om[k] = SH < 0 ? gm[k] : om[k] + gm[k];   // SH: add to the colour path's share
+                    ol[k] = gl[k];
+                }
 #pragma unroll
                 for (int k = 0; k < 4; k++) oq[k] = gq[k];
                 G.opl[g] = go;
+            }
+            if (SH < 0) {
+                float* oc = G.col + 3 * (int64_t)g;
 #pragma unroll
-                for (int k = 0; k < 3 * K; k++) oc[k] = gc[k];
+                for (int k = 0; k < 3; k++) oc[k] = accumulate ? oc[k] + gc[k] : gc[k];
             }
         }
     }
@@ -398,7 +578,8 @@ __global__ __launch_bounds__(kProjBlock, SH < 0 ? 4 : 1) void preprocess_bwd_ker
         double t = 0.0;
 #pragma unroll
         for (int i = 0; i < kProjBlock / 64; i++) t += s_pose[i][k / 6][k % 6];
-        pose_part[((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6] = t;
+        double* dst = pose_part + ((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6;
+        if (SH < 0) *dst = t; else *dst += t;   // SH: the colour path's partial is there already
     }
 }
 
@@ -436,8 +617,15 @@ __global__ __launch_bounds__(256) void pose_finalize_kernel(const double* part, 
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
                                  bool zero_g2, hipStream_t s, uint32_t* flags) {
     if (P.n == 0) return hipSuccess;
-    preprocess_fwd_kernel<<<(P.n + kProjBlock - 1) / kProjBlock, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2,
-                                                                                       flags);
+    const unsigned nb = (unsigned)((P.n + kProjBlock - 1) / kProjBlock);
+    switch (P.sh) {
+        case -1: preprocess_fwd_kernel<-1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
+        case 0: preprocess_fwd_kernel<0><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
+        case 1: preprocess_fwd_kernel<1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
+        case 2: preprocess_fwd_kernel<2><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
+        case 3: preprocess_fwd_kernel<3><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -447,12 +635,27 @@ hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const flo
     if (P.n == 0) return hipSuccess;
     const int nb = (P.n + kProjBwdSpan - 1) / kProjBwdSpan;
     if (nb != pose_blocks) return hipErrorInvalidValue;
+    const uint64_t* vm = rec.vmask;
     switch (P.sh) {
-        case -1: preprocess_bwd_kernel<-1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb); break;
-        case 0: preprocess_bwd_kernel<0><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb); break;
-        case 1: preprocess_bwd_kernel<1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb); break;
-        case 2: preprocess_bwd_kernel<2><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb); break;
-        case 3: preprocess_bwd_kernel<3><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb); break;
+        case -1:
+            preprocess_bwd_kernel<-1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            break;
+        case 0:
+            sh_bwd_kernel<0><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            preprocess_bwd_kernel<0><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            break;
+        case 1:
+            sh_bwd_kernel<1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            preprocess_bwd_kernel<1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            break;
+        case 2:
+            sh_bwd_kernel<2><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            preprocess_bwd_kernel<2><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            break;
+        case 3:
+            sh_bwd_kernel<3><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            preprocess_bwd_kernel<3><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
