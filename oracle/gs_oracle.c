@@ -370,19 +370,83 @@ typedef struct {
     double alpha, raw, G, dx, dy, T; /* T = transmittance before this fragment */
 } frag_t;
 
+/* Tie groups of blended fragments whose depths a single-precision renderer
+ * may order either way (consecutive in depth order, each within the order
+ * band of the previous one).  Reordering a group that starts at transmittance
+ * T0 leaves the product of its (1 - alpha) and everything behind it unchanged
+ * and changes the colour by at most T0 sum_{i<j} a_i a_j |c_i - c_j| (any
+ * order is reached by swapping each inverted pair once, each swap at a
+ * transmittance <= T0 changing the colour by a_i a_j T |c_i - c_j|); depth the
+ * same with z, alpha not at all.  Where the order also decides where the pixel
+ * stops (a tie with the stopping candidate), or the group is longer than
+ * GROUP_MAX, the coarser bound holds: whatever blends from T0 on contributes
+ * between 0 and T0 max c (a weighted sum with weights summing to at most 1),
+ * T0 max z to the depth, and leaves T_final in [0, T0]. */
+#define GROUP_MAX 32
+typedef struct {
+    double T0;
+    int n;
+    int coarse;
+    double cmax[3], zmax;
+    double a[GROUP_MAX], c[GROUP_MAX][3], z[GROUP_MAX];
+} group_t;
+
+static void group_open(group_t* g, double T0) {
+    g->T0 = T0;
+    g->n = 0;
+    g->coarse = 0;
+    g->cmax[0] = g->cmax[1] = g->cmax[2] = 0.0;
+    g->zmax = 0.0;
+}
+
+static void group_add(group_t* g, double a, const double* c, double z) {
+    for (int k = 0; k < 3; k++) g->cmax[k] = c[k] > g->cmax[k] ? c[k] : g->cmax[k];
+    g->zmax = z > g->zmax ? z : g->zmax;
+    if (g->n < GROUP_MAX) {
+        g->a[g->n] = a;
+        g->c[g->n][0] = c[0]; g->c[g->n][1] = c[1]; g->c[g->n][2] = c[2];
+        g->z[g->n] = z;
+        g->n++;
+    } else {
+        g->coarse = 1;
+    }
+}
+
+/* bound[0..2] colour, [3] depth, [4] alpha */
+static void group_close(group_t* g, double* bound) {
+    if (g->coarse) {
+        for (int k = 0; k < 3; k++) bound[k] += g->T0 * g->cmax[k];
+        bound[3] += g->T0 * g->zmax;
+        bound[4] += g->T0;
+    } else {
+        for (int i = 0; i < g->n; i++)
+            for (int j = i + 1; j < g->n; j++) {
+                const double w = g->T0 * g->a[i] * g->a[j];
+                for (int k = 0; k < 3; k++) bound[k] += w * fabs(g->c[i][k] - g->c[j][k]);
+                bound[3] += w * fabs(g->z[i] - g->z[j]);
+            }
+    }
+    g->n = 0;
+    g->coarse = 0;
+}
+
 /* Composite one pixel front to back (colour / depth compositing equations,
  * border-mask equation).  Candidates are the visible Gaussians whose pixel
  * rect contains (x, y), in ascending (depth, id) order.  Fills the outputs and,
- * if frags != NULL, the blended fragments.  Returns the number of blended
- * fragments. */
+ * if frags != NULL, the blended fragments; if bound != NULL, bound[0..4] =
+ * the largest change of C (per channel), D and A that reordering the tie
+ * groups can make.  Returns the number of blended fragments. */
 static int composite_pixel(const view_t* V, int x, int y, double band_skip, double band_clamp,
                            double band_term, double band_order, double* col, double* dep, double* Tfin,
-                           int* amb, int64_t* nvisit, frag_t** frags, int* fcap) {
+                           int* amb, int64_t* nvisit, frag_t** frags, int* fcap, double* bound) {
     const int64_t b = (int64_t)(y / BUCKET) * V->bx + x / BUCKET;
     double T = 1.0, C0 = 0, C1 = 0, C2 = 0, D = 0;
     double zprev = -1.0, zscprev = 0.0;
     int nb = 0;
     int64_t visits = 0;
+    group_t grp;
+    group_open(&grp, 1.0);
+    if (bound) bound[0] = bound[1] = bound[2] = bound[3] = bound[4] = 0.0;
     *amb = 0;
     for (int64_t k = V->bstart[b]; k < V->bstart[b + 1]; k++) {
         const int64_t id = V->blist[k];
@@ -400,10 +464,28 @@ static int composite_pixel(const view_t* V, int x, int y, double band_skip, doub
         if (alpha < ALPHA_MIN) continue;
         const double Tn = T * (1.0 - alpha);
         if (fabs(Tn - T_MIN) < band_term * T_MIN) *amb |= 4;
-        if (Tn < T_MIN) break;
         /* two blended Gaussians whose depths a single-precision renderer
            cannot order reliably: the blend order there is a rounding decision */
-        if (zprev >= 0 && fabs(p->z - zprev) <= band_order * (p->zsc > zscprev ? p->zsc : zscprev)) *amb |= 8;
+        const int tied = zprev >= 0 && fabs(p->z - zprev) <= band_order * (p->zsc > zscprev ? p->zsc : zscprev);
+        if (Tn < T_MIN) {
+            /* a tie at the stop: the order decides which fragments blend */
+            if (tied) {
+                *amb |= 16;
+                if (bound) {
+                    group_add(&grp, alpha, p->col, p->z);
+                    grp.coarse = 1;
+                }
+            }
+            break;
+        }
+        if (tied) *amb |= 8;
+        if (bound) {
+            if (!tied) {
+                group_close(&grp, bound);
+                group_open(&grp, T);
+            }
+            group_add(&grp, alpha, p->col, p->z);
+        }
         zprev = p->z;
         zscprev = p->zsc;
         const double w = alpha * T;
@@ -422,6 +504,7 @@ static int composite_pixel(const view_t* V, int x, int y, double band_skip, doub
         nb++;
         T = Tn;
     }
+    if (bound) group_close(&grp, bound);
     col[0] = C0; col[1] = C1; col[2] = C2;
     *dep = D;
     *Tfin = T;
@@ -467,13 +550,16 @@ int or_project(int64_t n, int sh, const double* means, const double* ls, const d
  * only), bit 2 the 1e-4 termination (relative band), bit 3 two blended
  * Gaussians whose depths differ by at most band_order times the magnitude of
  * the terms their depths are summed from (the order a single-precision sort
- * may swap).  nfrag_alg returns the number of
+ * may swap), bit 4 such a tie at the candidate that stops the pixel (the
+ * order decides which fragments blend).  order_bound (nullable, [5, np]): the
+ * largest change of C (per channel), D and A that reordering the tie groups
+ * can make.  nfrag_alg returns the number of
  * candidates visited up to and including the terminating one. */
 int or_render(int64_t n, int sh, const double* means, const double* ls, const double* q, const double* opl,
               const double* col, int W, int H, double fx, double fy, double cx, double cy, const double* T,
               int64_t npix, const int32_t* pix, double band_skip, double band_clamp, double band_term,
               double band_order, double* color, double* depth, double* alpha, double* tfinal, int32_t* nblend,
-              int8_t* ambiguous, int64_t* nfrag_alg) {
+              int8_t* ambiguous, int64_t* nfrag_alg, double* order_bound) {
     gs_t g; cam_t cam; view_t V;
     unpack_gs(&g, n, sh, means, ls, q, opl, col);
     make_cam(&cam, W, H, fx, fy, cx, cy, T);
@@ -487,8 +573,11 @@ int or_render(int64_t n, int sh, const double* means, const double* ls, const do
         double c3[3], d, t;
         int amb;
         int64_t visits;
+        double bd[5];
         int nb = composite_pixel(&V, x, y, band_skip, band_clamp, band_term, band_order, c3, &d, &t, &amb, &visits,
-                                 NULL, NULL);
+                                 NULL, NULL, order_bound ? bd : NULL);
+        if (order_bound)
+            for (int q = 0; q < 5; q++) order_bound[(int64_t)q * np + k] = bd[q];
         /* the terminating candidate counts as visited (it was evaluated) */
         total += visits;
         color[k] = c3[0]; color[np + k] = c3[1]; color[2 * np + k] = c3[2];
@@ -536,7 +625,7 @@ int or_backward(int64_t n, int sh, const double* means, const double* ls, const 
             double c3[3], d, Tf;
             int amb;
             int64_t visits;
-            int nb = composite_pixel(&V, x, y, 0, 0, 0, -1.0, c3, &d, &Tf, &amb, &visits, &fr, &fcap);
+            int nb = composite_pixel(&V, x, y, 0, 0, 0, -1.0, c3, &d, &Tf, &amb, &visits, &fr, &fcap, NULL);
             const double gC0 = dC ? dC[k] : 0, gC1 = dC ? dC[np + k] : 0, gC2 = dC ? dC[2 * np + k] : 0;
             const double gD = dD ? dD[k] : 0, gA = dA ? dA[k] : 0;
             /* suffix sums S of later weighted colours / depths */

@@ -46,9 +46,14 @@ BAND_TERM = 5e-4
 BAND_ORDER = 8 * 2.0 ** -24
 BANDS = (BAND_SKIP, BAND_CLAMP, BAND_TERM, BAND_ORDER)
 SMALL_BANDS = (5e-5, 5e-5, 2e-4, BAND_ORDER)
-# flag bits
-AMB_SKIP, AMB_CLAMP, AMB_TERM, AMB_ORDER = 1, 2, 4, 8
-AMB_VALUE = AMB_SKIP | AMB_TERM | AMB_ORDER    # decisions that change rendered values
+# flag bits: the 1/255 skip, the 0.99 clamp, the 1e-4 stop near their
+# thresholds; a blend order within FP32 depth rounding (a tie); a tie at the
+# candidate that stops the pixel
+AMB_SKIP, AMB_CLAMP, AMB_TERM, AMB_ORDER, AMB_ORDER_STOP = 1, 2, 4, 8, 16
+AMB_VALUE = AMB_SKIP | AMB_TERM | AMB_ORDER | AMB_ORDER_STOP   # decisions that change rendered values
+# decisions whose effect the oracle does not bound; a pixel flagged only
+# AMB_ORDER and / or AMB_ORDER_STOP is bounded by render()["order_bound"]
+AMB_UNBOUNDED = AMB_SKIP | AMB_TERM
 
 
 def build(force: bool = False) -> str:
@@ -75,7 +80,7 @@ def lib():
             [ctypes.c_double] * 4 + [ctypes.c_void_p, ctypes.c_void_p]
         L.or_render.argtypes = [i64, ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_int] + \
             [ctypes.c_double] * 4 + [ctypes.c_void_p, i64, ctypes.c_void_p] + [ctypes.c_double] * 4 + \
-            [ctypes.c_void_p] * 7
+            [ctypes.c_void_p] * 8
         L.or_backward.argtypes = [i64, ctypes.c_int] + [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_int] + \
             [ctypes.c_double] * 4 + [ctypes.c_void_p, i64, ctypes.c_void_p] + [ctypes.c_void_p] * 3 + \
             [ctypes.c_void_p] * 6
@@ -150,7 +155,9 @@ def render(g: Gaussians, cam, T, pixels: Optional[np.ndarray] = None, bands=BAND
     """Render one view (whole image, or the pixels [k,2] (x, y) listed).
 
     Returns color [3,H,W] (or [3,k]), depth, alpha, tfinal, nblend,
-    ambiguous (int8 flags) and nfrag (candidates visited)."""
+    ambiguous (int8 flags), order_bound [5,...] (the largest change of the
+    three colour channels, the depth and the alpha that reordering near-tied
+    blended Gaussians can make) and nfrag (candidates visited)."""
     ca, T = _cam_args(cam, T)
     if pixels is None:
         shape = (cam.height, cam.width)
@@ -167,13 +174,15 @@ def render(g: Gaussians, cam, T, pixels: Optional[np.ndarray] = None, bands=BAND
     nbl = np.zeros(np_, np.int32)
     amb = np.zeros(np_, np.int8)
     nfrag = np.zeros(1, np.int64)
+    bound = np.zeros(5 * np_, np.float64)
     b4 = tuple(bands) + ((BAND_ORDER,) if len(bands) == 3 else ())
-    rc = lib().or_render(*g.args(), *ca, _p(T), npix, _p(pix), *(float(b) for b in b4), _p(color), _p(depth), _p(alpha), _p(tfin), _p(nbl), _p(amb), _p(nfrag))
+    rc = lib().or_render(*g.args(), *ca, _p(T), npix, _p(pix), *(float(b) for b in b4), _p(color), _p(depth),
+                         _p(alpha), _p(tfin), _p(nbl), _p(amb), _p(nfrag), _p(bound))
     if rc != 0:
         raise MemoryError("oracle render failed")
     return {"color": color.reshape((3,) + shape), "depth": depth.reshape(shape), "alpha": alpha.reshape(shape),
             "tfinal": tfin.reshape(shape), "nblend": nbl.reshape(shape), "ambiguous": amb.reshape(shape),
-            "nfrag": int(nfrag[0])}
+            "order_bound": bound.reshape((5,) + shape), "nfrag": int(nfrag[0])}
 
 
 def backward(g: Gaussians, cam, T, dC=None, dD=None, dA=None, pixels: Optional[np.ndarray] = None,
@@ -213,6 +222,7 @@ def render_views(g: Gaussians, cams, poses, bands=BANDS) -> Dict[str, np.ndarray
             "tfinal": np.concatenate([o["tfinal"].reshape(-1) for o in outs]),
             "ambiguous": np.concatenate([o["ambiguous"].reshape(-1) for o in outs]),
             "nblend": np.concatenate([o["nblend"].reshape(-1) for o in outs]),
+            "order_bound": np.concatenate([o["order_bound"].reshape(5, -1) for o in outs], axis=1),
             "nfrag": sum(o["nfrag"] for o in outs)}
 
 

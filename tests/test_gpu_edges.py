@@ -8,8 +8,8 @@ import torch
 
 from oracle import oracle as O
 from synth import scenes
-from tests.gpu_helpers import (GRAD_NAMES, TOL_A, TOL_C, TOL_D_REL, TOL_G, cotangents, dev_scene, forward_errors,
-                               oracle_views, rel)
+from tests.gpu_helpers import (GRAD_NAMES, TOL_G, check_forward, check_grad, cotangents, dev_scene, oracle_views,
+                               rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -27,20 +27,19 @@ def _check_forward_backward(ctx, s, seed):
     g, poses = dev_scene(s)
     color, depth, alpha, state, plan = ctx.forward(g, s.cams, poses)
     og, ref = oracle_views(s)
-    ec, ed, ea, namb = forward_errors(s, color, depth, alpha, ref)
-    zm = float(np.max(np.abs(ref["depth"]), initial=0.0)) + 1.0
-    print(f"  V={s.V} pairs={plan.n_pairs} err C={ec:.2e} D={ed:.2e} A={ea:.2e} ambiguous={namb}", flush=True)
-    assert ec <= TOL_C and ea <= TOL_A and ed <= TOL_D_REL * zm
+    print(f"  V={s.V} pairs={plan.n_pairs}", flush=True)
+    label = f"edges V={s.V} {s.cams[0].width}x{s.cams[0].height}"
+    check_forward(s, color, depth, alpha, ref, label)
     dC, dD, dA = cotangents(s, ref, seed=seed)
     t = lambda a: torch.tensor(a, device="cuda")
     grads, dpose = ctx.backward(g, s.cams, poses, state, plan, t(dC), t(dD), t(dA))
     torch.cuda.synchronize()
     rg = O.backward_views(og, s.cams, s.poses, dC, dD, dA)
     for nm in GRAD_NAMES:
-        e = rel(getattr(grads, nm).cpu().numpy(), rg[nm])
-        assert e < TOL_G, (nm, e)
+        check_grad(label, nm, getattr(grads, nm), rg[nm])
     for v in range(s.V):
-        assert rel(dpose[v].cpu().numpy(), rg["pose"][v]) < TOL_G, v
+        if np.linalg.norm(rg["pose"][v]) > 0:
+            check_grad(label, f"pose[{v}]", dpose[v], rg["pose"][v])
 
 
 def test_max_views_in_one_launch(ctx):

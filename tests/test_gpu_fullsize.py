@@ -8,7 +8,7 @@ import torch
 
 from oracle import oracle as O
 from synth import scenes
-from tests.gpu_helpers import GRAD_NAMES, TOL_G, dev_scene, forward_errors, rel
+from tests.gpu_helpers import GRAD_NAMES, TOL_G, check_forward, check_grad, dev_scene, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -40,11 +40,7 @@ def test_c3_mapping_step_full_parity(setup):
     torch.cuda.synchronize()
     assert st.status()["flags"] == 0
     out = O.render_views(og, s.cams, s.poses)
-    ec, ed, ea, namb = forward_errors(s, st.color, st.depth, st.alpha, out)
-    zm = float(np.abs(out["depth"]).max()) + 1.0
-    print(f"  forward err C={ec:.2e} D={ed:.2e} A={ea:.2e} ambiguous={namb} ({namb / s.npix:.4f})", flush=True)
-    assert ec <= 1e-5 and ea <= 1e-5 and ed <= 1e-5 * zm
-    assert namb / s.npix < 0.10
+    check_forward(s, st.color, st.depth, st.alpha, out, "1M Gaussians, 8 views 1200x680 (full)")
     Lc, Ld, dC, dD = O.loss_and_upstream(s.cams, out, tc, td, 1.0, 0.1)
     loss = st.loss.cpu().numpy().astype(np.float64)
     total = float(np.mean(Lc + 0.1 * Ld))
@@ -52,13 +48,9 @@ def test_c3_mapping_step_full_parity(setup):
     assert abs(loss[0] - total) <= 1e-5 * total
     rg = O.backward_views(og, s.cams, s.poses, dC, dD, None)
     for nm in GRAD_NAMES:
-        e = rel(getattr(st.grads, nm).cpu().numpy(), rg[nm])
-        print(f"  {nm}: rel {e:.2e}", flush=True)
-        assert e < TOL_G, (nm, e)
+        check_grad("1M Gaussians, 8 views 1200x680 (full)", nm, getattr(st.grads, nm), rg[nm])
     for v in range(s.V):
-        e = rel(st.dpose[v].cpu().numpy(), rg["pose"][v])
-        print(f"  pose[{v}]: rel {e:.2e}", flush=True)
-        assert e < TOL_G, ("pose", v, e)
+        check_grad("1M Gaussians, 8 views 1200x680 (full)", f"pose[{v}]", st.dpose[v], rg["pose"][v])
 
 
 @pytest.mark.timeout(600)

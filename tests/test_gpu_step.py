@@ -6,7 +6,7 @@ import torch
 
 from oracle import oracle as O
 from synth import scenes
-from tests.gpu_helpers import GRAD_NAMES, TOL_G, dev_scene, forward_errors, rel
+from tests.gpu_helpers import GRAD_NAMES, TOL_G, check_forward, check_grad, dev_scene, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -33,10 +33,10 @@ def _targets(s):
     return ref["color"].astype(np.float32), ref["depth"].astype(np.float32)
 
 
-def _oracle_step(s, tc, td, wc, wd, wr, delta=2.0, gate=None, matches=True):
+def _oracle_step(s, tc, td, wc, wd, wr, delta=2.0, gate=None, matches=True, mask=None):
     og = O.Gaussians.from_scene(s)
     out = O.render_views(og, s.cams, s.poses, bands=O.SMALL_BANDS)
-    Lc, Ld, dC, dD = O.loss_and_upstream(s.cams, out, tc, td, wc, wd, gate_gamma=gate)
+    Lc, Ld, dC, dD = O.loss_and_upstream(s.cams, out, tc, td, wc, wd, gate_gamma=gate, mask=mask)
     g = O.backward_views(og, s.cams, s.poses, dC, dD, None)
     V = s.V
     Lr = np.zeros(V)
@@ -48,14 +48,21 @@ def _oracle_step(s, tc, td, wc, wd, wr, delta=2.0, gate=None, matches=True):
     return out, total, Lc, Ld, Lr, g
 
 
-def _step(ctx, s, tc, td, opts, matches=True, g=None, poses=None):
+def _step(ctx, s, tc, td, opts, matches=True, g=None, poses=None, mask=None):
     import paper_2405_19614_amd as gs
     if g is None:
         g, poses = dev_scene(s)
     t = lambda a: torch.tensor(a, device="cuda")
     m = (t(s.points), t(s.uv), t(s.view_idx)) if (matches and s.points is not None) else None
-    st = gs.MappingStep(ctx, g, s.cams, poses, t(tc), t(td), opts, matches=m)
+    st = gs.MappingStep(ctx, g, s.cams, poses, t(tc), t(td), opts, matches=m,
+                        mask=None if mask is None else t(mask.astype(np.float32)))
     return st
+
+
+# the filter gate compares the rendered alpha with gamma: the FP32 render and
+# the FP64 oracle may decide a pixel whose alpha lies this close to gamma
+# differently, so such pixels are masked out on both sides
+GATE_BAND = 1e-5
 
 
 @pytest.mark.parametrize("use_gate", [False, True])
@@ -67,14 +74,18 @@ def test_step_loss_and_gradients_match_oracle(ctx, use_gate):
     wc, wd, wr = 1.0, 0.1, 0.5
     opts = gs.StepOptions(w_color=wc, w_depth=wd, w_reproj=wr, huber_delta=2.0, use_gate=use_gate,
                           gate_gamma=0.99, use_graph=False)
-    st = _step(ctx, s, tc, td, opts)
+    mask = None
+    if use_gate:
+        ref0 = O.render_views(O.Gaussians.from_scene(s), s.cams, s.poses, bands=O.SMALL_BANDS)
+        amb_gate = np.abs(ref0["alpha"] - 0.99) < GATE_BAND
+        mask = (~amb_gate).astype(np.float64)
+        print(f"  gate-ambiguous pixels masked on both sides: {int(amb_gate.sum())} of {amb_gate.size}")
+    st = _step(ctx, s, tc, td, opts, mask=mask)
     st()
     torch.cuda.synchronize()
     assert st.status()["flags"] == 0
-    out, total, Lc, Ld, Lr, rg = _oracle_step(s, tc, td, wc, wd, wr, gate=0.99 if use_gate else None)
-    ec, ed, ea, namb = forward_errors(s, st.color, st.depth, st.alpha, out)
-    print(f"  forward err C={ec:.2e} D={ed:.2e} A={ea:.2e} ambiguous={namb}")
-    assert ec < 1e-5 and ea < 1e-5
+    out, total, Lc, Ld, Lr, rg = _oracle_step(s, tc, td, wc, wd, wr, gate=0.99 if use_gate else None, mask=mask)
+    check_forward(s, st.color, st.depth, st.alpha, out, f"step c4-like gate={use_gate}")
     loss = st.loss.cpu().numpy().astype(np.float64)
     print(f"  loss gpu={loss[0]:.8f} oracle={total:.8f}")
     assert abs(loss[0] - total) <= 1e-5 * abs(total)
@@ -83,13 +94,9 @@ def test_step_loss_and_gradients_match_oracle(ctx, use_gate):
     np.testing.assert_allclose(loss[3::4], Lr, rtol=1e-4)
     assert np.all(loss[4::4] == 0.0)   # no SSIM term requested
     for nm in GRAD_NAMES:
-        e = rel(getattr(st.grads, nm).cpu().numpy(), rg[nm])
-        print(f"  {nm}: rel {e:.2e}")
-        assert e < TOL_G, (nm, e)
+        check_grad(f"step c4-like gate={use_gate}", nm, getattr(st.grads, nm), rg[nm])
     for v in range(s.V):
-        e = rel(st.dpose[v].cpu().numpy(), rg["pose"][v])
-        print(f"  pose[{v}]: rel {e:.2e}")
-        assert e < TOL_G, ("pose", v, e)
+        check_grad(f"step c4-like gate={use_gate}", f"pose[{v}]", st.dpose[v], rg["pose"][v])
 
 
 def test_adam_and_pose_update_match_oracle(ctx):

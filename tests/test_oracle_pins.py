@@ -858,3 +858,87 @@ def test_se3_left_jacobian_vs_expm_logm(oracle):
             lm = vee(np.real(logm(expm(hat6(xi - e)) @ Einv)))
             Jn[:, k] = (lp - lm) / (2 * h)
         np.testing.assert_allclose(J, Jn, atol=1e-7)
+
+
+# --------------------------------------------------------------------------
+# blend-order ties: the bound on what reordering near-tied Gaussians changes
+# --------------------------------------------------------------------------
+
+def _tied(oracle, zs, cols, opls, scales):
+    k = len(zs)
+    return oracle.Gaussians(np.array([[0.0, 0.0, z] for z in zs]), np.log(np.array(scales))[:, None] * np.ones((1, 3)),
+                            np.tile([1.0, 0, 0, 0], (k, 1)), np.array(opls, float), np.array(cols, float))
+
+
+def test_order_bound_exact_for_a_swapped_pair(oracle):
+    """Two Gaussians whose depths differ by 1e-7 relative (within FP32
+    rounding of a depth): swapping which is nearer changes C by exactly
+    a1 a2 |c1 - c2| (T0 = 1), which is the oracle's bound, up to the 1e-7
+    change of the footprints."""
+    cam = _cam()
+    z = 2.0
+    cols = [[0.9, 0.1, 0.3], [0.2, 0.7, 0.5]]
+    a = _tied(oracle, [z, z * (1 + 1e-7)], cols, [0.4, 1.1], [0.05, 0.07])
+    b = _tied(oracle, [z * (1 + 1e-7), z], cols, [0.4, 1.1], [0.05, 0.07])
+    ra, rb = oracle.render(a, cam, np.eye(4)), oracle.render(b, cam, np.eye(4))
+    both = (ra["nblend"] == 2)
+    assert both.sum() > 20
+    assert np.all(ra["ambiguous"][both] & oracle.AMB_ORDER)
+    dC = np.abs(ra["color"] - rb["color"])[:, both]
+    bound = ra["order_bound"][:3, both]
+    # moving a depth by 1e-7 relative moves its footprint's alpha by at most
+    # ~1e-6 alpha (sigma <= ln(255 o) inside the support)
+    np.testing.assert_allclose(dC, bound, rtol=1e-5, atol=2e-6)
+    # alpha does not depend on the order
+    np.testing.assert_allclose(ra["alpha"], rb["alpha"], rtol=0, atol=2e-6)
+    # pixels with one Gaussian or none carry no bound
+    assert np.all(ra["order_bound"][:, ~both] == 0)
+
+
+def test_order_bound_covers_every_permutation_of_a_triple(oracle):
+    import itertools
+    cam = _cam()
+    z = 3.0
+    cols = [[0.9, 0.1, 0.3], [0.2, 0.7, 0.5], [0.5, 0.5, 0.95]]
+    opls, scales = [0.2, 1.5, -0.3], [0.06, 0.05, 0.08]
+    eps = [0.0, 0.8e-7, 1.6e-7]
+    base = oracle.render(_tied(oracle, [z * (1 + e) for e in eps], cols, opls, scales), cam, np.eye(4))
+    three = base["nblend"] == 3
+    assert three.sum() > 20
+    worst = np.zeros(3)
+    for perm in itertools.permutations(range(3)):
+        zs = [z * (1 + eps[perm[i]]) for i in range(3)]
+        r = oracle.render(_tied(oracle, zs, cols, opls, scales), cam, np.eye(4))
+        d = np.abs(r["color"] - base["color"])[:, three]
+        assert np.all(d <= base["order_bound"][:3, three] * (1 + 1e-5) + 2e-6)
+        worst = np.maximum(worst, (d / np.maximum(base["order_bound"][:3, three], 1e-30)).max(axis=1))
+    print("largest change / bound per channel:", worst)
+
+
+def test_order_bound_at_the_stop(oracle):
+    """A tied pair straddling the stop: an opaque front Gaussian (T = 0.05
+    behind it), then two Gaussians at depths 1e-7 apart with opacities 0.9
+    and 0.99.  In one order the 0.9 one blends (T = 5e-3) and the 0.99 one
+    stops the pixel; in the other the 0.99 one blends (T = 5e-4) and the 0.9
+    one stops it.  Colour, depth and alpha move by less than the oracle's
+    bound (T0 times the largest colour / depth, T0 for alpha, T0 = 0.05)."""
+    cam = _cam()
+    cols = [[0.1, 0.2, 0.3], [0.9, 0.1, 0.5], [0.2, 0.8, 0.6]]
+    ops = [0.95, 0.9, 0.99]
+    opl = [math.log(o / (1 - o)) for o in ops]
+    sc = [0.02, 0.02, 0.02]
+    z2 = 2.2
+    pix = np.array([[int(cam.cx), int(cam.cy)]], np.int32)
+    a = oracle.render(_tied(oracle, [2.0, z2, z2 * (1 + 1e-7)], cols, opl, sc), cam, np.eye(4), pixels=pix)
+    b = oracle.render(_tied(oracle, [2.0, z2 * (1 + 1e-7), z2], cols, opl, sc), cam, np.eye(4), pixels=pix)
+    assert a["ambiguous"][0] & oracle.AMB_ORDER_STOP and b["ambiguous"][0] & oracle.AMB_ORDER_STOP
+    assert int(a["nblend"][0]) == 2 and int(b["nblend"][0]) == 2
+    T0 = 1 - 0.95
+    np.testing.assert_allclose(a["tfinal"][0], T0 * (1 - 0.9), rtol=1e-6)
+    np.testing.assert_allclose(b["tfinal"][0], T0 * (1 - 0.99), rtol=1e-5)
+    bnd = a["order_bound"][:, 0]
+    np.testing.assert_allclose(bnd[:3], T0 * np.max(cols[1:], axis=0), rtol=1e-6)
+    np.testing.assert_allclose(bnd[4], T0, rtol=1e-12)
+    assert np.all(np.abs(a["color"][:, 0] - b["color"][:, 0]) <= bnd[:3])
+    assert abs(a["depth"][0] - b["depth"][0]) <= bnd[3]
+    assert abs(a["alpha"][0] - b["alpha"][0]) <= bnd[4]
