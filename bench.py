@@ -50,6 +50,8 @@ WORKLOADS = {
           "L1 colour + 0.1 L1 depth",
     "c3": "batched keyframe window: 1000000 Gaussians with RGB colour, room shell, 8 views 1200x680, f=600, "
           "L1 colour + 0.1 L1 depth",
+    "c3_iso": "the paper's own Gaussian (8 parameters: RGB, centre, one radius, opacity) in the c3 window: 1000000 "
+              "isotropic Gaussians, room shell, 8 views 1200x680, f=600, L1 colour + 0.1 L1 depth",
 }
 
 
@@ -59,7 +61,9 @@ def log(msg):
 
 def make_scene(name):
     from synth import scenes
-    return scenes.c5() if name == "c5" else scenes.c3()
+    if name == "c5":
+        return scenes.c5()
+    return scenes.isotropic(scenes.c3()) if name == "c3_iso" else scenes.c3()
 
 
 def dev_inputs(ctx, s):
@@ -267,7 +271,7 @@ def session(gs, ctx, s, g, base, nsteps, tile, binsz, btile):
     est = np.stack([scenes.perturb_pose(T, rng) for T in traj[:L]]).astype(np.float32)
     cams = [s.cams[0]] * V
     P = s.cams[0].npix
-    gm = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
+    gm = g.like(*(t.clone() for t in g.tensors()))
     tcol = torch.empty(L * 3 * P, dtype=torch.float32, device="cuda:0")
     tdep = torch.empty(L * P, dtype=torch.float32, device="cuda:0")
     tru = torch.tensor(traj[:L].astype(np.float32), device="cuda:0").reshape(L, 16)
@@ -357,7 +361,7 @@ def run_workload(gs, ctx, name, args, per_view=True, profile=True):
         res["_stage_ms"], res["_frag"] = stage_ms, frag
 
     # mapping iterations (Adam on every Gaussian parameter)
-    gm = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
+    gm = g.like(*(t.clone() for t in g.tensors()))
     stm = gs.MappingStep(ctx, gm, s.cams, poses.clone(), tc, td, gs.StepOptions(update_gaussians=True, **base),
                          capacity=st.capacity)
     ms_map, _ = timed_steps([stm], args.steps, args.warmup)
@@ -368,7 +372,7 @@ def run_workload(gs, ctx, name, args, per_view=True, profile=True):
     del stm, gm
 
     # the paper's mapping loss: (1 - zeta)(w4 L1_D + w5 L1_C) + zeta L_SSIM, Adam on the Gaussians
-    gp = gs.Gaussians(*(t.clone() for t in g.tensors()), g.sh_degree)
+    gp = g.like(*(t.clone() for t in g.tensors()))
     popts = dict(base)
     popts.update(gs.PAPER_MAPPING)
     stp = gs.MappingStep(ctx, gp, s.cams, poses.clone(), tc, td, gs.StepOptions(**popts), capacity=st.capacity)
@@ -479,13 +483,30 @@ def main():
                        tile, binsz, btile)
         log(f"[bench] session: {json.dumps(sess)}")
 
-    extra = None
+    extra = paper_model = None
     if not args.no_extra:
         other = "c3" if args.workload == "c5" else "c5"
         ctx2 = gs.Context(0)
         r2 = run_workload(gs, ctx2, other, args, per_view=not args.no_per_view, profile=True)
         extra = public(r2)
         extra["roofline"] = roofline(r2, other, ctx2)
+        if args.workload != "c3_iso":
+            # the same window with the paper's isotropic Gaussians: what the
+            # eight-parameter layout saves in projection and in the optimiser
+            ctx3 = gs.Context(0)
+            r3 = run_workload(gs, ctx3, "c3_iso", args, per_view=False, profile=True)
+            paper_model = public(r3)
+            paper_model["roofline"] = roofline(r3, "c3_iso", ctx3)
+            c3 = r2 if other == "c3" else None
+            if c3 is not None:
+                paper_model["vs_anisotropic_c3"] = {
+                    "parameter_bytes_per_gaussian": [32, 56],
+                    "adam_moment_bytes_per_gaussian": [64, 112],
+                    "stage_ms_ratio": {k: round(r3["_stage_ms"][k] / c3["_stage_ms"][k], 3)
+                                       for k in ("preprocess_fwd", "preprocess_bwd")
+                                       if c3["_stage_ms"].get(k)},
+                    "mapping_iters_ratio": round(r3["mapping_iters_per_s"] / c3["mapping_iters_per_s"], 3)}
+            del r3
         del r2
 
     cpu = None
@@ -530,6 +551,7 @@ def main():
     out["roofline"] = roof
     out["cpu_baseline"] = cpu
     out["extra_workload"] = extra
+    out["paper_model_workload"] = paper_model
     print(json.dumps(out), flush=True)
 
 

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 3
+#define GS_ABI_VERSION 4
 #define GS_MAX_VIEWS 64
 
 typedef enum {
@@ -60,12 +60,17 @@ typedef enum {
 
 typedef struct gs_ctx gs_ctx;
 
-/* Gaussian parameters (Sec. 3.4 "Gaussian Representation", generalised to an
- * anisotropic covariance).  n Gaussians, FP32, device.
+/* Gaussian parameters (Sec. 3.4 "Gaussian Representation", Eq. gauss, and
+ * its generalisation to an anisotropic covariance).  n Gaussians, FP32, device.
+ *   isotropic      0: anisotropic layout; 1: the paper's eight-parameter
+ *                  Gaussian f(x) = o exp(-|x - mu|^2 / (2 r^2)) (RGB colours
+ *                  give 8 floats per Gaussian; 14 anisotropic)
  *   means          [n][3]  world-space centres
- *   log_scales     [n][3]  scale = exp(log_scale) per principal axis (equal
- *                          values give the paper's isotropic Gaussian)
- *   quats          [n][4]  rotation (w, x, y, z), normalised inside the forward
+ *   log_scales     anisotropic: [n][3] scale = exp(log_scale) per principal
+ *                  axis; isotropic: [n] log radius, r = exp(log_radius)
+ *   quats          anisotropic: [n][4] rotation (w, x, y, z), normalised
+ *                  inside the forward, 16-byte aligned; isotropic: unused
+ *                  (may be NULL)
  *   opacity_logits [n]     opacity = sigmoid(logit)
  *   colors         sh_degree == -1: [n][3] RGB (view independent, as in the paper)
  *                  sh_degree in 0..3: [n][(L+1)^2][3] real orthonormal SH
@@ -74,6 +79,7 @@ typedef struct gs_ctx gs_ctx;
 typedef struct {
     int64_t n;
     int32_t sh_degree;
+    int32_t isotropic;
     float* means;
     float* log_scales;
     float* quats;
@@ -81,8 +87,9 @@ typedef struct {
     float* colors;
 } gs_gaussians;
 
-/* Gradients with the layout of gs_gaussians (device, FP32).  Overwritten by
- * gs_render_backward; gs_mapping_step overwrites or accumulates (opts). */
+/* Gradients with the layout of gs_gaussians (device, FP32; quats unused and
+ * may be NULL for an isotropic set).  Overwritten by gs_render_backward;
+ * gs_mapping_step overwrites or accumulates (opts). */
 typedef struct {
     float* means;
     float* log_scales;
@@ -254,9 +261,11 @@ typedef struct {
 
 /* Adam state (device): m and v each hold n*(11 + 3K) + 6V floats laid out as
  * means [3n], log_scales [3n], quats [4n], opacity [n], colors [3Kn] (K = 1 for
- * RGB, (L+1)^2 for SH), poses [6V]; step is a device int32[2]: the Gaussian
- * updates done and the pose updates done (incremented on the device).  Each
- * group's bias correction uses its own count, as two optimisers would. */
+ * RGB, (L+1)^2 for SH), poses [6V]; isotropic: n*(5 + 3K) + 6V floats, means
+ * [3n], log radii [n], opacity [n], colors [3Kn], poses [6V].  step is a
+ * device int32[2]: the Gaussian updates done and the pose updates done
+ * (incremented on the device).  Each group's bias correction uses its own
+ * count, as two optimisers would. */
 typedef struct {
     float* m;
     float* v;
@@ -442,9 +451,9 @@ int gs_select_viewpoints(const int32_t* covis, const int32_t* n_obs, int32_t F, 
  * order.  tau <= 0 keeps every Gaussian, tau >= 1 removes every one.  tau is a
  * double and the decision is exact: the FP32 logit is compared with
  * logit(tau) in FP64.
- *   in        device arrays of in->n Gaussians (sh_degree as in gs_gaussians).
- *   out       device arrays with room for in->n Gaussians, not overlapping in;
- *             out->n and out->sh_degree are ignored.
+ *   in        device arrays of in->n Gaussians (sh_degree, isotropic as in gs_gaussians).
+ *   out       device arrays of in's layout with room for in->n Gaussians, not
+ *             overlapping in; out->n, out->sh_degree, out->isotropic are ignored.
  *   adam_in / adam_out  optional (both NULL or both given, not overlapping):
  *             Adam moments laid out for in->n Gaussians and V poses (see
  *             gs_adam) are re-laid out for the kept ones; the step counter is
@@ -463,8 +472,9 @@ int gs_prune(gs_ctx* ctx, const gs_gaussians* in, double tau, gs_gaussians* out,
  * when all_pixels is set, as on the first frame -- and whose target depth d
  * is > 0, one Gaussian is appended after the g->n existing ones, in view then
  * row-major pixel order: mean = the pixel's sample point (x, y) back-projected
- * to depth d through the view's pose, isotropic log-scale log(d / fx) (a
- * one-pixel footprint), quaternion (1, 0, 0, 0), opacity logit 0, colour =
+ * to depth d through the view's pose, log-scale log(d / fx) on every axis (a
+ * one-pixel footprint; the log radius of an isotropic set), quaternion
+ * (1, 0, 0, 0) (anisotropic), opacity logit 0, colour =
  * the target colour (with SH, the DC coefficient (rgb - 0.5) / Y_00 and the
  * other coefficients 0).
  *   cams HOST [V]; poses device [V][16] world-to-camera; alpha device [sum HW]

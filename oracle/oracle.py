@@ -13,6 +13,9 @@ of numpy:
   L1 terms of the mapping loss (Sec. 3.4, mapping-loss equation), as means per
   view averaged over views, with an optional constant pixel mask and the
   filter gate of Sec. 3.3 (gate equation);
+* the paper's own eight-parameter isotropic Gaussian (Sec. 3.4 "Gaussian
+  Representation") as the anisotropic one with equal scales, and the reverse
+  mode of that map;
 * the SSIM term of the mapping loss (Sec. 3.4, mapping-loss equation) on the
   RGB render, with its gradient;
 * Gaussian pruning and densification (Sec. 3.4), with the re-layout of the
@@ -130,11 +133,34 @@ class Gaussians:
 
     @classmethod
     def from_scene(cls, s) -> "Gaussians":
+        if getattr(s, "isotropic", False):
+            return from_isotropic(s.means, s.log_scales, s.opacity_logits, s.colors, s.sh_degree)
         return cls(s.means, s.log_scales, s.quats, s.opacity_logits, s.colors, s.sh_degree)
 
     def args(self):
         return (self.n, self.sh_degree, _p(self.means), _p(self.log_scales), _p(self.quats),
                 _p(self.opacity_logits), _p(self.colors))
+
+
+def from_isotropic(means, log_radius, opacity_logits, colors, sh_degree: int = -1) -> Gaussians:
+    """The paper's eight-parameter Gaussian (Sec. 3.4 "Gaussian
+    Representation", Eq. gauss): centre mu, one radius r = exp(log_radius),
+    opacity and colour, f(x) = o exp(-|x - mu|^2 / (2 r^2)).  Its covariance
+    r^2 I is that of the anisotropic Gaussian with scale r on every axis,
+    whatever the rotation: the returned parameters hold log r on each axis and
+    the identity quaternion."""
+    lr = _d(log_radius).reshape(-1)
+    n = lr.shape[0]
+    return Gaussians(means, np.repeat(lr[:, None], 3, axis=1), np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)),
+                     opacity_logits, colors, sh_degree)
+
+
+def isotropic_grads(grads: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:
+    """Reverse mode of ``from_isotropic``: log r feeds all three log-scales,
+    so its gradient is their sum; the quaternion is a constant there."""
+    out = {k: v for k, v in grads.items() if k not in ("log_scales", "quats")}
+    out["log_radius"] = np.asarray(grads["log_scales"]).sum(axis=1)
+    return out
 
 
 def _cam_args(cam, T):
@@ -507,10 +533,12 @@ def prune(params: Dict[str, np.ndarray], tau: float):
     return {k: np.asarray(v)[keep] for k, v in params.items()}, keep
 
 
-def densify(cams, poses, alpha, tgt_color, tgt_depth, gamma: float, all_pixels: bool, sh_degree: int = -1):
+def densify(cams, poses, alpha, tgt_color, tgt_depth, gamma: float, all_pixels: bool, sh_degree: int = -1,
+            isotropic: bool = False):
     """New Gaussians (dict of FP64 arrays: means [m,3], log_scales [m,3],
-    quats [m,4], opacity_logits [m], colors [m,3] or [m,K,3]) and, for each,
-    its (view, x, y)."""
+    quats [m,4], opacity_logits [m], colors [m,3] or [m,K,3]; isotropic:
+    log_radius [m] in place of log_scales and quats) and, for each, its
+    (view, x, y)."""
     K = 1 if sh_degree < 0 else (sh_degree + 1) ** 2
     means, ls, cols, where = [], [], [], []
     po = 0
@@ -533,8 +561,12 @@ def densify(cams, poses, alpha, tgt_color, tgt_depth, gamma: float, all_pixels: 
                 where.append((v, x, y))
         po += P
     m = len(means)
-    out = {"means": np.array(means).reshape(m, 3), "log_scales": np.array(ls).reshape(m, 3),
-           "quats": np.tile([1.0, 0.0, 0.0, 0.0], (m, 1)), "opacity_logits": np.zeros(m)}
+    if isotropic:
+        out = {"means": np.array(means).reshape(m, 3), "log_radius": np.array(ls).reshape(m, 3)[:, 0],
+               "opacity_logits": np.zeros(m)}
+    else:
+        out = {"means": np.array(means).reshape(m, 3), "log_scales": np.array(ls).reshape(m, 3),
+               "quats": np.tile([1.0, 0.0, 0.0, 0.0], (m, 1)), "opacity_logits": np.zeros(m)}
     rgb = np.array(cols).reshape(m, 3)
     if sh_degree < 0:
         out["colors"] = rgb
@@ -545,11 +577,12 @@ def densify(cams, poses, alpha, tgt_color, tgt_depth, gamma: float, all_pixels: 
     return out, np.array(where, np.int64).reshape(m, 3)
 
 
-def adam_groups(n: int, sh_degree: int, V: int):
+def adam_groups(n: int, sh_degree: int, V: int, isotropic: bool = False):
     """(offset, per-Gaussian width) of each parameter group in the Adam
-    moment layout, and the offset of the 6V pose moments."""
+    moment layout (means, log-scales or log-radius, quaternions, opacity
+    logits, colours), and the offset of the 6V pose moments."""
     K = 1 if sh_degree < 0 else (sh_degree + 1) ** 2
-    widths = [3, 3, 4, 1, 3 * K]
+    widths = [3, 1, 0, 1, 3 * K] if isotropic else [3, 3, 4, 1, 3 * K]
     offs, o = [], 0
     for w in widths:
         offs.append(o)
@@ -557,12 +590,13 @@ def adam_groups(n: int, sh_degree: int, V: int):
     return list(zip(offs, widths)), o
 
 
-def adam_relayout(m: np.ndarray, n: int, sh_degree: int, V: int, src_index: np.ndarray, n_new: int):
+def adam_relayout(m: np.ndarray, n: int, sh_degree: int, V: int, src_index: np.ndarray, n_new: int,
+                  isotropic: bool = False):
     """Moments of n_new Gaussians whose i-th comes from old Gaussian
     src_index[i] (or is new with zero moments when src_index[i] < 0); the pose
     moments are carried over."""
-    old, pose_old = adam_groups(n, sh_degree, V)
-    new, pose_new = adam_groups(n_new, sh_degree, V)
+    old, pose_old = adam_groups(n, sh_degree, V, isotropic)
+    new, pose_new = adam_groups(n_new, sh_degree, V, isotropic)
     out = np.zeros(pose_new + 6 * V)
     for (oo, w), (on, _) in zip(old, new):
         src = np.asarray(m[oo:oo + w * n]).reshape(n, w)

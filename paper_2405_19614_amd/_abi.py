@@ -18,11 +18,12 @@ GS_OK, GS_EINVAL, GS_ENOMEM, GS_ECAPACITY, GS_EDEVICE, GS_ECAPTURE = 0, -1, -2, 
 STATUS_NAMES = {0: "GS_OK", -1: "GS_EINVAL", -2: "GS_ENOMEM", -3: "GS_ECAPACITY", -4: "GS_EDEVICE",
                 -5: "GS_ECAPTURE"}
 MAX_VIEWS = 64
+ABI_VERSION = 4     # GS_ABI_VERSION of include/gs.h
 
 
 class gs_gaussians(ctypes.Structure):
-    _fields_ = [("n", c_int64), ("sh_degree", c_int32), ("means", c_void_p), ("log_scales", c_void_p),
-                ("quats", c_void_p), ("opacity_logits", c_void_p), ("colors", c_void_p)]
+    _fields_ = [("n", c_int64), ("sh_degree", c_int32), ("isotropic", c_int32), ("means", c_void_p),
+                ("log_scales", c_void_p), ("quats", c_void_p), ("opacity_logits", c_void_p), ("colors", c_void_p)]
 
 
 class gs_gaussian_grads(ctypes.Structure):
@@ -86,6 +87,9 @@ def load() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     PC = ctypes.POINTER(gs_camera)
     L.gs_abi_version.restype = c_int32
+    if L.gs_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {L.gs_abi_version()}, this binding needs {ABI_VERSION}: "
+                          "rebuild it")
     L.gs_create.argtypes = [ctypes.POINTER(c_void_p), c_int32]
     L.gs_destroy.argtypes = [c_void_p]
     L.gs_destroy.restype = None

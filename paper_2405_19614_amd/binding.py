@@ -48,8 +48,8 @@ def _need(t: Optional[torch.Tensor], numel: int, name: str, dtype=torch.float32,
 def _check_gaussians(g: "Gaussians", device):
     n = g.n
     _need(g.means, 3 * n, "means", device=device)
-    _need(g.log_scales, 3 * n, "log_scales", device=device)
-    _need(g.quats, 4 * n, "quats", device=device)
+    _need(g.log_scales, n if g.isotropic else 3 * n, "log_scales", device=device)
+    _need(g.quats, 0 if g.isotropic else 4 * n, "quats", device=device)
     _need(g.opacity_logits, n, "opacity_logits", device=device)
     _need(g.colors, 3 * n * sh_coeffs(g.sh_degree), "colors", device=device)
 
@@ -96,42 +96,72 @@ def sh_coeffs(sh_degree: int) -> int:
     return 1 if sh_degree < 0 else (sh_degree + 1) ** 2
 
 
+def floats_per_gaussian(sh_degree: int, isotropic: bool = False) -> int:
+    """FP32 values per Gaussian in the parameter and Adam moment layouts:
+    means 3, log-scales 3 (log radius 1), quaternion 4 (none), opacity 1,
+    colour 3K -- 14 anisotropic, the paper's 8 isotropic, with RGB."""
+    return (5 if isotropic else 11) + 3 * sh_coeffs(sh_degree)
+
+
 @dataclass
 class Gaussians:
-    """Device FP32 parameters (structure of arrays)."""
+    """Device FP32 parameters (structure of arrays).  isotropic: the paper's
+    eight-parameter Gaussian, log_scales [n,1] holds the log radius and
+    quats is empty [n,0]."""
     means: torch.Tensor
     log_scales: torch.Tensor
     quats: torch.Tensor
     opacity_logits: torch.Tensor
     colors: torch.Tensor
     sh_degree: int = -1
+    isotropic: bool = False
 
     @property
     def n(self) -> int:
         return int(self.means.shape[0])
 
     @classmethod
-    def from_arrays(cls, means, log_scales, quats, opacity_logits, colors, sh_degree=-1, device="cuda"):
-        return cls(_dev_f32(means, device).reshape(-1, 3), _dev_f32(log_scales, device).reshape(-1, 3),
-                   _dev_f32(quats, device).reshape(-1, 4), _dev_f32(opacity_logits, device).reshape(-1),
-                   _dev_f32(colors, device), int(sh_degree))
+    def from_arrays(cls, means, log_scales, quats, opacity_logits, colors, sh_degree=-1, device="cuda",
+                    isotropic=False):
+        m = _dev_f32(means, device).reshape(-1, 3)
+        if isotropic:
+            ls = _dev_f32(log_scales, device).reshape(-1, 1)
+            q = torch.empty((m.shape[0], 0), dtype=torch.float32, device=device)
+        else:
+            ls = _dev_f32(log_scales, device).reshape(-1, 3)
+            q = _dev_f32(quats, device).reshape(-1, 4)
+        return cls(m, ls, q, _dev_f32(opacity_logits, device).reshape(-1), _dev_f32(colors, device),
+                   int(sh_degree), bool(isotropic))
+
+    @classmethod
+    def isotropic_from_arrays(cls, means, log_radius, opacity_logits, colors, sh_degree=-1, device="cuda"):
+        """The paper's Gaussian: centre, one log radius, opacity logit, colour."""
+        return cls.from_arrays(means, log_radius, None, opacity_logits, colors, sh_degree, device, True)
 
     @classmethod
     def from_scene(cls, s, device="cuda"):
-        return cls.from_arrays(s.means, s.log_scales, s.quats, s.opacity_logits, s.colors, s.sh_degree, device)
+        return cls.from_arrays(s.means, s.log_scales, s.quats, s.opacity_logits, s.colors, s.sh_degree, device,
+                               bool(getattr(s, "isotropic", False)))
+
+    def like(self, *tensors) -> "Gaussians":
+        """Another set of this layout (sh_degree, isotropic) from five tensors."""
+        return Gaussians(*tensors, self.sh_degree, self.isotropic)
 
     def struct(self) -> A.gs_gaussians:
-        return A.gs_gaussians(self.n, self.sh_degree, _p(self.means), _p(self.log_scales), _p(self.quats),
-                              _p(self.opacity_logits), _p(self.colors))
+        return A.gs_gaussians(self.n, self.sh_degree, int(self.isotropic), _p(self.means), _p(self.log_scales),
+                              _p(self.quats) if not self.isotropic else None, _p(self.opacity_logits),
+                              _p(self.colors))
 
     def zeros_like(self) -> "Gaussians":
-        return Gaussians(torch.zeros_like(self.means), torch.zeros_like(self.log_scales),
-                         torch.zeros_like(self.quats), torch.zeros_like(self.opacity_logits),
-                         torch.zeros_like(self.colors), self.sh_degree)
+        return self.like(*(torch.zeros_like(t) for t in self.tensors()))
+
+    @property
+    def floats_per_gaussian(self) -> int:
+        return floats_per_gaussian(self.sh_degree, self.isotropic)
 
     def grad_struct(self) -> A.gs_gaussian_grads:
-        return A.gs_gaussian_grads(_p(self.means), _p(self.log_scales), _p(self.quats), _p(self.opacity_logits),
-                                   _p(self.colors))
+        return A.gs_gaussian_grads(_p(self.means), _p(self.log_scales), None if self.isotropic else _p(self.quats),
+                                   _p(self.opacity_logits), _p(self.colors))
 
     def tensors(self) -> Tuple[torch.Tensor, ...]:
         return (self.means, self.log_scales, self.quats, self.opacity_logits, self.colors)
@@ -339,8 +369,7 @@ class Context:
         _check_gaussians(g, dev)
         m, v, step = adam
         V = 0 if poses is None else int(poses.numel() // 16)
-        K = sh_coeffs(g.sh_degree)
-        na = g.n * (11 + 3 * K) + 6 * V
+        na = g.n * g.floats_per_gaussian + 6 * V
         _need(m, na, "adam m", device=dev)
         _need(v, na, "adam v", device=dev)
         _need(step, 2, "adam step", dtype=torch.int32, device=dev)
@@ -400,8 +429,7 @@ class Context:
         kept count back (one synchronisation)."""
         dev = self.torch_device
         _check_gaussians(g, dev)
-        out = Gaussians(torch.empty_like(g.means), torch.empty_like(g.log_scales), torch.empty_like(g.quats),
-                        torch.empty_like(g.opacity_logits), torch.empty_like(g.colors), g.sh_degree)
+        out = g.like(*(torch.empty_like(t) for t in g.tensors()))
         nbytes = int(self.lib.gs_prune_workspace_bytes(g.n))
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
         nout = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -418,12 +446,10 @@ class Context:
                                _stream())
         self._check(rc)
         k = int(nout.item())
-        K = sh_coeffs(g.sh_degree)
-        pruned = Gaussians(out.means[:k], out.log_scales[:k], out.quats[:k], out.opacity_logits[:k], out.colors[:k],
-                           g.sh_degree)
+        pruned = g.like(*(t[:k] for t in out.tensors()))
         if adam is None:
             return pruned, None
-        keep = k * (11 + 3 * K) + 6 * V
+        keep = k * g.floats_per_gaussian + 6 * V
         return pruned, (m2[:keep], v2[:keep], adam[2])
 
     def densify(self, g: Gaussians, capacity: int, cams, poses: torch.Tensor, alpha: torch.Tensor,
@@ -440,15 +466,14 @@ class Context:
         if capacity < g.n:
             raise ValueError("capacity below the current count")
         K = sh_coeffs(g.sh_degree)
-        cap = Gaussians(torch.empty(capacity, 3, device=dev), torch.empty(capacity, 3, device=dev),
-                        torch.empty(capacity, 4, device=dev), torch.empty(capacity, device=dev),
-                        torch.empty((capacity, 3) if g.sh_degree < 0 else (capacity, K, 3), device=dev),
-                        g.sh_degree)
+        cap = g.like(torch.empty(capacity, 3, device=dev),
+                     torch.empty(capacity, 1 if g.isotropic else 3, device=dev),
+                     torch.empty(capacity, 0 if g.isotropic else 4, device=dev), torch.empty(capacity, device=dev),
+                     torch.empty((capacity, 3) if g.sh_degree < 0 else (capacity, K, 3), device=dev))
         for dst, src in zip(cap.tensors(), g.tensors()):
             dst[:g.n].copy_(src.reshape(dst[:g.n].shape))
-        held = Gaussians(*(t for t in cap.tensors()), g.sh_degree)
-        gst = A.gs_gaussians(g.n, g.sh_degree, _p(cap.means), _p(cap.log_scales), _p(cap.quats),
-                             _p(cap.opacity_logits), _p(cap.colors))
+        gst = cap.struct()
+        gst.n = g.n
         ca = cam_array(cams)
         nbytes = int(self.lib.gs_densify_workspace_bytes(ca, V))
         if nbytes == 0:
@@ -458,7 +483,7 @@ class Context:
         ain = aout = None
         if adam is not None:
             m, v, step = adam
-            m2 = torch.empty(capacity * (11 + 3 * K) + 6 * V, dtype=torch.float32, device=dev)
+            m2 = torch.empty(capacity * g.floats_per_gaussian + 6 * V, dtype=torch.float32, device=dev)
             v2 = torch.empty_like(m2)
             ain = A.gs_adam(_p(m), _p(v), _p(step))
             aout = A.gs_adam(_p(m2), _p(v2), _p(step))
@@ -474,11 +499,10 @@ class Context:
                                  _stream())
         self._check(rc)
         c0, c1 = (int(x) for x in counts.cpu())
-        out = Gaussians(held.means[:c0], held.log_scales[:c0], held.quats[:c0], held.opacity_logits[:c0],
-                        held.colors[:c0], g.sh_degree)
+        out = g.like(*(t[:c0] for t in cap.tensors()))
         if adam is None:
             return out, (c0, c1), None
-        keep = c0 * (11 + 3 * K) + 6 * V
+        keep = c0 * g.floats_per_gaussian + 6 * V
         return out, (c0, c1), (m2[:keep], v2[:keep], adam[2])
 
     def _bin(self, bin):
@@ -560,26 +584,26 @@ class GSRenderFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_tangent, poses, gs_ctx, cams,
-                sh_degree, tile):
+                sh_degree, isotropic, tile):
         g = Gaussians(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacity_logits.contiguous(),
-                      colors.contiguous(), sh_degree)
+                      colors.contiguous(), sh_degree, isotropic)
         rposes = gs_ctx.pose_retract(poses, pose_tangent)
         color, depth, alpha, state, plan = gs_ctx.forward(g, cams, rposes, tile=tile)
         ctx.save_for_backward(means, log_scales, quats, opacity_logits, colors, pose_tangent, rposes, state)
-        ctx.gs = (gs_ctx, cams, sh_degree, plan)
+        ctx.gs = (gs_ctx, cams, sh_degree, isotropic, plan)
         return color, depth, alpha
 
     @staticmethod
     def backward(ctx, dC, dD, dA):
         means, log_scales, quats, opacity_logits, colors, pose_tangent, rposes, state = ctx.saved_tensors
-        gs_ctx, cams, sh_degree, plan = ctx.gs
+        gs_ctx, cams, sh_degree, isotropic, plan = ctx.gs
         g = Gaussians(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacity_logits.contiguous(),
-                      colors.contiguous(), sh_degree)
+                      colors.contiguous(), sh_degree, isotropic)
         grads, dpose = gs_ctx.backward(g, cams, rposes, state, plan, dC, dD, dA)
         dxi = gs_ctx.pose_tangent_grad(pose_tangent, dpose)
         return (grads.means.view_as(means), grads.log_scales.view_as(log_scales), grads.quats.view_as(quats),
                 grads.opacity_logits.view_as(opacity_logits), grads.colors.view_as(colors),
-                dxi.view_as(pose_tangent), None, None, None, None, None)
+                dxi.view_as(pose_tangent), None, None, None, None, None, None)
 
 
 def render(g: Gaussians, cams, poses: torch.Tensor, pose_tangent: Optional[torch.Tensor] = None,
@@ -593,7 +617,8 @@ def render(g: Gaussians, cams, poses: torch.Tensor, pose_tangent: Optional[torch
     if pose_tangent is None:
         pose_tangent = torch.zeros(len(cams), 6, dtype=torch.float32, device=poses.device)
     return GSRenderFn.apply(g.means, g.log_scales, g.quats, g.opacity_logits, g.colors, pose_tangent,
-                            poses.detach().reshape(len(cams), 16).contiguous(), ctx, cams, g.sh_degree, tuple(tile))
+                            poses.detach().reshape(len(cams), 16).contiguous(), ctx, cams, g.sh_degree, g.isotropic,
+                            tuple(tile))
 
 
 class SSIMLossFn(torch.autograd.Function):
@@ -717,8 +742,7 @@ class MappingStep:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         self.ws[:64].zero_()     # the status words (the sticky flags start at zero)
         self.grads = g.zeros_like()
-        K = sh_coeffs(g.sh_degree)
-        na = g.n * (11 + 3 * K) + 6 * self.V
+        na = g.n * g.floats_per_gaussian + 6 * self.V
         self.adam_m = torch.zeros(na, dtype=torch.float32, device=dev)
         self.adam_v = torch.zeros(na, dtype=torch.float32, device=dev)
         self.adam_step = torch.zeros(2, dtype=torch.int32, device=dev)   # Gaussian updates, pose updates

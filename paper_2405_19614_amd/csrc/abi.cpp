@@ -210,16 +210,52 @@ int64_t max_tiles(const gs_camera* cams, int32_t V) {
     return t;
 }
 
+// every array the layout of g uses is non-NULL (the isotropic layout has no quaternions)
+bool arrays_ok(const gs_gaussians* g, const float* means, const float* ls, const float* q, const float* opl,
+               const float* col) {
+    return means && ls && (g->isotropic || q) && opl && col;
+}
+
 int check_gaussians(gs_ctx* c, const gs_gaussians* g) {
     if (!g) return fail(c, GS_EINVAL, "gaussians is NULL");
     if (g->n < 0) return fail(c, GS_EINVAL, "n is negative");
     if (g->sh_degree < -1 || g->sh_degree > 3) return fail(c, GS_EINVAL, "sh_degree=%d outside [-1, 3]", g->sh_degree);
+    if (g->isotropic != 0 && g->isotropic != 1) return fail(c, GS_EINVAL, "isotropic must be 0 or 1");
     if (g->n > 0) {
-        if (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->colors)
+        if (!arrays_ok(g, g->means, g->log_scales, g->quats, g->opacity_logits, g->colors))
             return fail(c, GS_EINVAL, "a Gaussian parameter pointer is NULL");
-        if (((uintptr_t)g->quats) % 16) return fail(c, GS_EINVAL, "quats must be 16-byte aligned");
+        if (!g->isotropic && ((uintptr_t)g->quats) % 16) return fail(c, GS_EINVAL, "quats must be 16-byte aligned");
     }
     return GS_OK;
+}
+
+bool grads_ok(const gs_gaussians* g, const gs_gaussian_grads* d) {
+    return d && arrays_ok(g, d->means, d->log_scales, d->quats, d->opacity_logits, d->colors);
+}
+
+// the Adam groups of g's layout: means, log-scales (log radii), quaternions
+// (none when isotropic), opacity logits, colours
+gs::AdamGroups adam_groups(const gs_gaussians* g, const gs_gaussian_grads* grads, const gs_step_opts* o) {
+    const int64_t n = g->n;
+    const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
+    gs::AdamGroups ag;
+    float* pp[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->colors};
+    const float* gg[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
+    const int64_t cnt[5] = {3 * n, g->isotropic ? n : 3 * n, g->isotropic ? 0 : 4 * n, n, 3 * K * n};
+    const float lr[5] = {o->lr_means, o->lr_log_scales, o->lr_quats, o->lr_opacity, o->lr_colors};
+    for (int i = 0; i < 5; i++) {
+        ag.p[i] = pp[i];
+        ag.g[i] = gg[i];
+        ag.cnt[i] = cnt[i];
+        ag.lr[i] = lr[i];
+    }
+    return ag;
+}
+
+// FP32 values per Gaussian in the parameter and Adam moment layouts
+int64_t gaussian_floats(const gs_gaussians* g) {
+    const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
+    return gs::floats_per_gaussian((int)(3 * K), g->isotropic);
 }
 
 gs::Params params_of(const gs_gaussians* g) {
@@ -231,6 +267,7 @@ gs::Params params_of(const gs_gaussians* g) {
     P.col = g->colors;
     P.n = (int)g->n;
     P.sh = g->sh_degree;
+    P.iso = g->isotropic;
     return P;
 }
 
@@ -595,8 +632,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     int r = check_gaussians(c, g);
     if (r) return r;
     if (!poses || !state || !dL_dpose || !grads) return fail(c, GS_EINVAL, "a device pointer is NULL");
-    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->colors))
-        return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if (g->n > 0 && !grads_ok(g, grads)) return fail(c, GS_EINVAL, "a gradient pointer is NULL");
     if (!tile_ok(plan->tile_w, plan->tile_h) || !bin_ok(plan->bin_w, plan->bin_h) ||
         !tile_ok(plan->bwd_tile_w, plan->bwd_tile_h))
         return fail(c, GS_EINVAL, "plan does not come from a forward pass");
@@ -695,27 +731,14 @@ int gs_adam_update(gs_ctx* c, gs_gaussians* g, const gs_gaussian_grads* grads, c
     if (r) return r;
     if (!adam || !adam->m || !adam->v || !adam->step) return fail(c, GS_EINVAL, "the Adam state is incomplete");
     if (V < 0 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V=%d outside [0, %d]", V, GS_MAX_VIEWS);
-    if (o->update_gaussians && g->n > 0 &&
-        (!grads || !grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->colors))
-        return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if (o->update_gaussians && g->n > 0 && !grads_ok(g, grads)) return fail(c, GS_EINVAL, "a gradient pointer is NULL");
     if (o->update_poses && V > 0 && (!poses || !dL_dpose)) return fail(c, GS_EINVAL, "poses or dL_dpose is NULL");
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = g->n;
-    const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
-    const int64_t np = n * (11 + 3 * K);
+    const int64_t np = n * gaussian_floats(g);
     if (o->update_gaussians) {
-        gs::AdamGroups ag;
-        float* pp[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->colors};
-        const float* gg[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
-        const int64_t cnt[5] = {3 * n, 3 * n, 4 * n, n, 3 * K * n};
-        const float lr[5] = {o->lr_means, o->lr_log_scales, o->lr_quats, o->lr_opacity, o->lr_colors};
-        for (int i = 0; i < 5; i++) {
-            ag.p[i] = pp[i];
-            ag.g[i] = gg[i];
-            ag.cnt[i] = cnt[i];
-            ag.lr[i] = lr[i];
-        }
+        const gs::AdamGroups ag = adam_groups(g, grads, o);
         GS_HIP(c, gs::launch_adam(ag, adam->m, adam->v, adam->step, o->adam_b1, o->adam_b2, o->adam_eps, nullptr, s));
     }
     if (o->update_poses && V > 0)
@@ -810,7 +833,7 @@ int gs_prune(gs_ctx* c, const gs_gaussians* in, double tau, gs_gaussians* out, c
     int r = check_gaussians(c, in);
     if (r) return r;
     if (!out || !n_out || !ws) return fail(c, GS_EINVAL, "a required pointer is NULL");
-    if (in->n > 0 && (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->colors))
+    if (in->n > 0 && !arrays_ok(in, out->means, out->log_scales, out->quats, out->opacity_logits, out->colors))
         return fail(c, GS_EINVAL, "an output array is NULL");
     if (in->n >= ((int64_t)1 << 31)) return fail(c, GS_EINVAL, "n too large");
     if (V < 0 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V outside [0, %d]", GS_MAX_VIEWS);
@@ -848,9 +871,10 @@ int gs_densify(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, 
         return fail(c, GS_EINVAL, "a required pointer is NULL");
     if (g->n < 0 || capacity < g->n || capacity >= ((int64_t)1 << 31))
         return fail(c, GS_EINVAL, "need 0 <= n <= capacity < 2^31");
-    if (capacity > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->colors))
+    if (capacity > 0 && !arrays_ok(g, g->means, g->log_scales, g->quats, g->opacity_logits, g->colors))
         return fail(c, GS_EINVAL, "a Gaussian array is NULL");
     if (g->sh_degree < -1 || g->sh_degree > 3) return fail(c, GS_EINVAL, "sh_degree outside [-1, 3]");
+    if (g->isotropic != 0 && g->isotropic != 1) return fail(c, GS_EINVAL, "isotropic must be 0 or 1");
     if (std::isnan(gamma)) return fail(c, GS_EINVAL, "gamma is NaN");
     gs::ViewTable vt;
     int r = build_vt(c, cams, V, 0, 16, 16, 64, 64, 0.f, 0.f, vt);
@@ -865,8 +889,8 @@ int gs_densify(gs_ctx* c, const gs_camera* cams, const float* poses, int32_t V, 
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     gs::GaussOut o{g->means, g->log_scales, g->quats, g->opacity_logits, g->colors};
-    GS_HIP(c, gs::launch_densify(vt, poses, alpha, tgt_color, tgt_depth, gamma, all_pixels, o, (int)g->n, K, capacity,
-                                 ha ? &io : nullptr, flag, off, bsum, total, counts, s));
+    GS_HIP(c, gs::launch_densify(vt, poses, alpha, tgt_color, tgt_depth, gamma, all_pixels, o, (int)g->n, K,
+                                 g->isotropic, capacity, ha ? &io : nullptr, flag, off, bsum, total, counts, s));
     return GS_OK;
 }
 
@@ -933,21 +957,9 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
                                        o->w_reproj / (float)vt.V, dL_dpose, s));
     GS_HIP(c, mark(7));
     if (o->update_gaussians || o->update_poses) {
-        const int64_t n = g->n;
-        const int64_t K = g->sh_degree < 0 ? 1 : (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
-        const int64_t np = n * (11 + 3 * K);
+        const int64_t np = g->n * gaussian_floats(g);
         if (o->update_gaussians) {
-            gs::AdamGroups ag;
-            float* pp[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->colors};
-            const float* gg[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
-            const int64_t cnt[5] = {3 * n, 3 * n, 4 * n, n, 3 * K * n};
-            const float lr[5] = {o->lr_means, o->lr_log_scales, o->lr_quats, o->lr_opacity, o->lr_colors};
-            for (int i = 0; i < 5; i++) {
-                ag.p[i] = pp[i];
-                ag.g[i] = gg[i];
-                ag.cnt[i] = cnt[i];
-                ag.lr[i] = lr[i];
-            }
+            const gs::AdamGroups ag = adam_groups(g, grads, o);
             GS_HIP(c, gs::launch_adam(ag, adam->m, adam->v, adam->step, o->adam_b1, o->adam_b2, o->adam_eps,
                                       p.scal + gs::kFlags, s));
         }
@@ -975,8 +987,7 @@ int check_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_ad
     if (r) return r;
     if (!grads || !poses || !tg || !ws || !color || !depth || !alpha || !loss_out || !dL_dpose)
         return fail(c, GS_EINVAL, "a required pointer is NULL");
-    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->colors))
-        return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if (g->n > 0 && !grads_ok(g, grads)) return fail(c, GS_EINVAL, "a gradient pointer is NULL");
     if (!tg->color || !tg->depth) return fail(c, GS_EINVAL, "target colour / depth is NULL");
     if (mt && mt->M > 0) {
         if (!mt->points || !mt->uv || !mt->view_idx) return fail(c, GS_EINVAL, "a match pointer is NULL");
@@ -1099,8 +1110,8 @@ int gs_step_profile(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const 
     };
     hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t*>(c->counts), 0u, 8, s);
     if (e != hipSuccess) { destroy(); return hip_fail(c, e, "counter fill"); }
-    r = enqueue_step(c, vt, vtb, L, static_cast<char*>(ws), g, grads, adam, poses, tg, mt, o, color, depth, alpha, loss_out,
-                     dL_dpose, s, ev, frag_counts ? c->counts : nullptr);
+    r = enqueue_step(c, vt, vtb, L, static_cast<char*>(ws), g, grads, adam, poses, tg, mt, o, color, depth, alpha,
+                     loss_out, dL_dpose, s, ev, frag_counts ? c->counts : nullptr);
     if (r) { destroy(); return r; }
     unsigned long long hc[4] = {0, 0, 0, 0};
     e = hipMemcpyAsync(hc, c->counts, sizeof hc, hipMemcpyDeviceToHost, s);
@@ -1189,6 +1200,7 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
     key = fnv(key, cams, sizeof(gs_camera) * V);
     key = fnv(key, &g->n, sizeof g->n);
     key = fnv(key, &g->sh_degree, sizeof g->sh_degree);
+    key = fnv(key, &g->isotropic, sizeof g->isotropic);
     auto apply = [&](const gs_ctx::Tuned& t) {
         c->tile_w = *tile_w = t.tw;
         c->tile_h = *tile_h = t.th;
@@ -1222,7 +1234,7 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
         bufs.clear();
     };
     float* img = static_cast<float*>(dalloc((size_t)npix * 5 * 4));
-    float* gr = static_cast<float*>(dalloc((size_t)n * (11 + 3 * K) * 4));
+    float* gr = static_cast<float*>(dalloc((size_t)n * gaussian_floats(g) * 4));
     float* dpose = static_cast<float*>(dalloc((size_t)V * 6 * 4));
     if (!img || !gr || !dpose) {
         release();
@@ -1232,7 +1244,8 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
         release();
         return fail(c, GS_EDEVICE, "autotune fill failed");
     }
-    gs_gaussian_grads G{gr, gr + 3 * n, gr + 6 * n, gr + 10 * n, gr + 11 * n};
+    const int64_t nls = g->isotropic ? n : 3 * n, nq = g->isotropic ? 0 : 4 * n;
+    gs_gaussian_grads G{gr, gr + 3 * n, gr + 3 * n + nls, gr + 3 * n + nls + nq, gr + 4 * n + nls + nq};
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);

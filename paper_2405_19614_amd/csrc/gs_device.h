@@ -182,17 +182,32 @@ struct Proj {
 };
 
 // View-independent part of a Gaussian's projection: activations and the
-// world covariance M = R diag(s^2) R^T.
+// world covariance M = R diag(s^2) R^T (isotropic: r^2 I, no rotation).
 struct GPrep {
     bool ok;
-    bool finite;        // mean, log-scales, quaternion and opacity logit all finite
+    bool finite;        // mean, log-scales (radius), quaternion and opacity logit all finite
     float qn, qh[4], R[9], s[3], o;
     float mu[3];
     float M[6];
 };
 
+template <bool ISO>
 __device__ __forceinline__ void gauss_prep(const Params& P, int g, GPrep& gp) {
     gp.ok = false;
+    if (ISO) {
+        // the paper's Gaussian: one radius r = exp(log r), covariance r^2 I
+        const float l = P.ls[g];
+        const float* mp = P.means + 3 * (int64_t)g;
+        gp.finite = __builtin_isfinite((mp[0] + mp[1] + mp[2]) + l + P.opl[g]);
+        gp.ok = true;
+        const float r = expf(l);
+        gp.s[0] = gp.s[1] = gp.s[2] = r;
+        gp.o = 1.f / (1.f + expf(-P.opl[g]));
+        gp.mu[0] = mp[0]; gp.mu[1] = mp[1]; gp.mu[2] = mp[2];
+        const float r2 = r * r;
+        gp.M[0] = r2; gp.M[1] = 0.f; gp.M[2] = 0.f; gp.M[3] = r2; gp.M[4] = 0.f; gp.M[5] = r2;
+        return;
+    }
     const float4 q = reinterpret_cast<const float4*>(P.q)[g];
     {
         const float* lp = P.ls + 3 * (int64_t)g;
@@ -225,17 +240,21 @@ __device__ __forceinline__ void gauss_prep(const Params& P, int g, GPrep& gp) {
 }
 
 // Project a prepared Gaussian g into view vi with pose T (row-major 4x4,
-// world->camera).  COL: also evaluate the colour (RGB or SH).
-template <bool COL>
+// world->camera).  COL: also evaluate the colour (RGB or SH).  ISO: the
+// camera covariance of r^2 I is r^2 I (a rigid motion keeps it), so the 2D
+// covariance is r^2 J J^T + 0.3 I; on the optical axis r2D = f r / d.
+template <bool COL, bool ISO>
 __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep& gp, const ViewInfo& vi,
                                              const float* T, Proj& o) {
     o.valid = false;
     if (!gp.ok) return;
-    o.qn = gp.qn;
+    if (!ISO) {
+        o.qn = gp.qn;
 #pragma unroll
-    for (int k = 0; k < 4; k++) o.qh[k] = gp.qh[k];
+        for (int k = 0; k < 4; k++) o.qh[k] = gp.qh[k];
 #pragma unroll
-    for (int k = 0; k < 9; k++) o.R[k] = gp.R[k];
+        for (int k = 0; k < 9; k++) o.R[k] = gp.R[k];
+    }
     o.s[0] = gp.s[0]; o.s[1] = gp.s[1]; o.s[2] = gp.s[2];
     o.o = gp.o;
 
@@ -264,7 +283,13 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
 
     // Sigma_c = W M W^T with the world covariance M of gauss_prep
     const float* M = gp.M;
-    {
+    if (ISO) {
+        o.Sc[0] = M[0]; o.Sc[1] = 0.f; o.Sc[2] = 0.f; o.Sc[3] = M[0]; o.Sc[4] = 0.f; o.Sc[5] = M[0];
+        const float r2 = M[0];
+        o.a = r2 * (o.j00 * o.j00 + o.j02 * o.j02) + kDilate;
+        o.b = r2 * (o.j02 * o.j12);
+        o.c = r2 * (o.j11 * o.j11 + o.j12 * o.j12) + kDilate;
+    } else {
         // WM = W * M (full 3x3), Sc = WM * W^T (symmetric)
         float Mf[9] = {M[0], M[1], M[2], M[1], M[3], M[4], M[2], M[4], M[5]};
         float WM[9];
@@ -281,7 +306,7 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
         o.Sc[5] = WM[6] * T[8] + WM[7] * T[9] + WM[8] * T[10];
     }
     // Sigma_2D = J Sc J^T with J = [[j00, 0, j02], [0, j11, j12]]
-    {
+    if (!ISO) {
         const float* S = o.Sc;
         const float r00 = o.j00 * S[0] + o.j02 * S[2], r01 = o.j00 * S[1] + o.j02 * S[4],
                     r02 = o.j00 * S[2] + o.j02 * S[5];
@@ -336,13 +361,6 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
     if (!(fx0 <= fx1) || !(fy0 <= fy1)) return;
     o.x0 = (int)fx0; o.x1 = (int)fx1; o.y0 = (int)fy0; o.y1 = (int)fy1;
     o.valid = true;
-}
-
-template <bool COL>
-__device__ __forceinline__ void project_one(const Params& P, int g, const ViewInfo& vi, const float* T, Proj& o) {
-    GPrep gp;
-    gauss_prep(P, g, gp);
-    project_view<COL>(P, g, gp, vi, T, o);
 }
 
 // Records keep the conic in base-2 units with the opacity folded in:

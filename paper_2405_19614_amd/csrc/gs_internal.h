@@ -85,7 +85,9 @@ inline TileGrid tile_grid(const ViewTable& vt) {
     return g;
 }
 
-// Gaussian parameters (device, FP32 SoA).
+// Gaussian parameters (device, FP32 SoA).  Anisotropic: ls [n][3] log-scales,
+// q [n][4] quaternions.  Isotropic (iso = 1, the paper's eight-parameter
+// Gaussian): ls [n] log radii, q unused.
 struct Params {
     const float* means;
     const float* ls;
@@ -94,7 +96,11 @@ struct Params {
     const float* col;
     int n;
     int sh;         // -1 = RGB
+    int iso;
 };
+
+// floats per Gaussian in the parameter (and Adam moment) layout
+__host__ __device__ inline int64_t floats_per_gaussian(int K3, int iso) { return (iso ? 5 : 11) + (int64_t)K3; }
 
 struct Grads {
     float* means;
@@ -335,7 +341,7 @@ struct GaussOut {
     float* col;
 };
 // Adam moments (m, v) of a layout for n Gaussians: groups of width 3, 3, 4,
-// 1, 3K floats per Gaussian, then 6V pose floats
+// 1, 3K floats per Gaussian (isotropic: 3, 1, 0, 1, 3K), then 6V pose floats
 struct AdamIO {
     const float* m_in;
     const float* v_in;
@@ -355,9 +361,9 @@ hipError_t launch_prune(const Params& in, int K3, double logit_tau, GaussOut out
 // now held, Gaussians the selection asked for); scratch as for pruning over
 // the n_pix pixels
 hipError_t launch_densify(const ViewTable& vt, const float* poses, const float* alpha, const float* tc,
-                          const float* td, double gamma, int all_pixels, GaussOut g, int n, int K, int64_t capacity,
-                          const AdamIO* adam, uint32_t* flag, uint32_t* off, uint32_t* bsum, uint32_t* total,
-                          int64_t* counts, hipStream_t s);
+                          const float* td, double gamma, int all_pixels, GaussOut g, int n, int K, int iso,
+                          int64_t capacity, const AdamIO* adam, uint32_t* flag, uint32_t* off, uint32_t* bsum,
+                          uint32_t* total, int64_t* counts, hipStream_t s);
 
 struct AdamGroups {
     float* p[5];

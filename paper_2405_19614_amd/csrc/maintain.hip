@@ -7,7 +7,8 @@
 // isotropic Gaussian for every pixel outside the border mask (rendered alpha
 // <= gamma; every pixel on the first frame) that has a sensor depth: the
 // pixel's sample point back-projected to that depth, radius depth / fx (a
-// one-pixel footprint, Eq. d), identity rotation, opacity 1/2, the target
+// one-pixel footprint, Eq. d; every axis, or the one radius of the isotropic
+// layout), identity rotation, opacity 1/2, the target
 // colour (with SH, in the DC coefficient).  New Gaussians follow the existing
 // ones in view, then row-major pixel order.
 #include "gs_internal.h"
@@ -35,25 +36,28 @@ __global__ void prune_scatter_kernel(Params in, int K3, GaussOut out, const uint
         if (!flag[i]) continue;
         const int64_t j = off[i];
 #pragma unroll
-        for (int e = 0; e < 3; e++) {
-            out.means[3 * j + e] = in.means[3 * i + e];
-            out.ls[3 * j + e] = in.ls[3 * i + e];
-        }
+        for (int e = 0; e < 3; e++) out.means[3 * j + e] = in.means[3 * i + e];
+        if (in.iso) {
+            out.ls[j] = in.ls[i];
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; e++) out.q[4 * j + e] = in.q[4 * i + e];
+            for (int e = 0; e < 3; e++) out.ls[3 * j + e] = in.ls[3 * i + e];
+#pragma unroll
+            for (int e = 0; e < 4; e++) out.q[4 * j + e] = in.q[4 * i + e];
+        }
         out.opl[j] = in.opl[i];
         for (int e = 0; e < K3; e++) out.col[K3 * j + e] = in.col[K3 * i + e];
     }
 }
 
 // moments of a kept Gaussian i -> new slot off[i]; the new count is *total
-__global__ void prune_adam_kernel(AdamIO a, int64_t n, int K3, int V, const uint32_t* __restrict__ flag,
+__global__ void prune_adam_kernel(AdamIO a, int64_t n, int K3, int iso, int V, const uint32_t* __restrict__ flag,
                                   const uint32_t* __restrict__ off, const uint32_t* __restrict__ total) {
     const int64_t nn = *total;
-    const int w[5] = {3, 3, 4, 1, K3};
+    const int w[5] = {3, iso ? 1 : 3, iso ? 0 : 4, 1, K3};
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid == 0) {
-        const int64_t po = (int64_t)(11 + K3) * n, pn = (int64_t)(11 + K3) * nn;
+        const int64_t po = floats_per_gaussian(K3, iso) * n, pn = floats_per_gaussian(K3, iso) * nn;
         for (int e = 0; e < 6 * V; e++) {
             a.m_out[pn + e] = a.m_in[po + e];
             a.v_out[pn + e] = a.v_in[po + e];
@@ -104,8 +108,9 @@ __global__ void densify_flags_kernel(ViewTable vt, const float* __restrict__ alp
 }
 
 __global__ void densify_write_kernel(ViewTable vt, const float* __restrict__ poses, const float* __restrict__ tc,
-                                     const float* __restrict__ td, GaussOut g, int n, int K, int64_t capacity,
-                                     const uint32_t* __restrict__ flag, const uint32_t* __restrict__ off) {
+                                     const float* __restrict__ td, GaussOut g, int n, int K, int iso,
+                                     int64_t capacity, const uint32_t* __restrict__ flag,
+                                     const uint32_t* __restrict__ off) {
     const int64_t np = vt.n_pix;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
         if (!flag[p]) continue;
@@ -124,12 +129,16 @@ __global__ void densify_write_kernel(ViewTable vt, const float* __restrict__ pos
 #pragma unroll
         for (int e = 0; e < 3; e++) g.means[3 * j + e] = R[e] * pc0 + R[4 + e] * pc1 + R[8 + e] * pc2;
         const float lsv = logf(d / vi.fx);
+        if (iso) {
+            g.ls[j] = lsv;
+        } else {
 #pragma unroll
-        for (int e = 0; e < 3; e++) g.ls[3 * j + e] = lsv;
-        g.q[4 * j] = 1.f;
-        g.q[4 * j + 1] = 0.f;
-        g.q[4 * j + 2] = 0.f;
-        g.q[4 * j + 3] = 0.f;
+            for (int e = 0; e < 3; e++) g.ls[3 * j + e] = lsv;
+            g.q[4 * j] = 1.f;
+            g.q[4 * j + 1] = 0.f;
+            g.q[4 * j + 2] = 0.f;
+            g.q[4 * j + 3] = 0.f;
+        }
         g.opl[j] = 0.f;
         const int64_t hw = (int64_t)vi.W * vi.H;
         const int64_t ci = 3 * (int64_t)vi.pix_off + pl;
@@ -147,13 +156,13 @@ __global__ void densify_write_kernel(ViewTable vt, const float* __restrict__ pos
 
 // moments for the grown layout: existing Gaussians keep theirs, new ones
 // start at zero; the new count is counts[0]
-__global__ void densify_adam_kernel(AdamIO a, int64_t n, int K3, int V, const int64_t* __restrict__ counts,
+__global__ void densify_adam_kernel(AdamIO a, int64_t n, int K3, int iso, int V, const int64_t* __restrict__ counts,
                                     int64_t capacity) {
     const int64_t nn = counts[0];
-    const int w[5] = {3, 3, 4, 1, K3};
+    const int w[5] = {3, iso ? 1 : 3, iso ? 0 : 4, 1, K3};
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid == 0) {
-        const int64_t po = (int64_t)(11 + K3) * n, pn = (int64_t)(11 + K3) * nn;
+        const int64_t po = floats_per_gaussian(K3, iso) * n, pn = floats_per_gaussian(K3, iso) * nn;
         for (int e = 0; e < 6 * V; e++) {
             a.m_out[pn + e] = a.m_in[po + e];
             a.v_out[pn + e] = a.v_in[po + e];
@@ -193,22 +202,23 @@ hipError_t launch_prune(const Params& in, int K3, double logit_tau, GaussOut out
     hipError_t e = launch_scan_u32(flag, n, off, bsum, total, s);
     if (e != hipSuccess) return e;
     if (n > 0) prune_scatter_kernel<<<grid_for(n), 256, 0, s>>>(in, K3, out, flag, off);
-    if (adam) prune_adam_kernel<<<grid_for(n), 256, 0, s>>>(*adam, n, K3, V, flag, off, total);
+    if (adam) prune_adam_kernel<<<grid_for(n), 256, 0, s>>>(*adam, n, K3, in.iso, V, flag, off, total);
     store_count_kernel<<<1, 1, 0, s>>>(total, 0, (int64_t)1 << 62, n_out, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_densify(const ViewTable& vt, const float* poses, const float* alpha, const float* tc,
-                          const float* td, double gamma, int all_pixels, GaussOut g, int n, int K, int64_t capacity,
-                          const AdamIO* adam, uint32_t* flag, uint32_t* off, uint32_t* bsum, uint32_t* total,
-                          int64_t* counts, hipStream_t s) {
+                          const float* td, double gamma, int all_pixels, GaussOut g, int n, int K, int iso,
+                          int64_t capacity, const AdamIO* adam, uint32_t* flag, uint32_t* off, uint32_t* bsum,
+                          uint32_t* total, int64_t* counts, hipStream_t s) {
     const int64_t np = vt.n_pix;
     densify_flags_kernel<<<grid_for(np), 256, 0, s>>>(vt, alpha, td, gamma, all_pixels, flag);
     hipError_t e = launch_scan_u32(flag, np, off, bsum, total, s);
     if (e != hipSuccess) return e;
-    densify_write_kernel<<<grid_for(np), 256, 0, s>>>(vt, poses, tc, td, g, n, K, capacity, flag, off);
+    densify_write_kernel<<<grid_for(np), 256, 0, s>>>(vt, poses, tc, td, g, n, K, iso, capacity, flag, off);
     store_count_kernel<<<1, 1, 0, s>>>(total, n, capacity, counts, 1);
-    if (adam) densify_adam_kernel<<<grid_for(capacity), 256, 0, s>>>(*adam, n, 3 * K, vt.V, counts, capacity);
+    if (adam)
+        densify_adam_kernel<<<grid_for(capacity), 256, 0, s>>>(*adam, n, 3 * K, iso, vt.V, counts, capacity);
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ constexpr int kProjChunk = 16;
 // visible view.  Instead each round of kProjChunk views queues its visible
 // pairs in LDS (geometry already written), and the block then evaluates the
 // colours of the queued pairs with every lane busy.
-template <int SH>
+template <int SH, bool ISO>
 __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt, Params P, const float* poses,
                                                                     Records rec, bool zero_g2, uint32_t* flags) {
     constexpr bool DEFER = SH >= 0;
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
     GPrep gp;
     gp.ok = false;
     gp.finite = true;
-    if (live) gauss_prep(P, g, gp);
+    if (live) gauss_prep<ISO>(P, g, gp);
     bool bad = !gp.finite;
     uint64_t vm = 0;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
 #pragma unroll
                 for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
                 Proj pr;
-                project_view<!DEFER>(P, g, gp, vi, T, pr);
+                project_view<!DEFER, ISO>(P, g, gp, vi, T, pr);
                 const int64_t r = (int64_t)v * P.n + g;
                 if (pr.valid) {
                     const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
@@ -349,8 +349,11 @@ __global__ __launch_bounds__(kProjBlock, 4) void sh_bwd_kernel(ViewTable vt, Par
 // order, with no barrier inside the walk.
 // With SH colours the colour part runs in sh_bwd_kernel first: this kernel
 // then adds its mean and pose gradients to what that one wrote.  At most 128
-// VGPRs (four waves per SIMD; it fits without spilling).
-template <int SH>
+// VGPRs (four waves per SIMD; it fits without spilling).  ISO: the camera
+// covariance r^2 I does not turn with the camera, so the covariance gradient
+// reaches only the log radius (2 r^2 trace of dL/dSigma_c) and the pose only
+// through the mean.
+template <int SH, bool ISO>
 __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable vt, Params P, const float* poses,
                                                                     const uint64_t* vmask, const float* g2, Grads G,
                                                                     int accumulate, double* pose_part,
@@ -375,8 +378,12 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
             block_zero(G.means, 3 * g0, 3 * g1);
             block_zero(G.col, 3 * g0, 3 * g1);
         }
-        block_zero(G.ls, 3 * g0, 3 * g1);
-        block_zero(G.q, 4 * g0, 4 * g1);
+        if (ISO) {
+            block_zero(G.ls, g0, g1);
+        } else {
+            block_zero(G.ls, 3 * g0, 3 * g1);
+            block_zero(G.q, 4 * g0, 4 * g1);
+        }
         block_zero(G.opl, g0, g1);
     }
     const int total = pack_visible(P, vmask, g0, s_loc, s_mask, s_cnt);
@@ -391,7 +398,7 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
         float gc[3] = {0.f, 0.f, 0.f};   // RGB only
         GPrep gp;
         gp.ok = false;
-        if (live) gauss_prep(P, g, gp);
+        if (live) gauss_prep<ISO>(P, g, gp);
 
         for (int v = 0; v < V; v++) {
             float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -404,7 +411,7 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
 #pragma unroll
                 for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
                 Proj pr;
-                project_view<false>(P, g, gp, vi, T, pr);
+                project_view<false, ISO>(P, g, gp, vi, T, pr);
                 const float4* a4 = reinterpret_cast<const float4*>(g2 + r * kG2Stride);
                 const float4 a0 = a4[0], a1 = a4[1], a2 = a4[2];
                 // undo the compositing kernel's constant factors (g2 layout)
@@ -472,50 +479,56 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
                     dpz += dJ12 * vi.fy * (pr.ty * iz) * iz2;
                 }
 
-                // world covariance gradient: GS = W^T Gs W
-                float t1[9], GS[9];
+                if (ISO) {
+                    // Sc = r^2 I: dL/dlog r = 2 r^2 (Gs_xx + Gs_yy + Gs_zz)
+                    gl[0] += 2.f * pr.s[0] * pr.s[0] * (Gs[0] + Gs[4] + Gs[8]);
+                } else {
+                    // world covariance gradient: GS = W^T Gs W
+                    float t1[9], GS[9];
 #pragma unroll
-                for (int r_ = 0; r_ < 3; r_++)
+                    for (int r_ = 0; r_ < 3; r_++)
 #pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        t1[3 * r_ + c] = T[r_] * Gs[c] + T[4 + r_] * Gs[3 + c] + T[8 + r_] * Gs[6 + c];
+                        for (int c = 0; c < 3; c++)
+                            t1[3 * r_ + c] = T[r_] * Gs[c] + T[4 + r_] * Gs[3 + c] + T[8 + r_] * Gs[6 + c];
 #pragma unroll
-                for (int r_ = 0; r_ < 3; r_++)
+                    for (int r_ = 0; r_ < 3; r_++)
 #pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        GS[3 * r_ + c] = t1[3 * r_] * T[c] + t1[3 * r_ + 1] * T[4 + c] + t1[3 * r_ + 2] * T[8 + c];
+                        for (int c = 0; c < 3; c++)
+                            GS[3 * r_ + c] = t1[3 * r_] * T[c] + t1[3 * r_ + 1] * T[4 + c] + t1[3 * r_ + 2] * T[8 + c];
 
-                // Sigma = R diag(s^2) R^T
-                float GR[9];
+                    // Sigma = R diag(s^2) R^T
+                    float GR[9];
 #pragma unroll
-                for (int r_ = 0; r_ < 3; r_++)
+                    for (int r_ = 0; r_ < 3; r_++)
 #pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        GR[3 * r_ + c] = GS[3 * r_] * pr.R[c] + GS[3 * r_ + 1] * pr.R[3 + c] + GS[3 * r_ + 2] * pr.R[6 + c];
+                        for (int c = 0; c < 3; c++)
+                            GR[3 * r_ + c] =
+                                GS[3 * r_] * pr.R[c] + GS[3 * r_ + 1] * pr.R[3 + c] + GS[3 * r_ + 2] * pr.R[6 + c];
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    // (R^T GS R)_kk = sum_r R[r][k] GR[r][k]
-                    const float rgr = pr.R[k] * GR[k] + pr.R[3 + k] * GR[3 + k] + pr.R[6 + k] * GR[6 + k];
-                    gl[k] += 2.f * pr.s[k] * pr.s[k] * rgr;
+                    for (int k = 0; k < 3; k++) {
+                        // (R^T GS R)_kk = sum_r R[r][k] GR[r][k]
+                        const float rgr = pr.R[k] * GR[k] + pr.R[3 + k] * GR[3 + k] + pr.R[6 + k] * GR[6 + k];
+                        gl[k] += 2.f * pr.s[k] * pr.s[k] * rgr;
+                    }
+                    float dR[9];
+#pragma unroll
+                    for (int r_ = 0; r_ < 3; r_++)
+#pragma unroll
+                        for (int c = 0; c < 3; c++) dR[3 * r_ + c] = 2.f * GR[3 * r_ + c] * pr.s[c] * pr.s[c];
+                    const float w = pr.qh[0], x = pr.qh[1], y = pr.qh[2], z = pr.qh[3];
+                    float dq[4];
+                    dq[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+                    dq[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] +
+                                   w * dR[7] - 2.f * x * dR[8]);
+                    dq[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                                   z * dR[7] - 2.f * y * dR[8]);
+                    dq[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] +
+                                   x * dR[6] + y * dR[7]);
+                    const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+                    const float iqn = 1.f / pr.qn;
+#pragma unroll
+                    for (int k = 0; k < 4; k++) gq[k] += (dq[k] - pr.qh[k] * qd) * iqn;
                 }
-                float dR[9];
-#pragma unroll
-                for (int r_ = 0; r_ < 3; r_++)
-#pragma unroll
-                    for (int c = 0; c < 3; c++) dR[3 * r_ + c] = 2.f * GR[3 * r_ + c] * pr.s[c] * pr.s[c];
-                const float w = pr.qh[0], x = pr.qh[1], y = pr.qh[2], z = pr.qh[3];
-                float dq[4];
-                dq[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-                dq[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
-                               2.f * x * dR[8]);
-                dq[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
-                               2.f * y * dR[8]);
-                dq[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] +
-                               x * dR[6] + y * dR[7]);
-                const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-                const float iqn = 1.f / pr.qn;
-#pragma unroll
-                for (int k = 0; k < 4; k++) gq[k] += (dq[k] - pr.qh[k] * qd) * iqn;
 
                 // p = W mu + t
                 dmu[0] += T[0] * dpx + T[4] * dpy + T[8] * dpz;
@@ -534,9 +547,9 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
                     return Sf[3 * i] * Gs[j] + Sf[3 * i + 1] * Gs[3 + j] + Sf[3 * i + 2] * Gs[6 + j] -
                            (Gs[3 * i] * Sf[j] + Gs[3 * i + 1] * Sf[3 + j] + Gs[3 * i + 2] * Sf[6 + j]);
                 };
-                pose[3] = py * dpz - pz * dpy + 2.f * Nij(1, 2);
-                pose[4] = pz * dpx - px * dpz + 2.f * Nij(2, 0);
-                pose[5] = px * dpy - py * dpx + 2.f * Nij(0, 1);
+                pose[3] = py * dpz - pz * dpy + (ISO ? 0.f : 2.f * Nij(1, 2));
+                pose[4] = pz * dpx - px * dpz + (ISO ? 0.f : 2.f * Nij(2, 0));
+                pose[5] = px * dpy - py * dpx + (ISO ? 0.f : 2.f * Nij(0, 1));
             }
             float ps[6];
 #pragma unroll
@@ -548,22 +561,29 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
         }
         if (live) {
             float* om = G.means + 3 * (int64_t)g;
-            float* ol = G.ls + 3 * (int64_t)g;
-            float* oq = G.q + 4 * (int64_t)g;
             if (accumulate) {
 #pragma unroll
-                for (int k = 0; k < 3; k++) { om[k] += gm[k]; ol[k] += gl[k]; }
+                for (int k = 0; k < 3; k++) om[k] += gm[k];
+                if (ISO) {
+                    G.ls[g] += gl[0];
+                } else {
 #pragma unroll
-                for (int k = 0; k < 4; k++) oq[k] += gq[k];
+                    for (int k = 0; k < 3; k++) G.ls[3 * (int64_t)g + k] += gl[k];
+#pragma unroll
+                    for (int k = 0; k < 4; k++) G.q[4 * (int64_t)g + k] += gq[k];
+                }
                 G.opl[g] += go;
             } else {
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    om[k] = SH < 0 ? gm[k] : om[k] + gm[k];   // SH: add to the colour path's share
-                    ol[k] = gl[k];
-                }
+                for (int k = 0; k < 3; k++) om[k] = SH < 0 ? gm[k] : om[k] + gm[k];   // SH: add to the colour share
+                if (ISO) {
+                    G.ls[g] = gl[0];
+                } else {
 #pragma unroll
-                for (int k = 0; k < 4; k++) oq[k] = gq[k];
+                    for (int k = 0; k < 3; k++) G.ls[3 * (int64_t)g + k] = gl[k];
+#pragma unroll
+                    for (int k = 0; k < 4; k++) G.q[4 * (int64_t)g + k] = gq[k];
+                }
                 G.opl[g] = go;
             }
             if (SH < 0) {
@@ -612,21 +632,56 @@ __global__ __launch_bounds__(256) void pose_finalize_kernel(const double* part, 
     }
 }
 
+template <int SH, bool ISO>
+void fwd_one(const ViewTable& vt, const Params& P, const float* poses, Records rec, bool zero_g2, hipStream_t s,
+             uint32_t* flags) {
+    const unsigned nb = (unsigned)((P.n + kProjBlock - 1) / kProjBlock);
+    preprocess_fwd_kernel<SH, ISO><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags);
+}
+
+template <bool ISO>
+hipError_t fwd_sh(const ViewTable& vt, const Params& P, const float* poses, Records rec, bool zero_g2, hipStream_t s,
+                  uint32_t* flags) {
+    switch (P.sh) {
+        case -1: fwd_one<-1, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
+        case 0: fwd_one<0, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
+        case 1: fwd_one<1, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
+        case 2: fwd_one<2, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
+        case 3: fwd_one<3, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int SH, bool ISO>
+void bwd_one(const ViewTable& vt, const Params& P, const float* poses, const uint64_t* vm, const float* g2, Grads G,
+             int accumulate, double* pose_part, int nb, hipStream_t s) {
+    if constexpr (SH >= 0)
+        sh_bwd_kernel<SH><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+    preprocess_bwd_kernel<SH, ISO><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+}
+
+template <bool ISO>
+hipError_t bwd_sh(const ViewTable& vt, const Params& P, const float* poses, const uint64_t* vm, const float* g2,
+                  Grads G, int accumulate, double* pose_part, int nb, hipStream_t s) {
+    switch (P.sh) {
+        case -1: bwd_one<-1, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
+        case 0: bwd_one<0, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
+        case 1: bwd_one<1, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
+        case 2: bwd_one<2, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
+        case 3: bwd_one<3, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
                                  bool zero_g2, hipStream_t s, uint32_t* flags) {
     if (P.n == 0) return hipSuccess;
-    const unsigned nb = (unsigned)((P.n + kProjBlock - 1) / kProjBlock);
-    switch (P.sh) {
-        case -1: preprocess_fwd_kernel<-1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
-        case 0: preprocess_fwd_kernel<0><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
-        case 1: preprocess_fwd_kernel<1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
-        case 2: preprocess_fwd_kernel<2><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
-        case 3: preprocess_fwd_kernel<3><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return P.iso ? fwd_sh<true>(vt, P, poses, rec, zero_g2, s, flags)
+                 : fwd_sh<false>(vt, P, poses, rec, zero_g2, s, flags);
 }
 
 hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const float* poses, const Records& rec,
@@ -635,30 +690,8 @@ hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const flo
     if (P.n == 0) return hipSuccess;
     const int nb = (P.n + kProjBwdSpan - 1) / kProjBwdSpan;
     if (nb != pose_blocks) return hipErrorInvalidValue;
-    const uint64_t* vm = rec.vmask;
-    switch (P.sh) {
-        case -1:
-            preprocess_bwd_kernel<-1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            break;
-        case 0:
-            sh_bwd_kernel<0><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            preprocess_bwd_kernel<0><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            break;
-        case 1:
-            sh_bwd_kernel<1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            preprocess_bwd_kernel<1><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            break;
-        case 2:
-            sh_bwd_kernel<2><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            preprocess_bwd_kernel<2><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            break;
-        case 3:
-            sh_bwd_kernel<3><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            preprocess_bwd_kernel<3><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-            break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return P.iso ? bwd_sh<true>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb, s)
+                 : bwd_sh<false>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb, s);
 }
 
 hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, int64_t pose_blocks,

@@ -94,13 +94,19 @@ class Scene:
             off[i + 1] = off[i] + c.npix
         return off
 
+    @property
+    def isotropic(self) -> bool:
+        """The paper's eight-parameter Gaussian: log_scales [N,1] holds one
+        log radius per Gaussian and quats is empty [N,0]."""
+        return bool(self.extra.get("isotropic", False))
+
     def subset_views(self, idx) -> "Scene":
         """Same Gaussians, only the views in ``idx`` (matches are dropped)."""
         idx = list(idx)
         s = Scene(self.name, self.means, self.log_scales, self.quats, self.opacity_logits,
                   self.colors, self.sh_degree, [self.cams[i] for i in idx],
                   self.poses[idx].copy(), self.poses_true[idx].copy(), self.w_color,
-                  self.w_depth, self.w_reproj, self.huber_delta)
+                  self.w_depth, self.w_reproj, self.huber_delta, extra=dict(self.extra))
         return s
 
 
@@ -359,6 +365,19 @@ def c5(n: int = 3_000_000, views: int = 16, width: int = 1200, height: int = 680
     T_est = np.stack([perturb_pose(T, rng) for T in T_true])
     return Scene("c5", *p, 3, [cam] * views, T_est.astype(F32), T_true.astype(F32),
                  1.0, 0.1, 0.0, 2.0, extra={"window": window, "trajectory": traj.astype(F32)})
+
+
+def isotropic(s: Scene) -> Scene:
+    """The same scene with the paper's own Gaussian (Sec. 3.4): one radius per
+    Gaussian instead of three scales and a rotation.  The log radius is the
+    first log-scale draw (the same N(-3, 0.5) distribution); quats becomes an
+    empty [N,0] array."""
+    extra = dict(s.extra)
+    extra["isotropic"] = True
+    return Scene(s.name + "_iso", s.means, np.ascontiguousarray(s.log_scales[:, :1]),
+                 np.zeros((s.n, 0), F32), s.opacity_logits, s.colors, s.sh_degree, s.cams, s.poses,
+                 s.poses_true, s.w_color, s.w_depth, s.w_reproj, s.huber_delta, s.target_color,
+                 s.target_depth, s.points, s.uv, s.view_idx, extra)
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}

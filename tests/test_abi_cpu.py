@@ -43,7 +43,7 @@ def test_python_binding_names_every_export(lib):
 
 
 def test_abi_version(lib):
-    assert lib.gs_abi_version() == 3
+    assert lib.gs_abi_version() == 4
 
 
 def test_null_context_rejected_without_device_work(lib):
