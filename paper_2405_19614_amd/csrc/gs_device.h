@@ -122,14 +122,29 @@ __device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const flo
     g[0] = gx; g[1] = gy; g[2] = gz;
 }
 
-// View-dependent colour of Gaussian g (SH, degree P.sh >= 0) seen from the
-// camera of world-to-camera pose T: dir = unit vector from the camera centre
-// C = -R^T t to the mean (mx, my, mz), colour = max(0, sum Y_lm(dir) k_lm +
-// 0.5) per channel.  The projection, its deferred colour pass and the
-// backward all evaluate the colour through this one function, so they agree
-// bit for bit (the clamp decisions included).
-__device__ __forceinline__ void sh_colour(const Params& P, int g, float mx, float my, float mz, const float* T,
-                                          float* dir, float& dirn, float* col, bool* cclamp, bool& colbad) {
+// Coefficient k = 3 l + channel of one Gaussian's SH colour, read from its
+// parameter array (CoefPtr) or from a copy strided S floats apart (CoefStrided,
+// the colour backward's LDS copy: lane t's coefficient k at t + S k).
+struct CoefPtr {
+    const float* p;
+    __device__ __forceinline__ float operator[](int k) const { return p[k]; }
+};
+template <int S>
+struct CoefStrided {
+    const float* p;
+    __device__ __forceinline__ float operator[](int k) const { return p[k * S]; }
+};
+
+// View-dependent colour (SH of degree deg >= 0, coefficients sh) of a
+// Gaussian with mean (mx, my, mz) seen from the camera of world-to-camera pose
+// T: dir = unit vector from the camera centre C = -R^T t to the mean, colour =
+// max(0, sum Y_lm(dir) k_lm + 0.5) per channel.  The projection, its deferred
+// colour pass and the backward all evaluate the colour through this one
+// function on the same coefficient values, so they agree bit for bit (the
+// clamp decisions included).
+template <class Coef>
+__device__ __forceinline__ void sh_colour_of(int deg, const Coef& sh, float mx, float my, float mz, const float* T,
+                                             float* dir, float& dirn, float* col, bool* cclamp, bool& colbad) {
     // camera centre C = -R_cw^T t_cw
     const float Cx = -(T[0] * T[3] + T[4] * T[7] + T[8] * T[11]);
     const float Cy = -(T[1] * T[3] + T[5] * T[7] + T[9] * T[11]);
@@ -139,9 +154,8 @@ __device__ __forceinline__ void sh_colour(const Params& P, int g, float mx, floa
     const float idn = 1.f / dirn;
     dir[0] = dx * idn; dir[1] = dy * idn; dir[2] = dz * idn;
     float Y[16];
-    sh_basis<false>(P.sh, dir[0], dir[1], dir[2], Y, nullptr);
-    const int K = (P.sh + 1) * (P.sh + 1);
-    const float* sh = P.col + (int64_t)g * K * 3;
+    sh_basis<false>(deg, dir[0], dir[1], dir[2], Y, nullptr);
+    const int K = (deg + 1) * (deg + 1);
     float acc[3] = {0.5f, 0.5f, 0.5f};
     for (int l = 0; l < K; l++) {
         acc[0] += Y[l] * sh[3 * l];
@@ -154,6 +168,13 @@ __device__ __forceinline__ void sh_colour(const Params& P, int g, float mx, floa
         col[k] = fmaxf(acc[k], 0.f);
     }
     colbad = !__builtin_isfinite(acc[0] + acc[1] + acc[2]);
+}
+
+// sh_colour_of for Gaussian g of P (degree P.sh), coefficients from P.col
+__device__ __forceinline__ void sh_colour(const Params& P, int g, float mx, float my, float mz, const float* T,
+                                          float* dir, float& dirn, float* col, bool* cclamp, bool& colbad) {
+    const int K = (P.sh + 1) * (P.sh + 1);
+    sh_colour_of(P.sh, CoefPtr{P.col + (int64_t)g * K * 3}, mx, my, mz, T, dir, dirn, col, cclamp, colbad);
 }
 
 // Everything the projection of one Gaussian into one view computes; the

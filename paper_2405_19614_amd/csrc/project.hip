@@ -134,27 +134,6 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
     if (flags && bad_lanes != 0ull && lane == first) atomicOr(flags, kFlagNonFinite);
 }
 
-template <int CTRL, int ROWM, int BANKM>
-__device__ __forceinline__ float dpp_mov(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWM, BANKM, true));
-}
-
-// Sum over the wavefront, left in lane 63, without LDS: three row shifts give
-// each lane the sum of itself and up to three lanes below it in its 16-lane
-// row, shifts by 4 and 8 (on the upper banks) complete each row's total in
-// its lane 15, and the two row broadcasts add row 0 into row 1, row 2 into
-// row 3 and then lane 31 into rows 2 and 3.
-__device__ __forceinline__ float wave_sum_to_last(float x) {
-    float t = x + dpp_mov<0x111, 0xf, 0xf>(x);   // row_shr:1
-    t += dpp_mov<0x112, 0xf, 0xf>(x);            // row_shr:2
-    t += dpp_mov<0x113, 0xf, 0xf>(x);            // row_shr:3
-    t += dpp_mov<0x114, 0xf, 0xe>(t);            // row_shr:4, lanes 4..15 of each row
-    t += dpp_mov<0x118, 0xf, 0xc>(t);            // row_shr:8, lanes 8..15
-    t += dpp_mov<0x142, 0xa, 0xf>(t);            // row_bcast:15 into rows 1 and 3
-    t += dpp_mov<0x143, 0xc, 0xf>(t);            // row_bcast:31 into rows 2 and 3
-    return t;
-}
-
 // Zero p[e0, e1) with the block's threads, in 16-byte stores when p + e0 is
 // 16-byte aligned.
 __device__ __forceinline__ void block_zero(float* p, int64_t e0, int64_t e1) {
@@ -172,53 +151,92 @@ __device__ __forceinline__ void block_zero(float* p, int64_t e0, int64_t e1) {
 constexpr int kBwdPer = kProjBwdSpan / kProjBlock;   // Gaussians each thread scans
 static_assert(kProjBwdSpan % kProjBlock == 0 && kProjBwdSpan <= 65536, "span of a backward block");
 
+// In-place exclusive prefix sum of a[0, ne), ne <= 4 kProjBlock, by the
+// block's threads; returns the total.  Starts and ends with a barrier.
+__device__ __forceinline__ int block_scan_excl(int* a, int ne, int* s_wsum) {
+    constexpr int kPer = 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    int loc[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        const int i = kPer * (int)threadIdx.x + k;
+        loc[k] = i < ne ? a[i] : 0;
+        sum += loc[k];
+    }
+    int x = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_wsum[w] = x;
+    __syncthreads();
+    int run = x - sum, total = 0;
+#pragma unroll
+    for (int i = 0; i < kProjBlock / 64; i++) {
+        if (i < w) run += s_wsum[i];
+        total += s_wsum[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        const int i = kPer * (int)threadIdx.x + k;
+        if (i < ne) a[i] = run;
+        run += loc[k];
+    }
+    __syncthreads();
+    return total;
+}
+
 // Pack the Gaussians of the span [g0, g0 + kProjBwdSpan) that some view sees
-// (view mask non-zero) into s_loc (offset in the span) and s_mask (their
-// masks), in increasing index order: the position of Gaussian g0 + threadIdx.x
-// + kProjBlock j is (j, wavefront, lane) order.  Returns their number (the
-// same in every thread).  Ends with a barrier.
-__device__ __forceinline__ int pack_visible(const Params& P, const uint64_t* vmask, int64_t g0, uint16_t* s_loc,
-                                            uint64_t* s_mask, int (*s_cnt)[kProjBlock / 64]) {
+// into s_loc (offset in the span) and s_mask (their view masks), ordered by
+// decreasing number of views that see them and, within one count, by
+// increasing index.  The backward walks the packed list 64 Gaussians per
+// wavefront, each lane looping over its own Gaussian's views: with the list
+// sorted by count, the lanes of a wavefront run nearly the same number of
+// iterations.  s_hist: ints [V][kBwdPer][kProjBlock / 64].  s_mask may be
+// NULL (the caller re-reads the masks).  Returns the number packed (the same
+// in every thread).  Ends with a barrier.
+__device__ __forceinline__ int pack_by_views(const uint64_t* vmask, int n, int64_t g0, int V, uint16_t* s_loc,
+                                             uint64_t* s_mask, int* s_hist, int* s_wsum) {
+    constexpr int NW = kProjBlock / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint64_t m[kBwdPer];
+    int c[kBwdPer];
 #pragma unroll
     for (int j = 0; j < kBwdPer; j++) {
         const int64_t g = g0 + threadIdx.x + kProjBlock * j;
-        m[j] = g < P.n ? vmask[g] : 0ull;
+        m[j] = g < n ? vmask[g] : 0ull;
+        c[j] = __popcll(m[j]);
     }
-    uint64_t ball[kBwdPer];
+    // entry (b, j, w) counts the wavefront's Gaussians of slot j seen by
+    // exactly V - b views
+    for (int b = 0; b < V; b++)
 #pragma unroll
-    for (int j = 0; j < kBwdPer; j++) ball[j] = __ballot(m[j] != 0);
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < kBwdPer; j++) s_cnt[j][w] = __popcll(ball[j]);
-    }
-    __syncthreads();
-    int total = 0, off[kBwdPer];
-#pragma unroll
-    for (int j = 0; j < kBwdPer; j++)
-#pragma unroll
-        for (int i = 0; i < kProjBlock / 64; i++) {
-            if (i == w) off[j] = total;
-            total += s_cnt[j][i];
+        for (int j = 0; j < kBwdPer; j++) {
+            const uint64_t bl = __ballot(c[j] == V - b);
+            if (lane == 0) s_hist[(b * kBwdPer + j) * NW + w] = __popcll(bl);
         }
+    const int total = block_scan_excl(s_hist, V * kBwdPer * NW, s_wsum);
     const uint64_t lt = (1ull << lane) - 1ull;
+    for (int b = 0; b < V; b++)
 #pragma unroll
-    for (int j = 0; j < kBwdPer; j++) {
-        const int loc = threadIdx.x + kProjBlock * j;
-        if (m[j] != 0) {
-            const int e = off[j] + __popcll(ball[j] & lt);
-            s_loc[e] = (uint16_t)loc;
-            s_mask[e] = m[j];
+        for (int j = 0; j < kBwdPer; j++) {
+            const bool mine = c[j] == V - b;
+            const uint64_t bl = __ballot(mine);
+            if (mine) {
+                const int e = s_hist[(b * kBwdPer + j) * NW + w] + __popcll(bl & lt);
+                s_loc[e] = (uint16_t)(threadIdx.x + kProjBlock * j);
+                if (s_mask) s_mask[e] = m[j];
+            }
         }
-    }
     __syncthreads();
     return total;
 }
 
 // Colour part of the projection backward for SH colours, one block per span
 // of kProjBwdSpan Gaussians, one thread per Gaussian some view sees looping
-// over its views (as preprocess_bwd_kernel): the SH coefficient gradient
+// over the views that see it (as preprocess_bwd_kernel): the SH coefficient gradient
 // sum_v Y(dir_v) dL/dcolour_v over the unclamped channels, the direction's
 // gradient mapped to the mean and to the camera centre (the pose tangent's
 // translation; the centre does not move under a rotation about itself).
@@ -226,54 +244,80 @@ __device__ __forceinline__ int pack_visible(const Params& P, const uint64_t* vma
 // to the means and to the pose partials written here.  Kept apart because the
 // coefficient gradients (3K floats per Gaussian) and the geometric chain rule
 // together need twice the registers (two wavefronts per SIMD instead of four).
+// Each lane copies its Gaussian's coefficients once into LDS (its own
+// column, lane-contiguous, so no barrier and no bank conflicts) and reads
+// them from there for every view: reading them from the parameter array per
+// view made one L2 request per lane and coefficient once the block's
+// working set outgrew L1 (70M requests per launch at 16 views of 3M SH3
+// Gaussians).
 template <int SH>
-__global__ __launch_bounds__(kProjBlock, 4) void sh_bwd_kernel(ViewTable vt, Params P, const float* poses,
+__global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(ViewTable vt, Params P, const float* poses,
                                                             const uint64_t* vmask, const float* g2, Grads G,
                                                             int accumulate, double* pose_part, int pose_blocks) {
     constexpr int K = (SH + 1) * (SH + 1);
+    constexpr bool VEC = (3 * K) % 4 == 0;   // a Gaussian's coefficients start 16-byte aligned
+    constexpr int kHist = kMaxViews * kBwdPer * (kProjBlock / 64);
+    // the packing's histogram lives in the coefficient buffer, which is
+    // written only after the packing's last barrier
+    __shared__ float s_sh[3 * K * kProjBlock > kHist ? 3 * K * kProjBlock : kHist];
     __shared__ uint16_t s_loc[kProjBwdSpan];
-    __shared__ uint64_t s_mask[kProjBwdSpan];
-    __shared__ int s_cnt[kBwdPer][kProjBlock / 64];
-    __shared__ double s_pose[kProjBlock / 64][kMaxViews][3];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ int s_wsum[kProjBlock / 64];
+    __shared__ double s_pose[kMaxViews][3];
+    int* s_hist = reinterpret_cast<int*>(s_sh);
+    const int w = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * kProjBwdSpan;
     const int V = vt.V;
-    for (int k = threadIdx.x; k < (kProjBlock / 64) * V * 3; k += kProjBlock)
-        s_pose[k / (V * 3)][(k / 3) % V][k % 3] = 0.0;
+    for (int k = threadIdx.x; k < V * 3; k += kProjBlock) s_pose[k / 3][k % 3] = 0.0;
     if (!accumulate) {
         const int64_t g1 = g0 + kProjBwdSpan < (int64_t)P.n ? g0 + kProjBwdSpan : (int64_t)P.n;
         block_zero(G.means, 3 * g0, 3 * g1);
         block_zero(G.col, 3 * K * g0, 3 * K * g1);
     }
-    const int total = pack_visible(P, vmask, g0, s_loc, s_mask, s_cnt);
+    const int total = pack_by_views(vmask, P.n, g0, V, s_loc, nullptr, s_hist, s_wsum);
 
     for (int base = 0; base < total; base += kProjBlock) {
         if (base + 64 * w >= total) break;   // nothing left for this wavefront
         const int e = base + (int)threadIdx.x;
         const bool live = e < total;
         const int g = live ? (int)(g0 + s_loc[e]) : 0;
-        const uint64_t vm = live ? s_mask[e] : 0ull;
+        const uint64_t vm = live ? vmask[g] : 0ull;
         float mx = 0.f, my = 0.f, mz = 0.f;
         if (live) {
             const float* mu = P.means + 3 * (int64_t)g;
             mx = mu[0]; my = mu[1]; mz = mu[2];
         }
-        const float* sh = P.col + (int64_t)g * K * 3;
+        float* my_sh = s_sh + threadIdx.x;
+        if (live) {
+            const float* src = P.col + (int64_t)g * K * 3;
+            if (VEC) {
+#pragma unroll
+                for (int q = 0; q < 3 * K / 4; q++) {
+                    const float4 c4 = reinterpret_cast<const float4*>(src)[q];
+                    my_sh[(4 * q) * kProjBlock] = c4.x;
+                    my_sh[(4 * q + 1) * kProjBlock] = c4.y;
+                    my_sh[(4 * q + 2) * kProjBlock] = c4.z;
+                    my_sh[(4 * q + 3) * kProjBlock] = c4.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3 * K; k++) my_sh[k * kProjBlock] = src[k];
+            }
+        }
+        const CoefStrided<kProjBlock> sh{my_sh};
         float gc[3 * K];
 #pragma unroll
         for (int k = 0; k < 3 * K; k++) gc[k] = 0.f;
         float dmu[3] = {0.f, 0.f, 0.f};
-        for (int v = 0; v < V; v++) {
-            const bool on = (vm >> v) & 1ull;
-            if (__ballot(on) == 0) continue;
-            float pose[3] = {0.f, 0.f, 0.f};
-            if (on) {
+        // the lane's own views, lowest first
+        for (uint64_t rem = vm; rem != 0ull; rem &= rem - 1ull) {
+            const int v = __ffsll((unsigned long long)rem) - 1;
+            {
                 float T[12];
 #pragma unroll
                 for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
                 float dir[3], dirn, col[3];
                 bool cclamp[3], cb;
-                sh_colour(P, g, mx, my, mz, T, dir, dirn, col, cclamp, cb);
+                sh_colour_of(SH, sh, mx, my, mz, T, dir, dirn, col, cclamp, cb);
                 const float* a = g2 + ((int64_t)v * P.n + g) * kG2Stride;
                 const float dcol[3] = {cclamp[0] ? 0.f : a[6], cclamp[1] ? 0.f : a[7], cclamp[2] ? 0.f : a[8]};
                 float Y[16];
@@ -299,14 +343,8 @@ __global__ __launch_bounds__(kProjBlock, 4) void sh_bwd_kernel(ViewTable vt, Par
                 }
                 // the centre C = -W^T t moves by -W^T v: dL/dv = -W dL/dC = W t
 #pragma unroll
-                for (int i = 0; i < 3; i++) pose[i] = T[4 * i] * t[0] + T[4 * i + 1] * t[1] + T[4 * i + 2] * t[2];
-            }
-            float ps[3];
-#pragma unroll
-            for (int k = 0; k < 3; k++) ps[k] = wave_sum_to_last(pose[k]);
-            if (lane == 63) {
-#pragma unroll
-                for (int k = 0; k < 3; k++) s_pose[w][v][k] += (double)ps[k];
+                for (int i = 0; i < 3; i++)
+                    atomicAdd(&s_pose[v][i], (double)(T[4 * i] * t[0] + T[4 * i + 1] * t[1] + T[4 * i + 2] * t[2]));
             }
         }
         if (live) {
@@ -320,33 +358,35 @@ __global__ __launch_bounds__(kProjBlock, 4) void sh_bwd_kernel(ViewTable vt, Par
             } else {
 #pragma unroll
                 for (int k = 0; k < 3; k++) om[k] = dmu[k];
+                if (VEC) {
 #pragma unroll
-                for (int k = 0; k < 3 * K; k++) oc[k] = gc[k];
+                    for (int q = 0; q < 3 * K / 4; q++)
+                        reinterpret_cast<float4*>(oc)[q] =
+                            make_float4(gc[4 * q], gc[4 * q + 1], gc[4 * q + 2], gc[4 * q + 3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 3 * K; k++) oc[k] = gc[k];
+                }
             }
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < V * 6; k += kProjBlock) {
-        double t = 0.0;
-        if (k % 6 < 3) {
-#pragma unroll
-            for (int i = 0; i < kProjBlock / 64; i++) t += s_pose[i][k / 6][k % 6];
-        }
-        pose_part[((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6] = t;
-    }
+    for (int k = threadIdx.x; k < V * 6; k += kProjBlock)
+        pose_part[((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6] = k % 6 < 3 ? s_pose[k / 6][k % 6] : 0.0;
 }
 
 // One block per span of kProjBwdSpan Gaussians.  The block first reads the
 // view masks the forward projection left (bit v: visible in view v); the
 // Gaussians visible in none get a zero gradient (or nothing, when
-// accumulating) and the others are packed, in increasing index order,
-// into a list that the block then walks 256 at a time.  Every lane of that
-// walk holds a Gaussian some view sees, so the per-view recomputation runs on
-// full wavefronts instead of on the few lanes a random 64 Gaussians leave
-// visible.  The per-Gaussian gradient is summed over views in registers; the
-// per-view pose 6-vector is summed over each wavefront (FP32), added to that
-// wavefront's FP64 slot, and the four slots are added at the end: a fixed
-// order, with no barrier inside the walk.
+// accumulating) and the others are packed, most-seen first, into a list that
+// the block then walks 256 at a time.  Each lane loops over the views that
+// see its Gaussian only, and the sort by view count gives the lanes of a
+// wavefront nearly equal trip counts, so the per-view recomputation runs on
+// nearly full wavefronts (a loop over all views, skipping a view only when
+// no lane sees it, keeps about one lane in ten busy at 16 views).  The
+// per-Gaussian gradient is summed over views in registers; the per-view pose
+// 6-vector is added into the block's FP64 slots in LDS (atomically: the
+// summation order is not fixed, as for the compositing backward's sums).
 // With SH colours the colour part runs in sh_bwd_kernel first: this kernel
 // then adds its mean and pose gradients to what that one wrote.  At most 128
 // VGPRs (four waves per SIMD; it fits without spilling).  ISO: the camera
@@ -361,14 +401,14 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
     constexpr int K = SH < 0 ? 1 : (SH + 1) * (SH + 1);
     __shared__ uint16_t s_loc[kProjBwdSpan];
     __shared__ uint64_t s_mask[kProjBwdSpan];
-    __shared__ int s_cnt[kBwdPer][kProjBlock / 64];
-    __shared__ double s_pose[kProjBlock / 64][kMaxViews][6];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ int s_hist[kMaxViews * kBwdPer * (kProjBlock / 64)];
+    __shared__ int s_wsum[kProjBlock / 64];
+    __shared__ double s_pose[kMaxViews][6];
+    const int w = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * kProjBwdSpan;
     const int V = vt.V;
 
-    for (int k = threadIdx.x; k < (kProjBlock / 64) * V * 6; k += kProjBlock)
-        s_pose[k / (V * 6)][(k / 6) % V][k % 6] = 0.0;
+    for (int k = threadIdx.x; k < V * 6; k += kProjBlock) s_pose[k / 6][k % 6] = 0.0;
     if (!accumulate) {
         // the whole span's gradient starts at zero; the walk below overwrites
         // the visible Gaussians' entries after the barrier (with SH colours
@@ -386,7 +426,7 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
         }
         block_zero(G.opl, g0, g1);
     }
-    const int total = pack_visible(P, vmask, g0, s_loc, s_mask, s_cnt);
+    const int total = pack_by_views(vmask, P.n, g0, V, s_loc, s_mask, s_hist, s_wsum);
 
     for (int base = 0; base < total; base += kProjBlock) {
         if (base + 64 * w >= total) break;   // nothing left for this wavefront
@@ -400,12 +440,12 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
         gp.ok = false;
         if (live) gauss_prep<ISO>(P, g, gp);
 
-        for (int v = 0; v < V; v++) {
-            float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        // the lane's own views, lowest first
+        for (uint64_t rem = vmask; rem != 0ull; rem &= rem - 1ull) {
+            const int v = __ffsll((unsigned long long)rem) - 1;
+            float pose[6];
             const int64_t r = (int64_t)v * P.n + g;
-            const bool on = (vmask >> v) & 1ull;
-            if (__ballot(on) == 0) continue;
-            if (on) {
+            {
                 const ViewInfo& vi = vt.v[v];
                 float T[12];
 #pragma unroll
@@ -551,13 +591,8 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
                 pose[4] = pz * dpx - px * dpz + (ISO ? 0.f : 2.f * Nij(2, 0));
                 pose[5] = px * dpy - py * dpx + (ISO ? 0.f : 2.f * Nij(0, 1));
             }
-            float ps[6];
 #pragma unroll
-            for (int k = 0; k < 6; k++) ps[k] = wave_sum_to_last(pose[k]);
-            if (lane == 63) {
-#pragma unroll
-                for (int k = 0; k < 6; k++) s_pose[w][v][k] += (double)ps[k];
-            }
+            for (int k = 0; k < 6; k++) atomicAdd(&s_pose[v][k], (double)pose[k]);
         }
         if (live) {
             float* om = G.means + 3 * (int64_t)g;
@@ -595,9 +630,7 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
     }
     __syncthreads();
     for (int k = threadIdx.x; k < V * 6; k += kProjBlock) {
-        double t = 0.0;
-#pragma unroll
-        for (int i = 0; i < kProjBlock / 64; i++) t += s_pose[i][k / 6][k % 6];
+        const double t = s_pose[k / 6][k % 6];
         double* dst = pose_part + ((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6;
         if (SH < 0) *dst = t; else *dst += t;   // SH: the colour path's partial is there already
     }
