@@ -298,7 +298,7 @@ struct Ptrs {
 Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     Ptrs p;
     p.rec.line = reinterpret_cast<gs::RecLine*>(base + L.off_line);
-    p.rec.nt = reinterpret_cast<uint32_t*>(base + L.off_nt);
+    p.rec.vis = reinterpret_cast<uint64_t*>(base + L.off_vis);
     p.rec.vmask = reinterpret_cast<uint64_t*>(base + L.off_vmask);
     p.ranges = reinterpret_cast<uint2*>(base + L.off_ranges);
     p.tfin = reinterpret_cast<float*>(base + L.off_tfin);
@@ -380,6 +380,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     Layout L;
     std::memset(&L, 0, sizeof L);
     L.R = (int64_t)vt.V * n;
+    L.Rp = (int64_t)vt.V * 64 * gs::vis_words(n);
     L.cap = cap;
     L.n_bins = vt.n_bins;
     L.n_tiles = vt.n_tiles;
@@ -395,13 +396,13 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
         return at;
     };
     L.off_scalars = take((size_t)kNumScalars * 4);   // first: gs_step_status finds it at offset 0
-    L.n_chunks = std::max<int64_t>(ceil_div(R, 2048), 1);
+    L.n_chunks = std::max<int64_t>(ceil_div(L.Rp, 2048), 1);
     L.lb_tiles_chunk = ceil_div(L.n_chunks, 2048);
     L.lb_tiles_hist = std::max<int64_t>(ceil_div(256 * L.sort_blocks, 2048), 1);
     L.off_lb = take((size_t)lb_words(L) * 8);       // cleared with the scalars at the start of binning
     L.off_chunk = take((size_t)L.n_chunks * 8);
     L.off_line = take((size_t)R * sizeof(RecLine));
-    L.off_nt = take((size_t)R * 4);
+    L.off_vis = take((size_t)std::max<int64_t>(L.Rp / 64, 1) * 8);
     L.off_k0 = take((size_t)R * 4);
     L.off_v0 = take((size_t)R * 4);
     L.off_k1 = take((size_t)R * 4);
@@ -604,7 +605,7 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     plan->bwd_tile_h = bth;
     GS_HIP(c, gs::launch_status_clear(L, base, s));
     GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, false, s, p.scal + gs::kFlags));
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.line, nullptr, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");
@@ -649,7 +650,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     Ptrs p = ptrs_of(L, static_cast<char*>(state), false);
     const gs::Params P = params_of(g);
     gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
-    GS_HIP(c, gs::launch_zero_g2(p.rec.nt, p.g2, L.R, s));
+    GS_HIP(c, gs::launch_zero_g2(p.rec.vis, p.g2, g->n, vt.V, s));
     GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, p.ts, vt,
                                        false, s));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, 0, p.posepart, L.pose_blocks, s));
@@ -918,7 +919,7 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, true, s, p.scal + gs::kFlags));
     GS_HIP(c, mark(1));
     uint32_t* vals = nullptr;
-    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.nt, p.rec.line, nullptr, L.cap, s, &vals));
+    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, L.cap, s, &vals));
     GS_HIP(c, mark(2));
     gs::LossArgs la{tg->color, tg->depth, tg->mask, o->use_gate, o->gate_gamma, p.dC, p.dD, p.tilepart};
     GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, p.ts, s,
@@ -1167,8 +1168,8 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
     Ptrs p = ptrs_of(L, base, false);
     const uint2* rc = reinterpret_cast<const uint2*>(rect);
     GS_HIP(c, gs::launch_status_clear(L, base, s));
-    GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.line, p.rec.nt, n, s));
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.nt, p.rec.line, depth, s));
+    GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.line, p.rec.vis, n, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, depth, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");

@@ -63,10 +63,12 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-struct LoadVis {   // 1 if the record is visible
-    const uint32_t* nt;
-    int64_t n;
-    __device__ uint32_t operator()(int64_t i) const { return (i < n && nt[i] != 0u) ? 1u : 0u; }
+struct LoadBits {   // 1 if padded record i is visible (the projection's bitmap)
+    const uint64_t* vis;
+    int64_t words;
+    __device__ uint32_t operator()(int64_t i) const {
+        return (i >> 6) < words ? (uint32_t)((vis[i >> 6] >> (i & 63)) & 1ull) : 0u;
+    }
 };
 struct LoadArr {
     const uint32_t* a;
@@ -124,11 +126,12 @@ template <class Ld>
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(Ld ld, int64_t n, uint32_t* bsum) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t s = 0;
-    if constexpr (std::is_same<Ld, LoadVis>::value) {
-        uint32_t v[kScanItems];
-        loadN(ld.nt, base, ld.n < n ? ld.n : n, v);
-#pragma unroll
-        for (int k = 0; k < kScanItems; k++) s += v[k] != 0u ? 1u : 0u;
+    if constexpr (std::is_same<Ld, LoadBits>::value) {
+        // eight records per thread: one byte of a visibility word
+        static_assert(kScanItems == 8, "a byte of bits per thread");
+        const int64_t wi = base >> 6;
+        const uint64_t wd = wi < ld.words ? ld.vis[wi] : 0ull;
+        s = (uint32_t)__popc((uint32_t)(wd >> (base & 63)) & 0xffu);
     } else {
 #pragma unroll
         for (int k = 0; k < kScanItems; k++)
@@ -332,27 +335,31 @@ __global__ __launch_bounds__(kScanThreads) void scan_chained_kernel(uint32_t* a,
 // the depth sort read one 16-byte entry of a dense array per record instead
 // of gathering from the record lines.  The last chunk stores the visible
 // count.  Depth from `depth` when given, else from the records' colour w.
-__global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* nt, const RecLine* lines,
+// Visible records of one 2048-record chunk of the padded index, in index
+// order: depth key, compaction slot, and the dense entry (record, bin count,
+// rect).  The bin count comes from the rect and the bin size, as the pair
+// kernels divide it.
+__global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint64_t* vis, int64_t words, int64_t n,
+                                                               int bw, int bh, const RecLine* lines,
                                                                const float* depth, const uint32_t* chunk_off,
-                                                               int64_t R, uint32_t* keys, uint32_t* vals,
-                                                               uint4* info, uint32_t* n_visible) {
+                                                               uint32_t* keys, uint32_t* vals, uint4* info,
+                                                               uint32_t* n_visible) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t c8[kScanItems];
-    loadN(nt, base, R, c8);
-    uint32_t vis = 0u, cnt = 0u;
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        const bool f = c8[k] != 0u;
-        vis |= (f ? 1u : 0u) << k;
-        cnt += f ? 1u : 0u;
-    }
+    const int64_t wi = base >> 6;
+    const uint32_t vis8 = wi < words ? (uint32_t)(vis[wi] >> (base & 63)) & 0xffu : 0u;
+    const uint32_t cnt = (uint32_t)__popc(vis8);
+    // a word never straddles two views (rows are padded to whole words): the
+    // thread's eight records are Gaussians g0 .. g0 + 7 of view v
+    const int64_t row = vis_words(n);
+    const int64_t v = wi / row;
+    const int64_t r0 = v * n + (wi - v * row) * 64 + (base & 63);
     // depths and rects are gathered before any store, so they are in flight at once
     float dz[kScanItems];
     uint2 rc[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-        const int64_t r = base + k;
-        const bool f = (vis >> k) & 1u;
+        const bool f = (vis8 >> k) & 1u;
+        const int64_t r = r0 + k;
         dz[k] = f ? (depth ? depth[r] : lines[r].col.w) : 0.f;
         rc[k] = f ? lines[r].rect : make_uint2(0u, 0u);
     }
@@ -361,10 +368,13 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint32_t* n
     uint32_t o = chunk_off[blockIdx.x] + ex;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-        if ((vis >> k) & 1u) {
+        if ((vis8 >> k) & 1u) {
+            const uint32_t x0 = rc[k].x & 0xffffu, x1 = rc[k].x >> 16, y0 = rc[k].y & 0xffffu, y1 = rc[k].y >> 16;
+            const uint32_t nt =
+                (x1 / (uint32_t)bw - x0 / (uint32_t)bw + 1u) * (y1 / (uint32_t)bh - y0 / (uint32_t)bh + 1u);
             keys[o] = __float_as_uint(dz[k]);
             vals[o] = o;
-            info[o] = make_uint4((uint32_t)(base + k), c8[k], rc[k].x, rc[k].y);
+            info[o] = make_uint4((uint32_t)(r0 + k), nt, rc[k].x, rc[k].y);
             o++;
         }
     }
@@ -651,19 +661,26 @@ __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* np, uint2* r
     if (i == (int64_t)P - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
 }
 
-// tile count of each record from its pixel rect (binning entry point); the
-// rect is clipped to its image and the clipped copy is what pairs are emitted
-// from, so a caller's out-of-image rect cannot address a tile of another view
-__global__ void rect_tiles_kernel(ViewTable vt, const uint2* rect, RecLine* lines, uint32_t* nt, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * vt.V) return;
-    const ViewInfo& vi = vt.v[i / n];
-    const uint2 rc = rect[i];
-    const uint32_t x0 = rc.x & 0xffffu, y0 = rc.y & 0xffffu;
-    const uint32_t x1 = min(rc.x >> 16, (uint32_t)vi.W - 1u), y1 = min(rc.y >> 16, (uint32_t)vi.H - 1u);
-    const bool empty = x0 > x1 || y0 > y1;
-    lines[i].rect = empty ? make_uint2(1u, 1u) : make_uint2(x0 | (x1 << 16), y0 | (y1 << 16));
-    nt[i] = empty ? 0u : (x1 / vt.bw - x0 / vt.bw + 1) * (y1 / vt.bh - y0 / vt.bh + 1);
+// each record's pixel rect (binning entry point) clipped to its image into
+// its line, and the visibility bitmap of the non-empty ones; the clipped rect
+// is what pairs are emitted from, so a caller's out-of-image rect cannot
+// address a tile of another view.  One thread per padded record.
+__global__ void rect_tiles_kernel(ViewTable vt, const uint2* rect, RecLine* lines, uint64_t* vis, int64_t n) {
+    const int64_t n64 = 64 * vis_words(n), words = (int64_t)vt.V * vis_words(n);
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = p / n64, g = p - v * n64;
+    bool valid = false;
+    if (v < vt.V && g < n) {
+        const ViewInfo& vi = vt.v[v];
+        const int64_t i = v * n + g;
+        const uint2 rc = rect[i];
+        const uint32_t x0 = rc.x & 0xffffu, y0 = rc.y & 0xffffu;
+        const uint32_t x1 = min(rc.x >> 16, (uint32_t)vi.W - 1u), y1 = min(rc.y >> 16, (uint32_t)vi.H - 1u);
+        valid = !(x0 > x1 || y0 > y1);
+        lines[i].rect = valid ? make_uint2(x0 | (x1 << 16), y0 | (y1 << 16)) : make_uint2(1u, 1u);
+    }
+    const uint64_t bm = __ballot(valid);
+    if ((threadIdx.x & 63) == 0 && (p >> 6) < words) vis[p >> 6] = bm;
 }
 
 inline int ceil_log2(int64_t x) {
@@ -685,11 +702,11 @@ hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* lines, uint32_t* nt, int64_t n,
+hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* lines, uint64_t* vis, int64_t n,
                              hipStream_t s) {
-    const int64_t R = n * vt.V;
-    if (R <= 0) return hipSuccess;
-    rect_tiles_kernel<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(vt, rect, lines, nt, n);
+    const int64_t Rp = 64 * vis_words(n) * vt.V;
+    if (Rp <= 0) return hipSuccess;
+    rect_tiles_kernel<<<(unsigned)((Rp + 255) / 256), 256, 0, s>>>(vt, rect, lines, vis, n);
     return hipGetLastError();
 }
 
@@ -712,7 +729,7 @@ hipError_t launch_status_clear(const Layout& L, char* base, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
+hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
                                 const RecLine* lines, const float* depth_src, hipStream_t s) {
     uint32_t* scal = GS_AT(uint32_t, L.off_scalars);
     uint64_t* lb = GS_AT(uint64_t, L.off_lb);
@@ -722,18 +739,18 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     uint32_t* v1 = GS_AT(uint32_t, L.off_v1);
     uint32_t* csum = GS_AT(uint32_t, L.off_chunk);
     uint64_t* psum = GS_AT(uint64_t, L.off_chunk);
-    const int64_t R = L.R;
+    const int64_t R = L.R, words = L.Rp / 64;
     const int64_t nc = L.n_chunks;
     const unsigned g = (unsigned)nc, gs = (unsigned)L.lb_tiles_chunk;
     hipError_t e;
     // (the scalars and every chained-scan status word were cleared by
     // launch_status_clear before the projection)
     // 1. visible records -> compacted (depth bits, record) in record order
-    scan_reduce_kernel<LoadVis><<<g, kScanThreads, 0, s>>>(LoadVis{nt_src, R}, R, csum);
+    scan_reduce_kernel<LoadBits><<<g, kScanThreads, 0, s>>>(LoadBits{vis, words}, L.Rp, csum);
     scan_chained_kernel<<<gs, kScanThreads, 0, s>>>(csum, nc, lb, scal + kLbVis, scal + kFlags);
     uint4* info = GS_AT(uint4, L.off_info);
-    compact_kernel<<<g, kScanThreads, 0, s>>>(nt_src, lines, depth_src, csum, R, k0, v0, info,
-                                              scal + kNVis);
+    compact_kernel<<<g, kScanThreads, 0, s>>>(vis, words, vt.n, vt.bw, vt.bh, lines, depth_src, csum, k0, v0,
+                                              info, scal + kNVis);
     // 2. stable sort by depth bits (4 passes: the result is back in (k0, v0))
     uint64_t* hs[kLbHistUses];
     for (int i = 0; i < kLbHistUses; i++) hs[i] = lb + 2 * L.lb_tiles_chunk + (int64_t)i * L.lb_tiles_hist;
@@ -778,10 +795,10 @@ hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base,
     return hipGetLastError();
 }
 
-hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
+hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
                           const RecLine* lines, const float* depth_src, int64_t pair_bound, hipStream_t s,
                           uint32_t** sorted_vals_out) {
-    hipError_t e = launch_binning_count(vt, L, base, nt_src, lines, depth_src, s);
+    hipError_t e = launch_binning_count(vt, L, base, vis, lines, depth_src, s);
     if (e != hipSuccess) return e;
     return launch_binning_sort(vt, L, base, pair_bound, s, sorted_vals_out);
 }

@@ -139,9 +139,16 @@ static_assert(sizeof(RecLine) == 128, "one record per 128-byte line");
 constexpr int kG2Stride = (int)(sizeof(RecLine) / sizeof(float));
 constexpr int kG2Offset = (int)(offsetof(RecLine, g2) / sizeof(float));
 
+// Visibility bitmap of the records: word v * vis_words(n) + g / 64, bit g % 64
+// set when record (v, g) is visible.  Each view's row is padded to whole
+// words, so one projection wavefront (64 consecutive Gaussians, a multiple
+// of 64 apart) writes one word per view from its ballot.  Binning scans the
+// padded index p = v * 64 vis_words(n) + g.
+__host__ __device__ inline int64_t vis_words(int64_t n) { return (n + 63) / 64; }
+
 struct Records {
     RecLine* line;    // R record lines
-    uint32_t* nt;     // bins touched (0 = not visible), dense
+    uint64_t* vis;    // V * vis_words(n) visibility words
     uint64_t* vmask;  // per Gaussian (n entries): bit v set when its record in view v is visible
 };
 
@@ -160,10 +167,11 @@ constexpr int kRsTileKeys = 2048;
 // Device layout of the forward state / mapping workspace (byte offsets).
 struct Layout {
     int64_t R;            // V * n records
+    int64_t Rp;           // V * 64 vis_words(n): records in the padded index of the visibility bitmap
     int64_t cap;          // pair capacity
     int64_t n_bins, n_tiles, n_pix;
     int64_t sort_blocks;  // radix-sort grid for max(R, cap), at most kRsMaxGrid
-    size_t off_line, off_nt;                      // R record lines (gradient sums inside), R bin counts
+    size_t off_line, off_vis;                     // R record lines (gradient sums inside), visibility bitmap
     size_t off_vmask;                             // n uint64 (last, so it moves no other array)
     size_t off_info;                              // R uint4: (record, bin count, rect) per visible record (binning)
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
@@ -175,7 +183,7 @@ struct Layout {
     size_t off_posepart;                          // V * pose_blocks * 6 doubles
     size_t off_scalars;                           // counters and flags
     size_t off_lb;                                // chained-scan tile status words (u64), right after the scalars
-    int64_t n_chunks;                             // 2048-record chunks of the records (binning)
+    int64_t n_chunks;                             // 2048-record chunks of the padded records (binning)
     int64_t lb_tiles_chunk, lb_tiles_hist;        // tiles of a chunk-sum scan and of a radix histogram scan
     size_t off_chunk;                             // n_chunks u64 chunk sums / offsets
     // mapping workspace only
@@ -213,7 +221,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
 // ---------------------------------------------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
-hipError_t launch_zero_g2(const uint32_t* nt, float* g2, int64_t R, hipStream_t s);
+hipError_t launch_zero_g2(const uint64_t* vis, float* g2, int64_t n, int V, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
 // step[0] += gaussians, step[1] += poses (the two update counters)
 hipError_t launch_step_bump(int32_t* step, int gaussians, int poses, hipStream_t s, const uint32_t* flags = nullptr);
@@ -221,7 +229,9 @@ hipError_t launch_step_bump(int32_t* step, int gaussians, int poses, hipStream_t
 hipError_t launch_pose_retract(int V, const float* pin, const float* xi, float* pout, hipStream_t s);
 // out = J_l(xi)^T g per view (device [V][6] each)
 hipError_t launch_pose_tangent_grad(int V, const float* xi, const float* g, float* out, hipStream_t s);
-hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* lines, uint32_t* nt, int64_t n,
+// binning entry point: each record's caller-given rect clipped into its line,
+// and the visibility bitmap of the non-empty ones
+hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* lines, uint64_t* vis, int64_t n,
                              hipStream_t s);
 
 // zero_g2: also clear each visible record's gradient sums (mapping step);
@@ -243,12 +253,12 @@ hipError_t launch_status_clear(const Layout& L, char* base, hipStream_t s);
 
 // Binning: records -> sorted pair values and tile ranges.  All sizes bounded by
 // the layout; counts live on the device in the scalars block.
-hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
+hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
                           const RecLine* lines, const float* depth_src, int64_t pair_bound, hipStream_t s,
                           uint32_t** sorted_vals_out);
 // first half of binning (visibility, depth sort, pair emission); leaves the
 // pair total on the device (kPairsLo/Hi) and flags an exceeded capacity
-hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint32_t* nt_src,
+hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
                                 const RecLine* lines, const float* depth_src, hipStream_t s);
 // second half: the pairs' sort by bin (pair_bound: an upper bound of the
 // pair count, which is read on the device) and the per-bin ranges

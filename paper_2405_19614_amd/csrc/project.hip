@@ -2,12 +2,12 @@
 //
 // Forward (Sec. 3.4 "Projection"): one thread per Gaussian looping over the
 // views, writes each visible (view, Gaussian) record line (conic + opacity,
-// colour + depth, mean, pixel rect), every record's bin count, and each
-// Gaussian's view mask.
+// colour + depth, mean, pixel rect), each wavefront's visibility word per view
+// (its ballot), and each Gaussian's view mask.
 // Backward: per block of Gaussians, the ones some view sees are packed into a
-// list and one thread per listed Gaussian loops over its views, so each
-// Gaussian's parameter gradient is summed in registers (no atomics) and the
-// per-view pose 6-vector is reduced in a fixed order in FP64 (deterministic).
+// list and one thread per listed Gaussian loops over the views that see it,
+// so each Gaussian's parameter gradient is summed in registers (no atomics);
+// the per-view pose 6-vector is summed in FP64 in LDS.
 #include "gs_device.h"
 
 namespace gs {
@@ -49,6 +49,9 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
     uint64_t vm = 0;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     const int step = DEFER ? kProjChunk : vt.V;
+    // this wavefront's word of each view's visibility row (64 consecutive
+    // Gaussians starting at a multiple of 64)
+    const int64_t vrow = vis_words(P.n), vword = (int64_t)(blockIdx.x * kProjBlock + (threadIdx.x & ~63)) >> 6;
     for (int v0 = 0; v0 < vt.V; v0 += step) {
         const int v1 = v0 + step < vt.V ? v0 + step : vt.V;
         if (DEFER) {
@@ -56,6 +59,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
             __syncthreads();
         }
         if (live) {
+            const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
             for (int v = v0; v < v1; v++) {
                 const ViewInfo& vi = vt.v[v];
                 float T[12];
@@ -65,8 +69,6 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
                 project_view<!DEFER, ISO>(P, g, gp, vi, T, pr);
                 const int64_t r = (int64_t)v * P.n + g;
                 if (pr.valid) {
-                    const uint32_t tx0 = (uint32_t)pr.x0 / vt.bw, tx1 = (uint32_t)pr.x1 / vt.bw;
-                    const uint32_t ty0 = (uint32_t)pr.y0 / vt.bh, ty1 = (uint32_t)pr.y1 / vt.bh;
                     // the record line in 16-byte stores: base-2 conic with
                     // log2(opacity) (the compositing kernels' form), colour and
                     // depth, mean and rect, then (mapping step) the zeroed
@@ -83,14 +85,12 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
                     if (zero_g2) {
                         q[4] = zero; q[5] = zero; q[6] = zero; q[7] = zero;
                     }
-                    rec.nt[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
                     vm |= 1ull << v;
-                } else {
-                    rec.nt[r] = 0u;
                 }
+                const uint64_t bm = __ballot(pr.valid);
+                if (lane == first) rec.vis[v * vrow + vword] = bm;
                 if (DEFER) {
                     // queue the wavefront's visible pairs: one LDS atomic per wavefront
-                    const uint64_t bm = __ballot(pr.valid);
                     if (bm != 0ull) {
                         const int leader = __ffsll((unsigned long long)bm) - 1;
                         int base = 0;
@@ -262,12 +262,16 @@ __global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(Vie
     __shared__ float s_sh[3 * K * kProjBlock > kHist ? 3 * K * kProjBlock : kHist];
     __shared__ uint16_t s_loc[kProjBwdSpan];
     __shared__ int s_wsum[kProjBlock / 64];
-    __shared__ double s_pose[kMaxViews][3];
+    // dynamic: FP64 pose translation sums [V][3], then the poses' top rows [V][12]
+    extern __shared__ double s_dyn[];
     int* s_hist = reinterpret_cast<int*>(s_sh);
     const int w = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * kProjBwdSpan;
     const int V = vt.V;
-    for (int k = threadIdx.x; k < V * 3; k += kProjBlock) s_pose[k / 3][k % 3] = 0.0;
+    double* s_pose = s_dyn;
+    float* s_T = reinterpret_cast<float*>(s_dyn + 3 * V);
+    for (int k = threadIdx.x; k < V * 3; k += kProjBlock) s_pose[k] = 0.0;
+    for (int k = threadIdx.x; k < V * 12; k += kProjBlock) s_T[k] = poses[16 * (k / 12) + k % 12];
     if (!accumulate) {
         const int64_t g1 = g0 + kProjBwdSpan < (int64_t)P.n ? g0 + kProjBwdSpan : (int64_t)P.n;
         block_zero(G.means, 3 * g0, 3 * g1);
@@ -314,7 +318,7 @@ __global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(Vie
             {
                 float T[12];
 #pragma unroll
-                for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
+                for (int k = 0; k < 12; k++) T[k] = s_T[12 * v + k];
                 float dir[3], dirn, col[3];
                 bool cclamp[3], cb;
                 sh_colour_of(SH, sh, mx, my, mz, T, dir, dirn, col, cclamp, cb);
@@ -344,7 +348,7 @@ __global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(Vie
                 // the centre C = -W^T t moves by -W^T v: dL/dv = -W dL/dC = W t
 #pragma unroll
                 for (int i = 0; i < 3; i++)
-                    atomicAdd(&s_pose[v][i], (double)(T[4 * i] * t[0] + T[4 * i + 1] * t[1] + T[4 * i + 2] * t[2]));
+                    atomicAdd(&s_pose[3 * v + i], (double)(T[4 * i] * t[0] + T[4 * i + 1] * t[1] + T[4 * i + 2] * t[2]));
             }
         }
         if (live) {
@@ -372,7 +376,7 @@ __global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(Vie
     }
     __syncthreads();
     for (int k = threadIdx.x; k < V * 6; k += kProjBlock)
-        pose_part[((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6] = k % 6 < 3 ? s_pose[k / 6][k % 6] : 0.0;
+        pose_part[((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6] = k % 6 < 3 ? s_pose[3 * (k / 6) + k % 6] : 0.0;
 }
 
 // One block per span of kProjBwdSpan Gaussians.  The block first reads the
@@ -403,12 +407,22 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
     __shared__ uint64_t s_mask[kProjBwdSpan];
     __shared__ int s_hist[kMaxViews * kBwdPer * (kProjBlock / 64)];
     __shared__ int s_wsum[kProjBlock / 64];
-    __shared__ double s_pose[kMaxViews][6];
+    // dynamic: FP64 pose sums [V][6], the poses' top rows [V][12], and the
+    // cameras [V][6] (fx, fy, cx, cy, W, H)
+    extern __shared__ double s_dyn[];
     const int w = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * kProjBwdSpan;
     const int V = vt.V;
-
-    for (int k = threadIdx.x; k < V * 6; k += kProjBlock) s_pose[k / 6][k % 6] = 0.0;
+    double* s_pose = s_dyn;
+    float* s_T = reinterpret_cast<float*>(s_dyn + 6 * V);
+    float* s_cam = s_T + 12 * V;
+    for (int k = threadIdx.x; k < V * 6; k += kProjBlock) s_pose[k] = 0.0;
+    for (int k = threadIdx.x; k < V * 12; k += kProjBlock) s_T[k] = poses[16 * (k / 12) + k % 12];
+    for (int k = threadIdx.x; k < V; k += kProjBlock) {
+        const ViewInfo& c = vt.v[k];
+        s_cam[6 * k] = c.fx; s_cam[6 * k + 1] = c.fy; s_cam[6 * k + 2] = c.cx; s_cam[6 * k + 3] = c.cy;
+        s_cam[6 * k + 4] = (float)c.W; s_cam[6 * k + 5] = (float)c.H;
+    }
     if (!accumulate) {
         // the whole span's gradient starts at zero; the walk below overwrites
         // the visible Gaussians' entries after the barrier (with SH colours
@@ -446,10 +460,12 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
             float pose[6];
             const int64_t r = (int64_t)v * P.n + g;
             {
-                const ViewInfo& vi = vt.v[v];
+                ViewInfo vi;
+                vi.fx = s_cam[6 * v]; vi.fy = s_cam[6 * v + 1]; vi.cx = s_cam[6 * v + 2]; vi.cy = s_cam[6 * v + 3];
+                vi.W = (int)s_cam[6 * v + 4]; vi.H = (int)s_cam[6 * v + 5];
                 float T[12];
 #pragma unroll
-                for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
+                for (int k = 0; k < 12; k++) T[k] = s_T[12 * v + k];
                 Proj pr;
                 project_view<false, ISO>(P, g, gp, vi, T, pr);
                 const float4* a4 = reinterpret_cast<const float4*>(g2 + r * kG2Stride);
@@ -592,7 +608,7 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
                 pose[5] = px * dpy - py * dpx + (ISO ? 0.f : 2.f * Nij(0, 1));
             }
 #pragma unroll
-            for (int k = 0; k < 6; k++) atomicAdd(&s_pose[v][k], (double)pose[k]);
+            for (int k = 0; k < 6; k++) atomicAdd(&s_pose[6 * v + k], (double)pose[k]);
         }
         if (live) {
             float* om = G.means + 3 * (int64_t)g;
@@ -630,7 +646,7 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
     }
     __syncthreads();
     for (int k = threadIdx.x; k < V * 6; k += kProjBlock) {
-        const double t = s_pose[k / 6][k % 6];
+        const double t = s_pose[k];
         double* dst = pose_part + ((int64_t)(k / 6) * pose_blocks + blockIdx.x) * 6 + k % 6;
         if (SH < 0) *dst = t; else *dst += t;   // SH: the colour path's partial is there already
     }
@@ -689,9 +705,12 @@ hipError_t fwd_sh(const ViewTable& vt, const Params& P, const float* poses, Reco
 template <int SH, bool ISO>
 void bwd_one(const ViewTable& vt, const Params& P, const float* poses, const uint64_t* vm, const float* g2, Grads G,
              int accumulate, double* pose_part, int nb, hipStream_t s) {
+    const size_t dyn_sh = (size_t)vt.V * (3 * sizeof(double) + 12 * sizeof(float));
+    const size_t dyn_geo = (size_t)vt.V * (6 * sizeof(double) + 18 * sizeof(float));
     if constexpr (SH >= 0)
-        sh_bwd_kernel<SH><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-    preprocess_bwd_kernel<SH, ISO><<<nb, kProjBlock, 0, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+        sh_bwd_kernel<SH><<<nb, kProjBlock, dyn_sh, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
+    preprocess_bwd_kernel<SH, ISO><<<nb, kProjBlock, dyn_geo, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part,
+                                                                  nb);
 }
 
 template <bool ISO>

@@ -12,9 +12,13 @@ namespace gs {
 
 namespace {
 
-__global__ void zero_g2_kernel(const uint32_t* nt, float* g2, int64_t R) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R || nt[r] == 0u) return;
+// one thread per record of the padded visibility index; visible ones only
+__global__ void zero_g2_kernel(const uint64_t* vis, float* g2, int64_t n, int V) {
+    const int64_t row = vis_words(n);
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= 64 * row * V || !((vis[p >> 6] >> (p & 63)) & 1ull)) return;
+    const int64_t v = (p >> 6) / row;
+    const int64_t r = v * n + (p - 64 * row * v);
     float4* z = reinterpret_cast<float4*>(g2 + r * kG2Stride);
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     z[0] = zero; z[1] = zero; z[2] = zero;
@@ -316,9 +320,10 @@ __global__ void step_bump_kernel(int32_t* step, int gaussians, int poses, const 
 
 }  // namespace
 
-hipError_t launch_zero_g2(const uint32_t* nt, float* g2, int64_t R, hipStream_t s) {
+hipError_t launch_zero_g2(const uint64_t* vis, float* g2, int64_t n, int V, hipStream_t s) {
+    const int64_t R = 64 * vis_words(n) * V;
     if (R <= 0) return hipSuccess;
-    zero_g2_kernel<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(nt, g2, R);
+    zero_g2_kernel<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(vis, g2, n, V);
     return hipGetLastError();
 }
 
