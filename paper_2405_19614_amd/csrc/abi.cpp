@@ -429,6 +429,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     }
     L.off_vmask = take((size_t)std::max<int64_t>(n, 1) * 8);
     L.off_info = take((size_t)std::max<int64_t>(R, 1) * 16);
+    L.off_sinfo = take((size_t)std::max<int64_t>(R, 1) * 16);
     L.bytes = o;
     return L;
 }

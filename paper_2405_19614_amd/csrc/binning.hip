@@ -388,16 +388,15 @@ constexpr int kPairThreads = 512;
 constexpr int kPairItems = kScanTile / kPairThreads;
 
 // pairs (touched bins) of the depth-sorted visible records of one chunk
-__global__ __launch_bounds__(kPairThreads) void pair_count_kernel(const uint32_t* ids, const uint4* info,
-                                                                  const uint32_t* nvis_p, uint64_t* chunk) {
+// (their entries in depth order: sinfo[i] = (record, bin count, rect))
+__global__ __launch_bounds__(kPairThreads) void pair_count_kernel(const uint4* sinfo, const uint32_t* nvis_p,
+                                                                  uint64_t* chunk) {
     const int64_t nvis = (int64_t)*nvis_p;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kPairItems;
-    uint32_t id[kPairItems];
-    loadN(ids, base, nvis, id);
     uint64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kPairItems; k++)
-        if (base + k < nvis) sum += info[id[k]].y;
+        if (base + k < nvis) sum += sinfo[base + k].y;
     uint64_t ex;
     const uint64_t tot = block_excl_scan64<kPairThreads>(sum, ex);
     if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
@@ -442,7 +441,7 @@ __global__ __launch_bounds__(kScanThreads) void pair_offsets_kernel(uint64_t* a,
 // One (global bin id, record) pair per bin each depth-sorted visible record
 // of the chunk touches, at the chunk's offset plus the rank within it; pairs
 // past the capacity are not written.  Also clears the per-bin ranges.
-__global__ __launch_bounds__(kPairThreads) void emit_kernel(ViewTable vt, const uint32_t* ids, const uint4* info,
+__global__ __launch_bounds__(kPairThreads) void emit_kernel(ViewTable vt, const uint4* sinfo,
                                                             const uint32_t* nvis_p,
                                                             const uint64_t* chunk_off, int64_t cap, uint32_t* pk,
                                                             uint32_t* pv, uint2* ranges, int64_t n_bins) {
@@ -451,13 +450,11 @@ __global__ __launch_bounds__(kPairThreads) void emit_kernel(ViewTable vt, const 
     const int64_t nvis = (int64_t)*nvis_p;
     if ((int64_t)blockIdx.x * kScanTile >= nvis) return;   // uniform: the whole chunk is past the records
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kPairItems;
-    uint32_t id[kPairItems];
     uint4 inf[kPairItems];   // (record, bin count, rect) of each depth-ordered record
-    loadN(ids, base, nvis, id);
     uint64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kPairItems; k++) {
-        inf[k] = base + k < nvis ? info[id[k]] : make_uint4(0u, 0u, 0u, 0u);
+        inf[k] = base + k < nvis ? sinfo[base + k] : make_uint4(0u, 0u, 0u, 0u);
         sum += inf[k].y;
     }
     uint64_t ex;
@@ -536,10 +533,13 @@ __global__ __launch_bounds__(kRsThreads) void rs_upsweep_kernel(const uint32_t* 
 // the 8 digit bits within a wavefront, per-wavefront digit counters across
 // them), place the tile in LDS in digit order, then write it out with
 // consecutive threads on consecutive positions of each digit's run.
+// pin / pout (nullable): instead of the keys and values, write pout[pos] =
+// pin[value] (the sort's last pass carries a payload in key order)
 __global__ __launch_bounds__(kRsThreads) void rs_downsweep_kernel(const uint32_t* kin, const uint32_t* vin,
                                                                   uint32_t* kout, uint32_t* vout,
                                                                   const uint32_t* n_dev, uint32_t n_host, int shift,
-                                                                  const uint32_t* hist) {
+                                                                  const uint32_t* hist, const uint4* pin,
+                                                                  uint4* pout) {
     static_assert(kRsThreads == kScanThreads && kRsThreads == 256, "one thread per digit");
     __shared__ uint32_t cnt[kRsWaves][256];
     __shared__ uint32_t goff[256];   // global position of the block's next key of each digit
@@ -613,8 +613,12 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep_kernel(const uint32_t
             const uint32_t kk = sk[i];
             const uint32_t d = (kk >> shift) & 255u;
             const uint32_t pos = goff[d] + (i - toff[d]);
-            kout[pos] = kk;
-            vout[pos] = sv[i];
+            if (pout) {
+                pout[pos] = pin[sv[i]];
+            } else {
+                kout[pos] = kk;
+                vout[pos] = sv[i];
+            }
         }
         __syncthreads();   // goff, cnt and the staging arrays are reused by the next tile
         goff[threadIdx.x] += tile_total;
@@ -626,9 +630,12 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep_kernel(const uint32_t
 // between (k0, v0) and (k1, v1); *in_second tells where the result is.  The
 // histogram of pass i is scanned by one chained launch using status[i] and
 // counters[i] (cleared beforehand).
+// pay_in / pay_out (nullable): the last pass writes pay_out[i] = pay_in[value]
+// in key order instead of the sorted keys and values
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
                       int64_t n_bound, int bits, uint32_t* hist, uint64_t* const* status, uint32_t* counters,
-                      uint32_t* flags, int max_passes, hipStream_t s, bool* in_second) {
+                      uint32_t* flags, int max_passes, hipStream_t s, bool* in_second,
+                      const uint4* pay_in = nullptr, uint4* pay_out = nullptr) {
     *in_second = false;
     const int64_t nb = std::min<int64_t>((n_bound + kRsTile - 1) / kRsTile, kRsMaxGrid);
     if (nb == 0 || bits <= 0) return hipSuccess;
@@ -644,7 +651,9 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, co
         uint32_t* vo = second ? v0 : v1;
         rs_upsweep_kernel<<<(unsigned)nb, kRsThreads, 0, s>>>(ki, n_dev, n_host, shift, hist);
         scan_chained_kernel<<<scan_grid, kScanThreads, 0, s>>>(hist, nh, status[pass], counters + pass, flags);
-        rs_downsweep_kernel<<<(unsigned)nb, kRsThreads, 0, s>>>(ki, vi, ko, vo, n_dev, n_host, shift, hist);
+        const bool last = shift + 8 >= bits;
+        rs_downsweep_kernel<<<(unsigned)nb, kRsThreads, 0, s>>>(ki, vi, ko, vo, n_dev, n_host, shift, hist,
+                                                                last ? pay_in : nullptr, last ? pay_out : nullptr);
         second = !second;
     }
     *in_second = second;
@@ -754,16 +763,17 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     // 2. stable sort by depth bits (4 passes: the result is back in (k0, v0))
     uint64_t* hs[kLbHistUses];
     for (int i = 0; i < kLbHistUses; i++) hs[i] = lb + 2 * L.lb_tiles_chunk + (int64_t)i * L.lb_tiles_hist;
+    // the last pass writes the dense entries themselves in depth order
+    uint4* sinfo = GS_AT(uint4, L.off_sinfo);
     bool second;
     e = radix_sort(k0, v0, k1, v1, scal + kNVis, R, 32, GS_AT(uint32_t, L.off_hist), hs, scal + kLbHist0,
-                   scal + kFlags, 4, s, &second);
+                   scal + kFlags, 4, s, &second, info, sinfo);
     if (e != hipSuccess) return e;
-    const uint32_t* ids = second ? v1 : v0;
     // 3. pairs in depth order: per-chunk counts, chained offsets (the total
     //    stays on the device), emission
-    pair_count_kernel<<<g, kPairThreads, 0, s>>>(ids, info, scal + kNVis, psum);
+    pair_count_kernel<<<g, kPairThreads, 0, s>>>(sinfo, scal + kNVis, psum);
     pair_offsets_kernel<<<gs, kScanThreads, 0, s>>>(psum, nc, L.cap, lb + L.lb_tiles_chunk, scal);
-    emit_kernel<<<g, kPairThreads, 0, s>>>(vt, ids, info, scal + kNVis, psum, L.cap,
+    emit_kernel<<<g, kPairThreads, 0, s>>>(vt, sinfo, scal + kNVis, psum, L.cap,
                                            GS_AT(uint32_t, L.off_pk0), GS_AT(uint32_t, L.off_pv0),
                                            GS_AT(uint2, L.off_ranges), L.n_bins);
     return hipGetLastError();

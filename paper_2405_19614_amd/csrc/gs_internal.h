@@ -174,6 +174,7 @@ struct Layout {
     size_t off_line, off_vis;                     // R record lines (gradient sums inside), visibility bitmap
     size_t off_vmask;                             // n uint64 (last, so it moves no other array)
     size_t off_info;                              // R uint4: (record, bin count, rect) per visible record (binning)
+    size_t off_sinfo;                             // R uint4: the same entries in depth order
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
     size_t off_pk0, off_pv0, off_pk1, off_pv1;    // pair sort (cap)
     size_t off_hist;                              // 256 * sort_blocks
