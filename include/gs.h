@@ -165,6 +165,21 @@ int gs_render_forward(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams,
                       float* color, float* depth, float* alpha, void* state, size_t state_bytes, gs_plan* plan,
                       void* stream);
 
+/* gs_render_forward without any host synchronisation (the same kernels; for
+ * graph capture and for loops that must not stall on the device).  The pair
+ * total stays on the device: plan->pair_capacity is the caller's bound, and
+ * plan->n_pairs and plan->n_visible are set to -1.  When the pairs exceed
+ * the capacity every per-bin list is left empty, so color, depth and alpha
+ * are 0 and a gs_render_backward of this state gives zero gradients; a
+ * non-finite parameter makes the results invalid.  Both are flagged in the
+ * state's status block: gs_step_status(ctx, state, ...) returns the flags
+ * (bit 0 overflow, bit 1 scan time-out, bit 2 non-finite parameter) and the
+ * pair and visible-record counts.  Errors returned are those of the
+ * arguments only. */
+int gs_render_forward_async(gs_ctx* ctx, const gs_gaussians* g, const gs_camera* cams, const float* poses,
+                            int32_t V, float* color, float* depth, float* alpha, void* state, size_t state_bytes,
+                            gs_plan* plan, void* stream);
+
 /* Reverse mode of gs_render_forward (differentiable rasterisation,
  * Sec. 3.4; pose gradient for the joint optimisation, Sec. 3.3).  Takes the
  * same g, cams, poses, V, state and the plan returned by the forward, and the
@@ -323,7 +338,8 @@ int gs_pose_retract(gs_ctx* ctx, int32_t V, const float* poses, const float* xi,
 int gs_pose_tangent_grad(gs_ctx* ctx, int32_t V, const float* xi, const float* dL_dpose, float* dL_dxi,
                          void* stream);
 
-/* Synchronous read of the workspace status after gs_mapping_step.  *flags is
+/* Synchronous read of the workspace status after gs_mapping_step (or of a
+ * forward state after gs_render_forward_async).  *flags is
  * the OR over every step since the previous gs_step_status call on this
  * workspace (the sticky word, which this call then clears) and the last
  * step: bit 0 = pair overflow, bit 1 = a binning scan gave up waiting for

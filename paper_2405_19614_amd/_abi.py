@@ -66,6 +66,7 @@ class gs_adam(ctypes.Structure):
 
 
 EXPORTS = ["gs_abi_version", "gs_create", "gs_destroy", "gs_last_error", "gs_state_bytes", "gs_render_forward",
+           "gs_render_forward_async",
            "gs_render_backward", "gs_reproj_residual", "gs_reproj_residual_noalloc", "gs_step_workspace_bytes", "gs_mapping_step",
            "gs_step_status", "gs_bin_records", "gs_autotune", "gs_set_tile", "gs_num_stages", "gs_stage_name",
            "gs_step_profile", "gs_set_pixels_per_thread", "gs_get_pixels_per_thread", "gs_set_bwd_shape", "gs_set_bin",
@@ -101,6 +102,7 @@ def load() -> ctypes.CDLL:
     L.gs_step_workspace_bytes.restype = c_size_t
     L.gs_render_forward.argtypes = [c_void_p, ctypes.POINTER(gs_gaussians), PC, c_void_p, c_int32, c_void_p,
                                     c_void_p, c_void_p, c_void_p, c_size_t, ctypes.POINTER(gs_plan), c_void_p]
+    L.gs_render_forward_async.argtypes = L.gs_render_forward.argtypes
     L.gs_render_backward.argtypes = [c_void_p, ctypes.POINTER(gs_gaussians), PC, c_void_p, c_int32, c_void_p,
                                      c_size_t, ctypes.POINTER(gs_plan), c_void_p, c_void_p, c_void_p,
                                      ctypes.POINTER(gs_gaussian_grads), c_void_p, c_void_p]

@@ -248,8 +248,11 @@ class Context:
 
     # -------------------------------------------------------------- render
     def forward(self, g: Gaussians, cams, poses: torch.Tensor, tile=(0, 0), capacity: Optional[int] = None,
-                bin=(0, 0)):
-        """Returns (color, depth, alpha, state, plan)."""
+                bin=(0, 0), sync: bool = True):
+        """Returns (color, depth, alpha, state, plan).  sync=False: no host
+        synchronisation (gs_render_forward_async) with ``capacity`` pairs (the
+        context's estimate by default); an overflow gives an empty render,
+        flagged in the state (``state_status``)."""
         cams = as_cameras(cams)
         ca = cam_array(cams)
         V = len(cams)
@@ -264,6 +267,14 @@ class Context:
         cap = int(capacity if capacity is not None else self.pair_estimate)
         gst = g.struct()
         bw, bh = self._bin(bin)
+        if not sync:
+            nbytes = self.state_bytes(cams, g.n, cap, (bw, bh))
+            state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            plan = A.gs_plan(tile[0], tile[1], bw, bh, cap, 0, 0)
+            self._check(self.lib.gs_render_forward_async(self.h, ctypes.byref(gst), ca, _p(poses), V, _p(color),
+                                                         _p(depth), _p(alpha), _p(state), nbytes,
+                                                         ctypes.byref(plan), _stream()))
+            return color, depth, alpha, state, plan
         for _ in range(3):
             nbytes = self.state_bytes(cams, g.n, cap, (bw, bh))
             state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -278,6 +289,32 @@ class Context:
             self.pair_estimate = max(self.pair_estimate, int(plan.n_pairs * 1.25) + 1024)
             return color, depth, alpha, state, plan
         raise GSError(A.GS_ECAPACITY, "pair capacity did not converge")
+
+    def state_status(self, state: torch.Tensor) -> Dict[str, int]:
+        """Flags and counts of the pass that wrote ``state`` (a forward state
+        or a mapping-step workspace); synchronises the stream."""
+        f = ctypes.c_int32()
+        npairs = ctypes.c_int64()
+        nvis = ctypes.c_int64()
+        self._check(self.lib.gs_step_status(self.h, _p(state), state.numel(), ctypes.byref(f), ctypes.byref(npairs),
+                                            ctypes.byref(nvis), _stream()))
+        return {"flags": int(f.value), "n_pairs": int(npairs.value), "n_visible": int(nvis.value)}
+
+    def check_async(self) -> Dict[str, int]:
+        """state_status of the last render(..., sync=False), raising GSError
+        when it overflowed its capacity (or read a non-finite parameter)."""
+        st = getattr(self, "last_async_state", None)
+        if st is None:
+            return {"flags": 0, "n_pairs": 0, "n_visible": 0}
+        s = self.state_status(st)
+        if s["flags"] & 1:
+            self.pair_estimate = max(self.pair_estimate, int(s["n_pairs"] * 1.25) + 1024)
+            raise GSError(A.GS_ECAPACITY, f"an asynchronous render needed {s['n_pairs']} pairs")
+        if s["flags"] & 4:
+            raise GSError(A.GS_EINVAL, "an asynchronous render read a non-finite Gaussian parameter")
+        if s["flags"]:
+            raise GSError(A.GS_EDEVICE, f"asynchronous render flags {s['flags']}")
+        return s
 
     def backward(self, g: Gaussians, cams, poses: torch.Tensor, state: torch.Tensor, plan, dC=None, dD=None,
                  dA=None) -> Tuple[Gaussians, torch.Tensor]:
@@ -584,11 +621,13 @@ class GSRenderFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_tangent, poses, gs_ctx, cams,
-                sh_degree, isotropic, tile):
+                sh_degree, isotropic, tile, sync):
         g = Gaussians(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacity_logits.contiguous(),
                       colors.contiguous(), sh_degree, isotropic)
         rposes = gs_ctx.pose_retract(poses, pose_tangent)
-        color, depth, alpha, state, plan = gs_ctx.forward(g, cams, rposes, tile=tile)
+        color, depth, alpha, state, plan = gs_ctx.forward(g, cams, rposes, tile=tile, sync=sync)
+        if not sync:
+            gs_ctx.last_async_state = state
         ctx.save_for_backward(means, log_scales, quats, opacity_logits, colors, pose_tangent, rposes, state)
         ctx.gs = (gs_ctx, cams, sh_degree, isotropic, plan)
         return color, depth, alpha
@@ -603,22 +642,26 @@ class GSRenderFn(torch.autograd.Function):
         dxi = gs_ctx.pose_tangent_grad(pose_tangent, dpose)
         return (grads.means.view_as(means), grads.log_scales.view_as(log_scales), grads.quats.view_as(quats),
                 grads.opacity_logits.view_as(opacity_logits), grads.colors.view_as(colors),
-                dxi.view_as(pose_tangent), None, None, None, None, None, None)
+                dxi.view_as(pose_tangent), None, None, None, None, None, None, None)
 
 
 def render(g: Gaussians, cams, poses: torch.Tensor, pose_tangent: Optional[torch.Tensor] = None,
-           ctx: Optional[Context] = None, tile=(0, 0)):
+           ctx: Optional[Context] = None, tile=(0, 0), sync: bool = True):
     """Differentiable render of V views at Exp(pose_tangent[v]) poses[v].
     Gradients flow to g's tensors (if they require grad) and to
     ``pose_tangent`` ([V,6], xi = (v, w), translation first; a zero tensor
-    with requires_grad gives the left-perturbation gradient d/dxi at 0)."""
+    with requires_grad gives the left-perturbation gradient d/dxi at 0).
+    sync=False renders without a host synchronisation, with the pair
+    capacity the context estimated from earlier synchronous renders: a pair
+    overflow then gives an empty render and zero gradients, flagged in the
+    state that ``ctx.check_async()`` reads."""
     cams = as_cameras(cams)
     ctx = ctx or default_context()
     if pose_tangent is None:
         pose_tangent = torch.zeros(len(cams), 6, dtype=torch.float32, device=poses.device)
     return GSRenderFn.apply(g.means, g.log_scales, g.quats, g.opacity_logits, g.colors, pose_tangent,
                             poses.detach().reshape(len(cams), 16).contiguous(), ctx, cams, g.sh_degree, g.isotropic,
-                            tuple(tile))
+                            tuple(tile), bool(sync))
 
 
 class SSIMLossFn(torch.autograd.Function):

@@ -571,9 +571,13 @@ size_t gs_step_workspace_bytes(const gs_camera* cams, int32_t V, int64_t n, int3
     return gs::make_layout(vt, n, cap, true, max_tiles(cams, V)).bytes;
 }
 
-int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
-                      float* color, float* depth, float* alpha, void* state, size_t state_bytes, gs_plan* plan,
-                      void* stream) {
+namespace {
+
+// gs_render_forward (sync: the pair count comes back to the host) and
+// gs_render_forward_async (everything stays on the device)
+int render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                   float* color, float* depth, float* alpha, void* state, size_t state_bytes, gs_plan* plan,
+                   void* stream, bool sync) {
     if (!c) return GS_EINVAL;
     if (!plan) return fail(c, GS_EINVAL, "plan is NULL");
     int r = check_gaussians(c, g);
@@ -605,7 +609,21 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     plan->bwd_tile_w = btw;
     plan->bwd_tile_h = bth;
     GS_HIP(c, gs::launch_status_clear(L, base, s));
+    // a forward state's sticky word holds nothing older than this pass
+    GS_HIP(c, gs::launch_fill_u32(p.scal + gs::kSticky, 0u, 1, s));
     GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, false, s, p.scal + gs::kFlags));
+    if (!sync) {
+        // the pair total stays on the device: an overflow zeroes the sort's
+        // count (kFlagCapacity), so every list is empty and the render is too
+        uint32_t* vals = nullptr;
+        GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, L.cap, s, &vals));
+        if (L.cap > 0 && vals != p.vals) return fail(c, GS_EDEVICE, "internal: sorted values in unexpected buffer");
+        GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, p.vals, p.rec, color, depth, alpha, p.tfin, p.last, nullptr,
+                                           p.ts, s));
+        plan->n_pairs = -1;
+        plan->n_visible = -1;
+        return GS_OK;
+    }
     GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
@@ -624,6 +642,20 @@ int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, c
     GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, p.vals, p.rec, color, depth, alpha, p.tfin, p.last, nullptr, p.ts,
                                        s));
     return GS_OK;
+}
+
+}  // namespace
+
+int gs_render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                      float* color, float* depth, float* alpha, void* state, size_t state_bytes, gs_plan* plan,
+                      void* stream) {
+    return render_forward(c, g, cams, poses, V, color, depth, alpha, state, state_bytes, plan, stream, true);
+}
+
+int gs_render_forward_async(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
+                            float* color, float* depth, float* alpha, void* state, size_t state_bytes, gs_plan* plan,
+                            void* stream) {
+    return render_forward(c, g, cams, poses, V, color, depth, alpha, state, state_bytes, plan, stream, false);
 }
 
 int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const float* poses, int32_t V,
