@@ -857,8 +857,9 @@ int or_reproj(int V, const int32_t* W, const int32_t* H, const double* intr /*[V
 
 /* ---------------- binning (integer stage) ----------------
  * Records r = v*n + i carry an inclusive pixel rect, packed
- * rect[2r] = x0 | x1 << 16, rect[2r+1] = y0 | y1 << 16 (empty if x0 > x1 or
- * y0 > y1), and an FP32 depth whose bit pattern orders positive depths.  The
+ * rect[2r] = x0 | x1 << 16, rect[2r+1] = y0 | y1 << 16 (clipped to its view's
+ * image: x1 <= W - 1, y1 <= H - 1; empty if then x0 > x1 or y0 > y1), and an
+ * FP32 depth whose bit pattern orders positive depths.  The
  * global id of tile (tx, ty) of view v is tile_off[v] + ty * tiles_x[v] + tx.
  * Output: every (tile, record) pair with the record's rect touching the tile,
  * sorted by (tile, depth bits, record); ranges[2t], ranges[2t+1] = [start,
@@ -873,16 +874,27 @@ static int cmp_trip(const void* a, const void* b) {
     return 0;
 }
 
+/* record r's rect clipped to its view's image (W x H); 0 when empty */
+static int clip_rect(const uint32_t* rect, int64_t r, int32_t W, int32_t H, uint32_t* x0, uint32_t* x1,
+                     uint32_t* y0, uint32_t* y1) {
+    *x0 = rect[2 * r] & 0xffff;
+    *x1 = rect[2 * r] >> 16;
+    *y0 = rect[2 * r + 1] & 0xffff;
+    *y1 = rect[2 * r + 1] >> 16;
+    if (*x1 > (uint32_t)W - 1) *x1 = (uint32_t)W - 1;
+    if (*y1 > (uint32_t)H - 1) *y1 = (uint32_t)H - 1;
+    return !(*x0 > *x1 || *y0 > *y1);
+}
+
 int64_t or_binning_count(int V, int64_t n, const int32_t* W, const int32_t* H, int tw, int th,
                          const uint32_t* rect) {
-    (void)W; (void)H;
     int64_t total = 0;
-    for (int64_t r = 0; r < (int64_t)V * n; r++) {
-        uint32_t x0 = rect[2 * r] & 0xffff, x1 = rect[2 * r] >> 16;
-        uint32_t y0 = rect[2 * r + 1] & 0xffff, y1 = rect[2 * r + 1] >> 16;
-        if (x0 > x1 || y0 > y1) continue;
-        total += (int64_t)(x1 / tw - x0 / tw + 1) * (y1 / th - y0 / th + 1);
-    }
+    for (int v = 0; v < V; v++)
+        for (int64_t i = 0; i < n; i++) {
+            uint32_t x0, x1, y0, y1;
+            if (!clip_rect(rect, (int64_t)v * n + i, W[v], H[v], &x0, &x1, &y0, &y1)) continue;
+            total += (int64_t)(x1 / tw - x0 / tw + 1) * (y1 / th - y0 / th + 1);
+        }
     return total;
 }
 
@@ -896,9 +908,8 @@ int or_binning(int V, int64_t n, const int32_t* W, const int32_t* H, int tw, int
         uint32_t tx = (uint32_t)((W[v] + tw - 1) / tw), ty = (uint32_t)((H[v] + th - 1) / th);
         for (int64_t i = 0; i < n; i++) {
             int64_t r = (int64_t)v * n + i;
-            uint32_t x0 = rect[2 * r] & 0xffff, x1 = rect[2 * r] >> 16;
-            uint32_t y0 = rect[2 * r + 1] & 0xffff, y1 = rect[2 * r + 1] >> 16;
-            if (x0 > x1 || y0 > y1) continue;
+            uint32_t x0, x1, y0, y1;
+            if (!clip_rect(rect, r, W[v], H[v], &x0, &x1, &y0, &y1)) continue;
             uint32_t bits;
             memcpy(&bits, &depth[r], 4);
             for (uint32_t b = y0 / th; b <= y1 / th; b++)

@@ -33,7 +33,9 @@ from typing import Dict, Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# GS_ORACLE_LIB names another build of gs_oracle.c to load instead (the
+# sanitizer test's instrumented one); it is then used as it is
+_LIB_PATH = os.environ.get("GS_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "gs_oracle.c")
 
 # decision bands for flagging pixels whose result an FP32 renderer may
@@ -61,6 +63,8 @@ AMB_UNBOUNDED = AMB_SKIP | AMB_TERM
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (-O2, OpenMP, no FP contraction)."""
+    if os.environ.get("GS_ORACLE_LIB"):
+        return _LIB_PATH
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",

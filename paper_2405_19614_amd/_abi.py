@@ -85,11 +85,17 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2405_19614_amd/build.py "
                           "(or __graft_entry__.build()); there is no CPU fallback")
-    L = ctypes.CDLL(LIB_PATH)
+    _lib = declare(ctypes.CDLL(LIB_PATH), LIB_PATH)
+    return _lib
+
+
+def declare(L: ctypes.CDLL, path: str) -> ctypes.CDLL:
+    """Argument and result types of every export of a loaded build of the
+    library (also used for instrumented builds in tests)."""
     PC = ctypes.POINTER(gs_camera)
     L.gs_abi_version.restype = c_int32
     if L.gs_abi_version() != ABI_VERSION:
-        raise ImportError(f"{LIB_PATH} has ABI version {L.gs_abi_version()}, this binding needs {ABI_VERSION}: "
+        raise ImportError(f"{path} has ABI version {L.gs_abi_version()}, this binding needs {ABI_VERSION}: "
                           "rebuild it")
     L.gs_create.argtypes = [ctypes.POINTER(c_void_p), c_int32]
     L.gs_destroy.argtypes = [c_void_p]
@@ -148,5 +154,4 @@ def load() -> ctypes.CDLL:
                                  ctypes.POINTER(gs_step_opts), c_void_p]
     L.gs_pose_retract.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     L.gs_pose_tangent_grad.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
-    _lib = L
     return L

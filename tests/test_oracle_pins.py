@@ -420,11 +420,22 @@ def test_reproj_behind_near_plane_excluded(oracle):
 # binning definition (integer) vs brute force
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("tw,th", [(16, 16), (8, 8), (32, 8)])
-def test_binning_brute_force(oracle, tw, th):
+@pytest.mark.parametrize("tw,th,overhang", [(16, 16, False), (8, 8, False), (32, 8, False), (16, 8, True)])
+def test_binning_brute_force(oracle, tw, th, overhang):
+    """overhang: rects reaching past their image (up to the 16-bit limit, or
+    starting beyond it) bin as their part inside the image; the brute force
+    visits only the image's tiles."""
     sizes = [(70, 45), (33, 17), (64, 48)]
     n = 60
     rect, depth = scenes.synthetic_binning_records(sizes, n, seed=tw * 7 + th)
+    if overhang:
+        rect = rect.copy()
+        rng = np.random.default_rng(5)
+        for v, (W, H) in enumerate(sizes):
+            idx = v * n + rng.choice(n, 20, replace=False)
+            rect[idx[:8], 0] = (rect[idx[:8], 0] & 0xFFFF) | (np.uint32(0xFFFF) << 16)
+            rect[idx[8:14], 1] = (rect[idx[8:14], 1] & 0xFFFF) | (np.uint32(H + 5) << 16)
+            rect[idx[14:], 0] = np.uint32(W + 3) | (np.uint32(W + 9) << 16)
     values, ranges = oracle.binning(sizes, n, tw, th, rect, depth)
     # brute force: per tile, scan every record
     tid = 0
@@ -434,13 +445,15 @@ def test_binning_brute_force(oracle, tw, th):
         for b in range(ty):
             for a in range(tx):
                 lst = []
+                # the tile's pixels inside the image
+                px0, px1 = a * tw, min((a + 1) * tw, W) - 1
+                py0, py1 = b * th, min((b + 1) * th, H) - 1
                 for i in range(n):
                     r = v * n + i
-                    x0, x1 = rect[r, 0] & 0xFFFF, rect[r, 0] >> 16
-                    y0, y1 = rect[r, 1] & 0xFFFF, rect[r, 1] >> 16
-                    if x0 > x1 or y0 > y1:
-                        continue
-                    if x0 // tw <= a <= x1 // tw and y0 // th <= b <= y1 // th:
+                    x0, x1 = int(rect[r, 0] & 0xFFFF), int(rect[r, 0] >> 16)
+                    y0, y1 = int(rect[r, 1] & 0xFFFF), int(rect[r, 1] >> 16)
+                    # some pixel of the rect is a pixel of the tile
+                    if max(x0, px0) <= min(x1, px1) and max(y0, py0) <= min(y1, py1):
                         lst.append((int(bits[r]), r))
                 lst.sort()
                 s0, s1 = ranges[tid]
