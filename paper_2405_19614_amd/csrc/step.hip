@@ -184,19 +184,56 @@ __global__ void loss_total_kernel(int V, const double* tot, float* out, uint32_t
     }
 }
 
-__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                            float eps, const int32_t* step, const uint32_t* flags) {
+// Adam over every parameter group in one launch.  Group i owns blocks
+// [blk[i], blk[i + 1]); its elements go four to a thread with 16-byte loads
+// and stores when its four arrays are 16-byte aligned and its count is a
+// multiple of four (vec[i]), else one to a thread.
+struct AdamLaunch {
+    float* p[5];
+    const float* g[5];
+    float* m[5];
+    float* v[5];
+    int64_t n[5];
+    float lr[5];
+    int vec[5];
+    int64_t blk[6];
+};
+
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1, float b2,
+                                         float eps, float c1, float c2) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    p -= lr * (m * c1) / (sqrtf(v * c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(AdamLaunch a, float b1, float b2, float eps, const int32_t* step,
+                                                   const uint32_t* flags) {
     if (flags && *flags != 0u) return;   // the step is invalid: leave everything as it was
+    int gi = 0;
+    while (gi < 4 && (int64_t)blockIdx.x >= a.blk[gi + 1]) gi++;
     const float t = (float)(*step + 1);
     const float c1 = 1.f / (1.f - powf(b1, t));
     const float c2 = 1.f / (1.f - powf(b2, t));
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float gi = g[i];
-        const float mi = b1 * m[i] + (1.f - b1) * gi;
-        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-        m[i] = mi;
-        v[i] = vi;
-        p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    const float lr = a.lr[gi];
+    const int64_t nb = a.blk[gi + 1] - a.blk[gi];
+    const int64_t t0 = (blockIdx.x - a.blk[gi]) * (int64_t)blockDim.x + threadIdx.x, stride = nb * blockDim.x;
+    if (a.vec[gi]) {
+        float4* P = reinterpret_cast<float4*>(a.p[gi]);
+        const float4* G = reinterpret_cast<const float4*>(a.g[gi]);
+        float4* M = reinterpret_cast<float4*>(a.m[gi]);
+        float4* Vv = reinterpret_cast<float4*>(a.v[gi]);
+        for (int64_t i = t0; i < a.n[gi] / 4; i += stride) {
+            float4 p4 = P[i], m4 = M[i], v4 = Vv[i];
+            const float4 g4 = G[i];
+            adam_one(p4.x, g4.x, m4.x, v4.x, lr, b1, b2, eps, c1, c2);
+            adam_one(p4.y, g4.y, m4.y, v4.y, lr, b1, b2, eps, c1, c2);
+            adam_one(p4.z, g4.z, m4.z, v4.z, lr, b1, b2, eps, c1, c2);
+            adam_one(p4.w, g4.w, m4.w, v4.w, lr, b1, b2, eps, c1, c2);
+            P[i] = p4; M[i] = m4; Vv[i] = v4;
+        }
+    } else {
+        for (int64_t i = t0; i < a.n[gi]; i += stride)
+            adam_one(a.p[gi][i], a.g[gi][i], a.m[gi][i], a.v[gi][i], lr, b1, b2, eps, c1, c2);
     }
 }
 
@@ -379,17 +416,25 @@ hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, con
 
 hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, float b1, float b2, float eps,
                        const uint32_t* flags, hipStream_t s) {
-    int64_t off = 0;
+    AdamLaunch a;
+    int64_t off = 0, blocks = 0;
+    const auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
     for (int i = 0; i < 5; i++) {
-        const int64_t n = ag.cnt[i];
-        if (n > 0) {
-            int64_t b = (n + 255) / 256;
-            if (b > 16384) b = 16384;
-            adam_kernel<<<(unsigned)b, 256, 0, s>>>(ag.p[i], ag.g[i], m + off, v + off, n, ag.lr[i], b1, b2, eps,
-                                                    step, flags);
-        }
+        const int64_t n = ag.cnt[i] > 0 ? ag.cnt[i] : 0;
+        a.p[i] = ag.p[i];
+        a.g[i] = ag.g[i];
+        a.m[i] = m + off;
+        a.v[i] = v + off;
+        a.n[i] = n;
+        a.lr[i] = ag.lr[i];
+        a.vec[i] = n % 4 == 0 && al16(ag.p[i]) && al16(ag.g[i]) && al16(m + off) && al16(v + off);
+        a.blk[i] = blocks;
+        const int64_t items = a.vec[i] ? n / 4 : n;
+        blocks += std::min<int64_t>((items + 255) / 256, 8192);
         off += n;
     }
+    a.blk[5] = blocks;
+    if (blocks > 0) adam_kernel<<<(unsigned)blocks, 256, 0, s>>>(a, b1, b2, eps, step, flags);
     return hipGetLastError();
 }
 
