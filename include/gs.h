@@ -449,9 +449,9 @@ int gs_ssim(gs_ctx* ctx, const gs_camera* cams, int32_t V, const float* img, con
  * host-side rule over F keyframes in time order: keyframe 0 is selected;
  * keyframe i > 0 is selected when beta <= M < alpha * T, where M =
  * covis[p * F + i] is the number of feature matches between i and the last
- * selected keyframe p, and T = n_obs[p] is the number of matched map points
- * the keyframe p observes (the paper's "total number of matches in the
- * previous keyframe"; "previous" is read as the previous selected one).
+ * selected keyframe p, and T = n_obs[p] is the number of map points the
+ * keyframe p observes through its matches (the paper's T, counted for the
+ * previously selected keyframe).
  *   covis HOST int32 [F][F], n_obs HOST int32 [F], selected HOST int32 [F]
  *   (out, 1 = selected).  The paper uses alpha = 0.75, beta = 20.
  * Returns GS_EINVAL for F < 0, NULL pointers (F > 0) or a negative or
