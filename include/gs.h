@@ -75,7 +75,8 @@ typedef struct gs_ctx gs_ctx;
  *   colors         sh_degree == -1: [n][3] RGB (view independent, as in the paper)
  *                  sh_degree in 0..3: [n][(L+1)^2][3] real orthonormal SH
  *                  coefficients; colour = max(0, sum Y_lm(dir) k_lm + 0.5)
- *                  with dir the unit vector from the camera centre to the mean. */
+ *                  with dir the unit vector from the camera centre to the mean;
+ *                  16-byte aligned for sh_degree 1 and 3 (GS_EINVAL otherwise). */
 typedef struct {
     int64_t n;
     int32_t sh_degree;
@@ -88,7 +89,8 @@ typedef struct {
 } gs_gaussians;
 
 /* Gradients with the layout of gs_gaussians (device, FP32; quats unused and
- * may be NULL for an isotropic set).  Overwritten by gs_render_backward;
+ * may be NULL for an isotropic set; colors 16-byte aligned for sh_degree 1
+ * and 3, as the parameters').  Overwritten by gs_render_backward;
  * gs_mapping_step overwrites or accumulates (opts). */
 typedef struct {
     float* means;

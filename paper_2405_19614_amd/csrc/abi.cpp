@@ -216,6 +216,10 @@ bool arrays_ok(const gs_gaussians* g, const float* means, const float* ls, const
     return means && ls && (g->isotropic || q) && opl && col;
 }
 
+// a Gaussian's 3 (L+1)^2 SH coefficients are a multiple of four floats for
+// L = 1 and 3, and the kernels then move them in 16-byte accesses
+bool colours_vec(const gs_gaussians* g) { return g->sh_degree == 1 || g->sh_degree == 3; }
+
 int check_gaussians(gs_ctx* c, const gs_gaussians* g) {
     if (!g) return fail(c, GS_EINVAL, "gaussians is NULL");
     if (g->n < 0) return fail(c, GS_EINVAL, "n is negative");
@@ -225,12 +229,21 @@ int check_gaussians(gs_ctx* c, const gs_gaussians* g) {
         if (!arrays_ok(g, g->means, g->log_scales, g->quats, g->opacity_logits, g->colors))
             return fail(c, GS_EINVAL, "a Gaussian parameter pointer is NULL");
         if (!g->isotropic && ((uintptr_t)g->quats) % 16) return fail(c, GS_EINVAL, "quats must be 16-byte aligned");
+        if (colours_vec(g) && ((uintptr_t)g->colors) % 16)
+            return fail(c, GS_EINVAL, "colors must be 16-byte aligned for sh_degree 1 and 3");
     }
     return GS_OK;
 }
 
-bool grads_ok(const gs_gaussians* g, const gs_gaussian_grads* d) {
-    return d && arrays_ok(g, d->means, d->log_scales, d->quats, d->opacity_logits, d->colors);
+// the gradient arrays of g's layout are all there (and the colours' aligned
+// as check_gaussians asks of the parameters)
+int check_grads(gs_ctx* c, const gs_gaussians* g, const gs_gaussian_grads* d) {
+    if (g->n == 0) return GS_OK;
+    if (!d || !arrays_ok(g, d->means, d->log_scales, d->quats, d->opacity_logits, d->colors))
+        return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if (colours_vec(g) && ((uintptr_t)d->colors) % 16)
+        return fail(c, GS_EINVAL, "gradient colors must be 16-byte aligned for sh_degree 1 and 3");
+    return GS_OK;
 }
 
 // the Adam groups of g's layout: means, log-scales (log radii), quaternions
@@ -666,7 +679,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     int r = check_gaussians(c, g);
     if (r) return r;
     if (!poses || !state || !dL_dpose || !grads) return fail(c, GS_EINVAL, "a device pointer is NULL");
-    if (g->n > 0 && !grads_ok(g, grads)) return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if ((r = check_grads(c, g, grads))) return r;
     if (!tile_ok(plan->tile_w, plan->tile_h) || !bin_ok(plan->bin_w, plan->bin_h) ||
         !tile_ok(plan->bwd_tile_w, plan->bwd_tile_h))
         return fail(c, GS_EINVAL, "plan does not come from a forward pass");
@@ -765,7 +778,9 @@ int gs_adam_update(gs_ctx* c, gs_gaussians* g, const gs_gaussian_grads* grads, c
     if (r) return r;
     if (!adam || !adam->m || !adam->v || !adam->step) return fail(c, GS_EINVAL, "the Adam state is incomplete");
     if (V < 0 || V > GS_MAX_VIEWS) return fail(c, GS_EINVAL, "V=%d outside [0, %d]", V, GS_MAX_VIEWS);
-    if (o->update_gaussians && g->n > 0 && !grads_ok(g, grads)) return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if (o->update_gaussians && g->n > 0 &&
+        (!grads || !arrays_ok(g, grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors)))
+        return fail(c, GS_EINVAL, "a gradient pointer is NULL");
     if (o->update_poses && V > 0 && (!poses || !dL_dpose)) return fail(c, GS_EINVAL, "poses or dL_dpose is NULL");
     DeviceGuard dg(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1021,7 +1036,7 @@ int check_step(gs_ctx* c, gs_gaussians* g, gs_gaussian_grads* grads, const gs_ad
     if (r) return r;
     if (!grads || !poses || !tg || !ws || !color || !depth || !alpha || !loss_out || !dL_dpose)
         return fail(c, GS_EINVAL, "a required pointer is NULL");
-    if (g->n > 0 && !grads_ok(g, grads)) return fail(c, GS_EINVAL, "a gradient pointer is NULL");
+    if ((r = check_grads(c, g, grads))) return r;
     if (!tg->color || !tg->depth) return fail(c, GS_EINVAL, "target colour / depth is NULL");
     if (mt && mt->M > 0) {
         if (!mt->points || !mt->uv || !mt->view_idx) return fail(c, GS_EINVAL, "a match pointer is NULL");

@@ -350,9 +350,11 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint64_t* v
     const uint32_t cnt = (uint32_t)__popc(vis8);
     // a word never straddles two views (rows are padded to whole words): the
     // thread's eight records are Gaussians g0 .. g0 + 7 of view v
-    const int64_t row = vis_words(n);
-    const int64_t v = wi / row;
-    const int64_t r0 = v * n + (wi - v * row) * 64 + (base & 63);
+    // (32-bit division: the word count stays below 2^31, and a 64-bit
+    // division is a long software sequence)
+    const uint32_t row = (uint32_t)vis_words(n);
+    const uint32_t v = (uint32_t)wi / row;
+    const int64_t r0 = (int64_t)v * n + (int64_t)((uint32_t)wi - v * row) * 64 + (base & 63);
     // depths and rects are gathered before any store, so they are in flight at once
     float dz[kScanItems];
     uint2 rc[kScanItems];

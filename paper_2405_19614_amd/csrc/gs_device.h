@@ -123,8 +123,11 @@ __device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const flo
 }
 
 // Coefficient k = 3 l + channel of one Gaussian's SH colour, read from its
-// parameter array (CoefPtr) or from a copy strided S floats apart (CoefStrided,
-// the colour backward's LDS copy: lane t's coefficient k at t + S k).
+// parameter array (CoefPtr), from a copy strided S floats apart (CoefStrided,
+// the colour backward's LDS copy: lane t's coefficient k at t + S k), or from
+// registers loaded up front (CoefRegs: all N coefficients in flight at once,
+// in 16-byte loads when N is a multiple of four, where the row starts 16-byte
+// aligned).
 struct CoefPtr {
     const float* p;
     __device__ __forceinline__ float operator[](int k) const { return p[k]; }
@@ -133,6 +136,23 @@ template <int S>
 struct CoefStrided {
     const float* p;
     __device__ __forceinline__ float operator[](int k) const { return p[k * S]; }
+};
+template <int N>
+struct CoefRegs {
+    float c[N];
+    __device__ __forceinline__ explicit CoefRegs(const float* p) {
+        if (N % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < N / 4; q++) {
+                const float4 t = reinterpret_cast<const float4*>(p)[q];
+                c[4 * q] = t.x; c[4 * q + 1] = t.y; c[4 * q + 2] = t.z; c[4 * q + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < N; k++) c[k] = p[k];
+        }
+    }
+    __device__ __forceinline__ float operator[](int k) const { return c[k]; }
 };
 
 // View-dependent colour (SH of degree deg >= 0, coefficients sh) of a
@@ -382,6 +402,42 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
     if (!(fx0 <= fx1) || !(fy0 <= fy1)) return;
     o.x0 = (int)fx0; o.x1 = (int)fx1; o.y0 = (int)fy0; o.y1 = (int)fy1;
     o.valid = true;
+}
+
+// Conservative visibility test of a prepared Gaussian in view vi: false only
+// when project_view would find no pixel rect.  It takes project_view's
+// camera-space mean and projected mean and bounds the rect's half-widths from
+// above.  With W the pose's linear part, the 2D covariance's diagonal entry
+// a = w^T M w + 0.3 for w = j00 W_0 + j02 W_2 (rows of W), and
+// w^T M w <= s_max^2 |w|^2 with s_max^2 the world covariance's largest
+// eigenvalue (the largest scale squared); likewise c with
+// w = j11 W_1 + j12 W_2.  This holds for any linear W, rigid or not.  Against
+// rounding, a and c are widened by 1 % plus 0.01 px^2, the half-width
+// sqrt(qbox a) + 0.01 by 0.1 % plus 0.01 px, the near plane by 0.1 % and the
+// image bounds by one pixel.  qbox = 2 ln(255 o) + 0.05, as project_view's;
+// it is negative (no visibility) for o < 1/255.
+__device__ __forceinline__ bool may_be_visible(const float* mu, float smax2, float qbox, const ViewInfo& vi,
+                                               const float* T) {
+    const float mx = mu[0], my = mu[1], mz = mu[2];
+    const float p0 = T[0] * mx + T[1] * my + T[2] * mz + T[3];
+    const float p1 = T[4] * mx + T[5] * my + T[6] * mz + T[7];
+    const float pz = T[8] * mx + T[9] * my + T[10] * mz + T[11];
+    if (!(pz > 0.999f * kZNear) || !(qbox > 0.f)) return false;
+    const float iz = 1.f / pz;
+    const float u = vi.fx * p0 * iz + vi.cx;
+    const float v = vi.fy * p1 * iz + vi.cy;
+    const float limx = kJClamp * (float)vi.W / (2.f * vi.fx);
+    const float limy = kJClamp * (float)vi.H / (2.f * vi.fy);
+    const float tx = fminf(fmaxf(p0 * iz, -limx), limx) * pz;
+    const float ty = fminf(fmaxf(p1 * iz, -limy), limy) * pz;
+    const float j00 = vi.fx * iz, j11 = vi.fy * iz;
+    const float j02 = -vi.fx * tx * iz * iz, j12 = -vi.fy * ty * iz * iz;
+    const float wx0 = j00 * T[0] + j02 * T[8], wx1 = j00 * T[1] + j02 * T[9], wx2 = j00 * T[2] + j02 * T[10];
+    const float wy0 = j11 * T[4] + j12 * T[8], wy1 = j11 * T[5] + j12 * T[9], wy2 = j11 * T[6] + j12 * T[10];
+    const float a = 1.01f * (wx0 * wx0 + wx1 * wx1 + wx2 * wx2) * smax2 + (kDilate + 0.01f);
+    const float c = 1.01f * (wy0 * wy0 + wy1 * wy1 + wy2 * wy2) * smax2 + (kDilate + 0.01f);
+    const float hx = 1.001f * sqrtf(qbox * a) + 0.02f, hy = 1.001f * sqrtf(qbox * c) + 0.02f;
+    return (u + hx >= -1.f) && (u - hx <= (float)vi.W) && (v + hy >= -1.f) && (v - hy <= (float)vi.H);
 }
 
 // Records keep the conic in base-2 units with the opacity folded in:

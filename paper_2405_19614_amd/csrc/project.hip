@@ -16,28 +16,33 @@ namespace {
 
 constexpr int kProjBlock = 256;
 
-// Views per round of the deferred colour pass (and the LDS queue it uses:
-// kProjBlock x kProjChunk entries of 8 bytes).
+// Views per round of the forward's queue (kProjBlock x kProjChunk entries of
+// 4 bytes in LDS).
 constexpr int kProjChunk = 16;
 
-// One thread per Gaussian, looping over the views: the parameters come from
-// HBM once and stay in the thread's cache lines for the other views.
-// RGB (SH < 0): the colour is written with the rest of the record.  SH: the
-// colour needs the Gaussian's (L+1)^2 x 3 coefficients, and only about a
-// tenth of the (view, Gaussian) pairs is visible, so evaluating it in the
-// view loop would run the SH code on nearly every wavefront for every view
-// (a lane is visible somewhere in it) and fetch the coefficients once per
-// visible view.  Instead each round of kProjChunk views queues its visible
-// pairs in LDS (geometry already written), and the block then evaluates the
-// colours of the queued pairs with every lane busy.
+// One thread per Gaussian prepares it (activations, world covariance) once;
+// then, per round of kProjChunk views, two phases:
+//  A. each thread tests its Gaussian against each view of the round with the
+//     conservative may_be_visible (a few dozen instructions) and queues the
+//     (thread, view) pairs that pass in LDS;
+//  B. the block's threads take the queued pairs, every lane busy, and run the
+//     full projection (and the SH colour), writing each visible record's
+//     line, its visibility bit and its view-mask bit.
+// About a tenth of the (view, Gaussian) pairs are visible and they are
+// scattered over the Gaussians, so a thread looping over its own views would
+// run the full projection on nearly every wavefront for every view.  The
+// prepared Gaussians wait in LDS for phase B; the records' contents do not
+// depend on which lane projects them.
 template <int SH, bool ISO>
 __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt, Params P, const float* poses,
                                                                     Records rec, bool zero_g2, uint32_t* flags) {
-    constexpr bool DEFER = SH >= 0;
-    constexpr int kQ = DEFER ? kProjBlock * kProjChunk : 1;
-    __shared__ uint32_t s_ent[kQ];   // (thread << 8) | view
-    __shared__ float s_z[kQ];        // its depth
+    constexpr int kW = kProjBlock / 64;
+    __shared__ uint32_t s_ent[kProjBlock * kProjChunk];   // (thread << 8) | view
     __shared__ int s_n;
+    __shared__ float s_gp[11][kProjBlock];                // mu (3), M (6), o, (ok ? 1 : 0)
+    __shared__ unsigned long long s_vis[kProjChunk][kW];  // visibility words of the round
+    __shared__ unsigned long long s_vm[kProjBlock];       // view masks
+    __shared__ float s_T[kProjChunk][12];                 // the round's poses
     const int lane = threadIdx.x & 63;
     const int g = blockIdx.x * kProjBlock + threadIdx.x;
     const bool live = g < P.n;
@@ -46,87 +51,104 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
     gp.finite = true;
     if (live) gauss_prep<ISO>(P, g, gp);
     bool bad = !gp.finite;
-    uint64_t vm = 0;
+    // inputs of the conservative test
+    const float smax2 = fmaxf(fmaxf(gp.s[0] * gp.s[0], gp.s[1] * gp.s[1]), gp.s[2] * gp.s[2]);
+    const float qbox = (gp.ok && gp.o >= kAlphaMin) ? 2.f * logf(255.f * gp.o) + 0.05f : -1.f;
+#pragma unroll
+    for (int k = 0; k < 3; k++) s_gp[k][threadIdx.x] = gp.mu[k];
+#pragma unroll
+    for (int k = 0; k < 6; k++) s_gp[3 + k][threadIdx.x] = gp.M[k];
+    s_gp[9][threadIdx.x] = gp.o;
+    s_gp[10][threadIdx.x] = gp.ok ? 1.f : 0.f;
+    s_vm[threadIdx.x] = 0ull;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int step = DEFER ? kProjChunk : vt.V;
-    // this wavefront's word of each view's visibility row (64 consecutive
-    // Gaussians starting at a multiple of 64)
-    const int64_t vrow = vis_words(P.n), vword = (int64_t)(blockIdx.x * kProjBlock + (threadIdx.x & ~63)) >> 6;
-    for (int v0 = 0; v0 < vt.V; v0 += step) {
-        const int v1 = v0 + step < vt.V ? v0 + step : vt.V;
-        if (DEFER) {
-            if (threadIdx.x == 0) s_n = 0;
-            __syncthreads();
-        }
-        if (live) {
-            const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
-            for (int v = v0; v < v1; v++) {
-                const ViewInfo& vi = vt.v[v];
-                float T[12];
+    const int64_t vrow = vis_words(P.n);
+    for (int v0 = 0; v0 < vt.V; v0 += kProjChunk) {
+        const int v1 = v0 + kProjChunk < vt.V ? v0 + kProjChunk : vt.V;
+        if (threadIdx.x == 0) s_n = 0;
+        for (int k = threadIdx.x; k < (v1 - v0) * kW; k += kProjBlock) s_vis[k / kW][k % kW] = 0ull;
+        for (int k = threadIdx.x; k < (v1 - v0) * 12; k += kProjBlock) s_T[k / 12][k % 12] = poses[16 * (v0 + k / 12) + k % 12];
+        __syncthreads();
+        // phase A: the pairs that may be visible, queued (one LDS atomic per wavefront and view)
+        for (int v = v0; v < v1; v++) {
+            const ViewInfo& vi = vt.v[v];
+            float T[12];
 #pragma unroll
-                for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
-                Proj pr;
-                project_view<!DEFER, ISO>(P, g, gp, vi, T, pr);
-                const int64_t r = (int64_t)v * P.n + g;
-                if (pr.valid) {
-                    // the record line in 16-byte stores: base-2 conic with
-                    // log2(opacity) (the compositing kernels' form), colour and
-                    // depth, mean and rect, then (mapping step) the zeroed
-                    // gradient sums
-                    float4* q = reinterpret_cast<float4*>(rec.line + r);
-                    q[0] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
-                    if (!DEFER) {
-                        q[1] = make_float4(pr.col[0], pr.col[1], pr.col[2], pr.p[2]);
-                        bad |= pr.colbad;
-                    }
-                    q[2] = make_float4(pr.u, pr.v, __uint_as_float((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16)),
-                                       __uint_as_float((uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16)));
-                    q[3] = zero;
-                    if (zero_g2) {
-                        q[4] = zero; q[5] = zero; q[6] = zero; q[7] = zero;
-                    }
-                    vm |= 1ull << v;
-                }
-                const uint64_t bm = __ballot(pr.valid);
-                if (lane == first) rec.vis[v * vrow + vword] = bm;
-                if (DEFER) {
-                    // queue the wavefront's visible pairs: one LDS atomic per wavefront
-                    if (bm != 0ull) {
-                        const int leader = __ffsll((unsigned long long)bm) - 1;
-                        int base = 0;
-                        if (lane == leader) base = atomicAdd(&s_n, __popcll(bm));
-                        base = __shfl(base, leader, 64);
-                        if (pr.valid) {
-                            const int k = base + __popcll(bm & ((1ull << lane) - 1ull));
-                            s_ent[k] = ((uint32_t)threadIdx.x << 8) | (uint32_t)v;
-                            s_z[k] = pr.p[2];
-                        }
-                    }
-                }
+            for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
+            const bool pass = gp.ok && may_be_visible(gp.mu, smax2, qbox, vi, T);
+            const uint64_t bm = __ballot(pass);
+            if (bm != 0ull) {
+                const int leader = __ffsll((unsigned long long)bm) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&s_n, __popcll(bm));
+                base = __shfl(base, leader, 64);
+                if (pass) s_ent[base + __popcll(bm & ((1ull << lane) - 1ull))] = ((uint32_t)threadIdx.x << 8) | (uint32_t)v;
             }
         }
-        if (DEFER) {
-            __syncthreads();
-            const int nq = s_n;
-            for (int i = threadIdx.x; i < nq; i += kProjBlock) {
-                const uint32_t e = s_ent[i];
-                const int v = (int)(e & 255u);
-                const int gg = blockIdx.x * kProjBlock + (int)(e >> 8);
-                float T[12];
+        __syncthreads();
+        // phase B: the full projection of the queued pairs
+        const int nq = s_n;
+        for (int i = threadIdx.x; i < nq; i += kProjBlock) {
+            const uint32_t e = s_ent[i];
+            const int v = (int)(e & 255u), t = (int)(e >> 8);
+            const int gg = blockIdx.x * kProjBlock + t;
+            GPrep q;
+            q.ok = s_gp[10][t] != 0.f;
+            q.finite = true;
+            q.qn = 1.f;
+            q.qh[0] = 1.f; q.qh[1] = q.qh[2] = q.qh[3] = 0.f;
 #pragma unroll
-                for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
-                const float* mu = P.means + 3 * (int64_t)gg;
-                float dir[3], dirn, col[3];
+            for (int k = 0; k < 9; k++) q.R[k] = (k % 4 == 0) ? 1.f : 0.f;
+            q.s[0] = q.s[1] = q.s[2] = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) q.mu[k] = s_gp[k][t];
+#pragma unroll
+            for (int k = 0; k < 6; k++) q.M[k] = s_gp[3 + k][t];
+            q.o = s_gp[9][t];
+            float T[12];
+#pragma unroll
+            for (int k = 0; k < 12; k++) T[k] = s_T[v - v0][k];
+            const ViewInfo& vi = vt.v[v];
+            Proj pr;
+            project_view<SH < 0, ISO>(P, gg, q, vi, T, pr);
+            if (!pr.valid) continue;
+            float col[3];
+            if (SH < 0) {
+                col[0] = pr.col[0]; col[1] = pr.col[1]; col[2] = pr.col[2];
+                bad |= pr.colbad;
+            } else {
+                constexpr int K3 = SH < 0 ? 3 : 3 * (SH + 1) * (SH + 1);
+                const CoefRegs<K3> sh(P.col + (int64_t)gg * K3);
+                float dir[3], dirn;
                 bool cclamp[3], cb;
-                sh_colour(P, gg, mu[0], mu[1], mu[2], T, dir, dirn, col, cclamp, cb);
+                sh_colour_of(SH, sh, q.mu[0], q.mu[1], q.mu[2], T, dir, dirn, col, cclamp, cb);
                 bad |= cb;
-                reinterpret_cast<float4*>(rec.line + ((int64_t)v * P.n + gg))[1] =
-                    make_float4(col[0], col[1], col[2], s_z[i]);
             }
-            __syncthreads();
+            // the record line in 16-byte stores: base-2 conic with
+            // log2(opacity) (the compositing kernels' form), colour and
+            // depth, mean and rect, a zero pad, then (mapping step) the
+            // zeroed gradient sums
+            float4* ql = reinterpret_cast<float4*>(rec.line + ((int64_t)v * P.n + gg));
+            ql[0] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
+            ql[1] = make_float4(col[0], col[1], col[2], pr.p[2]);
+            ql[2] = make_float4(pr.u, pr.v, __uint_as_float((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16)),
+                                __uint_as_float((uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16)));
+            ql[3] = zero;
+            if (zero_g2) {
+                ql[4] = zero; ql[5] = zero; ql[6] = zero; ql[7] = zero;
+            }
+            atomicOr(&s_vis[v - v0][t >> 6], 1ull << (t & 63));
+            atomicOr(&s_vm[t], 1ull << v);
         }
+        __syncthreads();
+        // the round's visibility words (a wavefront wholly past the Gaussians has none)
+        for (int k = threadIdx.x; k < (v1 - v0) * kW; k += kProjBlock) {
+            const int64_t word = (int64_t)blockIdx.x * kW + k % kW;
+            if (word < vrow) rec.vis[(int64_t)(v0 + k / kW) * vrow + word] = s_vis[k / kW][k % kW];
+        }
+        __syncthreads();   // s_vis, s_T, s_ent and s_n are rewritten by the next round
     }
-    if (live) rec.vmask[g] = vm;
+    if (live) rec.vmask[g] = s_vm[threadIdx.x];
     // one atomic per wavefront that read a non-finite parameter, from its
     // first active lane
     const uint64_t bad_lanes = __ballot(bad);

@@ -173,3 +173,42 @@ def test_misaligned_state_is_rejected(ctx):
         torch.cuda.synchronize()
         print(f"[alignment] offset {off}: rc {rc}", flush=True)
         assert rc == want, (off, rc, ctx.lib.gs_last_error(ctx.h))
+
+
+def test_misaligned_sh_colours_are_rejected(ctx):
+    """With SH degree 1 or 3 a Gaussian's coefficients are a multiple of four
+    floats and the kernels read and write them in 16-byte accesses: colour
+    parameters or colour gradients 4 bytes past an aligned address are refused
+    on the host (GS_EINVAL) before any launch, the aligned ones work."""
+    import ctypes
+    import paper_2405_19614_amd as gs
+    from paper_2405_19614_amd import _abi as A
+    from paper_2405_19614_amd.binding import _p, _stream, cam_array
+    s = scenes.c5(n=500, views=1, width=32, height=24, seed=4)
+    assert s.sh_degree == 3
+    g, poses = dev_scene(s)
+    _, _, _, state, plan = ctx.forward(g, s.cams, poses)
+    torch.cuda.synchronize()
+    # the same coefficients, 4 bytes past an aligned address
+    m = g.colors.numel()
+    buf = torch.zeros(m + 4, device="cuda")
+    shifted = buf[1:1 + m].view_as(g.colors)
+    shifted.copy_(g.colors)
+    assert shifted.data_ptr() % 16 == 4
+    bad = gs.Gaussians(g.means, g.log_scales, g.quats, g.opacity_logits, shifted, g.sh_degree)
+    with pytest.raises(gs.GSError, match="colors must be 16-byte aligned"):
+        ctx.forward(bad, s.cams, poses)
+    npix = s.npix
+    dC, dD, dA = (torch.ones(k * npix, device="cuda") for k in (3, 1, 1))
+    grads = g.zeros_like()
+    dpose = torch.zeros(s.V, 6, device="cuda")
+    gst = g.struct()
+    for colors, want in [(shifted, A.GS_EINVAL), (grads.colors, A.GS_OK)]:
+        gg = A.gs_gaussian_grads(_p(grads.means), _p(grads.log_scales), _p(grads.quats), _p(grads.opacity_logits),
+                                 _p(colors))
+        rc = ctx.lib.gs_render_backward(ctx.h, ctypes.byref(gst), cam_array(s.cams), _p(poses), s.V, _p(state),
+                                        state.numel(), ctypes.byref(plan), _p(dC), _p(dD), _p(dA),
+                                        ctypes.byref(gg), _p(dpose), _stream())
+        torch.cuda.synchronize()
+        print(f"[colour alignment] gradient colours at {colors.data_ptr() % 16} mod 16: rc {rc}", flush=True)
+        assert rc == want, ctx.lib.gs_last_error(ctx.h)
