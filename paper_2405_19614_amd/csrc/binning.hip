@@ -394,6 +394,10 @@ constexpr int kPairItems = kScanTile / kPairThreads;
 __global__ __launch_bounds__(kPairThreads) void pair_count_kernel(const uint4* sinfo, const uint32_t* nvis_p,
                                                                   uint64_t* chunk) {
     const int64_t nvis = (int64_t)*nvis_p;
+    if ((int64_t)blockIdx.x * kScanTile >= nvis) {   // uniform: the whole chunk is past the records
+        if (threadIdx.x == 0) chunk[blockIdx.x] = 0ull;
+        return;
+    }
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kPairItems;
     uint64_t sum = 0;
 #pragma unroll

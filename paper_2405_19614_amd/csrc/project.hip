@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
             const ViewInfo& vi = vt.v[v];
             float T[12];
 #pragma unroll
-            for (int k = 0; k < 12; k++) T[k] = poses[16 * v + k];
+            for (int k = 0; k < 12; k++) T[k] = s_T[v - v0][k];
             const bool pass = gp.ok && may_be_visible(gp.mu, smax2, qbox, vi, T);
             const uint64_t bm = __ballot(pass);
             if (bm != 0ull) {
