@@ -313,6 +313,9 @@ Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     p.rec.line = reinterpret_cast<gs::RecLine*>(base + L.off_line);
     p.rec.vis = reinterpret_cast<uint64_t*>(base + L.off_vis);
     p.rec.vmask = reinterpret_cast<uint64_t*>(base + L.off_vmask);
+    p.rec.stage = reinterpret_cast<uint4*>(base + L.off_sinfo);
+    p.rec.bcount = reinterpret_cast<uint32_t*>(base + L.off_bcount);
+    p.rec.qcount = reinterpret_cast<uint32_t*>(base + L.off_qcount);
     p.ranges = reinterpret_cast<uint2*>(base + L.off_ranges);
     p.tfin = reinterpret_cast<float*>(base + L.off_tfin);
     p.last = reinterpret_cast<uint32_t*>(base + L.off_last);
@@ -412,8 +415,11 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     L.n_chunks = std::max<int64_t>(ceil_div(L.Rp, 2048), 1);
     L.lb_tiles_chunk = ceil_div(L.n_chunks, 2048);
     L.lb_tiles_hist = std::max<int64_t>(ceil_div(256 * L.sort_blocks, 2048), 1);
+    L.lb_tiles_proj = ceil_div(gs::proj_blocks(n) + 1, 2048);
     L.off_lb = take((size_t)lb_words(L) * 8);       // cleared with the scalars at the start of binning
     L.off_chunk = take((size_t)L.n_chunks * 8);
+    L.off_bcount = take((size_t)(gs::proj_blocks(n) + 1) * 4);
+    L.off_qcount = take((size_t)std::max<int64_t>(gs::proj_blocks(n), 1) * 4);
     L.off_line = take((size_t)R * sizeof(RecLine));
     L.off_vis = take((size_t)std::max<int64_t>(L.Rp / 64, 1) * 8);
     L.off_k0 = take((size_t)R * 4);
@@ -442,7 +448,9 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     }
     L.off_vmask = take((size_t)std::max<int64_t>(n, 1) * 8);
     L.off_info = take((size_t)std::max<int64_t>(R, 1) * 16);
-    L.off_sinfo = take((size_t)std::max<int64_t>(R, 1) * 16);
+    // (also the projection's per-block lists: kProjBlock * V slots per block)
+    const int64_t staged = gs::proj_blocks(n) * gs::kProjBlock * vt.V;
+    L.off_sinfo = take((size_t)std::max<int64_t>(std::max<int64_t>(R, staged), 1) * 16);
     L.bytes = o;
     return L;
 }
@@ -629,7 +637,7 @@ int render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, cons
         // the pair total stays on the device: an overflow zeroes the sort's
         // count (kFlagCapacity), so every list is empty and the render is too
         uint32_t* vals = nullptr;
-        GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, L.cap, s, &vals));
+        GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, L.cap, s, &vals));
         if (L.cap > 0 && vals != p.vals) return fail(c, GS_EDEVICE, "internal: sorted values in unexpected buffer");
         GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, p.vals, p.rec, color, depth, alpha, p.tfin, p.last, nullptr,
                                            p.ts, s));
@@ -637,7 +645,7 @@ int render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, cons
         plan->n_visible = -1;
         return GS_OK;
     }
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, nullptr, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");
@@ -967,7 +975,7 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, true, s, p.scal + gs::kFlags));
     GS_HIP(c, mark(1));
     uint32_t* vals = nullptr;
-    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, L.cap, s, &vals));
+    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, L.cap, s, &vals));
     GS_HIP(c, mark(2));
     gs::LossArgs la{tg->color, tg->depth, tg->mask, o->use_gate, o->gate_gamma, p.dC, p.dD, p.tilepart};
     GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, p.ts, s,
@@ -1217,7 +1225,7 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
     const uint2* rc = reinterpret_cast<const uint2*>(rect);
     GS_HIP(c, gs::launch_status_clear(L, base, s));
     GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.line, p.rec.vis, n, s));
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, depth, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, depth, false, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");

@@ -383,6 +383,53 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint64_t* v
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *n_visible = chunk_off[blockIdx.x] + tot;
 }
 
+// The forward projection's per-block lists (block b: qcount[b] entries at
+// stage[b * kProjBlock * V ...], one per queued pair in queue order) moved to
+// the compacted order of the visible records: block b's records start at
+// boff[b] (the exclusive scan of the blocks' visible counts, whose last entry
+// boff[nb] is the total) and follow in (view, Gaussian) order, the rank of
+// record (v, thread t) being the visible records of the block's earlier
+// bitmap words (views before v, then wavefronts before t's) plus those of its
+// own word below t.  Within a view this is record order, as the bitmap
+// compaction gives; records of different views never share a bin, so the
+// (bin, depth, record) order of the pairs is the same either way.
+__global__ __launch_bounds__(kScanThreads) void stage_copy_kernel(const uint4* stage, const uint32_t* qcount,
+                                                                  const uint32_t* boff, const uint64_t* vis,
+                                                                  int64_t n, int V, int64_t nb, int bw, int bh,
+                                                                  uint32_t* keys, uint32_t* vals, uint4* info,
+                                                                  uint32_t* n_visible) {
+    constexpr int kW = kProjBlock / 64;   // bitmap words per view of one projection block
+    static_assert(kMaxViews * kW <= kScanThreads, "one thread per bitmap word of the block");
+    __shared__ uint64_t s_w[kMaxViews * kW];
+    __shared__ uint32_t s_pre[kMaxViews * kW];
+    const int64_t b = blockIdx.x;
+    const int64_t vrow = vis_words(n);
+    const int k = threadIdx.x;
+    uint64_t wd = 0ull;
+    if (k < V * kW && b * kW + k % kW < vrow) wd = vis[(int64_t)(k / kW) * vrow + b * kW + k % kW];
+    if (k < V * kW) s_w[k] = wd;
+    uint32_t ex;
+    block_excl_scan((uint32_t)__popcll(wd), ex);
+    if (k < V * kW) s_pre[k] = ex;
+    __syncthreads();
+    const uint32_t o0 = boff[b];
+    if (b == nb - 1 && threadIdx.x == 0) *n_visible = boff[nb];
+    const uint4* src = stage + b * kProjBlock * (int64_t)V;
+    const uint32_t nq = qcount[b];
+    for (uint32_t i = threadIdx.x; i < nq; i += kScanThreads) {
+        const uint4 e = src[i];
+        if (e.x == kStageNone) continue;
+        const int v = (int)(e.x >> 8), t = (int)(e.x & 255u);
+        const int wk = v * kW + (t >> 6);
+        const uint32_t o = o0 + s_pre[wk] + (uint32_t)__popcll(s_w[wk] & ((1ull << (t & 63)) - 1ull));
+        const uint32_t x0 = e.z & 0xffffu, x1 = e.z >> 16, y0 = e.w & 0xffffu, y1 = e.w >> 16;
+        const uint32_t nt = (x1 / (uint32_t)bw - x0 / (uint32_t)bw + 1u) * (y1 / (uint32_t)bh - y0 / (uint32_t)bh + 1u);
+        keys[o] = e.y;
+        vals[o] = o;
+        info[o] = make_uint4((uint32_t)((int64_t)v * n + b * kProjBlock + t), nt, e.z, e.w);
+    }
+}
+
 // The pair kernels walk the depth-sorted visible records: 512 threads per
 // 2048-record chunk (four records each), so that the few chunks there are
 // run as many wavefronts.
@@ -745,7 +792,7 @@ hipError_t launch_status_clear(const Layout& L, char* base, hipStream_t s) {
 }
 
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
-                                const RecLine* lines, const float* depth_src, hipStream_t s) {
+                                const RecLine* lines, const float* depth_src, bool staged, hipStream_t s) {
     uint32_t* scal = GS_AT(uint32_t, L.off_scalars);
     uint64_t* lb = GS_AT(uint64_t, L.off_lb);
     uint32_t* k0 = GS_AT(uint32_t, L.off_k0);
@@ -760,12 +807,28 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     hipError_t e;
     // (the scalars and every chained-scan status word were cleared by
     // launch_status_clear before the projection)
-    // 1. visible records -> compacted (depth bits, record) in record order
-    scan_reduce_kernel<LoadBits><<<g, kScanThreads, 0, s>>>(LoadBits{vis, words}, L.Rp, csum);
-    scan_chained_kernel<<<gs, kScanThreads, 0, s>>>(csum, nc, lb, scal + kLbVis, scal + kFlags);
+    // 1. visible records -> compacted (depth bits, record), in record order
+    //    within each view
     uint4* info = GS_AT(uint4, L.off_info);
-    compact_kernel<<<g, kScanThreads, 0, s>>>(vis, words, vt.n, vt.bw, vt.bh, lines, depth_src, csum, k0, v0,
-                                              info, scal + kNVis);
+    if (staged) {
+        // from the forward projection's per-block lists (none when n = 0:
+        // the visible count stays at its cleared 0)
+        const int64_t nb = proj_blocks(vt.n);
+        if (nb > 0) {
+            uint32_t* bcount = GS_AT(uint32_t, L.off_bcount);
+            uint64_t* lbp = lb + 2 * L.lb_tiles_chunk + (int64_t)kLbHistUses * L.lb_tiles_hist;
+            scan_chained_kernel<<<(unsigned)L.lb_tiles_proj, kScanThreads, 0, s>>>(bcount, nb + 1, lbp,
+                                                                                  scal + kLbProj, scal + kFlags);
+            stage_copy_kernel<<<(unsigned)nb, kScanThreads, 0, s>>>(
+                GS_AT(uint4, L.off_sinfo), GS_AT(uint32_t, L.off_qcount), bcount, vis, vt.n, vt.V, nb, vt.bw,
+                vt.bh, k0, v0, info, scal + kNVis);
+        }
+    } else {
+        scan_reduce_kernel<LoadBits><<<g, kScanThreads, 0, s>>>(LoadBits{vis, words}, L.Rp, csum);
+        scan_chained_kernel<<<gs, kScanThreads, 0, s>>>(csum, nc, lb, scal + kLbVis, scal + kFlags);
+        compact_kernel<<<g, kScanThreads, 0, s>>>(vis, words, vt.n, vt.bw, vt.bh, lines, depth_src, csum, k0,
+                                                  v0, info, scal + kNVis);
+    }
     // 2. stable sort by depth bits (4 passes: the result is back in (k0, v0))
     uint64_t* hs[kLbHistUses];
     for (int i = 0; i < kLbHistUses; i++) hs[i] = lb + 2 * L.lb_tiles_chunk + (int64_t)i * L.lb_tiles_hist;
@@ -812,9 +875,9 @@ hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base,
 }
 
 hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
-                          const RecLine* lines, const float* depth_src, int64_t pair_bound, hipStream_t s,
-                          uint32_t** sorted_vals_out) {
-    hipError_t e = launch_binning_count(vt, L, base, vis, lines, depth_src, s);
+                          const RecLine* lines, const float* depth_src, bool staged, int64_t pair_bound,
+                          hipStream_t s, uint32_t** sorted_vals_out) {
+    hipError_t e = launch_binning_count(vt, L, base, vis, lines, depth_src, staged, s);
     if (e != hipSuccess) return e;
     return launch_binning_sort(vt, L, base, pair_bound, s, sorted_vals_out);
 }

@@ -150,7 +150,21 @@ struct Records {
     RecLine* line;    // R record lines
     uint64_t* vis;    // V * vis_words(n) visibility words
     uint64_t* vmask;  // per Gaussian (n entries): bit v set when its record in view v is visible
+    // The projection's lists for the binning (stage NULL: none): block b of
+    // the forward projection writes one entry per pair it queued, qcount[b]
+    // in all, at stage[b * kProjBlock * V ...]: (view << 8 | thread, depth
+    // bits, rect) for a visible record, kStageNone in .x for a rejected pair;
+    // bcount[b] = its visible records, and block 0 zeroes bcount[blocks], so
+    // that an exclusive scan of the blocks + 1 counts ends with the total.
+    uint4* stage;
+    uint32_t* bcount;
+    uint32_t* qcount;
 };
+constexpr uint32_t kStageNone = 0xffffffffu;
+
+// Gaussians per block of the forward projection
+constexpr int kProjBlock = 256;
+inline int64_t proj_blocks(int64_t n) { return (n + kProjBlock - 1) / kProjBlock; }
 
 // Gaussians per block of the projection backward; the per-view pose partial
 // sums are kept per such block (Layout::pose_blocks = ceil(n / kProjBwdSpan)).
@@ -174,7 +188,8 @@ struct Layout {
     size_t off_line, off_vis;                     // R record lines (gradient sums inside), visibility bitmap
     size_t off_vmask;                             // n uint64 (last, so it moves no other array)
     size_t off_info;                              // R uint4: (record, bin count, rect) per visible record (binning)
-    size_t off_sinfo;                             // R uint4: the same entries in depth order
+    size_t off_sinfo;                             // R uint4: the same entries in depth order; before the
+                                                  // depth sort, the projection's per-block lists (stage)
     size_t off_k0, off_v0, off_k1, off_v1;        // record sort (R)
     size_t off_pk0, off_pv0, off_pk1, off_pv1;    // pair sort (cap)
     size_t off_hist;                              // 256 * sort_blocks
@@ -186,7 +201,10 @@ struct Layout {
     size_t off_lb;                                // chained-scan tile status words (u64), right after the scalars
     int64_t n_chunks;                             // 2048-record chunks of the padded records (binning)
     int64_t lb_tiles_chunk, lb_tiles_hist;        // tiles of a chunk-sum scan and of a radix histogram scan
+    int64_t lb_tiles_proj;                        // tiles of the scan of the projection blocks' counts
     size_t off_chunk;                             // n_chunks u64 chunk sums / offsets
+    size_t off_bcount;                            // proj_blocks(n) + 1 u32 visible counts / offsets
+    size_t off_qcount;                            // proj_blocks(n) u32 queued pairs
     // mapping workspace only
     size_t off_dC, off_dD;                        // upstream gradients
     size_t off_tilepart;                          // tile partials (sized for the smallest tile)
@@ -204,15 +222,17 @@ struct Layout {
 // chunk, radix histograms: up to kLbHistUses passes per step).
 enum ScalarSlot {
     kNVis = 0, kNPairs = 1, kFlags = 2, kSticky = 3, kPairsLo = 4, kPairsHi = 5,
-    kLbVis = 6, kLbPairs = 7, kLbHist0 = 8, kNumScalars = 16
+    kLbVis = 6, kLbPairs = 7, kLbHist0 = 8, kLbProj = 16, kNumScalars = 17
 };
-constexpr int kLbHistUses = kNumScalars - kLbHist0;
+constexpr int kLbHistUses = kLbProj - kLbHist0;
 // kFlags bits: pair capacity exceeded; a chained scan gave up waiting; a
 // Gaussian parameter the step read is not finite
 constexpr uint32_t kFlagCapacity = 1u, kFlagLookback = 2u, kFlagNonFinite = 4u;
 // status words of the chained scans: two chunk-sum scans (visible records,
-// pairs), then kLbHistUses histogram scans
-inline int64_t lb_words(const Layout& L) { return 2 * L.lb_tiles_chunk + (int64_t)kLbHistUses * L.lb_tiles_hist; }
+// pairs), then kLbHistUses histogram scans, then the projection blocks' counts
+inline int64_t lb_words(const Layout& L) {
+    return 2 * L.lb_tiles_chunk + (int64_t)kLbHistUses * L.lb_tiles_hist + L.lb_tiles_proj;
+}
 
 // tiles_bound: per-tile buffers (workspace) are sized for max(tiles_bound, n_tiles) tiles
 Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, int64_t tiles_bound = 0);
@@ -253,14 +273,16 @@ hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, in
 hipError_t launch_status_clear(const Layout& L, char* base, hipStream_t s);
 
 // Binning: records -> sorted pair values and tile ranges.  All sizes bounded by
-// the layout; counts live on the device in the scalars block.
+// the layout; counts live on the device in the scalars block.  staged: the
+// forward projection listed the visible records per block (Records::stage),
+// so the compaction moves those lists instead of reading the bitmap.
 hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
-                          const RecLine* lines, const float* depth_src, int64_t pair_bound, hipStream_t s,
-                          uint32_t** sorted_vals_out);
+                          const RecLine* lines, const float* depth_src, bool staged, int64_t pair_bound,
+                          hipStream_t s, uint32_t** sorted_vals_out);
 // first half of binning (visibility, depth sort, pair emission); leaves the
 // pair total on the device (kPairsLo/Hi) and flags an exceeded capacity
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
-                                const RecLine* lines, const float* depth_src, hipStream_t s);
+                                const RecLine* lines, const float* depth_src, bool staged, hipStream_t s);
 // second half: the pairs' sort by bin (pair_bound: an upper bound of the
 // pair count, which is read on the device) and the per-bin ranges
 hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base, int64_t pair_bound, hipStream_t s,

@@ -14,8 +14,6 @@ namespace gs {
 
 namespace {
 
-constexpr int kProjBlock = 256;
-
 // Views per round of the forward's queue (kProjBlock x kProjChunk entries of
 // 4 bytes in LDS).
 constexpr int kProjChunk = 16;
@@ -27,7 +25,12 @@ constexpr int kProjChunk = 16;
 //     (thread, view) pairs that pass in LDS;
 //  B. the block's threads take the queued pairs, every lane busy, and run the
 //     full projection (and the SH colour), writing each visible record's
-//     line, its visibility bit and its view-mask bit.
+//     line, its visibility bit and its view-mask bit;
+//     With rec.stage set, phase B also writes every queued pair's entry
+//     (view and thread, depth, rect; or a mark for a pair the projection
+//     rejects) to the block's list, densely in queue order: the binning's
+//     compaction then reads these lists instead of gathering depth and rect
+//     from HBM, one 128-byte record line per visible record.
 // About a tenth of the (view, Gaussian) pairs are visible and they are
 // scattered over the Gaussians, so a thread looping over its own views would
 // run the full projection on nearly every wavefront for every view.  The
@@ -43,6 +46,8 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
     __shared__ unsigned long long s_vis[kProjChunk][kW];  // visibility words of the round
     __shared__ unsigned long long s_vm[kProjBlock];       // view masks
     __shared__ float s_T[kProjChunk][12];                 // the round's poses
+    __shared__ uint32_t s_qrun;                           // pairs queued in earlier rounds
+    __shared__ uint32_t s_nvis;                           // visible records of the block
     const int lane = threadIdx.x & 63;
     const int g = blockIdx.x * kProjBlock + threadIdx.x;
     const bool live = g < P.n;
@@ -61,6 +66,10 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
     s_gp[9][threadIdx.x] = gp.o;
     s_gp[10][threadIdx.x] = gp.ok ? 1.f : 0.f;
     s_vm[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) {
+        s_qrun = 0u;
+        s_nvis = 0u;
+    }
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     const int64_t vrow = vis_words(P.n);
     for (int v0 = 0; v0 < vt.V; v0 += kProjChunk) {
@@ -88,6 +97,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
         __syncthreads();
         // phase B: the full projection of the queued pairs
         const int nq = s_n;
+        const uint32_t qb = s_qrun;
         for (int i = threadIdx.x; i < nq; i += kProjBlock) {
             const uint32_t e = s_ent[i];
             const int v = (int)(e & 255u), t = (int)(e >> 8);
@@ -111,6 +121,15 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
             const ViewInfo& vi = vt.v[v];
             Proj pr;
             project_view<SH < 0, ISO>(P, gg, q, vi, T, pr);
+            if (rec.stage) {
+                // the pair's entry in the block's list for the binning, in
+                // queue order (an invisible pair is marked as such)
+                rec.stage[(int64_t)blockIdx.x * kProjBlock * vt.V + qb + i] =
+                    pr.valid ? make_uint4(((uint32_t)v << 8) | (uint32_t)t, __float_as_uint(pr.p[2]),
+                                          (uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16),
+                                          (uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16))
+                             : make_uint4(kStageNone, 0u, 0u, 0u);
+            }
             if (!pr.valid) continue;
             float col[3];
             if (SH < 0) {
@@ -146,9 +165,24 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
             const int64_t word = (int64_t)blockIdx.x * kW + k % kW;
             if (word < vrow) rec.vis[(int64_t)(v0 + k / kW) * vrow + word] = s_vis[k / kW][k % kW];
         }
+        if (threadIdx.x == 0) s_qrun = qb + (uint32_t)nq;
         __syncthreads();   // s_vis, s_T, s_ent and s_n are rewritten by the next round
     }
     if (live) rec.vmask[g] = s_vm[threadIdx.x];
+    if (rec.stage) {
+        // the block's visible records (the bits of its view masks) and its
+        // queued pairs
+        uint32_t c = (uint32_t)__popcll(s_vm[threadIdx.x]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+        if (lane == 0) atomicAdd(&s_nvis, c);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            rec.bcount[blockIdx.x] = s_nvis;
+            rec.qcount[blockIdx.x] = s_qrun;
+            if (blockIdx.x == 0) rec.bcount[gridDim.x] = 0u;
+        }
+    }
     // one atomic per wavefront that read a non-finite parameter, from its
     // first active lane
     const uint64_t bad_lanes = __ballot(bad);
