@@ -40,9 +40,21 @@ template <int SH, bool ISO>
 __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt, Params P, const float* poses,
                                                                     Records rec, bool zero_g2, uint32_t* flags) {
     constexpr int kW = kProjBlock / 64;
-    __shared__ uint32_t s_ent[kProjBlock * kProjChunk];   // (thread << 8) | view
+    constexpr int K3 = SH < 0 ? 3 : 3 * (SH + 1) * (SH + 1);   // colour floats per Gaussian
+    // SH coefficients of the Gaussians with queued pairs, staged in LDS per
+    // round (coefficient-major, kShSlots Gaussians; the others read theirs
+    // from HBM in phase B): a visible Gaussian is seen by several views, and
+    // per-pair reads would fetch its row once per view, 16 bytes per lane
+    constexpr bool kStageSh = SH >= 1;
+    constexpr int kShSlots = 80;
+    constexpr int kShVec = K3 % 4 == 0 ? 4 : 1;   // floats per load (a row starts 16-byte aligned)
+    __shared__ uint16_t s_ent[kProjBlock * kProjChunk];   // (thread << 6) | view
     __shared__ int s_n;
-    __shared__ float s_gp[11][kProjBlock];                // mu (3), M (6), o, (ok ? 1 : 0)
+    __shared__ float s_gp[10][kProjBlock];                // mu (3), M (6), o
+    __shared__ float s_sh[kStageSh ? K3 * kShSlots : 1];
+    __shared__ int16_t s_slot[kProjBlock];                // the thread's staging slot, -1 for none
+    __shared__ uint8_t s_own[kShSlots];                   // the thread owning a slot
+    __shared__ int s_wq[kW];                              // threads with queued pairs, per wavefront
     __shared__ unsigned long long s_vis[kProjChunk][kW];  // visibility words of the round
     __shared__ unsigned long long s_vm[kProjBlock];       // view masks
     __shared__ float s_T[kProjChunk][12];                 // the round's poses
@@ -64,7 +76,6 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
 #pragma unroll
     for (int k = 0; k < 6; k++) s_gp[3 + k][threadIdx.x] = gp.M[k];
     s_gp[9][threadIdx.x] = gp.o;
-    s_gp[10][threadIdx.x] = gp.ok ? 1.f : 0.f;
     s_vm[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) {
         s_qrun = 0u;
@@ -79,6 +90,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
         for (int k = threadIdx.x; k < (v1 - v0) * 12; k += kProjBlock) s_T[k / 12][k % 12] = poses[16 * (v0 + k / 12) + k % 12];
         __syncthreads();
         // phase A: the pairs that may be visible, queued (one LDS atomic per wavefront and view)
+        bool queued = false;
         for (int v = v0; v < v1; v++) {
             const ViewInfo& vi = vt.v[v];
             float T[12];
@@ -91,19 +103,53 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
                 int base = 0;
                 if (lane == leader) base = atomicAdd(&s_n, __popcll(bm));
                 base = __shfl(base, leader, 64);
-                if (pass) s_ent[base + __popcll(bm & ((1ull << lane) - 1ull))] = ((uint32_t)threadIdx.x << 8) | (uint32_t)v;
+                if (pass) s_ent[base + __popcll(bm & ((1ull << lane) - 1ull))] = (uint16_t)((threadIdx.x << 6) | v);
             }
+            queued |= pass;
         }
+        const uint64_t qm = __ballot(queued);
+        if (kStageSh && lane == 0) s_wq[threadIdx.x >> 6] = __popcll(qm);
         __syncthreads();
+        if (kStageSh) {
+            // slots in thread order, then the coefficient rows of the first
+            // kShSlots, slot-fastest so that a store instruction's lanes hit
+            // distinct LDS banks
+            int before = 0, m = 0;
+#pragma unroll
+            for (int w = 0; w < kW; w++) {
+                before += w < (int)(threadIdx.x >> 6) ? s_wq[w] : 0;
+                m += s_wq[w];
+            }
+            const int slot = queued ? before + __popcll(qm & ((1ull << lane) - 1ull)) : -1;
+            s_slot[threadIdx.x] = (int16_t)(slot < kShSlots ? slot : -1);
+            if (slot >= 0 && slot < kShSlots) s_own[slot] = (uint8_t)threadIdx.x;
+            m = m < kShSlots ? m : kShSlots;
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < kShSlots * (K3 / kShVec); idx += kProjBlock) {
+                const int j = idx % kShSlots, q = idx / kShSlots;
+                if (j >= m) continue;
+                const float* src = P.col + (int64_t)(blockIdx.x * kProjBlock + s_own[j]) * K3;
+                if (kShVec == 4) {
+                    const float4 c = reinterpret_cast<const float4*>(src)[q];
+                    s_sh[(4 * q) * kShSlots + j] = c.x;
+                    s_sh[(4 * q + 1) * kShSlots + j] = c.y;
+                    s_sh[(4 * q + 2) * kShSlots + j] = c.z;
+                    s_sh[(4 * q + 3) * kShSlots + j] = c.w;
+                } else {
+                    s_sh[q * kShSlots + j] = src[q];
+                }
+            }
+            __syncthreads();
+        }
         // phase B: the full projection of the queued pairs
         const int nq = s_n;
         const uint32_t qb = s_qrun;
         for (int i = threadIdx.x; i < nq; i += kProjBlock) {
             const uint32_t e = s_ent[i];
-            const int v = (int)(e & 255u), t = (int)(e >> 8);
+            const int v = (int)(e & 63u), t = (int)(e >> 6);
             const int gg = blockIdx.x * kProjBlock + t;
             GPrep q;
-            q.ok = s_gp[10][t] != 0.f;
+            q.ok = true;   // (only prepared Gaussians pass the test of phase A)
             q.finite = true;
             q.qn = 1.f;
             q.qh[0] = 1.f; q.qh[1] = q.qh[2] = q.qh[3] = 0.f;
@@ -136,11 +182,16 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
                 col[0] = pr.col[0]; col[1] = pr.col[1]; col[2] = pr.col[2];
                 bad |= pr.colbad;
             } else {
-                constexpr int K3 = SH < 0 ? 3 : 3 * (SH + 1) * (SH + 1);
-                const CoefRegs<K3> sh(P.col + (int64_t)gg * K3);
                 float dir[3], dirn;
                 bool cclamp[3], cb;
-                sh_colour_of(SH, sh, q.mu[0], q.mu[1], q.mu[2], T, dir, dirn, col, cclamp, cb);
+                const int slot = kStageSh ? (int)s_slot[t] : -1;
+                if (slot >= 0) {
+                    sh_colour_of(SH, CoefStrided<kShSlots>{s_sh + slot}, q.mu[0], q.mu[1], q.mu[2], T, dir, dirn,
+                                 col, cclamp, cb);
+                } else {
+                    const CoefRegs<K3> sh(P.col + (int64_t)gg * K3);
+                    sh_colour_of(SH, sh, q.mu[0], q.mu[1], q.mu[2], T, dir, dirn, col, cclamp, cb);
+                }
                 bad |= cb;
             }
             // the record line in 16-byte stores: base-2 conic with
