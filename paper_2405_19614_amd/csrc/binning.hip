@@ -435,24 +435,27 @@ __global__ __launch_bounds__(kScanThreads) void stage_copy_kernel(const uint4* s
 // run as many wavefronts.
 constexpr int kPairThreads = 512;
 constexpr int kPairItems = kScanTile / kPairThreads;
+constexpr int kPairGrid = 1024;   // blocks of the pair counting (four per CU, 32 wavefronts)
 
 // pairs (touched bins) of the depth-sorted visible records of one chunk
 // (their entries in depth order: sinfo[i] = (record, bin count, rect))
 __global__ __launch_bounds__(kPairThreads) void pair_count_kernel(const uint4* sinfo, const uint32_t* nvis_p,
-                                                                  uint64_t* chunk) {
+                                                                  uint64_t* chunk, int64_t nc) {
     const int64_t nvis = (int64_t)*nvis_p;
-    if ((int64_t)blockIdx.x * kScanTile >= nvis) {   // uniform: the whole chunk is past the records
-        if (threadIdx.x == 0) chunk[blockIdx.x] = 0ull;
-        return;
-    }
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kPairItems;
-    uint64_t sum = 0;
+    for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {   // (c is uniform over the block)
+        if (c * kScanTile >= nvis) {   // the whole chunk is past the records
+            if (threadIdx.x == 0) chunk[c] = 0ull;
+            continue;
+        }
+        const int64_t base = c * kScanTile + (int64_t)threadIdx.x * kPairItems;
+        uint64_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kPairItems; k++)
-        if (base + k < nvis) sum += sinfo[base + k].y;
-    uint64_t ex;
-    const uint64_t tot = block_excl_scan64<kPairThreads>(sum, ex);
-    if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
+        for (int k = 0; k < kPairItems; k++)
+            if (base + k < nvis) sum += sinfo[base + k].y;
+        uint64_t ex;
+        const uint64_t tot = block_excl_scan64<kPairThreads>(sum, ex);
+        if (threadIdx.x == 0) chunk[c] = tot;
+    }
 }
 
 // In-place exclusive scan of the chunks' pair counts (64-bit), chained; the
@@ -840,7 +843,11 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
     if (e != hipSuccess) return e;
     // 3. pairs in depth order: per-chunk counts, chained offsets (the total
     //    stays on the device), emission
-    pair_count_kernel<<<g, kPairThreads, 0, s>>>(sinfo, scal + kNVis, psum);
+    // (the visible count is on the device: a capped grid loops over the
+    // chunks for the counts; emission keeps one block per chunk, which
+    // measured faster than the loop)
+    const unsigned gp = (unsigned)std::min<int64_t>(nc, kPairGrid);
+    pair_count_kernel<<<gp, kPairThreads, 0, s>>>(sinfo, scal + kNVis, psum, nc);
     pair_offsets_kernel<<<gs, kScanThreads, 0, s>>>(psum, nc, L.cap, lb + L.lb_tiles_chunk, scal);
     emit_kernel<<<g, kPairThreads, 0, s>>>(vt, sinfo, scal + kNVis, psum, L.cap,
                                            GS_AT(uint32_t, L.off_pk0), GS_AT(uint32_t, L.off_pv0),
