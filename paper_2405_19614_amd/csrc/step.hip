@@ -218,18 +218,27 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamLaunch a, float b1, float
     const int64_t nb = a.blk[gi + 1] - a.blk[gi];
     const int64_t t0 = (blockIdx.x - a.blk[gi]) * (int64_t)blockDim.x + threadIdx.x, stride = nb * blockDim.x;
     if (a.vec[gi]) {
-        float4* P = reinterpret_cast<float4*>(a.p[gi]);
-        const float4* G = reinterpret_cast<const float4*>(a.g[gi]);
-        float4* M = reinterpret_cast<float4*>(a.m[gi]);
-        float4* Vv = reinterpret_cast<float4*>(a.v[gi]);
+        // each element is touched once: streaming (non-temporal) 16-byte
+        // accesses, which keep the caches out of the way (1.11 -> 1.00 ms
+        // for 177M parameters)
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        v4f* P = reinterpret_cast<v4f*>(a.p[gi]);
+        const v4f* G = reinterpret_cast<const v4f*>(a.g[gi]);
+        v4f* M = reinterpret_cast<v4f*>(a.m[gi]);
+        v4f* Vv = reinterpret_cast<v4f*>(a.v[gi]);
         for (int64_t i = t0; i < a.n[gi] / 4; i += stride) {
-            float4 p4 = P[i], m4 = M[i], v4 = Vv[i];
-            const float4 g4 = G[i];
-            adam_one(p4.x, g4.x, m4.x, v4.x, lr, b1, b2, eps, c1, c2);
-            adam_one(p4.y, g4.y, m4.y, v4.y, lr, b1, b2, eps, c1, c2);
-            adam_one(p4.z, g4.z, m4.z, v4.z, lr, b1, b2, eps, c1, c2);
-            adam_one(p4.w, g4.w, m4.w, v4.w, lr, b1, b2, eps, c1, c2);
-            P[i] = p4; M[i] = m4; Vv[i] = v4;
+            v4f p4 = __builtin_nontemporal_load(P + i), m4 = __builtin_nontemporal_load(M + i),
+                v4 = __builtin_nontemporal_load(Vv + i);
+            const v4f g4 = __builtin_nontemporal_load(G + i);
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                float pc = p4[c], mc = m4[c], vc = v4[c];
+                adam_one(pc, g4[c], mc, vc, lr, b1, b2, eps, c1, c2);
+                p4[c] = pc; m4[c] = mc; v4[c] = vc;
+            }
+            __builtin_nontemporal_store(p4, P + i);
+            __builtin_nontemporal_store(m4, M + i);
+            __builtin_nontemporal_store(v4, Vv + i);
         }
     } else {
         for (int64_t i = t0; i < a.n[gi]; i += stride)
