@@ -169,8 +169,10 @@ __device__ __forceinline__ int bin_of_tile(const ViewTable& vt, const ViewInfo& 
     return vi.bin_off + ((tyi * TH) / vt.bh) * vi.bins_x + (txi * TW) / vt.bw;
 }
 
+// At most six waves per SIMD: the compiler otherwise keeps 64 VGPRs for
+// eight and recomputes the pixel coordinates in the inner loop.
 template <int TW, int TH, int PPT, bool LOSS, bool COUNT>
-__global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
+__global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(1, 6))) void composite_fwd_kernel(ViewTable vt, const uint2* __restrict__ ranges,
                                                                      const uint32_t* __restrict__ vals, Records rec,
                                                                      float* color, float* depth, float* alpha,
                                                                      float* tfin, uint32_t* last, LossArgs la,
@@ -179,10 +181,15 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
                                                                      unsigned long long* counts) {
     constexpr int NT = TW * TH / PPT;
     static_assert(64 % TW == 0 && NT % 64 == 0, "a wavefront spans whole rows of the tile");
-    __shared__ float2 s_xy[NT];
-    __shared__ float4 s_co[NT];
-    __shared__ float4 s_cz[NT];
-    __shared__ uint2 s_rc[NT];
+    // the staged entries, one 64-byte record each, so that the inner loop
+    // reads all of an entry's fields from one LDS address register
+    struct alignas(16) Staged {
+        float4 co, cz;
+        float2 xy;
+        uint2 rc;
+        uint32_t j, pad[3];
+    };
+    __shared__ Staged s_e[NT];
     const int t = order ? (int)order[blockIdx.x] : (int)blockIdx.x;   // heaviest tiles first when ordered
     const int v = view_of_tile(vt, t);
     const ViewInfo& vi = vt.v[v];
@@ -193,7 +200,6 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
     const float fpx = (float)px;
     const uint2 rg = ranges[bin_of_tile(vt, vi, txi, tyi, TW, TH)];
     const int bx0 = txi * TW, bx1 = bx0 + TW - 1, by0 = tyi * TH, by1 = by0 + TH - 1;
-    __shared__ uint32_t s_j[NT];
 
     // T[q] < 0 marks a pixel that has stopped (or lies outside the image);
     // its transmittance is then -T[q]
@@ -234,21 +240,21 @@ __global__ __launch_bounds__(TW* TH / PPT) void composite_fwd_kernel(ViewTable v
         int cnt;
         const int pos = block_compact<NT>(pass, &cnt);
         if (pass) {
-            s_xy[pos] = exy;
-            s_co[pos] = eco;
-            s_cz[pos] = rec.line[r].col;
-            s_rc[pos] = rc;
-            s_j[pos] = j;
+            s_e[pos].xy = exy;
+            s_e[pos].co = eco;
+            s_e[pos].cz = rec.line[r].col;
+            s_e[pos].rc = rc;
+            s_e[pos].j = j;
         }
         __syncthreads();
         n_entries += (uint32_t)cnt;
         // every owned pixel is evaluated with predicated selects, no branch
         for (int k = 0; k < cnt; k++) {
-            const uint2 rc = s_rc[k];
-            const float2 xy = s_xy[k];
-            const float4 co = s_co[k];
-            const float4 cz = s_cz[k];
-            const uint32_t jk = __builtin_amdgcn_readfirstlane(s_j[k]) + 1u;
+            const uint2 rc = s_e[k].rc;
+            const float2 xy = s_e[k].xy;
+            const float4 co = s_e[k].co;
+            const float4 cz = s_e[k].cz;
+            const uint32_t jk = __builtin_amdgcn_readfirstlane(s_e[k].j) + 1u;
             // predicates combine with & (not &&): no per-pixel exec-mask branches
             const RectS rs = rect_scalar(rc);
             const bool colok = (px >= rs.x0) & (px <= rs.x1);   // counters only
