@@ -319,7 +319,9 @@ Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     p.ranges = reinterpret_cast<uint2*>(base + L.off_ranges);
     p.tfin = reinterpret_cast<float*>(base + L.off_tfin);
     p.last = reinterpret_cast<uint32_t*>(base + L.off_last);
-    p.g2 = reinterpret_cast<float*>(base + L.off_line) + gs::kG2Offset;
+    p.g2 = reinterpret_cast<float*>(base + L.off_g2);
+    p.rec.info = reinterpret_cast<const uint4*>(base + L.off_info);
+    p.rec.pre = reinterpret_cast<uint32_t*>(base + L.off_pre);
     p.ts.order = reinterpret_cast<uint32_t*>(base + L.off_torder);
     p.ts.work = reinterpret_cast<uint32_t*>(base + L.off_twork);
     p.posepart = reinterpret_cast<double*>(base + L.off_posepart);
@@ -420,7 +422,9 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     L.off_chunk = take((size_t)L.n_chunks * 8);
     L.off_bcount = take((size_t)(gs::proj_blocks(n) + 1) * 4);
     L.off_qcount = take((size_t)std::max<int64_t>(gs::proj_blocks(n), 1) * 4);
+    L.off_pre = take((size_t)std::max<int64_t>(gs::proj_blocks(n) * vt.V * (gs::kProjBlock / 64), 1) * 4);
     L.off_line = take((size_t)R * sizeof(RecLine));
+    L.off_g2 = take((size_t)std::max<int64_t>(R, 1) * gs::kG2Floats * 4);
     L.off_vis = take((size_t)std::max<int64_t>(L.Rp / 64, 1) * 8);
     L.off_k0 = take((size_t)R * 4);
     L.off_v0 = take((size_t)R * 4);
@@ -632,12 +636,12 @@ int render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, cons
     GS_HIP(c, gs::launch_status_clear(L, base, s));
     // a forward state's sticky word holds nothing older than this pass
     GS_HIP(c, gs::launch_fill_u32(p.scal + gs::kSticky, 0u, 1, s));
-    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, false, s, p.scal + gs::kFlags));
+    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, s, p.scal + gs::kFlags));
     if (!sync) {
         // the pair total stays on the device: an overflow zeroes the sort's
         // count (kFlagCapacity), so every list is empty and the render is too
         uint32_t* vals = nullptr;
-        GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, L.cap, s, &vals));
+        GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, nullptr, L.cap, s, &vals));
         if (L.cap > 0 && vals != p.vals) return fail(c, GS_EDEVICE, "internal: sorted values in unexpected buffer");
         GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, p.vals, p.rec, color, depth, alpha, p.tfin, p.last, nullptr,
                                            p.ts, s));
@@ -645,7 +649,7 @@ int render_forward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, cons
         plan->n_visible = -1;
         return GS_OK;
     }
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");
@@ -704,7 +708,7 @@ int gs_render_backward(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, 
     Ptrs p = ptrs_of(L, static_cast<char*>(state), false);
     const gs::Params P = params_of(g);
     gs::Grads G{grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->colors};
-    GS_HIP(c, gs::launch_zero_g2(p.rec.vis, p.g2, g->n, vt.V, s));
+    GS_HIP(c, gs::launch_zero_g2(p.scal + gs::kNVis, p.g2, L.R, s));
     GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, p.vals, p.rec, p.tfin, p.last, dC, dD, dA, p.g2, p.ts, vt,
                                        false, s));
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, 0, p.posepart, L.pose_blocks, s));
@@ -972,12 +976,14 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     GS_HIP(c, mark(0));
     GS_HIP(c, gs::launch_status_clear(L, base, s));
-    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, true, s, p.scal + gs::kFlags));
+    GS_HIP(c, gs::launch_preprocess_fwd(vt, P, poses, p.rec, s, p.scal + gs::kFlags));
     GS_HIP(c, mark(1));
     uint32_t* vals = nullptr;
-    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, L.cap, s, &vals));
+    GS_HIP(c, gs::launch_binning(vt, L, base, p.rec.vis, p.rec.line, nullptr, true, nullptr, L.cap, s, &vals));
     GS_HIP(c, mark(2));
-    gs::LossArgs la{tg->color, tg->depth, tg->mask, o->use_gate, o->gate_gamma, p.dC, p.dD, p.tilepart};
+    // (the forward compositing also zeroes the visible records' gradient sums)
+    gs::LossArgs la{tg->color, tg->depth, tg->mask, o->use_gate, o->gate_gamma, p.dC, p.dD, p.tilepart,
+                    p.g2, p.scal + gs::kNVis};
     GS_HIP(c, gs::launch_composite_fwd(vt, p.ranges, vals, p.rec, color, depth, alpha, p.tfin, p.last, &la, p.ts, s,
                                        counts));
     GS_HIP(c, mark(3));
@@ -1225,7 +1231,7 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
     const uint2* rc = reinterpret_cast<const uint2*>(rect);
     GS_HIP(c, gs::launch_status_clear(L, base, s));
     GS_HIP(c, gs::launch_rect_tiles(vt, rc, p.rec.line, p.rec.vis, n, s));
-    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, depth, false, s));
+    GS_HIP(c, gs::launch_binning_count(vt, L, base, p.rec.vis, p.rec.line, depth, false, nullptr, s));
     GS_HIP(c, hipMemcpyAsync(c->pinned, p.scal, gs::kNumScalars * 4, hipMemcpyDeviceToHost, s));
     GS_HIP(c, hipStreamSynchronize(s));
     if (c->pinned[gs::kFlags] & gs::kFlagLookback) return fail(c, GS_EDEVICE, "binning scan timed out");
@@ -1235,7 +1241,10 @@ int gs_bin_records(gs_ctx* c, const gs_camera* cams, int32_t V, int64_t n, int32
         return fail(c, GS_ECAPACITY, "%lld pairs exceed the capacity %lld", (long long)total, (long long)cap);
     uint32_t* vals = nullptr;
     GS_HIP(c, gs::launch_binning_sort(vt, L, base, total, s, &vals));
-    if (total > 0) GS_HIP(c, hipMemcpyAsync(values, vals, (size_t)total * 4, hipMemcpyDeviceToDevice, s));
+    // the sorted pairs carry compaction slots; the caller gets records
+    if (total > 0)
+        GS_HIP(c, gs::launch_slots_to_records(vals, p.rec.info, p.scal + gs::kNPairs, total,
+                                              reinterpret_cast<uint32_t*>(values), s));
     GS_HIP(c, hipMemcpyAsync(ranges, p.ranges, (size_t)L.n_bins * 8, hipMemcpyDeviceToDevice, s));
     return GS_OK;
 }

@@ -329,6 +329,11 @@ __global__ __launch_bounds__(kScanThreads) void scan_chained_kernel(uint32_t* a,
     }
 }
 
+// info[o].y = bin count | view << kInfoViewShift (a record's bins number at
+// most (16384 / 8)^2 < 2^22; views are at most 64)
+constexpr uint32_t kInfoViewShift = 24, kInfoCountMask = (1u << kInfoViewShift) - 1u;
+static_assert(kMaxViews <= 256, "the view fits above the bin count");
+
 // Visible records (nt != 0) of chunk blockIdx.x (kScanTile records), in
 // record order from the chunk's offset o: sort key = depth bits, sort value =
 // o, and info[o] = (record, bin count, pixel rect), so that the passes after
@@ -376,7 +381,7 @@ __global__ __launch_bounds__(kScanThreads) void compact_kernel(const uint64_t* v
                 (x1 / (uint32_t)bw - x0 / (uint32_t)bw + 1u) * (y1 / (uint32_t)bh - y0 / (uint32_t)bh + 1u);
             keys[o] = __float_as_uint(dz[k]);
             vals[o] = o;
-            info[o] = make_uint4((uint32_t)(r0 + k), nt, rc[k].x, rc[k].y);
+            info[o] = make_uint4((uint32_t)(r0 + k), nt | (v << kInfoViewShift), rc[k].x, rc[k].y);
             o++;
         }
     }
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(kScanThreads) void stage_copy_kernel(const uint4* s
                                                                   const uint32_t* boff, const uint64_t* vis,
                                                                   int64_t n, int V, int64_t nb, int bw, int bh,
                                                                   uint32_t* keys, uint32_t* vals, uint4* info,
-                                                                  uint32_t* n_visible) {
+                                                                  uint32_t* pre, float* g2, uint32_t* n_visible) {
     constexpr int kW = kProjBlock / 64;   // bitmap words per view of one projection block
     static_assert(kMaxViews * kW <= kScanThreads, "one thread per bitmap word of the block");
     __shared__ uint64_t s_w[kMaxViews * kW];
@@ -411,8 +416,10 @@ __global__ __launch_bounds__(kScanThreads) void stage_copy_kernel(const uint4* s
     uint32_t ex;
     block_excl_scan((uint32_t)__popcll(wd), ex);
     if (k < V * kW) s_pre[k] = ex;
-    __syncthreads();
     const uint32_t o0 = boff[b];
+    // the slot bases for the projection backward
+    if (k < V * kW) pre[b * V * kW + k] = o0 + ex;
+    __syncthreads();
     if (b == nb - 1 && threadIdx.x == 0) *n_visible = boff[nb];
     const uint4* src = stage + b * kProjBlock * (int64_t)V;
     const uint32_t nq = qcount[b];
@@ -426,7 +433,12 @@ __global__ __launch_bounds__(kScanThreads) void stage_copy_kernel(const uint4* s
         const uint32_t nt = (x1 / (uint32_t)bw - x0 / (uint32_t)bw + 1u) * (y1 / (uint32_t)bh - y0 / (uint32_t)bh + 1u);
         keys[o] = e.y;
         vals[o] = o;
-        info[o] = make_uint4((uint32_t)((int64_t)v * n + b * kProjBlock + t), nt, e.z, e.w);
+        info[o] = make_uint4((uint32_t)((int64_t)v * n + b * kProjBlock + t), nt | ((uint32_t)v << kInfoViewShift),
+                             e.z, e.w);
+        if (g2) {
+            float4* z = reinterpret_cast<float4*>(g2 + (int64_t)o * kG2Floats);
+            z[0] = z[1] = z[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
     }
 }
 
@@ -438,7 +450,7 @@ constexpr int kPairItems = kScanTile / kPairThreads;
 constexpr int kPairGrid = 1024;   // blocks of the pair counting (four per CU, 32 wavefronts)
 
 // pairs (touched bins) of the depth-sorted visible records of one chunk
-// (their entries in depth order: sinfo[i] = (record, bin count, rect))
+// (their entries in depth order: sinfo[i] = (slot, bin count | view << 24, rect))
 __global__ __launch_bounds__(kPairThreads) void pair_count_kernel(const uint4* sinfo, const uint32_t* nvis_p,
                                                                   uint64_t* chunk, int64_t nc) {
     const int64_t nvis = (int64_t)*nvis_p;
@@ -451,7 +463,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_count_kernel(const uint4* s
         uint64_t sum = 0;
 #pragma unroll
         for (int k = 0; k < kPairItems; k++)
-            if (base + k < nvis) sum += sinfo[base + k].y;
+            if (base + k < nvis) sum += sinfo[base + k].y & kInfoCountMask;
         uint64_t ex;
         const uint64_t tot = block_excl_scan64<kPairThreads>(sum, ex);
         if (threadIdx.x == 0) chunk[c] = tot;
@@ -494,7 +506,7 @@ __global__ __launch_bounds__(kScanThreads) void pair_offsets_kernel(uint64_t* a,
     }
 }
 
-// One (global bin id, record) pair per bin each depth-sorted visible record
+// One (global bin id, compaction slot) pair per bin each depth-sorted visible record
 // of the chunk touches, at the chunk's offset plus the rank within it; pairs
 // past the capacity are not written.  Also clears the per-bin ranges.
 __global__ __launch_bounds__(kPairThreads) void emit_kernel(ViewTable vt, const uint4* sinfo,
@@ -506,21 +518,21 @@ __global__ __launch_bounds__(kPairThreads) void emit_kernel(ViewTable vt, const 
     const int64_t nvis = (int64_t)*nvis_p;
     if ((int64_t)blockIdx.x * kScanTile >= nvis) return;   // uniform: the whole chunk is past the records
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kPairItems;
-    uint4 inf[kPairItems];   // (record, bin count, rect) of each depth-ordered record
+    uint4 inf[kPairItems];   // (slot, bin count | view << 24, rect) of each depth-ordered record
     uint64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kPairItems; k++) {
         inf[k] = base + k < nvis ? sinfo[base + k] : make_uint4(0u, 0u, 0u, 0u);
-        sum += inf[k].y;
+        sum += inf[k].y & kInfoCountMask;
     }
     uint64_t ex;
     block_excl_scan64<kPairThreads>(sum, ex);
     uint64_t o = chunk_off[blockIdx.x] + ex;
 #pragma unroll
     for (int k = 0; k < kPairItems; k++) {
-        if (inf[k].y == 0u) continue;
-        const uint32_t r = inf[k].x;
-        const ViewInfo& vi = vt.v[(int)(r / (uint32_t)vt.n)];
+        if ((inf[k].y & kInfoCountMask) == 0u) continue;
+        const uint32_t r = inf[k].x;   // the record's compaction slot
+        const ViewInfo& vi = vt.v[(int)(inf[k].y >> kInfoViewShift)];
         const uint2 rc = make_uint2(inf[k].z, inf[k].w);
         const uint32_t tx0 = (rc.x & 0xffffu) / vt.bw, tx1 = (rc.x >> 16) / vt.bw;
         const uint32_t ty0 = (rc.y & 0xffffu) / vt.bh, ty1 = (rc.y >> 16) / vt.bh;
@@ -670,7 +682,9 @@ __global__ __launch_bounds__(kRsThreads) void rs_downsweep_kernel(const uint32_t
             const uint32_t d = (kk >> shift) & 255u;
             const uint32_t pos = goff[d] + (i - toff[d]);
             if (pout) {
-                pout[pos] = pin[sv[i]];
+                // the entry in key order, its record replaced by its slot
+                const uint4 e = pin[sv[i]];
+                pout[pos] = make_uint4(sv[i], e.y, e.z, e.w);
             } else {
                 kout[pos] = kk;
                 vout[pos] = sv[i];
@@ -724,6 +738,11 @@ __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* np, uint2* r
     const uint32_t k = keys[i];
     if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
     if (i == (int64_t)P - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+}
+
+__global__ void slots_to_records_kernel(const uint32_t* slots, const uint4* info, const uint32_t* np, uint32_t* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (int64_t)*np) out[i] = info[slots[i]].x;
 }
 
 // each record's pixel rect (binning entry point) clipped to its image into
@@ -795,7 +814,8 @@ hipError_t launch_status_clear(const Layout& L, char* base, hipStream_t s) {
 }
 
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
-                                const RecLine* lines, const float* depth_src, bool staged, hipStream_t s) {
+                                const RecLine* lines, const float* depth_src, bool staged, float* zero_g2,
+                                hipStream_t s) {
     uint32_t* scal = GS_AT(uint32_t, L.off_scalars);
     uint64_t* lb = GS_AT(uint64_t, L.off_lb);
     uint32_t* k0 = GS_AT(uint32_t, L.off_k0);
@@ -824,7 +844,7 @@ hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base
                                                                                   scal + kLbProj, scal + kFlags);
             stage_copy_kernel<<<(unsigned)nb, kScanThreads, 0, s>>>(
                 GS_AT(uint4, L.off_sinfo), GS_AT(uint32_t, L.off_qcount), bcount, vis, vt.n, vt.V, nb, vt.bw,
-                vt.bh, k0, v0, info, scal + kNVis);
+                vt.bh, k0, v0, info, GS_AT(uint32_t, L.off_pre), zero_g2, scal + kNVis);
         }
     } else {
         scan_reduce_kernel<LoadBits><<<g, kScanThreads, 0, s>>>(LoadBits{vis, words}, L.Rp, csum);
@@ -882,14 +902,21 @@ hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base,
 }
 
 hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
-                          const RecLine* lines, const float* depth_src, bool staged, int64_t pair_bound,
-                          hipStream_t s, uint32_t** sorted_vals_out) {
-    hipError_t e = launch_binning_count(vt, L, base, vis, lines, depth_src, staged, s);
+                          const RecLine* lines, const float* depth_src, bool staged, float* zero_g2,
+                          int64_t pair_bound, hipStream_t s, uint32_t** sorted_vals_out) {
+    hipError_t e = launch_binning_count(vt, L, base, vis, lines, depth_src, staged, zero_g2, s);
     if (e != hipSuccess) return e;
     return launch_binning_sort(vt, L, base, pair_bound, s, sorted_vals_out);
 }
 
 #undef GS_AT
+
+hipError_t launch_slots_to_records(const uint32_t* slots, const uint4* info, const uint32_t* n, int64_t bound,
+                                   uint32_t* out, hipStream_t s) {
+    if (bound <= 0) return hipSuccess;
+    slots_to_records_kernel<<<(unsigned)((bound + 255) / 256), 256, 0, s>>>(slots, info, n, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_scan_u32(const uint32_t* a, int64_t n, uint32_t* out, uint32_t* bsum, uint32_t* total32,
                            hipStream_t s) {

@@ -117,27 +117,24 @@ struct Grads {
 //   [2] 2 dL/dA = sum sd dx^2   [3] dL/dB = sum sd dx dy   [4] 2 dL/dC = sum sd dy^2
 //   [5] o dL/do = -sum sd       [6..8] dL/dcolour          [9] dL/dz
 // The projection backward undoes the constant factors once per record.
+// They sit in a dense array indexed by the record's compaction slot o (its
+// rank among the visible records, Records::pre), kG2Floats floats each, so
+// that the backward kernels read 48 bytes per visible record from a few
+// hundred MB rather than a line each from the whole record array.
 constexpr int kG2Floats = 12;
 
-// One (view, Gaussian) record, r = v*n + g, in one 128-byte line: what the
-// projection leaves for binning and compositing in the first half, the
-// compositing backward's gradient sums in the second.  The projection of a
-// visible record writes the whole line, and compositing reads one half-line
-// per staged entry, instead of partial lines of five separate arrays.
-struct alignas(128) RecLine {
+// One (view, Gaussian) record, r = v*n + g, in one 64-byte line: what the
+// projection leaves for binning and compositing.  The projection of a
+// visible record writes its first 48 bytes; compositing reads them per
+// staged entry, instead of partial lines of several separate arrays.
+struct alignas(64) RecLine {
     float4 conic;   // (A', B', C', log2 opacity): conic in base-2 units, see frag_col
     float4 col;     // (r, g, b, depth)
     float2 xy;      // projected mean
     uint2 rect;     // inclusive pixel rect (x0 | x1 << 16, y0 | y1 << 16)
     float4 pad0;
-    float g2[kG2Floats];
-    float4 pad1;
 };
-static_assert(sizeof(RecLine) == 128, "one record per 128-byte line");
-
-// The gradient sums seen as a strided float array: g2 + r * kG2Stride.
-constexpr int kG2Stride = (int)(sizeof(RecLine) / sizeof(float));
-constexpr int kG2Offset = (int)(offsetof(RecLine, g2) / sizeof(float));
+static_assert(sizeof(RecLine) == 64, "one record per 64-byte line");
 
 // Visibility bitmap of the records: word v * vis_words(n) + g / 64, bit g % 64
 // set when record (v, g) is visible.  Each view's row is padded to whole
@@ -159,6 +156,14 @@ struct Records {
     uint4* stage;
     uint32_t* bcount;
     uint32_t* qcount;
+    // After binning: info[o] = (record, bin count | view << 24, rect) of the
+    // visible record in compaction slot o, and for projection block b,
+    // pre[(b * V + v) * 4 + w] = the slot of the first visible record of its
+    // wavefront w in view v; record (v, g) of block b's wavefront w then has
+    // slot pre[...] + (the visible records below g in its bitmap word).
+    // The sorted pairs carry slots, not records.
+    const uint4* info;
+    uint32_t* pre;
 };
 constexpr uint32_t kStageNone = 0xffffffffu;
 
@@ -205,6 +210,8 @@ struct Layout {
     size_t off_chunk;                             // n_chunks u64 chunk sums / offsets
     size_t off_bcount;                            // proj_blocks(n) + 1 u32 visible counts / offsets
     size_t off_qcount;                            // proj_blocks(n) u32 queued pairs
+    size_t off_pre;                               // proj_blocks(n) * V * 4 u32 slot bases (Records::pre)
+    size_t off_g2;                                // R * kG2Floats floats: gradient sums by compaction slot
     // mapping workspace only
     size_t off_dC, off_dD;                        // upstream gradients
     size_t off_tilepart;                          // tile partials (sized for the smallest tile)
@@ -242,7 +249,8 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
 // ---------------------------------------------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
-hipError_t launch_zero_g2(const uint64_t* vis, float* g2, int64_t n, int V, hipStream_t s);
+// zero the gradient sums of the visible records (device count *nvis, at most bound)
+hipError_t launch_zero_g2(const uint32_t* nvis, float* g2, int64_t bound, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
 // step[0] += gaussians, step[1] += poses (the two update counters)
 hipError_t launch_step_bump(int32_t* step, int gaussians, int poses, hipStream_t s, const uint32_t* flags = nullptr);
@@ -260,7 +268,7 @@ hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* li
 // log-scale, quaternion or opacity logit, or the colour of a visible record,
 // is not finite
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
-                                 bool zero_g2, hipStream_t s, uint32_t* flags = nullptr);
+                                 hipStream_t s, uint32_t* flags = nullptr);
 hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const float* poses, const Records& rec,
                                  const float* g2, Grads G, int accumulate, double* pose_part, int64_t pose_blocks,
                                  hipStream_t s);
@@ -272,17 +280,24 @@ hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, in
 // non-finite check already writes kFlags.
 hipError_t launch_status_clear(const Layout& L, char* base, hipStream_t s);
 
-// Binning: records -> sorted pair values and tile ranges.  All sizes bounded by
-// the layout; counts live on the device in the scalars block.  staged: the
-// forward projection listed the visible records per block (Records::stage),
-// so the compaction moves those lists instead of reading the bitmap.
+// Binning: records -> sorted pair values (compaction slots) and tile ranges.
+// All sizes bounded by the layout; counts live on the device in the scalars
+// block.  staged: the forward projection listed the visible records per block
+// (Records::stage), so the compaction moves those lists instead of reading the
+// bitmap, and writes the slot bases (Records::pre); zero_g2 (nullable): the
+// gradient sums of the visible records are zeroed on the way.
 hipError_t launch_binning(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
-                          const RecLine* lines, const float* depth_src, bool staged, int64_t pair_bound,
-                          hipStream_t s, uint32_t** sorted_vals_out);
+                          const RecLine* lines, const float* depth_src, bool staged, float* zero_g2,
+                          int64_t pair_bound, hipStream_t s, uint32_t** sorted_vals_out);
 // first half of binning (visibility, depth sort, pair emission); leaves the
 // pair total on the device (kPairsLo/Hi) and flags an exceeded capacity
 hipError_t launch_binning_count(const ViewTable& vt, const Layout& L, char* base, const uint64_t* vis,
-                                const RecLine* lines, const float* depth_src, bool staged, hipStream_t s);
+                                const RecLine* lines, const float* depth_src, bool staged, float* zero_g2,
+                                hipStream_t s);
+// the record of each of the n (device count) sorted pair slots, for callers
+// that take records: out[i] = info[slots[i]].x
+hipError_t launch_slots_to_records(const uint32_t* slots, const uint4* info, const uint32_t* n, int64_t bound,
+                                   uint32_t* out, hipStream_t s);
 // second half: the pairs' sort by bin (pair_bound: an upper bound of the
 // pair count, which is read on the device) and the per-bin ranges
 hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base, int64_t pair_bound, hipStream_t s,
@@ -297,6 +312,11 @@ struct LossArgs {
     float* dC;
     float* dD;
     double2* tile_part;
+    // (nullable) the gradient sums of the *nvis visible records, zeroed by
+    // the compositing blocks after their tiles (a grid-stride fill that the
+    // compute-bound forward hides)
+    float* g2;
+    const uint32_t* nvis;
 };
 
 // Order in which the compositing launches take their tiles (device, n_tiles

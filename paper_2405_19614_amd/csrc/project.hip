@@ -38,7 +38,7 @@ constexpr int kProjChunk = 16;
 // depend on which lane projects them.
 template <int SH, bool ISO>
 __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt, Params P, const float* poses,
-                                                                    Records rec, bool zero_g2, uint32_t* flags) {
+                                                                    Records rec, uint32_t* flags) {
     constexpr int kW = kProjBlock / 64;
     constexpr int K3 = SH < 0 ? 3 : 3 * (SH + 1) * (SH + 1);   // colour floats per Gaussian
     // SH coefficients of the Gaussians with queued pairs, staged in LDS per
@@ -81,7 +81,6 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
         s_qrun = 0u;
         s_nvis = 0u;
     }
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     const int64_t vrow = vis_words(P.n);
     for (int v0 = 0; v0 < vt.V; v0 += kProjChunk) {
         const int v1 = v0 + kProjChunk < vt.V ? v0 + kProjChunk : vt.V;
@@ -196,17 +195,12 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
             }
             // the record line in 16-byte stores: base-2 conic with
             // log2(opacity) (the compositing kernels' form), colour and
-            // depth, mean and rect, a zero pad, then (mapping step) the
-            // zeroed gradient sums
+            // depth, mean and rect (the pad is never read)
             float4* ql = reinterpret_cast<float4*>(rec.line + ((int64_t)v * P.n + gg));
             ql[0] = make_float4(kHalfLog2e * pr.A, 2.f * kHalfLog2e * pr.B, kHalfLog2e * pr.C, log2f(pr.o));
             ql[1] = make_float4(col[0], col[1], col[2], pr.p[2]);
             ql[2] = make_float4(pr.u, pr.v, __uint_as_float((uint32_t)pr.x0 | ((uint32_t)pr.x1 << 16)),
                                 __uint_as_float((uint32_t)pr.y0 | ((uint32_t)pr.y1 << 16)));
-            ql[3] = zero;
-            if (zero_g2) {
-                ql[4] = zero; ql[5] = zero; ql[6] = zero; ql[7] = zero;
-            }
             atomicOr(&s_vis[v - v0][t >> 6], 1ull << (t & 63));
             atomicOr(&s_vm[t], 1ull << v);
         }
@@ -347,6 +341,16 @@ __device__ __forceinline__ int pack_by_views(const uint64_t* vmask, int n, int64
 // sum_v Y(dir_v) dL/dcolour_v over the unclamped channels, the direction's
 // gradient mapped to the mean and to the camera centre (the pose tangent's
 // translation; the centre does not move under a rotation about itself).
+// Compaction slot of the visible record (v, g): the slot base of g's bitmap
+// word (its projection block's wavefront, in view v) plus the visible records
+// below g in that word (Records::pre)
+__device__ __forceinline__ uint32_t record_slot(const Records& rec, int64_t n, int V, int v, int64_t g) {
+    const uint64_t wd = rec.vis[(int64_t)v * vis_words(n) + (g >> 6)];
+    const int64_t b = g / kProjBlock;
+    const int w = (int)((g % kProjBlock) >> 6);
+    return rec.pre[(b * V + v) * (kProjBlock / 64) + w] + (uint32_t)__popcll(wd & ((1ull << (g & 63)) - 1ull));
+}
+
 // Runs before preprocess_bwd_kernel<SH>, which adds the geometric gradients
 // to the means and to the pose partials written here.  Kept apart because the
 // coefficient gradients (3K floats per Gaussian) and the geometric chain rule
@@ -359,7 +363,7 @@ __device__ __forceinline__ int pack_by_views(const uint64_t* vmask, int n, int64
 // Gaussians).
 template <int SH>
 __global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(ViewTable vt, Params P, const float* poses,
-                                                            const uint64_t* vmask, const float* g2, Grads G,
+                                                            Records rec, const float* g2, Grads G,
                                                             int accumulate, double* pose_part, int pose_blocks) {
     constexpr int K = (SH + 1) * (SH + 1);
     constexpr bool VEC = (3 * K) % 4 == 0;   // a Gaussian's coefficients start 16-byte aligned
@@ -384,14 +388,14 @@ __global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(Vie
         block_zero(G.means, 3 * g0, 3 * g1);
         block_zero(G.col, 3 * K * g0, 3 * K * g1);
     }
-    const int total = pack_by_views(vmask, P.n, g0, V, s_loc, nullptr, s_hist, s_wsum);
+    const int total = pack_by_views(rec.vmask, P.n, g0, V, s_loc, nullptr, s_hist, s_wsum);
 
     for (int base = 0; base < total; base += kProjBlock) {
         if (base + 64 * w >= total) break;   // nothing left for this wavefront
         const int e = base + (int)threadIdx.x;
         const bool live = e < total;
         const int g = live ? (int)(g0 + s_loc[e]) : 0;
-        const uint64_t vm = live ? vmask[g] : 0ull;
+        const uint64_t vm = live ? rec.vmask[g] : 0ull;
         float mx = 0.f, my = 0.f, mz = 0.f;
         if (live) {
             const float* mu = P.means + 3 * (int64_t)g;
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(Vie
                 float dir[3], dirn, col[3];
                 bool cclamp[3], cb;
                 sh_colour_of(SH, sh, mx, my, mz, T, dir, dirn, col, cclamp, cb);
-                const float* a = g2 + ((int64_t)v * P.n + g) * kG2Stride;
+                const float* a = g2 + (int64_t)record_slot(rec, P.n, V, v, g) * kG2Floats;
                 const float dcol[3] = {cclamp[0] ? 0.f : a[6], cclamp[1] ? 0.f : a[7], cclamp[2] ? 0.f : a[8]};
                 float Y[16];
                 sh_basis<false>(SH, dir[0], dir[1], dir[2], Y, nullptr);
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(kProjBlock, SH >= 3 ? 3 : 4) void sh_bwd_kernel(Vie
 // through the mean.
 template <int SH, bool ISO>
 __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable vt, Params P, const float* poses,
-                                                                    const uint64_t* vmask, const float* g2, Grads G,
+                                                                    Records rec, const float* g2, Grads G,
                                                                     int accumulate, double* pose_part,
                                                                     int pose_blocks) {
     constexpr int K = SH < 0 ? 1 : (SH + 1) * (SH + 1);
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
         }
         block_zero(G.opl, g0, g1);
     }
-    const int total = pack_by_views(vmask, P.n, g0, V, s_loc, s_mask, s_hist, s_wsum);
+    const int total = pack_by_views(rec.vmask, P.n, g0, V, s_loc, s_mask, s_hist, s_wsum);
 
     for (int base = 0; base < total; base += kProjBlock) {
         if (base + 64 * w >= total) break;   // nothing left for this wavefront
@@ -565,7 +569,6 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
         for (uint64_t rem = vmask; rem != 0ull; rem &= rem - 1ull) {
             const int v = __ffsll((unsigned long long)rem) - 1;
             float pose[6];
-            const int64_t r = (int64_t)v * P.n + g;
             {
                 ViewInfo vi;
                 vi.fx = s_cam[6 * v]; vi.fy = s_cam[6 * v + 1]; vi.cx = s_cam[6 * v + 2]; vi.cy = s_cam[6 * v + 3];
@@ -575,7 +578,8 @@ __global__ __launch_bounds__(kProjBlock, 4) void preprocess_bwd_kernel(ViewTable
                 for (int k = 0; k < 12; k++) T[k] = s_T[12 * v + k];
                 Proj pr;
                 project_view<false, ISO>(P, g, gp, vi, T, pr);
-                const float4* a4 = reinterpret_cast<const float4*>(g2 + r * kG2Stride);
+                const float4* a4 =
+                    reinterpret_cast<const float4*>(g2 + (int64_t)record_slot(rec, P.n, V, v, g) * kG2Floats);
                 const float4 a0 = a4[0], a1 = a4[1], a2 = a4[2];
                 // undo the compositing kernel's constant factors (g2 layout)
                 const float du = a0.x * (1.f / kHalfLog2e), dv = a0.y * (1.f / kHalfLog2e);
@@ -789,46 +793,46 @@ __global__ __launch_bounds__(256) void pose_finalize_kernel(const double* part, 
 }
 
 template <int SH, bool ISO>
-void fwd_one(const ViewTable& vt, const Params& P, const float* poses, Records rec, bool zero_g2, hipStream_t s,
+void fwd_one(const ViewTable& vt, const Params& P, const float* poses, Records rec, hipStream_t s,
              uint32_t* flags) {
     const unsigned nb = (unsigned)((P.n + kProjBlock - 1) / kProjBlock);
-    preprocess_fwd_kernel<SH, ISO><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, zero_g2, flags);
+    preprocess_fwd_kernel<SH, ISO><<<nb, kProjBlock, 0, s>>>(vt, P, poses, rec, flags);
 }
 
 template <bool ISO>
-hipError_t fwd_sh(const ViewTable& vt, const Params& P, const float* poses, Records rec, bool zero_g2, hipStream_t s,
+hipError_t fwd_sh(const ViewTable& vt, const Params& P, const float* poses, Records rec, hipStream_t s,
                   uint32_t* flags) {
     switch (P.sh) {
-        case -1: fwd_one<-1, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
-        case 0: fwd_one<0, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
-        case 1: fwd_one<1, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
-        case 2: fwd_one<2, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
-        case 3: fwd_one<3, ISO>(vt, P, poses, rec, zero_g2, s, flags); break;
+        case -1: fwd_one<-1, ISO>(vt, P, poses, rec, s, flags); break;
+        case 0: fwd_one<0, ISO>(vt, P, poses, rec, s, flags); break;
+        case 1: fwd_one<1, ISO>(vt, P, poses, rec, s, flags); break;
+        case 2: fwd_one<2, ISO>(vt, P, poses, rec, s, flags); break;
+        case 3: fwd_one<3, ISO>(vt, P, poses, rec, s, flags); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <int SH, bool ISO>
-void bwd_one(const ViewTable& vt, const Params& P, const float* poses, const uint64_t* vm, const float* g2, Grads G,
+void bwd_one(const ViewTable& vt, const Params& P, const float* poses, const Records& rec, const float* g2, Grads G,
              int accumulate, double* pose_part, int nb, hipStream_t s) {
     const size_t dyn_sh = (size_t)vt.V * (3 * sizeof(double) + 12 * sizeof(float));
     const size_t dyn_geo = (size_t)vt.V * (6 * sizeof(double) + 18 * sizeof(float));
     if constexpr (SH >= 0)
-        sh_bwd_kernel<SH><<<nb, kProjBlock, dyn_sh, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb);
-    preprocess_bwd_kernel<SH, ISO><<<nb, kProjBlock, dyn_geo, s>>>(vt, P, poses, vm, g2, G, accumulate, pose_part,
+        sh_bwd_kernel<SH><<<nb, kProjBlock, dyn_sh, s>>>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb);
+    preprocess_bwd_kernel<SH, ISO><<<nb, kProjBlock, dyn_geo, s>>>(vt, P, poses, rec, g2, G, accumulate, pose_part,
                                                                   nb);
 }
 
 template <bool ISO>
-hipError_t bwd_sh(const ViewTable& vt, const Params& P, const float* poses, const uint64_t* vm, const float* g2,
+hipError_t bwd_sh(const ViewTable& vt, const Params& P, const float* poses, const Records& rec, const float* g2,
                   Grads G, int accumulate, double* pose_part, int nb, hipStream_t s) {
     switch (P.sh) {
-        case -1: bwd_one<-1, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
-        case 0: bwd_one<0, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
-        case 1: bwd_one<1, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
-        case 2: bwd_one<2, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
-        case 3: bwd_one<3, ISO>(vt, P, poses, vm, g2, G, accumulate, pose_part, nb, s); break;
+        case -1: bwd_one<-1, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
+        case 0: bwd_one<0, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
+        case 1: bwd_one<1, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
+        case 2: bwd_one<2, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
+        case 3: bwd_one<3, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -837,10 +841,9 @@ hipError_t bwd_sh(const ViewTable& vt, const Params& P, const float* poses, cons
 }  // namespace
 
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
-                                 bool zero_g2, hipStream_t s, uint32_t* flags) {
+                                 hipStream_t s, uint32_t* flags) {
     if (P.n == 0) return hipSuccess;
-    return P.iso ? fwd_sh<true>(vt, P, poses, rec, zero_g2, s, flags)
-                 : fwd_sh<false>(vt, P, poses, rec, zero_g2, s, flags);
+    return P.iso ? fwd_sh<true>(vt, P, poses, rec, s, flags) : fwd_sh<false>(vt, P, poses, rec, s, flags);
 }
 
 hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const float* poses, const Records& rec,
@@ -849,8 +852,8 @@ hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const flo
     if (P.n == 0) return hipSuccess;
     const int nb = (P.n + kProjBwdSpan - 1) / kProjBwdSpan;
     if (nb != pose_blocks) return hipErrorInvalidValue;
-    return P.iso ? bwd_sh<true>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb, s)
-                 : bwd_sh<false>(vt, P, poses, rec.vmask, g2, G, accumulate, pose_part, nb, s);
+    return P.iso ? bwd_sh<true>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s)
+                 : bwd_sh<false>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s);
 }
 
 hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, int64_t pose_blocks,

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(1,
         float2 exy;
         float4 eco;
         if (j < rg.y) {
-            r = vals[j];
+            r = rec.info[vals[j]].x;   // the pair carries the record's compaction slot
             const float4 xr = reinterpret_cast<const float4*>(rec.line + r)[2];   // (x, y, rect)
             rc = make_uint2(__float_as_uint(xr.z), __float_as_uint(xr.w));
             pass = rect_meets(rc, bx0, bx1, by0, by1);
@@ -330,6 +330,11 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(1,
         }
     }
     if (threadIdx.x == 0) work[t] = n_entries;   // orders the backward
+    if (LOSS && la.g2) {
+        const int64_t m = (int64_t)*la.nvis * (kG2Floats / 4);
+        for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (int64_t)gridDim.x * NT)
+            reinterpret_cast<float4*>(la.g2)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     if (LOSS) {
         const double2 s = block_sum2<NT>(lc, ld);
         if (threadIdx.x == 0) la.tile_part[t] = s;
@@ -431,13 +436,14 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
         const int span = (int)(hi - lo);
         // stage, back to front, the entries whose rect meets this tile
         const uint32_t jj = hi - 1u - threadIdx.x;
-        uint32_t r = 0u;
+        uint32_t r = 0u, o = 0u;
         uint2 rc0 = make_uint2(1u, 1u);
         bool pass = false;
         float2 exy;
         float4 eco;
         if ((int)threadIdx.x < span) {
-            r = vals[jj];
+            o = vals[jj];              // the record's compaction slot (its gradient sums')
+            r = rec.info[o].x;
             const float4 xr = reinterpret_cast<const float4*>(rec.line + r)[2];   // (x, y, rect)
             rc0 = make_uint2(__float_as_uint(xr.z), __float_as_uint(xr.w));
             pass = rect_meets(rc0, bx0, bx1, by0, by1);
@@ -451,7 +457,7 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
         int cnt;
         const int pos = block_compact<NT>(pass, &cnt);
         if (pass) {
-            s_id[pos] = r;
+            s_id[pos] = o;
             s_j[pos] = jj;
             s_xy[pos] = exy;
             s_co[pos] = eco;
@@ -558,7 +564,7 @@ __global__ __launch_bounds__(TW* TH / PPT) __attribute__((amdgpu_waves_per_eu(4)
         }
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
-            float* dst = g2 + (int64_t)s_id[threadIdx.x] * kG2Stride;
+            float* dst = g2 + (int64_t)s_id[threadIdx.x] * kG2Floats;
             // d sigma / d mean is linear in (dx, dy) with the entry's conic
             // coefficients, which every pixel shares, so the mean gradient is
             // those coefficients applied to the two summed moments; slot 5

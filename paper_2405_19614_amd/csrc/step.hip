@@ -6,22 +6,20 @@
 // FP64 reduction of the per-tile partials written by the compositing epilogue.
 // Updates: Adam on every parameter group; pose steps applied on SE(3) by
 // left multiplication with the exponential of the Adam step.
+#include <algorithm>
+
 #include "gs_device.h"
 
 namespace gs {
 
 namespace {
 
-// one thread per record of the padded visibility index; visible ones only
-__global__ void zero_g2_kernel(const uint64_t* vis, float* g2, int64_t n, int V) {
-    const int64_t row = vis_words(n);
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= 64 * row * V || !((vis[p >> 6] >> (p & 63)) & 1ull)) return;
-    const int64_t v = (p >> 6) / row;
-    const int64_t r = v * n + (p - 64 * row * v);
-    float4* z = reinterpret_cast<float4*>(g2 + r * kG2Stride);
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    z[0] = zero; z[1] = zero; z[2] = zero;
+// the gradient sums of the *nvis visible records (their slots 0 .. *nvis - 1),
+// in 16-byte stores (the count is on the device: a capped grid strides)
+__global__ void zero_g2_kernel(const uint32_t* nvis, float* g2) {
+    const int64_t m = (int64_t)*nvis * (kG2Floats / 4);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        reinterpret_cast<float4*>(g2)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __global__ void zero_f64_kernel(double* p, int n) {
@@ -366,10 +364,10 @@ __global__ void step_bump_kernel(int32_t* step, int gaussians, int poses, const 
 
 }  // namespace
 
-hipError_t launch_zero_g2(const uint64_t* vis, float* g2, int64_t n, int V, hipStream_t s) {
-    const int64_t R = 64 * vis_words(n) * V;
-    if (R <= 0) return hipSuccess;
-    zero_g2_kernel<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(vis, g2, n, V);
+hipError_t launch_zero_g2(const uint32_t* nvis, float* g2, int64_t bound, hipStream_t s) {
+    const int64_t m = bound * (kG2Floats / 4);
+    if (m <= 0) return hipSuccess;
+    zero_g2_kernel<<<(unsigned)std::min<int64_t>((m + 255) / 256, 4096), 256, 0, s>>>(nvis, g2);
     return hipGetLastError();
 }
 
