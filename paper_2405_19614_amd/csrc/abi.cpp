@@ -324,6 +324,7 @@ Ptrs ptrs_of(const gs::Layout& L, char* base, bool workspace) {
     p.rec.pre = reinterpret_cast<uint32_t*>(base + L.off_pre);
     p.ts.order = reinterpret_cast<uint32_t*>(base + L.off_torder);
     p.ts.work = reinterpret_cast<uint32_t*>(base + L.off_twork);
+    p.ts.bucket = reinterpret_cast<uint8_t*>(base + L.off_tbucket);
     p.posepart = reinterpret_cast<double*>(base + L.off_posepart);
     p.scal = reinterpret_cast<uint32_t*>(base + L.off_scalars);
     p.vals = reinterpret_cast<uint32_t*>(base + ((tile_passes(L.n_bins) & 1) ? L.off_pv1 : L.off_pv0));
@@ -441,6 +442,7 @@ Layout make_layout(const ViewTable& vt, int64_t n, int64_t cap, bool workspace, 
     const int64_t tb = std::max<int64_t>(tiles_bound, vt.n_tiles);
     L.off_torder = take((size_t)tb * 4);
     L.off_twork = take((size_t)tb * 4);
+    L.off_tbucket = take((size_t)tb);
     L.off_posepart = take((size_t)vt.V * std::max<int64_t>(L.pose_blocks, 1) * 6 * 8);
     if (workspace) {
         L.off_dC = take((size_t)vt.n_pix * 3 * 4);

@@ -201,6 +201,7 @@ struct Layout {
     size_t off_ranges;                            // n_bins uint2
     size_t off_tfin, off_last;                    // n_pix
     size_t off_torder, off_twork;                 // tile order and work, sized for the smallest tile
+    size_t off_tbucket;                           // per-tile work bucket (u8), same size
     size_t off_posepart;                          // V * pose_blocks * 6 doubles
     size_t off_scalars;                           // counters and flags
     size_t off_lb;                                // chained-scan tile status words (u64), right after the scalars
@@ -326,6 +327,7 @@ struct LossArgs {
 struct TileSched {
     uint32_t* order;
     uint32_t* work;
+    uint8_t* bucket;   // per tile being ordered: its work bucket (scratch of the ordering)
 };
 
 // counts (nullable, device u64[4]): += candidates visited (rect contains the

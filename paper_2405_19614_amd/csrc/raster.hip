@@ -636,32 +636,48 @@ __device__ __forceinline__ int order_bucket(const ViewTable& vt, const TileGrid&
     return kOrderBuckets - 1 - (int)min(b, (uint32_t)(kOrderBuckets - 1));
 }
 
-__global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt, TileGrid vtf,
-                                                                    const uint2* __restrict__ ranges,
-                                                                    const uint32_t* __restrict__ work,
-                                                                    uint32_t* __restrict__ order) {
-    __shared__ uint32_t cnt[kOrderBuckets];
-    __shared__ OrderViews ov;
-    constexpr int kKeep = 8;   // buckets a thread keeps for the second pass
-    const int n = vt.n_tiles;
-    for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) cnt[i] = 0u;
-    for (int v = threadIdx.x; v < vt.V; v += kOrderThreads) {
+// Per-view tile geometry of the ordering, staged in LDS by each block
+__device__ __forceinline__ void stage_order_views(const ViewTable& vt, const TileGrid& vtf, OrderViews& ov,
+                                                  int nthreads) {
+    for (int v = threadIdx.x; v < vt.V; v += nthreads) {
         ov.toff[v] = vt.v[v].tile_off; ov.tx[v] = vt.v[v].tiles_x;
         ov.ftoff[v] = vtf.tile_off[v]; ov.ftx[v] = vtf.tiles_x[v]; ov.fty[v] = vtf.tiles_y[v];
         ov.boff[v] = vt.v[v].bin_off; ov.bx[v] = vt.v[v].bins_x;
     }
+}
+
+// the work bucket of every tile, one thread per tile over many workgroups (a
+// tile's estimate sums several forward tiles' counts: one workgroup issuing
+// them in sequence was the ordering's whole cost)
+constexpr int kBucketThreads = 256;
+__global__ __launch_bounds__(kBucketThreads) void tile_bucket_kernel(ViewTable vt, TileGrid vtf,
+                                                                     const uint2* __restrict__ ranges,
+                                                                     const uint32_t* __restrict__ work,
+                                                                     uint8_t* __restrict__ bucket) {
+    __shared__ OrderViews ov;
+    stage_order_views(vt, vtf, ov, kBucketThreads);
+    __syncthreads();
+    const int t = blockIdx.x * kBucketThreads + threadIdx.x;
+    if (t < vt.n_tiles) bucket[t] = (uint8_t)order_bucket(vt, vtf, ov, ranges, work, t);
+}
+
+// a counting sort of the tiles by bucket, in one workgroup
+__global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(int n, const uint8_t* __restrict__ bucket,
+                                                                    uint32_t* __restrict__ order) {
+    __shared__ uint32_t cnt[kOrderBuckets];
+    constexpr int kKeep = 8;   // buckets a thread keeps for the second pass
+    for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) cnt[i] = 0u;
     __syncthreads();
     int keep[kKeep];
 #pragma unroll
     for (int k = 0; k < kKeep; k++) {
         const int t = threadIdx.x + k * kOrderThreads;
-        keep[k] = t < n ? order_bucket(vt, vtf, ov, ranges, work, t) : 0;
+        keep[k] = t < n ? (int)bucket[t] : 0;
     }
 #pragma unroll
     for (int k = 0; k < kKeep; k++)
         if (threadIdx.x + k * kOrderThreads < n) atomicAdd(&cnt[keep[k]], 1u);
-    for (int t = threadIdx.x + kKeep * kOrderThreads; t < n; t += kOrderThreads)
-        atomicAdd(&cnt[order_bucket(vt, vtf, ov, ranges, work, t)], 1u);
+    for (int t = threadIdx.x + kKeep * kOrderThreads; t < n; t += kOrderThreads) atomicAdd(&cnt[bucket[t]], 1u);
     __syncthreads();
     static_assert(kOrderBuckets == 128, "two buckets per lane of one wavefront");
     if (threadIdx.x < 64) {
@@ -685,7 +701,7 @@ __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(ViewTable vt
         if (t < n) order[atomicAdd(&cnt[keep[k]], 1u)] = (uint32_t)t;
     }
     for (int t = threadIdx.x + kKeep * kOrderThreads; t < n; t += kOrderThreads)
-        order[atomicAdd(&cnt[order_bucket(vt, vtf, ov, ranges, work, t)], 1u)] = (uint32_t)t;
+        order[atomicAdd(&cnt[bucket[t]], 1u)] = (uint32_t)t;
 }
 
 template <int TW, int TH, int PPT>
@@ -716,7 +732,10 @@ hipError_t bwd_t(const ViewTable& vt, const uint2* ranges, const uint32_t* vals,
                  float* g2, const TileSched& ts, const ViewTable& vtf, bool ordered, hipStream_t s) {
     if (vt.n_tiles == 0) return hipSuccess;
     constexpr int NT = TW * TH / PPT;
-    if (!ordered) order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt, tile_grid(vtf), ranges, ts.work, ts.order);
+    if (!ordered) {
+        const hipError_t e = launch_order_tiles(vt, vtf, ranges, ts, s);
+        if (e != hipSuccess) return e;
+    }
     composite_bwd_kernel<TW, TH, PPT><<<vt.n_tiles, NT, 0, s>>>(vt, ranges, vals, rec, tfin, last, dC, dD, dA, g2,
                                                                  ts.order);
     return hipGetLastError();
@@ -764,7 +783,9 @@ hipError_t launch_composite_bwd(const ViewTable& vt, const uint2* ranges, const 
 hipError_t launch_order_tiles(const ViewTable& vt, const ViewTable& vtf, const uint2* ranges, const TileSched& ts,
                               hipStream_t s) {
     if (vt.n_tiles == 0) return hipSuccess;
-    order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt, tile_grid(vtf), ranges, ts.work, ts.order);
+    tile_bucket_kernel<<<(unsigned)((vt.n_tiles + kBucketThreads - 1) / kBucketThreads), kBucketThreads, 0, s>>>(
+        vt, tile_grid(vtf), ranges, ts.work, ts.bucket);
+    order_tiles_kernel<<<1, kOrderThreads, 0, s>>>(vt.n_tiles, ts.bucket, ts.order);
     return hipGetLastError();
 }
 
