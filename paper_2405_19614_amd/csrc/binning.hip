@@ -740,6 +740,19 @@ __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* np, uint2* r
     if (i == (int64_t)P - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
 }
 
+// Per-bin ranges when the pairs were sorted in one 8-bit pass: the pass's
+// scanned histogram table (digit-major, nb blocks) holds at hist[d * nb] the
+// number of pairs whose bin is below d, i.e. where bin d's range starts.
+// Empty bins get (0, 0), as ranges_kernel leaves them.
+__global__ void ranges_from_hist_kernel(const uint32_t* hist, int64_t nb, const uint32_t* np, int n_bins,
+                                        uint2* ranges) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n_bins) return;
+    const uint32_t b = hist[(int64_t)d * nb];
+    const uint32_t e = d + 1 < 256 ? hist[(int64_t)(d + 1) * nb] : *np;
+    ranges[d] = e > b ? make_uint2(b, e) : make_uint2(0u, 0u);
+}
+
 __global__ void slots_to_records_kernel(const uint32_t* slots, const uint4* info, const uint32_t* np, uint32_t* out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < (int64_t)*np) out[i] = info[slots[i]].x;
@@ -893,7 +906,13 @@ hipError_t launch_binning_sort(const ViewTable& vt, const Layout& L, char* base,
     if (e != hipSuccess) return e;
     const uint32_t* keys = second ? pk1 : pk0;
     uint2* ranges = GS_AT(uint2, L.off_ranges);
-    if (pair_bound > 0) {
+    const int bits = ceil_log2(L.n_bins);
+    if (pair_bound > 0 && bits >= 1 && bits <= 8) {
+        // one pass: the ranges are the scanned histogram's digit offsets
+        const int64_t nb = std::min<int64_t>((pair_bound + kRsTile - 1) / kRsTile, kRsMaxGrid);
+        ranges_from_hist_kernel<<<(unsigned)((L.n_bins + 255) / 256), 256, 0, s>>>(
+            GS_AT(uint32_t, L.off_hist), nb, scal + kNPairs, (int)L.n_bins, ranges);
+    } else if (pair_bound > 0) {
         const int64_t g = (pair_bound + 255) / 256;
         ranges_kernel<<<(unsigned)g, 256, 0, s>>>(keys, scal + kNPairs, ranges);
     }
