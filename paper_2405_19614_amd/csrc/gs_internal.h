@@ -264,7 +264,6 @@ hipError_t launch_pose_tangent_grad(int V, const float* xi, const float* g, floa
 hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* lines, uint64_t* vis, int64_t n,
                              hipStream_t s);
 
-// zero_g2: also clear each visible record's gradient sums (mapping step);
 // flags (nullable, device u32): OR-ed with kFlagNonFinite when a mean,
 // log-scale, quaternion or opacity logit, or the colour of a visible record,
 // is not finite

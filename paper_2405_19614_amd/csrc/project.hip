@@ -30,7 +30,7 @@ constexpr int kProjChunk = 16;
 //     (view and thread, depth, rect; or a mark for a pair the projection
 //     rejects) to the block's list, densely in queue order: the binning's
 //     compaction then reads these lists instead of gathering depth and rect
-//     from HBM, one 128-byte record line per visible record.
+//     from HBM, one record line per visible record.
 // About a tenth of the (view, Gaussian) pairs are visible and they are
 // scattered over the Gaussians, so a thread looping over its own views would
 // run the full projection on nearly every wavefront for every view.  The
