@@ -204,6 +204,8 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
     p -= lr * (m * c1) / (sqrtf(v * c2) + eps);
 }
 
+constexpr int64_t kAdamMaxBlocks = int64_t(1) << 21;   // per group; five groups stay below 2^32 threads
+
 __global__ __launch_bounds__(256) void adam_kernel(AdamLaunch a, float b1, float b2, float eps, const int32_t* step,
                                                    const uint32_t* flags) {
     if (flags && *flags != 0u) return;   // the step is invalid: leave everything as it was
@@ -437,7 +439,10 @@ hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, 
         a.vec[i] = n % 4 == 0 && al16(ag.p[i]) && al16(ag.g[i]) && al16(m + off) && al16(v + off);
         a.blk[i] = blocks;
         const int64_t items = a.vec[i] ? n / 4 : n;
-        blocks += std::min<int64_t>((items + 255) / 256, 8192);
+        // one 16-byte item per thread: a grid-stride loop over a capped grid
+        // (8192 blocks per group) ran 0.96 ms for 177M parameters, this 0.81
+        // ms; the cap only keeps the grid's thread count within 32 bits
+        blocks += std::min<int64_t>((items + 255) / 256, kAdamMaxBlocks);
         off += n;
     }
     a.blk[5] = blocks;
