@@ -219,7 +219,7 @@ def set_shape(ctx, spec, g, cams, poses):
     TWxTH,PPT,BWxBH[,BTWxBTH,BPPT].  Returns (tile, bin, bwd tile, seconds)."""
     t0 = time.perf_counter()
     if spec == "auto":
-        tile, binsz = ctx.autotune(g, cams, poses, iters=2)
+        tile, binsz = ctx.autotune(g, cams, poses, iters=3)
     else:
         vals = [int(x) for x in spec.lower().replace("x", ",").split(",")]
         tw, th, ppt, bw, bh = vals[:5]

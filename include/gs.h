@@ -395,8 +395,8 @@ int gs_bin_records(gs_ctx* ctx, const gs_camera* cams, int32_t V, int64_t n, int
  * bins and keeps the fastest forward and the fastest backward shape
  * separately, then times every bin size that is a multiple of both, then
  * every shape again at the chosen bins (allocating temporary device
- * buffers).  A candidate displaces an earlier one only when it is more than
- * 2 % faster, so near-ties resolve the same way from run to run.  Keeps the
+ * buffers).  A tile shape displaces an earlier one only when it is more
+ * than 2 % faster, so near-ties resolve the same way from run to run.  Keeps the
  * result as the context's
  * choice for this (V, sizes, n) class and returns the forward tile, the bin
  * and the backward tile (HOST outputs).  Synchronises the device.  No result

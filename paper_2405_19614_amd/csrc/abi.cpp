@@ -1362,10 +1362,11 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
     const int cand[kCand][3] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {16, 8, 1},  {16, 8, 2},  {8, 8, 1},
                                 {32, 8, 1},  {32, 8, 2},  {32, 8, 4},  {32, 16, 1}, {32, 16, 2}, {32, 16, 4},
                                 {32, 16, 8}, {32, 32, 4}, {32, 32, 8}, {32, 64, 8}, {64, 32, 8}, {64, 64, 8}};
-    // a later candidate (or bin size) replaces the best so far only when it is
-    // faster by more than this margin: near-equal shapes (the backward's 32x64
-    // and 64x32 differ by less than run-to-run noise) then resolve to the same
-    // one from run to run, the earliest in list order
+    // a later tile shape replaces the best so far only when it is faster by
+    // more than this margin: near-equal shapes (the backward's 32x64 and 64x32
+    // differ by less than run-to-run noise) then resolve to the same one from
+    // run to run, the earliest in list order.  Bin sizes take no margin: the
+    // smaller ones come first and are rarely the better choice.
     constexpr float kBetter = 0.98f;
     gs_ctx::Tuned best{16, 16, 64, 64, 2, 16, 16, 2};
     float best_f = 1e30f, best_b = 1e30f;
@@ -1397,7 +1398,7 @@ int gs_autotune(gs_ctx* c, const gs_gaussians* g, const gs_camera* cams, const f
         if (bw % best.tw || bh % best.th || bw % best.btw || bh % best.bth || (bw == 64 && bh == 64)) continue;
         float fm, bm;
         if (!time_cfg(best.tw, best.th, best.ppt, best.btw, best.bth, best.bppt, bw, bh, &fm, &bm, &rc)) break;
-        if (fm + bm < kBetter * best_ms) {
+        if (fm + bm < best_ms) {
             best_ms = fm + bm;
             best.bw = bw;
             best.bh = bh;
