@@ -406,8 +406,11 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
 
 // Conservative visibility test of a prepared Gaussian in view vi: false only
 // when project_view would find no pixel rect.  It takes project_view's
-// camera-space mean and projected mean and bounds the rect's half-widths from
-// above.  With W the pose's linear part, the 2D covariance's diagonal entry
+// camera-space mean and, up to the hardware reciprocal's and square root's
+// rounding (a few ulps: below 1e-3 px at any image coordinate, far inside the
+// margins below), its projected mean, and bounds the rect's half-widths from
+// above.  limx, limy are project_view's Jacobian clamp limits of the view
+// (the caller computes them once per view, with the same expression).  With W the pose's linear part, the 2D covariance's diagonal entry
 // a = w^T M w + 0.3 for w = j00 W_0 + j02 W_2 (rows of W), and
 // w^T M w <= s_max^2 |w|^2 with s_max^2 the world covariance's largest
 // eigenvalue (the largest scale squared); likewise c with
@@ -417,17 +420,15 @@ __device__ __forceinline__ void project_view(const Params& P, int g, const GPrep
 // image bounds by one pixel.  qbox = 2 ln(255 o) + 0.05, as project_view's;
 // it is negative (no visibility) for o < 1/255.
 __device__ __forceinline__ bool may_be_visible(const float* mu, float smax2, float qbox, const ViewInfo& vi,
-                                               const float* T) {
+                                               const float* T, float limx, float limy) {
     const float mx = mu[0], my = mu[1], mz = mu[2];
     const float p0 = T[0] * mx + T[1] * my + T[2] * mz + T[3];
     const float p1 = T[4] * mx + T[5] * my + T[6] * mz + T[7];
     const float pz = T[8] * mx + T[9] * my + T[10] * mz + T[11];
     if (!(pz > 0.999f * kZNear) || !(qbox > 0.f)) return false;
-    const float iz = 1.f / pz;
+    const float iz = __builtin_amdgcn_rcpf(pz);
     const float u = vi.fx * p0 * iz + vi.cx;
     const float v = vi.fy * p1 * iz + vi.cy;
-    const float limx = kJClamp * (float)vi.W / (2.f * vi.fx);
-    const float limy = kJClamp * (float)vi.H / (2.f * vi.fy);
     const float tx = fminf(fmaxf(p0 * iz, -limx), limx) * pz;
     const float ty = fminf(fmaxf(p1 * iz, -limy), limy) * pz;
     const float j00 = vi.fx * iz, j11 = vi.fy * iz;
@@ -436,7 +437,8 @@ __device__ __forceinline__ bool may_be_visible(const float* mu, float smax2, flo
     const float wy0 = j11 * T[4] + j12 * T[8], wy1 = j11 * T[5] + j12 * T[9], wy2 = j11 * T[6] + j12 * T[10];
     const float a = 1.01f * (wx0 * wx0 + wx1 * wx1 + wx2 * wx2) * smax2 + (kDilate + 0.01f);
     const float c = 1.01f * (wy0 * wy0 + wy1 * wy1 + wy2 * wy2) * smax2 + (kDilate + 0.01f);
-    const float hx = 1.001f * sqrtf(qbox * a) + 0.02f, hy = 1.001f * sqrtf(qbox * c) + 0.02f;
+    const float hx = 1.001f * __builtin_amdgcn_sqrtf(qbox * a) + 0.02f;
+    const float hy = 1.001f * __builtin_amdgcn_sqrtf(qbox * c) + 0.02f;
     return (u + hx >= -1.f) && (u - hx <= (float)vi.W) && (v + hy >= -1.f) && (v - hy <= (float)vi.H);
 }
 

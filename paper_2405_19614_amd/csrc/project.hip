@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
     __shared__ unsigned long long s_vis[kProjChunk][kW];  // visibility words of the round
     __shared__ unsigned long long s_vm[kProjBlock];       // view masks
     __shared__ float s_T[kProjChunk][12];                 // the round's poses
+    __shared__ float2 s_lim[kProjChunk];                  // their views' Jacobian clamp limits
     __shared__ uint32_t s_qrun;                           // pairs queued in earlier rounds
     __shared__ uint32_t s_nvis;                           // visible records of the block
     const int lane = threadIdx.x & 63;
@@ -87,6 +88,10 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
         if (threadIdx.x == 0) s_n = 0;
         for (int k = threadIdx.x; k < (v1 - v0) * kW; k += kProjBlock) s_vis[k / kW][k % kW] = 0ull;
         for (int k = threadIdx.x; k < (v1 - v0) * 12; k += kProjBlock) s_T[k / 12][k % 12] = poses[16 * (v0 + k / 12) + k % 12];
+        for (int k = threadIdx.x; k < v1 - v0; k += kProjBlock) {
+            const ViewInfo& vk = vt.v[v0 + k];
+            s_lim[k] = make_float2(kJClamp * (float)vk.W / (2.f * vk.fx), kJClamp * (float)vk.H / (2.f * vk.fy));
+        }
         __syncthreads();
         // phase A: the pairs that may be visible, queued (one LDS atomic per wavefront and view)
         bool queued = false;
@@ -95,7 +100,8 @@ __global__ __launch_bounds__(kProjBlock) void preprocess_fwd_kernel(ViewTable vt
             float T[12];
 #pragma unroll
             for (int k = 0; k < 12; k++) T[k] = s_T[v - v0][k];
-            const bool pass = gp.ok && may_be_visible(gp.mu, smax2, qbox, vi, T);
+            const float2 lim = s_lim[v - v0];
+            const bool pass = gp.ok && may_be_visible(gp.mu, smax2, qbox, vi, T, lim.x, lim.y);
             const uint64_t bm = __ballot(pass);
             if (bm != 0ull) {
                 const int leader = __ffsll((unsigned long long)bm) - 1;
