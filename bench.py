@@ -185,10 +185,10 @@ KERNEL_SOURCES = ["paper_2405_19614_amd/csrc/raster.hip", "paper_2405_19614_amd/
                   "paper_2405_19614_amd/csrc/gs_internal.h"]
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, bins=None):
     """HBM bytes per launch of ``kernel`` at ``workload`` from the committed
-    PMC summary, or None when it is missing or the kernel sources changed
-    since it was taken."""
+    PMC summary, or None when it is missing, the kernel sources changed
+    since it was taken, or it was taken at other bins than ``bins`` ("WxH")."""
     path = os.path.join(ROOT, "profiles", f"composite_hbm_traffic_{workload}.md")
     try:
         text = open(path).read()
@@ -198,6 +198,10 @@ def measured_traffic(workload, kernel):
     m = re.search(r"source digest[^`]*`([0-9a-f]+)`", text)
     if not m or m.group(1) != source_digest(KERNEL_SOURCES):
         return None
+    if bins is not None:
+        mb = re.search(r"bins (\d+x\d+)", text.splitlines()[0])
+        if not mb or mb.group(1) != bins:
+            return None
     m = re.search(r"^\| `?" + re.escape(kernel) + r"`? \|[^|]*\|[^|]*\|[^|]*\| ([0-9.]+) \|", text, re.M)
     return None if not m else float(m.group(1)) * 1e6
 
@@ -421,10 +425,10 @@ def roofline(res, workload, ctx):
     else:
         flops = BWD_PER_VISIT * vis + BWD_PER_BLEND * blend
     achieved = flops / (stage_ms[dom] / 1000.0) / 1e12
-    tile, _, btile = res["_shape"]
+    tile, binsz, btile = res["_shape"]
     kt = btile if dom == "composite_bwd" else tile
     kname = f"composite_{dom.split('_')[1]}_kernel<{kt[0]}, {kt[1]}, {ctx.ppt_choice(kt, dom == 'composite_bwd')}>"
-    traffic = measured_traffic(workload, kname)
+    traffic = measured_traffic(workload, kname, f"{binsz[0]}x{binsz[1]}")
     return {"bound": "alu", "kernel": dom, "kernel_name": kname, "achieved": round(achieved, 3),
             "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
             "traffic": None if traffic is None else int(traffic), "flops_per_launch": int(flops),
