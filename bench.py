@@ -180,9 +180,10 @@ def source_digest(paths):
     return h.hexdigest()[:16]
 
 
-# sources that determine the compositing kernels' code
+# sources that determine the compositing kernels' code (the build script
+# holds their compile flags)
 KERNEL_SOURCES = ["paper_2405_19614_amd/csrc/raster.hip", "paper_2405_19614_amd/csrc/gs_device.h",
-                  "paper_2405_19614_amd/csrc/gs_internal.h"]
+                  "paper_2405_19614_amd/csrc/gs_internal.h", "paper_2405_19614_amd/build.py"]
 
 
 def measured_traffic(workload, kernel, bins=None):

@@ -31,9 +31,16 @@ FLAGS = [
 ]
 
 
+# Per-file flags.  The compositing kernels are scheduled by LLVM's iterative
+# ILP scheduler: the backward, bound by instruction issue at four waves per
+# SIMD, runs 1.22 -> 1.19 ms with it (the forward is unchanged; the
+# projection kernels are slower with it, so the rest keeps the default).
+FILE_FLAGS = {"raster.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(src, [])]
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
