@@ -33,6 +33,7 @@ struct gs_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipStream_t fork = nullptr;      // second stream of a step: the backward's tile order beside the loss
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_col = nullptr, ev_col_join = nullptr;   // the colour groups' Adam update beside the geometric backward
     int tile_w = 16, tile_h = 16;
     int btile_w = 0, btile_h = 0;      // backward tile (0, 0: the forward's)
     int bin_w = 64, bin_h = 64;
@@ -509,6 +510,8 @@ int gs_create(gs_ctx** out, int device) {
     e = hipStreamCreateWithFlags(&c->fork, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_col, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_col_join, hipEventDisableTiming);
     if (e != hipSuccess) {
         gs_destroy(c);
         return fail(nullptr, GS_EDEVICE, "stream or event creation: %s", hipGetErrorString(e));
@@ -527,6 +530,8 @@ void gs_destroy(gs_ctx* c) {
     if (c->fork) (void)hipStreamDestroy(c->fork);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_col) (void)hipEventDestroy(c->ev_col);
+    if (c->ev_col_join) (void)hipEventDestroy(c->ev_col_join);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->rp_acc) (void)hipFree(c->rp_acc);
     delete c;
@@ -1016,8 +1021,20 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
     GS_HIP(c, gs::launch_composite_bwd(vtb, p.ranges, vals, p.rec, p.tfin, p.last, p.dC, p.dD, nullptr, p.g2, p.ts, vt,
                                        true, s));
     GS_HIP(c, mark(6));
+    // With SH colours the colour gradients are final once the colour kernel
+    // has run (the geometric kernel adds mean and pose terms only): their Adam
+    // update, most of the optimiser's traffic, runs on the second stream beside
+    // the geometric backward, which reads no colour parameter.
+    const bool split_adam = o->update_gaussians && g->sh_degree >= 0;
     GS_HIP(c, gs::launch_preprocess_bwd(vt, P, poses, p.rec, p.g2, G, o->accumulate_grads, p.posepart, L.pose_blocks,
-                                        s));
+                                        s, split_adam ? c->ev_col : nullptr));
+    if (split_adam) {
+        const gs::AdamGroups ag = adam_groups(g, grads, o);
+        GS_HIP(c, hipStreamWaitEvent(c->fork, c->ev_col, 0));
+        GS_HIP(c, gs::launch_adam(ag, adam->m, adam->v, adam->step, o->adam_b1, o->adam_b2, o->adam_eps,
+                                  p.scal + gs::kFlags, c->fork, 1u << 4));
+        GS_HIP(c, hipEventRecord(c->ev_col_join, c->fork));
+    }
     GS_HIP(c, gs::launch_pose_finalize(vt, p.posepart, L.pose_blocks, rp ? p.rpacc : nullptr,
                                        o->w_reproj / (float)vt.V, dL_dpose, s));
     GS_HIP(c, mark(7));
@@ -1026,12 +1043,14 @@ int enqueue_step(gs_ctx* c, const gs::ViewTable& vt, const gs::ViewTable& vtb, c
         if (o->update_gaussians) {
             const gs::AdamGroups ag = adam_groups(g, grads, o);
             GS_HIP(c, gs::launch_adam(ag, adam->m, adam->v, adam->step, o->adam_b1, o->adam_b2, o->adam_eps,
-                                      p.scal + gs::kFlags, s));
+                                      p.scal + gs::kFlags, s, split_adam ? 0x0fu : 0x1fu));
         }
         if (o->update_poses)
             GS_HIP(c, gs::launch_pose_update(vt.V, poses, dL_dpose, adam->m + np, adam->v + np, adam->step,
                                              o->lr_pose, o->adam_b1, o->adam_b2, o->adam_eps, p.scal + gs::kFlags,
                                              s));
+        // every update has read the step counter before it moves
+        if (split_adam) GS_HIP(c, hipStreamWaitEvent(s, c->ev_col_join, 0));
         GS_HIP(c, gs::launch_step_bump(adam->step, o->update_gaussians ? 1 : 0, o->update_poses ? 1 : 0, s,
                                        p.scal + gs::kFlags));
     }

@@ -269,9 +269,11 @@ hipError_t launch_rect_tiles(const ViewTable& vt, const uint2* rect, RecLine* li
 // is not finite
 hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const float* poses, Records rec,
                                  hipStream_t s, uint32_t* flags = nullptr);
+// colour_done (nullable): with SH colours, recorded on s once the colour
+// gradients are complete (after the colour kernel, before the geometric one)
 hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const float* poses, const Records& rec,
                                  const float* g2, Grads G, int accumulate, double* pose_part, int64_t pose_blocks,
-                                 hipStream_t s);
+                                 hipStream_t s, hipEvent_t colour_done = nullptr);
 hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, int64_t pose_blocks,
                                 const double* rp_acc, float rp_weight, float* dL_dpose, hipStream_t s);
 
@@ -429,8 +431,9 @@ struct AdamGroups {
 // kFlags word; nullable = always update) is non-zero: a step whose binning
 // overflowed or read a non-finite parameter leaves parameters, poses, moments
 // and the step counter as they were.
+// groups: bit i updates group i (the moments keep the layout of all five)
 hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, float b1, float b2, float eps,
-                       const uint32_t* flags, hipStream_t s);
+                       const uint32_t* flags, hipStream_t s, unsigned groups = 0x1fu);
 hipError_t launch_pose_update(int V, float* poses, const float* dpose, float* m, float* v, int32_t* step, float lr,
                               float b1, float b2, float eps, const uint32_t* flags, hipStream_t s);
 

@@ -821,24 +821,26 @@ hipError_t fwd_sh(const ViewTable& vt, const Params& P, const float* poses, Reco
 
 template <int SH, bool ISO>
 void bwd_one(const ViewTable& vt, const Params& P, const float* poses, const Records& rec, const float* g2, Grads G,
-             int accumulate, double* pose_part, int nb, hipStream_t s) {
+             int accumulate, double* pose_part, int nb, hipStream_t s, hipEvent_t colour_done) {
     const size_t dyn_sh = (size_t)vt.V * (3 * sizeof(double) + 12 * sizeof(float));
     const size_t dyn_geo = (size_t)vt.V * (6 * sizeof(double) + 18 * sizeof(float));
-    if constexpr (SH >= 0)
+    if constexpr (SH >= 0) {
         sh_bwd_kernel<SH><<<nb, kProjBlock, dyn_sh, s>>>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb);
+        if (colour_done) (void)hipEventRecord(colour_done, s);
+    }
     preprocess_bwd_kernel<SH, ISO><<<nb, kProjBlock, dyn_geo, s>>>(vt, P, poses, rec, g2, G, accumulate, pose_part,
                                                                   nb);
 }
 
 template <bool ISO>
 hipError_t bwd_sh(const ViewTable& vt, const Params& P, const float* poses, const Records& rec, const float* g2,
-                  Grads G, int accumulate, double* pose_part, int nb, hipStream_t s) {
+                  Grads G, int accumulate, double* pose_part, int nb, hipStream_t s, hipEvent_t cd) {
     switch (P.sh) {
-        case -1: bwd_one<-1, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
-        case 0: bwd_one<0, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
-        case 1: bwd_one<1, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
-        case 2: bwd_one<2, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
-        case 3: bwd_one<3, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s); break;
+        case -1: bwd_one<-1, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s, cd); break;
+        case 0: bwd_one<0, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s, cd); break;
+        case 1: bwd_one<1, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s, cd); break;
+        case 2: bwd_one<2, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s, cd); break;
+        case 3: bwd_one<3, ISO>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s, cd); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -854,12 +856,15 @@ hipError_t launch_preprocess_fwd(const ViewTable& vt, const Params& P, const flo
 
 hipError_t launch_preprocess_bwd(const ViewTable& vt, const Params& P, const float* poses, const Records& rec,
                                  const float* g2, Grads G, int accumulate, double* pose_part, int64_t pose_blocks,
-                                 hipStream_t s) {
-    if (P.n == 0) return hipSuccess;
+                                 hipStream_t s, hipEvent_t colour_done) {
+    if (P.n == 0) {
+        if (colour_done) (void)hipEventRecord(colour_done, s);
+        return hipSuccess;
+    }
     const int nb = (P.n + kProjBwdSpan - 1) / kProjBwdSpan;
     if (nb != pose_blocks) return hipErrorInvalidValue;
-    return P.iso ? bwd_sh<true>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s)
-                 : bwd_sh<false>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s);
+    return P.iso ? bwd_sh<true>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s, colour_done)
+                 : bwd_sh<false>(vt, P, poses, rec, g2, G, accumulate, pose_part, nb, s, colour_done);
 }
 
 hipError_t launch_pose_finalize(const ViewTable& vt, const double* pose_part, int64_t pose_blocks,

@@ -424,21 +424,22 @@ hipError_t launch_loss_reduce(const ViewTable& vt, const double2* tile_part, con
 }
 
 hipError_t launch_adam(const AdamGroups& ag, float* m, float* v, int32_t* step, float b1, float b2, float eps,
-                       const uint32_t* flags, hipStream_t s) {
+                       const uint32_t* flags, hipStream_t s, unsigned groups) {
     AdamLaunch a;
     int64_t off = 0, blocks = 0;
     const auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
     for (int i = 0; i < 5; i++) {
         const int64_t n = ag.cnt[i] > 0 ? ag.cnt[i] : 0;
+        const bool on = (groups >> i) & 1u;
         a.p[i] = ag.p[i];
         a.g[i] = ag.g[i];
         a.m[i] = m + off;
         a.v[i] = v + off;
-        a.n[i] = n;
+        a.n[i] = on ? n : 0;
         a.lr[i] = ag.lr[i];
         a.vec[i] = n % 4 == 0 && al16(ag.p[i]) && al16(ag.g[i]) && al16(m + off) && al16(v + off);
         a.blk[i] = blocks;
-        const int64_t items = a.vec[i] ? n / 4 : n;
+        const int64_t items = !on ? 0 : a.vec[i] ? n / 4 : n;
         // one 16-byte item per thread: a grid-stride loop over a capped grid
         // (8192 blocks per group) ran 0.96 ms for 177M parameters, this 0.81
         // ms; the cap only keeps the grid's thread count within 32 bits
